@@ -1,0 +1,222 @@
+#!/usr/bin/env python
+"""Throughput of the condensation hot path on one MI355X.
+
+One step = one pass of the whole hot path on one synthetic iterate of the
+1354-bus network: derivative values, refactorisation of G_x, K_cond (all nu
+columns) with the condensed right-hand side, dense Cholesky + solve for p_u,
+and the recovery of (p_x, p_s, p_lambda, p_y) -- what one iteration of the
+linearize-then-reduce IPM spends on linear algebra (Algorithm 1). The value is
+condensations per second with every input resident in HBM.
+
+Prints ONE JSON line (rank 0). Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("reduced-Hessian condensations/s + IPM iters/s, 1354-bus FP64; "
+          "plain vs batched/adjoint")
+HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_condense_syn1354_pmc.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2203_11875_amd", "csrc", "kernels.hip")
+# Paper context (V100, Table 3, 1354pegase: 40 iterations, 0.29 s reduction)
+PAPER_CONTEXT = {"hardware": "NVIDIA V100 (paper, Table 3)", "case": "1354pegase",
+                 "condensations_per_s_derived": 138.0}
+
+
+def workload(name):
+    import synthnet
+    if name == "syn1354":
+        return synthnet.case1354(0)
+    if name == "syn9241":
+        return synthnet.case9241(0)
+    if name == "syn118":
+        return synthnet.case118(0)
+    if name == "syn9":
+        return synthnet.case9(0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def iterate(G, net, seed=0):
+    """Seeded iterate in the library's variable order (rh_get_index_maps).
+    Multipliers and barrier terms of a late-stage iterate: K_cond is positive
+    definite, so each step factorises once (an IPM step with delta_w = 0)."""
+    import numpy as np
+    import synthnet
+    xk, xb, uk, ur = G.index_maps()
+    it = synthnet.random_iterate(net, G.m, seed, lam_scale=1.0, sig_range=(10.0, 1e4))
+    x = np.where(xk == 0, it.theta[xb], it.vm[xb])
+    lam = np.where(xk == 0, it.lam_p[xb], it.lam_q[xb])
+    sx = np.where(xk == 0, 0.0, it.sig_vm[xb])
+    u = np.where(uk == 1, it.vm[np.minimum(ur, net.nb - 1)], it.pg[np.minimum(ur, net.ng - 1)])
+    su = np.where(uk == 1, it.sig_vm[np.minimum(ur, net.nb - 1)],
+                  it.sig_pg[np.minimum(ur, net.ng - 1)])
+    r = synthnet.random_vector(G.nu + 2 * G.nx + 2 * G.m, seed + 1)
+    return x, u, lam, it.y.copy(), sx, su, it.sig_s.copy(), r
+
+
+def algorithmic_bytes(info, ncols):
+    """Paper-dataflow bytes of one condensation launch: every stage reads its
+    input panel and writes its output panel (8 (12 nx + 5 nu) bytes per
+    column) plus one pass over the matrix data per stage (12 bytes per
+    stored nonzero: value + index)."""
+    nx, nu = info["nx"], info["nu"]
+    per_col = 8 * (12 * nx + 5 * nu)
+    matrix = 12 * (2 * info["nnz_lu"] + info["nnz_k"] + 2 * info["nnz_gu"])
+    return per_col * ncols + matrix, per_col
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    txt = open(PMC_SUMMARY).read()
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or m_sha.group(1) != sha:
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(net, args_np, seconds):
+    """The oracle's full step (dense LU of G_x, explicit K_cond, RHS, Cholesky,
+    recovery) on the host, repeated for a bounded time."""
+    import numpy as np
+    from oracle.model import Model
+    from oracle import reduction as R, cholesky as OC
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    M = Model(net)
+    x, u, lam, y, sx, su, ss, r = args_np
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
+        S, lu = R.sensitivity(B)
+        Kc = R.symmetrize(R.condensed_matrix(B, S))
+        b, _, _ = R.condensed_rhs(B, r, S, lu)
+        L, delta = OC.factor_with_correction(Kc)
+        pu = OC.solve_with_factor(L, b)
+        R.recover(B, r, pu, S, lu)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or done >= 200:
+            break
+    return {"value": done / el, "unit": "condensations/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{done} full steps of the oracle on {net.name} (numpy/scipy FP64, "
+                      f"{el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="syn1354")
+    ap.add_argument("--width", type=int, default=0)
+    ap.add_argument("--lds", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the condensation of one instance runs on a "
+              "single MI355X (multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    from paper_2203_11875_amd import api
+
+    net = workload(args.workload)
+    dev = torch.device("cuda", 0)
+    G = api.Net(net, panel_width=args.width, lds_panel=args.lds)
+    args_np = iterate(G, net)
+    T = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=dev)
+    x, u, lam, y, sx, su, ss, r = map(T, args_np)
+    nu = G.nu
+    K = torch.empty((nu, nu), dtype=torch.float64, device=dev)
+    rhs = torch.empty(nu, dtype=torch.float64, device=dev)
+
+    def step(delta):
+        G.condense_reduced_hessian(x, u, lam, y, sx, su, ss, r=r, K=K, rhs=rhs)
+        p, code = G.solve_condensed_kkt(K, delta, rhs, r)
+        return code
+
+    delta = 0.0
+    for _ in range(max(1, args.warmup)):
+        code = step(delta)
+        while code == 1:        # inertia correction as in an IPM iteration
+            delta = 1e-4 if delta == 0.0 else delta * 8.0
+            code = step(delta)
+        if code != 0:
+            raise SystemExit(f"solve failed with status {code}")
+    torch.cuda.synchronize()
+    G.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(delta)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phases = G.profile_read()
+    G.profile_enable(False)
+
+    ms_step = 1e3 * el / args.steps
+    cond_ms, cond_calls = phases["condense"]
+    kern_s = cond_ms / 1e3 / max(1, cond_calls)
+    ncols = nu + 1
+    alg_bytes, per_col = algorithmic_bytes(G.info, ncols)
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = measured_traffic()
+    line = {
+        "metric": METRIC,
+        "value": args.steps / el,
+        "unit": "condensations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{net.name}: seeded synthetic 1354-bus stand-in for "
+                               f"1354pegase (nb {net.nb}, nl {net.nl}, ng {net.ng})"
+                               if args.workload == "syn1354" else net.name,
+                   "nx": G.nx, "nu": nu, "m": G.m,
+                   "step": "eval + refactor + condense (nu+1 columns) + symmetrize + "
+                           "Cholesky + solve + recovery",
+                   "panel_width": G.info["panel_width"], "lds_panel": G.info["lds_panel"],
+                   "levels": G.info["levels_lower"], "nnz_lu": G.info["nnz_lu"],
+                   "delta_w": delta},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_condense", "kernel_avg_us": kern_s * 1e6,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "bytes_per_column": per_col, "columns_per_launch": ncols},
+        "phases_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in phases.items()},
+        "paper_context": PAPER_CONTEXT,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(net, args_np, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * rhipm: condensed reduced-space interior-point KKT kernels for AMD MI355X.
+ *
+ * C ABI of the hot path of the linearize-then-reduce interior-point method
+ * (Pacaud et al., "Condensed interior-point methods: porting reduced-space
+ * approaches on GPU hardware", Section 2.2 and Section 3):
+ *
+ *   rh_eval_residual             g(x,u), h(x,u), f(x,u)          (Section 2.1)
+ *   rh_condense_reduced_hessian  K_cond = [I;S]^T K [I;S] and the condensed
+ *                                right-hand side                 (Theorems 1-2,
+ *                                eq. algo:reduction, Algorithm 1 "Reduction")
+ *   rh_solve_condensed_kkt       dense Cholesky of K_cond (+ delta_w I), p_u,
+ *                                then p_x, p_s, p_lambda, p_y    (Algorithm 1,
+ *                                control/dual/slack/state/adjoint steps;
+ *                                inertia theorem of Section 2.2.1)
+ *
+ * The optimisation problem is polar AC optimal power flow in the paper's
+ * state-control form. Conventions (all arrays float64 unless stated):
+ *
+ *   buses 0..nb-1, lines 0..nl-1, generators 0..ng-1 (one per generator bus;
+ *   the generator on the reference bus is "the reference generator").
+ *   x  (nx) = [theta at non-reference buses, bus order ; Vm at PQ buses, bus order]
+ *   u  (nu) = [Vm at generator buses, generator order ;
+ *              Pg of non-reference generators, generator order]
+ *   g  (nx) = [P balance at non-reference buses ; Q balance at PQ buses]
+ *             (same order as x: P balance pairs with theta, Q balance with Vm)
+ *   h  (m)  = [Pg_ref ; Qg of every generator ; |S_from|^2 of limited lines ;
+ *              |S_to|^2 of limited lines], m = 1 + ng + 2 * (#lines with rate > 0)
+ *   f       = sum_g c2 (base Pg)^2 + c1 (base Pg) + c0   (Pg in MW)
+ *   lambda (nx) multiplies g, y (m) multiplies h + s = 0.
+ *   Sigma_x (nx), Sigma_u (nu), Sigma_s (m): diagonal barrier terms.
+ *   K = W + diag(Sigma_u, Sigma_x) + A^T diag(Sigma_s) A, W = Hessian of
+ *   f + lambda^T g + y^T h.
+ *   Residual r packed as [r1 (nu) ; r2 (nx) ; r3 (m) ; r4 (nx) ; r5 (m)] for the
+ *   augmented system K_aug p = -r with the (s, y) coupling blocks +I (the sign
+ *   that follows from the Lagrangian f + lambda^T g + y^T (h + s) - z^T s).
+ *   Step p packed as [p_u (nu) ; p_x (nx) ; p_s (m) ; p_lambda (nx) ; p_y (m)].
+ *
+ * Memory: "device" pointers are HIP device memory (e.g. torch tensors'
+ * data_ptr()), owned by the caller, contiguous. The library owns the handle,
+ * the symbolic data, the LU factors and its workspaces. Every device call is
+ * ordered on the stream given at rh_init_network. A handle is not thread safe.
+ *
+ * Errors: functions return rh_status and never abort. Positive codes are
+ * numerical outcomes the caller acts on; negative codes are hard errors.
+ */
+#ifndef RHIPM_H
+#define RHIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RH_OK = 0,
+  RH_NOT_POSDEF = 1,      /* Cholesky met a non-positive pivot: K_cond + delta_w I
+                             is not positive definite (wrong inertia of K_aug)   */
+  RH_SMALL_PIVOT = 2,     /* static-pivot refactorisation of G_x met |u_kk| below
+                             1e-14 * max|G_x|                                      */
+  RH_NOT_CONVERGED = 3,
+  RH_ERR_ARG = -1,        /* invalid argument (null pointer, bad size, bad data)  */
+  RH_ERR_HIP = -2,        /* a HIP runtime call failed                            */
+  RH_ERR_OOM = -3,        /* device or host allocation failed                     */
+  RH_ERR_SINGULAR = -4,   /* G_x structurally singular                            */
+  RH_ERR_STATE = -5       /* call order violated (e.g. solve before condense)     */
+} rh_status;
+
+/* Network description: HOST arrays, copied by rh_init_network / rh_analyze. */
+typedef struct {
+  int32_t nb, nl, ng;
+  double base_mva;
+  const int32_t* bus_type;   /* nb: 3 reference (exactly one), 2 PV, 1 PQ         */
+  const double* pd;          /* nb: active load, p.u.                              */
+  const double* qd;          /* nb: reactive load, p.u.                            */
+  const double* vmin;        /* nb                                                 */
+  const double* vmax;        /* nb                                                 */
+  const int32_t* from;       /* nl                                                 */
+  const int32_t* to;         /* nl                                                 */
+  const double* r;           /* nl: series resistance, p.u.                        */
+  const double* x;           /* nl: series reactance, p.u.                         */
+  const double* b;           /* nl: total line charging, p.u. (half at each end)   */
+  const double* rate;        /* nl: |S| limit, p.u.; <= 0 means unlimited          */
+  const int32_t* gen_bus;    /* ng: distinct buses; exactly the PV + ref buses     */
+  const double* c2;          /* ng: $/MW^2                                         */
+  const double* c1;          /* ng: $/MW                                           */
+  const double* c0;          /* ng: $                                              */
+  const double* pmin;        /* ng, p.u.                                           */
+  const double* pmax;
+  const double* qmin;
+  const double* qmax;
+} rh_network_desc;
+
+typedef struct {
+  int32_t panel_width;       /* columns per condensation work-group; 0 = auto    */
+  int32_t ordering;          /* 0 = minimum degree on the pattern of G_x          */
+  int32_t lds_panel;         /* 1 = keep panels in LDS when they fit, 0 = global  */
+  int32_t reserved;
+} rh_options;
+
+typedef struct {
+  int64_t nx, nu, m, nb, nl, ng;
+  int64_t nnz_gx, nnz_lu, nnz_gu, nnz_a, nnz_k;
+  int64_t levels_lower, levels_upper;  /* level sets of the L / U sweeps         */
+  int64_t refactor_ops;                /* multiply-adds of one refactorisation   */
+  int64_t max_lu_row;
+  int64_t panel_width, lds_panel;      /* chosen launch shape of the condensation */
+} rh_info;
+
+typedef struct rh_symbolic rh_symbolic;
+typedef struct rh_net rh_net;
+
+const char* rh_status_str(rh_status s);
+
+/* ---------------------------------------------------------------------------
+ * Host-only symbolic analysis (no GPU needed). Builds the index maps, the
+ * fixed sparsity patterns of G_x, G_u, A and K, a fill-reducing symmetric
+ * ordering of G_x, the symbolic LU (static pivots on the diagonal), the level
+ * sets of the four triangular sweeps and the refactorisation schedule. This is
+ * the one-time host step that precedes GPU refactorisation (Section 3.1, SpRF;
+ * Section 3.3). Returns RH_ERR_ARG on inconsistent data, RH_ERR_SINGULAR if
+ * G_x is structurally singular (a bus with no line).
+ * ------------------------------------------------------------------------- */
+rh_status rh_analyze_network(const rh_network_desc* desc, const rh_options* opts,
+                             rh_symbolic** out);
+void rh_destroy_symbolic(rh_symbolic* sym);
+rh_status rh_symbolic_info(const rh_symbolic* sym, rh_info* info);
+/* Host arrays: x_kind[nx] (0 theta, 1 Vm), x_bus[nx]; u_kind[nu] (1 Vm, 2 Pg),
+ * u_ref[nu] (bus for Vm, generator for Pg). Any pointer may be NULL. */
+rh_status rh_symbolic_index_maps(const rh_symbolic* sym, int32_t* x_kind, int32_t* x_bus,
+                                 int32_t* u_kind, int32_t* u_ref);
+/* Host arrays: pattern of G_x in natural (row, column) = (g row, x index)
+ * order as CSR with sorted columns; rowptr[nx+1], col[nnz_gx]; and the
+ * symmetric pivot order perm[nx] (perm[k] = natural index eliminated k-th). */
+rh_status rh_symbolic_gx_pattern(const rh_symbolic* sym, int32_t* rowptr, int32_t* col,
+                                 int32_t* perm);
+/* Host check of the symbolic data with caller-supplied numbers: refactorise
+ * G_x (values in the CSR order of rh_symbolic_gx_pattern) with the same
+ * schedule the GPU uses, then solve G_x z = b (transpose = 0) or
+ * G_x^T z = b (transpose = 1) with the level-ordered sweeps. Host arrays. */
+rh_status rh_symbolic_host_solve(const rh_symbolic* sym, const double* gx_values,
+                                 const double* b, double* z, int32_t transpose);
+/* 0 if every dependency of every sweep lies in an earlier level set. */
+rh_status rh_symbolic_check_levels(const rh_symbolic* sym);
+
+/* ---------------------------------------------------------------------------
+ * Device handle. rh_init_network runs the analysis, uploads everything once
+ * (host -> device) and allocates the workspaces. hip_stream: hipStream_t
+ * (NULL = default stream). Errors: RH_ERR_ARG, RH_ERR_SINGULAR, RH_ERR_HIP,
+ * RH_ERR_OOM.
+ * ------------------------------------------------------------------------- */
+rh_status rh_init_network(const rh_network_desc* desc, const rh_options* opts,
+                          void* hip_stream, rh_net** out);
+void rh_destroy_network(rh_net* net);
+rh_status rh_get_info(const rh_net* net, rh_info* info);
+rh_status rh_get_dims(const rh_net* net, int64_t* nx, int64_t* nu, int64_t* m);
+rh_status rh_get_index_maps(const rh_net* net, int32_t* x_kind, int32_t* x_bus,
+                            int32_t* u_kind, int32_t* u_ref);
+/* Replace the loads (scenarios). Device arrays pd[nb], qd[nb]. */
+rh_status rh_set_loads(rh_net* net, const double* pd_dev, const double* qd_dev);
+
+/* g (nx), h (m), f (1): device outputs at device inputs x (nx), u (nu)
+ * (Section 2.1's functions of the state-control form). */
+rh_status rh_eval_residual(rh_net* net, const double* x, const double* u,
+                           double* g, double* h, double* f);
+
+/* Reduction (Algorithm 1, "Reduction"): evaluates G, A, W at (x, u, lambda, y)
+ * (Section 3.2), refactorises G_x on the device with the static pivots of the
+ * analysis, and builds K_cond = [I;S]^T K [I;S] column block by column block
+ * with the batched adjoint-adjoint products of Section 3.3: Z = -G_x^{-1} G_u V,
+ * H = K [V; Z], Psi = G_x^{-T} H_x, K_cond V = H_u - G_u^T Psi.
+ * All inputs/outputs are device arrays. K (output) is nu x nu column-major with
+ * leading dimension ldk >= nu, symmetrised ((K + K^T)/2). If r is not NULL
+ * (packed r1..r5, device), rhs (device, nu) receives the condensed right-hand
+ * side b with K_cond p_u = b, riding along as one more column of the same
+ * launch. Stream-ordered; no host synchronisation. Returns RH_SMALL_PIVOT only
+ * from a later rh_solve_condensed_kkt (the pivot flag lives on the device). */
+rh_status rh_condense_reduced_hessian(rh_net* net, const double* x, const double* u,
+                                      const double* lam, const double* y,
+                                      const double* sig_x, const double* sig_u,
+                                      const double* sig_s, const double* r,
+                                      double* K, int64_t ldk, double* rhs);
+
+/* Control step and recovery (Algorithm 1): factorises K + delta_w I in place
+ * (lower triangle; dense blocked Cholesky, FP64 MFMA trailing updates), solves
+ * for p_u with rhs, then recovers p_x = -G_x^{-1}(r4 + G_u p_u),
+ * p_lambda = -G_x^{-T}(rt_x + (K p)_x), p_s = -r5 - A p, p_y = -r3 - Sigma_s p_s
+ * using the factors and K of the last rh_condense_reduced_hessian on this
+ * handle (RH_ERR_STATE if none). Device arrays: K (in: K_cond, out: Cholesky
+ * factor in the lower triangle), rhs (nu), r (packed), p (packed step, output).
+ * dev_status (device int32[2], may be NULL): [status, index of failing pivot].
+ * The call synchronises the stream once and returns RH_NOT_POSDEF when the
+ * factorisation fails (p is then undefined) or RH_SMALL_PIVOT if the last
+ * refactorisation of G_x met a tiny pivot. */
+rh_status rh_solve_condensed_kkt(rh_net* net, double* K, int64_t ldk, double delta_w,
+                                 const double* rhs, const double* r, double* p,
+                                 int32_t* dev_status);
+
+/* ---------------------------------------------------------------------------
+ * Per-phase device timers (hipEvent pairs on the handle's stream), reported
+ * like the paper's per-phase totals (Table 3: Chol., Reduction). Phases:
+ * RH_PHASE_EVAL        derivative values, K assembly, condensed residual rt
+ * RH_PHASE_REFACTOR    static-pivot refactorisation of G_x
+ * RH_PHASE_CONDENSE    the fused solve / Hessian-product / adjoint kernel
+ * RH_PHASE_SYMMETRIZE  (K + K^T)/2
+ * RH_PHASE_CHOLESKY    dense Cholesky with forward/backward substitution
+ * RH_PHASE_RECOVER     p_x, p_lambda, p_s, p_y
+ * rh_profile_enable resets the totals; rh_profile_read waits for the
+ * recorded events and returns milliseconds and call counts per phase (host
+ * arrays of RH_NPHASES entries, either may be NULL).
+ * ------------------------------------------------------------------------- */
+enum { RH_PHASE_EVAL = 0, RH_PHASE_REFACTOR, RH_PHASE_CONDENSE, RH_PHASE_SYMMETRIZE,
+       RH_PHASE_CHOLESKY, RH_PHASE_RECOVER, RH_NPHASES };
+rh_status rh_profile_enable(rh_net* net, int32_t on);
+rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RHIPM_H */

@@ -1,0 +1,88 @@
+"""ctypes declarations of the C ABI in include/rhipm.h (argument marshalling only).
+
+The library is loaded from this package directory; there is no fallback: if
+librhipm.so is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librhipm.so")
+
+RH_OK, RH_NOT_POSDEF, RH_SMALL_PIVOT, RH_NOT_CONVERGED = 0, 1, 2, 3
+RH_ERR_ARG, RH_ERR_HIP, RH_ERR_OOM, RH_ERR_SINGULAR, RH_ERR_STATE = -1, -2, -3, -4, -5
+
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+vp = C.c_void_p
+
+
+class rh_network_desc(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("nl", C.c_int32), ("ng", C.c_int32),
+                ("base_mva", C.c_double),
+                ("bus_type", i32p), ("pd", f64p), ("qd", f64p), ("vmin", f64p),
+                ("vmax", f64p), ("from_", i32p), ("to", i32p), ("r", f64p), ("x", f64p),
+                ("b", f64p), ("rate", f64p), ("gen_bus", i32p), ("c2", f64p), ("c1", f64p),
+                ("c0", f64p), ("pmin", f64p), ("pmax", f64p), ("qmin", f64p), ("qmax", f64p)]
+
+
+class rh_options(C.Structure):
+    _fields_ = [("panel_width", C.c_int32), ("ordering", C.c_int32),
+                ("lds_panel", C.c_int32), ("reserved", C.c_int32)]
+
+
+class rh_info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "nx", "nu", "m", "nb", "nl", "ng", "nnz_gx", "nnz_lu", "nnz_gu", "nnz_a", "nnz_k",
+        "levels_lower", "levels_upper", "refactor_ops", "max_lu_row", "panel_width",
+        "lds_panel")]
+
+
+# name -> (restype, argtypes); every symbol declared in include/rhipm.h
+SIGNATURES = {
+    "rh_status_str": (C.c_char_p, [C.c_int]),
+    "rh_analyze_network": (C.c_int, [C.POINTER(rh_network_desc), C.POINTER(rh_options),
+                                     C.POINTER(vp)]),
+    "rh_destroy_symbolic": (None, [vp]),
+    "rh_symbolic_info": (C.c_int, [vp, C.POINTER(rh_info)]),
+    "rh_symbolic_index_maps": (C.c_int, [vp, i32p, i32p, i32p, i32p]),
+    "rh_symbolic_gx_pattern": (C.c_int, [vp, i32p, i32p, i32p]),
+    "rh_symbolic_host_solve": (C.c_int, [vp, f64p, f64p, f64p, C.c_int32]),
+    "rh_symbolic_check_levels": (C.c_int, [vp]),
+    "rh_init_network": (C.c_int, [C.POINTER(rh_network_desc), C.POINTER(rh_options), vp,
+                                  C.POINTER(vp)]),
+    "rh_destroy_network": (None, [vp]),
+    "rh_get_info": (C.c_int, [vp, C.POINTER(rh_info)]),
+    "rh_get_dims": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                              C.POINTER(C.c_int64)]),
+    "rh_get_index_maps": (C.c_int, [vp, i32p, i32p, i32p, i32p]),
+    "rh_set_loads": (C.c_int, [vp, vp, vp]),
+    "rh_eval_residual": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+    "rh_condense_reduced_hessian": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                              C.c_int64, vp]),
+    "rh_solve_condensed_kkt": (C.c_int, [vp, vp, C.c_int64, C.c_double, vp, vp, vp, vp]),
+    "rh_profile_enable": (C.c_int, [vp, C.c_int32]),
+    "rh_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+}
+
+PHASES = ["eval", "refactor", "condense", "symmetrize", "cholesky", "recover"]
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2203_11875_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+class RhError(RuntimeError):
+    def __init__(self, code: int, where: str, lib=None):
+        msg = lib.rh_status_str(code).decode() if lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (status {code})")
+        self.code = code

@@ -1,0 +1,221 @@
+"""Thin Python binding of the C ABI (include/rhipm.h): same names, argument
+marshalling only. Every step of the hot path runs in the HIP library; torch is
+used for device memory and streams."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = _abi.load()
+    return _LIB
+
+
+def _check(code, where):
+    if code != _abi.RH_OK:
+        raise _abi.RhError(code, where, lib())
+
+
+class _Desc:
+    """Keeps numpy copies alive while the C struct points at them."""
+
+    def __init__(self, net):
+        self.arrays = {}
+
+        def a(name, dtype):
+            v = np.ascontiguousarray(getattr(net, name), dtype=dtype)
+            self.arrays[name] = v
+            return v.ctypes.data_as(_abi.i32p if dtype == np.int32 else _abi.f64p)
+
+        d = _abi.rh_network_desc()
+        d.nb, d.nl, d.ng = int(net.nb), int(net.nl), int(net.ng)
+        d.base_mva = float(net.base_mva)
+        d.bus_type = a("bus_type", np.int32)
+        for n in ("pd", "qd", "vmin", "vmax", "r", "x", "b", "rate", "c2", "c1", "c0",
+                  "pmin", "pmax", "qmin", "qmax"):
+            setattr(d, n, a(n, np.float64))
+        d.from_ = a("f", np.int32)
+        d.to = a("t", np.int32)
+        d.gen_bus = a("gen_bus", np.int32)
+        self.desc = d
+
+
+def _opts(panel_width=0, lds_panel=1):
+    o = _abi.rh_options()
+    o.panel_width = int(panel_width)
+    o.ordering = 0
+    o.lds_panel = int(lds_panel)
+    return o
+
+
+def _info_dict(info):
+    return {name: int(getattr(info, name)) for name, _ in _abi.rh_info._fields_}
+
+
+class Symbolic:
+    """Host-only symbolic analysis (rh_analyze_network); needs no GPU."""
+
+    def __init__(self, net, panel_width=0, lds_panel=1):
+        self._desc = _Desc(net)
+        h = C.c_void_p()
+        o = _opts(panel_width, lds_panel)
+        _check(lib().rh_analyze_network(C.byref(self._desc.desc), C.byref(o), C.byref(h)),
+               "rh_analyze_network")
+        self.h = h
+        info = _abi.rh_info()
+        _check(lib().rh_symbolic_info(self.h, C.byref(info)), "rh_symbolic_info")
+        self.info = _info_dict(info)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().rh_destroy_symbolic(self.h)
+            self.h = None
+
+    def index_maps(self):
+        nx, nu = self.info["nx"], self.info["nu"]
+        xk, xb = np.zeros(nx, np.int32), np.zeros(nx, np.int32)
+        uk, ur = np.zeros(nu, np.int32), np.zeros(nu, np.int32)
+        p = lambda v: v.ctypes.data_as(_abi.i32p)
+        _check(lib().rh_symbolic_index_maps(self.h, p(xk), p(xb), p(uk), p(ur)),
+               "rh_symbolic_index_maps")
+        return xk, xb, uk, ur
+
+    def gx_pattern(self):
+        nx, nnz = self.info["nx"], self.info["nnz_gx"]
+        ptr, col, perm = np.zeros(nx + 1, np.int32), np.zeros(nnz, np.int32), np.zeros(nx, np.int32)
+        p = lambda v: v.ctypes.data_as(_abi.i32p)
+        _check(lib().rh_symbolic_gx_pattern(self.h, p(ptr), p(col), p(perm)),
+               "rh_symbolic_gx_pattern")
+        return ptr, col, perm
+
+    def host_solve(self, gx_values, b, transpose=False):
+        v = np.ascontiguousarray(gx_values, np.float64)
+        bb = np.ascontiguousarray(b, np.float64)
+        z = np.zeros_like(bb)
+        p = lambda a: a.ctypes.data_as(_abi.f64p)
+        code = lib().rh_symbolic_host_solve(self.h, p(v), p(bb), p(z), 1 if transpose else 0)
+        _check(code, "rh_symbolic_host_solve")
+        return z
+
+    def check_levels(self):
+        return lib().rh_symbolic_check_levels(self.h)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Net:
+    """Device handle (rh_init_network). Inputs are float64 CUDA tensors."""
+
+    def __init__(self, net, panel_width=0, lds_panel=1, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("rhipm.Net needs a HIP device")
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._desc = _Desc(net)
+        h = C.c_void_p()
+        o = _opts(panel_width, lds_panel)
+        _check(lib().rh_init_network(C.byref(self._desc.desc), C.byref(o),
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+               "rh_init_network")
+        self.h = h
+        info = _abi.rh_info()
+        _check(lib().rh_get_info(self.h, C.byref(info)), "rh_get_info")
+        self.info = _info_dict(info)
+        self.nx, self.nu, self.m = self.info["nx"], self.info["nu"], self.info["m"]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rh_destroy_network(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _t(self, a, n=None):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            v = a.to(device=self.device, dtype=t.float64).contiguous()
+        else:
+            v = t.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
+        if n is not None and v.numel() != n:
+            raise ValueError(f"expected {n} entries, got {v.numel()}")
+        return v
+
+    def index_maps(self):
+        nx, nu = self.nx, self.nu
+        xk, xb = np.zeros(nx, np.int32), np.zeros(nx, np.int32)
+        uk, ur = np.zeros(nu, np.int32), np.zeros(nu, np.int32)
+        p = lambda v: v.ctypes.data_as(_abi.i32p)
+        _check(lib().rh_get_index_maps(self.h, p(xk), p(xb), p(uk), p(ur)), "rh_get_index_maps")
+        return xk, xb, uk, ur
+
+    def set_loads(self, pd, qd):
+        pd, qd = self._t(pd), self._t(qd)
+        _check(lib().rh_set_loads(self.h, _ptr(pd), _ptr(qd)), "rh_set_loads")
+        self._keep = (pd, qd)
+
+    def eval_residual(self, x, u):
+        t = self.torch
+        x, u = self._t(x, self.nx), self._t(u, self.nu)
+        g = t.empty(self.nx, dtype=t.float64, device=self.device)
+        h = t.empty(self.m, dtype=t.float64, device=self.device)
+        f = t.empty(1, dtype=t.float64, device=self.device)
+        _check(lib().rh_eval_residual(self.h, _ptr(x), _ptr(u), _ptr(g), _ptr(h), _ptr(f)),
+               "rh_eval_residual")
+        return g, h, f
+
+    def condense_reduced_hessian(self, x, u, lam, y, sig_x, sig_u, sig_s, r=None, K=None,
+                                 rhs=None):
+        t = self.torch
+        nx, nu, m = self.nx, self.nu, self.m
+        args = [self._t(x, nx), self._t(u, nu), self._t(lam, nx), self._t(y, m),
+                self._t(sig_x, nx), self._t(sig_u, nu), self._t(sig_s, m)]
+        rr = self._t(r, nu + 2 * nx + 2 * m) if r is not None else None
+        if K is None:
+            K = t.empty((nu, nu), dtype=t.float64, device=self.device)
+        if rr is not None and rhs is None:
+            rhs = t.empty(nu, dtype=t.float64, device=self.device)
+        # K is column-major nu x nu with ld = nu: a contiguous (nu, nu) tensor
+        # read as row-major holds K^T; K is symmetric after the call.
+        code = lib().rh_condense_reduced_hessian(self.h, *[_ptr(a) for a in args], _ptr(rr),
+                                                 _ptr(K), nu, _ptr(rhs) if rr is not None else None)
+        _check(code, "rh_condense_reduced_hessian")
+        self._keep = (args, rr)
+        return K, rhs
+
+    def profile_enable(self, on=True):
+        _check(lib().rh_profile_enable(self.h, 1 if on else 0), "rh_profile_enable")
+
+    def profile_read(self):
+        n = len(_abi.PHASES)
+        ms = (C.c_double * n)()
+        calls = (C.c_int64 * n)()
+        _check(lib().rh_profile_read(self.h, ms, calls), "rh_profile_read")
+        return {name: (float(ms[k]), int(calls[k])) for k, name in enumerate(_abi.PHASES)}
+
+    def solve_condensed_kkt(self, K, delta_w, rhs, r):
+        """Returns (p, status) where status is the rh_status integer; raises on
+        hard errors only."""
+        t = self.torch
+        nx, nu, m = self.nx, self.nu, self.m
+        rr = self._t(r, nu + 2 * nx + 2 * m)
+        rhs = self._t(rhs, nu)
+        p = t.empty(nu + 2 * nx + 2 * m, dtype=t.float64, device=self.device)
+        st = t.zeros(2, dtype=t.int32, device=self.device)
+        code = lib().rh_solve_condensed_kkt(self.h, _ptr(K), nu, float(delta_w), _ptr(rhs),
+                                            _ptr(rr), _ptr(p), _ptr(st))
+        if code < 0:
+            _check(code, "rh_solve_condensed_kkt")
+        return p, code

@@ -1,0 +1,662 @@
+// Host symbolic analysis (see analysis.hpp).
+//
+// The state Jacobian G_x of the polar power-flow equations has the structure
+// of the network: the P balance at bus i (paired with theta_i) and the Q
+// balance at a PQ bus i (paired with Vm_i) depend on theta_j and Vm_j of i and
+// its neighbours. Its pattern is therefore structurally symmetric under that
+// pairing, and a symmetric permutation with pivots on the diagonal keeps the
+// strong diagonal of the power-flow Jacobian. The paper refactorises G_x on
+// the GPU with a fixed pattern and fixed permutations computed once on the
+// host (Section 3.1, SpRF; Section 4.2); this file computes that fixed data.
+#include "analysis.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+#include <set>
+#include <utility>
+
+namespace rh {
+
+namespace {
+
+rh_status fail(Symbolic& s, rh_status st, const std::string& msg) {
+  s.error = msg;
+  return st;
+}
+
+int find_pos(const std::vector<int>& ptr, const std::vector<int>& col, int r, int c) {
+  auto b = col.begin() + ptr[r];
+  auto e = col.begin() + ptr[r + 1];
+  auto it = std::lower_bound(b, e, c);
+  if (it == e || *it != c) return -1;
+  return int(it - col.begin());
+}
+
+void to_csr(int nrow, std::vector<std::vector<int>>& rows, std::vector<int>& ptr,
+            std::vector<int>& col) {
+  ptr.assign(nrow + 1, 0);
+  col.clear();
+  for (int r = 0; r < nrow; ++r) {
+    auto& v = rows[r];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    ptr[r + 1] = ptr[r] + int(v.size());
+    col.insert(col.end(), v.begin(), v.end());
+  }
+}
+
+void transpose(int nrow, int ncol, const std::vector<int>& ptr, const std::vector<int>& col,
+               std::vector<int>& tptr, std::vector<int>& trow, std::vector<int>& from) {
+  tptr.assign(ncol + 1, 0);
+  for (int c : col) tptr[c + 1]++;
+  for (int c = 0; c < ncol; ++c) tptr[c + 1] += tptr[c];
+  trow.assign(col.size(), 0);
+  from.assign(col.size(), 0);
+  std::vector<int> next(tptr.begin(), tptr.end() - 1);
+  for (int r = 0; r < nrow; ++r)
+    for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+      int q = next[col[p]]++;
+      trow[q] = r;
+      from[q] = p;
+    }
+}
+
+// Exact minimum degree on an undirected graph (elimination graph kept
+// explicitly; ties broken by the smaller node id). Returns the elimination
+// order; higher[v] receives v's neighbours at the moment it is eliminated,
+// i.e. the off-diagonal pattern of its row of U.
+std::vector<int> minimum_degree(int n, std::vector<std::vector<int>> adj,
+                                std::vector<std::vector<int>>& higher) {
+  std::set<std::pair<int, int>> pq;
+  for (int v = 0; v < n; ++v) pq.insert({int(adj[v].size()), v});
+  std::vector<int> order;
+  order.reserve(n);
+  higher.assign(n, {});
+  std::vector<int> merged;
+  while (!pq.empty()) {
+    int v = pq.begin()->second;
+    pq.erase(pq.begin());
+    order.push_back(v);
+    std::vector<int> nbrs = adj[v];
+    higher[v] = nbrs;
+    for (int u : nbrs) {
+      pq.erase({int(adj[u].size()), u});
+      merged.clear();
+      std::set_union(adj[u].begin(), adj[u].end(), nbrs.begin(), nbrs.end(),
+                     std::back_inserter(merged));
+      std::vector<int> out;
+      out.reserve(merged.size());
+      for (int w : merged)
+        if (w != u && w != v) out.push_back(w);
+      adj[u].swap(out);
+      pq.insert({int(adj[u].size()), u});
+    }
+    adj[v].clear();
+  }
+  return order;
+}
+
+void build_sweep(Sweep& sw, int n, const std::vector<int>& level, int nlev,
+                 const std::vector<std::vector<std::pair<int, int>>>& entries,
+                 bool has_diag, const std::vector<int>& diag_pos) {
+  sw.nlev = nlev;
+  sw.has_diag = has_diag;
+  std::vector<std::vector<int>> bylev(nlev);
+  for (int i = 0; i < n; ++i) bylev[level[i]].push_back(i);
+  sw.lev_ptr.assign(nlev + 1, 0);
+  sw.rows.clear();
+  sw.ptr.assign(1, 0);
+  sw.col.clear();
+  sw.src.clear();
+  sw.diag_src.clear();
+  for (int l = 0; l < nlev; ++l) {
+    for (int i : bylev[l]) {
+      sw.rows.push_back(i);
+      for (auto& e : entries[i]) {
+        sw.col.push_back(e.first);
+        sw.src.push_back(e.second);
+      }
+      sw.ptr.push_back(int(sw.col.size()));
+      if (has_diag) sw.diag_src.push_back(diag_pos[i]);
+    }
+    sw.lev_ptr[l + 1] = int(sw.rows.size());
+  }
+}
+
+}  // namespace
+
+rh_status analyze(const rh_network_desc& d, const rh_options* /*opts*/, Symbolic& s) {
+  // ------------------------------------------------------------ validation
+  if (d.nb < 2 || d.nl < 1 || d.ng < 1) return fail(s, RH_ERR_ARG, "need nb>=2, nl>=1, ng>=1");
+  if (!d.bus_type || !d.pd || !d.qd || !d.vmin || !d.vmax || !d.from || !d.to || !d.r ||
+      !d.x || !d.b || !d.rate || !d.gen_bus || !d.c2 || !d.c1 || !d.c0 || !d.pmin ||
+      !d.pmax || !d.qmin || !d.qmax)
+    return fail(s, RH_ERR_ARG, "null array in network description");
+  if (!(d.base_mva > 0)) return fail(s, RH_ERR_ARG, "base_mva must be positive");
+  const int nb = d.nb, nl = d.nl, ng = d.ng;
+  s.nb = nb;
+  s.nl = nl;
+  s.ng = ng;
+  s.base = d.base_mva;
+  s.ref = -1;
+  for (int i = 0; i < nb; ++i) {
+    int t = d.bus_type[i];
+    if (t < 1 || t > 3) return fail(s, RH_ERR_ARG, "bus_type must be 1, 2 or 3");
+    if (t == 3) {
+      if (s.ref >= 0) return fail(s, RH_ERR_ARG, "more than one reference bus");
+      s.ref = i;
+    }
+  }
+  if (s.ref < 0) return fail(s, RH_ERR_ARG, "no reference bus");
+  s.gen_of_bus.assign(nb, -1);
+  for (int g = 0; g < ng; ++g) {
+    int b = d.gen_bus[g];
+    if (b < 0 || b >= nb) return fail(s, RH_ERR_ARG, "gen_bus out of range");
+    if (s.gen_of_bus[b] >= 0) return fail(s, RH_ERR_ARG, "two generators on one bus");
+    if (d.bus_type[b] == 1) return fail(s, RH_ERR_ARG, "generator on a PQ bus");
+    s.gen_of_bus[b] = g;
+  }
+  for (int i = 0; i < nb; ++i)
+    if (d.bus_type[i] != 1 && s.gen_of_bus[i] < 0)
+      return fail(s, RH_ERR_ARG, "PV/reference bus without generator");
+  s.ref_gen = s.gen_of_bus[s.ref];
+  std::vector<std::vector<int>> adj(nb);
+  for (int l = 0; l < nl; ++l) {
+    int f = d.from[l], t = d.to[l];
+    if (f < 0 || f >= nb || t < 0 || t >= nb || f == t)
+      return fail(s, RH_ERR_ARG, "bad line ends");
+    if (!(std::abs(d.r[l]) + std::abs(d.x[l]) > 0))
+      return fail(s, RH_ERR_ARG, "zero line impedance");
+    adj[f].push_back(t);
+    adj[t].push_back(f);
+  }
+  for (auto& a : adj) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+  {  // connectivity from the reference bus (else G_x is singular)
+    std::vector<char> seen(nb, 0);
+    std::vector<int> stack{s.ref};
+    seen[s.ref] = 1;
+    int cnt = 1;
+    while (!stack.empty()) {
+      int v = stack.back();
+      stack.pop_back();
+      for (int w : adj[v])
+        if (!seen[w]) {
+          seen[w] = 1;
+          ++cnt;
+          stack.push_back(w);
+        }
+    }
+    if (cnt != nb) return fail(s, RH_ERR_SINGULAR, "network not connected to the reference bus");
+  }
+
+  // ------------------------------------------------------------- host data
+  s.pd.assign(d.pd, d.pd + nb);
+  s.qd.assign(d.qd, d.qd + nb);
+  s.lf.assign(d.from, d.from + nl);
+  s.lt.assign(d.to, d.to + nl);
+  s.gff.resize(nl);
+  s.bff.resize(nl);
+  s.gft.resize(nl);
+  s.bft.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    std::complex<double> ys = 1.0 / std::complex<double>(d.r[l], d.x[l]);
+    s.gff[l] = ys.real();
+    s.bff[l] = ys.imag() + 0.5 * d.b[l];
+    s.gft[l] = -ys.real();
+    s.bft[l] = -ys.imag();
+  }
+  s.c2.assign(d.c2, d.c2 + ng);
+  s.c1.assign(d.c1, d.c1 + ng);
+
+  // ---------------------------------------------------- natural index maps
+  s.th_nat.assign(nb, -1);
+  s.vmx_nat.assign(nb, -1);
+  s.vmu.assign(nb, -1);
+  s.pg_u.assign(ng, -1);
+  int k = 0;
+  for (int i = 0; i < nb; ++i)
+    if (i != s.ref) s.th_nat[i] = k++;
+  for (int i = 0; i < nb; ++i)
+    if (d.bus_type[i] == 1) s.vmx_nat[i] = k++;
+  s.nx = k;
+  for (int g = 0; g < ng; ++g) s.vmu[d.gen_bus[g]] = g;
+  k = ng;
+  for (int g = 0; g < ng; ++g)
+    if (g != s.ref_gen) s.pg_u[g] = k++;
+  s.nu = k;
+  s.nw = s.nu + s.nx;
+  const int nx = s.nx, nu = s.nu;
+  s.x_kind.assign(nx, 0);
+  s.x_bus.assign(nx, 0);
+  for (int i = 0; i < nb; ++i) {
+    if (s.th_nat[i] >= 0) { s.x_kind[s.th_nat[i]] = 0; s.x_bus[s.th_nat[i]] = i; }
+    if (s.vmx_nat[i] >= 0) { s.x_kind[s.vmx_nat[i]] = 1; s.x_bus[s.vmx_nat[i]] = i; }
+  }
+  s.u_kind.assign(nu, 0);
+  s.u_ref.assign(nu, 0);
+  for (int g = 0; g < ng; ++g) {
+    s.u_kind[g] = 1;
+    s.u_ref[g] = d.gen_bus[g];
+    if (s.pg_u[g] >= 0) { s.u_kind[s.pg_u[g]] = 2; s.u_ref[s.pg_u[g]] = g; }
+  }
+  s.lim_of_line.assign(nl, -1);
+  s.nlim = 0;
+  for (int l = 0; l < nl; ++l)
+    if (d.rate[l] > 0) s.lim_of_line[l] = s.nlim++;
+  s.m = 1 + ng + 2 * s.nlim;
+
+  // ------------------------------------------------ natural G_x pattern
+  // row of a bus equation = natural x index of its paired variable
+  std::vector<std::vector<int>> gxrows(nx);
+  auto bus_xcols = [&](int i, std::vector<int>& out) {
+    auto add_bus = [&](int j) {
+      if (s.th_nat[j] >= 0) out.push_back(s.th_nat[j]);
+      if (s.vmx_nat[j] >= 0) out.push_back(s.vmx_nat[j]);
+    };
+    add_bus(i);
+    for (int j : adj[i]) add_bus(j);
+  };
+  for (int i = 0; i < nb; ++i) {
+    if (s.th_nat[i] >= 0) bus_xcols(i, gxrows[s.th_nat[i]]);
+    if (s.vmx_nat[i] >= 0) bus_xcols(i, gxrows[s.vmx_nat[i]]);
+  }
+  to_csr(nx, gxrows, s.gx_ptr, s.gx_col);
+
+  // ------------------------------------------------------------- ordering
+  std::vector<std::vector<int>> gadj(nx);
+  for (int r = 0; r < nx; ++r)
+    for (int p = s.gx_ptr[r]; p < s.gx_ptr[r + 1]; ++p)
+      if (s.gx_col[p] != r) gadj[r].push_back(s.gx_col[p]);
+  for (auto& a : gadj) std::sort(a.begin(), a.end());
+  std::vector<std::vector<int>> higher;
+  s.perm = minimum_degree(nx, gadj, higher);
+  s.iperm.assign(nx, 0);
+  for (int i = 0; i < nx; ++i) s.iperm[s.perm[i]] = i;
+
+  // ---------------------------------------------------------- symbolic LU
+  std::vector<std::vector<int>> urows(nx), lrows(nx);
+  for (int i = 0; i < nx; ++i) {
+    for (int v : higher[s.perm[i]]) urows[i].push_back(s.iperm[v]);
+    std::sort(urows[i].begin(), urows[i].end());
+    for (int j : urows[i]) lrows[j].push_back(i);
+  }
+  s.lu_ptr.assign(nx + 1, 0);
+  s.lu_col.clear();
+  s.lu_diag.assign(nx, 0);
+  s.max_row = 0;
+  for (int i = 0; i < nx; ++i) {
+    std::sort(lrows[i].begin(), lrows[i].end());
+    for (int c : lrows[i]) s.lu_col.push_back(c);
+    s.lu_diag[i] = int(s.lu_col.size());
+    s.lu_col.push_back(i);
+    for (int c : urows[i]) s.lu_col.push_back(c);
+    s.lu_ptr[i + 1] = int(s.lu_col.size());
+    s.max_row = std::max(s.max_row, s.lu_ptr[i + 1] - s.lu_ptr[i]);
+  }
+  s.gx_lu.assign(s.gx_col.size(), -1);
+  for (int r = 0; r < nx; ++r)
+    for (int p = s.gx_ptr[r]; p < s.gx_ptr[r + 1]; ++p) {
+      int pos = find_pos(s.lu_ptr, s.lu_col, s.iperm[r], s.iperm[s.gx_col[p]]);
+      if (pos < 0) return fail(s, RH_ERR_ARG, "internal: G_x entry missing from LU pattern");
+      s.gx_lu[p] = pos;
+    }
+
+  // ------------------------------------------------------------- levels
+  std::vector<int> levL(nx, 0), levU(nx, 0);
+  int nlevL = 0, nlevU = 0;
+  for (int i = 0; i < nx; ++i) {
+    int lv = 0;
+    for (int p = s.lu_ptr[i]; p < s.lu_diag[i]; ++p) lv = std::max(lv, levL[s.lu_col[p]] + 1);
+    levL[i] = lv;
+    nlevL = std::max(nlevL, lv + 1);
+  }
+  for (int i = nx - 1; i >= 0; --i) {
+    int lv = 0;
+    for (int p = s.lu_diag[i] + 1; p < s.lu_ptr[i + 1]; ++p)
+      lv = std::max(lv, levU[s.lu_col[p]] + 1);
+    levU[i] = lv;
+    nlevU = std::max(nlevU, lv + 1);
+  }
+  {
+    std::vector<std::vector<std::pair<int, int>>> eL(nx), eU(nx), eUT(nx), eLT(nx);
+    for (int i = 0; i < nx; ++i) {
+      for (int p = s.lu_ptr[i]; p < s.lu_diag[i]; ++p) {
+        int c = s.lu_col[p];
+        eL[i].push_back({c, p});      // L(i, c), c < i
+        eLT[c].push_back({i, p});     // L^T(c, i) = L(i, c), i > c
+      }
+      for (int p = s.lu_diag[i] + 1; p < s.lu_ptr[i + 1]; ++p) {
+        int c = s.lu_col[p];
+        eU[i].push_back({c, p});      // U(i, c), c > i
+        eUT[c].push_back({i, p});     // U^T(c, i) = U(i, c), i < c
+      }
+    }
+    build_sweep(s.sl, nx, levL, nlevL, eL, false, s.lu_diag);
+    build_sweep(s.su, nx, levU, nlevU, eU, true, s.lu_diag);
+    // U^T is lower triangular with the pattern of L (symmetric structure);
+    // L^T is upper triangular with the pattern of U.
+    build_sweep(s.sut, nx, levL, nlevL, eUT, true, s.lu_diag);
+    build_sweep(s.slt, nx, levU, nlevU, eLT, false, s.lu_diag);
+  }
+
+  // ----------------------------------------------- refactorisation schedule
+  // Row-by-row Doolittle elimination (rows in any order consistent with the
+  // L levels): for each lower entry (i, k) in increasing k,
+  //   l_ik = a_ik / u_kk;  a_ij -= l_ik * u_kj  for every U entry (k, j).
+  s.rf_kptr.assign(s.lu_col.size() + 1, 0);
+  s.rf_op_src.clear();
+  s.rf_op_dst.clear();
+  s.refactor_ops = 0;
+  for (int i = 0; i < nx; ++i) {
+    for (int p = s.lu_ptr[i]; p < s.lu_ptr[i + 1]; ++p) {
+      if (p < s.lu_diag[i]) {
+        int kk = s.lu_col[p];
+        for (int q = s.lu_diag[kk] + 1; q < s.lu_ptr[kk + 1]; ++q) {
+          int dst = find_pos(s.lu_ptr, s.lu_col, i, s.lu_col[q]);
+          if (dst < 0) return fail(s, RH_ERR_ARG, "internal: LU pattern not closed");
+          s.rf_op_src.push_back(q);
+          s.rf_op_dst.push_back(dst);
+        }
+      }
+      s.rf_kptr[p + 1] = int(s.rf_op_src.size());
+    }
+  }
+  s.refactor_ops = long(s.rf_op_src.size());
+
+  // -------------------------------------------------- w = [u ; x internal]
+  auto w_theta = [&](int i) { return s.th_nat[i] >= 0 ? nu + s.iperm[s.th_nat[i]] : -1; };
+  auto w_vm = [&](int i) {
+    if (s.vmx_nat[i] >= 0) return nu + s.iperm[s.vmx_nat[i]];
+    return s.vmu[i];
+  };
+  s.line_w.assign(4 * nl, -1);
+  s.line_wsrc.assign(8 * nl, -1);
+  for (int l = 0; l < nl; ++l) {
+    int f = d.from[l], t = d.to[l];
+    s.line_w[4 * l + 0] = w_theta(f);
+    s.line_w[4 * l + 1] = w_theta(t);
+    s.line_w[4 * l + 2] = w_vm(f);
+    s.line_w[4 * l + 3] = w_vm(t);
+    int* ws = &s.line_wsrc[8 * l];
+    ws[0] = s.th_nat[f];                       // lambda of P balance at from (natural g row)
+    ws[1] = s.vmx_nat[f];                      // lambda of Q balance at from
+    ws[2] = s.th_nat[t];
+    ws[3] = s.vmx_nat[t];
+    ws[4] = s.gen_of_bus[f] >= 0 ? 1 + s.gen_of_bus[f] : -1;   // y of Qg
+    ws[5] = s.gen_of_bus[t] >= 0 ? 1 + s.gen_of_bus[t] : -1;
+    int kl = s.lim_of_line[l];
+    ws[6] = kl >= 0 ? 1 + ng + kl : -1;        // y of |S_from|^2
+    ws[7] = kl >= 0 ? 1 + ng + s.nlim + kl : -1;
+    if (f == s.ref || t == s.ref) {
+      s.ref_lines.push_back(l);
+      s.ref_ends.push_back(f == s.ref ? 0 : 1);
+    }
+  }
+  s.sig_map.assign(s.nw, 0);
+  for (int v = 0; v < nu; ++v) s.sig_map[v] = v;
+  for (int i = 0; i < nx; ++i) s.sig_map[nu + i] = nu + s.perm[i];
+
+  // ---------------------------------------------------------- G_u and A
+  // line-ends incident to each bus, in line order
+  std::vector<std::vector<std::pair<int, int>>> ends(nb);
+  for (int l = 0; l < nl; ++l) {
+    ends[d.from[l]].push_back({l, 0});
+    ends[d.to[l]].push_back({l, 1});
+  }
+  std::vector<std::vector<int>> gurows(nx), arows(s.m);
+  auto bus_wcols = [&](int i, std::vector<int>& out) {
+    auto add = [&](int j) {
+      if (w_theta(j) >= 0) out.push_back(w_theta(j));
+      out.push_back(w_vm(j));
+    };
+    add(i);
+    for (int j : adj[i]) add(j);
+  };
+  auto gu_of_bus = [&](int i, int row_internal) {
+    std::vector<int> wc;
+    bus_wcols(i, wc);
+    for (int w : wc)
+      if (w < nu) gurows[row_internal].push_back(w);
+  };
+  for (int i = 0; i < nb; ++i) {
+    if (s.th_nat[i] >= 0) {
+      int ri = s.iperm[s.th_nat[i]];
+      gu_of_bus(i, ri);
+      int g = s.gen_of_bus[i];
+      if (g >= 0 && s.pg_u[g] >= 0) gurows[ri].push_back(s.pg_u[g]);
+    }
+    if (s.vmx_nat[i] >= 0) gu_of_bus(i, s.iperm[s.vmx_nat[i]]);
+  }
+  to_csr(nx, gurows, s.gu_ptr, s.gu_col);
+  transpose(nx, nu, s.gu_ptr, s.gu_col, s.gucsc_ptr, s.gucsc_row, s.gucsc_from_csr);
+  bus_wcols(s.ref, arows[0]);
+  for (int g = 0; g < ng; ++g) bus_wcols(d.gen_bus[g], arows[1 + g]);
+  for (int l = 0; l < nl; ++l) {
+    int kl = s.lim_of_line[l];
+    if (kl < 0) continue;
+    for (int kk = 0; kk < 4; ++kk) {
+      int w = s.line_w[4 * l + kk];
+      if (w >= 0) {
+        arows[1 + ng + kl].push_back(w);
+        arows[1 + ng + s.nlim + kl].push_back(w);
+      }
+    }
+  }
+  to_csr(s.m, arows, s.a_ptr, s.a_col);
+  transpose(s.m, s.nw, s.a_ptr, s.a_col, s.acsc_ptr, s.acsc_row, s.acsc_from_csr);
+
+  // -------------------------------------------------------------- K pattern
+  std::vector<std::vector<int>> krows(s.nw);
+  for (int v = 0; v < s.nw; ++v) krows[v].push_back(v);
+  for (int l = 0; l < nl; ++l)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int wa = s.line_w[4 * l + a], wb = s.line_w[4 * l + b];
+        if (wa >= 0 && wb >= 0) krows[wa].push_back(wb);
+      }
+  for (int j = 0; j < s.m; ++j)
+    for (int p = s.a_ptr[j]; p < s.a_ptr[j + 1]; ++p)
+      for (int q = s.a_ptr[j]; q < s.a_ptr[j + 1]; ++q) krows[s.a_col[p]].push_back(s.a_col[q]);
+  to_csr(s.nw, krows, s.k_ptr, s.k_col);
+  const int nnzk = int(s.k_col.size());
+  {
+    std::vector<std::vector<int>> hl(nnzk);
+    std::vector<std::vector<std::array<int, 3>>> at(nnzk);
+    for (int l = 0; l < nl; ++l)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          int wa = s.line_w[4 * l + a], wb = s.line_w[4 * l + b];
+          if (wa < 0 || wb < 0) continue;
+          int e = find_pos(s.k_ptr, s.k_col, wa, wb);
+          hl[e].push_back(HL_STRIDE * l + hl_index(std::min(a, b), std::max(a, b)));
+        }
+    for (int j = 0; j < s.m; ++j)
+      for (int p = s.a_ptr[j]; p < s.a_ptr[j + 1]; ++p)
+        for (int q = s.a_ptr[j]; q < s.a_ptr[j + 1]; ++q) {
+          int e = find_pos(s.k_ptr, s.k_col, s.a_col[p], s.a_col[q]);
+          at[e].push_back({p, q, j});
+        }
+    auto& kg = s.kg;
+    kg.hl_ptr.assign(nnzk + 1, 0);
+    kg.ata_ptr.assign(nnzk + 1, 0);
+    kg.diag_var.assign(nnzk, -1);
+    for (int e = 0; e < nnzk; ++e) {
+      for (int v : hl[e]) kg.hl_idx.push_back(v);
+      kg.hl_ptr[e + 1] = int(kg.hl_idx.size());
+      for (auto& t : at[e]) {
+        kg.ata_a1.push_back(t[0]);
+        kg.ata_a2.push_back(t[1]);
+        kg.ata_row.push_back(t[2]);
+      }
+      kg.ata_ptr[e + 1] = int(kg.ata_a1.size());
+    }
+    for (int v = 0; v < s.nw; ++v) kg.diag_var[find_pos(s.k_ptr, s.k_col, v, v)] = v;
+  }
+  s.k_cdiag.assign(s.nw, 0.0);
+  for (int g = 0; g < ng; ++g)
+    if (s.pg_u[g] >= 0) s.k_cdiag[s.pg_u[g]] = 2.0 * d.c2[g] * s.base * s.base;
+  s.cost_rank1 = 2.0 * d.c2[s.ref_gen] * s.base * s.base;
+
+  // ---------------------------------------------------- evaluation gather
+  // src = [LF (LF_STRIDE * nl) | u (nu) | pd (nb) | qd (nb)]
+  s.src_u = LF_STRIDE * nl;
+  const int src_pd = s.src_u + nu, src_qd = src_pd + nb;
+  s.src_total = src_qd + nb;
+  s.d_lu = 0;
+  s.d_gu = s.d_lu + int(s.lu_col.size());
+  s.d_a = s.d_gu + int(s.gu_col.size());
+  s.d_g = s.d_a + int(s.a_col.size());
+  s.d_h = s.d_g + nx;
+  s.d_total = s.d_h + s.m;
+  std::vector<std::vector<std::pair<int, double>>> terms(s.d_total);
+  std::vector<double> cst(s.d_total, 0.0);
+  auto jac_row = [&](int bus, bool isP, auto dst_of_w) {
+    for (auto& le : ends[bus]) {
+      int l = le.first, e = le.second;
+      int base = isP ? (e == 0 ? LF_DPF : LF_DPT) : (e == 0 ? LF_DQF : LF_DQT);
+      for (int kk = 0; kk < 4; ++kk) {
+        int w = s.line_w[4 * l + kk];
+        if (w < 0) continue;
+        terms[dst_of_w(w)].push_back({LF_STRIDE * l + base + kk, 1.0});
+      }
+    }
+  };
+  auto value_sum = [&](int bus, bool isP, int dst) {
+    for (auto& le : ends[bus]) {
+      int l = le.first, e = le.second;
+      int slot = isP ? (e == 0 ? LF_PF : LF_PT) : (e == 0 ? LF_QF : LF_QT);
+      terms[dst].push_back({LF_STRIDE * l + slot, 1.0});
+    }
+  };
+  for (int i = 0; i < nb; ++i) {
+    for (int isP = 1; isP >= 0; --isP) {
+      int nat = isP ? s.th_nat[i] : s.vmx_nat[i];
+      if (nat < 0) continue;
+      int ri = s.iperm[nat];
+      jac_row(i, isP, [&](int w) {
+        if (w >= nu) return s.d_lu + find_pos(s.lu_ptr, s.lu_col, ri, w - nu);
+        return s.d_gu + find_pos(s.gu_ptr, s.gu_col, ri, w);
+      });
+      int gdst = s.d_g + nat;
+      value_sum(i, isP, gdst);
+      if (isP) {
+        terms[gdst].push_back({src_pd + i, 1.0});
+        int g = s.gen_of_bus[i];
+        if (g >= 0 && s.pg_u[g] >= 0) {
+          terms[gdst].push_back({s.src_u + s.pg_u[g], -1.0});
+          cst[s.d_gu + find_pos(s.gu_ptr, s.gu_col, ri, s.pg_u[g])] = -1.0;
+        }
+      } else {
+        terms[gdst].push_back({src_qd + i, 1.0});
+      }
+    }
+  }
+  auto arow_dst = [&](int row) {
+    return [&, row](int w) { return s.d_a + find_pos(s.a_ptr, s.a_col, row, w); };
+  };
+  jac_row(s.ref, true, arow_dst(0));
+  value_sum(s.ref, true, s.d_h + 0);
+  terms[s.d_h + 0].push_back({src_pd + s.ref, 1.0});
+  for (int g = 0; g < ng; ++g) {
+    int b = d.gen_bus[g];
+    jac_row(b, false, arow_dst(1 + g));
+    value_sum(b, false, s.d_h + 1 + g);
+    terms[s.d_h + 1 + g].push_back({src_qd + b, 1.0});
+  }
+  for (int l = 0; l < nl; ++l) {
+    int kl = s.lim_of_line[l];
+    if (kl < 0) continue;
+    for (int e = 0; e < 2; ++e) {
+      int row = 1 + ng + e * s.nlim + kl;
+      for (int kk = 0; kk < 4; ++kk) {
+        int w = s.line_w[4 * l + kk];
+        if (w < 0) continue;
+        terms[s.d_a + find_pos(s.a_ptr, s.a_col, row, w)].push_back(
+            {LF_STRIDE * l + (e == 0 ? LF_DSF2 : LF_DST2) + kk, 1.0});
+      }
+      terms[s.d_h + row].push_back({LF_STRIDE * l + (e == 0 ? LF_SF2 : LF_ST2), 1.0});
+    }
+  }
+  s.eg.ptr.assign(s.d_total + 1, 0);
+  s.eg.idx.clear();
+  s.eg.coef.clear();
+  for (int e = 0; e < s.d_total; ++e) {
+    for (auto& t : terms[e]) {
+      s.eg.idx.push_back(t.first);
+      s.eg.coef.push_back(t.second);
+    }
+    s.eg.ptr[e + 1] = int(s.eg.idx.size());
+  }
+  s.eg.cst = cst;
+  return RH_OK;
+}
+
+// ------------------------------------------------------------------ checks
+rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, double* z,
+                     bool transpose) {
+  const int nx = s.nx;
+  std::vector<double> lu(s.lu_col.size(), 0.0);
+  for (size_t p = 0; p < s.gx_col.size(); ++p) lu[s.gx_lu[p]] = gxv[p];
+  // refactorise level by level (same schedule as the device)
+  for (int lv = 0; lv < s.sl.nlev; ++lv)
+    for (int sl = s.sl.lev_ptr[lv]; sl < s.sl.lev_ptr[lv + 1]; ++sl) {
+      int i = s.sl.rows[sl];
+      for (int p = s.lu_ptr[i]; p < s.lu_diag[i]; ++p) {
+        double piv = lu[s.lu_diag[s.lu_col[p]]];
+        if (piv == 0.0) return RH_SMALL_PIVOT;
+        double l = lu[p] / piv;
+        lu[p] = l;
+        for (int o = s.rf_kptr[p]; o < s.rf_kptr[p + 1]; ++o) lu[s.rf_op_dst[o]] -= l * lu[s.rf_op_src[o]];
+      }
+    }
+  for (int i = 0; i < nx; ++i)
+    if (lu[s.lu_diag[i]] == 0.0) return RH_SMALL_PIVOT;
+  std::vector<double> w(nx);
+  for (int i = 0; i < nx; ++i) w[i] = b[s.perm[i]];
+  auto run = [&](const Sweep& sw) {
+    for (int lv = 0; lv < sw.nlev; ++lv)
+      for (int sl = sw.lev_ptr[lv]; sl < sw.lev_ptr[lv + 1]; ++sl) {
+        int i = sw.rows[sl];
+        double acc = w[i];
+        for (int e = sw.ptr[sl]; e < sw.ptr[sl + 1]; ++e) acc -= lu[sw.src[e]] * w[sw.col[e]];
+        if (sw.has_diag) acc /= lu[sw.diag_src[sl]];
+        w[i] = acc;
+      }
+  };
+  if (!transpose) {
+    run(s.sl);
+    run(s.su);
+  } else {
+    run(s.sut);
+    run(s.slt);
+  }
+  for (int i = 0; i < nx; ++i) z[s.perm[i]] = w[i];
+  return RH_OK;
+}
+
+rh_status check_levels(const Symbolic& s) {
+  for (const Sweep* sw : {&s.sl, &s.su, &s.sut, &s.slt}) {
+    std::vector<int> lv(s.nx, -1);
+    for (int l = 0; l < sw->nlev; ++l)
+      for (int q = sw->lev_ptr[l]; q < sw->lev_ptr[l + 1]; ++q) {
+        if (lv[sw->rows[q]] != -1) return RH_ERR_STATE;
+        lv[sw->rows[q]] = l;
+      }
+    for (int i = 0; i < s.nx; ++i)
+      if (lv[i] < 0) return RH_ERR_STATE;
+    for (int l = 0; l < sw->nlev; ++l)
+      for (int q = sw->lev_ptr[l]; q < sw->lev_ptr[l + 1]; ++q)
+        for (int e = sw->ptr[q]; e < sw->ptr[q + 1]; ++e)
+          if (lv[sw->col[e]] >= l) return RH_ERR_STATE;
+  }
+  return RH_OK;
+}
+
+}  // namespace rh

@@ -1,0 +1,94 @@
+// Device-side view of one analysed network and the launch wrappers of the
+// condensation hot path. All pointers are HIP device memory owned by rh_net.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rh {
+
+struct DevSweep {
+  int nlev = 0;
+  const int* lev_ptr = nullptr;   // nlev + 1
+  const int* rows = nullptr;      // nx
+  const int* ptr = nullptr;       // nx + 1
+  const int* col = nullptr;       // entries
+  const int* src = nullptr;       // entries -> LU position
+  const int* diag_src = nullptr;  // nx (U-type sweeps) or null
+  double* val = nullptr;          // entries, transcribed after refactorisation
+  double* dinv = nullptr;         // nx reciprocal pivots (U-type) or null
+  int nnz = 0;
+};
+
+struct DevNet {
+  int nb, nl, ng, nx, nu, m, nw, nlim, ref, ref_gen;
+  double base, c2_ref, c1_ref, cost_rank1;
+  const double *c2, *c1, *c0;
+  const int* pg_u;
+  // lines and buses
+  const int *lf, *lt;
+  const double *gff, *bff, *gft, *bft;
+  const int *th_nat, *vmx_nat, *vmu;
+  const int *line_w, *line_wsrc;
+  const int *ref_lines, *ref_ends;
+  int n_ref_lines;
+  const int *perm, *iperm;
+  // LU and refactorisation
+  int nnz_lu, max_row;
+  const int *lu_ptr, *lu_col, *lu_diag;
+  const int *rf_kptr, *rf_src, *rf_dst;
+  const int *rf_rows;             // rows in L-level order (= sl.rows)
+  const int *rf_lev_ptr;
+  int rf_nlev;
+  DevSweep sl, su, sut, slt;
+  // G_u, A, K patterns
+  int nnz_gu, nnz_a, nnz_k;
+  const int *gu_ptr, *gu_col, *gucsc_ptr, *gucsc_row, *gucsc_from;
+  const int *a_ptr, *a_col, *acsc_ptr, *acsc_row, *acsc_from;
+  const int *k_ptr, *k_col;
+  const int *kg_hl_ptr, *kg_hl_idx, *kg_ata_ptr, *kg_a1, *kg_a2, *kg_row, *kg_diag;
+  const int* sig_map;
+  const double* k_cdiag;
+  // evaluation gather
+  int d_total, d_lu, d_gu, d_a, d_g, d_h, src_u, src_total;
+  const int *eg_ptr, *eg_idx;
+  const double *eg_coef, *eg_cst;
+  // workspaces
+  double* src;        // [LF | u | pd | qd]
+  double* dst;        // [luval | gu | a | g | h]
+  double* hl;         // 10 per line
+  double* kval;       // nnz_k
+  double* rt;         // nw: condensed residual rt in w order
+  double* pw;         // nw: step in w order (recovery)
+  double* vtmp;       // nu: scratch vector (Cholesky solve)
+  double* panel;      // global panel workspace (when not in LDS)
+  size_t panel_doubles;
+  int* status;        // [0] Cholesky status, [1] failing index, [2] small pivot flag, [3] pivot row
+};
+
+hipError_t launch_eval(const DevNet& d, const double* x, const double* u, const double* lam,
+                       const double* y, bool hessian, hipStream_t st);
+hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double* sig_u,
+                             const double* sig_s, hipStream_t st);
+hipError_t launch_refactor(const DevNet& d, hipStream_t st);
+hipError_t launch_rtilde(const DevNet& d, const double* r, const double* sig_s, hipStream_t st);
+// mode 0: identity columns [col0, col0 + ncols) (col == nu: the right-hand-side column)
+hipError_t launch_condense(const DevNet& d, int col0, int ncols, int width, bool lds,
+                           const double* r, double* K, long ldk, double* rhs, hipStream_t st);
+// recovery of p_x and p_lambda from p_u (one column)
+hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, double* p,
+                          hipStream_t st);
+hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,
+                              hipStream_t st);
+hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
+// Cholesky of the lower triangle of K + delta I in place, L y = b (b is
+// destroyed), then L^T x = y with x written over y. status[0..1] device.
+hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
+                                 double* y, int* status, hipStream_t st);
+hipError_t launch_eval_objective(const DevNet& d, const double* u, double* f, hipStream_t st);
+int max_lds_bytes();
+// Allow dynamic LDS up to `bytes` for the LDS-resident condensation kernels.
+void prepare_lds_kernels(size_t bytes);
+
+}  // namespace rh

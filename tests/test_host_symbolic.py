@@ -1,0 +1,104 @@
+"""Host logic of the HIP library, run on the CPU: the C ABI loads and exports
+every declared symbol; the symbolic analysis (index maps, patterns, ordering,
+symbolic LU, level sets, refactorisation schedule) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthnet
+from oracle.model import Model
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2203_11875_amd import api
+    return api
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_2203_11875_amd import _abi
+    header = open(os.path.join(ROOT, "include", "rhipm.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    names = set(re.findall(r"\b(rh_[a-z_]+)\s*\(", header))
+    assert names, "no declarations parsed"
+    lib = ctypes.CDLL(_abi.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert names == set(_abi.SIGNATURES), "binding and header disagree"
+
+
+NETS = [synthnet.case9(0), synthnet.small(5, 7, 2, seed=1), synthnet.case118(0),
+        synthnet.case300(0), synthnet.case1354(0)]
+
+
+@pytest.mark.parametrize("net", NETS, ids=lambda n: n.name)
+def test_dimensions_and_index_maps_match_oracle(net):
+    S = _lib().Symbolic(net)
+    M = Model(net)
+    assert (S.info["nx"], S.info["nu"], S.info["m"]) == (M.nx, M.nu, M.m)
+    xk, xb, uk, ur = S.index_maps()
+    assert np.array_equal(xk, M.x_kind) and np.array_equal(xb, M.x_bus)
+    assert np.array_equal(uk, M.u_kind) and np.array_equal(ur, M.u_ref)
+
+
+@pytest.mark.parametrize("net", NETS, ids=lambda n: n.name)
+def test_levels_valid(net):
+    S = _lib().Symbolic(net)
+    assert S.check_levels() == 0
+    assert S.info["levels_lower"] >= 1 and S.info["nnz_lu"] >= S.info["nnz_gx"]
+
+
+@pytest.mark.parametrize("net", NETS, ids=lambda n: n.name)
+def test_patterns_cover_oracle_and_host_refactorisation_solves(net):
+    """The G_x pattern holds every structural nonzero of the oracle's G_x, the
+    pivot order is a permutation, and refactorising with the device schedule
+    then sweeping the level sets solves G_x z = b and G_x^T z = b."""
+    S = _lib().Symbolic(net)
+    M = Model(net)
+    rng = np.random.default_rng(0)
+    x, u = M.join(rng.normal(0, .1, net.nb), rng.uniform(.95, 1.05, net.nb),
+                  rng.uniform(0, 1, net.ng))
+    G, _, _ = M.jacobians(x, u)
+    Gx = G[:, M.nu:].tocsr()
+    ptr, col, perm = S.gx_pattern()
+    assert np.array_equal(np.sort(perm), np.arange(M.nx))
+    pat = {(r, c) for r in range(M.nx) for c in col[ptr[r]:ptr[r + 1]]}
+    Gc = Gx.tocoo()
+    assert all((r, c) in pat for r, c in zip(Gc.row, Gc.col))
+    vals = np.asarray(Gx[np.repeat(np.arange(M.nx), np.diff(ptr)), col]).ravel()
+    Gd = Gx.toarray()
+    for tr in (False, True):
+        b = rng.normal(size=M.nx)
+        z = S.host_solve(vals, b, transpose=tr)
+        A = Gd.T if tr else Gd
+        assert np.abs(A @ z - b).max() <= 1e-10 * max(1.0, np.abs(b).max()) * np.abs(Gd).max()
+
+
+def test_rejects_bad_networks():
+    api = _lib()
+    net = synthnet.case9(0)
+    bad = net.copy(bus_type=np.full(net.nb, 1, np.int32))          # no reference bus
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        api.Symbolic(bad)
+    f = net.f.copy()
+    f[0] = net.t[0]                                                  # self loop
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        api.Symbolic(net.copy(f=f))
+    iso = synthnet.make_network(6, 5, 2, seed=0, load_frac=0.5)      # tree
+    f, t = iso.f.copy(), iso.t.copy()                                 # cut bus 5 off
+    keep = (f != 5) & (t != 5)
+    cut = iso.copy(f=f[keep], t=t[keep], r=iso.r[keep], x=iso.x[keep], b=iso.b[keep],
+                   rate=iso.rate[keep])
+    if 5 not in cut.gen_bus:
+        with pytest.raises(RuntimeError, match="singular"):
+            api.Symbolic(cut)
+
+
+def test_nine_bus_sizes_and_9241_analysis():
+    S = _lib().Symbolic(synthnet.case9241(0))
+    assert (S.info["nx"], S.info["nu"]) == (17036, 2889)
+    assert S.check_levels() == 0
