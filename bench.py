@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--lds", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one device copy of 512 MiB first (a plain copy kernel of known "
+                         "size that scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -148,6 +151,12 @@ def main():
 
     net = workload(args.workload)
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     G = api.Net(net, panel_width=args.width, lds_panel=args.lds)
     args_np = iterate(G, net)
     T = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=dev)

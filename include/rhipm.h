@@ -107,6 +107,7 @@ typedef struct {
   int64_t refactor_ops;                /* multiply-adds of one refactorisation   */
   int64_t max_lu_row;
   int64_t panel_width, lds_panel;      /* chosen launch shape of the condensation */
+  int64_t max_row_ops;                 /* refactorisation multiply-adds of one row */
 } rh_info;
 
 typedef struct rh_symbolic rh_symbolic;
@@ -215,6 +216,13 @@ enum { RH_PHASE_EVAL = 0, RH_PHASE_REFACTOR, RH_PHASE_CONDENSE, RH_PHASE_SYMMETR
        RH_PHASE_CHOLESKY, RH_PHASE_RECOVER, RH_NPHASES };
 rh_status rh_profile_enable(rh_net* net, int32_t on);
 rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
+/* In-kernel phase timestamps (device wall clock, 100 MHz) of the first
+ * work-group of the last condensation launched while profiling was on:
+ * [0] start, [1] panel filled, [2] after L, [3] after U (Z), [4] after the
+ * Hessian product, [5] after U^T, [6] after L^T (Psi), [7] columns written.
+ * [16 + l] end of level l of the L sweep. Host array of 256 entries;
+ * synchronises the stream. */
+rh_status rh_profile_kernel_trace(rh_net* net, int64_t* ticks);
 
 #ifdef __cplusplus
 }

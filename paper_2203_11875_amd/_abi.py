@@ -37,7 +37,7 @@ class rh_info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "nx", "nu", "m", "nb", "nl", "ng", "nnz_gx", "nnz_lu", "nnz_gu", "nnz_a", "nnz_k",
         "levels_lower", "levels_upper", "refactor_ops", "max_lu_row", "panel_width",
-        "lds_panel")]
+        "lds_panel", "max_row_ops")]
 
 
 # name -> (restype, argtypes); every symbol declared in include/rhipm.h
@@ -65,6 +65,7 @@ SIGNATURES = {
     "rh_solve_condensed_kkt": (C.c_int, [vp, vp, C.c_int64, C.c_double, vp, vp, vp, vp]),
     "rh_profile_enable": (C.c_int, [vp, C.c_int32]),
     "rh_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "rh_profile_kernel_trace": (C.c_int, [vp, C.POINTER(C.c_int64)]),
 }
 
 PHASES = ["eval", "refactor", "condense", "symmetrize", "cholesky", "recover"]

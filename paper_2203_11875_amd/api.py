@@ -205,6 +205,14 @@ class Net:
         _check(lib().rh_profile_read(self.h, ms, calls), "rh_profile_read")
         return {name: (float(ms[k]), int(calls[k])) for k, name in enumerate(_abi.PHASES)}
 
+    def profile_kernel_trace(self):
+        t = (C.c_int64 * 256)()
+        _check(lib().rh_profile_kernel_trace(self.h, t), "rh_profile_kernel_trace")
+        names = ["start", "filled", "L", "U", "hvp", "UT", "LT", "written"]
+        out = {names[k]: (t[k] - t[0]) / 100.0 for k in range(8)}   # microseconds
+        out["levels_L"] = [(t[16 + k] - t[1]) / 100.0 for k in range(self.info["levels_lower"])]
+        return out
+
     def solve_condensed_kkt(self, K, delta_w, rhs, r):
         """Returns (p, status) where status is the rh_status integer; raises on
         hard errors only."""

@@ -125,6 +125,43 @@ void build_sweep(Sweep& sw, int n, const std::vector<int>& level, int nlev,
     }
     sw.lev_ptr[l + 1] = int(sw.rows.size());
   }
+  // Lanes per row of each level: enough that a lane handles about two
+  // entries of the longest row, but not more than fit in one pass of a
+  // 256-thread work-group over the level; a power of two, at most 32.
+  sw.lev_lanes.assign(nlev, 1);
+  for (int l = 0; l < nlev; ++l) {
+    int rows = sw.lev_ptr[l + 1] - sw.lev_ptr[l];
+    int maxlen = 0;
+    for (int q = sw.lev_ptr[l]; q < sw.lev_ptr[l + 1]; ++q)
+      maxlen = std::max(maxlen, sw.ptr[q + 1] - sw.ptr[q]);
+    int want = 1;
+    while (want < 32 && want * 2 <= (maxlen + 1) / 2) want *= 2;
+    int fit = 1;
+    while (fit < 32 && fit * 2 * rows <= 256) fit *= 2;
+    sw.lev_lanes[l] = std::max(1, std::min(want, fit));
+  }
+  sw.lev_base.assign(nlev, 0);
+  sw.lev_len.assign(nlev, 0);
+  sw.ell_col.clear();
+  sw.ell_src.clear();
+  for (int l = 0; l < nlev; ++l) {
+    const int q0 = sw.lev_ptr[l], R = sw.lev_ptr[l + 1] - q0;
+    int len = 0;
+    for (int q = q0; q < q0 + R; ++q) len = std::max(len, sw.ptr[q + 1] - sw.ptr[q]);
+    sw.lev_base[l] = int(sw.ell_col.size());
+    sw.lev_len[l] = len;
+    for (int k = 0; k < len; ++k)
+      for (int r = 0; r < R; ++r) {
+        const int q = q0 + r, e = sw.ptr[q] + k;
+        if (e < sw.ptr[q + 1]) {
+          sw.ell_col.push_back(sw.col[e]);
+          sw.ell_src.push_back(sw.src[e]);
+        } else {
+          sw.ell_col.push_back(sw.rows[q]);
+          sw.ell_src.push_back(-1);
+        }
+      }
+  }
 }
 
 }  // namespace
@@ -369,6 +406,51 @@ rh_status analyze(const rh_network_desc& d, const rh_options* /*opts*/, Symbolic
     }
   }
   s.refactor_ops = long(s.rf_op_src.size());
+  s.rf_piv.assign(s.lu_col.size(), -1);
+  s.rf_dst_local.assign(s.rf_op_dst.size(), 0);
+  s.max_row_ops = 0;
+  s.max_row_lower = 0;
+  for (int i = 0; i < nx; ++i) {
+    for (int p = s.lu_ptr[i]; p < s.lu_diag[i]; ++p) s.rf_piv[p] = s.lu_diag[s.lu_col[p]];
+    for (int o = s.rf_kptr[s.lu_ptr[i]]; o < s.rf_kptr[s.lu_diag[i]]; ++o)
+      s.rf_dst_local[o] = s.rf_op_dst[o] - s.lu_ptr[i];
+    s.max_row_ops = std::max(s.max_row_ops, s.rf_kptr[s.lu_diag[i]] - s.rf_kptr[s.lu_ptr[i]]);
+    s.max_row_lower = std::max(s.max_row_lower, s.lu_diag[i] - s.lu_ptr[i]);
+  }
+  // Per level: as many rows in flight as the LDS allows. A row stages its
+  // values, the U entries its elimination reads, its pivots (doubles) and
+  // the op offsets and pointers (ints) in LDS.
+  s.rf_lmeta.assign(6 * s.sl.nlev, 0);
+  s.rf_lds_doubles = 0;
+  for (int l = 0; l < s.sl.nlev; ++l) {
+    int mrow = 1, mops = 0, mlow = 0;
+    for (int q = s.sl.lev_ptr[l]; q < s.sl.lev_ptr[l + 1]; ++q) {
+      const int i = s.sl.rows[q];
+      mrow = std::max(mrow, s.lu_ptr[i + 1] - s.lu_ptr[i]);
+      mops = std::max(mops, s.rf_kptr[s.lu_diag[i]] - s.rf_kptr[s.lu_ptr[i]]);
+      mlow = std::max(mlow, s.lu_diag[i] - s.lu_ptr[i]);
+    }
+    const int dbl = mrow + mops + mlow;
+    const int ints = mops + mlow + 1;
+    const int stride = dbl + (ints + 1) / 2;
+    const int rows = s.sl.lev_ptr[l + 1] - s.sl.lev_ptr[l];
+    int lanes = 4;
+    // fewest lanes per row (most rows in flight) whose staging fits in LDS,
+    // but no more groups than rows
+    while (lanes < 64 && (size_t(1024 / lanes) * stride * 8 > size_t(kRefLdsBudget) ||
+                          (1024 / lanes) / 2 >= rows))
+      lanes *= 2;
+    if (size_t(1024 / lanes) * stride * 8 > size_t(kRefLdsBudget))
+      return fail(s, RH_ERR_ARG, "a row of the LU factors is too long for the refactorisation");
+    int* mt = &s.rf_lmeta[6 * l];
+    mt[0] = lanes;
+    mt[1] = stride;
+    mt[2] = mrow;                 // offset of the U sources
+    mt[3] = mrow + mops;          // offset of the pivots
+    mt[4] = dbl;                  // offset (in doubles) of the int area: dst offsets
+    mt[5] = mops;                 // op pointers follow the dst offsets (in ints)
+    s.rf_lds_doubles = std::max(s.rf_lds_doubles, (1024 / lanes) * stride);
+  }
 
   // -------------------------------------------------- w = [u ; x internal]
   auto w_theta = [&](int i) { return s.th_nat[i] >= 0 ? nu + s.iperm[s.th_nat[i]] : -1; };
@@ -498,6 +580,32 @@ rh_status analyze(const rh_network_desc& d, const rh_options* /*opts*/, Symbolic
       kg.ata_ptr[e + 1] = int(kg.ata_a1.size());
     }
     for (int v = 0; v < s.nw; ++v) kg.diag_var[find_pos(s.k_ptr, s.k_col, v, v)] = v;
+  }
+  {
+    const int nblk = (s.nw + kKRowBlock - 1) / kKRowBlock;
+    s.kb_base.assign(nblk, 0);
+    s.kb_len.assign(nblk, 0);
+    s.kell_col.clear();
+    s.kell_pos.clear();
+    for (int bk = 0; bk < nblk; ++bk) {
+      const int v0 = bk * kKRowBlock;
+      int len = 0;
+      for (int v = v0; v < std::min(s.nw, v0 + kKRowBlock); ++v)
+        len = std::max(len, s.k_ptr[v + 1] - s.k_ptr[v]);
+      s.kb_base[bk] = int(s.kell_col.size());
+      s.kb_len[bk] = len;
+      for (int kk = 0; kk < len; ++kk)
+        for (int t = 0; t < kKRowBlock; ++t) {
+          const int v = v0 + t;
+          if (v < s.nw && s.k_ptr[v] + kk < s.k_ptr[v + 1]) {
+            s.kell_col.push_back(s.k_col[s.k_ptr[v] + kk]);
+            s.kell_pos.push_back(s.k_ptr[v] + kk);
+          } else {
+            s.kell_col.push_back(v < s.nw ? v : 0);
+            s.kell_pos.push_back(-1);
+          }
+        }
+    }
   }
   s.k_cdiag.assign(s.nw, 0.0);
   for (int g = 0; g < ng; ++g)

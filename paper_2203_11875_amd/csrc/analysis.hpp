@@ -14,6 +14,10 @@
 
 namespace rh {
 
+constexpr int kKRowBlock = 256;
+constexpr int kMaxRowBlocks = 16;   // LDS-resident panels: nu + nx <= 16 * 256
+constexpr int kRefLdsBudget = 155 * 1024;   // bytes of LDS the refactorisation may use
+
 // Per-line record written by the line-evaluation kernel (doubles).
 enum LineSlot : int {
   LF_PF = 0, LF_QF = 1, LF_PT = 2, LF_QT = 3,
@@ -40,6 +44,13 @@ struct Sweep {
   std::vector<int> src;       // entry -> position in the LU value array
   bool has_diag = false;      // divide by the diagonal (U-type sweeps)
   std::vector<int> diag_src;  // slot -> position of the diagonal in LU values
+  std::vector<int> lev_lanes; // lanes that cooperate on one row in each level
+  // Padded per-level layout: level l holds rows lev_ptr[l] .. lev_ptr[l+1]
+  // (R of them) and lev_len[l] entry columns; entry k of the r-th row sits at
+  // lev_base[l] + k * R + r, so its address needs no row pointer. Padding
+  // entries point at their own row with source -1 (value 0).
+  std::vector<int> lev_base, lev_len;
+  std::vector<int> ell_col, ell_src;
 };
 
 struct Gather {          // dst[e] = c[e] + sum_t coef[t] * src[idx[t]]
@@ -90,6 +101,10 @@ struct Symbolic {
   std::vector<int> rf_op_src, rf_op_dst;   // U source position, destination position
   std::vector<int> rf_lower_ptr;           // per internal row: first lower-entry id
   int max_row = 0;
+  int max_row_ops = 0;                     // refactorisation multiply-adds of one row
+  int max_row_lower = 0;                   // lower entries of one row
+  std::vector<int> rf_piv;                 // per LU position (lower entries): pivot position
+  std::vector<int> rf_dst_local;           // per op: destination offset within its row
   long refactor_ops = 0;
   // sweeps
   Sweep sl, su, sut, slt;
@@ -99,6 +114,16 @@ struct Symbolic {
   // K pattern (w x w), CSR with sorted columns
   std::vector<int> k_ptr, k_col;
   KGather kg;
+  // K rows in blocks of kKRowBlock (one row per thread of the condensation
+  // work-group), padded to the longest row of the block: entry k of row
+  // kKRowBlock*b + t sits at kb_base[b] + k*kKRowBlock + t; kell_pos maps
+  // each slot to its CSR entry (-1 = padding, value 0, column = own row).
+  std::vector<int> kb_base, kb_len, kell_col, kell_pos;
+  // refactorisation launch shape per level: lanes per row and the LDS
+  // layout of one row's staging area (in doubles): stride, offsets of the U
+  // sources, the pivots, the destination offsets and the op pointers
+  std::vector<int> rf_lmeta;               // 6 per level
+  int rf_lds_doubles = 0;                  // LDS the refactorisation needs
   std::vector<double> k_cdiag;             // constant diagonal (2 c2 base^2 on Pg)
   std::vector<int> sig_map;                // w -> index into [Sigma_u ; Sigma_x(natural)]
   // evaluation gather: dst = [luval | gu | a | g(natural) | h]

@@ -16,8 +16,16 @@ struct DevSweep {
   const int* col = nullptr;       // entries
   const int* src = nullptr;       // entries -> LU position
   const int* diag_src = nullptr;  // nx (U-type sweeps) or null
+  const int* lev_lanes = nullptr; // nlev: lanes per row in each level
+  const int* lev_base = nullptr;  // nlev: padded-layout offset of each level
+  const int* lev_len = nullptr;   // nlev: padded row length of each level
+  const int* ell_col = nullptr;   // padded layout: column
+  const int* ell_src = nullptr;   // padded layout: LU position or -1
+  double* ell_val = nullptr;      // padded layout: value (transcribed)
+  int ell_n = 0;
   double* val = nullptr;          // entries, transcribed after refactorisation
-  double* dinv = nullptr;         // nx reciprocal pivots (U-type) or null
+  double* dinv = nullptr;         // nx reciprocal pivots (all ones for unit-diagonal sweeps)
+  int unit = 0;                   // 1: unit diagonal (L and L^T sweeps)
   int nnz = 0;
 };
 
@@ -38,6 +46,8 @@ struct DevNet {
   int nnz_lu, max_row;
   const int *lu_ptr, *lu_col, *lu_diag;
   const int *rf_kptr, *rf_src, *rf_dst;
+  const int *rf_piv, *rf_dst_local;
+  int max_row_ops, max_row_lower, rf_groups;   // rf_groups rows factored at once
   const int *rf_rows;             // rows in L-level order (= sl.rows)
   const int *rf_lev_ptr;
   int rf_nlev;
@@ -49,6 +59,11 @@ struct DevNet {
   const int *k_ptr, *k_col;
   const int *kg_hl_ptr, *kg_hl_idx, *kg_ata_ptr, *kg_a1, *kg_a2, *kg_row, *kg_diag;
   const int* sig_map;
+  const int *kb_base, *kb_len, *kell_col, *kell_pos;
+  double* kell_val;
+  int kell_n, kb_n;
+  const int* rf_lmeta;    // 6 ints per refactorisation level
+  int rf_lds_doubles;
   const double* k_cdiag;
   // evaluation gather
   int d_total, d_lu, d_gu, d_a, d_g, d_h, src_u, src_total;
@@ -62,9 +77,12 @@ struct DevNet {
   double* rt;         // nw: condensed residual rt in w order
   double* pw;         // nw: step in w order (recovery)
   double* vtmp;       // nu: scratch vector (Cholesky solve)
+  double* rinv;       // nx: reciprocal pivots written by the refactorisation
+  const int* rf_info; // per refactorisation slot: row, lu_ptr, lu_ptr+1, diag, op0, nops
   double* panel;      // global panel workspace (when not in LDS)
   size_t panel_doubles;
   int* status;        // [0] Cholesky status, [1] failing index, [2] small pivot flag, [3] pivot row
+  long long* trace;   // in-kernel phase timestamps of work-group 0 (null = off)
 };
 
 hipError_t launch_eval(const DevNet& d, const double* x, const double* u, const double* lam,
@@ -88,6 +106,10 @@ hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, doubl
                                  double* y, int* status, hipStream_t st);
 hipError_t launch_eval_objective(const DevNet& d, const double* u, double* f, hipStream_t st);
 int max_lds_bytes();
+// LDS one row of the refactorisation stages (row, U sources, pivots, schedule).
+size_t refactor_lds_per_row(const DevNet& d);
+// LDS of the level metadata the condensation kernel stages (all four sweeps).
+size_t condense_meta_bytes(const DevNet& d);
 // Allow dynamic LDS up to `bytes` for the LDS-resident condensation kernels.
 void prepare_lds_kernels(size_t bytes);
 

@@ -164,22 +164,27 @@ __global__ void __launch_bounds__(kBlock) k_gather(int n, const int* __restrict_
 __global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* sig_x,
                                                       const double* sig_u,
                                                       const double* sig_s) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= d.nnz_k) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.kell_n) return;
+  const int e = d.kell_pos[t];
+  if (e < 0) {
+    d.kell_val[t] = 0.0;
+    return;
+  }
   double acc = 0.0;
-  for (int t = d.kg_hl_ptr[e]; t < d.kg_hl_ptr[e + 1]; ++t) acc += d.hl[d.kg_hl_idx[t]];
+  for (int q = d.kg_hl_ptr[e]; q < d.kg_hl_ptr[e + 1]; ++q) acc += d.hl[d.kg_hl_idx[q]];
   const double* av = d.dst + d.d_a;
-  for (int t = d.kg_ata_ptr[e]; t < d.kg_ata_ptr[e + 1]; ++t) {
-    const int j = d.kg_row[t];
+  for (int q = d.kg_ata_ptr[e]; q < d.kg_ata_ptr[e + 1]; ++q) {
+    const int j = d.kg_row[q];
     const double w = sig_s[j] + (j == 0 ? d.cost_rank1 : 0.0);
-    acc += av[d.kg_a1[t]] * av[d.kg_a2[t]] * w;
+    acc += av[d.kg_a1[q]] * av[d.kg_a2[q]] * w;
   }
   const int v = d.kg_diag[e];
   if (v >= 0) {
-    const int s = d.sig_map[v];
-    acc += (s < d.nu ? sig_u[s] : sig_x[s - d.nu]) + d.k_cdiag[v];
+    const int sm = d.sig_map[v];
+    acc += (sm < d.nu ? sig_u[sm] : sig_x[sm - d.nu]) + d.k_cdiag[v];
   }
-  d.kval[e] = acc;
+  d.kell_val[t] = acc;
 }
 
 __global__ void k_fill_int(int* p, int n, int v) {
@@ -188,42 +193,62 @@ __global__ void k_fill_int(int* p, int n, int v) {
 }
 
 // ------------------------------------------------------- refactorisation
-// One work-group; each wave factors one row at a time (rows of a level are
-// independent). The row is staged in LDS; for each lower entry (i, k) in
-// increasing k: l = a_ik / u_kk, then a_ij -= l * u_kj over row k of U, the
-// lanes of the wave taking distinct j. Rows of U read here were finished in
-// earlier levels.
-constexpr int kRefWaves = 16;
+// One work-group of 1024 threads walks the levels of the L sweep (rows of a
+// level are independent). In each level, groups of lanes (a per-level power
+// of two chosen by the analysis so that as many rows as the LDS allows are in
+// flight) each factor one row: the row, the U entries its elimination reads
+// (rows finished in earlier levels) and its pivot reciprocals are staged in
+// LDS with all loads of the row in flight together; then for each lower entry
+// (i, k) in increasing k: l = a_ik / u_kk and a_ij -= l * u_kj over row k of
+// U, the lanes of the group taking distinct j. The reciprocal of the new
+// pivot is kept for the rows that follow.
+constexpr int kRefThreads = 1024;
 
-__global__ void __launch_bounds__(64 * kRefWaves) k_refactor(DevNet d) {
-  extern __shared__ double rowbuf_all[];
+__global__ void __launch_bounds__(kRefThreads) k_refactor(DevNet d) {
+  extern __shared__ double ref_lds[];
   double* lu = d.dst + d.d_lu;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  double* rowbuf = rowbuf_all + (size_t)wave * d.max_row;
   for (int lev = 0; lev < d.rf_nlev; ++lev) {
     const int s0 = d.rf_lev_ptr[lev], s1 = d.rf_lev_ptr[lev + 1];
-    for (int slot = s0 + wave; slot < s1; slot += kRefWaves) {
-      const int i = d.rf_rows[slot];
-      const int rp0 = d.lu_ptr[i], rp1 = d.lu_ptr[i + 1], rd = d.lu_diag[i];
+    const int* mt = d.rf_lmeta + 6 * lev;
+    const int lanes = mt[0], stride = mt[1];
+    const int groups = kRefThreads / lanes;
+    const int g = threadIdx.x / lanes, lane = threadIdx.x & (lanes - 1);
+    double* rowbuf = ref_lds + (size_t)g * stride;
+    double* srcbuf = rowbuf + mt[2];
+    double* pivbuf = rowbuf + mt[3];
+    int* dstbuf = reinterpret_cast<int*>(rowbuf + mt[4]);
+    int* kbuf = dstbuf + mt[5];
+    for (int slot = s0 + g; slot < s1; slot += groups) {
+      const int4 i0 = *reinterpret_cast<const int4*>(d.rf_info + 8 * slot);
+      const int2 i1 = *reinterpret_cast<const int2*>(d.rf_info + 8 * slot + 4);
+      const int i = i0.x, rp0 = i0.y, rp1 = i0.z, rd = i0.w, o0 = i1.x, nops = i1.y;
+      const int nlow = rd - rp0;
       double amax = 0.0;
-      for (int t = lane; t < rp1 - rp0; t += 64) {
+      for (int t = lane; t < rp1 - rp0; t += lanes) {
         const double v = lu[rp0 + t];
         rowbuf[t] = v;
         amax = fmax(amax, fabs(v));
       }
-      for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+      for (int t = lane; t < nops; t += lanes) {
+        srcbuf[t] = lu[d.rf_src[o0 + t]];
+        dstbuf[t] = d.rf_dst_local[o0 + t];
+      }
+      for (int t = lane; t < nlow; t += lanes) pivbuf[t] = d.rinv[d.lu_col[rp0 + t]];
+      for (int t = lane; t <= nlow; t += lanes) kbuf[t] = d.rf_kptr[rp0 + t] - o0;
+      for (int off = lanes / 2; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
       __builtin_amdgcn_wave_barrier();
-      for (int p = rp0; p < rd; ++p) {
-        const double l = rowbuf[p - rp0] / lu[d.lu_diag[d.lu_col[p]]];
+      for (int q = 0; q < nlow; ++q) {
+        const double l = rowbuf[q] * pivbuf[q];
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) rowbuf[p - rp0] = l;
-        for (int o = d.rf_kptr[p] + lane; o < d.rf_kptr[p + 1]; o += 64)
-          rowbuf[d.rf_dst[o] - rp0] -= l * lu[d.rf_src[o]];
+        if (lane == 0) rowbuf[q] = l;
+        for (int t = kbuf[q] + lane; t < kbuf[q + 1]; t += lanes)
+          rowbuf[dstbuf[t]] = fma(-l, srcbuf[t], rowbuf[dstbuf[t]]);
         __builtin_amdgcn_wave_barrier();
       }
-      for (int t = lane; t < rp1 - rp0; t += 64) lu[rp0 + t] = rowbuf[t];
+      for (int t = lane; t < rp1 - rp0; t += lanes) lu[rp0 + t] = rowbuf[t];
       if (lane == 0) {
         const double piv = rowbuf[rd - rp0];
+        d.rinv[i] = 1.0 / piv;
         if (!(fabs(piv) > 1e-14 * amax)) {
           d.status[2] = 1;
           d.status[3] = i;
@@ -244,7 +269,8 @@ __global__ void __launch_bounds__(kBlock) k_transcribe(DevNet d) {
   for (int s = 0; s < 4; ++s) {
     const DevSweep& w = *sw[s];
     for (int t = tid; t < w.nnz; t += stride) w.val[t] = lu[w.src[t]];
-    if (w.dinv)
+    for (int t = tid; t < w.ell_n; t += stride) w.ell_val[t] = w.ell_src[t] >= 0 ? lu[w.ell_src[t]] : 0.0;
+    if (!w.unit)
       for (int t = tid; t < d.nx; t += stride) w.dinv[t] = 1.0 / lu[w.diag_src[t]];
   }
 }
@@ -267,28 +293,176 @@ __global__ void __launch_bounds__(kBlock) k_rtilde(DevNet d, const double* r, co
 }
 
 // ------------------------------------------------- condensation pipeline
-// One level-ordered triangular sweep over a panel X (rows x W, W contiguous).
-// Rows of one level are independent; work items are (row, column) pairs with
-// the column fastest so that neighbouring lanes share matrix entries.
-template <int W>
-__device__ __forceinline__ void sweep(const DevSweep& s, double* X) {
-  const int tid = threadIdx.x, T = blockDim.x;
-  for (int lev = 0; lev < s.nlev; ++lev) {
-    const int s0 = s.lev_ptr[lev], s1 = s.lev_ptr[lev + 1];
-    const int n = (s1 - s0) * W;
-    for (int item = tid; item < n; item += T) {
-      const int slot = s0 + item / W, c = item % W;
-      const int row = s.rows[slot];
-      double acc = X[row * W + c];
-      for (int e = s.ptr[slot]; e < s.ptr[slot + 1]; ++e) acc -= s.val[e] * X[s.col[e] * W + c];
-      if (s.dinv) acc *= s.dinv[slot];
-      X[row * W + c] = acc;
-    }
+// Work-group barrier. When every value exchanged between threads lives in
+// LDS, only LDS operations need to complete before the barrier: global loads
+// issued ahead of time (the next level's matrix entries) stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <bool LDS>
+__device__ __forceinline__ void block_sync() {
+  if (LDS)
+    lds_barrier();
+  else
     __syncthreads();
+}
+
+// Level metadata of one sweep, staged in LDS at kernel start:
+// [slot0, rows, base, len, log2(lanes)] per level.
+constexpr int kMeta = 5;
+
+__device__ __forceinline__ void stage_meta(const DevSweep& s, int* meta) {
+  for (int l = threadIdx.x; l < s.nlev; l += blockDim.x) {
+    meta[kMeta * l + 0] = s.lev_ptr[l];
+    meta[kMeta * l + 1] = s.lev_ptr[l + 1] - s.lev_ptr[l];
+    meta[kMeta * l + 2] = s.lev_base[l];
+    meta[kMeta * l + 3] = s.lev_len[l];
+    meta[kMeta * l + 4] = __ffs(s.lev_lanes[l]) - 1;
+  }
+}
+
+// Entries of one level that a thread loads ahead of time: up to PF entries
+// of its first row, that row's index and its reciprocal pivot.
+constexpr int PF = 4;
+struct LevelFetch {
+  int col[PF];
+  double val[PF];
+  int row;
+  double dinv;
+};
+
+__device__ __forceinline__ void fetch_level(const DevSweep& s, const int* m, LevelFetch& f) {
+  // branch-free (addresses clamped, values masked) so that the number of
+  // loads in flight is the same on every path and waits stay exact
+  const int R = m[1], ls = m[4];
+  const int g = threadIdx.x >> ls, lane = threadIdx.x & ((1 << ls) - 1);
+  const bool live = g < R;
+  const int base = m[2], Lm = m[3];
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    const int k = lane + (j << ls);
+    const bool ok = live && k < Lm;
+    const int idx = ok ? base + k * R + g : 0;
+    const int c = s.ell_col[idx];
+    const double v = s.ell_val[idx];
+    f.col[j] = ok ? c : 0;
+    f.val[j] = ok ? v : 0.0;
+  }
+  const int q = live ? m[0] + g : 0;
+  f.row = s.rows[q];
+  f.dinv = s.dinv[q];
+}
+
+// One level of a triangular sweep over a panel X (rows x W, the W columns of
+// a row contiguous). Rows of a level are independent. Each row is taken by a
+// group of 2^ls lanes (chosen per level from its longest row); each lane
+// accumulates a strided share of the row's entries for all W columns, and the
+// group reduces with cross-lane shuffles. The summation order depends only on
+// the level structure, so results repeat bitwise and do not depend on W.
+template <int W, bool LDS>
+__device__ __forceinline__ void sweep_level(const DevSweep& s, const int* m, const LevelFetch& f,
+                                            double* X) {
+  const int s0 = m[0], R = m[1], base = m[2], Lm = m[3], ls = m[4];
+  if (Lm == 0 && s.unit) return;    // nothing changes in this level: no barrier needed
+  const int S = 1 << ls;
+  const int g = threadIdx.x >> ls, lane = threadIdx.x & (S - 1), G = blockDim.x >> ls;
+  for (int r = g; r < R; r += G) {
+    double acc[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] = 0.0;
+    int row, k0;
+    double dv;
+    if (r == g) {
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        const double* xc = X + f.col[j] * W;
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[c] = fma(f.val[j], xc[c], acc[c]);
+      }
+      row = f.row;
+      dv = f.dinv;
+      k0 = lane + PF * S;
+    } else {
+      row = s.rows[s0 + r];
+      dv = s.dinv[s0 + r];
+      k0 = lane;
+    }
+    for (int k = k0; k < Lm; k += S) {
+      const int idx = base + k * R + r;
+      const double v = s.ell_val[idx];
+      const double* xc = X + s.ell_col[idx] * W;
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] = fma(v, xc[c], acc[c]);
+    }
+    for (int off = S >> 1; off > 0; off >>= 1)
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] += __shfl_xor(acc[c], off);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        X[row * W + c] = (X[row * W + c] - acc[c]) * dv;
+      }
+    }
+  }
+  block_sync<LDS>();
+}
+
+// A whole sweep, level by level. Entries come from the padded per-level
+// layout, whose addresses need no row pointers, so the loads of level l+1
+// are issued before level l is computed (two register sets used in turn, so
+// the wait for one level's loads never waits for the next level's).
+template <int W, bool LDS>
+__device__ __forceinline__ void sweep(const DevSweep& s, const int* meta, double* X,
+                                      long long* lt = nullptr) {
+  LevelFetch a, b;
+  const int n = s.nlev;
+  fetch_level(s, meta, a);
+  for (int lev = 0; lev < n; lev += 2) {
+    if (lev + 1 < n) fetch_level(s, meta + kMeta * (lev + 1), b);
+    sweep_level<W, LDS>(s, meta + kMeta * lev, a, X);
+    if (lt && threadIdx.x == 0) lt[lev] = wall_clock64();
+    if (lev + 1 >= n) break;
+    if (lev + 2 < n) fetch_level(s, meta + kMeta * (lev + 2), a);
+    sweep_level<W, LDS>(s, meta + kMeta * (lev + 1), b, X);
+    if (lt && threadIdx.x == 0) lt[lev + 1] = wall_clock64();
   }
 }
 
 enum { MODE_COLUMNS = 0, MODE_RECOVER = 1 };
+
+// Phase timestamp of work-group 0 (wall clock) when tracing is on.
+__device__ __forceinline__ void tick(const DevNet& d, int k) {
+  if (d.trace && blockIdx.x == 0 && threadIdx.x == 0) d.trace[k] = wall_clock64();
+}
+
+// Row kKRowBlock * bk + tid of H = K [V ; Z] (+ rt for the right-hand-side /
+// recovery column), from the padded row-block layout of K.
+template <int W>
+__device__ __forceinline__ void hvp_row(const DevNet& d, const double* P, int bk, int tid,
+                                        int jc0, int mode, double (&h)[W]) {
+  const int v = bk * kKRowBlock + tid;
+  const int base = d.kb_base[bk], len = d.kb_len[bk];
+  double acc[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < len; ++k) {
+    const int idx = base + k * kKRowBlock + tid;
+    const double kv = d.kell_val[idx];
+    const double* pc = P + d.kell_col[idx] * W;
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] = fma(kv, pc[c], acc[c]);
+  }
+  const double rt = (v < d.nw) ? d.rt[v] : 0.0;
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int j = jc0 + c;
+    h[c] = (mode == MODE_RECOVER || j == d.nu) ? acc[c] + rt : acc[c];
+  }
+}
 
 // Columns [col0 + blockIdx.x * W, ...) of the condensed matrix (Section 3.3):
 //   Z   = -G_x^{-1} G_u V          (L then U sweep; V = identity columns)
@@ -305,8 +479,20 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
                                                     double* p_out) {
   extern __shared__ double panel_lds[];
   const int nw = d.nw, nu = d.nu, nx = d.nx;
+  // LDS: one panel P (the Hessian product is held in registers and written
+  // back over it); global: two panels P and H per work-group
   double* P = LDS ? panel_lds : d.panel + (size_t)blockIdx.x * 2 * nw * W;
-  double* H = P + (size_t)nw * W;
+  int* meta = reinterpret_cast<int*>(panel_lds + (LDS ? (size_t)nw * W : 0));
+  int* m_sl = meta;
+  int* m_su = m_sl + kMeta * d.sl.nlev;
+  int* m_sut = m_su + kMeta * d.su.nlev;
+  int* m_slt = m_sut + kMeta * d.sut.nlev;
+  stage_meta(d.sl, m_sl);
+  stage_meta(d.su, m_su);
+  stage_meta(d.sut, m_sut);
+  stage_meta(d.slt, m_slt);
+  tick(d, 0);
+  double* H = LDS ? P : P + (size_t)nw * W;
   const int jc0 = col0 + blockIdx.x * W;
   const int tid = threadIdx.x, T = blockDim.x;
   const double* gu = d.dst + d.d_gu;
@@ -332,17 +518,11 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
     }
   }
   __syncthreads();
-  sweep<W>(d.sl, P + nu * W);
-  sweep<W>(d.su, P + nu * W);
-  for (int item = tid; item < nw * W; item += T) {
-    const int v = item / W, c = item % W;
-    double acc = 0.0;
-    for (int e = d.k_ptr[v]; e < d.k_ptr[v + 1]; ++e) acc += d.kval[e] * P[d.k_col[e] * W + c];
-    const int j = jc0 + c;
-    if (mode == MODE_RECOVER || j == nu) acc += d.rt[v];
-    H[item] = acc;
-  }
-  __syncthreads();
+  tick(d, 1);
+  sweep<W, LDS>(d.sl, m_sl, P + nu * W, (d.trace && blockIdx.x == 0) ? d.trace + 16 : nullptr);
+  tick(d, 2);
+  sweep<W, LDS>(d.su, m_su, P + nu * W);
+  tick(d, 3);
   if (mode == MODE_RECOVER) {
     double* px = p_out + nu;
     for (int i = tid; i < nx; i += T) {
@@ -355,25 +535,68 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
       p_out[v] = vin[v];
     }
   }
-  sweep<W>(d.sut, H + nu * W);
-  sweep<W>(d.slt, H + nu * W);
+  // H = K [V ; Z]: thread t takes row kKRowBlock * b + t of every row block.
+  // With the panel in LDS the rows are kept in registers until every thread
+  // has read P, then written over it.
+  if (LDS) {
+    double hreg[kMaxRowBlocks][W];
+#pragma unroll
+    for (int bk = 0; bk < kMaxRowBlocks; ++bk) {
+#pragma unroll
+      for (int c = 0; c < W; ++c) hreg[bk][c] = 0.0;
+      if (bk < d.kb_n) hvp_row<W>(d, P, bk, tid, jc0, mode, hreg[bk]);
+    }
+    block_sync<LDS>();
+#pragma unroll
+    for (int bk = 0; bk < kMaxRowBlocks; ++bk) {
+      const int v = bk * kKRowBlock + tid;
+      if (bk < d.kb_n && v < nw)
+#pragma unroll
+        for (int c = 0; c < W; ++c) H[v * W + c] = hreg[bk][c];
+    }
+    block_sync<LDS>();
+  } else {
+    for (int bk = 0; bk < d.kb_n; ++bk) {
+      double h[W];
+      hvp_row<W>(d, P, bk, tid, jc0, mode, h);
+      const int v = bk * kKRowBlock + tid;
+      if (v < nw)
+#pragma unroll
+        for (int c = 0; c < W; ++c) H[v * W + c] = h[c];
+    }
+    block_sync<LDS>();
+  }
+  tick(d, 4);
+  sweep<W, LDS>(d.sut, m_sut, H + nu * W);
+  tick(d, 5);
+  sweep<W, LDS>(d.slt, m_slt, H + nu * W);
+  tick(d, 6);
   if (mode == MODE_RECOVER) {
     double* plam = p_out + nu + nx + d.m;
     for (int i = tid; i < nx; i += T) plam[d.perm[i]] = -H[(nu + i) * W];
     return;
   }
-  for (int item = tid; item < nu * W; item += T) {
-    const int q = item % nu, c = item / nu;
-    const int j = jc0 + c;
-    if (j >= col_end) continue;
-    double acc = H[q * W + c];
-    for (int e = d.gucsc_ptr[q]; e < d.gucsc_ptr[q + 1]; ++e)
-      acc -= gu[d.gucsc_from[e]] * H[(nu + d.gucsc_row[e]) * W + c];
-    if (j < nu)
-      K[(size_t)j * ldk + q] = acc;
-    else
-      rhs[q] = -acc;
+  for (int q = tid; q < nu; q += T) {
+    double acc[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] = H[q * W + c];
+    for (int e = d.gucsc_ptr[q]; e < d.gucsc_ptr[q + 1]; ++e) {
+      const double gv = gu[d.gucsc_from[e]];
+      const double* hc = H + (nu + d.gucsc_row[e]) * W;
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] = fma(-gv, hc[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      const int j = jc0 + c;
+      if (j >= col_end) break;
+      if (j < nu)
+        K[(size_t)j * ldk + q] = acc[c];
+      else
+        rhs[q] = -acc[c];
+    }
   }
+  tick(d, 7);
 }
 
 // p_s = -r5 - A p,  p_y = -r3 - Sigma_s p_s   (p in w order from the recovery)
@@ -423,166 +646,200 @@ __global__ void k_symmetrize(double* K, long ld, int n) {
 
 constexpr int NB = 32;   // panel width of the blocked Cholesky
 
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                (unsigned long long)(unsigned)lo));
+}
+
 // Panel step k0 of a right-looking blocked Cholesky of the lower triangle of
 // A + delta I, with the forward substitution L y = b folded in (b is a work
 // copy whose rows below the panel receive b_i -= L_ik y_k). Block 0 owns the
-// diagonal block and writes y_k; block t >= 1 owns rows [k0 + t NB, ...).
-// Every block factors the (already updated) diagonal block and solves for
-// y_k redundantly in LDS, so the panel needs no second launch.
+// diagonal block and writes L_kk and y_k; block t >= 1 owns rows
+// [k0 + t NB, ...) and writes L_ik = A_ik L_kk^{-T}. Every block factors the
+// (already updated) diagonal block redundantly, so the panel needs one
+// launch. 1024 threads: thread (i, c) = (tid % 32, tid / 32) keeps element
+// (i, c) of the diagonal block and of its row block in registers; each pivot
+// broadcasts one column through LDS, so a pivot costs three barriers.
 __global__ void __launch_bounds__(1024) k_potrf_panel(double* A, long ld, int n, int k0,
                                                      double delta, double* b, double* y,
                                                      int* status) {
   if (status[0] != 0) return;
-  __shared__ double L[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ double yk[NB];
+  __shared__ double lcol[NB];   // column j of L_kk
+  __shared__ double xcol[NB];   // column j of the row block's L_ik
+  __shared__ double piv;
+  __shared__ double yj;
   const int tid = threadIdx.x;
-  const int ti = tid % NB, tj = tid / NB;   // 32 x 32 threads
+  const int ti = tid % NB, tc = tid / NB;
   const int bsz = min(NB, n - k0);
-  {
-    double v = 0.0;
-    if (ti < bsz && tj < bsz && ti >= tj) v = A[(size_t)(k0 + tj) * ld + k0 + ti];
-    if (ti == tj && ti < bsz) v += delta;
-    L[ti][tj] = v;
-  }
-  __syncthreads();
+  const int r0 = k0 + blockIdx.x * NB;
+  const int rb = blockIdx.x ? min(NB, n - r0) : 0;
+  double a = 0.0, x = 0.0, bi = 0.0, bacc = 0.0, yv = 0.0;
+  if (ti < bsz && tc <= ti) a = A[(size_t)(k0 + tc) * ld + k0 + ti];
+  if (ti == tc && ti < bsz) a += delta;
+  if (ti < rb && tc < bsz) x = A[(size_t)(k0 + tc) * ld + r0 + ti];
+  if (tc == 0 && ti < bsz) bi = b[k0 + ti];
   for (int j = 0; j < bsz; ++j) {
-    const double djj = L[j][j];
-    if (!(djj > 0.0)) {
+    if (ti == j && tc == j) piv = a;
+    __syncthreads();
+    const double d = piv;
+    if (!(d > 0.0)) {
       if (blockIdx.x == 0 && tid == 0) {
         status[0] = 1;
         status[1] = k0 + j;
       }
       return;   // uniform: every thread read the same pivot
     }
-    const double s = sqrt(djj);
-    __syncthreads();
-    if (tj == 0 && ti > j && ti < bsz) L[ti][j] /= s;
-    __syncthreads();
-    if (tj > j && ti >= tj && ti < bsz) L[ti][tj] -= L[ti][j] * L[tj][j];
-    if (tid == 0) L[j][j] = s;
-    __syncthreads();
-  }
-  // y_k = L_kk^{-1} b_k (one wave, lane j owns row j)
-  if (tid < 64) {
-    const int lane = tid;
-    const double bj = lane < bsz ? b[k0 + lane] : 0.0;
-    double acc = 0.0, mine = 0.0;
-    for (int c = 0; c < bsz; ++c) {
-      const double val = lane < bsz ? (bj - acc) / L[lane][lane] : 0.0;
-      const double yc = __shfl(val, c);
-      if (lane == c) mine = yc;
-      if (lane > c && lane < bsz) acc += L[lane][c] * yc;
+    const double rs = rsqrt(d);
+    if (tc == j && ti >= j && ti < bsz) {
+      a = ti == j ? d * rs : a * rs;   // column j of L
+      lcol[ti] = a;
     }
-    if (lane < bsz) yk[lane] = mine;
+    __syncthreads();
+    const double ljj = lcol[j];
+    if (tc > j && tc <= ti && ti < bsz) a = fma(-lcol[ti], lcol[tc], a);
+    // forward substitution: y_j = b_j / l_jj (thread (j, 0) holds b_j)
+    if (tc == 0 && ti == j) {
+      yv = bi / ljj;
+      yj = yv;
+    }
+    // row block: x_ij = x_ij / l_jj
+    if (tc == j && ti < rb) {
+      x /= ljj;
+      xcol[ti] = x;
+    }
+    __syncthreads();
+    const double yc = yj;
+    if (tc == 0 && ti > j && ti < bsz) bi = fma(-lcol[ti], yc, bi);
+    if (ti < rb) {
+      if (tc > j && tc < bsz) x = fma(-xcol[ti], lcol[tc], x);
+      if (tc == 0) bacc = fma(xcol[ti], yc, bacc);
+    }
   }
-  __syncthreads();
   if (blockIdx.x == 0) {
-    if (ti < bsz && tj < bsz && ti >= tj) A[(size_t)(k0 + tj) * ld + k0 + ti] = L[ti][tj];
-    if (tid < bsz) y[k0 + tid] = yk[tid];
+    if (ti < bsz && tc <= ti) A[(size_t)(k0 + tc) * ld + k0 + ti] = a;
+    if (tc == 0 && ti < bsz) y[k0 + ti] = yv;
     return;
   }
-  const int r0 = k0 + blockIdx.x * NB;
-  const int rb = min(NB, n - r0);
-  X[ti][tj] = (ti < rb && tj < bsz) ? A[(size_t)(k0 + tj) * ld + r0 + ti] : 0.0;
-  __syncthreads();
-  // X L^T = A_ik, column by column
-  for (int j = 0; j < bsz; ++j) {
-    if (tj == 0 && ti < rb) X[ti][j] /= L[j][j];
-    __syncthreads();
-    if (tj > j && tj < bsz && ti < rb) X[ti][tj] -= X[ti][j] * L[tj][j];
-    __syncthreads();
-  }
-  if (ti < rb && tj < bsz) A[(size_t)(k0 + tj) * ld + r0 + ti] = X[ti][tj];
-  if (tj == 0 && ti < rb) {
-    double acc = 0.0;
-    for (int c = 0; c < bsz; ++c) acc += X[ti][c] * yk[c];
-    b[r0 + ti] -= acc;
-  }
+  if (ti < rb && tc < bsz) A[(size_t)(k0 + tc) * ld + r0 + ti] = x;
+  if (tc == 0 && ti < rb) b[r0 + ti] -= bacc;
 }
 
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
 // Trailing update A[i, j] -= sum_c L[i, c] L[j, c] over the panel columns
-// [k0, k0 + NB) for the lower tiles of the trailing matrix, 32 x 32 tiles.
+// [k0, k0 + NB) for the lower 32 x 32 tiles of the trailing matrix, on FP64
+// MFMA (16x16x4). Four waves per tile, one 16 x 16 quadrant each. Operand
+// layout of v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k, D[i][j] in lane j + 16 (i % 4), register i / 4.
 __global__ void __launch_bounds__(256) k_syrk(double* A, long ld, int n, int k0, int* status) {
   if (status[0] != 0) return;
   const int k1 = k0 + NB;
-  // triangular tile index -> (ti, tj), tj <= ti
   int t = blockIdx.x, ti = 0;
   while (t > ti) {
     t -= ti + 1;
     ++ti;
   }
   const int tj = t;
-  const int i0 = k1 + ti * 32, j0 = k1 + tj * 32;
-  __shared__ double Ai[32][NB + 1];
-  __shared__ double Aj[32][NB + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 32 * NB; e += 256) {
-    const int r = e % 32, c = e / 32;
-    Ai[r][c] = (i0 + r < n) ? A[(size_t)(k0 + c) * ld + i0 + r] : 0.0;
-    Aj[r][c] = (j0 + r < n) ? A[(size_t)(k0 + c) * ld + j0 + r] : 0.0;
-  }
-  __syncthreads();
-  const int r = tid % 32, cq = tid / 32;   // each thread: row r, columns cq*4 .. cq*4+3
-  double acc[4] = {0, 0, 0, 0};
-  for (int c = 0; c < NB; ++c) {
-    const double a = Ai[r][c];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int qi = wave / 2, qj = wave % 2;
+  if (ti == tj && qi < qj) return;            // strictly upper quadrant of a diagonal tile
+  const int ri = k1 + ti * 32 + qi * 16;      // first row of the quadrant
+  const int cj = k1 + tj * 32 + qj * 16;      // first column of the quadrant
+  const int li = lane % 16, kk = lane / 16;
+  const bool rok = ri + li < n, cok = cj + li < n;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] += a * Aj[cq * 4 + q][c];
+  for (int s4 = 0; s4 < NB / 4; ++s4) {
+    const size_t col = (size_t)(k0 + 4 * s4 + kk) * ld;
+    const double av = rok ? A[col + ri + li] : 0.0;
+    const double bv = cok ? A[col + cj + li] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
   }
+  const int j = cj + li;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int gi = i0 + r, gj = j0 + cq * 4 + q;
-    if (gi < n && gj < n && gj <= gi) A[(size_t)gj * ld + gi] -= acc[q];
+  for (int r = 0; r < 4; ++r) {
+    const int i = ri + 4 * r + kk;
+    if (i < n && j < n && j <= i) A[(size_t)j * ld + i] -= acc[r];
   }
 }
 
-// Backward substitution L^T x = y in one work-group (x stored into y).
+// Backward substitution L^T x = y in one work-group (x written over y).
+// Blocks of 64 unknowns from the bottom: the coupling to the solved part is a
+// set of dot products over contiguous columns of L (coalesced), the 64 x 64
+// diagonal block is staged in LDS, and one wave solves it with lane j owning
+// x_j.
 __global__ void __launch_bounds__(256) k_trsv_lt(const double* A, long ld, int n, double* y,
                                                  const int* status) {
   if (status[0] != 0) return;
   extern __shared__ double xs[];
-  __shared__ double part[4][64];
-  const int tid = threadIdx.x;
+  __shared__ double rhsb[64];
+  __shared__ double Ld[64][65];
+  __shared__ double red[64][65];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   for (int i = tid; i < n; i += 256) xs[i] = y[i];
   __syncthreads();
   const int nblk = (n + 63) / 64;
   for (int jb = nblk - 1; jb >= 0; --jb) {
-    const int j0 = jb * 64, j1 = min(n, j0 + 64);
-    // rhs_j -= sum_{i >= j1} L[i, j] x_i
+    const int j0 = jb * 64, j1 = min(n, j0 + 64), nbk = j1 - j0;
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e % 64, c = e / 64;   // Ld[r][c] = L[j0 + r][j0 + c]
+      Ld[r][c] = (r < nbk && c < nbk && r >= c) ? A[(size_t)(j0 + c) * ld + j0 + r] : 0.0;
+    }
+    // rhs_j = y_j - sum_{i >= j1} L[i, j] x_i: wave w takes columns
+    // 16 w .. 16 w + 15 with 16 independent accumulators per lane (rows
+    // strided by 64, coalesced), then reduces through LDS
     {
-      const int j = j0 + tid % 64, q = tid / 64;
-      double acc = 0.0;
-      if (j < j1)
-        for (int i = j1 + q; i < n; i += 4) acc += A[(size_t)j * ld + i] * xs[i];
-      part[q][tid % 64] = acc;
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int i = j1 + lane; i < n; i += 64) {
+        const double xi = xs[i];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int j = j0 + wave * 16 + q;
+          if (j < j1) acc[q] = fma(A[(size_t)j * ld + i], xi, acc[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) red[wave * 16 + q][lane] = acc[q];
     }
     __syncthreads();
     if (tid < 64) {
-      const int lane = tid, j = j0 + lane;
-      double rhs = 0.0;
-      if (j < j1) rhs = xs[j] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
-      // solve the diagonal block backwards: lane j owns x_j
-      double acc = 0.0, mine = 0.0;
-      for (int c = j1 - 1; c >= j0; --c) {
-        const double val = j < j1 ? (rhs - acc) / A[(size_t)j * ld + j] : 0.0;
-        const double xc = __shfl(val, c - j0);
-        if (j == c) mine = xc;
-        if (j < c) acc += A[(size_t)j * ld + c] * xc;
+      double sacc = 0.0;
+      for (int l = 0; l < 64; ++l) sacc += red[tid][l];
+      const int j = j0 + tid;
+      rhsb[tid] = j < j1 ? xs[j] - sacc : 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double rhs = rhsb[lane];
+      const double rdiag = lane < nbk ? 1.0 / Ld[lane][lane] : 0.0;
+      double xv = 0.0;
+      for (int c = nbk - 1; c >= 0; --c) {
+        const double xc = readlane_d(rhs * rdiag, c);
+        if (lane == c) xv = xc;
+        if (lane < c) rhs = fma(-Ld[c][lane], xc, rhs);
       }
-      if (j < j1) xs[j] = mine;
+      if (lane < nbk) xs[j0 + lane] = xv;
     }
     __syncthreads();
   }
   for (int i = tid; i < n; i += 256) y[i] = xs[i];
 }
 
+}  // namespace
+size_t condense_meta_bytes(const DevNet& d);
+namespace {
+
 template <int W, bool LDS>
 hipError_t launch_condense_t(const DevNet& d, int col0, int ncols, int mode, const double* r,
                              const double* vin, double* K, long ldk, double* rhs, double* p,
                              hipStream_t st) {
   const int nblk = (ncols + W - 1) / W;
-  const size_t lds = LDS ? (size_t)2 * d.nw * W * sizeof(double) : 0;
+  const size_t lds = (LDS ? (size_t)d.nw * W * sizeof(double) : 0) + condense_meta_bytes(d);
   hipLaunchKernelGGL((k_condense<W, LDS>), dim3(nblk), dim3(kBlock), lds, st, d, col0,
                      col0 + ncols, mode, r, vin, K, ldk, rhs, p);
   return hipGetLastError();
@@ -606,14 +863,28 @@ inline int cdiv(long a, long b) { return int((a + b - 1) / b); }
 
 }  // namespace
 
+size_t condense_meta_bytes(const DevNet& d) {
+  return sizeof(int) * kMeta * (size_t)(d.sl.nlev + d.su.nlev + d.sut.nlev + d.slt.nlev);
+}
+
 void prepare_lds_kernels(size_t bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   const void* fns[] = {
       reinterpret_cast<const void*>(&k_condense<1, true>),
       reinterpret_cast<const void*>(&k_condense<2, true>),
       reinterpret_cast<const void*>(&k_condense<3, true>),
       reinterpret_cast<const void*>(&k_condense<4, true>),
       reinterpret_cast<const void*>(&k_condense<8, true>)};
+  const void* gfns[] = {
+      reinterpret_cast<const void*>(&k_condense<1, false>),
+      reinterpret_cast<const void*>(&k_condense<2, false>),
+      reinterpret_cast<const void*>(&k_condense<3, false>),
+      reinterpret_cast<const void*>(&k_condense<4, false>),
+      reinterpret_cast<const void*>(&k_condense<8, false>)};
   for (const void* f : fns)
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  for (const void* f : gfns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
   (void)hipGetLastError();
 }
@@ -638,15 +909,15 @@ hipError_t launch_eval(const DevNet& d, const double* x, const double* u, const 
 
 hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double* sig_u,
                              const double* sig_s, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble_k, dim3(cdiv(d.nnz_k, kBlock)), dim3(kBlock), 0, st, d, sig_x,
+  hipLaunchKernelGGL(k_assemble_k, dim3(cdiv(d.kell_n, kBlock)), dim3(kBlock), 0, st, d, sig_x,
                      sig_u, sig_s);
   return hipGetLastError();
 }
 
 hipError_t launch_refactor(const DevNet& d, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, d.status + 2, 2, 0);
-  hipLaunchKernelGGL(k_refactor, dim3(1), dim3(64 * kRefWaves),
-                     (size_t)kRefWaves * d.max_row * sizeof(double), st, d);
+  hipLaunchKernelGGL(k_refactor, dim3(1), dim3(kRefThreads),
+                     (size_t)d.rf_lds_doubles * sizeof(double), st, d);
   hipLaunchKernelGGL(k_transcribe, dim3(64), dim3(kBlock), 0, st, d);
   return hipGetLastError();
 }
@@ -667,7 +938,8 @@ hipError_t launch_condense(const DevNet& d, int col0, int ncols, int width, bool
 
 hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, double* p,
                           hipStream_t st) {
-  const bool lds = (size_t)2 * d.nw * sizeof(double) <= (size_t)max_lds_bytes();
+  const bool lds = d.kb_n <= kMaxRowBlocks &&
+      (size_t)d.nw * sizeof(double) + condense_meta_bytes(d) <= (size_t)max_lds_bytes();
   if (lds)
     return dispatch_width<true>(d, 0, 1, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
   return dispatch_width<false>(d, 0, 1, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
@@ -689,8 +961,8 @@ hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, doubl
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, status, 2, 0);
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nblk = cdiv(n - k0, NB);
-    hipLaunchKernelGGL(k_potrf_panel, dim3(nblk), dim3(1024), 0, st, K, ldk, n, k0, delta, b,
-                       y, status);
+    hipLaunchKernelGGL(k_potrf_panel, dim3(nblk), dim3(1024), 0, st, K, ldk, n, k0, delta, b, y,
+                       status);
     const int rest = n - (k0 + NB);
     if (rest > 0) {
       const int nt = cdiv(rest, 32);

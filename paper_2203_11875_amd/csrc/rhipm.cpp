@@ -38,6 +38,7 @@ struct rh_net {
   double* sig_s = nullptr;   // copy of Sigma_s from the last condensation
   double* bwork = nullptr;   // Cholesky right-hand-side work copy
   int* status = nullptr;
+  long long* trace = nullptr;
   size_t panel_cap = 0;
 };
 
@@ -117,13 +118,23 @@ rh_status upload_sweep(rh_net* n, const rh::Sweep& s, rh::DevSweep& d) {
   RH_TRY(upload(n, s.ptr, &d.ptr));
   RH_TRY(upload(n, s.col, &d.col));
   RH_TRY(upload(n, s.src, &d.src));
+  RH_TRY(upload(n, s.lev_lanes, &d.lev_lanes));
+  RH_TRY(upload(n, s.lev_base, &d.lev_base));
+  RH_TRY(upload(n, s.lev_len, &d.lev_len));
+  RH_TRY(upload(n, s.ell_col, &d.ell_col));
+  RH_TRY(upload(n, s.ell_src, &d.ell_src));
+  RH_TRY(alloc(n, s.ell_col.size(), &d.ell_val));
+  d.ell_n = int(s.ell_col.size());
   RH_TRY(alloc(n, s.col.size(), &d.val));
+  d.unit = s.has_diag ? 0 : 1;
   if (s.has_diag) {
     RH_TRY(upload(n, s.diag_src, &d.diag_src));
     RH_TRY(alloc(n, s.diag_src.size(), &d.dinv));
   } else {
     d.diag_src = nullptr;
-    d.dinv = nullptr;
+    const double* ones;
+    RH_TRY(upload(n, std::vector<double>(s.rows.size(), 1.0), &ones));
+    d.dinv = const_cast<double*>(ones);
   }
   return RH_OK;
 }
@@ -145,6 +156,7 @@ void fill_info(const rh::Symbolic& s, rh_info* info) {
   info->levels_upper = s.su.nlev;
   info->refactor_ops = s.refactor_ops;
   info->max_lu_row = s.max_row;
+  info->max_row_ops = s.max_row_ops;
 }
 
 void copy_maps(const rh::Symbolic& s, int32_t* x_kind, int32_t* x_bus, int32_t* u_kind,
@@ -192,6 +204,10 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(upload(n, s.rf_kptr, &d.rf_kptr));
   RH_TRY(upload(n, s.rf_op_src, &d.rf_src));
   RH_TRY(upload(n, s.rf_op_dst, &d.rf_dst));
+  RH_TRY(upload(n, s.rf_piv, &d.rf_piv));
+  RH_TRY(upload(n, s.rf_dst_local, &d.rf_dst_local));
+  d.max_row_ops = s.max_row_ops;
+  d.max_row_lower = s.max_row_lower;
   RH_TRY(upload_sweep(n, s.sl, d.sl));
   RH_TRY(upload_sweep(n, s.su, d.su));
   RH_TRY(upload_sweep(n, s.sut, d.sut));
@@ -222,6 +238,15 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(upload(n, s.kg.ata_row, &d.kg_row));
   RH_TRY(upload(n, s.kg.diag_var, &d.kg_diag));
   RH_TRY(upload(n, s.sig_map, &d.sig_map));
+  RH_TRY(upload(n, s.kb_base, &d.kb_base));
+  RH_TRY(upload(n, s.kb_len, &d.kb_len));
+  RH_TRY(upload(n, s.kell_col, &d.kell_col));
+  RH_TRY(upload(n, s.kell_pos, &d.kell_pos));
+  RH_TRY(alloc(n, s.kell_col.size(), &d.kell_val));
+  d.kell_n = int(s.kell_col.size());
+  d.kb_n = int(s.kb_base.size());
+  RH_TRY(upload(n, s.rf_lmeta, &d.rf_lmeta));
+  d.rf_lds_doubles = s.rf_lds_doubles;
   RH_TRY(upload(n, s.k_cdiag, &d.k_cdiag));
   d.d_total = s.d_total; d.d_lu = s.d_lu; d.d_gu = s.d_gu; d.d_a = s.d_a; d.d_g = s.d_g;
   d.d_h = s.d_h; d.src_u = s.src_u; d.src_total = s.src_total;
@@ -244,26 +269,42 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(alloc(n, s.nw, &d.rt));
   RH_TRY(alloc(n, s.nw, &d.pw));
   RH_TRY(alloc(n, s.nu, &d.vtmp));
+  RH_TRY(alloc(n, s.nx, &d.rinv));
+  {
+    std::vector<int> info;
+    for (int q = 0; q < s.nx; ++q) {
+      const int i = s.sl.rows[q];
+      const int rp0 = s.lu_ptr[i], rd = s.lu_diag[i];
+      info.insert(info.end(), {i, rp0, s.lu_ptr[i + 1], rd, s.rf_kptr[rp0],
+                               s.rf_kptr[rd] - s.rf_kptr[rp0], 0, 0});
+    }
+    RH_TRY(upload(n, info, &d.rf_info));
+  }
   RH_TRY(alloc(n, s.m, &n->sig_s));
   RH_TRY(alloc(n, s.nu, &n->bwork));
   RH_TRY(alloc(n, 8, &n->status));
+  RH_TRY(alloc(n, 256, &n->trace));
+  RH_HIP(hipMemset(n->trace, 0, 256 * sizeof(long long)));
+  d.trace = nullptr;
   d.status = n->status;
   RH_HIP(hipMemset(n->status, 0, 8 * sizeof(int)));
   // launch shape of the condensation
-  const size_t col_bytes = size_t(2) * s.nw * sizeof(double);
+  const size_t col_bytes = size_t(s.nw) * sizeof(double);   // one LDS panel column
   const size_t lds_max = size_t(rh::max_lds_bytes());
-  int want = opts && opts->panel_width > 0 ? opts->panel_width : 2;
+  const size_t meta = rh::condense_meta_bytes(d);
+  int want = opts && opts->panel_width > 0 ? opts->panel_width : 1;
   if (want != 1 && want != 2 && want != 3 && want != 4 && want != 8) return RH_ERR_ARG;
-  bool lds = !opts || opts->lds_panel != 0;
-  if (lds && col_bytes * want > lds_max) {
+  bool lds = (!opts || opts->lds_panel != 0) && int(s.kb_base.size()) <= rh::kMaxRowBlocks;
+  if (lds && col_bytes * want + meta > lds_max) {
     // keep the panel in LDS with a narrower tile if possible
     int w = want;
-    while (w > 1 && col_bytes * w > lds_max) w = (w == 8 ? 4 : w - 1);
-    if (col_bytes * w <= lds_max) want = w; else lds = false;
+    while (w > 1 && col_bytes * w + meta > lds_max) w = (w == 8 ? 4 : w - 1);
+    if (col_bytes * w + meta <= lds_max) want = w; else lds = false;
   }
+  if (meta > lds_max) return RH_ERR_ARG;
   n->width = want;
   n->lds = lds;
-  if (lds) rh::prepare_lds_kernels(col_bytes * want);
+  rh::prepare_lds_kernels(lds ? col_bytes * want + meta : meta);
   d.panel = nullptr;
   d.panel_doubles = 0;
   if (!lds) {
@@ -271,7 +312,7 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
     d.panel_doubles = nblk * 2 * size_t(s.nw) * want;
     RH_TRY(alloc(n, d.panel_doubles, &d.panel));
   }
-  if (size_t(16) * s.max_row * sizeof(double) > lds_max) return RH_ERR_ARG;
+  if (size_t(s.rf_lds_doubles) * sizeof(double) > lds_max) return RH_ERR_ARG;
   RH_HIP(hipDeviceSynchronize());
   return RH_OK;
 }
@@ -491,6 +532,16 @@ rh_status rh_profile_enable(rh_net* n, int32_t on) {
     t.calls = 0;
   }
   n->profiling = on != 0;
+  n->d.trace = n->profiling ? n->trace : nullptr;
+  return RH_OK;
+}
+
+rh_status rh_profile_kernel_trace(rh_net* n, int64_t* ticks) {
+  if (!n || !ticks) return RH_ERR_ARG;
+  RH_HIP(hipStreamSynchronize(n->stream));
+  long long h[256];
+  RH_HIP(hipMemcpy(h, n->trace, sizeof(h), hipMemcpyDeviceToHost));
+  for (int k = 0; k < 256; ++k) ticks[k] = h[k];
   return RH_OK;
 }
 

@@ -108,6 +108,10 @@ def test_solve_matches_oracle(name, delta):
     want = np.concatenate(R.recover(B, r, pu, S, lu))
     got = _np(p)
     assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+    # the lower triangle of K now holds the Cholesky factor of K_cond + delta I
+    Lg = np.tril(_np(K).T)
+    Lo = np.linalg.cholesky(Kc)
+    assert _rel(Lg, Lo) <= 1e-8
 
 
 def test_cholesky_reports_indefinite():
