@@ -472,8 +472,8 @@ __device__ __forceinline__ void hvp_row(const DevNet& d, const double* P, int bk
 // Column nu (if requested) is the condensed right-hand side: V = 0, Z = -G_x^{-1} r4,
 // H += rt, and rhs = -out. In MODE_RECOVER (one column): V = p_u,
 // Z = -G_x^{-1}(r4 + G_u p_u) = p_x, H += rt, Psi = -p_lambda.
-template <int W, bool LDS>
-__global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col_end, int mode,
+template <int W, bool LDS, int mode>
+__global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col_end,
                                                     const double* r, const double* vin,
                                                     double* K, long ldk, double* rhs,
                                                     double* p_out) {
@@ -840,8 +840,12 @@ hipError_t launch_condense_t(const DevNet& d, int col0, int ncols, int mode, con
                              hipStream_t st) {
   const int nblk = (ncols + W - 1) / W;
   const size_t lds = (LDS ? (size_t)d.nw * W * sizeof(double) : 0) + condense_meta_bytes(d);
-  hipLaunchKernelGGL((k_condense<W, LDS>), dim3(nblk), dim3(kBlock), lds, st, d, col0,
-                     col0 + ncols, mode, r, vin, K, ldk, rhs, p);
+  if (mode == MODE_RECOVER)
+    hipLaunchKernelGGL((k_condense<W, LDS, MODE_RECOVER>), dim3(nblk), dim3(kBlock), lds, st, d,
+                       col0, col0 + ncols, r, vin, K, ldk, rhs, p);
+  else
+    hipLaunchKernelGGL((k_condense<W, LDS, MODE_COLUMNS>), dim3(nblk), dim3(kBlock), lds, st, d,
+                       col0, col0 + ncols, r, vin, K, ldk, rhs, p);
   return hipGetLastError();
 }
 
@@ -871,17 +875,19 @@ void prepare_lds_kernels(size_t bytes) {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   const void* fns[] = {
-      reinterpret_cast<const void*>(&k_condense<1, true>),
-      reinterpret_cast<const void*>(&k_condense<2, true>),
-      reinterpret_cast<const void*>(&k_condense<3, true>),
-      reinterpret_cast<const void*>(&k_condense<4, true>),
-      reinterpret_cast<const void*>(&k_condense<8, true>)};
+      reinterpret_cast<const void*>(&k_condense<1, true, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<2, true, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<3, true, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<4, true, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<8, true, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, true, MODE_RECOVER>)};
   const void* gfns[] = {
-      reinterpret_cast<const void*>(&k_condense<1, false>),
-      reinterpret_cast<const void*>(&k_condense<2, false>),
-      reinterpret_cast<const void*>(&k_condense<3, false>),
-      reinterpret_cast<const void*>(&k_condense<4, false>),
-      reinterpret_cast<const void*>(&k_condense<8, false>)};
+      reinterpret_cast<const void*>(&k_condense<1, false, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<2, false, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<3, false, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<4, false, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<8, false, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, false, MODE_RECOVER>)};
   for (const void* f : fns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
   for (const void* f : gfns)
@@ -941,8 +947,8 @@ hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, do
   const bool lds = d.kb_n <= kMaxRowBlocks &&
       (size_t)d.nw * sizeof(double) + condense_meta_bytes(d) <= (size_t)max_lds_bytes();
   if (lds)
-    return dispatch_width<true>(d, 0, 1, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
-  return dispatch_width<false>(d, 0, 1, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
+    return launch_condense_t<1, true>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
+  return launch_condense_t<1, false>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
 }
 
 hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,
