@@ -189,7 +189,9 @@ rh_status rh_condense_reduced_hessian(rh_net* net, const double* x, const double
  * for p_u with rhs, then recovers p_x = -G_x^{-1}(r4 + G_u p_u),
  * p_lambda = -G_x^{-T}(rt_x + (K p)_x), p_s = -r5 - A p, p_y = -r3 - Sigma_s p_s
  * using the factors and K of the last rh_condense_reduced_hessian on this
- * handle (RH_ERR_STATE if none). Device arrays: K (in: K_cond, out: Cholesky
+ * handle (RH_ERR_STATE if none). When that condensation was given r, p_x and
+ * p_lambda come from the columns it stored (Z = S e_j, Psi = G_x^{-T} H_x and
+ * those of its right-hand-side column): r must then be the same residual. Device arrays: K (in: K_cond, out: Cholesky
  * factor in the lower triangle), rhs (nu), r (packed), p (packed step, output).
  * dev_status (device int32[2], may be NULL): [status, index of failing pivot].
  * The call synchronises the stream once and returns RH_NOT_POSDEF when the

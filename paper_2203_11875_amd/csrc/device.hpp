@@ -80,6 +80,9 @@ struct DevNet {
   double* rinv;       // nx: reciprocal pivots written by the refactorisation
   const int* rf_info; // per refactorisation slot: row, lu_ptr, lu_ptr+1, diag, op0, nops
   double* panel;      // global panel workspace (when not in LDS)
+  double* zcols;      // nx x (nu+1), column-major: Z = S e_j per column, then d (internal x order)
+  double* psicols;    // nx x (nu+1): Psi = G_x^{-T} H_x per column, then that of the RHS column
+  double* rpart;      // 2 x kRecChunks x nx partial sums of the recovery
   size_t panel_doubles;
   int* status;        // [0] Cholesky status, [1] failing index, [2] small pivot flag, [3] pivot row
   long long* trace;   // in-kernel phase timestamps of work-group 0 (null = off)
@@ -97,6 +100,9 @@ hipError_t launch_condense(const DevNet& d, int col0, int ncols, int width, bool
 // recovery of p_x and p_lambda from p_u (one column)
 hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, double* p,
                           hipStream_t st);
+// Recovery from the stored columns of the last condensation (which included
+// the right-hand-side column): p_x = Z p_u + d, p_lambda = -(Psi p_u + Psi_rhs).
+hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st);
 hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,
                               hipStream_t st);
 hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);

@@ -523,6 +523,15 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
   tick(d, 2);
   sweep<W, LDS>(d.su, m_su, P + nu * W);
   tick(d, 3);
+  if (mode == MODE_COLUMNS) {
+    // keep Z = S e_j (and d for the right-hand-side column) for the recovery
+    for (int c = 0; c < W; ++c) {
+      const int j = jc0 + c;
+      if (j >= col_end) break;
+      double* zc = d.zcols + (size_t)j * nx;
+      for (int i = tid; i < nx; i += T) zc[i] = P[(nu + i) * W + c];
+    }
+  }
   if (mode == MODE_RECOVER) {
     double* px = p_out + nu;
     for (int i = tid; i < nx; i += T) {
@@ -571,6 +580,14 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
   tick(d, 5);
   sweep<W, LDS>(d.slt, m_slt, H + nu * W);
   tick(d, 6);
+  if (mode == MODE_COLUMNS) {
+    for (int c = 0; c < W; ++c) {
+      const int j = jc0 + c;
+      if (j >= col_end) break;
+      double* pc = d.psicols + (size_t)j * nx;
+      for (int i = tid; i < nx; i += T) pc[i] = H[(nu + i) * W + c];
+    }
+  }
   if (mode == MODE_RECOVER) {
     double* plam = p_out + nu + nx + d.m;
     for (int i = tid; i < nx; i += T) plam[d.perm[i]] = -H[(nu + i) * W];
@@ -597,6 +614,46 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
     }
   }
   tick(d, 7);
+}
+
+// Recovery from the stored columns: thread i (internal x index) of chunk ch
+// sums the columns [ch * cw, (ch + 1) * cw) of Z and Psi against p_u; the
+// partial sums are combined in a fixed order by k_recover_finish, so the
+// result repeats bitwise.
+constexpr int kRecChunks = 8;
+
+__global__ void __launch_bounds__(kBlock) k_recover_partial(DevNet d, const double* pu) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (i >= d.nx) return;
+  const int cw = (d.nu + kRecChunks - 1) / kRecChunks;
+  const int j0 = ch * cw, j1 = min(d.nu, j0 + cw);
+  double sz = 0.0, sp = 0.0;
+#pragma unroll 4
+  for (int j = j0; j < j1; ++j) {
+    const double u = pu[j];
+    sz = fma(d.zcols[(size_t)j * d.nx + i], u, sz);
+    sp = fma(d.psicols[(size_t)j * d.nx + i], u, sp);
+  }
+  d.rpart[(size_t)ch * d.nx + i] = sz;
+  d.rpart[(size_t)(kRecChunks + ch) * d.nx + i] = sp;
+}
+
+__global__ void __launch_bounds__(kBlock) k_recover_finish(DevNet d, double* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.nu) {
+    d.pw[i] = p[i];
+  }
+  if (i >= d.nx) return;
+  double sz = d.zcols[(size_t)d.nu * d.nx + i];
+  double sp = d.psicols[(size_t)d.nu * d.nx + i];
+  for (int ch = 0; ch < kRecChunks; ++ch) {
+    sz += d.rpart[(size_t)ch * d.nx + i];
+    sp += d.rpart[(size_t)(kRecChunks + ch) * d.nx + i];
+  }
+  d.pw[d.nu + i] = sz;
+  p[d.nu + d.perm[i]] = sz;                         // p_x
+  p[d.nu + d.nx + d.m + d.perm[i]] = -sp;           // p_lambda
 }
 
 // p_s = -r5 - A p,  p_y = -r3 - Sigma_s p_s   (p in w order from the recovery)
@@ -949,6 +1006,14 @@ hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, do
   if (lds)
     return launch_condense_t<1, true>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
   return launch_condense_t<1, false>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
+}
+
+hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_recover_partial, dim3(cdiv(d.nx, kBlock), kRecChunks), dim3(kBlock), 0, st,
+                     d, (const double*)p);
+  hipLaunchKernelGGL(k_recover_finish, dim3(cdiv(d.nx > d.nu ? d.nx : d.nu, kBlock)), dim3(kBlock),
+                     0, st, d, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,

@@ -35,6 +35,7 @@ struct rh_net {
   int width = 2;
   bool lds = true;
   bool condensed = false;
+  bool rhs_cols = false;     // the last condensation stored the right-hand-side column
   double* sig_s = nullptr;   // copy of Sigma_s from the last condensation
   double* bwork = nullptr;   // Cholesky right-hand-side work copy
   int* status = nullptr;
@@ -270,6 +271,9 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(alloc(n, s.nw, &d.pw));
   RH_TRY(alloc(n, s.nu, &d.vtmp));
   RH_TRY(alloc(n, s.nx, &d.rinv));
+  RH_TRY(alloc(n, size_t(s.nx) * (s.nu + 1), &d.zcols));
+  RH_TRY(alloc(n, size_t(s.nx) * (s.nu + 1), &d.psicols));
+  RH_TRY(alloc(n, size_t(2) * 8 * s.nx, &d.rpart));
   {
     std::vector<int> info;
     for (int q = 0; q < s.nx; ++q) {
@@ -491,6 +495,7 @@ rh_status rh_condense_reduced_hessian(rh_net* n, const double* x, const double* 
     RH_HIP(rh::launch_symmetrize(K, long(ldk), d.nu, st));
   }
   n->condensed = true;
+  n->rhs_cols = r != nullptr;
   return RH_OK;
 }
 
@@ -510,8 +515,14 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   }
   {
     PhaseScope ps(n, RH_PHASE_RECOVER);
-    RH_HIP(rh::launch_rtilde(d, r, n->sig_s, st));
-    RH_HIP(rh::launch_recover(d, p, r, p, st));
+    if (n->rhs_cols) {
+      // p_x = Z p_u + d, p_lambda = -(Psi p_u + Psi_rhs) from the columns the
+      // condensation stored (same r as the condensation's right-hand side)
+      RH_HIP(rh::launch_recover_stored(d, p, st));
+    } else {
+      RH_HIP(rh::launch_rtilde(d, r, n->sig_s, st));
+      RH_HIP(rh::launch_recover(d, p, r, p, st));
+    }
     RH_HIP(rh::launch_finish_step(d, r, n->sig_s, p, st));
   }
   if (dev_status)

@@ -159,3 +159,28 @@ def test_set_loads_changes_residual():
     torch.cuda.synchronize()
     go, ho, fo = Model(net2).functions(x, u)
     assert _rel(_np(g), go) <= 1e-12 and _rel(_np(h), ho) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["syn9", "syn1354"])
+def test_solve_after_condensation_without_rhs(name):
+    """Recovery by the single-column pass (condensation called without r),
+    with the right-hand side condensed separately on the same factors."""
+    net = NETS[name]()
+    M = Model(net)
+    G = _net_api().Net(net)
+    x, u, lam, y, sx, su, ss = random_point(M, 3, lam_scale=1.0, sig_range=(10.0, 1e4))
+    r = residual_vector(M, 4)
+    args = list(map(_t, (x, u, lam, y, sx, su, ss)))
+    _, rhs = G.condense_reduced_hessian(*args, r=_t(r))       # right-hand side only
+    K, _ = G.condense_reduced_hessian(*args)                   # no stored RHS column
+    B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
+    S, lu = R.sensitivity(B)
+    Kc = R.symmetrize(R.condensed_matrix(B, S))
+    delta = max(0.0, -np.linalg.eigvalsh(Kc).min()) * 1.5
+    p, code = G.solve_condensed_kkt(K, delta, rhs, _t(r))
+    torch.cuda.synchronize()
+    assert code == 0
+    b, _, _ = R.condensed_rhs(B, r, S, lu)
+    pu = np.linalg.solve(Kc + delta * np.eye(M.nu), b)
+    want = np.concatenate(R.recover(B, r, pu, S, lu))
+    assert np.abs(_np(p) - want).max() <= 1e-8 * np.abs(want).max()
