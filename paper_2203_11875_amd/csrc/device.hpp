@@ -108,8 +108,9 @@ hipError_t launch_finish_step(const DevNet& d, const double* r, const double* si
 hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
 // Cholesky of the lower triangle of K + delta I in place, L y = b (b is
 // destroyed), then L^T x = y with x written over y. status[0..1] device.
+// dinv: workspace of ceil(n / 32) * 32 * 32 doubles (inverted diagonal blocks).
 hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
-                                 double* y, int* status, hipStream_t st);
+                                 double* y, double* dinv, int* status, hipStream_t st);
 hipError_t launch_eval_objective(const DevNet& d, const double* u, double* f, hipStream_t st);
 int max_lds_bytes();
 // LDS one row of the refactorisation stages (row, U sources, pivots, schedule).

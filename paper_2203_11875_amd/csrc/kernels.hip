@@ -717,30 +717,43 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // diagonal block and writes L_kk and y_k; block t >= 1 owns rows
 // [k0 + t NB, ...) and writes L_ik = A_ik L_kk^{-T}. Every block factors the
 // (already updated) diagonal block redundantly, so the panel needs one
-// launch. 1024 threads: thread (i, c) = (tid % 32, tid / 32) keeps element
-// (i, c) of the diagonal block and of its row block in registers; each pivot
-// broadcasts one column through LDS, so a pivot costs three barriers.
-__global__ void __launch_bounds__(1024) k_potrf_panel(double* A, long ld, int n, int k0,
-                                                     double delta, double* b, double* y,
-                                                     int* status) {
+// launch. 256 threads; thread (i, c0) keeps elements (i, c0 + 8 q), q < 4, of
+// the diagonal block and of its row block in registers. A pivot costs two
+// barriers: (A) the pivot value is published; every thread forms the
+// reciprocal square root and the owners of column j scale it, divide the
+// row block's column j and form y_j; (B) the scaled columns are published
+// and every thread applies the rank-one updates.
+constexpr int kPanelThreads = 256;
+constexpr int kPanelQ = NB * NB / kPanelThreads;   // elements per thread (4)
+
+__global__ void __launch_bounds__(kPanelThreads) k_potrf_panel(double* A, long ld, int n, int k0,
+                                                              double delta, double* b, double* y,
+                                                              int* status) {
   if (status[0] != 0) return;
   __shared__ double lcol[NB];   // column j of L_kk
   __shared__ double xcol[NB];   // column j of the row block's L_ik
   __shared__ double piv;
   __shared__ double yj;
   const int tid = threadIdx.x;
-  const int ti = tid % NB, tc = tid / NB;
+  const int ti = tid % NB, c0 = tid / NB;          // c0 in [0, 8)
   const int bsz = min(NB, n - k0);
   const int r0 = k0 + blockIdx.x * NB;
   const int rb = blockIdx.x ? min(NB, n - r0) : 0;
-  double a = 0.0, x = 0.0, bi = 0.0, bacc = 0.0, yv = 0.0;
-  if (ti < bsz && tc <= ti) a = A[(size_t)(k0 + tc) * ld + k0 + ti];
-  if (ti == tc && ti < bsz) a += delta;
-  if (ti < rb && tc < bsz) x = A[(size_t)(k0 + tc) * ld + r0 + ti];
-  if (tc == 0 && ti < bsz) bi = b[k0 + ti];
+  double a[kPanelQ], x[kPanelQ];
+#pragma unroll
+  for (int q = 0; q < kPanelQ; ++q) {
+    const int c = c0 + 8 * q;
+    double v = 0.0;
+    if (ti < bsz && c <= ti) v = A[(size_t)(k0 + c) * ld + k0 + ti];
+    if (ti == c && ti < bsz) v += delta;
+    a[q] = v;
+    x[q] = (ti < rb && c < bsz) ? A[(size_t)(k0 + c) * ld + r0 + ti] : 0.0;
+  }
+  double bi = (c0 == 0 && ti < bsz) ? b[k0 + ti] : 0.0;
+  double bacc = 0.0, yv = 0.0;
+  if (tid == 0) piv = a[0];                         // element (0, 0)
   for (int j = 0; j < bsz; ++j) {
-    if (ti == j && tc == j) piv = a;
-    __syncthreads();
+    __syncthreads();                                // (A)
     const double d = piv;
     if (!(d > 0.0)) {
       if (blockIdx.x == 0 && tid == 0) {
@@ -750,38 +763,80 @@ __global__ void __launch_bounds__(1024) k_potrf_panel(double* A, long ld, int n,
       return;   // uniform: every thread read the same pivot
     }
     const double rs = rsqrt(d);
-    if (tc == j && ti >= j && ti < bsz) {
-      a = ti == j ? d * rs : a * rs;   // column j of L
-      lcol[ti] = a;
+#pragma unroll
+    for (int q = 0; q < kPanelQ; ++q) {
+      if (c0 + 8 * q == j) {
+        if (ti >= j && ti < bsz) {
+          a[q] = ti == j ? d * rs : a[q] * rs;      // column j of L
+          lcol[ti] = a[q];
+        }
+        if (ti < rb) {
+          x[q] *= rs;                               // x_ij / l_jj
+          xcol[ti] = x[q];
+        }
+      }
     }
-    __syncthreads();
-    const double ljj = lcol[j];
-    if (tc > j && tc <= ti && ti < bsz) a = fma(-lcol[ti], lcol[tc], a);
-    // forward substitution: y_j = b_j / l_jj (thread (j, 0) holds b_j)
-    if (tc == 0 && ti == j) {
-      yv = bi / ljj;
+    if (c0 == 0 && ti == j) {
+      yv = bi * rs;                                 // y_j = b_j / l_jj
       yj = yv;
     }
-    // row block: x_ij = x_ij / l_jj
-    if (tc == j && ti < rb) {
-      x /= ljj;
-      xcol[ti] = x;
+    __syncthreads();                                // (B)
+    const double li = lcol[ti], xi = xcol[ti], yc = yj;
+#pragma unroll
+    for (int q = 0; q < kPanelQ; ++q) {
+      const int c = c0 + 8 * q;
+      if (c > j && c < bsz) {
+        const double lc = lcol[c];
+        if (c <= ti && ti < bsz) a[q] = fma(-li, lc, a[q]);
+        if (ti < rb) x[q] = fma(-xi, lc, x[q]);
+      }
+      if (c == j + 1 && ti == j + 1) piv = a[q];    // next pivot, after its update
     }
-    __syncthreads();
-    const double yc = yj;
-    if (tc == 0 && ti > j && ti < bsz) bi = fma(-lcol[ti], yc, bi);
-    if (ti < rb) {
-      if (tc > j && tc < bsz) x = fma(-xcol[ti], lcol[tc], x);
-      if (tc == 0) bacc = fma(xcol[ti], yc, bacc);
+    if (c0 == 0) {
+      if (ti > j && ti < bsz) bi = fma(-li, yc, bi);
+      if (ti < rb) bacc = fma(xi, yc, bacc);
     }
   }
   if (blockIdx.x == 0) {
-    if (ti < bsz && tc <= ti) A[(size_t)(k0 + tc) * ld + k0 + ti] = a;
-    if (tc == 0 && ti < bsz) y[k0 + ti] = yv;
+#pragma unroll
+    for (int q = 0; q < kPanelQ; ++q) {
+      const int c = c0 + 8 * q;
+      if (ti < bsz && c <= ti) A[(size_t)(k0 + c) * ld + k0 + ti] = a[q];
+    }
+    if (c0 == 0 && ti < bsz) y[k0 + ti] = yv;
     return;
   }
-  if (ti < rb && tc < bsz) A[(size_t)(k0 + tc) * ld + r0 + ti] = x;
-  if (tc == 0 && ti < rb) b[r0 + ti] -= bacc;
+#pragma unroll
+  for (int q = 0; q < kPanelQ; ++q) {
+    const int c = c0 + 8 * q;
+    if (ti < rb && c < bsz) A[(size_t)(k0 + c) * ld + r0 + ti] = x[q];
+  }
+  if (c0 == 0 && ti < rb) b[r0 + ti] -= bacc;
+}
+
+// Inverse of every NB x NB lower-triangular diagonal block of the factor
+// (one work-group per block), for the blocked backward substitution:
+// X = L_bb^{-1} column by column, right-looking over the rows of L_bb.
+__global__ void __launch_bounds__(NB * NB) k_diag_inverse(const double* A, long ld, int n,
+                                                         double* inv, const int* status) {
+  if (status[0] != 0) return;
+  __shared__ double L[NB][NB + 1];
+  __shared__ double xr[NB];
+  const int bk = blockIdx.x, k0 = bk * NB, bsz = min(NB, n - k0);
+  const int ti = threadIdx.x % NB, tc = threadIdx.x / NB;   // element (row ti, column tc)
+  L[ti][tc] = (ti < bsz && tc <= ti) ? A[(size_t)(k0 + tc) * ld + k0 + ti] : 0.0;
+  double xv = (ti == tc && ti < bsz) ? 1.0 : 0.0;          // X = I, then forward elimination
+  __syncthreads();
+  for (int j = 0; j < bsz; ++j) {
+    if (ti == j) {
+      xv /= L[j][j];
+      xr[tc] = xv;
+    }
+    __syncthreads();
+    if (ti > j && ti < bsz) xv = fma(-L[ti][j], xr[tc], xv);
+    __syncthreads();
+  }
+  inv[(size_t)bk * NB * NB + tc * NB + ti] = (ti < bsz && tc < bsz) ? xv : 0.0;   // column-major
 }
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -823,64 +878,51 @@ __global__ void __launch_bounds__(256) k_syrk(double* A, long ld, int n, int k0,
   }
 }
 
-// Backward substitution L^T x = y in one work-group (x written over y).
-// Blocks of 64 unknowns from the bottom: the coupling to the solved part is a
-// set of dot products over contiguous columns of L (coalesced), the 64 x 64
-// diagonal block is staged in LDS, and one wave solves it with lane j owning
-// x_j.
+// Backward substitution L^T x = y in one work-group (x written over y), by
+// NB-row blocks from the bottom: rhs_b = y_b - sum_{i below} L_ib^T x_i (dot
+// products over contiguous columns of L, coalesced, no sequential chain),
+// then x_b = L_bb^{-T} rhs_b with the inverted diagonal block.
 __global__ void __launch_bounds__(256) k_trsv_lt(const double* A, long ld, int n, double* y,
-                                                 const int* status) {
+                                                 const double* inv, const int* status) {
   if (status[0] != 0) return;
   extern __shared__ double xs[];
-  __shared__ double rhsb[64];
-  __shared__ double Ld[64][65];
-  __shared__ double red[64][65];
-  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  __shared__ double red[NB][65];
+  __shared__ double rhsb[NB];
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   for (int i = tid; i < n; i += 256) xs[i] = y[i];
   __syncthreads();
-  const int nblk = (n + 63) / 64;
-  for (int jb = nblk - 1; jb >= 0; --jb) {
-    const int j0 = jb * 64, j1 = min(n, j0 + 64), nbk = j1 - j0;
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int r = e % 64, c = e / 64;   // Ld[r][c] = L[j0 + r][j0 + c]
-      Ld[r][c] = (r < nbk && c < nbk && r >= c) ? A[(size_t)(j0 + c) * ld + j0 + r] : 0.0;
-    }
-    // rhs_j = y_j - sum_{i >= j1} L[i, j] x_i: wave w takes columns
-    // 16 w .. 16 w + 15 with 16 independent accumulators per lane (rows
-    // strided by 64, coalesced), then reduces through LDS
+  const int nblk = (n + NB - 1) / NB;
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int j0 = bk * NB, j1 = min(n, j0 + NB);
+    // each wave takes NB/4 columns with independent accumulators
     {
-      double acc[16];
+      double acc[NB / 4];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int q = 0; q < NB / 4; ++q) acc[q] = 0.0;
       for (int i = j1 + lane; i < n; i += 64) {
         const double xi = xs[i];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int j = j0 + wave * 16 + q;
+        for (int q = 0; q < NB / 4; ++q) {
+          const int j = j0 + wave * (NB / 4) + q;
           if (j < j1) acc[q] = fma(A[(size_t)j * ld + i], xi, acc[q]);
         }
       }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) red[wave * 16 + q][lane] = acc[q];
+      for (int q = 0; q < NB / 4; ++q) red[wave * (NB / 4) + q][lane] = acc[q];
     }
     __syncthreads();
-    if (tid < 64) {
+    if (tid < NB) {
       double sacc = 0.0;
       for (int l = 0; l < 64; ++l) sacc += red[tid][l];
-      const int j = j0 + tid;
-      rhsb[tid] = j < j1 ? xs[j] - sacc : 0.0;
+      rhsb[tid] = j0 + tid < j1 ? xs[j0 + tid] - sacc : 0.0;
     }
     __syncthreads();
-    if (wave == 0) {
-      double rhs = rhsb[lane];
-      const double rdiag = lane < nbk ? 1.0 / Ld[lane][lane] : 0.0;
-      double xv = 0.0;
-      for (int c = nbk - 1; c >= 0; --c) {
-        const double xc = readlane_d(rhs * rdiag, c);
-        if (lane == c) xv = xc;
-        if (lane < c) rhs = fma(-Ld[c][lane], xc, rhs);
-      }
-      if (lane < nbk) xs[j0 + lane] = xv;
+    if (tid < NB && j0 + tid < j1) {
+      // x_b = L_bb^{-T} rhs_b: row tid of L_bb^{-T} is column tid of L_bb^{-1}
+      const double* iv = inv + (size_t)bk * NB * NB + (size_t)tid * NB;
+      double v = 0.0;
+      for (int c = 0; c < NB; ++c) v = fma(iv[c], rhsb[c], v);
+      xs[j0 + tid] = v;
     }
     __syncthreads();
   }
@@ -1028,20 +1070,22 @@ hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st) {
 }
 
 hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
-                                 double* y, int* status, hipStream_t st) {
+                                 double* y, double* dinv, int* status, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, status, 2, 0);
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nblk = cdiv(n - k0, NB);
-    hipLaunchKernelGGL(k_potrf_panel, dim3(nblk), dim3(1024), 0, st, K, ldk, n, k0, delta, b, y,
-                       status);
+    hipLaunchKernelGGL(k_potrf_panel, dim3(nblk), dim3(kPanelThreads), 0, st, K, ldk, n, k0,
+                       delta, b, y, status);
     const int rest = n - (k0 + NB);
     if (rest > 0) {
       const int nt = cdiv(rest, 32);
       hipLaunchKernelGGL(k_syrk, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, K, ldk, n, k0, status);
     }
   }
+  hipLaunchKernelGGL(k_diag_inverse, dim3(cdiv(n, NB)), dim3(NB * NB), 0, st, (const double*)K,
+                     ldk, n, dinv, (const int*)status);
   hipLaunchKernelGGL(k_trsv_lt, dim3(1), dim3(256), (size_t)n * sizeof(double), st,
-                     (const double*)K, ldk, n, y, (const int*)status);
+                     (const double*)K, ldk, n, y, (const double*)dinv, (const int*)status);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct rh_net {
   bool rhs_cols = false;     // the last condensation stored the right-hand-side column
   double* sig_s = nullptr;   // copy of Sigma_s from the last condensation
   double* bwork = nullptr;   // Cholesky right-hand-side work copy
+  double* cinv = nullptr;    // inverted 32 x 32 diagonal blocks of the Cholesky factor
   int* status = nullptr;
   long long* trace = nullptr;
   size_t panel_cap = 0;
@@ -286,6 +287,7 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   }
   RH_TRY(alloc(n, s.m, &n->sig_s));
   RH_TRY(alloc(n, s.nu, &n->bwork));
+  RH_TRY(alloc(n, size_t((s.nu + 31) / 32) * 32 * 32, &n->cinv));
   RH_TRY(alloc(n, 8, &n->status));
   RH_TRY(alloc(n, 256, &n->trace));
   RH_HIP(hipMemset(n->trace, 0, 256 * sizeof(long long)));
@@ -511,7 +513,8 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   {
     // L y = b is solved into p[0:nu], then L^T p_u = y in place
     PhaseScope ps(n, RH_PHASE_CHOLESKY);
-    RH_HIP(rh::launch_cholesky_solve(K, long(ldk), d.nu, delta_w, n->bwork, p, n->status, st));
+    RH_HIP(rh::launch_cholesky_solve(K, long(ldk), d.nu, delta_w, n->bwork, p, n->cinv, n->status,
+                                     st));
   }
   {
     PhaseScope ps(n, RH_PHASE_RECOVER);
