@@ -97,7 +97,9 @@ typedef struct {
   int32_t panel_width;       /* columns per condensation work-group; 0 = auto    */
   int32_t ordering;          /* 0 = minimum degree on the pattern of G_x          */
   int32_t lds_panel;         /* 1 = keep panels in LDS when they fit, 0 = global  */
-  int32_t reserved;
+  int32_t refactor;          /* 0 = wave-resident refactorisation when every LU
+                                row has at most 64 entries and U fits in LDS,
+                                1 = always the level-staged kernel              */
 } rh_options;
 
 typedef struct {
@@ -108,6 +110,7 @@ typedef struct {
   int64_t max_lu_row;
   int64_t panel_width, lds_panel;      /* chosen launch shape of the condensation */
   int64_t max_row_ops;                 /* refactorisation multiply-adds of one row */
+  int64_t refactor_kernel;             /* 0 wave-resident, 1 level-staged          */
 } rh_info;
 
 typedef struct rh_symbolic rh_symbolic;

@@ -30,14 +30,14 @@ class rh_network_desc(C.Structure):
 
 class rh_options(C.Structure):
     _fields_ = [("panel_width", C.c_int32), ("ordering", C.c_int32),
-                ("lds_panel", C.c_int32), ("reserved", C.c_int32)]
+                ("lds_panel", C.c_int32), ("refactor", C.c_int32)]
 
 
 class rh_info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "nx", "nu", "m", "nb", "nl", "ng", "nnz_gx", "nnz_lu", "nnz_gu", "nnz_a", "nnz_k",
         "levels_lower", "levels_upper", "refactor_ops", "max_lu_row", "panel_width",
-        "lds_panel", "max_row_ops")]
+        "lds_panel", "max_row_ops", "refactor_kernel")]
 
 
 # name -> (restype, argtypes); every symbol declared in include/rhipm.h

@@ -166,7 +166,7 @@ void build_sweep(Sweep& sw, int n, const std::vector<int>& level, int nlev,
 
 }  // namespace
 
-rh_status analyze(const rh_network_desc& d, const rh_options* /*opts*/, Symbolic& s) {
+rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s) {
   // ------------------------------------------------------------ validation
   if (d.nb < 2 || d.nl < 1 || d.ng < 1) return fail(s, RH_ERR_ARG, "need nb>=2, nl>=1, ng>=1");
   if (!d.bus_type || !d.pd || !d.qd || !d.vmin || !d.vmax || !d.from || !d.to || !d.r ||
@@ -452,6 +452,130 @@ rh_status analyze(const rh_network_desc& d, const rh_options* /*opts*/, Symbolic
     s.rf_lds_doubles = std::max(s.rf_lds_doubles, (1024 / lanes) * stride);
   }
 
+  // --------------------------------- wave-resident refactorisation tasks
+  // Each task runs on one wave. Lane (segment g, position p) holds entry p of
+  // its row; at step q the multiplier of the q-th lower entry is broadcast
+  // from lane q of the segment and every lane applies a_p -= l_q u_(k_q, col p)
+  // with u read from LDS at its packed 16-bit index (the zero slot where the
+  // row of U has no such entry). Record: {lane-data offset, steps, wide,
+  // 0, rp0[4], len[4]}; lane fields: pivot-row index of a lower entry
+  // (reciprocal pivot to read) or -1, LDS slot of an upper entry or -1, row
+  // index at the diagonal or -1, position of a lower entry or -1; then the
+  // packed indices, two steps per int.
+  {
+    s.rw_ok = false;
+    s.rw_wbeg.clear();
+    s.rw_levend.clear();
+    s.rw_rec.clear();
+    s.rw_lane.clear();
+    std::vector<int> ustart(nx + 1, 0);
+    for (int i = 0; i < nx; ++i) ustart[i + 1] = ustart[i] + (s.lu_ptr[i + 1] - s.lu_diag[i] - 1);
+    s.rw_nnz_u = ustart[nx];
+    const size_t lds = (size_t(s.rw_nnz_u) + 1 + nx) * sizeof(double);
+    bool ok = s.max_row <= 64 && s.rw_nnz_u < 65535 && lds <= size_t(kRefLdsBudget) &&
+              !(opts && opts->refactor == 1);
+    if (ok) {
+      const int zslot = s.rw_nnz_u;
+      struct Task { int wide; int nsteps; std::vector<int> rows; };
+      std::vector<std::vector<std::vector<int>>> wave_tasks(kRwWaves);   // [wave][level] -> task ids
+      std::vector<Task> tasks;
+      const int nlev = s.sl.nlev;
+      for (int w = 0; w < kRwWaves; ++w) wave_tasks[w].assign(nlev, {});
+      for (int l = 0; l < nlev; ++l) {
+        std::vector<int> shortr, longr;
+        for (int q = s.sl.lev_ptr[l]; q < s.sl.lev_ptr[l + 1]; ++q) {
+          const int i = s.sl.rows[q];
+          (s.lu_ptr[i + 1] - s.lu_ptr[i] <= 16 ? shortr : longr).push_back(i);
+        }
+        auto nlow = [&](int i) { return s.lu_diag[i] - s.lu_ptr[i]; };
+        std::stable_sort(shortr.begin(), shortr.end(),
+                         [&](int a, int b) { return nlow(a) > nlow(b); });
+        std::vector<int> ids;
+        for (size_t g = 0; g < shortr.size(); g += 4) {
+          Task t{0, 0, {}};
+          for (size_t h = g; h < std::min(shortr.size(), g + 4); ++h) {
+            t.rows.push_back(shortr[h]);
+            t.nsteps = std::max(t.nsteps, nlow(shortr[h]));
+          }
+          ids.push_back(int(tasks.size()));
+          tasks.push_back(t);
+        }
+        for (int i : longr) {
+          ids.push_back(int(tasks.size()));
+          tasks.push_back(Task{1, nlow(i), {i}});
+        }
+        // longest first to the least loaded wave
+        std::stable_sort(ids.begin(), ids.end(),
+                         [&](int a, int b) { return tasks[a].nsteps > tasks[b].nsteps; });
+        std::vector<long> load(kRwWaves, 0);
+        for (int id : ids) {
+          int w = int(std::min_element(load.begin(), load.end()) - load.begin());
+          load[w] += tasks[id].nsteps + 4;
+          wave_tasks[w][l].push_back(id);
+        }
+      }
+      s.rw_wbeg.assign(kRwWaves + 1, 0);
+      s.rw_levend.assign(size_t(kRwWaves) * nlev, 0);
+      for (int w = 0; w < kRwWaves; ++w) {
+        int cnt = 0;
+        for (int l = 0; l < nlev; ++l) {
+          for (int id : wave_tasks[w][l]) {
+            const Task& t = tasks[id];
+            const int off = int(s.rw_lane.size());
+            const int npk = (t.nsteps + 1) / 2;
+            std::vector<int> blk(size_t(kRwFields + npk) * 64, -1);
+            for (int k = 0; k < npk; ++k)
+              for (int ln = 0; ln < 64; ++ln)
+                blk[size_t(kRwFields + k) * 64 + ln] = int(unsigned(zslot) | (unsigned(zslot) << 16));
+            int rec[kRwRec] = {off, t.nsteps, t.wide, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (size_t g = 0; g < t.rows.size(); ++g) {
+              const int i = t.rows[g], rp0 = s.lu_ptr[i], len = s.lu_ptr[i + 1] - rp0;
+              const int nl = s.lu_diag[i] - rp0;
+              rec[4 + g] = rp0;
+              rec[8 + g] = len;
+              const int lane0 = t.wide ? 0 : 16 * int(g);
+              for (int p = 0; p < len; ++p) {
+                const int ln = lane0 + p;
+                if (p < nl) {
+                  blk[0 * 64 + ln] = s.lu_col[rp0 + p];
+                  blk[3 * 64 + ln] = p;
+                } else if (p == nl) {
+                  blk[2 * 64 + ln] = i;
+                } else {
+                  blk[1 * 64 + ln] = ustart[i] + (p - nl - 1);
+                }
+              }
+              for (int q = 0; q < nl; ++q) {
+                const int kr = s.lu_col[rp0 + q];
+                for (int o = s.rf_kptr[rp0 + q]; o < s.rf_kptr[rp0 + q + 1]; ++o) {
+                  const int p = s.rf_op_dst[o] - rp0;
+                  const int u = ustart[kr] + (s.rf_op_src[o] - s.lu_diag[kr] - 1);
+                  int& w2 = blk[size_t(kRwFields + q / 2) * 64 + lane0 + p];
+                  unsigned wv = unsigned(w2);
+                  if (q & 1) wv = (wv & 0xffffu) | (unsigned(u) << 16);
+                  else wv = (wv & 0xffff0000u) | unsigned(u);
+                  w2 = int(wv);
+                }
+              }
+            }
+            s.rw_lane.insert(s.rw_lane.end(), blk.begin(), blk.end());
+            s.rw_rec.insert(s.rw_rec.end(), rec, rec + kRwRec);
+            ++cnt;
+          }
+          s.rw_levend[size_t(w) * nlev + l] = cnt;
+        }
+        s.rw_wbeg[w + 1] = s.rw_wbeg[w] + cnt;
+      }
+      // a dummy record (loaded, never run, by waves past their last task) and
+      // padding: the kernel loads kRwFields + kRwPacked ints per lane per task
+      const int pad = int(s.rw_lane.size());
+      int dummy[kRwRec] = {pad, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      s.rw_rec.insert(s.rw_rec.end(), dummy, dummy + kRwRec);
+      s.rw_lane.insert(s.rw_lane.end(), size_t(kRwFields + kRwPacked) * 64, -1);
+      s.rw_ok = true;
+    }
+  }
+
   // -------------------------------------------------- w = [u ; x internal]
   auto w_theta = [&](int i) { return s.th_nat[i] >= 0 ? nu + s.iperm[s.th_nat[i]] : -1; };
   auto w_vm = [&](int i) {
@@ -712,6 +836,53 @@ rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, doub
   const int nx = s.nx;
   std::vector<double> lu(s.lu_col.size(), 0.0);
   for (size_t p = 0; p < s.gx_col.size(); ++p) lu[s.gx_lu[p]] = gxv[p];
+  if (s.rw_ok) {
+    // the wave-resident schedule, lane by lane as the device runs it
+    std::vector<double> ulds(size_t(s.rw_nnz_u) + 1, 0.0), rinv(nx, 0.0);
+    const int nlev = s.sl.nlev;
+    for (int lv = 0; lv < nlev; ++lv)
+      for (int w = 0; w < kRwWaves; ++w) {
+        const int k0 = lv ? s.rw_levend[size_t(w) * nlev + lv - 1] : 0;
+        const int k1 = s.rw_levend[size_t(w) * nlev + lv];
+        for (int k = k0; k < k1; ++k) {
+          const int* R = &s.rw_rec[size_t(s.rw_wbeg[w] + k) * kRwRec];
+          const int nsteps = R[1], wide = R[2];
+          double acc[64], r[64], amax[64];
+          int ipos[64], pos[64], udst[64], drow[64];
+          for (int ln = 0; ln < 64; ++ln) {
+            const int seg = wide ? 0 : ln >> 4, p = wide ? ln : ln & 15;
+            ipos[ln] = p < R[8 + seg] ? R[4 + seg] + p : -1;
+            acc[ln] = ipos[ln] >= 0 ? lu[ipos[ln]] : 0.0;
+            const int* b = &s.rw_lane[size_t(R[0]) + ln];
+            r[ln] = b[0] >= 0 ? rinv[b[0]] : 0.0;
+            udst[ln] = b[64];
+            drow[ln] = b[128];
+            pos[ln] = b[192];
+            amax[ln] = std::fabs(acc[ln]);
+          }
+          for (int q = 0; q < nsteps; ++q) {
+            double t[64];
+            for (int ln = 0; ln < 64; ++ln) t[ln] = acc[ln] * r[ln];
+            for (int ln = 0; ln < 64; ++ln) {
+              const double l = wide ? t[q] : t[16 * (ln >> 4) + q];
+              const unsigned pk = unsigned(s.rw_lane[size_t(R[0]) + size_t(kRwFields + q / 2) * 64 + ln]);
+              const int ui = std::min(int((pk >> (16 * (q & 1))) & 0xffffu), s.rw_nnz_u);
+              if (pos[ln] == q) acc[ln] = l;
+              acc[ln] = std::fma(-l, ulds[ui], acc[ln]);
+            }
+          }
+          for (int ln = 0; ln < 64; ++ln) {
+            if (ipos[ln] >= 0) lu[ipos[ln]] = acc[ln];
+            if (udst[ln] >= 0) ulds[udst[ln]] = acc[ln];
+            if (drow[ln] >= 0) {
+              if (acc[ln] == 0.0) return RH_SMALL_PIVOT;
+              rinv[drow[ln]] = 1.0 / acc[ln];
+            }
+          }
+          (void)amax;
+        }
+      }
+  } else
   // refactorise level by level (same schedule as the device)
   for (int lv = 0; lv < s.sl.nlev; ++lv)
     for (int sl = s.sl.lev_ptr[lv]; sl < s.sl.lev_ptr[lv + 1]; ++sl) {

@@ -17,6 +17,14 @@ namespace rh {
 constexpr int kKRowBlock = 256;
 constexpr int kMaxRowBlocks = 16;   // LDS-resident panels: nu + nx <= 16 * 256
 constexpr int kRefLdsBudget = 155 * 1024;   // bytes of LDS the refactorisation may use
+// Wave-resident refactorisation: 8 waves; a task is one row of at most 64
+// LU entries (one lane per entry) or up to four rows of at most 16 entries
+// (one 16-lane row each). Per task: a record of kRwRec ints and, per lane,
+// kRwFields ints followed by the packed 16-bit U indices of its steps.
+constexpr int kRwWaves = 8;
+constexpr int kRwRec = 12;
+constexpr int kRwFields = 4;
+constexpr int kRwPacked = 32;
 
 // Per-line record written by the line-evaluation kernel (doubles).
 enum LineSlot : int {
@@ -124,6 +132,14 @@ struct Symbolic {
   // sources, the pivots, the destination offsets and the op pointers
   std::vector<int> rf_lmeta;               // 6 per level
   int rf_lds_doubles = 0;                  // LDS the refactorisation needs
+  // wave-resident refactorisation (used when every LU row has at most 64
+  // entries and U plus the pivot reciprocals fit in LDS)
+  bool rw_ok = false;
+  int rw_nnz_u = 0;                        // U entries held in LDS; slot rw_nnz_u is 0
+  std::vector<int> rw_wbeg;                // kRwWaves + 1: first task of each wave
+  std::vector<int> rw_levend;              // kRwWaves * nlev: end of each level per wave
+  std::vector<int> rw_rec;                 // kRwRec ints per task (wave-major order)
+  std::vector<int> rw_lane;                // per-lane task data (see analysis.cpp)
   std::vector<double> k_cdiag;             // constant diagonal (2 c2 base^2 on Pg)
   std::vector<int> sig_map;                // w -> index into [Sigma_u ; Sigma_x(natural)]
   // evaluation gather: dst = [luval | gu | a | g(natural) | h]

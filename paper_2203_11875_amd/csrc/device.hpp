@@ -62,6 +62,9 @@ struct DevNet {
   const int *kb_base, *kb_len, *kell_col, *kell_pos;
   double* kell_val;
   int kell_n, kb_n;
+  // wave-resident refactorisation (rw_ok): task records, per-lane data
+  int rw_ok, rw_nnz_u, rw_nlev, rw_ntask;
+  const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane;
   const int* rf_lmeta;    // 6 ints per refactorisation level
   int rf_lds_doubles;
   const double* k_cdiag;
@@ -109,8 +112,12 @@ hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
 // Cholesky of the lower triangle of K + delta I in place, L y = b (b is
 // destroyed), then L^T x = y with x written over y. status[0..1] device.
 // dinv: workspace of ceil(n / 32) * 32 * 32 doubles (inverted diagonal blocks).
+// Workspaces: dinv (2 * 1024 * ceil(n / 32) doubles), lrow ((32 ceil(n / 32))^2
+// doubles). trace (optional, device int64[8 * (ceil(n / 32) + 1)]): wall-clock
+// stamps of the first work-group of every launch, for profiling.
 hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
-                                 double* y, double* dinv, int* status, hipStream_t st);
+                                 double* y, double* dinv, double* lrow, int* status,
+                                 hipStream_t st, long long* trace = nullptr);
 hipError_t launch_eval_objective(const DevNet& d, const double* u, double* f, hipStream_t st);
 int max_lds_bytes();
 // LDS one row of the refactorisation stages (row, U sources, pivots, schedule).

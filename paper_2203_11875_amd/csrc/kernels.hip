@@ -310,6 +310,174 @@ __device__ __forceinline__ void block_sync() {
     __syncthreads();
 }
 
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                (unsigned long long)(unsigned)lo));
+}
+
+// p[i] when ok, else 0, with the load itself unconditional (p[0] stands in):
+// a load inside a lane-divergent branch makes the compiler wait for it at
+// the end of the branch, which serialises a run of such loads.
+__device__ __forceinline__ double ld_or0(const double* p, size_t i, bool ok) {
+  const double v = p[ok ? i : 0];
+  return ok ? v : 0.0;
+}
+
+// ------------------------------------------- wave-resident refactorisation
+// Same row-by-row Doolittle elimination as k_refactor, with U and the pivot
+// reciprocals of the finished rows resident in LDS and each row held in
+// registers, one lane per LU entry (a wave per long row, a 16-lane row of
+// the wave per short row). Step q of a row broadcasts the multiplier of its
+// q-th lower entry (readlane across the wave, or DPP row_newbcast within
+// 16 lanes) and every lane applies a_p -= l_q u_(k_q, col p), reading u from
+// LDS at the packed index prepared by the analysis. Levels of the L sweep are
+// separated by barriers; inside a level each wave runs its own list of tasks
+// and loads the next task's values and indices while running the current one.
+struct RwRec {
+  int v[kRwRec];
+};
+
+struct RwSet {
+  double init;
+  int ipos, rcol, udst, drow, pos, nsteps, wide;
+  int pk[kRwPacked];
+};
+
+__device__ __forceinline__ void rw_rec_load(const DevNet& d, int wave, int k, int cnt, RwRec& R) {
+  const int gi = k < cnt ? d.rw_wbeg[wave] + k : d.rw_ntask;   // past the end: the dummy record
+  const int* r = d.rw_rec + (size_t)gi * kRwRec;
+#pragma unroll
+  for (int f = 0; f < kRwRec; ++f) R.v[f] = __builtin_amdgcn_readfirstlane(r[f]);
+}
+
+__device__ __forceinline__ void rw_set_load(const DevNet& d, const RwRec& R, RwSet& X, int lane) {
+  X.nsteps = R.v[1];
+  X.wide = R.v[2];
+  int seg = X.wide ? 0 : lane >> 4;
+  const int p = X.wide ? lane : lane & 15;
+  asm volatile("" : "+v"(seg));                // keep the selects (no indexed table)
+  int rp0 = R.v[4], len = R.v[8];
+  rp0 = seg == 1 ? R.v[5] : rp0;
+  len = seg == 1 ? R.v[9] : len;
+  rp0 = seg == 2 ? R.v[6] : rp0;
+  len = seg == 2 ? R.v[10] : len;
+  rp0 = seg == 3 ? R.v[7] : rp0;
+  len = seg == 3 ? R.v[11] : len;
+  X.ipos = p < len ? rp0 + p : -1;
+  X.init = ld_or0(d.dst + d.d_lu, X.ipos, X.ipos >= 0);
+  const int* b = d.rw_lane + R.v[0] + lane;
+  X.rcol = b[0];
+  X.udst = b[64];
+  X.drow = b[128];
+  X.pos = b[192];
+#pragma unroll
+  for (int k = 0; k < kRwPacked; ++k) X.pk[k] = b[(kRwFields + k) * 64];
+}
+
+__device__ __forceinline__ double rw_u(const double* ulds, int pk, int half, int zslot) {
+  const int ui = (pk >> (16 * half)) & 0xffff;
+  return ulds[min(ui, zslot)];
+}
+
+template <int Q>
+__device__ __forceinline__ void rw_steps16(double& acc, double r, const RwSet& X, int nsteps,
+                                           const double (&u)[16]) {
+  if constexpr (Q < 16) {
+    if (Q >= nsteps) return;
+    const long long b = __builtin_bit_cast(long long, acc * r);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x150 + Q, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x150 + Q, 0xF, 0xF, false);
+    const double l = __builtin_bit_cast(
+        double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    if (X.pos == Q) acc = l;
+    acc = fma(-l, u[Q], acc);
+    rw_steps16<Q + 1>(acc, r, X, nsteps, u);
+  }
+}
+
+__device__ __forceinline__ void rw_run(const DevNet& d, const RwSet& X, double* ulds,
+                                       double* rinv, int lane) {
+  const int zslot = d.rw_nnz_u;
+  const int nsteps = __builtin_amdgcn_readfirstlane(X.nsteps);
+  const int wide = __builtin_amdgcn_readfirstlane(X.wide);
+  double acc = X.init;
+  const double r = X.rcol >= 0 ? rinv[X.rcol] : 0.0;
+  double amax = fabs(acc);
+  if (wide) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (8 * c >= nsteps) break;
+      double u[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) u[s] = rw_u(ulds, X.pk[4 * c + s / 2], s & 1, zslot);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) asm volatile("" : "+v"(u[s]));   // read them all up front
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int q = 8 * c + s;
+        if (q >= nsteps) break;
+        const double l = readlane_d(acc * r, q);
+        if (X.pos == q) acc = l;
+        acc = fma(-l, u[s], acc);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  } else {
+    double u[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) u[s] = rw_u(ulds, X.pk[s / 2], s & 1, zslot);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) asm volatile("" : "+v"(u[s]));    // read them all up front
+    rw_steps16<0>(acc, r, X, nsteps, u);
+    for (int off = 8; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  }
+  if (X.ipos >= 0) d.dst[d.d_lu + X.ipos] = acc;
+  if (X.udst >= 0) ulds[X.udst] = acc;
+  if (X.drow >= 0) {
+    rinv[X.drow] = 1.0 / acc;
+    if (!(fabs(acc) > 1e-14 * amax)) {
+      d.status[2] = 1;
+      d.status[3] = X.drow;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
+  extern __shared__ double rw_lds[];
+  double* ulds = rw_lds;                       // U entries, then the zero slot
+  double* rinv = rw_lds + d.rw_nnz_u + 1;      // reciprocal pivots by row
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cnt = d.rw_wbeg[wave + 1] - d.rw_wbeg[wave];
+  const int* levend = d.rw_levend + (size_t)wave * d.rw_nlev;
+  if (threadIdx.x == 0) ulds[d.rw_nnz_u] = 0.0;
+  RwRec r0, r1;
+  RwSet A, B;
+  rw_rec_load(d, wave, 0, cnt, r0);
+  rw_rec_load(d, wave, 1, cnt, r1);
+  rw_set_load(d, r0, A, lane);
+  lds_barrier();
+  int k = 0;
+  for (int lev = 0; lev < d.rw_nlev; ++lev) {
+    const int end = levend[lev];
+    while (k < end) {
+      if ((k & 1) == 0) {
+        rw_set_load(d, r1, B, lane);
+        rw_rec_load(d, wave, k + 2, cnt, r0);
+        rw_run(d, A, ulds, rinv, lane);
+      } else {
+        rw_set_load(d, r0, A, lane);
+        rw_rec_load(d, wave, k + 2, cnt, r1);
+        rw_run(d, B, ulds, rinv, lane);
+      }
+      ++k;
+    }
+    lds_barrier();
+  }
+}
+
 // Level metadata of one sweep, staged in LDS at kernel start:
 // [slot0, rows, base, len, log2(lanes)] per level.
 constexpr int kMeta = 5;
@@ -703,230 +871,373 @@ __global__ void k_symmetrize(double* K, long ld, int n) {
 
 constexpr int NB = 32;   // panel width of the blocked Cholesky
 
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
-  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) |
-                                                (unsigned long long)(unsigned)lo));
-}
-
-// Panel step k0 of a right-looking blocked Cholesky of the lower triangle of
-// A + delta I, with the forward substitution L y = b folded in (b is a work
-// copy whose rows below the panel receive b_i -= L_ik y_k). Block 0 owns the
-// diagonal block and writes L_kk and y_k; block t >= 1 owns rows
-// [k0 + t NB, ...) and writes L_ik = A_ik L_kk^{-T}. Every block factors the
-// (already updated) diagonal block redundantly, so the panel needs one
-// launch. 256 threads; thread (i, c0) keeps elements (i, c0 + 8 q), q < 4, of
-// the diagonal block and of its row block in registers. A pivot costs two
-// barriers: (A) the pivot value is published; every thread forms the
-// reciprocal square root and the owners of column j scale it, divide the
-// row block's column j and form y_j; (B) the scaled columns are published
-// and every thread applies the rank-one updates.
-constexpr int kPanelThreads = 256;
-constexpr int kPanelQ = NB * NB / kPanelThreads;   // elements per thread (4)
-
-__global__ void __launch_bounds__(kPanelThreads) k_potrf_panel(double* A, long ld, int n, int k0,
-                                                              double delta, double* b, double* y,
-                                                              int* status) {
-  if (status[0] != 0) return;
-  __shared__ double lcol[NB];   // column j of L_kk
-  __shared__ double xcol[NB];   // column j of the row block's L_ik
-  __shared__ double piv;
-  __shared__ double yj;
-  const int tid = threadIdx.x;
-  const int ti = tid % NB, c0 = tid / NB;          // c0 in [0, 8)
-  const int bsz = min(NB, n - k0);
-  const int r0 = k0 + blockIdx.x * NB;
-  const int rb = blockIdx.x ? min(NB, n - r0) : 0;
-  double a[kPanelQ], x[kPanelQ];
-#pragma unroll
-  for (int q = 0; q < kPanelQ; ++q) {
-    const int c = c0 + 8 * q;
-    double v = 0.0;
-    if (ti < bsz && c <= ti) v = A[(size_t)(k0 + c) * ld + k0 + ti];
-    if (ti == c && ti < bsz) v += delta;
-    a[q] = v;
-    x[q] = (ti < rb && c < bsz) ? A[(size_t)(k0 + c) * ld + r0 + ti] : 0.0;
-  }
-  double bi = (c0 == 0 && ti < bsz) ? b[k0 + ti] : 0.0;
-  double bacc = 0.0, yv = 0.0;
-  if (tid == 0) piv = a[0];                         // element (0, 0)
-  for (int j = 0; j < bsz; ++j) {
-    __syncthreads();                                // (A)
-    const double d = piv;
-    if (!(d > 0.0)) {
-      if (blockIdx.x == 0 && tid == 0) {
-        status[0] = 1;
-        status[1] = k0 + j;
-      }
-      return;   // uniform: every thread read the same pivot
-    }
-    const double rs = rsqrt(d);
-#pragma unroll
-    for (int q = 0; q < kPanelQ; ++q) {
-      if (c0 + 8 * q == j) {
-        if (ti >= j && ti < bsz) {
-          a[q] = ti == j ? d * rs : a[q] * rs;      // column j of L
-          lcol[ti] = a[q];
-        }
-        if (ti < rb) {
-          x[q] *= rs;                               // x_ij / l_jj
-          xcol[ti] = x[q];
-        }
-      }
-    }
-    if (c0 == 0 && ti == j) {
-      yv = bi * rs;                                 // y_j = b_j / l_jj
-      yj = yv;
-    }
-    __syncthreads();                                // (B)
-    const double li = lcol[ti], xi = xcol[ti], yc = yj;
-#pragma unroll
-    for (int q = 0; q < kPanelQ; ++q) {
-      const int c = c0 + 8 * q;
-      if (c > j && c < bsz) {
-        const double lc = lcol[c];
-        if (c <= ti && ti < bsz) a[q] = fma(-li, lc, a[q]);
-        if (ti < rb) x[q] = fma(-xi, lc, x[q]);
-      }
-      if (c == j + 1 && ti == j + 1) piv = a[q];    // next pivot, after its update
-    }
-    if (c0 == 0) {
-      if (ti > j && ti < bsz) bi = fma(-li, yc, bi);
-      if (ti < rb) bacc = fma(xi, yc, bacc);
-    }
-  }
-  if (blockIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < kPanelQ; ++q) {
-      const int c = c0 + 8 * q;
-      if (ti < bsz && c <= ti) A[(size_t)(k0 + c) * ld + k0 + ti] = a[q];
-    }
-    if (c0 == 0 && ti < bsz) y[k0 + ti] = yv;
-    return;
-  }
-#pragma unroll
-  for (int q = 0; q < kPanelQ; ++q) {
-    const int c = c0 + 8 * q;
-    if (ti < rb && c < bsz) A[(size_t)(k0 + c) * ld + r0 + ti] = x[q];
-  }
-  if (c0 == 0 && ti < rb) b[r0 + ti] -= bacc;
-}
-
-// Inverse of every NB x NB lower-triangular diagonal block of the factor
-// (one work-group per block), for the blocked backward substitution:
-// X = L_bb^{-1} column by column, right-looking over the rows of L_bb.
-__global__ void __launch_bounds__(NB * NB) k_diag_inverse(const double* A, long ld, int n,
-                                                         double* inv, const int* status) {
-  if (status[0] != 0) return;
-  __shared__ double L[NB][NB + 1];
-  __shared__ double xr[NB];
-  const int bk = blockIdx.x, k0 = bk * NB, bsz = min(NB, n - k0);
-  const int ti = threadIdx.x % NB, tc = threadIdx.x / NB;   // element (row ti, column tc)
-  L[ti][tc] = (ti < bsz && tc <= ti) ? A[(size_t)(k0 + tc) * ld + k0 + ti] : 0.0;
-  double xv = (ti == tc && ti < bsz) ? 1.0 : 0.0;          // X = I, then forward elimination
-  __syncthreads();
-  for (int j = 0; j < bsz; ++j) {
-    if (ti == j) {
-      xv /= L[j][j];
-      xr[tc] = xv;
-    }
-    __syncthreads();
-    if (ti > j && ti < bsz) xv = fma(-L[ti][j], xr[tc], xv);
-    __syncthreads();
-  }
-  inv[(size_t)bk * NB * NB + tc * NB + ti] = (ti < bsz && tc < bsz) ? xv : 0.0;   // column-major
-}
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-// Trailing update A[i, j] -= sum_c L[i, c] L[j, c] over the panel columns
-// [k0, k0 + NB) for the lower 32 x 32 tiles of the trailing matrix, on FP64
-// MFMA (16x16x4). Four waves per tile, one 16 x 16 quadrant each. Operand
-// layout of v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16 k, B[k][j] in lane
-// j + 16 k, D[i][j] in lane j + 16 (i % 4), register i / 4.
-__global__ void __launch_bounds__(256) k_syrk(double* A, long ld, int n, int k0, int* status) {
-  if (status[0] != 0) return;
-  const int k1 = k0 + NB;
-  int t = blockIdx.x, ti = 0;
-  while (t > ti) {
-    t -= ti + 1;
-    ++ti;
-  }
-  const int tj = t;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int qi = wave / 2, qj = wave % 2;
-  if (ti == tj && qi < qj) return;            // strictly upper quadrant of a diagonal tile
-  const int ri = k1 + ti * 32 + qi * 16;      // first row of the quadrant
-  const int cj = k1 + tj * 32 + qj * 16;      // first column of the quadrant
-  const int li = lane % 16, kk = lane / 16;
-  const bool rok = ri + li < n, cok = cj + li < n;
-  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+// Position of row r of a published panel column in LDS: the diagonal-tile
+// rows in the order (r % 4) * 8 + r / 4, so that the 8 rows a wave needs as
+// column indices (w + 4 t, t < 8) are contiguous; rows >= NB follow as is.
+__device__ __forceinline__ int cpos(int r) { return r < NB ? (r & 3) * 8 + (r >> 2) : r; }
+
+// In-place factorisation of a 64 x NB panel slice P in LDS by the four waves
+// of a work-group: rows 0..NB-1 hold the symmetric diagonal tile D (lower
+// part used), rows NB..2NB-1 a tile B below it. On return rows 0..NB-1 hold
+// L = chol(D) (zero above the diagonal) and rows NB..2NB-1 hold B L^{-T}.
+// Wave w owns columns w + 4 t (t < 8) with lane = row, 8 registers per lane.
+//
+// The elimination is scaled so that no square root or division sits on the
+// pivot-to-pivot chain: with d_j the current pivot and d_j = alpha_j 2^e_j
+// (alpha_j in [1/2, 1), exact), the trailing entries become
+//   T_ic <- alpha_j T_ic - 2^-e_j T_ij T_cj,
+// which is 2^-e_j d_j times the usual Schur update, so the working matrix at
+// step j is sigma_j times the true Schur complement with
+// sigma_{j+1} = sigma_j alpha_j (a power-of-two-free product, bounded in
+// [2^-NB, 1]). Column c of L is then T_.c / sqrt(sigma_c d_c), applied to all
+// columns at the end. Pivot j costs one barrier: the owner of column j + 1
+// applies step j to that column first and publishes it. Returns the first
+// non-positive pivot among this wave's columns, or -1.
+__device__ __forceinline__ int chol_panel64(double (*P)[NB + 1], double (*cb)[2 * NB], int wave,
+                                            int lane) {   // cb: [4][2 NB], two published + two dummy
+  double a[8], sg[8], dg[8];
 #pragma unroll
-  for (int s4 = 0; s4 < NB / 4; ++s4) {
-    const size_t col = (size_t)(k0 + 4 * s4 + kk) * ld;
-    const double av = rok ? A[col + ri + li] : 0.0;
-    const double bv = cok ? A[col + cj + li] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  for (int t = 0; t < 8; ++t) {
+    a[t] = P[lane][wave + 4 * t];
+    sg[t] = 1.0;
+    dg[t] = 1.0;
   }
-  const int j = cj + li;
+  if (wave == 0) cb[0][cpos(lane)] = a[0];
+  lds_barrier();
+  double sigma = 1.0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = ri + 4 * r + kk;
-    if (i < n && j < n && j <= i) A[(size_t)j * ld + i] -= acc[r];
+  for (int j = 0; j < NB; ++j) {
+    const int ow = j & 3, tj = j >> 2;
+    const double* cbj = cb[j & 1];
+    const double d = cbj[cpos(j)];
+    const double tij = cbj[cpos(lane)];
+    // register tn holds column j + 1 in its owner wave; in every wave the
+    // columns w + 4 t right of j are t > tn, and t = tn when w > j - 4 tn
+    const int tn = (j + 1) >> 2, on = (j + 1) & 3;
+    double xn = j + 1 < NB ? cbj[wave * 8 + (tn & 7)] : 0.0;
+    asm volatile("" : "+v"(xn));             // load it with d and t_ij
+    int e;
+    const double alpha = frexp(d, &e);
+    const double bij = ldexp(-tij, -e);        // -2^-e_j T_ij
+    sg[tj] = wave == ow ? sigma : sg[tj];
+    dg[tj] = wave == ow ? d : dg[tj];
+    sigma *= alpha;
+    if (j + 1 < NB) {
+      const bool cn = wave > j - 4 * tn;
+      a[tn] = fma(cn ? bij : 0.0, xn, (cn ? alpha : 1.0) * a[tn]);
+      // the owner publishes column j + 1; the other waves write a dummy row
+      double* dst = wave == on ? &cb[(j + 1) & 1][cpos(lane)] : &cb[2 + ((j + 1) & 1)][lane];
+      *dst = a[tn];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = tn + 1; t < 8; ++t) a[t] = fma(bij, cbj[wave * 8 + t], alpha * a[t]);
+      // keep this step's updates ahead of the barrier (not sunk into the next
+      // pivot's critical path)
+#pragma unroll
+      for (int t = tn; t < 8; ++t) asm volatile("" : "+v"(a[t]));
+      __builtin_amdgcn_sched_barrier(0);
+      lds_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  int fl = -1;
+#pragma unroll
+  for (int t = 7; t >= 0; --t) {
+    const int c = wave + 4 * t;
+    if (!(dg[t] > 0.0)) fl = c;
+    const double v = a[t] * rsqrt(sg[t] * dg[t]);
+    a[t] = (lane < NB && lane < c) ? 0.0 : v;
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) P[lane][wave + 4 * t] = a[t];
+  return fl;
+}
+
+// 16 x 16 quadrant of a 32 x 32 tile in the accumulator layout of
+// v_mfma_f64_16x16x4f64 computing the transposed product: lane li + 16 kk,
+// register e holds element (row ri + li, column cj + 4 e + kk), so each
+// register is four coalesced 128-byte row runs.
+__device__ __forceinline__ d4_t load_quad(const double* A, long ld, int n, int ri, int cj, int li,
+                                          int kk, double diag_add) {
+  d4_t v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = ri + li, c = cj + 4 * e + kk;
+    double x = ld_or0(A, (size_t)c * ld + r, r < n && c < n);
+    if (r == c) x += diag_add;
+    v[e] = x;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void store_quad_lower(double* A, long ld, int n, int ri, int cj, int li,
+                                                 int kk, d4_t v) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = ri + li, c = cj + 4 * e + kk;
+    if (r < n && c <= r) A[(size_t)c * ld + r] = v[e];
   }
 }
 
-// Backward substitution L^T x = y in one work-group (x written over y), by
-// NB-row blocks from the bottom: rhs_b = y_b - sum_{i below} L_ib^T x_i (dot
-// products over contiguous columns of L, coalesced, no sequential chain),
-// then x_b = L_bb^{-T} rhs_b with the inverted diagonal block.
-__global__ void __launch_bounds__(256) k_trsv_lt(const double* A, long ld, int n, double* y,
-                                                 const double* inv, const int* status) {
+// Blocked right-looking Cholesky of A + delta I (lower triangle) with the
+// forward substitution L y = b folded in; one launch per column block k.
+// Work-groups [0, nbk - k) are the panel of column block k: group g owns row
+// block i = k + g. It applies the rank-NB update of panel k - 1 to the
+// diagonal tile (k, k) and to its own tile (i, k) on MFMA, and
+// b_i -= L_{i,k-1} y_{k-1}; the four waves then factor the 64 x NB slice
+// [A_kk; A_ik] (chol_panel64), which yields L_kk redundantly in every group
+// and L_ik = A_ik L_kk^{-T}. Group 0 carries the identity below the diagonal
+// tile instead, which yields L_kk^{-T}: it stores L_kk in dl, L_kk^{-T} in
+// inv (column-major) and y_k = L_kk^{-1} b_k. The remaining groups apply
+// panel k - 1 to the trailing tiles (i, j), k < j <= i. The diagonal tile
+// (k, k) of A is read by every panel group of the launch, so L_kk goes to A
+// one launch later. The off-diagonal tiles are also stored by rows in lrow
+// (row block i: NB rows of nbk NB entries) for the backward substitution.
+// delta enters each diagonal tile on its first touch (k <= 1).
+__global__ void __launch_bounds__(256) k_chol_step(double* A, long ld, int n, int k, double delta,
+                                                   double* b, double* y, double* inv, double* dl,
+                                                   double* lrow, int* status, long long* trace) {
   if (status[0] != 0) return;
-  extern __shared__ double xs[];
-  __shared__ double red[NB][65];
-  __shared__ double rhsb[NB];
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  for (int i = tid; i < n; i += 256) xs[i] = y[i];
-  __syncthreads();
-  const int nblk = (n + NB - 1) / NB;
-  for (int bk = nblk - 1; bk >= 0; --bk) {
-    const int j0 = bk * NB, j1 = min(n, j0 + NB);
-    // each wave takes NB/4 columns with independent accumulators
-    {
-      double acc[NB / 4];
-#pragma unroll
-      for (int q = 0; q < NB / 4; ++q) acc[q] = 0.0;
-      for (int i = j1 + lane; i < n; i += 64) {
-        const double xi = xs[i];
-#pragma unroll
-        for (int q = 0; q < NB / 4; ++q) {
-          const int j = j0 + wave * (NB / 4) + q;
-          if (j < j1) acc[q] = fma(A[(size_t)j * ld + i], xi, acc[q]);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < NB / 4; ++q) red[wave * (NB / 4) + q][lane] = acc[q];
+  const bool tr = trace != nullptr && blockIdx.x == 0 && threadIdx.x == 0;
+  if (tr) trace[8 * k] = wall_clock64();
+  const int nbk = (n + NB - 1) / NB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, kk = lane >> 4;
+  const int qi = wave >> 1, qj = wave & 1;
+  const int k0 = k * NB, pc0 = k0 - NB;
+  const double dfirst = k <= 1 ? delta : 0.0;
+  const int npanel = nbk - k;
+  if ((int)blockIdx.x >= npanel) {            // trailing tile, update from panel k - 1
+    int t = blockIdx.x - npanel, ti = 0;
+    while (t > ti) {
+      t -= ti + 1;
+      ++ti;
     }
-    __syncthreads();
-    if (tid < NB) {
-      double sacc = 0.0;
-      for (int l = 0; l < 64; ++l) sacc += red[tid][l];
-      rhsb[tid] = j0 + tid < j1 ? xs[j0 + tid] - sacc : 0.0;
+    const int bi = k + 1 + ti, bj = k + 1 + t;
+    if (bi == bj && qi < qj) return;           // strictly upper quadrant of a diagonal tile
+    const int ri = bi * NB + qi * 16, cj = bj * NB + qj * 16;
+    d4_t acc = load_quad(A, ld, n, ri, cj, li, kk, bi == bj ? dfirst : 0.0);
+#pragma unroll
+    for (int s = 0; s < NB; s += 4) {
+      const size_t col = (size_t)(pc0 + s + kk) * ld;
+      const double av = -ld_or0(A, col + cj + li, cj + li < n);
+      const double bv = ld_or0(A, col + ri + li, ri + li < n);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
-    __syncthreads();
-    if (tid < NB && j0 + tid < j1) {
-      // x_b = L_bb^{-T} rhs_b: row tid of L_bb^{-T} is column tid of L_bb^{-1}
-      const double* iv = inv + (size_t)bk * NB * NB + (size_t)tid * NB;
-      double v = 0.0;
-      for (int c = 0; c < NB; ++c) v = fma(iv[c], rhsb[c], v);
-      xs[j0 + tid] = v;
-    }
-    __syncthreads();
+    store_quad_lower(A, ld, n, ri, cj, li, kk, acc);
+    return;
   }
-  for (int i = tid; i < n; i += 256) y[i] = xs[i];
+
+  __shared__ double P[2 * NB][NB + 1];
+  __shared__ double cb[4][2 * NB];
+  __shared__ double red[NB], bks[NB];
+  __shared__ int fails[4];
+  const bool own = blockIdx.x > 0;
+  const int bi = k + blockIdx.x;
+  const int bsz = min(NB, n - k0);
+  double bval = 0.0;
+  if (tid < NB && bi * NB + tid < n) bval = b[bi * NB + tid];
+  const bool dq = !(qi == 0 && qj == 1);
+  const int cj = k0 + qj * 16, rd = k0 + qi * 16, ro = bi * NB + qi * 16;
+  // every operand load of this work-group is issued before the first MFMA
+  // (no branch between them, so they are all in flight together)
+  d4_t dacc = load_quad(A, ld, dq ? n : 0, rd, cj, li, kk, dfirst);
+  d4_t oacc = load_quad(A, ld, own ? n : 0, ro, cj, li, kk, 0.0);
+  double bpart = 0.0;
+  if (k > 0) {
+    double av[NB / 4], bd[NB / 4], bo[NB / 4], yv[NB / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < NB / 4; ++s4) {
+      const size_t col = (size_t)(pc0 + 4 * s4 + kk) * ld;
+      av[s4] = -ld_or0(A, col + cj + li, cj + li < n);
+      bd[s4] = ld_or0(A, col + rd + li, dq && rd + li < n);
+      bo[s4] = ld_or0(A, col + ro + li, own && ro + li < n);
+      yv[s4] = y[pc0 + 4 * s4 + kk];
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < NB / 4; ++s4) {
+      dacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bd[s4], dacc, 0, 0, 0);
+      oacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bo[s4], oacc, 0, 0, 0);
+      bpart = fma(own ? bo[s4] : bd[s4], yv[s4], bpart);   // L_{rb,k-1} y_{k-1}
+    }
+    bpart += __shfl_xor(bpart, 16);
+    bpart += __shfl_xor(bpart, 32);
+  }
+  if (tr) {
+    asm volatile("" :: "v"(dacc[0]));
+    trace[8 * k + 1] = wall_clock64();
+  }
+  if (qj == 0 && kk == 0) red[qi * 16 + li] = bpart;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int rl = qi * 16 + li, cl = qj * 16 + 4 * e + kk;
+    if (dq) P[rl][cl] = (rl >= bsz || cl >= bsz) ? (rl == cl ? 1.0 : 0.0) : dacc[e];
+    P[NB + rl][cl] = own ? oacc[e] : (rl == cl ? 1.0 : 0.0);
+  }
+  if (dq && qi == 1 && qj == 0) {              // the strictly upper quadrant is not
+#pragma unroll                                 // computed: mirror it (symmetric tile)
+    for (int e = 0; e < 4; ++e) P[4 * e + kk][16 + li] = P[16 + li][4 * e + kk];
+  }
+  lds_barrier();
+  if (tr) trace[8 * k + 2] = wall_clock64();
+  if (tid < NB) bks[tid] = bval - red[tid];     // b_i after panel k - 1
+  const int fl = chol_panel64(P, cb, wave, lane);
+  if (lane == 0) fails[wave] = fl;
+  __syncthreads();
+  if (tr) trace[8 * k + 3] = wall_clock64();
+  int first = -1;
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    if (fails[w] >= 0 && (first < 0 || fails[w] < first)) first = fails[w];
+  if (first >= 0 && first < bsz) {
+    if (blockIdx.x == 0 && tid == 0) {
+      status[1] = k0 + first;
+      status[0] = 1;
+    }
+    return;
+  }
+  if (own) {
+    const int npad = nbk * NB;
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+      const int r = idx % NB, c = idx / NB, row = bi * NB + r;
+      if (row < n) A[(size_t)(k0 + c) * ld + row] = P[NB + r][c];
+      // the same tile by rows, for the backward substitution
+      const int rr = idx / NB, cc = idx % NB;
+      lrow[((size_t)bi * NB + rr) * npad + k0 + cc] = P[NB + rr][cc];
+    }
+    if (tid < NB && bi * NB + tid < n) b[bi * NB + tid] = bks[tid];
+    return;
+  }
+  const bool last = k + 1 == nbk;               // the only work-group of its launch
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx % NB, c = idx / NB;
+    inv[(size_t)k * NB * NB + idx] = P[NB + r][c];       // L_kk^{-T}, column-major
+    if (last) {
+      if (c <= r && k0 + r < n) A[(size_t)(k0 + c) * ld + k0 + r] = P[r][c];
+    } else {
+      dl[(size_t)k * NB * NB + idx] = P[r][c];           // L_kk, column-major
+    }
+    // tile (k - 1, k - 1) is read by no work-group of this launch: store
+    // the factor left there by the previous launch
+    if (k > 0 && c <= r) A[(size_t)(k0 - NB + c) * ld + k0 - NB + r] = dl[(size_t)(k - 1) * NB * NB + idx];
+  }
+  if (tid < bsz) {                             // y_k = L_kk^{-1} b_k
+    double v = 0.0;
+#pragma unroll 8
+    for (int s = 0; s < NB; ++s) v = fma(P[NB + s][tid], bks[s], v);
+    y[k0 + tid] = v;
+  }
+  if (tr) trace[8 * k + 4] = wall_clock64();
+}
+
+// One step of the backward substitution for row block bk (b0 = bk NB):
+// lv holds this thread's half column of L_{bk, c} (c = tid / 2 < b0, rows
+// b0 + 16 (tid & 1) + q), loaded one step ahead; Ms[bk % 3] holds
+// L_bk,bk^{-T} (column-major), parked one step ahead from mpark.
+template <bool WIDE>
+__device__ __forceinline__ void backward_block(const double* lrow, int npad, int n, int bk,
+                                               double* ys, double* xb, double (*Ms)[NB * NB],
+                                               const double (&lv)[16], double mpark, int tid) {
+  const int b0 = bk * NB, lane = tid & 63, wave = tid >> 6, hh = tid & 1;
+  if (wave == 0) {                              // x_b = L_bb^{-T} y_b
+    const int t = lane & 31, hs = lane >> 5;
+    const double* m = Ms[bk % 3];
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v = fma(m[(16 * hs + q) * NB + t], ys[b0 + 16 * hs + q], v);
+    v += __shfl_xor(v, 32);
+    if (hs == 0) {
+      xb[t] = v;
+      ys[b0 + t] = v;
+    }
+  }
+  if (bk > 0) Ms[(bk + 2) % 3][tid] = mpark;    // inverse of block bk - 1
+  lds_barrier();
+  for (int base = 0; base < (WIDE ? 2 * b0 : 1); base += NB * NB) {
+    const int idx = base + tid, c = idx >> 1;
+    double v = 0.0;
+    if (base == 0) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v = fma(lv[q], xb[16 * hh + q], v);
+    } else if (WIDE && idx < 2 * b0) {         // columns beyond the first 512
+      const double* rows = lrow + ((size_t)b0 + 16 * hh) * npad + c;
+#pragma nounroll
+      for (int q = 0; q < 16; ++q)
+        v = fma(ld_or0(rows, (size_t)q * npad, b0 + 16 * hh + q < n), xb[16 * hh + q], v);
+    }
+    v += __shfl_xor(v, 1);
+    if (hh == 0 && idx < 2 * b0) ys[c] -= v;
+  }
+  lds_barrier();
+}
+
+__device__ __forceinline__ void backward_load(const double* lrow, int npad, int n, int bk,
+                                              const double* inv, double (&lv)[16], double& mv,
+                                              int tid) {
+  if (bk < 0) return;
+  const int b0 = bk * NB, hh = tid & 1, c = tid >> 1;
+  const bool have = 2 * b0 > tid;
+  const double* rows = lrow + ((size_t)b0 + 16 * hh) * npad + c;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) lv[q] = ld_or0(rows, (size_t)q * npad, have && b0 + 16 * hh + q < n);
+  mv = inv[(size_t)bk * NB * NB + tid];
+}
+
+// Backward substitution L^T x = y (x over y) by work-group 0, by NB-row
+// blocks from the bottom (right-looking): x_b = L_bb^{-T} y_b, then
+// y_c -= L_bc^T x_b for every column c left of the block. The operands of
+// block b - 1 are loaded while block b is processed (two register sets).
+// Work-groups 8 h (h >= 1), dispatched to the same XCD as work-group 0, read
+// the rows of L ahead of it into that XCD's L2 and exit; the rest exit.
+// WIDE: n > 33 NB, some row blocks span more columns than one pass of the
+// work-group covers (the columns past the first pass are loaded in place).
+template <bool WIDE>
+__global__ void __launch_bounds__(NB * NB) k_chol_backward(const double* lrow, int n, double* y,
+                                                           const double* inv, const int* status,
+                                                           long long* trace) {
+  if (status[0] != 0) return;
+  const int tid = threadIdx.x;
+  const int nbk = (n + NB - 1) / NB, npad = nbk * NB;
+  if (blockIdx.x != 0) {
+    if (blockIdx.x % 8 != 0) return;
+    const int h = blockIdx.x / 8, nh = (gridDim.x - 1) / 8;
+    // helper h touches row blocks nbk - 1 - h, nbk - 1 - h - nh, ...
+    double acc = 0.0;
+    for (int bk = nbk - 1 - h; bk >= 0; bk -= nh) {
+      const int b0 = bk * NB;
+      for (int idx = tid; idx < NB * b0 / 8; idx += NB * NB) {   // one 64-byte piece each
+        const int r = idx / (b0 / 8), c8 = idx % (b0 / 8);
+        acc += lrow[((size_t)b0 + r) * npad + 8 * c8];
+      }
+    }
+    asm volatile("" :: "v"(acc));             // keeps the loads
+    return;
+  }
+  extern __shared__ double ys[];               // nbk * NB
+  __shared__ double xb[NB];
+  __shared__ double Ms[3][NB * NB];
+  const bool tr = trace != nullptr && tid == 0;
+  if (tr) trace[0] = wall_clock64();
+  double l0[16], l1[16], m0 = 0.0, m1 = 0.0;
+  backward_load(lrow, npad, n, nbk - 1, inv, l0, m0, tid);
+  backward_load(lrow, npad, n, nbk - 2, inv, l1, m1, tid);
+  for (int i = tid; i < nbk * NB; i += NB * NB) ys[i] = i < n ? y[i] : 0.0;
+  Ms[(nbk - 1) % 3][tid] = m0;
+  __syncthreads();
+  if (tr) trace[1] = wall_clock64();
+  int bk = nbk - 1;
+  for (; bk >= 1; bk -= 2) {
+    backward_block<WIDE>(lrow, npad, n, bk, ys, xb, Ms, l0, m1, tid);
+    backward_load(lrow, npad, n, bk - 2, inv, l0, m0, tid);
+    backward_block<WIDE>(lrow, npad, n, bk - 1, ys, xb, Ms, l1, m0, tid);
+    backward_load(lrow, npad, n, bk - 3, inv, l1, m1, tid);
+  }
+  if (bk == 0) backward_block<WIDE>(lrow, npad, n, 0, ys, xb, Ms, l0, 0.0, tid);
+  if (tr) trace[2] = wall_clock64();
+  for (int i = tid; i < n; i += NB * NB) y[i] = ys[i];
 }
 
 }  // namespace
@@ -973,6 +1284,12 @@ size_t condense_meta_bytes(const DevNet& d) {
 void prepare_lds_kernels(size_t bytes) {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor_wave),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
   const void* fns[] = {
       reinterpret_cast<const void*>(&k_condense<1, true, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<2, true, MODE_COLUMNS>),
@@ -1021,8 +1338,12 @@ hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double*
 
 hipError_t launch_refactor(const DevNet& d, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, d.status + 2, 2, 0);
-  hipLaunchKernelGGL(k_refactor, dim3(1), dim3(kRefThreads),
-                     (size_t)d.rf_lds_doubles * sizeof(double), st, d);
+  if (d.rw_ok)
+    hipLaunchKernelGGL(k_refactor_wave, dim3(1), dim3(kRwWaves * 64),
+                       (size_t)(d.rw_nnz_u + 1 + d.nx) * sizeof(double), st, d);
+  else
+    hipLaunchKernelGGL(k_refactor, dim3(1), dim3(kRefThreads),
+                       (size_t)d.rf_lds_doubles * sizeof(double), st, d);
   hipLaunchKernelGGL(k_transcribe, dim3(64), dim3(kBlock), 0, st, d);
   return hipGetLastError();
 }
@@ -1070,22 +1391,26 @@ hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st) {
 }
 
 hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
-                                 double* y, double* dinv, int* status, hipStream_t st) {
+                                 double* y, double* dinv, double* lrow, int* status,
+                                 hipStream_t st, long long* trace) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, status, 2, 0);
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int nblk = cdiv(n - k0, NB);
-    hipLaunchKernelGGL(k_potrf_panel, dim3(nblk), dim3(kPanelThreads), 0, st, K, ldk, n, k0,
-                       delta, b, y, status);
-    const int rest = n - (k0 + NB);
-    if (rest > 0) {
-      const int nt = cdiv(rest, 32);
-      hipLaunchKernelGGL(k_syrk, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, K, ldk, n, k0, status);
-    }
+  if (n <= 0) return hipGetLastError();
+  const int nbk = cdiv(n, NB);
+  double* dl = dinv + (size_t)nbk * NB * NB;
+  for (int k = 0; k < nbk; ++k) {
+    const int T = nbk - 1 - k;
+    const int grid = (nbk - k) + (k >= 1 ? T * (T + 1) / 2 : 0);
+    hipLaunchKernelGGL(k_chol_step, dim3(grid), dim3(256), 0, st, K, ldk, n, k, delta, b, y, dinv,
+                       dl, lrow, status, trace);
   }
-  hipLaunchKernelGGL(k_diag_inverse, dim3(cdiv(n, NB)), dim3(NB * NB), 0, st, (const double*)K,
-                     ldk, n, dinv, (const int*)status);
-  hipLaunchKernelGGL(k_trsv_lt, dim3(1), dim3(256), (size_t)n * sizeof(double), st,
-                     (const double*)K, ldk, n, y, (const double*)dinv, (const int*)status);
+  if (nbk <= 33)
+    hipLaunchKernelGGL(k_chol_backward<false>, dim3(64), dim3(NB * NB),
+                       (size_t)nbk * NB * sizeof(double), st, (const double*)lrow, n, y,
+                       (const double*)dinv, (const int*)status, trace ? trace + 8 * nbk : nullptr);
+  else
+    hipLaunchKernelGGL(k_chol_backward<true>, dim3(64), dim3(NB * NB),
+                       (size_t)nbk * NB * sizeof(double), st, (const double*)lrow, n, y,
+                       (const double*)dinv, (const int*)status, trace ? trace + 8 * nbk : nullptr);
   return hipGetLastError();
 }
 

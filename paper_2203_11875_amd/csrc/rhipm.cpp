@@ -38,7 +38,8 @@ struct rh_net {
   bool rhs_cols = false;     // the last condensation stored the right-hand-side column
   double* sig_s = nullptr;   // copy of Sigma_s from the last condensation
   double* bwork = nullptr;   // Cholesky right-hand-side work copy
-  double* cinv = nullptr;    // inverted 32 x 32 diagonal blocks of the Cholesky factor
+  double* cinv = nullptr;    // 32 x 32 diagonal blocks of the Cholesky factor: inverses, then factors
+  double* lrow = nullptr;    // the Cholesky factor by row blocks (backward substitution)
   int* status = nullptr;
   long long* trace = nullptr;
   size_t panel_cap = 0;
@@ -159,6 +160,7 @@ void fill_info(const rh::Symbolic& s, rh_info* info) {
   info->refactor_ops = s.refactor_ops;
   info->max_lu_row = s.max_row;
   info->max_row_ops = s.max_row_ops;
+  info->refactor_kernel = s.rw_ok ? 0 : 1;
 }
 
 void copy_maps(const rh::Symbolic& s, int32_t* x_kind, int32_t* x_bus, int32_t* u_kind,
@@ -247,6 +249,18 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(alloc(n, s.kell_col.size(), &d.kell_val));
   d.kell_n = int(s.kell_col.size());
   d.kb_n = int(s.kb_base.size());
+  d.rw_ok = s.rw_ok ? 1 : 0;
+  d.rw_nnz_u = s.rw_nnz_u;
+  d.rw_nlev = s.sl.nlev;
+  d.rw_wbeg = d.rw_levend = d.rw_rec = d.rw_lane = nullptr;
+  d.rw_ntask = 0;
+  if (s.rw_ok) {
+    d.rw_ntask = int(s.rw_rec.size()) / rh::kRwRec - 1;
+    RH_TRY(upload(n, s.rw_wbeg, &d.rw_wbeg));
+    RH_TRY(upload(n, s.rw_levend, &d.rw_levend));
+    RH_TRY(upload(n, s.rw_rec, &d.rw_rec));
+    RH_TRY(upload(n, s.rw_lane, &d.rw_lane));
+  }
   RH_TRY(upload(n, s.rf_lmeta, &d.rf_lmeta));
   d.rf_lds_doubles = s.rf_lds_doubles;
   RH_TRY(upload(n, s.k_cdiag, &d.k_cdiag));
@@ -287,7 +301,8 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   }
   RH_TRY(alloc(n, s.m, &n->sig_s));
   RH_TRY(alloc(n, s.nu, &n->bwork));
-  RH_TRY(alloc(n, size_t((s.nu + 31) / 32) * 32 * 32, &n->cinv));
+  RH_TRY(alloc(n, 2 * size_t((s.nu + 31) / 32) * 32 * 32, &n->cinv));
+  RH_TRY(alloc(n, size_t((s.nu + 31) / 32 * 32) * size_t((s.nu + 31) / 32 * 32), &n->lrow));
   RH_TRY(alloc(n, 8, &n->status));
   RH_TRY(alloc(n, 256, &n->trace));
   RH_HIP(hipMemset(n->trace, 0, 256 * sizeof(long long)));
@@ -508,13 +523,16 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   if (ldk < n->s.nu || !(delta_w >= 0.0)) return RH_ERR_ARG;
   if (!n->condensed) return RH_ERR_STATE;
   const auto& d = n->d;
+  // the backward substitution keeps the right-hand side in LDS
+  if (size_t((d.nu + 31) / 32) * 32 * sizeof(double) + 25 * 1024 > size_t(rh::max_lds_bytes()))
+    return RH_ERR_ARG;
   hipStream_t st = n->stream;
   RH_HIP(hipMemcpyAsync(n->bwork, rhs, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, st));
   {
     // L y = b is solved into p[0:nu], then L^T p_u = y in place
     PhaseScope ps(n, RH_PHASE_CHOLESKY);
-    RH_HIP(rh::launch_cholesky_solve(K, long(ldk), d.nu, delta_w, n->bwork, p, n->cinv, n->status,
-                                     st));
+    RH_HIP(rh::launch_cholesky_solve(K, long(ldk), d.nu, delta_w, n->bwork, p, n->cinv, n->lrow,
+                                     n->status, st));
   }
   {
     PhaseScope ps(n, RH_PHASE_RECOVER);

@@ -66,10 +66,12 @@ def test_eval_residual(name):
 
 @pytest.mark.parametrize("name", list(NETS))
 @pytest.mark.parametrize("seed", [0, 1])
-def test_condense_matches_oracle(name, seed):
+@pytest.mark.parametrize("refactor", [0, 1], ids=["wave", "staged"])
+def test_condense_matches_oracle(name, seed, refactor):
     net = NETS[name]()
     M = Model(net)
-    G = _net_api().Net(net)
+    G = _net_api().Net(net, refactor=refactor)
+    assert G.info["refactor_kernel"] == refactor
     x, u, lam, y, sx, su, ss = random_point(M, seed)
     r = residual_vector(M, seed)
     K, rhs = G.condense_reduced_hessian(*map(_t, (x, u, lam, y, sx, su, ss)), r=_t(r))

@@ -52,12 +52,15 @@ def test_levels_valid(net):
     assert S.info["levels_lower"] >= 1 and S.info["nnz_lu"] >= S.info["nnz_gx"]
 
 
+@pytest.mark.parametrize("refactor", [0, 1], ids=["wave", "staged"])
 @pytest.mark.parametrize("net", NETS, ids=lambda n: n.name)
-def test_patterns_cover_oracle_and_host_refactorisation_solves(net):
+def test_patterns_cover_oracle_and_host_refactorisation_solves(net, refactor):
     """The G_x pattern holds every structural nonzero of the oracle's G_x, the
     pivot order is a permutation, and refactorising with the device schedule
+    (wave-resident tasks emulated lane by lane, or the level-staged rows)
     then sweeping the level sets solves G_x z = b and G_x^T z = b."""
-    S = _lib().Symbolic(net)
+    S = _lib().Symbolic(net, refactor=refactor)
+    assert S.info["refactor_kernel"] == refactor
     M = Model(net)
     rng = np.random.default_rng(0)
     x, u = M.join(rng.normal(0, .1, net.nb), rng.uniform(.95, 1.05, net.nb),
