@@ -457,11 +457,8 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
   // its row; at step q the multiplier of the q-th lower entry is broadcast
   // from lane q of the segment and every lane applies a_p -= l_q u_(k_q, col p)
   // with u read from LDS at its packed 16-bit index (the zero slot where the
-  // row of U has no such entry). Record: {lane-data offset, steps, wide,
-  // 0, rp0[4], len[4]}; lane fields: pivot-row index of a lower entry
-  // (reciprocal pivot to read) or -1, LDS slot of an upper entry or -1, row
-  // index at the diagonal or -1, position of a lower entry or -1; then the
-  // packed indices, two steps per int.
+  // row of U has no such entry). The record and the lane data are described
+  // with kRwRec.
   {
     s.rw_ok = false;
     s.rw_wbeg.clear();
@@ -471,7 +468,9 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
     std::vector<int> ustart(nx + 1, 0);
     for (int i = 0; i < nx; ++i) ustart[i + 1] = ustart[i] + (s.lu_ptr[i + 1] - s.lu_diag[i] - 1);
     s.rw_nnz_u = ustart[nx];
-    const size_t lds = (size_t(s.rw_nnz_u) + 1 + nx) * sizeof(double);
+    s.rw_ustart.assign(ustart.begin(), ustart.end() - 1);
+    const size_t lds = (size_t(s.rw_nnz_u) + 1 + nx) * sizeof(double) +
+                       size_t(kRwWaves) * s.sl.nlev * sizeof(int);
     bool ok = s.max_row <= 64 && s.rw_nnz_u < 65535 && lds <= size_t(kRefLdsBudget) &&
               !(opts && opts->refactor == 1);
     if (ok) {
@@ -481,7 +480,9 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
       std::vector<Task> tasks;
       const int nlev = s.sl.nlev;
       for (int w = 0; w < kRwWaves; ++w) wave_tasks[w].assign(nlev, {});
-      for (int l = 0; l < nlev; ++l) {
+      // level 0 (rows without lower entries: U row and pivot are the values
+      // themselves) is copied by all threads at kernel start, not in tasks
+      for (int l = 1; l < nlev; ++l) {
         std::vector<int> shortr, longr;
         for (int q = s.sl.lev_ptr[l]; q < s.sl.lev_ptr[l + 1]; ++q) {
           const int i = s.sl.rows[q];
@@ -523,34 +524,23 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
             const Task& t = tasks[id];
             const int off = int(s.rw_lane.size());
             const int npk = (t.nsteps + 1) / 2;
-            std::vector<int> blk(size_t(kRwFields + npk) * 64, -1);
-            for (int k = 0; k < npk; ++k)
-              for (int ln = 0; ln < 64; ++ln)
-                blk[size_t(kRwFields + k) * 64 + ln] = int(unsigned(zslot) | (unsigned(zslot) << 16));
-            int rec[kRwRec] = {off, t.nsteps, t.wide, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            std::vector<int> blk(size_t(npk) * 64, int(unsigned(zslot) | (unsigned(zslot) << 16)));
+            int rec[kRwRec] = {off, t.nsteps, t.wide, 0};
             for (size_t g = 0; g < t.rows.size(); ++g) {
               const int i = t.rows[g], rp0 = s.lu_ptr[i], len = s.lu_ptr[i + 1] - rp0;
               const int nl = s.lu_diag[i] - rp0;
               rec[4 + g] = rp0;
               rec[8 + g] = len;
+              rec[12 + g] = nl;
+              rec[16 + g] = ustart[i];
+              rec[20 + g] = i;
               const int lane0 = t.wide ? 0 : 16 * int(g);
-              for (int p = 0; p < len; ++p) {
-                const int ln = lane0 + p;
-                if (p < nl) {
-                  blk[0 * 64 + ln] = s.lu_col[rp0 + p];
-                  blk[3 * 64 + ln] = p;
-                } else if (p == nl) {
-                  blk[2 * 64 + ln] = i;
-                } else {
-                  blk[1 * 64 + ln] = ustart[i] + (p - nl - 1);
-                }
-              }
               for (int q = 0; q < nl; ++q) {
                 const int kr = s.lu_col[rp0 + q];
                 for (int o = s.rf_kptr[rp0 + q]; o < s.rf_kptr[rp0 + q + 1]; ++o) {
                   const int p = s.rf_op_dst[o] - rp0;
                   const int u = ustart[kr] + (s.rf_op_src[o] - s.lu_diag[kr] - 1);
-                  int& w2 = blk[size_t(kRwFields + q / 2) * 64 + lane0 + p];
+                  int& w2 = blk[size_t(q / 2) * 64 + lane0 + p];
                   unsigned wv = unsigned(w2);
                   if (q & 1) wv = (wv & 0xffffu) | (unsigned(u) << 16);
                   else wv = (wv & 0xffff0000u) | unsigned(u);
@@ -566,12 +556,13 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
         }
         s.rw_wbeg[w + 1] = s.rw_wbeg[w] + cnt;
       }
-      // a dummy record (loaded, never run, by waves past their last task) and
-      // padding: the kernel loads kRwFields + kRwPacked ints per lane per task
+      // a dummy record (loaded, never run, by waves past their last task)
+      // pointing at one block of 64 ints that also stands in for the packed
+      // steps a task does not have
       const int pad = int(s.rw_lane.size());
-      int dummy[kRwRec] = {pad, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      int dummy[kRwRec] = {pad, 0, 0, 0};
       s.rw_rec.insert(s.rw_rec.end(), dummy, dummy + kRwRec);
-      s.rw_lane.insert(s.rw_lane.end(), size_t(kRwFields + kRwPacked) * 64, -1);
+      s.rw_lane.insert(s.rw_lane.end(), 64, int(unsigned(zslot) | (unsigned(zslot) << 16)));
       s.rw_ok = true;
     }
   }
@@ -840,6 +831,13 @@ rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, doub
     // the wave-resident schedule, lane by lane as the device runs it
     std::vector<double> ulds(size_t(s.rw_nnz_u) + 1, 0.0), rinv(nx, 0.0);
     const int nlev = s.sl.nlev;
+    for (int q = 0; q < s.sl.lev_ptr[1]; ++q) {            // level 0
+      const int i = s.sl.rows[q];
+      for (int p = s.lu_diag[i] + 1; p < s.lu_ptr[i + 1]; ++p)
+        ulds[s.rw_ustart[i] + (p - s.lu_diag[i] - 1)] = lu[p];
+      if (lu[s.lu_diag[i]] == 0.0) return RH_SMALL_PIVOT;
+      rinv[i] = 1.0 / lu[s.lu_diag[i]];
+    }
     for (int lv = 0; lv < nlev; ++lv)
       for (int w = 0; w < kRwWaves; ++w) {
         const int k0 = lv ? s.rw_levend[size_t(w) * nlev + lv - 1] : 0;
@@ -851,13 +849,13 @@ rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, doub
           int ipos[64], pos[64], udst[64], drow[64];
           for (int ln = 0; ln < 64; ++ln) {
             const int seg = wide ? 0 : ln >> 4, p = wide ? ln : ln & 15;
-            ipos[ln] = p < R[8 + seg] ? R[4 + seg] + p : -1;
+            const int rp0 = R[4 + seg], len = R[8 + seg], nl = R[12 + seg];
+            ipos[ln] = p < len ? rp0 + p : -1;
             acc[ln] = ipos[ln] >= 0 ? lu[ipos[ln]] : 0.0;
-            const int* b = &s.rw_lane[size_t(R[0]) + ln];
-            r[ln] = b[0] >= 0 ? rinv[b[0]] : 0.0;
-            udst[ln] = b[64];
-            drow[ln] = b[128];
-            pos[ln] = b[192];
+            r[ln] = p < nl ? rinv[s.lu_col[rp0 + p]] : 0.0;
+            udst[ln] = p > nl && p < len ? R[16 + seg] + (p - nl - 1) : -1;
+            drow[ln] = p == nl && p < len ? R[20 + seg] : -1;
+            pos[ln] = p < nl ? p : -1;
             amax[ln] = std::fabs(acc[ln]);
           }
           for (int q = 0; q < nsteps; ++q) {
@@ -865,7 +863,7 @@ rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, doub
             for (int ln = 0; ln < 64; ++ln) t[ln] = acc[ln] * r[ln];
             for (int ln = 0; ln < 64; ++ln) {
               const double l = wide ? t[q] : t[16 * (ln >> 4) + q];
-              const unsigned pk = unsigned(s.rw_lane[size_t(R[0]) + size_t(kRwFields + q / 2) * 64 + ln]);
+              const unsigned pk = unsigned(s.rw_lane[size_t(R[0]) + size_t(q / 2) * 64 + ln]);
               const int ui = std::min(int((pk >> (16 * (q & 1))) & 0xffffu), s.rw_nnz_u);
               if (pos[ln] == q) acc[ln] = l;
               acc[ln] = std::fma(-l, ulds[ui], acc[ln]);

@@ -19,11 +19,13 @@ constexpr int kMaxRowBlocks = 16;   // LDS-resident panels: nu + nx <= 16 * 256
 constexpr int kRefLdsBudget = 155 * 1024;   // bytes of LDS the refactorisation may use
 // Wave-resident refactorisation: 8 waves; a task is one row of at most 64
 // LU entries (one lane per entry) or up to four rows of at most 16 entries
-// (one 16-lane row each). Per task: a record of kRwRec ints and, per lane,
-// kRwFields ints followed by the packed 16-bit U indices of its steps.
+// (one 16-lane row each). Per task: a record of kRwRec ints
+// {lane-data offset, steps, wide, 0, rp0[4], len[4], nlow[4], ustart[4],
+// row[4]} (per row of the task: first LU position, entries, lower entries,
+// first LDS slot of its U entries, row index) and, per lane, the packed
+// 16-bit U indices of its steps (two steps per int, ceil(steps / 2) ints).
 constexpr int kRwWaves = 8;
-constexpr int kRwRec = 12;
-constexpr int kRwFields = 4;
+constexpr int kRwRec = 24;
 constexpr int kRwPacked = 32;
 
 // Per-line record written by the line-evaluation kernel (doubles).
@@ -140,6 +142,7 @@ struct Symbolic {
   std::vector<int> rw_levend;              // kRwWaves * nlev: end of each level per wave
   std::vector<int> rw_rec;                 // kRwRec ints per task (wave-major order)
   std::vector<int> rw_lane;                // per-lane task data (see analysis.cpp)
+  std::vector<int> rw_ustart;              // nx: first LDS slot of each row's U entries
   std::vector<double> k_cdiag;             // constant diagonal (2 c2 base^2 on Pg)
   std::vector<int> sig_map;                // w -> index into [Sigma_u ; Sigma_x(natural)]
   // evaluation gather: dst = [luval | gu | a | g(natural) | h]

@@ -63,8 +63,8 @@ struct DevNet {
   double* kell_val;
   int kell_n, kb_n;
   // wave-resident refactorisation (rw_ok): task records, per-lane data
-  int rw_ok, rw_nnz_u, rw_nlev, rw_ntask;
-  const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane;
+  int rw_ok, rw_nnz_u, rw_nlev, rw_ntask, rw_lane_pad;
+  const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane, *rw_ustart;
   const int* rf_lmeta;    // 6 ints per refactorisation level
   int rf_lds_doubles;
   const double* k_cdiag;

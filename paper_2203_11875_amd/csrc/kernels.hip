@@ -346,35 +346,48 @@ struct RwSet {
   int pk[kRwPacked];
 };
 
+// Loads a task record (uniform). The values are only made scalar where they
+// are used, a task later: waiting for them here would also wait for the
+// loads of the next task issued just before.
 __device__ __forceinline__ void rw_rec_load(const DevNet& d, int wave, int k, int cnt, RwRec& R) {
   const int gi = k < cnt ? d.rw_wbeg[wave] + k : d.rw_ntask;   // past the end: the dummy record
   const int* r = d.rw_rec + (size_t)gi * kRwRec;
 #pragma unroll
-  for (int f = 0; f < kRwRec; ++f) R.v[f] = __builtin_amdgcn_readfirstlane(r[f]);
+  for (int f = 0; f < kRwRec; ++f) R.v[f] = r[f];
+}
+
+// Per-segment value of a record field (4 consecutive ints), chosen by selects
+// of register values (readfirstlane keeps them from being folded back into
+// one indexed load, which would put the record in scratch memory).
+__device__ __forceinline__ int rw_seg(const RwRec& R, int f, int seg) {
+  const int v0 = __builtin_amdgcn_readfirstlane(R.v[f]);
+  const int v1 = __builtin_amdgcn_readfirstlane(R.v[f + 1]);
+  const int v2 = __builtin_amdgcn_readfirstlane(R.v[f + 2]);
+  const int v3 = __builtin_amdgcn_readfirstlane(R.v[f + 3]);
+  return seg == 0 ? v0 : seg == 1 ? v1 : seg == 2 ? v2 : v3;
 }
 
 __device__ __forceinline__ void rw_set_load(const DevNet& d, const RwRec& R, RwSet& X, int lane) {
-  X.nsteps = R.v[1];
-  X.wide = R.v[2];
+  X.nsteps = __builtin_amdgcn_readfirstlane(R.v[1]);
+  X.wide = __builtin_amdgcn_readfirstlane(R.v[2]);
   int seg = X.wide ? 0 : lane >> 4;
   const int p = X.wide ? lane : lane & 15;
   asm volatile("" : "+v"(seg));                // keep the selects (no indexed table)
-  int rp0 = R.v[4], len = R.v[8];
-  rp0 = seg == 1 ? R.v[5] : rp0;
-  len = seg == 1 ? R.v[9] : len;
-  rp0 = seg == 2 ? R.v[6] : rp0;
-  len = seg == 2 ? R.v[10] : len;
-  rp0 = seg == 3 ? R.v[7] : rp0;
-  len = seg == 3 ? R.v[11] : len;
-  X.ipos = p < len ? rp0 + p : -1;
-  X.init = ld_or0(d.dst + d.d_lu, X.ipos, X.ipos >= 0);
-  const int* b = d.rw_lane + R.v[0] + lane;
-  X.rcol = b[0];
-  X.udst = b[64];
-  X.drow = b[128];
-  X.pos = b[192];
+  const int rp0 = rw_seg(R, 4, seg), len = rw_seg(R, 8, seg), nl = rw_seg(R, 12, seg);
+  const bool active = p < len, lower = p < nl;
+  X.ipos = active ? rp0 + p : -1;
+  X.init = ld_or0(d.dst + d.d_lu, X.ipos, active);
+  X.rcol = d.lu_col[lower ? rp0 + p : 0];      // used only where lower
+  X.pos = lower ? p : -1;
+  X.udst = active && p > nl ? rw_seg(R, 16, seg) + (p - nl - 1) : -1;
+  X.drow = active && p == nl ? rw_seg(R, 20, seg) : -1;
+  // packed steps: rows past the task's own read the 64-int block at the end
 #pragma unroll
-  for (int k = 0; k < kRwPacked; ++k) X.pk[k] = b[(kRwFields + k) * 64];
+  for (int k = 0; k < kRwPacked; ++k) {
+    const int o = __builtin_amdgcn_readfirstlane(2 * k < X.nsteps ? R.v[0] + k * 64
+                                                                   : d.rw_lane_pad);
+    X.pk[k] = d.rw_lane[o + lane];
+  }
 }
 
 __device__ __forceinline__ double rw_u(const double* ulds, int pk, int half, int zslot) {
@@ -404,7 +417,7 @@ __device__ __forceinline__ void rw_run(const DevNet& d, const RwSet& X, double* 
   const int nsteps = __builtin_amdgcn_readfirstlane(X.nsteps);
   const int wide = __builtin_amdgcn_readfirstlane(X.wide);
   double acc = X.init;
-  const double r = X.rcol >= 0 ? rinv[X.rcol] : 0.0;
+  const double r = X.pos >= 0 ? rinv[X.rcol] : 0.0;
   double amax = fabs(acc);
   if (wide) {
 #pragma unroll
@@ -445,23 +458,67 @@ __device__ __forceinline__ void rw_run(const DevNet& d, const RwSet& X, double* 
   }
 }
 
+// Work-group 0 factors. Work-groups 8 h (h >= 1), dispatched to the same XCD
+// as work-group 0, read the task tables and the values into that XCD's L2
+// ahead of it and exit; the others exit at once.
 __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
+  if (blockIdx.x != 0) {
+    if (blockIdx.x % 8 != 0) return;
+    const int h = blockIdx.x / 8 - 1, nh = gridDim.x / 8 - 1;
+    const int nrec = (d.rw_ntask + 1) * kRwRec, nlane = d.rw_lane_pad + 64;
+    int iacc = 0;
+    double acc = 0.0;
+    // 16-int (64-byte) pieces, interleaved over the helpers, in table order
+    for (int t = (h * kRwWaves * 64 + threadIdx.x) * 16; t < nrec; t += nh * kRwWaves * 64 * 16)
+      iacc += d.rw_rec[t];
+    for (int t = (h * kRwWaves * 64 + threadIdx.x) * 16; t < nlane; t += nh * kRwWaves * 64 * 16)
+      iacc += d.rw_lane[t];
+    for (int t = (h * kRwWaves * 64 + threadIdx.x) * 8; t < d.nnz_lu; t += nh * kRwWaves * 64 * 8)
+      acc += d.dst[d.d_lu + t];
+    asm volatile("" :: "v"(acc), "v"(iacc));   // keeps the loads
+    return;
+  }
   extern __shared__ double rw_lds[];
   double* ulds = rw_lds;                       // U entries, then the zero slot
   double* rinv = rw_lds + d.rw_nnz_u + 1;      // reciprocal pivots by row
+  int* levend = reinterpret_cast<int*>(rinv + d.nx);   // per wave: end of each level
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // optional profile: wall clock at the start, after level 0 and after
+  // every later level
+  long long* tr = d.trace && threadIdx.x == 0 ? d.trace + 127 : nullptr;
+  if (tr) tr[0] = wall_clock64();
   const int cnt = d.rw_wbeg[wave + 1] - d.rw_wbeg[wave];
-  const int* levend = d.rw_levend + (size_t)wave * d.rw_nlev;
-  if (threadIdx.x == 0) ulds[d.rw_nnz_u] = 0.0;
   RwRec r0, r1;
   RwSet A, B;
   rw_rec_load(d, wave, 0, cnt, r0);
   rw_rec_load(d, wave, 1, cnt, r1);
   rw_set_load(d, r0, A, lane);
+  if (threadIdx.x == 0) ulds[d.rw_nnz_u] = 0.0;
+  for (int t = threadIdx.x; t < kRwWaves * d.rw_nlev; t += kRwWaves * 64) levend[t] = d.rw_levend[t];
+  // level 0: rows without lower entries keep their values
+  const double* lu = d.dst + d.d_lu;
+  for (int q = threadIdx.x; q < d.rf_lev_ptr[1]; q += kRwWaves * 64) {
+    const int i = d.rf_rows[q], rp0 = d.lu_ptr[i], rd = d.lu_diag[i], r1e = d.lu_ptr[i + 1];
+    const int u0 = d.rw_ustart[i];
+    double amax = 0.0;
+    for (int p = rp0; p < r1e; ++p) {
+      const double v = lu[p];
+      amax = fmax(amax, fabs(v));
+      if (p > rd) ulds[u0 + (p - rd - 1)] = v;
+    }
+    const double piv = lu[rd];
+    rinv[i] = 1.0 / piv;
+    if (!(fabs(piv) > 1e-14 * amax)) {
+      d.status[2] = 1;
+      d.status[3] = i;
+    }
+  }
   lds_barrier();
+  const int* lend = levend + wave * d.rw_nlev;
+  if (tr) tr[1] = wall_clock64();
   int k = 0;
-  for (int lev = 0; lev < d.rw_nlev; ++lev) {
-    const int end = levend[lev];
+  for (int lev = 1; lev < d.rw_nlev; ++lev) {
+    const int end = lend[lev];
     while (k < end) {
       if ((k & 1) == 0) {
         rw_set_load(d, r1, B, lane);
@@ -475,6 +532,7 @@ __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
       ++k;
     }
     lds_barrier();
+    if (tr && lev < 128) tr[1 + lev] = wall_clock64();
   }
 }
 
@@ -1339,8 +1397,9 @@ hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double*
 hipError_t launch_refactor(const DevNet& d, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, d.status + 2, 2, 0);
   if (d.rw_ok)
-    hipLaunchKernelGGL(k_refactor_wave, dim3(1), dim3(kRwWaves * 64),
-                       (size_t)(d.rw_nnz_u + 1 + d.nx) * sizeof(double), st, d);
+    hipLaunchKernelGGL(k_refactor_wave, dim3(32), dim3(kRwWaves * 64),
+                       (size_t)(d.rw_nnz_u + 1 + d.nx) * sizeof(double) +
+                           (size_t)kRwWaves * d.rw_nlev * sizeof(int), st, d);
   else
     hipLaunchKernelGGL(k_refactor, dim3(1), dim3(kRefThreads),
                        (size_t)d.rf_lds_doubles * sizeof(double), st, d);

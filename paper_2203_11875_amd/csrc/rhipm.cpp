@@ -252,14 +252,17 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   d.rw_ok = s.rw_ok ? 1 : 0;
   d.rw_nnz_u = s.rw_nnz_u;
   d.rw_nlev = s.sl.nlev;
-  d.rw_wbeg = d.rw_levend = d.rw_rec = d.rw_lane = nullptr;
+  d.rw_wbeg = d.rw_levend = d.rw_rec = d.rw_lane = d.rw_ustart = nullptr;
   d.rw_ntask = 0;
+  d.rw_lane_pad = 0;
   if (s.rw_ok) {
     d.rw_ntask = int(s.rw_rec.size()) / rh::kRwRec - 1;
+    d.rw_lane_pad = int(s.rw_lane.size()) - 64;
     RH_TRY(upload(n, s.rw_wbeg, &d.rw_wbeg));
     RH_TRY(upload(n, s.rw_levend, &d.rw_levend));
     RH_TRY(upload(n, s.rw_rec, &d.rw_rec));
     RH_TRY(upload(n, s.rw_lane, &d.rw_lane));
+    RH_TRY(upload(n, s.rw_ustart, &d.rw_ustart));
   }
   RH_TRY(upload(n, s.rf_lmeta, &d.rf_lmeta));
   d.rf_lds_doubles = s.rf_lds_doubles;
