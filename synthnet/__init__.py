@@ -12,8 +12,9 @@ available, so each instance is a seeded stand-in:
 * topology: a random recursive spanning tree over a random bus permutation, plus
   *local* chords obtained from 2-4 step random walks (real grids are nearly
   planar; uniformly random chords would give a sparse LU with ~10x more fill);
-* line data r ~ U[0.005, 0.05], x ~ U[0.02, 0.3], total charging b ~ U[0, 0.2]
-  (per unit on a 100 MVA base), thermal limit rate ~ U[1, 5] p.u. or none;
+* line data x ~ U[0.005, 0.05], r = x U[0.1, 0.3], total charging b ~ U[0, 0.1]
+  (per unit on a 100 MVA base, transmission-like r/x), thermal limit
+  rate ~ U[2, 8] p.u. or none;
 * one generator per generator bus, the first one sits on the reference bus;
   quadratic cost c2 ~ U[0.01, 0.1] $/MW^2, c1 ~ U[10, 40] $/MW, c0 = 0;
 * loads Pd ~ U[lo, hi] p.u. on a random fraction of the buses, Qd = 0.3 Pd;
@@ -104,7 +105,7 @@ def _tree_plus_local_chords(rng: np.random.Generator, nb: int, nl: int):
 
 
 def make_network(nb: int, nl: int, ng: int, *, seed: int, load_frac: float,
-                 pd_range=(0.1, 2.0), rated: bool = True, name: str = "",
+                 pd_range=(0.1, 1.0), rated: bool = True, name: str = "",
                  ring: bool = False) -> Network:
     """Seeded synthetic network (see module docstring for the recipe)."""
     if ng < 1 or ng > nb:
@@ -117,10 +118,10 @@ def make_network(nb: int, nl: int, ng: int, *, seed: int, load_frac: float,
         t = ((np.arange(nb) + 1) % nb).astype(np.int32)
     else:
         f, t = _tree_plus_local_chords(rng, nb, nl)
-    r = rng.uniform(0.005, 0.05, nl)
-    x = rng.uniform(0.02, 0.3, nl)
-    b = rng.uniform(0.0, 0.2, nl)
-    rate = rng.uniform(1.0, 5.0, nl) if rated else np.zeros(nl)
+    x = rng.uniform(0.005, 0.05, nl)
+    r = x * rng.uniform(0.1, 0.3, nl)
+    b = rng.uniform(0.0, 0.1, nl)
+    rate = rng.uniform(2.0, 8.0, nl) if rated else np.zeros(nl)
 
     gen_bus = rng.choice(nb, size=ng, replace=False).astype(np.int32)
     bus_type = np.full(nb, BUS_PQ, dtype=np.int32)
