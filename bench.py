@@ -6,7 +6,9 @@ One step = one pass of the whole hot path on one synthetic iterate of the
 columns) with the condensed right-hand side, dense Cholesky + solve for p_u,
 and the recovery of (p_x, p_s, p_lambda, p_y) -- what one iteration of the
 linearize-then-reduce IPM spends on linear algebra (Algorithm 1). The value is
-condensations per second with every input resident in HBM.
+condensations per second with every input resident in HBM. The "ipm" entry
+reports the second half of the metric: IPM iterations per second of the full
+method (rh_ipm_step) solving the same network from the flat start.
 
 Prints ONE JSON line (rank 0). Runs on one GPU only.
 """
@@ -89,6 +91,31 @@ def measured_traffic():
     return float(m_b.group(1))
 
 
+def ipm_run(api, net, torch, max_iter):
+    """IPM iterations per second: Algorithm 1 (rh_ipm_step) from the flat
+    start to a scaled KKT error of 1e-6, every iteration timed (evaluation,
+    condensation, Cholesky with inertia correction, recovery, filter line
+    search)."""
+    G = api.Net(net)
+    ipm = api.Ipm(G, tol=1e-6, max_iter=max_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, code, info = 0, 0, {}
+    while iters <= max_iter:
+        code, info = ipm.step()
+        if code != 0 or info["converged"]:
+            break
+        iters += 1
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ipm.close()
+    G.close()
+    return {"iters_per_s": iters / el if iters else 0.0, "iterations": iters,
+            "ms_per_iter": 1e3 * el / max(1, iters), "converged": bool(info.get("converged")),
+            "status": int(code), "objective": info.get("obj"), "kkt_error": info.get("err"),
+            "tol": 1e-6, "start": "flat (theta 0, Vm 1, Pg mid-range)"}
+
+
 def cpu_baseline(net, args_np, seconds):
     """The oracle's full step (dense LU of G_x, explicit K_cond, RHS, Cholesky,
     recovery) on the host, repeated for a bounded time."""
@@ -132,6 +159,8 @@ def main():
     ap.add_argument("--lds", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ipm", action="store_true")
+    ap.add_argument("--ipm-iters", type=int, default=150)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 512 MiB first (a plain copy kernel of known "
                          "size that scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -219,9 +248,11 @@ def main():
                      "kernel": "k_condense", "kernel_avg_us": kern_s * 1e6,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "bytes_per_column": per_col, "columns_per_launch": ncols},
-        "phases_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in phases.items()},
+        "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
         "paper_context": PAPER_CONTEXT,
     }
+    if not args.no_ipm:
+        line["ipm"] = ipm_run(api, net, torch, args.ipm_iters)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args_np, args.cpu_seconds)
     print(json.dumps(line), flush=True)

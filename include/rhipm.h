@@ -229,6 +229,80 @@ rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
  * synchronises the stream. */
 rh_status rh_profile_kernel_trace(rh_net* net, int64_t* ticks);
 
+/* Multiplies the objective (every generator cost coefficient) by scale > 0
+ * in every later evaluation on this handle, until set again; 1 restores the
+ * network's own costs. The interior-point driver sets it (objective scaling
+ * at the initial point) and resets it to 1 when destroyed. Synchronises the
+ * stream. RH_ERR_ARG for scale <= 0 or not finite. */
+rh_status rh_set_objective_scale(rh_net* net, double scale);
+
+/* ---------------------------------------------------------------------------
+ * Interior-point method: Algorithm 1 ("LinRed"), each iteration evaluating
+ * the derivatives, condensing the KKT system (rh_condense_reduced_hessian's
+ * path), solving it with inertia correction (Section 4.3: K_cond + delta_w I
+ * must be positive definite; delta_w grows until it is) and recovering the
+ * step, then moving along it with a filter line search. The paper leaves the
+ * line search, the barrier update and the initial point to the underlying
+ * solver; this one follows the filter line-search method of Waechter and
+ * Biegler (2006) without second-order correction or restoration phase (a
+ * failed line search returns RH_NOT_CONVERGED), with a monotone barrier
+ * update mu <- max(tol / 10, min(0.2 mu, mu^1.5)) once the scaled KKT error
+ * of the barrier problem is below 10 mu. Bounds: Vm in [vmin, vmax], Pg in
+ * [pmin, pmax], theta free; h (Pg_ref, Qg, |S_from|^2, |S_to|^2) in
+ * [(pmin_ref, qmin, -inf, -inf), (pmax_ref, qmax, rate^2, rate^2)] through the
+ * slack s = -h. Initial point: the caller's (x0, u0) or, if both are NULL,
+ * theta = 0, Vm = 1, Pg mid-range; pushed inside its bounds; s = -h pushed
+ * inside its bounds; lambda = y = 0; bound multipliers 1.
+ * ------------------------------------------------------------------------- */
+typedef struct rh_ipm rh_ipm;
+
+typedef struct {
+  double tol;            /* stop when the scaled KKT error E_0 <= tol (default 1e-6) */
+  int32_t max_iter;      /* default 200                                              */
+  int32_t reserved0;
+  double mu_init;        /* default 0.1                                              */
+  double obj_scale;      /* > 0: objective scale; 0: min(1, 100 / max|grad f(w0)|)   */
+  int64_t reserved[4];
+} rh_ipm_options;
+
+typedef struct {
+  int64_t iter;          /* iterations taken so far                                  */
+  double obj;            /* objective f (unscaled) at the current point              */
+  double inf_pr;         /* max(|g|, |h + s|) at the current point                   */
+  double err;            /* scaled KKT error E_0 at the start of this call           */
+  double mu;             /* barrier parameter used by the step                       */
+  double alpha_pr;       /* primal step length                                       */
+  double alpha_du;       /* bound-multiplier step length                             */
+  double delta_w;        /* inertia-correction shift used (0 if none)                */
+  int64_t ls_trials;     /* line-search trial points evaluated                       */
+  double obj_scale;      /* objective scale in use                                   */
+  int32_t converged;     /* 1: E_0 <= tol at the start of this call (no step taken)   */
+  int32_t reserved;
+} rh_ipm_info;
+
+/* Fills the defaults. */
+rh_status rh_ipm_default_options(rh_ipm_options* opts);
+/* Creates the solver on a network handle (which it then drives; the handle's
+ * other calls must not be interleaved with the solver's). opts may be NULL
+ * (defaults). x0 (nx), u0 (nu): device initial point, both or neither.
+ * Allocates its device vectors and two nu x nu matrices. Errors: RH_ERR_ARG,
+ * RH_ERR_OOM, RH_ERR_HIP. */
+rh_status rh_ipm_create(rh_net* net, const rh_ipm_options* opts, const double* x0,
+                        const double* u0, rh_ipm** out);
+/* One iteration. If the point already satisfies E_0 <= tol, takes no step and
+ * sets info->converged. Returns RH_NOT_CONVERGED when the line search fails,
+ * the inertia correction exceeds 1e40 or max_iter iterations were taken;
+ * RH_SMALL_PIVOT is not fatal (the step is taken). info (host) may be NULL.
+ * Synchronises the stream a few times per iteration. */
+rh_status rh_ipm_step(rh_ipm* ipm, rh_ipm_info* info);
+/* Iterates until converged (RH_OK) or a step fails (its code). */
+rh_status rh_ipm_solve(rh_ipm* ipm, rh_ipm_info* info);
+/* Device copies of the current point (any pointer may be NULL). */
+rh_status rh_ipm_get_state(const rh_ipm* ipm, double* x, double* u, double* s, double* lam,
+                           double* y);
+/* Frees the solver and restores the network's objective scale to 1. */
+void rh_ipm_destroy(rh_ipm* ipm);
+
 #ifdef __cplusplus
 }
 #endif

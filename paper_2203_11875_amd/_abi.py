@@ -40,6 +40,19 @@ class rh_info(C.Structure):
         "lds_panel", "max_row_ops", "refactor_kernel")]
 
 
+class rh_ipm_options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("reserved0", C.c_int32),
+                ("mu_init", C.c_double), ("obj_scale", C.c_double),
+                ("reserved", C.c_int64 * 4)]
+
+
+class rh_ipm_info(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("obj", C.c_double), ("inf_pr", C.c_double),
+                ("err", C.c_double), ("mu", C.c_double), ("alpha_pr", C.c_double),
+                ("alpha_du", C.c_double), ("delta_w", C.c_double), ("ls_trials", C.c_int64),
+                ("obj_scale", C.c_double), ("converged", C.c_int32), ("reserved", C.c_int32)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/rhipm.h
 SIGNATURES = {
     "rh_status_str": (C.c_char_p, [C.c_int]),
@@ -66,6 +79,13 @@ SIGNATURES = {
     "rh_profile_enable": (C.c_int, [vp, C.c_int32]),
     "rh_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "rh_profile_kernel_trace": (C.c_int, [vp, C.POINTER(C.c_int64)]),
+    "rh_set_objective_scale": (C.c_int, [vp, C.c_double]),
+    "rh_ipm_default_options": (C.c_int, [C.POINTER(rh_ipm_options)]),
+    "rh_ipm_create": (C.c_int, [vp, C.POINTER(rh_ipm_options), vp, vp, C.POINTER(vp)]),
+    "rh_ipm_step": (C.c_int, [vp, C.POINTER(rh_ipm_info)]),
+    "rh_ipm_solve": (C.c_int, [vp, C.POINTER(rh_ipm_info)]),
+    "rh_ipm_get_state": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+    "rh_ipm_destroy": (None, [vp]),
 }
 
 PHASES = ["eval", "refactor", "condense", "symmetrize", "cholesky", "recover"]

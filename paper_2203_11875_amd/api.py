@@ -76,9 +76,9 @@ class Symbolic:
         self.info = _info_dict(info)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().rh_destroy_symbolic(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.rh_destroy_symbolic(self.h)
+        self.h = None
 
     def index_maps(self):
         nx, nu = self.info["nx"], self.info["nu"]
@@ -137,12 +137,17 @@ class Net:
         self.nx, self.nu, self.m = self.info["nx"], self.info["nu"], self.info["m"]
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().rh_destroy_network(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _LIB is not None:
+            if getattr(self, "_ipm", None) is not None:
+                self._ipm.close()
+            _LIB.rh_destroy_network(self.h)
+        self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def _t(self, a, n=None):
         t = self.torch
@@ -228,3 +233,65 @@ class Net:
         if code < 0:
             _check(code, "rh_solve_condensed_kkt")
         return p, code
+
+
+def _info_ipm(info):
+    return {name: (float(getattr(info, name)) if isinstance(getattr(info, name), float)
+                   else int(getattr(info, name)))
+            for name, _ in _abi.rh_ipm_info._fields_ if name != "reserved"}
+
+
+class Ipm:
+    """Interior-point solver on a device network handle (rh_ipm_*)."""
+
+    def __init__(self, net, x0=None, u0=None, tol=1e-6, max_iter=200, mu_init=0.1,
+                 obj_scale=0.0):
+        if not isinstance(net, Net):
+            raise TypeError("Ipm needs an api.Net")
+        self.net = net
+        o = _abi.rh_ipm_options()
+        _check(lib().rh_ipm_default_options(C.byref(o)), "rh_ipm_default_options")
+        o.tol, o.max_iter, o.mu_init, o.obj_scale = float(tol), int(max_iter), float(mu_init), \
+            float(obj_scale)
+        xs = net._t(x0, net.nx) if x0 is not None else None
+        us = net._t(u0, net.nu) if u0 is not None else None
+        h = C.c_void_p()
+        _check(lib().rh_ipm_create(net.h, C.byref(o), _ptr(xs), _ptr(us), C.byref(h)),
+               "rh_ipm_create")
+        self.h = h
+        net._ipm = self
+
+    def close(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.rh_ipm_destroy(self.h)
+        self.h = None
+        if getattr(self, "net", None) is not None and getattr(self.net, "_ipm", None) is self:
+            self.net._ipm = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self):
+        """One iteration; returns (status, info dict)."""
+        info = _abi.rh_ipm_info()
+        code = lib().rh_ipm_step(self.h, C.byref(info))
+        if code < 0:
+            _check(code, "rh_ipm_step")
+        return code, _info_ipm(info)
+
+    def solve(self):
+        info = _abi.rh_ipm_info()
+        code = lib().rh_ipm_solve(self.h, C.byref(info))
+        if code < 0:
+            _check(code, "rh_ipm_solve")
+        return code, _info_ipm(info)
+
+    def state(self):
+        t = self.net.torch
+        n = self.net
+        out = [t.empty(k, dtype=t.float64, device=n.device) for k in (n.nx, n.nu, n.m, n.nx, n.m)]
+        _check(lib().rh_ipm_get_state(self.h, *[_ptr(a) for a in out]), "rh_ipm_get_state")
+        return dict(zip(("x", "u", "s", "lam", "y"), out))

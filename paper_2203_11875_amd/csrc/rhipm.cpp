@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -11,6 +12,7 @@
 
 #include "analysis.hpp"
 #include "device.hpp"
+#include "ipm.hpp"
 
 struct rh_symbolic {
   rh::Symbolic s;
@@ -43,6 +45,13 @@ struct rh_net {
   int* status = nullptr;
   long long* trace = nullptr;
   size_t panel_cap = 0;
+  // objective scale (rh_set_objective_scale): unscaled cost data
+  double obj_scale = 1.0;
+  std::vector<double> c2, c1, c0, k_cdiag;
+  double c2_ref = 0.0, c1_ref = 0.0, cost_rank1 = 0.0;
+  // variable and slack bounds in the natural order (+-inf where none), for
+  // the interior-point driver
+  std::vector<double> wl, wu, sl, su;
 };
 
 namespace {
@@ -180,6 +189,50 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   d.c2_ref = desc.c2[s.ref_gen];
   d.c1_ref = desc.c1[s.ref_gen];
   d.cost_rank1 = s.cost_rank1;
+  n->c2.assign(desc.c2, desc.c2 + s.ng);
+  n->c1.assign(desc.c1, desc.c1 + s.ng);
+  n->c0.assign(desc.c0, desc.c0 + s.ng);
+  n->k_cdiag = s.k_cdiag;
+  n->c2_ref = d.c2_ref;
+  n->c1_ref = d.c1_ref;
+  n->cost_rank1 = d.cost_rank1;
+  {
+    // bounds: theta free, Vm in [vmin, vmax], Pg in [pmin, pmax]; h = (Pg_ref,
+    // Qg, |S_from|^2, |S_to|^2) in [(pmin_ref, qmin, -inf, -inf), (pmax_ref,
+    // qmax, rate^2, rate^2)] and s = -h
+    const double inf = HUGE_VAL;
+    n->wl.assign(s.nw, -inf);
+    n->wu.assign(s.nw, inf);
+    for (int k = 0; k < s.nu; ++k) {
+      const int r = s.u_ref[k];
+      n->wl[k] = s.u_kind[k] == 1 ? desc.vmin[r] : desc.pmin[r];
+      n->wu[k] = s.u_kind[k] == 1 ? desc.vmax[r] : desc.pmax[r];
+    }
+    for (int k = 0; k < s.nx; ++k)
+      if (s.x_kind[k] == 1) {
+        n->wl[s.nu + k] = desc.vmin[s.x_bus[k]];
+        n->wu[s.nu + k] = desc.vmax[s.x_bus[k]];
+      }
+    std::vector<double> hl(s.m, -inf), hu(s.m, inf);
+    hl[0] = desc.pmin[s.ref_gen];
+    hu[0] = desc.pmax[s.ref_gen];
+    for (int g = 0; g < s.ng; ++g) {
+      hl[1 + g] = desc.qmin[g];
+      hu[1 + g] = desc.qmax[g];
+    }
+    for (int l = 0; l < s.nl; ++l) {
+      const int kl = s.lim_of_line[l];
+      if (kl < 0) continue;
+      hu[1 + s.ng + kl] = desc.rate[l] * desc.rate[l];
+      hu[1 + s.ng + s.nlim + kl] = desc.rate[l] * desc.rate[l];
+    }
+    n->sl.resize(s.m);
+    n->su.resize(s.m);
+    for (int j = 0; j < s.m; ++j) {
+      n->sl[j] = -hu[j];
+      n->su[j] = -hl[j];
+    }
+  }
   RH_TRY(upload(n, std::vector<double>(desc.c2, desc.c2 + s.ng), &d.c2));
   RH_TRY(upload(n, std::vector<double>(desc.c1, desc.c1 + s.ng), &d.c1));
   RH_TRY(upload(n, std::vector<double>(desc.c0, desc.c0 + s.ng), &d.c0));
@@ -485,19 +538,22 @@ rh_status rh_eval_residual(rh_net* n, const double* x, const double* u, double* 
   return RH_OK;
 }
 
-rh_status rh_condense_reduced_hessian(rh_net* n, const double* x, const double* u,
-                                      const double* lam, const double* y, const double* sig_x,
-                                      const double* sig_u, const double* sig_s, const double* r,
-                                      double* K, int64_t ldk, double* rhs) {
-  if (!n || !x || !u || !lam || !y || !sig_x || !sig_u || !sig_s || !K) return RH_ERR_ARG;
-  if (ldk < n->s.nu || (r && !rhs) || (rhs && !r)) return RH_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Condensation once the derivative values at (x, u, lambda, y) are in place
+// (rh_condense_reduced_hessian after its evaluation; the interior-point
+// driver after its own).
+rh_status condense_evaluated(rh_net* n, const double* sig_x, const double* sig_u,
+                             const double* sig_s, const double* r, double* K, int64_t ldk,
+                             double* rhs) {
   const auto& d = n->d;
   hipStream_t st = n->stream;
   n->condensed = false;
   RH_HIP(hipMemcpyAsync(n->sig_s, sig_s, sizeof(double) * d.m, hipMemcpyDeviceToDevice, st));
   {
     PhaseScope ps(n, RH_PHASE_EVAL);
-    RH_HIP(rh::launch_eval(d, x, u, lam, y, true, st));
     RH_HIP(rh::launch_assemble_k(d, sig_x, sig_u, sig_s, st));
     if (r) RH_HIP(rh::launch_rtilde(d, r, sig_s, st));
   }
@@ -516,6 +572,48 @@ rh_status rh_condense_reduced_hessian(rh_net* n, const double* x, const double* 
   }
   n->condensed = true;
   n->rhs_cols = r != nullptr;
+  return RH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rh_status rh_condense_reduced_hessian(rh_net* n, const double* x, const double* u,
+                                      const double* lam, const double* y,
+                                      const double* sig_x, const double* sig_u,
+                                      const double* sig_s, const double* r,
+                                      double* K, int64_t ldk, double* rhs) {
+  if (!n || !x || !u || !lam || !y || !sig_x || !sig_u || !sig_s || !K) return RH_ERR_ARG;
+  if (ldk < n->s.nu || (r && !rhs) || (rhs && !r)) return RH_ERR_ARG;
+  {
+    PhaseScope ps(n, RH_PHASE_EVAL);
+    RH_HIP(rh::launch_eval(n->d, x, u, lam, y, true, n->stream));
+  }
+  return condense_evaluated(n, sig_x, sig_u, sig_s, r, K, ldk, rhs);
+}
+
+rh_status rh_set_objective_scale(rh_net* n, double scale) {
+  if (!n || !(scale > 0.0) || !std::isfinite(scale)) return RH_ERR_ARG;
+  auto& d = n->d;
+  const size_t ng = n->c2.size();
+  std::vector<double> c2(ng), c1(ng), c0(ng), kc(n->k_cdiag.size());
+  for (size_t g = 0; g < ng; ++g) {
+    c2[g] = scale * n->c2[g];
+    c1[g] = scale * n->c1[g];
+    c0[g] = scale * n->c0[g];
+  }
+  for (size_t k = 0; k < kc.size(); ++k) kc[k] = scale * n->k_cdiag[k];
+  RH_HIP(hipStreamSynchronize(n->stream));
+  RH_HIP(hipMemcpy(const_cast<double*>(d.c2), c2.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+  RH_HIP(hipMemcpy(const_cast<double*>(d.c1), c1.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+  RH_HIP(hipMemcpy(const_cast<double*>(d.c0), c0.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+  RH_HIP(hipMemcpy(const_cast<double*>(d.k_cdiag), kc.data(), kc.size() * sizeof(double),
+                   hipMemcpyHostToDevice));
+  d.c2_ref = scale * n->c2_ref;
+  d.c1_ref = scale * n->c1_ref;
+  d.cost_rank1 = scale * n->cost_rank1;
+  n->obj_scale = scale;
   return RH_OK;
 }
 
@@ -587,6 +685,409 @@ rh_status rh_profile_read(rh_net* n, double* ms, int64_t* calls) {
     if (ms) ms[k] = n->timers[k].ms;
     if (calls) calls[k] = n->timers[k].calls;
   }
+  return RH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Interior-point driver (Algorithm 1, linearize-then-reduce). The host runs
+// the scalar logic (barrier update, inertia correction, filter line search);
+// every vector operation, evaluation, condensation and solve runs on the
+// device and the host reads a few reduced scalars per stage.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Fixed constants of the method (the filter line search of Waechter and
+// Biegler with a monotone barrier update; see rh_ipm_options).
+constexpr double kKappaEps = 10.0, kKappaMu = 0.2, kThetaMu = 1.5, kTauMin = 0.99;
+constexpr double kSMax = 100.0, kKappaSigma = 1e10, kBoundPush = 1e-2, kBoundFrac = 1e-2;
+constexpr double kDelta0 = 1e-4, kDeltaMin = 1e-20, kDeltaMax = 1e40;
+constexpr double kKwMinus = 1.0 / 3.0, kKwPlus = 8.0, kKwPlusBar = 100.0;
+constexpr double kGammaTheta = 1e-5, kGammaPhi = 1e-8, kDeltaSw = 1.0, kSTheta = 1.1;
+constexpr double kSPhi = 2.3, kEtaPhi = 1e-8, kGammaAlpha = 0.05;
+
+}  // namespace
+
+struct rh_ipm {
+  rh_net* net = nullptr;
+  rh_ipm_options opt{};
+  rh::IpmDev v{};
+  std::vector<void*> allocs;
+  double* K = nullptr;      // nu x nu condensed matrix (factored in place)
+  double* Kc = nullptr;     // its copy for inertia-correction retries
+  double* rhs = nullptr;
+  double mu = 0.1, delta_last = 0.0, theta0 = -1.0, sigma_f = 1.0;
+  std::vector<std::pair<double, double>> filt;
+  long iter = 0;
+  int nfin = 0;             // finite bounds of w and s
+  bool converged = false;
+};
+
+namespace {
+
+template <typename T>
+rh_status ialloc(rh_ipm* p, size_t count, T** out) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) return RH_ERR_OOM;
+  p->allocs.push_back(q);
+  *out = static_cast<T*>(q);
+  return RH_OK;
+}
+
+template <typename T>
+rh_status iupload(rh_ipm* p, const std::vector<T>& h, const T** out) {
+  T* q = nullptr;
+  RH_TRY(ialloc(p, h.size(), &q));
+  if (!h.empty() && hipMemcpy(q, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return RH_ERR_HIP;
+  *out = q;
+  return RH_OK;
+}
+
+void free_ipm(rh_ipm* p) {
+  for (void* q : p->allocs) (void)hipFree(q);
+  p->allocs.clear();
+}
+
+// Reads the reduction slots (and the two objective values) after the stream
+// has drained.
+rh_status read_red(rh_ipm* p, double* red, double* f) {
+  RH_HIP(hipStreamSynchronize(p->net->stream));
+  RH_HIP(hipMemcpy(red, p->v.red, sizeof(double) * rh::IR_NSLOT, hipMemcpyDeviceToHost));
+  if (f) RH_HIP(hipMemcpy(f, p->v.f, sizeof(double) * 2, hipMemcpyDeviceToHost));
+  return RH_OK;
+}
+
+// Scaled optimality error E_mu from the reductions of launch_ipm_stats.
+double opt_error(const rh_ipm* p, const double* red, double mu) {
+  const auto& v = p->v;
+  const double sd = std::max(kSMax, (red[rh::IR_LYSUM] + red[rh::IR_ZSUM]) /
+                                        std::max(1, v.nx + v.m + p->nfin)) / kSMax;
+  const double sc = std::max(kSMax, red[rh::IR_ZSUM] / std::max(1, p->nfin)) / kSMax;
+  const double ed = std::max(red[rh::IR_DUAL_W], v.m ? red[rh::IR_DUAL_S] : 0.0) / sd;
+  const double ep = std::max(red[rh::IR_PRIM_G], v.m ? red[rh::IR_PRIM_H] : 0.0);
+  const double ec =
+      p->nfin ? std::max(red[rh::IR_DZ_MAX] - mu, mu - red[rh::IR_DZ_MIN]) / sc : 0.0;
+  return std::max(ed, std::max(ep, ec));
+}
+
+// Evaluation at the current iterate: derivative values (with the Hessian),
+// gradient of the Lagrangian, reductions and the objective.
+rh_status eval_iterate(rh_ipm* p, double* red, double* f) {
+  rh_net* n = p->net;
+  const auto& d = n->d;
+  auto& v = p->v;
+  hipStream_t st = n->stream;
+  {
+    PhaseScope ps(n, RH_PHASE_EVAL);
+    RH_HIP(rh::launch_eval(d, v.w + v.nu, v.w, v.lam, v.y, true, st));
+    RH_HIP(rh::launch_eval_objective(d, v.w, v.f, st));
+    RH_HIP(rh::launch_ipm_lag_grad(d, v, st));
+    RH_HIP(rh::launch_ipm_stats(d, v, v.w, v.s, 1, st));
+  }
+  return read_red(p, red, f);
+}
+
+void fill_info(const rh_ipm* p, rh_ipm_info* info, double obj, double inf_pr, double err,
+               double alpha, double alpha_z, double delta, long trials) {
+  if (!info) return;
+  std::memset(info, 0, sizeof(*info));
+  info->iter = p->iter;
+  info->obj = obj;
+  info->inf_pr = inf_pr;
+  info->err = err;
+  info->mu = p->mu;
+  info->alpha_pr = alpha;
+  info->alpha_du = alpha_z;
+  info->delta_w = delta;
+  info->ls_trials = trials;
+  info->converged = p->converged ? 1 : 0;
+  info->obj_scale = p->sigma_f;
+}
+
+}  // namespace
+
+extern "C" {
+
+rh_status rh_ipm_default_options(rh_ipm_options* o) {
+  if (!o) return RH_ERR_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-6;
+  o->max_iter = 200;
+  o->mu_init = 0.1;
+  o->obj_scale = 0.0;
+  return RH_OK;
+}
+
+rh_status rh_ipm_create(rh_net* n, const rh_ipm_options* opts, const double* x0,
+                        const double* u0, rh_ipm** out) {
+  if (!n || !out) return RH_ERR_ARG;
+  std::unique_ptr<rh_ipm> p(new (std::nothrow) rh_ipm());
+  if (!p) return RH_ERR_OOM;
+  p->net = n;
+  if (opts) p->opt = *opts; else rh_ipm_default_options(&p->opt);
+  if (!(p->opt.tol > 0.0) || p->opt.max_iter < 0 || !(p->opt.mu_init > 0.0) ||
+      !(p->opt.obj_scale >= 0.0))
+    return RH_ERR_ARG;
+  const rh::Symbolic& s = n->s;
+  auto& v = p->v;
+  v.nu = s.nu;
+  v.nx = s.nx;
+  v.m = s.m;
+  const int nw = s.nw, m = s.m, nx = s.nx, nu = s.nu;
+  rh_status st_ = RH_OK;
+  auto fail = [&](rh_status c) { free_ipm(p.get()); return c; };
+#define IPM_TRY(expr)              \
+  do {                             \
+    st_ = (expr);                  \
+    if (st_ != RH_OK) return fail(st_); \
+  } while (0)
+  IPM_TRY(iupload(p.get(), n->wl, &v.wl));
+  IPM_TRY(iupload(p.get(), n->wu, &v.wu));
+  IPM_TRY(iupload(p.get(), n->sl, &v.sl));
+  IPM_TRY(iupload(p.get(), n->su, &v.su));
+  for (const auto* b : {&n->wl, &n->wu, &n->sl, &n->su})
+    for (double x : *b) p->nfin += std::isfinite(x) ? 1 : 0;
+  {
+    std::vector<int> ug(nu, -1);
+    for (int k = 0; k < nu; ++k)
+      if (s.u_kind[k] == 2) ug[k] = s.u_ref[k];
+    IPM_TRY(iupload(p.get(), ug, &v.u_gen));
+    // G_x by internal columns (transposed products with lambda)
+    std::vector<std::vector<std::pair<int, int>>> cols(nx);
+    for (int r = 0; r < nx; ++r)
+      for (int e = s.gx_ptr[r]; e < s.gx_ptr[r + 1]; ++e)
+        cols[s.iperm[s.gx_col[e]]].push_back({s.iperm[r], s.gx_lu[e]});
+    std::vector<int> cptr(nx + 1, 0), crow, cpos;
+    for (int c = 0; c < nx; ++c) {
+      for (auto& q : cols[c]) {
+        crow.push_back(q.first);
+        cpos.push_back(q.second);
+      }
+      cptr[c + 1] = int(crow.size());
+    }
+    IPM_TRY(iupload(p.get(), cptr, &v.gx_cptr));
+    IPM_TRY(iupload(p.get(), crow, &v.gx_crow));
+    IPM_TRY(iupload(p.get(), cpos, &v.gx_cpos));
+  }
+  const size_t np = size_t(nw) + 2 * size_t(m) + nx;
+  IPM_TRY(ialloc(p.get(), nw, &v.w));
+  IPM_TRY(ialloc(p.get(), m, &v.s));
+  IPM_TRY(ialloc(p.get(), nx, &v.lam));
+  IPM_TRY(ialloc(p.get(), m, &v.y));
+  IPM_TRY(ialloc(p.get(), nw, &v.zl));
+  IPM_TRY(ialloc(p.get(), nw, &v.zu));
+  IPM_TRY(ialloc(p.get(), m, &v.zsl));
+  IPM_TRY(ialloc(p.get(), m, &v.zsu));
+  IPM_TRY(ialloc(p.get(), nw, &v.gf));
+  IPM_TRY(ialloc(p.get(), nw, &v.gl));
+  IPM_TRY(ialloc(p.get(), nw, &v.sig_w));
+  IPM_TRY(ialloc(p.get(), m, &v.sig_s));
+  IPM_TRY(ialloc(p.get(), np, &v.r));
+  IPM_TRY(ialloc(p.get(), np, &v.p));
+  IPM_TRY(ialloc(p.get(), nw, &v.pzl));
+  IPM_TRY(ialloc(p.get(), nw, &v.pzu));
+  IPM_TRY(ialloc(p.get(), m, &v.pzsl));
+  IPM_TRY(ialloc(p.get(), m, &v.pzsu));
+  IPM_TRY(ialloc(p.get(), nw, &v.wt));
+  IPM_TRY(ialloc(p.get(), m, &v.st));
+  IPM_TRY(ialloc(p.get(), rh::IR_NSLOT, &v.red));
+  IPM_TRY(ialloc(p.get(), 2, &v.f));
+  IPM_TRY(ialloc(p.get(), size_t(nu) * nu, &p->K));
+  IPM_TRY(ialloc(p.get(), size_t(nu) * nu, &p->Kc));
+  IPM_TRY(ialloc(p.get(), nu, &p->rhs));
+  hipStream_t st = n->stream;
+  // initial point: the caller's, or theta = 0, Vm = 1, Pg mid-range
+  if (x0 && u0) {
+    if (hipMemcpyAsync(v.w, u0, sizeof(double) * nu, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(v.w + nu, x0, sizeof(double) * nx, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return fail(RH_ERR_HIP);
+  } else if (x0 || u0) {
+    return fail(RH_ERR_ARG);
+  } else {
+    std::vector<double> w(nw, 0.0);
+    for (int k = 0; k < nu; ++k)
+      w[k] = s.u_kind[k] == 1 ? 1.0 : 0.5 * (n->wl[k] + n->wu[k]);
+    for (int k = 0; k < nx; ++k) w[nu + k] = s.x_kind[k] == 1 ? 1.0 : 0.0;
+    if (hipMemcpy(v.w, w.data(), sizeof(double) * nw, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RH_ERR_HIP);
+  }
+  // the objective is scaled at the initial point (pushed inside the bounds)
+  IPM_TRY(rh_set_objective_scale(n, 1.0));
+  if (rh::launch_ipm_init_w(v, kBoundPush, kBoundFrac, st) != hipSuccess ||
+      rh::launch_eval(n->d, v.w + nu, v.w, v.lam, v.y, false, st) != hipSuccess ||
+      rh::launch_ipm_init_s(n->d, v, kBoundPush, kBoundFrac, st) != hipSuccess ||
+      rh::launch_ipm_lag_grad(n->d, v, st) != hipSuccess ||
+      rh::launch_ipm_stats(n->d, v, v.w, v.s, 1, st) != hipSuccess)
+    return fail(RH_ERR_HIP);
+  double red[rh::IR_NSLOT];
+  IPM_TRY(read_red(p.get(), red, nullptr));
+  p->sigma_f = p->opt.obj_scale > 0.0 ? p->opt.obj_scale
+                                      : std::min(1.0, 100.0 / std::max(red[rh::IR_GFMAX], 1e-300));
+  IPM_TRY(rh_set_objective_scale(n, p->sigma_f));
+#undef IPM_TRY
+  p->mu = p->opt.mu_init;
+  *out = p.release();
+  return RH_OK;
+}
+
+void rh_ipm_destroy(rh_ipm* p) {
+  if (!p) return;
+  if (p->net) {
+    (void)hipStreamSynchronize(p->net->stream);
+    (void)rh_set_objective_scale(p->net, 1.0);
+  }
+  free_ipm(p);
+  delete p;
+}
+
+rh_status rh_ipm_step(rh_ipm* p, rh_ipm_info* info) {
+  if (!p) return RH_ERR_ARG;
+  rh_net* n = p->net;
+  auto& v = p->v;
+  const auto& d = n->d;
+  hipStream_t st = n->stream;
+  const int nu = v.nu, nw = v.nu + v.nx;
+  double red[rh::IR_NSLOT], f2[2];
+  RH_TRY(eval_iterate(p, red, f2));
+  const double f0 = f2[0];
+  const double e0 = opt_error(p, red, 0.0);
+  if (e0 <= p->opt.tol) {
+    p->converged = true;
+    fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
+              0.0, 0.0, 0.0, 0);
+    return RH_OK;
+  }
+  if (p->iter >= p->opt.max_iter) {
+    fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
+              0.0, 0.0, 0.0, 0);
+    return RH_NOT_CONVERGED;
+  }
+  // barrier update (monotone)
+  for (int k = 0; k < 10; ++k) {
+    if (opt_error(p, red, p->mu) > kKappaEps * p->mu) break;
+    const double nm = std::max(p->opt.tol / 10.0, std::min(kKappaMu * p->mu, std::pow(p->mu, kThetaMu)));
+    if (nm == p->mu) break;
+    p->mu = nm;
+    p->filt.clear();
+  }
+  const double mu = p->mu;
+  // step: residuals and Sigma, condensation, Cholesky with inertia correction
+  RH_HIP(rh::launch_ipm_prep(d, v, mu, st));
+  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
+  RH_HIP(hipMemcpyAsync(p->Kc, p->K, sizeof(double) * size_t(nu) * nu, hipMemcpyDeviceToDevice, st));
+  double delta = 0.0;
+  rh_status code = rh_solve_condensed_kkt(n, p->K, nu, 0.0, p->rhs, v.r, v.p, nullptr);
+  if (code == RH_NOT_POSDEF) {
+    delta = p->delta_last == 0.0 ? kDelta0 : std::max(kDeltaMin, kKwMinus * p->delta_last);
+    for (;;) {
+      RH_HIP(hipMemcpyAsync(p->K, p->Kc, sizeof(double) * size_t(nu) * nu,
+                            hipMemcpyDeviceToDevice, st));
+      code = rh_solve_condensed_kkt(n, p->K, nu, delta, p->rhs, v.r, v.p, nullptr);
+      if (code != RH_NOT_POSDEF) break;
+      delta *= p->delta_last == 0.0 ? kKwPlusBar : kKwPlus;
+      if (delta > kDeltaMax) {
+        fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
+                  0.0, 0.0, delta, 0);
+        return RH_NOT_CONVERGED;
+      }
+    }
+    p->delta_last = delta;
+  }
+  if (code < 0) return code;
+  // bound-multiplier steps and the largest steps to the boundary
+  const double tau = std::max(kTauMin, 1.0 - mu);
+  RH_HIP(rh::launch_ipm_dir(v, mu, tau, st));
+  double rd[rh::IR_NSLOT];
+  RH_TRY(read_red(p, rd, nullptr));
+  const double a_pri = rd[rh::IR_APRI], a_dual = rd[rh::IR_ADUAL], dphi = rd[rh::IR_DPHI];
+  // filter line search on the barrier objective phi and the violation theta
+  const double theta = red[rh::IR_THETA];
+  const double phi = f0 - mu * red[rh::IR_LOGSUM];
+  if (p->iter == 0 && p->theta0 < 0.0) p->theta0 = theta;
+  const double th0 = p->theta0 < 0.0 ? theta : p->theta0;
+  const double theta_max = 1e4 * std::max(1.0, th0), theta_min = 1e-4 * std::max(1.0, th0);
+  double a_min = kGammaTheta;
+  if (dphi < 0.0) {
+    a_min = std::min(a_min, kGammaPhi * theta / -dphi);
+    if (theta <= theta_min)
+      a_min = std::min(a_min, kDeltaSw * std::pow(theta, kSTheta) / std::pow(-dphi, kSPhi));
+  }
+  a_min *= kGammaAlpha;
+  double alpha = a_pri;
+  long trials = 0;
+  bool ftype = false;
+  double rt[rh::IR_NSLOT], ft[2];
+  for (;;) {
+    if (alpha < a_min) {
+      fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
+                alpha, a_dual, delta, trials);
+      return RH_NOT_CONVERGED;
+    }
+    RH_HIP(rh::launch_ipm_trial(v, alpha, st));
+    RH_HIP(rh::launch_eval(d, v.wt + nu, v.wt, nullptr, nullptr, false, st));
+    RH_HIP(rh::launch_eval_objective(d, v.wt, v.f + 1, st));
+    RH_HIP(rh::launch_ipm_stats(d, v, v.wt, v.st, 0, st));
+    RH_TRY(read_red(p, rt, ft));
+    ++trials;
+    const double th_t = rt[rh::IR_THETA];
+    const double ph_t = ft[1] - mu * rt[rh::IR_LOGSUM];
+    bool ok = std::isfinite(ph_t) && th_t <= theta_max;
+    if (ok)
+      for (const auto& e : p->filt)
+        if (th_t >= e.first && ph_t >= e.second) {
+          ok = false;
+          break;
+        }
+    ftype = false;
+    if (ok) {
+      const bool switching =
+          dphi < 0.0 && alpha * std::pow(-dphi, kSPhi) > kDeltaSw * std::pow(theta, kSTheta);
+      if (switching && theta <= theta_min) {
+        ok = ph_t <= phi + kEtaPhi * alpha * dphi;
+        ftype = true;
+      } else {
+        ok = th_t <= (1.0 - kGammaTheta) * theta || ph_t <= phi - kGammaPhi * theta;
+      }
+    }
+    if (ok) break;
+    alpha *= 0.5;
+  }
+  if (!ftype) p->filt.push_back({(1.0 - kGammaTheta) * theta, phi - kGammaPhi * theta});
+  RH_HIP(rh::launch_ipm_update(v, alpha, a_dual, mu, kKappaSigma, st));
+  p->iter += 1;
+  fill_info(p, info, ft[1] / p->sigma_f, std::max(rt[rh::IR_PRIM_G], rt[rh::IR_PRIM_H]), e0, alpha,
+            a_dual, delta, trials);
+  (void)nw;
+  return RH_OK;
+}
+
+rh_status rh_ipm_solve(rh_ipm* p, rh_ipm_info* info) {
+  if (!p) return RH_ERR_ARG;
+  rh_ipm_info last{};
+  for (;;) {
+    rh_status c = rh_ipm_step(p, &last);
+    if (c != RH_OK) {
+      if (info) *info = last;
+      return c;
+    }
+    if (last.converged) break;
+  }
+  if (info) *info = last;
+  return RH_OK;
+}
+
+rh_status rh_ipm_get_state(const rh_ipm* p, double* x, double* u, double* s, double* lam,
+                           double* y) {
+  if (!p) return RH_ERR_ARG;
+  const auto& v = p->v;
+  hipStream_t st = p->net->stream;
+  if (u) RH_HIP(hipMemcpyAsync(u, v.w, sizeof(double) * v.nu, hipMemcpyDeviceToDevice, st));
+  if (x) RH_HIP(hipMemcpyAsync(x, v.w + v.nu, sizeof(double) * v.nx, hipMemcpyDeviceToDevice, st));
+  if (s) RH_HIP(hipMemcpyAsync(s, v.s, sizeof(double) * v.m, hipMemcpyDeviceToDevice, st));
+  if (lam) RH_HIP(hipMemcpyAsync(lam, v.lam, sizeof(double) * v.nx, hipMemcpyDeviceToDevice, st));
+  if (y) RH_HIP(hipMemcpyAsync(y, v.y, sizeof(double) * v.m, hipMemcpyDeviceToDevice, st));
   return RH_OK;
 }
 

@@ -105,7 +105,7 @@ def _tree_plus_local_chords(rng: np.random.Generator, nb: int, nl: int):
 
 
 def make_network(nb: int, nl: int, ng: int, *, seed: int, load_frac: float,
-                 pd_range=(0.1, 1.0), rated: bool = True, name: str = "",
+                 pd_range=(0.05, 0.5), rated: bool = True, name: str = "",
                  ring: bool = False) -> Network:
     """Seeded synthetic network (see module docstring for the recipe)."""
     if ng < 1 or ng > nb:
