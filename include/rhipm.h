@@ -111,6 +111,8 @@ typedef struct {
   int64_t panel_width, lds_panel;      /* chosen launch shape of the condensation */
   int64_t max_row_ops;                 /* refactorisation multiply-adds of one row */
   int64_t refactor_kernel;             /* 0 wave-resident, 1 level-staged          */
+  int64_t steps_lower;                 /* work-group passes of the L sweep         */
+  int64_t sweep_steps;                 /* passes of all four sweeps of one column  */
 } rh_info;
 
 typedef struct rh_symbolic rh_symbolic;
@@ -146,8 +148,20 @@ rh_status rh_symbolic_gx_pattern(const rh_symbolic* sym, int32_t* rowptr, int32_
  * G_x^T z = b (transpose = 1) with the level-ordered sweeps. Host arrays. */
 rh_status rh_symbolic_host_solve(const rh_symbolic* sym, const double* gx_values,
                                  const double* b, double* z, int32_t transpose);
-/* 0 if every dependency of every sweep lies in an earlier level set. */
+/* 0 if every dependency of every sweep lies in an earlier level set and the
+ * condensation's step schedule is consistent (each row written once, by
+ * the last lane of its group, with exactly its entries, after the rows it
+ * reads). */
 rh_status rh_symbolic_check_levels(const rh_symbolic* sym);
+/* Host check of the condensation's device records for panel width `width`
+ * (1, 2, 3, 4, 8): emulates the condensation kernel lane by lane on random
+ * values drawn from `seed` (G_x with a dominant diagonal, G_u, K, rt, r4) for
+ * columns 0, nu/2 and the right-hand side, and compares with a dense
+ * computation of the same columns of [I;S]^T K [I;S] (Section 3.3).
+ * *max_rel_err (host) receives the largest error relative to each column's
+ * largest entry. RH_ERR_ARG on a bad width or null pointer. */
+rh_status rh_symbolic_check_condense(const rh_symbolic* sym, int32_t width, uint64_t seed,
+                                     double* max_rel_err);
 
 /* ---------------------------------------------------------------------------
  * Device handle. rh_init_network runs the analysis, uploads everything once

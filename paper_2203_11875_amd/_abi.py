@@ -37,7 +37,7 @@ class rh_info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "nx", "nu", "m", "nb", "nl", "ng", "nnz_gx", "nnz_lu", "nnz_gu", "nnz_a", "nnz_k",
         "levels_lower", "levels_upper", "refactor_ops", "max_lu_row", "panel_width",
-        "lds_panel", "max_row_ops", "refactor_kernel")]
+        "lds_panel", "max_row_ops", "refactor_kernel", "steps_lower", "sweep_steps")]
 
 
 class rh_ipm_options(C.Structure):
@@ -64,6 +64,7 @@ SIGNATURES = {
     "rh_symbolic_gx_pattern": (C.c_int, [vp, i32p, i32p, i32p]),
     "rh_symbolic_host_solve": (C.c_int, [vp, f64p, f64p, f64p, C.c_int32]),
     "rh_symbolic_check_levels": (C.c_int, [vp]),
+    "rh_symbolic_check_condense": (C.c_int, [vp, C.c_int32, C.c_uint64, C.POINTER(C.c_double)]),
     "rh_init_network": (C.c_int, [C.POINTER(rh_network_desc), C.POINTER(rh_options), vp,
                                   C.POINTER(vp)]),
     "rh_destroy_network": (None, [vp]),

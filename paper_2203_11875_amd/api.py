@@ -109,6 +109,15 @@ class Symbolic:
     def check_levels(self):
         return lib().rh_symbolic_check_levels(self.h)
 
+    def check_condense(self, width=1, seed=0):
+        """Host emulation of the condensation kernel on its device records
+        (rh_symbolic_check_condense): largest relative error against a dense
+        computation of three columns."""
+        err = C.c_double(0.0)
+        _check(lib().rh_symbolic_check_condense(self.h, int(width), int(seed), C.byref(err)),
+               "rh_symbolic_check_condense")
+        return err.value
+
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
@@ -216,7 +225,6 @@ class Net:
         _check(lib().rh_profile_kernel_trace(self.h, t), "rh_profile_kernel_trace")
         names = ["start", "filled", "L", "U", "hvp", "UT", "LT", "written"]
         out = {names[k]: (t[k] - t[0]) / 100.0 for k in range(8)}   # microseconds
-        out["levels_L"] = [(t[16 + k] - t[1]) / 100.0 for k in range(self.info["levels_lower"])]
         return out
 
     def solve_condensed_kkt(self, K, delta_w, rhs, r):

@@ -100,7 +100,7 @@ std::vector<int> minimum_degree(int n, std::vector<std::vector<int>> adj,
   return order;
 }
 
-void build_sweep(Sweep& sw, int n, const std::vector<int>& level, int nlev,
+bool build_sweep(Sweep& sw, int n, const std::vector<int>& level, int nlev,
                  const std::vector<std::vector<std::pair<int, int>>>& entries,
                  bool has_diag, const std::vector<int>& diag_pos) {
   sw.nlev = nlev;
@@ -125,44 +125,126 @@ void build_sweep(Sweep& sw, int n, const std::vector<int>& level, int nlev,
     }
     sw.lev_ptr[l + 1] = int(sw.rows.size());
   }
-  // Lanes per row of each level: enough that a lane handles about two
-  // entries of the longest row, but not more than fit in one pass of a
-  // 256-thread work-group over the level; a power of two, at most 32.
-  sw.lev_lanes.assign(nlev, 1);
+  // Condensation schedule: per level, the rows with work sorted by length
+  // (longest first, ties by slot), cut into steps of at most
+  // kSweepThreads / S rows, S the fewest lanes (a power of two) that leave
+  // each lane at most kSweepPF entries of the step's longest row.
+  sw.ks_nstep = 0;
+  sw.ks_meta.clear();
+  sw.lb_n = 0;
+  sw.lb_col.clear();
+  sw.lb_src.clear();
+  sw.lb_row.clear();
+  sw.lb_wr.clear();
+  sw.lb_dsrc.clear();
+  auto add_block = [&](int row, int wr, int dsrc) {
+    sw.lb_row.push_back(row);
+    sw.lb_wr.push_back(wr);
+    sw.lb_dsrc.push_back(dsrc);
+    ++sw.lb_n;
+  };
   for (int l = 0; l < nlev; ++l) {
-    int rows = sw.lev_ptr[l + 1] - sw.lev_ptr[l];
-    int maxlen = 0;
+    std::vector<int> qs;
     for (int q = sw.lev_ptr[l]; q < sw.lev_ptr[l + 1]; ++q)
-      maxlen = std::max(maxlen, sw.ptr[q + 1] - sw.ptr[q]);
-    int want = 1;
-    while (want < 32 && want * 2 <= (maxlen + 1) / 2) want *= 2;
-    int fit = 1;
-    while (fit < 32 && fit * 2 * rows <= 256) fit *= 2;
-    sw.lev_lanes[l] = std::max(1, std::min(want, fit));
+      if (has_diag || sw.ptr[q + 1] > sw.ptr[q]) qs.push_back(q);
+    std::stable_sort(qs.begin(), qs.end(), [&](int a, int b) {
+      return sw.ptr[a + 1] - sw.ptr[a] > sw.ptr[b + 1] - sw.ptr[b];
+    });
+    for (size_t i = 0; i < qs.size();) {
+      const int maxlen = sw.ptr[qs[i] + 1] - sw.ptr[qs[i]];
+      int ls = 0;
+      while ((1 << ls) < kSweepMaxLanes && (maxlen + (1 << ls) - 1) / (1 << ls) > kSweepPF) ++ls;
+      const int S = 1 << ls;
+      if ((maxlen + S - 1) / S > kSweepPF) return false;
+      const int R = int(std::min<size_t>(qs.size() - i, size_t(kSweepThreads / S)));
+      sw.ks_meta.insert(sw.ks_meta.end(), {sw.lb_n, R * S, ls, 0});
+      for (int t = 0; t < R * S; ++t) {
+        const int q = qs[i + t / S], k = t % S;
+        for (int j = 0; j < kSweepPF; ++j) {
+          const int e = sw.ptr[q] + k + j * S;
+          if (e < sw.ptr[q + 1]) {
+            sw.lb_col.push_back(sw.col[e]);
+            sw.lb_src.push_back(sw.src[e]);
+          } else {
+            sw.lb_col.push_back(0);
+            sw.lb_src.push_back(-1);
+          }
+        }
+        const bool wr = k == S - 1;
+        add_block(sw.rows[q], wr ? 1 : 0, wr && has_diag ? sw.diag_src[q] : -1);
+      }
+      for (int j = 0; j < kSweepPF; ++j) {   // the idle lanes' block
+        sw.lb_col.push_back(0);
+        sw.lb_src.push_back(-1);
+      }
+      add_block(0, 0, -1);
+      ++sw.ks_nstep;
+      i += R;
+    }
   }
-  sw.lev_base.assign(nlev, 0);
-  sw.lev_len.assign(nlev, 0);
-  sw.ell_col.clear();
-  sw.ell_src.clear();
-  for (int l = 0; l < nlev; ++l) {
-    const int q0 = sw.lev_ptr[l], R = sw.lev_ptr[l + 1] - q0;
+  return true;
+}
+
+
+// Row-blocked record stream of a CSR matrix with n rows plus one extra term
+// per row (see Symbolic::LaneStream): rows sorted by length (longest first,
+// ties by index) so that rows of one block have similar lengths, in blocks of
+// kKRowBlock, one row per lane, each block padded to its longest row.
+template <class Col, class Src, class Extra>
+void build_stream(Symbolic::LaneStream& ls, int n, const std::vector<int>& ptr, Col col, Src src,
+                  Extra extra_col) {
+  const int nblk = (n + kKRowBlock - 1) / kKRowBlock;
+  ls.row.assign(size_t(nblk) * kKRowBlock, -1);
+  for (int v = 0; v < n; ++v) ls.row[v] = v;
+  std::stable_sort(ls.row.begin(), ls.row.begin() + n, [&](int a, int b) {
+    return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b];
+  });
+  ls.pos.assign(n, 0);
+  for (int p = 0; p < n; ++p) ls.pos[ls.row[p]] = p;
+  ls.end.assign(nblk, 0);
+  std::vector<std::vector<int>> lc(kKRowBlock), lsrc(kKRowBlock), lk(kKRowBlock);
+  int acc = 0;
+  for (int bk = 0; bk < nblk; ++bk) {
     int len = 0;
-    for (int q = q0; q < q0 + R; ++q) len = std::max(len, sw.ptr[q + 1] - sw.ptr[q]);
-    sw.lev_base[l] = int(sw.ell_col.size());
-    sw.lev_len[l] = len;
-    for (int k = 0; k < len; ++k)
-      for (int r = 0; r < R; ++r) {
-        const int q = q0 + r, e = sw.ptr[q] + k;
-        if (e < sw.ptr[q + 1]) {
-          sw.ell_col.push_back(sw.col[e]);
-          sw.ell_src.push_back(sw.src[e]);
+    for (int t = 0; t < kKRowBlock; ++t) {
+      const int v = ls.row[size_t(bk) * kKRowBlock + t];
+      if (v >= 0) len = std::max(len, ptr[v + 1] - ptr[v] + 1);
+    }
+    for (int t = 0; t < kKRowBlock; ++t) {
+      const int v = ls.row[size_t(bk) * kKRowBlock + t];
+      const int nv = v >= 0 ? ptr[v + 1] - ptr[v] : 0;
+      for (int k = 0; k < len; ++k) {
+        if (k < nv) {
+          lc[t].push_back(col(ptr[v] + k));
+          lsrc[t].push_back(src(ptr[v] + k));
+          lk[t].push_back(1);
+        } else if (k == nv && v >= 0) {
+          lc[t].push_back(extra_col(v));
+          lsrc[t].push_back(v);
+          lk[t].push_back(2);
         } else {
-          sw.ell_col.push_back(sw.rows[q]);
-          sw.ell_src.push_back(-1);
+          lc[t].push_back(0);
+          lsrc[t].push_back(-1);
+          lk[t].push_back(0);
         }
       }
+    }
+    acc += len;
+    ls.end[bk] = acc;
   }
+  ls.nbat = std::max(1, (acc + kStreamBatch - 1) / kStreamBatch);
+  const size_t per = size_t(ls.nbat) * kStreamBatch;
+  ls.col.assign(per * kKRowBlock, 0);
+  ls.src.assign(per * kKRowBlock, -1);
+  ls.kind.assign(per * kKRowBlock, 0);
+  for (int t = 0; t < kKRowBlock; ++t)
+    for (int p = 0; p < acc; ++p) {
+      ls.col[t * per + p] = lc[t][p];
+      ls.src[t * per + p] = lsrc[t][p];
+      ls.kind[t * per + p] = lk[t][p];
+    }
 }
+
 
 }  // namespace
 
@@ -375,12 +457,14 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
         eUT[c].push_back({i, p});     // U^T(c, i) = U(i, c), i < c
       }
     }
-    build_sweep(s.sl, nx, levL, nlevL, eL, false, s.lu_diag);
-    build_sweep(s.su, nx, levU, nlevU, eU, true, s.lu_diag);
+    bool ok = build_sweep(s.sl, nx, levL, nlevL, eL, false, s.lu_diag) &&
+              build_sweep(s.su, nx, levU, nlevU, eU, true, s.lu_diag);
     // U^T is lower triangular with the pattern of L (symmetric structure);
     // L^T is upper triangular with the pattern of U.
-    build_sweep(s.sut, nx, levL, nlevL, eUT, true, s.lu_diag);
-    build_sweep(s.slt, nx, levU, nlevU, eLT, false, s.lu_diag);
+    ok = ok && build_sweep(s.sut, nx, levL, nlevL, eUT, true, s.lu_diag) &&
+         build_sweep(s.slt, nx, levU, nlevU, eLT, false, s.lu_diag);
+    if (!ok)
+      return fail(s, RH_ERR_ARG, "an LU row has more entries than one wave's sweep step holds");
   }
 
   // ----------------------------------------------- refactorisation schedule
@@ -696,32 +780,10 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
     }
     for (int v = 0; v < s.nw; ++v) kg.diag_var[find_pos(s.k_ptr, s.k_col, v, v)] = v;
   }
-  {
-    const int nblk = (s.nw + kKRowBlock - 1) / kKRowBlock;
-    s.kb_base.assign(nblk, 0);
-    s.kb_len.assign(nblk, 0);
-    s.kell_col.clear();
-    s.kell_pos.clear();
-    for (int bk = 0; bk < nblk; ++bk) {
-      const int v0 = bk * kKRowBlock;
-      int len = 0;
-      for (int v = v0; v < std::min(s.nw, v0 + kKRowBlock); ++v)
-        len = std::max(len, s.k_ptr[v + 1] - s.k_ptr[v]);
-      s.kb_base[bk] = int(s.kell_col.size());
-      s.kb_len[bk] = len;
-      for (int kk = 0; kk < len; ++kk)
-        for (int t = 0; t < kKRowBlock; ++t) {
-          const int v = v0 + t;
-          if (v < s.nw && s.k_ptr[v] + kk < s.k_ptr[v + 1]) {
-            s.kell_col.push_back(s.k_col[s.k_ptr[v] + kk]);
-            s.kell_pos.push_back(s.k_ptr[v] + kk);
-          } else {
-            s.kell_col.push_back(v < s.nw ? v : 0);
-            s.kell_pos.push_back(-1);
-          }
-        }
-    }
-  }
+  build_stream(s.kst, s.nw, s.k_ptr, [&](int e) { return s.k_col[e]; }, [](int e) { return e; },
+               [&](int) { return s.nw; });
+  build_stream(s.gst, s.nu, s.gucsc_ptr, [&](int e) { return s.gucsc_row[e]; },
+               [&](int e) { return s.gucsc_from_csr[e]; }, [](int q) { return q; });
   s.k_cdiag.assign(s.nw, 0.0);
   for (int g = 0; g < ng; ++g)
     if (s.pg_u[g] >= 0) s.k_cdiag[s.pg_u[g]] = 2.0 * d.c2[g] * s.base * s.base;
@@ -822,10 +884,95 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
 }
 
 // ------------------------------------------------------------------ checks
-rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, double* z,
-                     bool transpose) {
+void build_condense_records(const Symbolic& s, int W, CondenseRecords& R) {
+  const long nw = s.nw, nu = s.nu;
+  auto p_row = [&](long v) { return unsigned(v * W * 8); };                          // P row v
+  auto h_row = [&](long v) { return unsigned((nw + 1 + s.kst.pos[v]) * W * 8); };  // H row v
+  const Sweep* sws[4] = {&s.sl, &s.su, &s.sut, &s.slt};
+  size_t nsteps = 0;
+  for (auto* sw : sws) nsteps += size_t(sw->ks_nstep) + 1;
+  R.steps.assign(nsteps * kStepDoubles, 0.0);
+  R.tr_dst.clear();
+  R.tr_src.clear();
+  R.trd_dst.clear();
+  R.trd_src.clear();
+  size_t g = 0;
+  for (int k = 0; k < 4; ++k) {
+    const Sweep& sw = *sws[k];
+    const bool on_h = k >= 2;   // U^T and L^T sweeps run on H
+    R.meta[k].clear();
+    for (int st = 0; st <= sw.ks_nstep; ++st, ++g) {
+      const bool idle_step = st == sw.ks_nstep;
+      const int* m = idle_step ? nullptr : &sw.ks_meta[size_t(kSweepMeta) * st];
+      R.meta[k].insert(R.meta[k].end(), {int(g), idle_step ? 0 : m[2], 0, 0});
+      double* S = &R.steps[g * kStepDoubles];
+      for (int t = 0; t < kSweepThreads; ++t) {
+        // lanes past the step's rows take its padding block
+        const int b = idle_step ? -1 : m[0] + std::min(t, m[1]);
+        for (int j = 0; j < kSweepPF; ++j) {
+          unsigned* off = reinterpret_cast<unsigned*>(S + (4 + j / 4) * kChunk + 2 * t);
+          const size_t e = b >= 0 ? size_t(b) * kSweepPF + j : 0;
+          const long row = nu + (b >= 0 ? sw.lb_col[e] : 0);
+          off[j % 4] = on_h ? h_row(row) : p_row(row);
+          if (b >= 0 && sw.lb_src[e] >= 0) {
+            R.tr_dst.push_back(int(g * kStepDoubles + (j / 2) * kChunk + 2 * t + j % 2));
+            R.tr_src.push_back(sw.lb_src[e]);
+          }
+        }
+        double* piv = S + 6 * kChunk + 2 * t;
+        unsigned* ro = reinterpret_cast<unsigned*>(piv + 1);
+        const long row = nu + (b >= 0 ? sw.lb_row[b] : 0);
+        ro[0] = on_h ? h_row(row) : p_row(row);
+        ro[1] = b >= 0 && sw.lb_wr[b] ? 1u : 0u;
+        if (ro[1] && sw.has_diag) {
+          R.trd_dst.push_back(int(g * kStepDoubles + 6 * kChunk + 2 * t));
+          R.trd_src.push_back(sw.lb_dsrc[b]);
+        } else if (ro[1]) {
+          *piv = 1.0;
+        }
+      }
+    }
+  }
+  // record streams
+  auto stream = [&](const Symbolic::LaneStream& ls, bool gt, std::vector<double>& str,
+                    std::vector<int>& dst, std::vector<int>* xdst) {
+    const size_t per = size_t(ls.nbat) * kStreamBatch;
+    str.assign(size_t(ls.nbat) * kBatchDoubles, 0.0);
+    for (int t = 0; t < kKRowBlock; ++t)
+      for (size_t q = 0; q < per; ++q) {
+        const size_t rec = t * per + q, i = q / kStreamBatch, r = q % kStreamBatch;
+        const size_t vi = i * kBatchDoubles + (r / 2) * kChunk + 2 * t + r % 2;
+        unsigned* off = reinterpret_cast<unsigned*>(&str[i * kBatchDoubles + (4 + r / 4) * kChunk + 2 * t]);
+        const int kind = ls.kind[rec], c = ls.col[rec];
+        if (kind == 0) {
+          off[r % 4] = 0;
+        } else if (!gt) {   // K: P rows (nw = the indicator row)
+          off[r % 4] = p_row(c);
+          (kind == 1 ? dst[ls.src[rec]] : (*xdst)[ls.src[rec]]) = int(vi);
+        } else if (kind == 1) {   // G_u^T entry: H_x row
+          off[r % 4] = h_row(nu + c);
+          dst[ls.src[rec]] = int(vi);
+        } else {   // -H_u of the row
+          off[r % 4] = h_row(c);
+          str[vi] = -1.0;
+        }
+      }
+  };
+  R.kdst.assign(std::max<size_t>(1, s.k_col.size()), 0);
+  R.krt_dst.assign(size_t(nw), 0);
+  R.gdst.assign(std::max<size_t>(1, s.gu_col.size()), 0);
+  stream(s.kst, false, R.kstr, R.kdst, &R.krt_dst);
+  stream(s.gst, true, R.gstr, R.gdst, nullptr);
+  R.hpos = s.kst.pos;
+  R.grow.assign(s.gst.row.begin(), s.gst.row.begin() + nu);
+}
+
+// Host refactorisation of G_x (values in natural CSR order) into LU
+// positions, with the device's schedule (see host_solve).
+rh_status host_refactor(const Symbolic& s, const double* gxv, std::vector<double>& lu_out) {
   const int nx = s.nx;
-  std::vector<double> lu(s.lu_col.size(), 0.0);
+  std::vector<double>& lu = lu_out;
+  lu.assign(s.lu_col.size(), 0.0);
   for (size_t p = 0; p < s.gx_col.size(); ++p) lu[s.gx_lu[p]] = gxv[p];
   if (s.rw_ok) {
     // the wave-resident schedule, lane by lane as the device runs it
@@ -895,17 +1042,49 @@ rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, doub
     }
   for (int i = 0; i < nx; ++i)
     if (lu[s.lu_diag[i]] == 0.0) return RH_SMALL_PIVOT;
+  return RH_OK;
+}
+
+rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, double* z,
+                     bool transpose) {
+  const int nx = s.nx;
+  std::vector<double> lu;
+  {
+    const rh_status st = host_refactor(s, gxv, lu);
+    if (st != RH_OK) return st;
+  }
+  for (int i = 0; i < nx; ++i)
+    if (lu[s.lu_diag[i]] == 0.0) return RH_SMALL_PIVOT;
   std::vector<double> w(nx);
   for (int i = 0; i < nx; ++i) w[i] = b[s.perm[i]];
+  // the sweeps follow the device's step schedule lane by lane: per lane an
+  // FMA chain over its block, per row the DPP shift tree, then the writing
+  // lane's (b - sum) * reciprocal pivot
   auto run = [&](const Sweep& sw) {
-    for (int lv = 0; lv < sw.nlev; ++lv)
-      for (int sl = sw.lev_ptr[lv]; sl < sw.lev_ptr[lv + 1]; ++sl) {
-        int i = sw.rows[sl];
-        double acc = w[i];
-        for (int e = sw.ptr[sl]; e < sw.ptr[sl + 1]; ++e) acc -= lu[sw.src[e]] * w[sw.col[e]];
-        if (sw.has_diag) acc /= lu[sw.diag_src[sl]];
-        w[i] = acc;
+    for (int st = 0; st < sw.ks_nstep; ++st) {
+      const int* m = &sw.ks_meta[size_t(kSweepMeta) * st];
+      const int b0 = m[0], TL = m[1], S = 1 << m[2];
+      std::vector<double> a(TL), out(TL);
+      for (int t = 0; t < TL; ++t) {
+        double acc = 0.0;
+        for (int j = 0; j < kSweepPF; ++j) {
+          const size_t e = size_t(b0 + t) * kSweepPF + j;
+          const double v = sw.lb_src[e] >= 0 ? lu[sw.lb_src[e]] : 0.0;
+          acc = std::fma(v, w[sw.lb_col[e]], acc);
+        }
+        a[t] = acc;
       }
+      for (int g = 0; g < TL; g += S)
+        for (int h = 1; h < S; h *= 2)
+          for (int ln = S - 1; ln >= h; --ln) a[g + ln] += a[g + ln - h];
+      for (int t = 0; t < TL; ++t)
+        if (sw.lb_wr[b0 + t]) {
+          const double dv = sw.has_diag ? 1.0 / lu[sw.lb_dsrc[b0 + t]] : 1.0;
+          out[t] = (w[sw.lb_row[b0 + t]] - a[t]) * dv;
+        }
+      for (int t = 0; t < TL; ++t)
+        if (sw.lb_wr[b0 + t]) w[sw.lb_row[b0 + t]] = out[t];
+    }
   };
   if (!transpose) {
     run(s.sl);
@@ -915,6 +1094,213 @@ rh_status host_solve(const Symbolic& s, const double* gxv, const double* b, doub
     run(s.slt);
   }
   for (int i = 0; i < nx; ++i) z[s.perm[i]] = w[i];
+  return RH_OK;
+}
+
+namespace {
+
+// Dense solve A x = b (row-major n x n copy, partial pivoting).
+void dense_solve(std::vector<double> A, int n, std::vector<double>& x) {
+  for (int k = 0; k < n; ++k) {
+    int pr = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[size_t(i) * n + k]) > std::fabs(A[size_t(pr) * n + k])) pr = i;
+    if (pr != k) {
+      for (int c = 0; c < n; ++c) std::swap(A[size_t(k) * n + c], A[size_t(pr) * n + c]);
+      std::swap(x[k], x[pr]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = A[size_t(i) * n + k] / A[size_t(k) * n + k];
+      if (f == 0.0) continue;
+      for (int c = k; c < n; ++c) A[size_t(i) * n + c] -= f * A[size_t(k) * n + c];
+      x[i] -= f * x[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double acc = x[k];
+    for (int c = k + 1; c < n; ++c) acc -= A[size_t(k) * n + c] * x[c];
+    x[k] = acc / A[size_t(k) * n + k];
+  }
+}
+
+}  // namespace
+
+rh_status host_check_condense(const Symbolic& s, int W, uint64_t seed, int ncols,
+                              double* max_rel_err) {
+  const int nx = s.nx, nu = s.nu, nw = s.nw;
+  uint64_t st = seed * 6364136223846793005ull + 1442695040888963407ull;
+  auto rnd = [&]() {   // uniform in [-1, 1)
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    return double(st >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  };
+  // values: G_x (natural CSR, dominant diagonal), G_u (CSR), K (CSR), rt, r4
+  std::vector<double> gx(s.gx_col.size()), gu(s.gu_col.size()), kv(s.k_col.size()), rt(nw),
+      r4(nx);
+  for (int i = 0; i < nx; ++i) {
+    double sum = 0.0;
+    int dpos = -1;
+    for (int p = s.gx_ptr[i]; p < s.gx_ptr[i + 1]; ++p) {
+      gx[p] = rnd();
+      sum += std::fabs(gx[p]);
+      if (s.gx_col[p] == i) dpos = p;
+    }
+    if (dpos < 0) return RH_ERR_STATE;
+    gx[dpos] = 2.0 + sum;
+  }
+  for (auto& v : gu) v = rnd();
+  for (auto& v : kv) v = rnd();
+  for (auto& v : rt) v = rnd();
+  for (auto& v : r4) v = rnd();
+  std::vector<double> lu;
+  {
+    const rh_status rs = host_refactor(s, gx.data(), lu);
+    if (rs != RH_OK) return rs;
+  }
+  // device records with transcribed values
+  CondenseRecords R;
+  build_condense_records(s, W, R);
+  for (size_t t = 0; t < R.tr_dst.size(); ++t) R.steps[R.tr_dst[t]] = lu[R.tr_src[t]];
+  for (size_t t = 0; t < R.trd_dst.size(); ++t) R.steps[R.trd_dst[t]] = 1.0 / lu[R.trd_src[t]];
+  for (size_t e = 0; e < s.k_col.size(); ++e) R.kstr[R.kdst[e]] = kv[e];
+  for (int v = 0; v < nw; ++v) R.kstr[R.krt_dst[v]] = rt[v];
+  for (size_t e = 0; e < s.gu_col.size(); ++e) R.gstr[R.gdst[e]] = gu[e];
+  // dense references in the internal order (internal i <-> natural perm[i])
+  std::vector<double> Gi(size_t(nx) * nx, 0.0), GiT(size_t(nx) * nx, 0.0);
+  for (int r = 0; r < nx; ++r)
+    for (int p = s.gx_ptr[r]; p < s.gx_ptr[r + 1]; ++p) {
+      const int i = s.iperm[r], k = s.iperm[s.gx_col[p]];
+      Gi[size_t(i) * nx + k] = gx[p];
+      GiT[size_t(k) * nx + i] = gx[p];
+    }
+  double worst = 0.0;
+  const int cols[3] = {0, nu / 2, nu};   // two control columns and the right-hand side
+  for (int ci = 0; ci < std::min(ncols, 3); ++ci) {
+    const int j = cols[ci];
+    const bool rhs = j == nu;
+    // ---- emulation of the condensation kernel for column 0 of a W-wide panel
+    std::vector<double> pan(size_t(2 * nw + 1) * W, 0.0);
+    auto at = [&](unsigned off) -> double& { return pan[off / 8]; };
+    if (rhs) {
+      pan[size_t(nw) * W] = 1.0;
+      for (int i = 0; i < nx; ++i) pan[size_t(nu + i) * W] = -r4[i];
+    } else {
+      pan[size_t(j) * W] = 1.0;
+      for (int e = s.gucsc_ptr[j]; e < s.gucsc_ptr[j + 1]; ++e)
+        pan[size_t(nu + s.gucsc_row[e]) * W] = -gu[s.gucsc_from_csr[e]];
+    }
+    for (int k = 0; k < 4; ++k) {
+      const std::vector<int>& M = R.meta[k];
+      const int n = int(M.size()) / 4 - 1;
+      for (int q = 0; q < n; ++q) {
+        const double* S = &R.steps[size_t(M[4 * q]) * kStepDoubles];
+        const int ls = M[4 * q + 1];
+        double a[kSweepThreads], xr[kSweepThreads];
+        for (int t = 0; t < kSweepThreads; ++t) {
+          double acc = 0.0;
+          for (int jj = 0; jj < kSweepPF; ++jj) {
+            const double v = S[(jj / 2) * kChunk + 2 * t + jj % 2];
+            const unsigned o = reinterpret_cast<const unsigned*>(S + (4 + jj / 4) * kChunk + 2 * t)[jj % 4];
+            acc = std::fma(v, at(o), acc);
+          }
+          a[t] = acc;
+          xr[t] = at(reinterpret_cast<const unsigned*>(S + 6 * kChunk + 2 * t + 1)[0]);
+        }
+        for (int lv = 0; lv < std::min(ls, 4); ++lv) {   // DPP row shifts by 1, 2, 4, 8
+          const int h = 1 << lv;
+          double b2[kSweepThreads];
+          for (int t = 0; t < kSweepThreads; ++t) b2[t] = a[t] + ((t % 16) >= h ? a[t - h] : 0.0);
+          std::copy(b2, b2 + kSweepThreads, a);
+        }
+        if (ls >= 5) {
+          double b2[kSweepThreads];
+          for (int t = 0; t < kSweepThreads; ++t) {
+            const int row = t / 16;
+            b2[t] = a[t] + ((row == 1 || row == 3) ? a[16 * row - 1] : 0.0);
+          }
+          std::copy(b2, b2 + kSweepThreads, a);
+        }
+        if (ls >= 6) {
+          double b2[kSweepThreads];
+          for (int t = 0; t < kSweepThreads; ++t) b2[t] = a[t] + (t >= 32 ? a[31] : 0.0);
+          std::copy(b2, b2 + kSweepThreads, a);
+        }
+        for (int t = 0; t < kSweepThreads; ++t) {
+          const unsigned* ro = reinterpret_cast<const unsigned*>(S + 6 * kChunk + 2 * t + 1);
+          if (ro[1]) at(ro[0]) = (xr[t] - a[t]) * S[6 * kChunk + 2 * t];
+        }
+      }
+      if (k == 1) {   // H = K [V; Z] after the L and U sweeps
+        const Symbolic::LaneStream& ls = s.kst;
+        for (int t = 0; t < kKRowBlock; ++t) {
+          double acc = 0.0;
+          int b = 0;
+          for (int q = 0; q < ls.end.back(); ++q) {
+            const size_t i = q / kStreamBatch, r = q % kStreamBatch;
+            const double v = R.kstr[i * kBatchDoubles + (r / 2) * kChunk + 2 * t + r % 2];
+            const unsigned o = reinterpret_cast<const unsigned*>(&R.kstr[i * kBatchDoubles + (4 + r / 4) * kChunk + 2 * t])[r % 4];
+            acc = std::fma(v, at(o), acc);
+            while (b < int(ls.end.size()) && q + 1 == ls.end[b]) {
+              const int p = b * kKRowBlock + t;
+              if (p < nw) pan[size_t(nw + 1 + p) * W] = acc;
+              acc = 0.0;
+              ++b;
+            }
+          }
+        }
+      }
+    }
+    std::vector<double> out(nu);
+    {
+      const Symbolic::LaneStream& ls = s.gst;
+      for (int t = 0; t < kKRowBlock; ++t) {
+        double acc = 0.0;
+        int b = 0;
+        for (int q = 0; q < (ls.end.empty() ? 0 : ls.end.back()); ++q) {
+          const size_t i = q / kStreamBatch, r = q % kStreamBatch;
+          const double v = R.gstr[i * kBatchDoubles + (r / 2) * kChunk + 2 * t + r % 2];
+          const unsigned o = reinterpret_cast<const unsigned*>(&R.gstr[i * kBatchDoubles + (4 + r / 4) * kChunk + 2 * t])[r % 4];
+          acc = std::fma(v, at(o), acc);
+          while (b < int(ls.end.size()) && q + 1 == ls.end[b]) {
+            const int p = b * kKRowBlock + t;
+            if (p < nu) out[R.grow[p]] = -acc;
+            acc = 0.0;
+            ++b;
+          }
+        }
+      }
+    }
+    // ---- dense reference
+    std::vector<double> z(nx, 0.0);
+    if (rhs) {
+      for (int i = 0; i < nx; ++i) z[i] = -r4[i];
+    } else {
+      for (int i = 0; i < nx; ++i)
+        for (int e = s.gu_ptr[i]; e < s.gu_ptr[i + 1]; ++e)
+          if (s.gu_col[e] == j) z[i] -= gu[e];
+    }
+    dense_solve(Gi, nx, z);
+    std::vector<double> w(nw, 0.0), hcol(nw, 0.0);
+    if (!rhs) w[j] = 1.0;
+    for (int i = 0; i < nx; ++i) w[nu + i] = z[i];
+    for (int v = 0; v < nw; ++v) {
+      double acc = rhs ? rt[v] : 0.0;
+      for (int p = s.k_ptr[v]; p < s.k_ptr[v + 1]; ++p) acc += kv[p] * w[s.k_col[p]];
+      hcol[v] = acc;
+    }
+    std::vector<double> psi(hcol.begin() + nu, hcol.end());
+    dense_solve(GiT, nx, psi);
+    double scale = 0.0, err = 0.0;
+    for (int q = 0; q < nu; ++q) {
+      double ref = hcol[q];
+      for (int i = 0; i < nx; ++i)
+        for (int e = s.gu_ptr[i]; e < s.gu_ptr[i + 1]; ++e)
+          if (s.gu_col[e] == q) ref -= gu[e] * psi[i];
+      scale = std::max(scale, std::fabs(ref));
+      err = std::max(err, std::fabs(ref - out[q]));
+    }
+    worst = std::max(worst, err / std::max(scale, 1e-300));
+  }
+  *max_rel_err = worst;
   return RH_OK;
 }
 
@@ -928,10 +1314,64 @@ rh_status check_levels(const Symbolic& s) {
       }
     for (int i = 0; i < s.nx; ++i)
       if (lv[i] < 0) return RH_ERR_STATE;
+    std::vector<int> slot_of(s.nx, -1);
     for (int l = 0; l < sw->nlev; ++l)
-      for (int q = sw->lev_ptr[l]; q < sw->lev_ptr[l + 1]; ++q)
+      for (int q = sw->lev_ptr[l]; q < sw->lev_ptr[l + 1]; ++q) {
+        slot_of[sw->rows[q]] = q;
         for (int e = sw->ptr[q]; e < sw->ptr[q + 1]; ++e)
           if (lv[sw->col[e]] >= l) return RH_ERR_STATE;
+      }
+    // step schedule: shapes, every row with work written by exactly one
+    // lane, each group's lanes on one row with exactly the row's entries,
+    // every column read finished in an earlier step (or never written: a
+    // unit-diagonal row with no entries), idle blocks all padding
+    std::vector<int> step_of(s.nx, -1);
+    for (int st = 0; st < sw->ks_nstep; ++st) {
+      const int* m = &sw->ks_meta[size_t(kSweepMeta) * st];
+      const int b0 = m[0], TL = m[1], ls = m[2], S = 1 << ls;
+      if (ls < 0 || S > kSweepMaxLanes || TL < S || TL % S || TL > kSweepThreads)
+        return RH_ERR_STATE;
+      if (b0 < 0 || b0 + TL + 1 > sw->lb_n || (st + 1 < sw->ks_nstep && sw->ks_meta[size_t(kSweepMeta) * (st + 1)] != b0 + TL + 1))
+        return RH_ERR_STATE;
+      for (int t = 0; t < TL; t += S) {
+        const int i = sw->lb_row[b0 + t];
+        if (i < 0 || i >= s.nx || step_of[i] != -1) return RH_ERR_STATE;
+        step_of[i] = st;
+        for (int k = 0; k < S; ++k)
+          if (sw->lb_row[b0 + t + k] != i || sw->lb_wr[b0 + t + k] != (k == S - 1 ? 1 : 0))
+            return RH_ERR_STATE;
+        if (sw->has_diag && sw->lb_dsrc[b0 + t + S - 1] != sw->diag_src[slot_of[i]])
+          return RH_ERR_STATE;
+      }
+      const int idle = b0 + TL;
+      if (sw->lb_wr[idle] != 0) return RH_ERR_STATE;
+      for (int j = 0; j < kSweepPF; ++j)
+        if (sw->lb_src[size_t(idle) * kSweepPF + j] != -1) return RH_ERR_STATE;
+    }
+    for (int i = 0; i < s.nx; ++i) {
+      const int q = slot_of[i];
+      const bool work = sw->has_diag || sw->ptr[q + 1] > sw->ptr[q];
+      if ((step_of[i] >= 0) != work) return RH_ERR_STATE;
+    }
+    for (int st = 0; st < sw->ks_nstep; ++st) {
+      const int* m = &sw->ks_meta[size_t(kSweepMeta) * st];
+      const int b0 = m[0], TL = m[1], S = 1 << m[2];
+      for (int t = 0; t < TL; t += S) {
+        const int i = sw->lb_row[b0 + t], q = slot_of[i];
+        std::vector<std::pair<int, int>> got, want;
+        for (int k = 0; k < S; ++k)
+          for (int j = 0; j < kSweepPF; ++j) {
+            const size_t e = size_t(b0 + t + k) * kSweepPF + j;
+            if (sw->lb_src[e] >= 0) got.push_back({sw->lb_col[e], sw->lb_src[e]});
+          }
+        for (int e = sw->ptr[q]; e < sw->ptr[q + 1]; ++e) want.push_back({sw->col[e], sw->src[e]});
+        std::sort(got.begin(), got.end());
+        std::sort(want.begin(), want.end());
+        if (got != want) return RH_ERR_STATE;
+        for (auto& ce : got)
+          if (step_of[ce.first] >= st) return RH_ERR_STATE;
+      }
+    }
   }
   return RH_OK;
 }

@@ -14,8 +14,7 @@
 
 namespace rh {
 
-constexpr int kKRowBlock = 256;
-constexpr int kMaxRowBlocks = 16;   // LDS-resident panels: nu + nx <= 16 * 256
+constexpr int kKRowBlock = 64;      // rows per block of the row-blocked record layouts
 constexpr int kRefLdsBudget = 155 * 1024;   // bytes of LDS the refactorisation may use
 // Wave-resident refactorisation: 8 waves; a task is one row of at most 64
 // LU entries (one lane per entry) or up to four rows of at most 16 entries
@@ -27,6 +26,24 @@ constexpr int kRefLdsBudget = 155 * 1024;   // bytes of LDS the refactorisation 
 constexpr int kRwWaves = 8;
 constexpr int kRwRec = 24;
 constexpr int kRwPacked = 32;
+// Condensation sweep steps: entries a lane holds in registers, most lanes
+// per row (one DPP row), threads of the work-group, ints of step metadata.
+constexpr int kSweepPF = 8;
+constexpr int kSweepMaxLanes = 64;
+constexpr int kSweepThreads = 64;
+constexpr int kSweepMeta = 4;
+// Row-blocked record streams of the condensation (K, G_u^T): batches of
+// kStreamBatch records per lane.
+constexpr int kStreamBatch = 8;
+// Device record sizes in doubles: a sweep lane block (kSweepPF values,
+// kSweepPF 32-bit offsets, pivot, row offset + pad) and a stream batch.
+// Device record layouts (doubles). A sweep step: 7 chunks of 64 lanes x 16
+// bytes (values 0-1, 2-3, 4-5, 6-7; offsets 0-3, 4-7; reciprocal pivot, row
+// offset, writer flag), so that each 16-byte load of the wave is contiguous.
+// A stream batch: 6 such chunks (values 0-1 .. 6-7; offsets 0-3, 4-7).
+constexpr int kChunk = 2 * kSweepThreads;           // doubles per chunk
+constexpr int kStepDoubles = 7 * kChunk;
+constexpr int kBatchDoubles = 6 * kChunk;
 
 // Per-line record written by the line-evaluation kernel (doubles).
 enum LineSlot : int {
@@ -54,13 +71,20 @@ struct Sweep {
   std::vector<int> src;       // entry -> position in the LU value array
   bool has_diag = false;      // divide by the diagonal (U-type sweeps)
   std::vector<int> diag_src;  // slot -> position of the diagonal in LU values
-  std::vector<int> lev_lanes; // lanes that cooperate on one row in each level
-  // Padded per-level layout: level l holds rows lev_ptr[l] .. lev_ptr[l+1]
-  // (R of them) and lev_len[l] entry columns; entry k of the r-th row sits at
-  // lev_base[l] + k * R + r, so its address needs no row pointer. Padding
-  // entries point at their own row with source -1 (value 0).
-  std::vector<int> lev_base, lev_len;
-  std::vector<int> ell_col, ell_src;
+  // Schedule of the condensation kernel's sweeps, in steps of one wave. A
+  // step holds R rows with S = 2^ls lanes per row (S <= kSweepMaxLanes),
+  // TL = R * S lanes in use; lane t = r * S + k takes entries k + j * S
+  // (j < kSweepPF) of its row r. A step owns TL + 1 lane blocks (the last,
+  // all padding, serves the idle lanes); per block: kSweepPF (column, LU
+  // position) pairs (position -1 = padding), the row, whether this lane
+  // writes the row (the last lane of its group) and the LU position of the
+  // pivot (U-type sweeps, writing lanes). Rows with nothing to do (no entries
+  // in a unit-diagonal sweep) are left out.
+  int ks_nstep = 0;
+  std::vector<int> ks_meta;        // kSweepMeta ints per step: first block, TL, ls, 0
+  int lb_n = 0;                    // lane blocks
+  std::vector<int> lb_col, lb_src; // kSweepPF per block
+  std::vector<int> lb_row, lb_wr, lb_dsrc;   // per block (row 0, wr 0 on padding blocks)
 };
 
 struct Gather {          // dst[e] = c[e] + sum_t coef[t] * src[idx[t]]
@@ -124,11 +148,22 @@ struct Symbolic {
   // K pattern (w x w), CSR with sorted columns
   std::vector<int> k_ptr, k_col;
   KGather kg;
-  // K rows in blocks of kKRowBlock (one row per thread of the condensation
-  // work-group), padded to the longest row of the block: entry k of row
-  // kKRowBlock*b + t sits at kb_base[b] + k*kKRowBlock + t; kell_pos maps
-  // each slot to its CSR entry (-1 = padding, value 0, column = own row).
-  std::vector<int> kb_base, kb_len, kell_col, kell_pos;
+  // Row-blocked record streams (one row per lane of the condensation's
+  // wave): the rows, sorted by length (row[p] = row at stream position p,
+  // -1 past the end; pos = its inverse), in blocks of kKRowBlock; position
+  // p = kKRowBlock*b + t belongs to lane t; lane t's records, block after
+  // block (each block padded to its longest row), form one stream of
+  // nbat * kStreamBatch records, record q of lane t at t * nbat *
+  // kStreamBatch + q; end[b] = records per lane through block b.
+  // kind: 0 padding (value 0, column 0), 1 matrix entry (src = its position
+  // in the CSR values of K / G_u),
+  // 2 extra term of the row (K: rt, column nw; G_u^T: -H_u of the row, column
+  // = the row). K columns are w indices; G_u^T columns internal state rows.
+  struct LaneStream {
+    int nbat = 0;
+    std::vector<int> row, pos, end, col, src, kind;
+  };
+  LaneStream kst, gst;
   // refactorisation launch shape per level: lanes per row and the LDS
   // layout of one row's staging area (in doubles): stride, offsets of the U
   // sources, the pivots, the destination offsets and the op pointers
@@ -156,9 +191,35 @@ struct Symbolic {
 // Returns RH_OK or an error code (message in sym.error).
 rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& sym);
 
+// The condensation's device records for launch width W: panel offsets are
+// bytes from the start of a work-group's panels, P = [V; Z; indicator]
+// (nw + 1 rows, natural order) then H (nw rows in K-stream order: H row v at
+// position kst.pos[v]); W doubles per row. The output of G_u^T Psi - H_u is
+// written over P's first nu rows in G-stream order (control gst.row[p] at p).
+struct CondenseRecords {
+  std::vector<double> steps;         // kStepDoubles per step (all sweeps, idle steps)
+  std::vector<int> meta[4];          // per sweep, per step: {global step, ls, 0, 0}; then idle
+  std::vector<int> tr_dst, tr_src;   // steps[tr_dst] = LU value tr_src
+  std::vector<int> trd_dst, trd_src; // steps[trd_dst] = 1 / LU value trd_src
+  std::vector<double> kstr, gstr;    // kBatchDoubles per batch
+  std::vector<int> kdst;             // nnz_k: kstr index of each K entry (CSR)
+  std::vector<int> krt_dst;          // nw: kstr index of each row's rt term
+  std::vector<int> gdst;             // nnz_gu: gstr index of each G_u entry (CSR)
+  std::vector<int> hpos;             // nw: H position of w row v
+  std::vector<int> grow;             // nu: control at G-stream position p
+};
+void build_condense_records(const Symbolic& sym, int W, CondenseRecords& out);
+
 // Host refactorisation + sweeps (for CPU tests of the schedule).
 rh_status host_solve(const Symbolic& sym, const double* gx_values_natural_csr,
                      const double* b_nat, double* z_nat, bool transpose);
 rh_status check_levels(const Symbolic& sym);
+// Host emulation of the condensation kernel on its device records for width
+// W (random G_x with dominant diagonal, G_u, K, rt and r4 values drawn from
+// seed), columns 0, nu/2 and the right-hand side (ncols of them), against a
+// dense computation; the largest error relative to each column's largest
+// entry.
+rh_status host_check_condense(const Symbolic& sym, int W, uint64_t seed, int ncols,
+                              double* max_rel_err);
 
 }  // namespace rh

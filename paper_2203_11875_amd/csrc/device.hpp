@@ -10,23 +10,13 @@ namespace rh {
 
 struct DevSweep {
   int nlev = 0;
-  const int* lev_ptr = nullptr;   // nlev + 1
-  const int* rows = nullptr;      // nx
-  const int* ptr = nullptr;       // nx + 1
-  const int* col = nullptr;       // entries
-  const int* src = nullptr;       // entries -> LU position
-  const int* diag_src = nullptr;  // nx (U-type sweeps) or null
-  const int* lev_lanes = nullptr; // nlev: lanes per row in each level
-  const int* lev_base = nullptr;  // nlev: padded-layout offset of each level
-  const int* lev_len = nullptr;   // nlev: padded row length of each level
-  const int* ell_col = nullptr;   // padded layout: column
-  const int* ell_src = nullptr;   // padded layout: LU position or -1
-  double* ell_val = nullptr;      // padded layout: value (transcribed)
-  int ell_n = 0;
-  double* val = nullptr;          // entries, transcribed after refactorisation
-  double* dinv = nullptr;         // nx reciprocal pivots (all ones for unit-diagonal sweeps)
+  const int* lev_ptr = nullptr;   // nlev + 1: level sets (refactorisation schedule)
+  const int* rows = nullptr;      // nx: row per level-ordered slot
+  // condensation schedule: kSweepMeta ints per step {step index in
+  // DevNet::lblk, log2 lanes per row, 0, 0}, then the idle step
+  int nstep = 0;
+  const int* meta = nullptr;
   int unit = 0;                   // 1: unit diagonal (L and L^T sweeps)
-  int nnz = 0;
 };
 
 struct DevNet {
@@ -59,9 +49,18 @@ struct DevNet {
   const int *k_ptr, *k_col;
   const int *kg_hl_ptr, *kg_hl_idx, *kg_ata_ptr, *kg_a1, *kg_a2, *kg_row, *kg_diag;
   const int* sig_map;
-  const int *kb_base, *kb_len, *kell_col, *kell_pos;
-  double* kell_val;
-  int kell_n, kb_n;
+  // Condensation records for the launch width (rh::CondenseRecords): sweep
+  // steps (kStepDoubles each; entry values and reciprocal pivots transcribed
+  // after every refactorisation: lblk[tr_dst] = lu[tr_src], lblk[trd_dst] =
+  // 1/lu[trd_src]) and the K / G_u^T record streams (kBatchDoubles per
+  // batch; block ends per lane; destinations of the K entries, rt terms and
+  // G_u entries); H position of each w row, control at each G position.
+  double* lblk;
+  int tr_n, trd_n;
+  const int *tr_dst, *tr_src, *trd_dst, *trd_src;
+  double *kstr, *gstr;
+  int kst_nbat, kb_n, gst_nbat, gt_nb;
+  const int *kb_end, *gt_end, *kdst, *krt_dst, *gdst, *hpos, *grow;
   // wave-resident refactorisation (rw_ok): task records, per-lane data
   int rw_ok, rw_nnz_u, rw_nlev, rw_ntask, rw_lane_pad;
   const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane, *rw_ustart;
@@ -122,9 +121,11 @@ hipError_t launch_eval_objective(const DevNet& d, const double* u, double* f, hi
 int max_lds_bytes();
 // LDS one row of the refactorisation stages (row, U sources, pivots, schedule).
 size_t refactor_lds_per_row(const DevNet& d);
-// LDS of the level metadata the condensation kernel stages (all four sweeps).
-size_t condense_meta_bytes(const DevNet& d);
-// Allow dynamic LDS up to `bytes` for the LDS-resident condensation kernels.
-void prepare_lds_kernels(size_t bytes);
+// Dynamic LDS of one condensation work-group: the staged step metadata and
+// stream block ends, after the panels P and H (2 nw + 1 rows of `width`
+// doubles) when those live in LDS.
+size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels);
+// Allow the LDS-staged kernels dynamic LDS up to the device's maximum.
+void prepare_lds_kernels();
 
 }  // namespace rh

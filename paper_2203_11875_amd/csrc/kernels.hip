@@ -164,13 +164,8 @@ __global__ void __launch_bounds__(kBlock) k_gather(int n, const int* __restrict_
 __global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* sig_x,
                                                       const double* sig_u,
                                                       const double* sig_s) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d.kell_n) return;
-  const int e = d.kell_pos[t];
-  if (e < 0) {
-    d.kell_val[t] = 0.0;
-    return;
-  }
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d.nnz_k) return;
   double acc = 0.0;
   for (int q = d.kg_hl_ptr[e]; q < d.kg_hl_ptr[e + 1]; ++q) acc += d.hl[d.kg_hl_idx[q]];
   const double* av = d.dst + d.d_a;
@@ -184,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* s
     const int sm = d.sig_map[v];
     acc += (sm < d.nu ? sig_u[sm] : sig_x[sm - d.nu]) + d.k_cdiag[v];
   }
-  d.kell_val[t] = acc;
+  d.kstr[d.kdst[e]] = acc;
 }
 
 __global__ void k_fill_int(int* p, int n, int v) {
@@ -259,26 +254,28 @@ __global__ void __launch_bounds__(kRefThreads) k_refactor(DevNet d) {
   }
 }
 
-// Copy the refactorised values into the four sweep layouts (level-ordered
-// entries, reciprocal pivots).
+// Copy the refactorised values into the sweeps' lane blocks (entries,
+// reciprocal pivots of the writing lanes) and the G_u values into the G_u^T
+// record stream.
 __global__ void __launch_bounds__(kBlock) k_transcribe(DevNet d) {
   const double* lu = d.dst + d.d_lu;
+  const double* gu = d.dst + d.d_gu;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  const DevSweep* sw[4] = {&d.sl, &d.su, &d.sut, &d.slt};
-  for (int s = 0; s < 4; ++s) {
-    const DevSweep& w = *sw[s];
-    for (int t = tid; t < w.nnz; t += stride) w.val[t] = lu[w.src[t]];
-    for (int t = tid; t < w.ell_n; t += stride) w.ell_val[t] = w.ell_src[t] >= 0 ? lu[w.ell_src[t]] : 0.0;
-    if (!w.unit)
-      for (int t = tid; t < d.nx; t += stride) w.dinv[t] = 1.0 / lu[w.diag_src[t]];
-  }
+  for (int t = tid; t < d.tr_n; t += stride) d.lblk[d.tr_dst[t]] = lu[d.tr_src[t]];
+  for (int t = tid; t < d.trd_n; t += stride) d.lblk[d.trd_dst[t]] = 1.0 / lu[d.trd_src[t]];
+  for (int e = tid; e < d.nnz_gu; e += stride) d.gstr[d.gdst[e]] = gu[e];
 }
 
 // rt = [r1 ; r2] + A^T (Sigma_s r5 - r3), in w = [u ; x internal] order.
 __global__ void __launch_bounds__(kBlock) k_rtilde(DevNet d, const double* r, const double* sig_s) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= d.nw) return;
+  if (!r) {
+    d.rt[v] = 0.0;
+    d.kstr[d.krt_dst[v]] = 0.0;
+    return;
+  }
   const double* r1 = r;
   const double* r2 = r + d.nu;
   const double* r3 = r2 + d.nx;
@@ -290,6 +287,7 @@ __global__ void __launch_bounds__(kBlock) k_rtilde(DevNet d, const double* r, co
     acc += av[d.acsc_from[e]] * (sig_s[j] * r5[j] - r3[j]);
   }
   d.rt[v] = acc;
+  d.kstr[d.krt_dst[v]] = acc;   // the rt term of K row v in the condensation's stream
 }
 
 // ------------------------------------------------- condensation pipeline
@@ -536,124 +534,182 @@ __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
   }
 }
 
-// Level metadata of one sweep, staged in LDS at kernel start:
-// [slot0, rows, base, len, log2(lanes)] per level.
-constexpr int kMeta = 5;
+// The condensation runs one wave per work-group (one thread per lane of a
+// sweep step or of a row block).
+constexpr int kCondThreads = kSweepThreads;
+static_assert(kCondThreads == 64 && kKRowBlock == kCondThreads, "one wave per work-group");
 
-__device__ __forceinline__ void stage_meta(const DevSweep& s, int* meta) {
-  for (int l = threadIdx.x; l < s.nlev; l += blockDim.x) {
-    meta[kMeta * l + 0] = s.lev_ptr[l];
-    meta[kMeta * l + 1] = s.lev_ptr[l + 1] - s.lev_ptr[l];
-    meta[kMeta * l + 2] = s.lev_base[l];
-    meta[kMeta * l + 3] = s.lev_len[l];
-    meta[kMeta * l + 4] = __ffs(s.lev_lanes[l]) - 1;
-  }
+// Ordering of panel accesses between the steps of one wave. A wave's LDS
+// operations complete in issue order, so for LDS panels a wavefront-scope
+// fence (no instruction; it keeps the compiler from moving accesses across)
+// is enough; panels in global memory take a workgroup-scope fence, which
+// waits for the stores.
+template <bool LDS>
+__device__ __forceinline__ void panel_sync() {
+  if (LDS)
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  else
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 }
 
-// Entries of one level that a thread loads ahead of time: up to PF entries
-// of its first row, that row's index and its reciprocal pivot.
-constexpr int PF = 4;
-struct LevelFetch {
-  int col[PF];
-  double val[PF];
-  int row;
-  double dinv;
+// Step metadata of one sweep, staged in LDS at kernel start:
+// {step index, log2 lanes per row, 0, 0} per step, then the idle step (every
+// lane on padding that writes nothing).
+__device__ __forceinline__ void stage_meta(const DevSweep& s, int4* meta) {
+  const int4* src = reinterpret_cast<const int4*>(s.meta);
+  for (int i = threadIdx.x; i <= s.nstep; i += blockDim.x) meta[i] = src[i];
+}
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// What a lane loads ahead of time for one step: its kSweepPF values and
+// panel offsets, reciprocal pivot, row offset and writer flag (every loaded
+// dword is used, so that no register of an in-flight load is reused early,
+// which would make the compiler wait for the load), and the step's uniform
+// shape.
+constexpr int PF = kSweepPF;
+static_assert(PF == 8 && kStepDoubles == 7 * 128, "a step = 7 chunks of 64 x 16 bytes");
+struct StepFetch {
+  f64x2 v[PF / 2];
+  u32x4 o[2];
+  f64x2 piv;
+  int ls;
 };
 
-__device__ __forceinline__ void fetch_level(const DevSweep& s, const int* m, LevelFetch& f) {
-  // branch-free (addresses clamped, values masked) so that the number of
-  // loads in flight is the same on every path and waits stay exact
-  const int R = m[1], ls = m[4];
-  const int g = threadIdx.x >> ls, lane = threadIdx.x & ((1 << ls) - 1);
-  const bool live = g < R;
-  const int base = m[2], Lm = m[3];
+// Seven 16-byte loads, each contiguous over the wave (chunk k of the step at
+// k * kChunk doubles, lane t at 2 t).
+__device__ __forceinline__ void fetch_step(const double* lblk, const int4 m, StepFetch& f) {
+  const f64x2* b = reinterpret_cast<const f64x2*>(lblk + (size_t)m.x * kStepDoubles) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < PF / 2; ++k) f.v[k] = b[k * (kChunk / 2)];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) f.o[k] = reinterpret_cast<const u32x4*>(b + (4 + k) * (kChunk / 2))[0];
+  f.piv = b[6 * (kChunk / 2)];
+  f.ls = m.y;
+}
+
+// v + (v of lane `lane - SH` in the same 16-lane row; 0 at the row start)
+template <int SH>
+__device__ __forceinline__ double add_shr(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x110 + SH, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x110 + SH, 0xF, 0xF, true);
+  return v + __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                    (unsigned long long)(unsigned)lo));
+}
+// v + (lane 15 of the previous 16-lane row) in rows 1 and 3 (CTRL 0x142,
+// rows 0xA), or + lane 31 in rows 2 and 3 (CTRL 0x143, rows 0xC).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double add_bcast(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROWS, 0xF, false);
+  return v + __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                    (unsigned long long)(unsigned)lo));
+}
+
+// Panel access by byte offset. LDS panels start at LDS address 0 (the
+// condensation kernel has no static LDS, so its dynamic LDS begins there;
+// the kernel checks this at start), so the offset is the address itself and
+// costs no instruction; global panels use pb as a scalar base.
+typedef __attribute__((address_space(3))) double lds_double;
+template <bool LDS>
+__device__ __forceinline__ double panel_ld(const char* pb, unsigned off) {
+  if (LDS) return *reinterpret_cast<const lds_double*>((size_t)off);
+  return *reinterpret_cast<const double*>(pb + off);
+}
+template <bool LDS>
+__device__ __forceinline__ void panel_st(char* pb, unsigned off, double v) {
+  if (LDS)
+    *reinterpret_cast<lds_double*>((size_t)off) = v;
+  else
+    *reinterpret_cast<double*>(pb + off) = v;
+}
+
+// One step of a triangular sweep over the panels (byte offsets from pb; W
+// columns of a row contiguous). The rows of a step are independent. Each row
+// is taken by S = 2^ls consecutive lanes; a lane accumulates its entries for
+// all W columns and the group sums with DPP shifts and row broadcasts, which
+// leaves the row total in the group's last lane, the one that writes. The
+// summation order depends only on the schedule, so results repeat bitwise and
+// do not depend on W.
+template <int W, bool LDS>
+__device__ __forceinline__ void sweep_step(const StepFetch& f, char* pb) {
+  double acc[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
 #pragma unroll
   for (int j = 0; j < PF; ++j) {
-    const int k = lane + (j << ls);
-    const bool ok = live && k < Lm;
-    const int idx = ok ? base + k * R + g : 0;
-    const int c = s.ell_col[idx];
-    const double v = s.ell_val[idx];
-    f.col[j] = ok ? c : 0;
-    f.val[j] = ok ? v : 0.0;
+    const double v = f.v[j / 2][j % 2];
+    const unsigned o = f.o[j / 4][j % 4];
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] = fma(v, panel_ld<LDS>(pb, o + 8 * c), acc[c]);
   }
-  const int q = live ? m[0] + g : 0;
-  f.row = s.rows[q];
-  f.dinv = s.dinv[q];
+  // row offset and writer flag (through a scalar: a bit cast of a vector
+  // element subscript reads element 0)
+  const double piv1 = f.piv.y;
+  const unsigned long long rw = __builtin_bit_cast(unsigned long long, piv1);
+  const unsigned row = unsigned(rw);
+  double xr[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) xr[c] = panel_ld<LDS>(pb, row + 8 * c);
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    if (f.ls >= 1) acc[c] = add_shr<1>(acc[c]);
+    if (f.ls >= 2) acc[c] = add_shr<2>(acc[c]);
+    if (f.ls >= 3) acc[c] = add_shr<4>(acc[c]);
+    if (f.ls >= 4) acc[c] = add_shr<8>(acc[c]);
+    if (f.ls >= 5) acc[c] = add_bcast<0x142, 0xA>(acc[c]);
+    if (f.ls >= 6) acc[c] = add_bcast<0x143, 0xC>(acc[c]);
+  }
+  if (rw >> 32) {
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      panel_st<LDS>(pb, row + 8 * c, (xr[c] - acc[c]) * f.piv.x);
+  }
+  panel_sync<LDS>();
 }
 
-// One level of a triangular sweep over a panel X (rows x W, the W columns of
-// a row contiguous). Rows of a level are independent. Each row is taken by a
-// group of 2^ls lanes (chosen per level from its longest row); each lane
-// accumulates a strided share of the row's entries for all W columns, and the
-// group reduces with cross-lane shuffles. The summation order depends only on
-// the level structure, so results repeat bitwise and do not depend on W.
-template <int W, bool LDS>
-__device__ __forceinline__ void sweep_level(const DevSweep& s, const int* m, const LevelFetch& f,
-                                            double* X) {
-  const int s0 = m[0], R = m[1], base = m[2], Lm = m[3], ls = m[4];
-  if (Lm == 0 && s.unit) return;    // nothing changes in this level: no barrier needed
-  const int S = 1 << ls;
-  const int g = threadIdx.x >> ls, lane = threadIdx.x & (S - 1), G = blockDim.x >> ls;
-  for (int r = g; r < R; r += G) {
-    double acc[W];
-#pragma unroll
-    for (int c = 0; c < W; ++c) acc[c] = 0.0;
-    int row, k0;
-    double dv;
-    if (r == g) {
-#pragma unroll
-      for (int j = 0; j < PF; ++j) {
-        const double* xc = X + f.col[j] * W;
-#pragma unroll
-        for (int c = 0; c < W; ++c) acc[c] = fma(f.val[j], xc[c], acc[c]);
-      }
-      row = f.row;
-      dv = f.dinv;
-      k0 = lane + PF * S;
-    } else {
-      row = s.rows[s0 + r];
-      dv = s.dinv[s0 + r];
-      k0 = lane;
-    }
-    for (int k = k0; k < Lm; k += S) {
-      const int idx = base + k * R + r;
-      const double v = s.ell_val[idx];
-      const double* xc = X + s.ell_col[idx] * W;
-#pragma unroll
-      for (int c = 0; c < W; ++c) acc[c] = fma(v, xc[c], acc[c]);
-    }
-    for (int off = S >> 1; off > 0; off >>= 1)
-#pragma unroll
-      for (int c = 0; c < W; ++c) acc[c] += __shfl_xor(acc[c], off);
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) {
-        X[row * W + c] = (X[row * W + c] - acc[c]) * dv;
-      }
-    }
-  }
-  block_sync<LDS>();
-}
+// A whole sweep, step by step. A step's lane block needs only the step's
+// metadata (staged in LDS, read through lane registers), so the block of
+// step k is requested while step k - kDepth + 1 is computed (kDepth register
+// sets used in turn). Every pass of the loop requests one step and computes one:
+// before the first step and after the last the sets hold the sweep's idle
+// step (metadata entry n: every lane on a padding block that writes nothing),
+// so the computation is unconditional and the compiler has no branch to sink
+// a load into; and every load pending at the loop's back edge was issued in
+// the same order on every path, so its waits stay exact (a step waits for its
+// own block, never for the later steps').
+constexpr int kDepth = 4;
 
-// A whole sweep, level by level. Entries come from the padded per-level
-// layout, whose addresses need no row pointers, so the loads of level l+1
-// are issued before level l is computed (two register sets used in turn, so
-// the wait for one level's loads never waits for the next level's).
 template <int W, bool LDS>
-__device__ __forceinline__ void sweep(const DevSweep& s, const int* meta, double* X,
-                                      long long* lt = nullptr) {
-  LevelFetch a, b;
-  const int n = s.nlev;
-  fetch_level(s, meta, a);
-  for (int lev = 0; lev < n; lev += 2) {
-    if (lev + 1 < n) fetch_level(s, meta + kMeta * (lev + 1), b);
-    sweep_level<W, LDS>(s, meta + kMeta * lev, a, X);
-    if (lt && threadIdx.x == 0) lt[lev] = wall_clock64();
-    if (lev + 1 >= n) break;
-    if (lev + 2 < n) fetch_level(s, meta + kMeta * (lev + 2), a);
-    sweep_level<W, LDS>(s, meta + kMeta * (lev + 1), b, X);
-    if (lt && threadIdx.x == 0) lt[lev + 1] = wall_clock64();
+__device__ __forceinline__ void sweep(const DevSweep& s, const double* lblk, const int4* meta,
+                                      char* pb) {
+  const int n = s.nstep;
+  if (n == 0) return;
+  StepFetch f[kDepth];
+  const int4 idle = meta[n];
+#pragma unroll
+  for (int j = 0; j < kDepth; ++j) fetch_step(lblk, idle, f[j]);
+  // metadata in chunks of 64 steps: lane l holds step c + l (the idle step
+  // past the end), a step's entry is read into scalar registers with lane
+  // reads, so no memory latency falls inside the step loop
+  for (int c = 0; c < n + kDepth - 1; c += 64) {
+    const int4 mv = meta[min(c + (int)threadIdx.x, n)];
+    // wait for it here (lgkmcnt(0)), once per chunk, so that no wait for it is
+    // left at the head of the step loop
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    const int kend = min(c + 64, n + kDepth - 1);
+    for (int k0 = c; k0 < kend; k0 += kDepth) {
+#pragma unroll
+      for (int j = 0; j < kDepth; ++j) {
+        const int l = max(min(k0 + j, n) - c, 0);
+        const int4 m{__builtin_amdgcn_readlane(mv.x, l), __builtin_amdgcn_readlane(mv.y, l), 0, 0};
+        fetch_step(lblk, m, f[j]);
+        sweep_step<W, LDS>(f[(j + 1) % kDepth], pb);
+      }
+    }
   }
 }
 
@@ -664,33 +720,88 @@ __device__ __forceinline__ void tick(const DevNet& d, int k) {
   if (d.trace && blockIdx.x == 0 && threadIdx.x == 0) d.trace[k] = wall_clock64();
 }
 
-// Row kKRowBlock * bk + tid of H = K [V ; Z] (+ rt for the right-hand-side /
-// recovery column), from the padded row-block layout of K.
-template <int W>
-__device__ __forceinline__ void hvp_row(const DevNet& d, const double* P, int bk, int tid,
-                                        int jc0, int mode, double (&h)[W]) {
-  const int v = bk * kKRowBlock + tid;
-  const int base = d.kb_base[bk], len = d.kb_len[bk];
+// Row-blocked record stream (one wave): lane t owns stream position
+// kKRowBlock * b + t of every block b; its records, kStreamBatch per batch
+// (values, then panel byte offsets from pb; each 16-byte chunk contiguous
+// over the wave), follow one another, block b covering records
+// [end[b-1], end[b]). Per record acc += value * panel[offset]; at the end of
+// a block flush(b, acc) and restart. Batch k is requested while batch
+// k - kStreamDepth + 1 is computed (no prologue, as in the sweeps). end
+// (LDS) and nblk are uniform.
+constexpr int kStreamDepth = 4;
+static_assert(kStreamBatch == 8 && kBatchDoubles == 6 * 128, "batch = 4 + 2 chunks of 64 x 16 bytes");
+template <int W, bool LDS, class Flush>
+__device__ __forceinline__ void row_stream(const double* str, int nbat, const int* end_lds, int nblk,
+                                           const char* pb, Flush&& flush) {
+  // block ends through lane registers (refilled every 64 blocks)
+  int ev = 0, ebase = -64;
+  auto end = [&](int b) {
+    if (b - ebase >= 64) {
+      ebase = b;
+      ev = end_lds[min(b + (int)threadIdx.x, nblk - 1)];
+    }
+    return __builtin_amdgcn_readlane(ev, b - ebase);
+  };
+  const f64x2* lane = reinterpret_cast<const f64x2*>(str) + threadIdx.x;
   double acc[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) acc[c] = 0.0;
-#pragma unroll 8
-  for (int k = 0; k < len; ++k) {
-    const int idx = base + k * kKRowBlock + tid;
-    const double kv = d.kell_val[idx];
-    const double* pc = P + d.kell_col[idx] * W;
-#pragma unroll
-    for (int c = 0; c < W; ++c) acc[c] = fma(kv, pc[c], acc[c]);
+  int b = 0, e = nblk > 0 ? end(0) : 0;
+  while (b < nblk && e == 0) {   // blocks without records
+    flush(b, acc);
+    ++b;
+    e = b < nblk ? end(b) : 0x7fffffff;
   }
-  const double rt = (v < d.nw) ? d.rt[v] : 0.0;
+  f64x2 bv[kStreamDepth][kStreamBatch / 2];
+  u32x4 bo[kStreamDepth][2];
 #pragma unroll
-  for (int c = 0; c < W; ++c) {
-    const int j = jc0 + c;
-    h[c] = (mode == MODE_RECOVER || j == d.nu) ? acc[c] + rt : acc[c];
+  for (int j = 0; j < kStreamDepth; ++j) {
+#pragma unroll
+    for (int k = 0; k < kStreamBatch / 2; ++k) bv[j][k] = f64x2{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) bo[j][k] = u32x4{0u, 0u, 0u, 0u};
+  }
+  // every pass requests one batch and computes one (zero records before the
+  // first batch, repeats of the last after it: no flush falls there)
+  for (int i0 = 0; i0 < nbat + kStreamDepth - 1; i0 += kStreamDepth) {
+#pragma unroll
+    for (int j = 0; j < kStreamDepth; ++j) {
+      const f64x2* q = lane + (size_t)min(i0 + j, nbat - 1) * (kBatchDoubles / 2);
+#pragma unroll
+      for (int k = 0; k < kStreamBatch / 2; ++k) bv[j][k] = q[k * (kChunk / 2)];
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        bo[j][k] = reinterpret_cast<const u32x4*>(q + (4 + k) * (kChunk / 2))[0];
+      const int cb = i0 + j - (kStreamDepth - 1);
+      const int jj = (j + 1) % kStreamDepth;
+      // the batch's panel reads first: a flush writes only the other panel
+      // region (H for K [V; Z], P for G_u^T Psi), so none of them depends on
+      // a flush, and all are in flight together
+      double x[kStreamBatch][W];
+#pragma unroll
+      for (int r = 0; r < kStreamBatch; ++r)
+#pragma unroll
+        for (int c = 0; c < W; ++c) x[r][c] = panel_ld<LDS>(pb, bo[jj][r / 4][r % 4] + 8 * c);
+#pragma unroll
+      for (int r = 0; r < kStreamBatch; ++r) {
+        const int p = cb * kStreamBatch + r;
+        const double v = bv[jj][r / 2][r % 2];
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[c] = fma(v, x[r][c], acc[c]);
+        while (p + 1 == e) {
+          flush(b, acc);
+#pragma unroll
+          for (int c = 0; c < W; ++c) acc[c] = 0.0;
+          ++b;
+          e = b < nblk ? end(b) : 0x7fffffff;
+        }
+      }
+    }
   }
 }
 
-// Columns [col0 + blockIdx.x * W, ...) of the condensed matrix (Section 3.3):
+// Columns [col0 + blockIdx.x * W, ...) of the condensed matrix (Section 3.3),
+// one wave per work-group:
 //   Z   = -G_x^{-1} G_u V          (L then U sweep; V = identity columns)
 //   H   =  K [V ; Z]               (one sparse product over all nu + nx rows)
 //   Psi =  G_x^{-T} H_x            (U^T then L^T sweep)
@@ -698,36 +809,51 @@ __device__ __forceinline__ void hvp_row(const DevNet& d, const double* P, int bk
 // Column nu (if requested) is the condensed right-hand side: V = 0, Z = -G_x^{-1} r4,
 // H += rt, and rhs = -out. In MODE_RECOVER (one column): V = p_u,
 // Z = -G_x^{-1}(r4 + G_u p_u) = p_x, H += rt, Psi = -p_lambda.
+// Panels (LDS or global, W doubles per row): P = [V; Z; indicator] (nw + 1
+// rows; the indicator row is 1 in the right-hand-side / recovery column and
+// multiplies each K row's rt term), then H (nw rows, in K-stream order:
+// w row v at hpos[v]).
 template <int W, bool LDS, int mode>
-__global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col_end,
-                                                    const double* r, const double* vin,
-                                                    double* K, long ldk, double* rhs,
-                                                    double* p_out) {
+__global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, int col_end,
+                                                          const double* r, const double* vin,
+                                                          double* K, long ldk, double* rhs,
+                                                          double* p_out) {
   extern __shared__ double panel_lds[];
+  if (LDS && (size_t)(lds_double*)panel_lds != 0) {   // the records assume LDS address 0
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.status[4] = 1;
+    return;
+  }
   const int nw = d.nw, nu = d.nu, nx = d.nx;
-  // LDS: one panel P (the Hessian product is held in registers and written
-  // back over it); global: two panels P and H per work-group
-  double* P = LDS ? panel_lds : d.panel + (size_t)blockIdx.x * 2 * nw * W;
-  int* meta = reinterpret_cast<int*>(panel_lds + (LDS ? (size_t)nw * W : 0));
-  int* m_sl = meta;
-  int* m_su = m_sl + kMeta * d.sl.nlev;
-  int* m_sut = m_su + kMeta * d.su.nlev;
-  int* m_slt = m_sut + kMeta * d.sut.nlev;
+  double* P = LDS ? panel_lds : d.panel + (size_t)blockIdx.x * (2 * nw + 1) * W;
+  double* H = P + (size_t)(nw + 1) * W;
+  char* pb = reinterpret_cast<char*>(P);
+  // step metadata of the four sweeps (with their idle steps) and the block
+  // ends of the two record streams, staged in LDS
+  int4* m_sl = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(2 * nw + 1) * W : 0));
+  int4* m_su = m_sl + d.sl.nstep + 1;
+  int4* m_sut = m_su + d.su.nstep + 1;
+  int4* m_slt = m_sut + d.sut.nstep + 1;
+  int* kb_end = reinterpret_cast<int*>(m_slt + d.slt.nstep + 1);
+  int* gt_end = kb_end + d.kb_n;
   stage_meta(d.sl, m_sl);
   stage_meta(d.su, m_su);
   stage_meta(d.sut, m_sut);
   stage_meta(d.slt, m_slt);
+  for (int i = threadIdx.x; i < d.kb_n; i += kCondThreads) kb_end[i] = d.kb_end[i];
+  for (int i = threadIdx.x; i < d.gt_nb; i += kCondThreads) gt_end[i] = d.gt_end[i];
+  panel_sync<LDS>();
   tick(d, 0);
-  double* H = LDS ? P : P + (size_t)nw * W;
   const int jc0 = col0 + blockIdx.x * W;
-  const int tid = threadIdx.x, T = blockDim.x;
+  const int tid = threadIdx.x, T = kCondThreads;
   const double* gu = d.dst + d.d_gu;
   const double* r4 = r ? r + d.nu + d.nx + d.m : nullptr;
-  for (int i = tid; i < nw * W; i += T) P[i] = 0.0;
-  __syncthreads();
+  for (int i = tid; i < (nw + 1) * W; i += T) P[i] = 0.0;
+  panel_sync<LDS>();
   for (int c = 0; c < W; ++c) {
     const int j = jc0 + c;
     if (j >= col_end) break;
+    if (mode == MODE_RECOVER || j == nu)
+      if (tid == 0) P[nw * W + c] = 1.0;
     if (mode == MODE_RECOVER) {
       for (int v = tid; v < nu; v += T) P[v * W + c] = vin[v];
       for (int i = tid; i < nx; i += T) {
@@ -743,11 +869,11 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
       for (int i = tid; i < nx; i += T) P[(nu + i) * W + c] = -r4[d.perm[i]];
     }
   }
-  __syncthreads();
+  panel_sync<LDS>();
   tick(d, 1);
-  sweep<W, LDS>(d.sl, m_sl, P + nu * W, (d.trace && blockIdx.x == 0) ? d.trace + 16 : nullptr);
+  sweep<W, LDS>(d.sl, d.lblk, m_sl, pb);
   tick(d, 2);
-  sweep<W, LDS>(d.su, m_su, P + nu * W);
+  sweep<W, LDS>(d.su, d.lblk, m_su, pb);
   tick(d, 3);
   if (mode == MODE_COLUMNS) {
     // keep Z = S e_j (and d for the right-hand-side column) for the recovery
@@ -770,74 +896,51 @@ __global__ void __launch_bounds__(kBlock) k_condense(DevNet d, int col0, int col
       p_out[v] = vin[v];
     }
   }
-  // H = K [V ; Z]: thread t takes row kKRowBlock * b + t of every row block.
-  // With the panel in LDS the rows are kept in registers until every thread
-  // has read P, then written over it.
-  if (LDS) {
-    double hreg[kMaxRowBlocks][W];
+  // H = K [V ; Z] (+ rt through the indicator row), row block by row block,
+  // H rows in stream order
+  row_stream<W, LDS>(d.kstr, d.kst_nbat, kb_end, d.kb_n, pb,
+                     [&](int b, const double(&acc)[W]) {
+                       const int p = b * kKRowBlock + tid;
+                       if (p < nw)
 #pragma unroll
-    for (int bk = 0; bk < kMaxRowBlocks; ++bk) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) hreg[bk][c] = 0.0;
-      if (bk < d.kb_n) hvp_row<W>(d, P, bk, tid, jc0, mode, hreg[bk]);
-    }
-    block_sync<LDS>();
-#pragma unroll
-    for (int bk = 0; bk < kMaxRowBlocks; ++bk) {
-      const int v = bk * kKRowBlock + tid;
-      if (bk < d.kb_n && v < nw)
-#pragma unroll
-        for (int c = 0; c < W; ++c) H[v * W + c] = hreg[bk][c];
-    }
-    block_sync<LDS>();
-  } else {
-    for (int bk = 0; bk < d.kb_n; ++bk) {
-      double h[W];
-      hvp_row<W>(d, P, bk, tid, jc0, mode, h);
-      const int v = bk * kKRowBlock + tid;
-      if (v < nw)
-#pragma unroll
-        for (int c = 0; c < W; ++c) H[v * W + c] = h[c];
-    }
-    block_sync<LDS>();
-  }
+                         for (int c = 0; c < W; ++c) H[p * W + c] = acc[c];
+                     });
+  panel_sync<LDS>();
   tick(d, 4);
-  sweep<W, LDS>(d.sut, m_sut, H + nu * W);
+  sweep<W, LDS>(d.sut, d.lblk, m_sut, pb);
   tick(d, 5);
-  sweep<W, LDS>(d.slt, m_slt, H + nu * W);
+  sweep<W, LDS>(d.slt, d.lblk, m_slt, pb);
   tick(d, 6);
   if (mode == MODE_COLUMNS) {
     for (int c = 0; c < W; ++c) {
       const int j = jc0 + c;
       if (j >= col_end) break;
       double* pc = d.psicols + (size_t)j * nx;
-      for (int i = tid; i < nx; i += T) pc[i] = H[(nu + i) * W + c];
+      for (int i = tid; i < nx; i += T) pc[i] = H[d.hpos[nu + i] * W + c];
     }
   }
   if (mode == MODE_RECOVER) {
     double* plam = p_out + nu + nx + d.m;
-    for (int i = tid; i < nx; i += T) plam[d.perm[i]] = -H[(nu + i) * W];
+    for (int i = tid; i < nx; i += T) plam[d.perm[i]] = -H[d.hpos[nu + i] * W];
     return;
   }
-  for (int q = tid; q < nu; q += T) {
-    double acc[W];
+  // out = H_u - G_u^T Psi: the stream sums G_u^T Psi - H_u; written over the
+  // (no longer needed) V rows of P in stream order, then to K / rhs
+  row_stream<W, LDS>(d.gstr, d.gst_nbat, gt_end, d.gt_nb, pb,
+                     [&](int b, const double(&acc)[W]) {
+                       const int p = b * kKRowBlock + tid;
+                       if (p < nu)
 #pragma unroll
-    for (int c = 0; c < W; ++c) acc[c] = H[q * W + c];
-    for (int e = d.gucsc_ptr[q]; e < d.gucsc_ptr[q + 1]; ++e) {
-      const double gv = gu[d.gucsc_from[e]];
-      const double* hc = H + (nu + d.gucsc_row[e]) * W;
-#pragma unroll
-      for (int c = 0; c < W; ++c) acc[c] = fma(-gv, hc[c], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-      const int j = jc0 + c;
-      if (j >= col_end) break;
-      if (j < nu)
-        K[(size_t)j * ldk + q] = acc[c];
-      else
-        rhs[q] = -acc[c];
-    }
+                         for (int c = 0; c < W; ++c) P[p * W + c] = -acc[c];
+                     });
+  panel_sync<LDS>();
+  for (int c = 0; c < W; ++c) {
+    const int j = jc0 + c;
+    if (j >= col_end) break;
+    if (j < nu)
+      for (int p = tid; p < nu; p += T) K[(size_t)j * ldk + d.grow[p]] = P[p * W + c];
+    else
+      for (int p = tid; p < nu; p += T) rhs[d.grow[p]] = -P[p * W + c];
   }
   tick(d, 7);
 }
@@ -1298,22 +1401,19 @@ __global__ void __launch_bounds__(NB * NB) k_chol_backward(const double* lrow, i
   for (int i = tid; i < n; i += NB * NB) y[i] = ys[i];
 }
 
-}  // namespace
-size_t condense_meta_bytes(const DevNet& d);
-namespace {
 
 template <int W, bool LDS>
 hipError_t launch_condense_t(const DevNet& d, int col0, int ncols, int mode, const double* r,
                              const double* vin, double* K, long ldk, double* rhs, double* p,
                              hipStream_t st) {
   const int nblk = (ncols + W - 1) / W;
-  const size_t lds = (LDS ? (size_t)d.nw * W * sizeof(double) : 0) + condense_meta_bytes(d);
+  const size_t lds = condense_lds_bytes(d, W, LDS);
   if (mode == MODE_RECOVER)
-    hipLaunchKernelGGL((k_condense<W, LDS, MODE_RECOVER>), dim3(nblk), dim3(kBlock), lds, st, d,
-                       col0, col0 + ncols, r, vin, K, ldk, rhs, p);
+    hipLaunchKernelGGL((k_condense<W, LDS, MODE_RECOVER>), dim3(nblk), dim3(kCondThreads), lds,
+                       st, d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
   else
-    hipLaunchKernelGGL((k_condense<W, LDS, MODE_COLUMNS>), dim3(nblk), dim3(kBlock), lds, st, d,
-                       col0, col0 + ncols, r, vin, K, ldk, rhs, p);
+    hipLaunchKernelGGL((k_condense<W, LDS, MODE_COLUMNS>), dim3(nblk), dim3(kCondThreads), lds,
+                       st, d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
   return hipGetLastError();
 }
 
@@ -1335,11 +1435,15 @@ inline int cdiv(long a, long b) { return int((a + b - 1) / b); }
 
 }  // namespace
 
-size_t condense_meta_bytes(const DevNet& d) {
-  return sizeof(int) * kMeta * (size_t)(d.sl.nlev + d.su.nlev + d.sut.nlev + d.slt.nlev);
+size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels) {
+  static_assert(kSweepMeta == 4, "one int4 of metadata per step");
+  const size_t meta = sizeof(int) * (kSweepMeta * (size_t)(d.sl.nstep + d.su.nstep + d.sut.nstep +
+                                                           d.slt.nstep + 4) +
+                                     (size_t)d.kb_n + (size_t)d.gt_nb);
+  return (lds_panels ? (size_t)(2 * d.nw + 1) * width * sizeof(double) : 0) + meta;
 }
 
-void prepare_lds_kernels(size_t bytes) {
+void prepare_lds_kernels() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor_wave),
@@ -1363,9 +1467,9 @@ void prepare_lds_kernels(size_t bytes) {
       reinterpret_cast<const void*>(&k_condense<8, false, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<1, false, MODE_RECOVER>)};
   for (const void* f : fns)
-    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   for (const void* f : gfns)
-    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   (void)hipGetLastError();
 }
 
@@ -1389,7 +1493,7 @@ hipError_t launch_eval(const DevNet& d, const double* x, const double* u, const 
 
 hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double* sig_u,
                              const double* sig_s, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble_k, dim3(cdiv(d.kell_n, kBlock)), dim3(kBlock), 0, st, d, sig_x,
+  hipLaunchKernelGGL(k_assemble_k, dim3(cdiv(d.nnz_k, kBlock)), dim3(kBlock), 0, st, d, sig_x,
                      sig_u, sig_s);
   return hipGetLastError();
 }
@@ -1423,8 +1527,7 @@ hipError_t launch_condense(const DevNet& d, int col0, int ncols, int width, bool
 
 hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, double* p,
                           hipStream_t st) {
-  const bool lds = d.kb_n <= kMaxRowBlocks &&
-      (size_t)d.nw * sizeof(double) + condense_meta_bytes(d) <= (size_t)max_lds_bytes();
+  const bool lds = condense_lds_bytes(d, 1, true) <= (size_t)max_lds_bytes();
   if (lds)
     return launch_condense_t<1, true>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
   return launch_condense_t<1, false>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);

@@ -124,30 +124,39 @@ rh_status alloc(rh_net* n, size_t count, T** out) {
 
 rh_status upload_sweep(rh_net* n, const rh::Sweep& s, rh::DevSweep& d) {
   d.nlev = s.nlev;
-  d.nnz = int(s.col.size());
   RH_TRY(upload(n, s.lev_ptr, &d.lev_ptr));
   RH_TRY(upload(n, s.rows, &d.rows));
-  RH_TRY(upload(n, s.ptr, &d.ptr));
-  RH_TRY(upload(n, s.col, &d.col));
-  RH_TRY(upload(n, s.src, &d.src));
-  RH_TRY(upload(n, s.lev_lanes, &d.lev_lanes));
-  RH_TRY(upload(n, s.lev_base, &d.lev_base));
-  RH_TRY(upload(n, s.lev_len, &d.lev_len));
-  RH_TRY(upload(n, s.ell_col, &d.ell_col));
-  RH_TRY(upload(n, s.ell_src, &d.ell_src));
-  RH_TRY(alloc(n, s.ell_col.size(), &d.ell_val));
-  d.ell_n = int(s.ell_col.size());
-  RH_TRY(alloc(n, s.col.size(), &d.val));
+  d.nstep = s.ks_nstep;
   d.unit = s.has_diag ? 0 : 1;
-  if (s.has_diag) {
-    RH_TRY(upload(n, s.diag_src, &d.diag_src));
-    RH_TRY(alloc(n, s.diag_src.size(), &d.dinv));
-  } else {
-    d.diag_src = nullptr;
-    const double* ones;
-    RH_TRY(upload(n, std::vector<double>(s.rows.size(), 1.0), &ones));
-    d.dinv = const_cast<double*>(ones);
-  }
+  return RH_OK;
+}
+
+// Condensation records for launch width W (see rh::CondenseRecords).
+rh_status upload_condense_records(rh_net* n, int W) {
+  rh::DevNet& d = n->d;
+  rh::CondenseRecords R;
+  rh::build_condense_records(n->s, W, R);
+  if (R.steps.size() >= size_t(1) << 31 || R.kstr.size() >= size_t(1) << 31) return RH_ERR_ARG;
+  const double* pd;
+  RH_TRY(upload(n, R.steps, &pd));
+  d.lblk = const_cast<double*>(pd);
+  rh::DevSweep* dsw[4] = {&d.sl, &d.su, &d.sut, &d.slt};
+  for (int k = 0; k < 4; ++k) RH_TRY(upload(n, R.meta[k], &dsw[k]->meta));
+  d.tr_n = int(R.tr_dst.size());
+  d.trd_n = int(R.trd_dst.size());
+  RH_TRY(upload(n, R.tr_dst, &d.tr_dst));
+  RH_TRY(upload(n, R.tr_src, &d.tr_src));
+  RH_TRY(upload(n, R.trd_dst, &d.trd_dst));
+  RH_TRY(upload(n, R.trd_src, &d.trd_src));
+  RH_TRY(upload(n, R.kstr, &pd));
+  d.kstr = const_cast<double*>(pd);
+  RH_TRY(upload(n, R.gstr, &pd));
+  d.gstr = const_cast<double*>(pd);
+  RH_TRY(upload(n, R.kdst, &d.kdst));
+  RH_TRY(upload(n, R.krt_dst, &d.krt_dst));
+  RH_TRY(upload(n, R.gdst, &d.gdst));
+  RH_TRY(upload(n, R.hpos, &d.hpos));
+  RH_TRY(upload(n, R.grow, &d.grow));
   return RH_OK;
 }
 
@@ -166,6 +175,8 @@ void fill_info(const rh::Symbolic& s, rh_info* info) {
   info->nnz_k = long(s.k_col.size());
   info->levels_lower = s.sl.nlev;
   info->levels_upper = s.su.nlev;
+  info->steps_lower = s.sl.ks_nstep;
+  info->sweep_steps = s.sl.ks_nstep + s.su.ks_nstep + s.sut.ks_nstep + s.slt.ks_nstep;
   info->refactor_ops = s.refactor_ops;
   info->max_lu_row = s.max_row;
   info->max_row_ops = s.max_row_ops;
@@ -295,13 +306,12 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(upload(n, s.kg.ata_row, &d.kg_row));
   RH_TRY(upload(n, s.kg.diag_var, &d.kg_diag));
   RH_TRY(upload(n, s.sig_map, &d.sig_map));
-  RH_TRY(upload(n, s.kb_base, &d.kb_base));
-  RH_TRY(upload(n, s.kb_len, &d.kb_len));
-  RH_TRY(upload(n, s.kell_col, &d.kell_col));
-  RH_TRY(upload(n, s.kell_pos, &d.kell_pos));
-  RH_TRY(alloc(n, s.kell_col.size(), &d.kell_val));
-  d.kell_n = int(s.kell_col.size());
-  d.kb_n = int(s.kb_base.size());
+  RH_TRY(upload(n, s.kst.end, &d.kb_end));
+  d.kst_nbat = s.kst.nbat;
+  d.kb_n = int(s.kst.end.size());
+  RH_TRY(upload(n, s.gst.end, &d.gt_end));
+  d.gst_nbat = s.gst.nbat;
+  d.gt_nb = int(s.gst.end.size());
   d.rw_ok = s.rw_ok ? 1 : 0;
   d.rw_nnz_u = s.rw_nnz_u;
   d.rw_nlev = s.sl.nlev;
@@ -366,22 +376,20 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   d.status = n->status;
   RH_HIP(hipMemset(n->status, 0, 8 * sizeof(int)));
   // launch shape of the condensation
-  const size_t col_bytes = size_t(s.nw) * sizeof(double);   // one LDS panel column
   const size_t lds_max = size_t(rh::max_lds_bytes());
-  const size_t meta = rh::condense_meta_bytes(d);
   int want = opts && opts->panel_width > 0 ? opts->panel_width : 1;
   if (want != 1 && want != 2 && want != 3 && want != 4 && want != 8) return RH_ERR_ARG;
-  bool lds = (!opts || opts->lds_panel != 0) && int(s.kb_base.size()) <= rh::kMaxRowBlocks;
-  if (lds && col_bytes * want + meta > lds_max) {
-    // keep the panel in LDS with a narrower tile if possible
+  bool lds = !opts || opts->lds_panel != 0;
+  if (lds && rh::condense_lds_bytes(d, want, true) > lds_max) {
+    // keep the panels in LDS with a narrower tile if possible
     int w = want;
-    while (w > 1 && col_bytes * w + meta > lds_max) w = (w == 8 ? 4 : w - 1);
-    if (col_bytes * w + meta <= lds_max) want = w; else lds = false;
+    while (w > 1 && rh::condense_lds_bytes(d, w, true) > lds_max) w = (w == 8 ? 4 : w - 1);
+    if (rh::condense_lds_bytes(d, w, true) <= lds_max) want = w; else lds = false;
   }
-  if (meta > lds_max) return RH_ERR_ARG;
   n->width = want;
   n->lds = lds;
-  rh::prepare_lds_kernels(lds ? col_bytes * want + meta : meta);
+  RH_TRY(upload_condense_records(n, want));
+  rh::prepare_lds_kernels();
   d.panel = nullptr;
   d.panel_doubles = 0;
   if (!lds) {
@@ -457,6 +465,13 @@ rh_status rh_symbolic_host_solve(const rh_symbolic* sym, const double* gx_values
                                  const double* b, double* z, int32_t transpose) {
   if (!sym || !gx_values || !b || !z) return RH_ERR_ARG;
   return rh::host_solve(sym->s, gx_values, b, z, transpose != 0);
+}
+
+rh_status rh_symbolic_check_condense(const rh_symbolic* sym, int32_t width, uint64_t seed,
+                                     double* max_rel_err) {
+  if (!sym || !max_rel_err || (width != 1 && width != 2 && width != 3 && width != 4 && width != 8))
+    return RH_ERR_ARG;
+  return rh::host_check_condense(sym->s, width, seed, 3, max_rel_err);
 }
 
 rh_status rh_symbolic_check_levels(const rh_symbolic* sym) {
@@ -555,7 +570,7 @@ rh_status condense_evaluated(rh_net* n, const double* sig_x, const double* sig_u
   {
     PhaseScope ps(n, RH_PHASE_EVAL);
     RH_HIP(rh::launch_assemble_k(d, sig_x, sig_u, sig_s, st));
-    if (r) RH_HIP(rh::launch_rtilde(d, r, sig_s, st));
+    RH_HIP(rh::launch_rtilde(d, r, sig_s, st));   // r == NULL: rt = 0
   }
   {
     PhaseScope ps(n, RH_PHASE_REFACTOR);
@@ -649,9 +664,10 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   }
   if (dev_status)
     RH_HIP(hipMemcpyAsync(dev_status, n->status, 2 * sizeof(int), hipMemcpyDeviceToDevice, st));
-  int hs[4];
+  int hs[5];
   RH_HIP(hipMemcpyAsync(hs, n->status, sizeof(hs), hipMemcpyDeviceToHost, st));
   RH_HIP(hipStreamSynchronize(st));
+  if (hs[4] != 0) return RH_ERR_STATE;   // condensation panels not at LDS address 0
   if (hs[0] != 0) return RH_NOT_POSDEF;
   if (hs[2] != 0) return RH_SMALL_PIVOT;
   return RH_OK;

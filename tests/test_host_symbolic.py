@@ -52,6 +52,21 @@ def test_levels_valid(net):
     assert S.info["levels_lower"] >= 1 and S.info["nnz_lu"] >= S.info["nnz_gx"]
 
 
+@pytest.mark.parametrize("width", [1, 3])
+@pytest.mark.parametrize("net", NETS[:4], ids=lambda n: n.name)
+def test_condensation_records_emulated_match_dense(net, width):
+    """The condensation kernel's device records (sweep steps, K and G_u^T
+    streams with their byte offsets for the panel width, row orders and
+    transcription lists), run lane by lane on the host as the wave runs them
+    (FMA chains, DPP shift tree, flushes), give the columns of
+    [I;S]^T K [I;S] and the right-hand-side column that a dense computation
+    gives for random values (Section 3.3)."""
+    S = _lib().Symbolic(net)
+    for seed in (1, 2):
+        err = S.check_condense(width=width, seed=seed)
+        assert err <= 1e-11, (net.name, width, seed, err)
+
+
 @pytest.mark.parametrize("refactor", [0, 1], ids=["wave", "staged"])
 @pytest.mark.parametrize("net", NETS, ids=lambda n: n.name)
 def test_patterns_cover_oracle_and_host_refactorisation_solves(net, refactor):
