@@ -800,6 +800,21 @@ __device__ __forceinline__ void row_stream(const double* str, int nbat, const in
   }
 }
 
+// body(i, idx[i]) for i < n over the wave's lanes, the index loads of eight
+// rounds issued together (clamped, so that none sits in a branch) before
+// their bodies, whose stores could otherwise hold back the next loads.
+template <class F>
+__device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kCondThreads) {
+    int ix[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ix[u] = idx[min(i0 + u * kCondThreads, n - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * kCondThreads < n) body(i0 + u * kCondThreads, ix[u]);
+  }
+}
+
 // Columns [col0 + blockIdx.x * W, ...) of the condensed matrix (Section 3.3),
 // one wave per work-group:
 //   Z   = -G_x^{-1} G_u V          (L then U sweep; V = identity columns)
@@ -916,12 +931,12 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, i
       const int j = jc0 + c;
       if (j >= col_end) break;
       double* pc = d.psicols + (size_t)j * nx;
-      for (int i = tid; i < nx; i += T) pc[i] = H[d.hpos[nu + i] * W + c];
+      indexed_loop(d.hpos + nu, nx, [&](int i, int hp) { pc[i] = H[hp * W + c]; });
     }
   }
   if (mode == MODE_RECOVER) {
     double* plam = p_out + nu + nx + d.m;
-    for (int i = tid; i < nx; i += T) plam[d.perm[i]] = -H[d.hpos[nu + i] * W];
+    indexed_loop(d.hpos + nu, nx, [&](int i, int hp) { plam[d.perm[i]] = -H[hp * W]; });
     return;
   }
   // out = H_u - G_u^T Psi: the stream sums G_u^T Psi - H_u; written over the
@@ -938,9 +953,9 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, i
     const int j = jc0 + c;
     if (j >= col_end) break;
     if (j < nu)
-      for (int p = tid; p < nu; p += T) K[(size_t)j * ldk + d.grow[p]] = P[p * W + c];
+      indexed_loop(d.grow, nu, [&](int p, int q) { K[(size_t)j * ldk + q] = P[p * W + c]; });
     else
-      for (int p = tid; p < nu; p += T) rhs[d.grow[p]] = -P[p * W + c];
+      indexed_loop(d.grow, nu, [&](int p, int q) { rhs[q] = -P[p * W + c]; });
   }
   tick(d, 7);
 }
