@@ -179,6 +179,46 @@ rh_status rh_get_index_maps(const rh_net* net, int32_t* x_kind, int32_t* x_bus,
 /* Replace the loads (scenarios). Device arrays pd[nb], qd[nb]. */
 rh_status rh_set_loads(rh_net* net, const double* pd_dev, const double* qd_dev);
 
+/* ---------------------------------------------------------------------------
+ * Batches (several networks or load scenarios condensed and solved together;
+ * Sections 3.3-3.4 per instance). A batch refers to existing handles, which
+ * must share the panel width and LDS placement (the defaults do) and must
+ * not be used by other calls while a batch call runs; the handles outlive
+ * the batch. Every batched kernel serves all instances in one launch, with
+ * the same kernel bodies as the single-instance calls, so each instance's
+ * results equal, bit for bit, those of rh_condense_reduced_hessian (with r)
+ * and rh_solve_condensed_kkt on the same inputs. hip_stream: the batch's
+ * stream (NULL = default). Errors: RH_ERR_ARG (mixed widths / placements,
+ * an instance too large for LDS staging), RH_ERR_OOM, RH_ERR_HIP.
+ * ------------------------------------------------------------------------- */
+typedef struct rh_batch rh_batch;
+typedef struct {
+  const double *x, *u, *lam, *y;          /* device, as rh_condense_reduced_hessian */
+  const double *sig_x, *sig_u, *sig_s;
+  const double* r;                        /* packed r1..r5 (required)                */
+  double* K;                              /* nu x nu output, leading dimension ldk   */
+  int64_t ldk;
+  double* rhs;                            /* nu output                               */
+} rh_batch_condense_item;
+typedef struct {
+  double* K;                              /* the instance's condensed matrix (overwritten) */
+  int64_t ldk;
+  double delta_w;
+  const double* rhs;                      /* its condensed right-hand side           */
+  const double* r;                        /* the r of the condensation               */
+  double* p;                              /* the step, as rh_solve_condensed_kkt     */
+} rh_batch_solve_item;
+rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream, rh_batch** out);
+void rh_batch_destroy(rh_batch* batch);
+/* items: host array of count entries (pointers to device memory). Stream-
+ * ordered on the batch stream, no host synchronisation. */
+rh_status rh_batch_condense(rh_batch* batch, const rh_batch_condense_item* items);
+/* items: host array of count entries. status: host array of count codes
+ * (RH_OK, RH_NOT_POSDEF, RH_SMALL_PIVOT, RH_ERR_STATE) or NULL; returns the
+ * first non-OK code or RH_OK. Synchronises the batch stream. RH_ERR_STATE if
+ * an instance was not condensed with a right-hand side before. */
+rh_status rh_batch_solve(rh_batch* batch, const rh_batch_solve_item* items, int32_t* status);
+
 /* g (nx), h (m), f (1): device outputs at device inputs x (nx), u (nu)
  * (Section 2.1's functions of the state-control form). */
 rh_status rh_eval_residual(rh_net* net, const double* x, const double* u,

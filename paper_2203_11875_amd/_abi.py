@@ -53,6 +53,16 @@ class rh_ipm_info(C.Structure):
                 ("obj_scale", C.c_double), ("converged", C.c_int32), ("reserved", C.c_int32)]
 
 
+class rh_batch_condense_item(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("x", "u", "lam", "y", "sig_x", "sig_u", "sig_s", "r",
+                                          "K")] + [("ldk", C.c_int64), ("rhs", C.c_void_p)]
+
+
+class rh_batch_solve_item(C.Structure):
+    _fields_ = [("K", C.c_void_p), ("ldk", C.c_int64), ("delta_w", C.c_double),
+                ("rhs", C.c_void_p), ("r", C.c_void_p), ("p", C.c_void_p)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/rhipm.h
 SIGNATURES = {
     "rh_status_str": (C.c_char_p, [C.c_int]),
@@ -87,6 +97,10 @@ SIGNATURES = {
     "rh_ipm_solve": (C.c_int, [vp, C.POINTER(rh_ipm_info)]),
     "rh_ipm_get_state": (C.c_int, [vp, vp, vp, vp, vp, vp]),
     "rh_ipm_destroy": (None, [vp]),
+    "rh_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]),
+    "rh_batch_destroy": (None, [vp]),
+    "rh_batch_condense": (C.c_int, [vp, C.POINTER(rh_batch_condense_item)]),
+    "rh_batch_solve": (C.c_int, [vp, C.POINTER(rh_batch_solve_item), i32p]),
 }
 
 PHASES = ["eval", "refactor", "condense", "symmetrize", "cholesky", "recover"]

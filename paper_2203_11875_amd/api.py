@@ -243,6 +243,81 @@ class Net:
         return p, code
 
 
+class Batch:
+    """Several device network handles condensed and solved together
+    (rh_batch_*): one launch per kernel for all instances."""
+
+    def __init__(self, nets, stream=None):
+        import torch
+        self.torch = torch
+        self.nets = list(nets)
+        arr = (C.c_void_p * len(self.nets))(*[n.h for n in self.nets])
+        h = C.c_void_p()
+        st = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib().rh_batch_create(arr, len(self.nets), C.c_void_p(st), C.byref(h)),
+               "rh_batch_create")
+        self.h = h
+        self._keep = None
+
+    def condense(self, points):
+        """points: per instance (x, u, lam, y, sig_x, sig_u, sig_s, r); returns
+        lists of K (nu x nu, column-major as in Net) and rhs."""
+        t = self.torch
+        items = (_abi.rh_batch_condense_item * len(self.nets))()
+        keep, Ks, rhss = [], [], []
+        for i, (G, pt) in enumerate(zip(self.nets, points)):
+            nx, nu, m = G.nx, G.nu, G.m
+            x, u, lam, y, sx, su, ss, r = pt
+            a = [G._t(x, nx), G._t(u, nu), G._t(lam, nx), G._t(y, m), G._t(sx, nx),
+                 G._t(su, nu), G._t(ss, m), G._t(r, nu + 2 * nx + 2 * m)]
+            K = t.empty((nu, nu), dtype=t.float64, device=G.device)
+            rhs = t.empty(nu, dtype=t.float64, device=G.device)
+            it = items[i]
+            for name, v in zip(("x", "u", "lam", "y", "sig_x", "sig_u", "sig_s", "r"), a):
+                setattr(it, name, _ptr(v))
+            it.K, it.ldk, it.rhs = _ptr(K), nu, _ptr(rhs)
+            keep.append(a)
+            Ks.append(K)
+            rhss.append(rhs)
+        _check(lib().rh_batch_condense(self.h, items), "rh_batch_condense")
+        self._keep = keep
+        return Ks, rhss
+
+    def solve(self, Ks, delta_w, rhss, rs):
+        """Returns (list of p, list of status codes)."""
+        t = self.torch
+        items = (_abi.rh_batch_solve_item * len(self.nets))()
+        ps, keep = [], []
+        for i, G in enumerate(self.nets):
+            nx, nu, m = G.nx, G.nu, G.m
+            rr = G._t(rs[i], nu + 2 * nx + 2 * m)
+            rhs = G._t(rhss[i], nu)
+            p = t.empty(nu + 2 * nx + 2 * m, dtype=t.float64, device=G.device)
+            it = items[i]
+            it.K, it.ldk = _ptr(Ks[i]), nu
+            it.delta_w = float(delta_w[i] if hasattr(delta_w, "__len__") else delta_w)
+            it.rhs, it.r, it.p = _ptr(rhs), _ptr(rr), _ptr(p)
+            keep.append((rr, rhs))
+            ps.append(p)
+        st = (C.c_int32 * len(self.nets))()
+        code = lib().rh_batch_solve(self.h, items, st)
+        if code < 0 and not any(int(v) for v in st):
+            _check(code, "rh_batch_solve")
+        self._keep = keep
+        return ps, [int(v) for v in st]
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _LIB is not None:
+            lib().rh_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _info_ipm(info):
     return {name: (float(getattr(info, name)) if isinstance(getattr(info, name), float)
                    else int(getattr(info, name)))

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace rh {
 
@@ -89,6 +90,39 @@ struct DevNet {
   int* status;        // [0] Cholesky status, [1] failing index, [2] small pivot flag, [3] pivot row
   long long* trace;   // in-kernel phase timestamps of work-group 0 (null = off)
 };
+
+// Per-instance arguments of a batched launch (device array, one per
+// instance; pointers to device memory).
+struct BatchArg {
+  const double *x, *u, *lam, *y, *sig_x, *sig_u, *sig_s, *r;
+  double* K;
+  long ldk;
+  double* rhs;            // condensation: output; solve: input
+  double* p;              // solve: the step (packed p_u p_x p_s p_lambda p_y)
+  double delta;           // solve: delta_w
+  double *sig_s_keep, *bwork, *cinv, *lrow;   // the handle's own buffers
+  int* status;
+  int nu, m;
+};
+// Host-side shape of a batch: maxima over the instances for the grids and
+// dynamic LDS of the batched launches.
+struct BatchShape {
+  int count = 0, width = 1, ntiles = 0;
+  bool lds = true, any_wave = false, any_staged = false;
+  int max_lines = 0, max_dst = 0, max_nnz_k = 0, max_nw = 0, max_nx = 0, max_nu = 0, max_m = 0;
+  size_t lds_wave = 0, lds_staged = 0, lds_condense = 0;
+  std::vector<int> nbk;   // Cholesky blocks of each instance
+};
+// Condensation of every instance (eval, K assembly, rt, refactorisation,
+// columns with the right-hand side, symmetrisation) and the solve with
+// recovery from the stored columns (Cholesky, backward substitution, p_x,
+// p_lambda, p_s, p_y); nets, args, tiles are device arrays.
+hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const int2* tiles,
+                                 const BatchShape& sh, hipStream_t st);
+hipError_t launch_batch_solve(const DevNet* nets, const BatchArg* args, const BatchShape& sh,
+                              hipStream_t st);
+// out[5 b + i] = status word i of instance b (device array of 5 count ints)
+hipError_t launch_batch_status(const DevNet* nets, int count, int* out, hipStream_t st);
 
 hipError_t launch_eval(const DevNet& d, const double* x, const double* u, const double* lam,
                        const double* y, bool hessian, hipStream_t st);

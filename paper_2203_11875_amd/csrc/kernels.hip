@@ -83,9 +83,7 @@ __device__ double ref_injection(const DevNet& d, const double* x, const double* 
 }
 
 // ---------------------------------------------------------------- evaluation
-__global__ void __launch_bounds__(kBlock) k_eval_lines(DevNet d, const double* x, const double* u,
-                                                      const double* lam, const double* y,
-                                                      int hessian) {
+__device__ __forceinline__ void k_eval_lines_body(const DevNet& d, const double* x, const double* u, const double* lam, const double* y, int hessian) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l < d.nu) d.src[d.src_u + l] = u[l];
   if (l >= d.nl) return;
@@ -144,26 +142,25 @@ __global__ void __launch_bounds__(kBlock) k_eval_lines(DevNet d, const double* x
       h[idx] = v;
     }
 }
+__global__ void __launch_bounds__(kBlock) k_eval_lines(DevNet d, const double* x, const double* u, const double* lam, const double* y, int hessian) {
+  k_eval_lines_body(d, x, u, lam, y, hessian);
+}
 
-__global__ void __launch_bounds__(kBlock) k_gather(int n, const int* __restrict__ ptr,
-                                                  const int* __restrict__ idx,
-                                                  const double* __restrict__ coef,
-                                                  const double* __restrict__ cst,
-                                                  const double* __restrict__ src,
-                                                  double* __restrict__ dst) {
+__device__ __forceinline__ void k_gather_body(int n, const int* __restrict__ ptr, const int* __restrict__ idx, const double* __restrict__ coef, const double* __restrict__ cst, const double* __restrict__ src, double* __restrict__ dst) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double acc = cst[e];
   for (int t = ptr[e]; t < ptr[e + 1]; ++t) acc += coef[t] * src[idx[t]];
   dst[e] = acc;
 }
+__global__ void __launch_bounds__(kBlock) k_gather(int n, const int* __restrict__ ptr, const int* __restrict__ idx, const double* __restrict__ coef, const double* __restrict__ cst, const double* __restrict__ src, double* __restrict__ dst) {
+  k_gather_body(n, ptr, idx, coef, cst, src, dst);
+}
 
 // K = W + diag(Sigma_u, Sigma_x) + A^T diag(Sigma_s) A on the fixed pattern.
 // The reference generator's quadratic cost adds 2 c2 base^2 grad P_ref
 // grad P_ref^T, i.e. it enlarges the weight of A's first row.
-__global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* sig_x,
-                                                      const double* sig_u,
-                                                      const double* sig_s) {
+__device__ __forceinline__ void k_assemble_k_body(const DevNet& d, const double* sig_x, const double* sig_u, const double* sig_s) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= d.nnz_k) return;
   double acc = 0.0;
@@ -180,6 +177,9 @@ __global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* s
     acc += (sm < d.nu ? sig_u[sm] : sig_x[sm - d.nu]) + d.k_cdiag[v];
   }
   d.kstr[d.kdst[e]] = acc;
+}
+__global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* sig_x, const double* sig_u, const double* sig_s) {
+  k_assemble_k_body(d, sig_x, sig_u, sig_s);
 }
 
 __global__ void k_fill_int(int* p, int n, int v) {
@@ -199,7 +199,7 @@ __global__ void k_fill_int(int* p, int n, int v) {
 // pivot is kept for the rows that follow.
 constexpr int kRefThreads = 1024;
 
-__global__ void __launch_bounds__(kRefThreads) k_refactor(DevNet d) {
+__device__ __forceinline__ void k_refactor_body(const DevNet& d) {
   extern __shared__ double ref_lds[];
   double* lu = d.dst + d.d_lu;
   for (int lev = 0; lev < d.rf_nlev; ++lev) {
@@ -253,11 +253,14 @@ __global__ void __launch_bounds__(kRefThreads) k_refactor(DevNet d) {
     __syncthreads();
   }
 }
+__global__ void __launch_bounds__(kRefThreads) k_refactor(DevNet d) {
+  k_refactor_body(d);
+}
 
 // Copy the refactorised values into the sweeps' lane blocks (entries,
 // reciprocal pivots of the writing lanes) and the G_u values into the G_u^T
 // record stream.
-__global__ void __launch_bounds__(kBlock) k_transcribe(DevNet d) {
+__device__ __forceinline__ void k_transcribe_body(const DevNet& d) {
   const double* lu = d.dst + d.d_lu;
   const double* gu = d.dst + d.d_gu;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -266,9 +269,12 @@ __global__ void __launch_bounds__(kBlock) k_transcribe(DevNet d) {
   for (int t = tid; t < d.trd_n; t += stride) d.lblk[d.trd_dst[t]] = 1.0 / lu[d.trd_src[t]];
   for (int e = tid; e < d.nnz_gu; e += stride) d.gstr[d.gdst[e]] = gu[e];
 }
+__global__ void __launch_bounds__(kBlock) k_transcribe(DevNet d) {
+  k_transcribe_body(d);
+}
 
 // rt = [r1 ; r2] + A^T (Sigma_s r5 - r3), in w = [u ; x internal] order.
-__global__ void __launch_bounds__(kBlock) k_rtilde(DevNet d, const double* r, const double* sig_s) {
+__device__ __forceinline__ void k_rtilde_body(const DevNet& d, const double* r, const double* sig_s) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= d.nw) return;
   if (!r) {
@@ -288,6 +294,9 @@ __global__ void __launch_bounds__(kBlock) k_rtilde(DevNet d, const double* r, co
   }
   d.rt[v] = acc;
   d.kstr[d.krt_dst[v]] = acc;   // the rt term of K row v in the condensation's stream
+}
+__global__ void __launch_bounds__(kBlock) k_rtilde(DevNet d, const double* r, const double* sig_s) {
+  k_rtilde_body(d, r, sig_s);
 }
 
 // ------------------------------------------------- condensation pipeline
@@ -459,7 +468,7 @@ __device__ __forceinline__ void rw_run(const DevNet& d, const RwSet& X, double* 
 // Work-group 0 factors. Work-groups 8 h (h >= 1), dispatched to the same XCD
 // as work-group 0, read the task tables and the values into that XCD's L2
 // ahead of it and exit; the others exit at once.
-__global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
+__device__ __forceinline__ void k_refactor_wave_body(const DevNet& d) {
   if (blockIdx.x != 0) {
     if (blockIdx.x % 8 != 0) return;
     const int h = blockIdx.x / 8 - 1, nh = gridDim.x / 8 - 1;
@@ -532,6 +541,9 @@ __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
     lds_barrier();
     if (tr && lev < 128) tr[1 + lev] = wall_clock64();
   }
+}
+__global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
+  k_refactor_wave_body(d);
 }
 
 // The condensation runs one wave per work-group (one thread per lane of a
@@ -815,8 +827,8 @@ __device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
   }
 }
 
-// Columns [col0 + blockIdx.x * W, ...) of the condensed matrix (Section 3.3),
-// one wave per work-group:
+// Columns [col0 + blk * W, ...) of the condensed matrix (Section 3.3), one
+// wave per work-group (blk = the work-group's tile):
 //   Z   = -G_x^{-1} G_u V          (L then U sweep; V = identity columns)
 //   H   =  K [V ; Z]               (one sparse product over all nu + nx rows)
 //   Psi =  G_x^{-T} H_x            (U^T then L^T sweep)
@@ -829,17 +841,16 @@ __device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
 // multiplies each K row's rt term), then H (nw rows, in K-stream order:
 // w row v at hpos[v]).
 template <int W, bool LDS, int mode>
-__global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, int col_end,
-                                                          const double* r, const double* vin,
-                                                          double* K, long ldk, double* rhs,
-                                                          double* p_out) {
+__device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int col0, int col_end,
+                                                const double* r, const double* vin, double* K,
+                                                long ldk, double* rhs, double* p_out) {
   extern __shared__ double panel_lds[];
   if (LDS && (size_t)(lds_double*)panel_lds != 0) {   // the records assume LDS address 0
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.status[4] = 1;
+    if (blk == 0 && threadIdx.x == 0) d.status[4] = 1;
     return;
   }
   const int nw = d.nw, nu = d.nu, nx = d.nx;
-  double* P = LDS ? panel_lds : d.panel + (size_t)blockIdx.x * (2 * nw + 1) * W;
+  double* P = LDS ? panel_lds : d.panel + (size_t)blk * (2 * nw + 1) * W;
   double* H = P + (size_t)(nw + 1) * W;
   char* pb = reinterpret_cast<char*>(P);
   // step metadata of the four sweeps (with their idle steps) and the block
@@ -858,7 +869,7 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, i
   for (int i = threadIdx.x; i < d.gt_nb; i += kCondThreads) gt_end[i] = d.gt_end[i];
   panel_sync<LDS>();
   tick(d, 0);
-  const int jc0 = col0 + blockIdx.x * W;
+  const int jc0 = col0 + blk * W;
   const int tid = threadIdx.x, T = kCondThreads;
   const double* gu = d.dst + d.d_gu;
   const double* r4 = r ? r + d.nu + d.nx + d.m : nullptr;
@@ -959,6 +970,13 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, i
   }
   tick(d, 7);
 }
+template <int W, bool LDS, int mode>
+__global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, int col_end,
+                                                          const double* r, const double* vin,
+                                                          double* K, long ldk, double* rhs,
+                                                          double* p_out) {
+  k_condense_body<W, LDS, mode>(d, blockIdx.x, col0, col_end, r, vin, K, ldk, rhs, p_out);
+}
 
 // Recovery from the stored columns: thread i (internal x index) of chunk ch
 // sums the columns [ch * cw, (ch + 1) * cw) of Z and Psi against p_u; the
@@ -966,7 +984,7 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, i
 // result repeats bitwise.
 constexpr int kRecChunks = 8;
 
-__global__ void __launch_bounds__(kBlock) k_recover_partial(DevNet d, const double* pu) {
+__device__ __forceinline__ void k_recover_partial_body(const DevNet& d, const double* pu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y;
   if (i >= d.nx) return;
@@ -982,8 +1000,11 @@ __global__ void __launch_bounds__(kBlock) k_recover_partial(DevNet d, const doub
   d.rpart[(size_t)ch * d.nx + i] = sz;
   d.rpart[(size_t)(kRecChunks + ch) * d.nx + i] = sp;
 }
+__global__ void __launch_bounds__(kBlock) k_recover_partial(DevNet d, const double* pu) {
+  k_recover_partial_body(d, pu);
+}
 
-__global__ void __launch_bounds__(kBlock) k_recover_finish(DevNet d, double* p) {
+__device__ __forceinline__ void k_recover_finish_body(const DevNet& d, double* p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < d.nu) {
     d.pw[i] = p[i];
@@ -999,10 +1020,12 @@ __global__ void __launch_bounds__(kBlock) k_recover_finish(DevNet d, double* p) 
   p[d.nu + d.perm[i]] = sz;                         // p_x
   p[d.nu + d.nx + d.m + d.perm[i]] = -sp;           // p_lambda
 }
+__global__ void __launch_bounds__(kBlock) k_recover_finish(DevNet d, double* p) {
+  k_recover_finish_body(d, p);
+}
 
 // p_s = -r5 - A p,  p_y = -r3 - Sigma_s p_s   (p in w order from the recovery)
-__global__ void __launch_bounds__(kBlock) k_finish_step(DevNet d, const double* r,
-                                                       const double* sig_s, double* p) {
+__device__ __forceinline__ void k_finish_step_body(const DevNet& d, const double* r, const double* sig_s, double* p) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d.m) return;
   const double* r3 = r + d.nu + d.nx;
@@ -1013,6 +1036,9 @@ __global__ void __launch_bounds__(kBlock) k_finish_step(DevNet d, const double* 
   const double ps = -r5[j] - ap;
   p[d.nu + d.nx + j] = ps;
   p[d.nu + 2 * d.nx + d.m + j] = -r3[j] - sig_s[j] * ps;
+}
+__global__ void __launch_bounds__(kBlock) k_finish_step(DevNet d, const double* r, const double* sig_s, double* p) {
+  k_finish_step_body(d, r, sig_s, p);
 }
 
 __global__ void __launch_bounds__(kBlock) k_objective(DevNet d, const double* u,
@@ -1036,13 +1062,16 @@ __global__ void __launch_bounds__(kBlock) k_objective(DevNet d, const double* u,
 }
 
 // --------------------------------------------------------- dense Cholesky
-__global__ void k_symmetrize(double* K, long ld, int n) {
+__device__ __forceinline__ void k_symmetrize_body(double* K, long ld, int n) {
   const int i = blockIdx.x * 16 + threadIdx.x;
   const int j = blockIdx.y * 16 + threadIdx.y;
   if (i >= n || j >= i) return;
   const double v = 0.5 * (K[(size_t)j * ld + i] + K[(size_t)i * ld + j]);
   K[(size_t)j * ld + i] = v;
   K[(size_t)i * ld + j] = v;
+}
+__global__ void k_symmetrize(double* K, long ld, int n) {
+  k_symmetrize_body(K, ld, n);
 }
 
 constexpr int NB = 32;   // panel width of the blocked Cholesky
@@ -1173,9 +1202,7 @@ __device__ __forceinline__ void store_quad_lower(double* A, long ld, int n, int 
 // one launch later. The off-diagonal tiles are also stored by rows in lrow
 // (row block i: NB rows of nbk NB entries) for the backward substitution.
 // delta enters each diagonal tile on its first touch (k <= 1).
-__global__ void __launch_bounds__(256) k_chol_step(double* A, long ld, int n, int k, double delta,
-                                                   double* b, double* y, double* inv, double* dl,
-                                                   double* lrow, int* status, long long* trace) {
+__device__ __forceinline__ void k_chol_step_body(double* A, long ld, int n, int k, double delta, double* b, double* y, double* inv, double* dl, double* lrow, int* status, long long* trace) {
   if (status[0] != 0) return;
   const bool tr = trace != nullptr && blockIdx.x == 0 && threadIdx.x == 0;
   if (tr) trace[8 * k] = wall_clock64();
@@ -1308,6 +1335,9 @@ __global__ void __launch_bounds__(256) k_chol_step(double* A, long ld, int n, in
   }
   if (tr) trace[8 * k + 4] = wall_clock64();
 }
+__global__ void __launch_bounds__(256) k_chol_step(double* A, long ld, int n, int k, double delta, double* b, double* y, double* inv, double* dl, double* lrow, int* status, long long* trace) {
+  k_chol_step_body(A, ld, n, k, delta, b, y, inv, dl, lrow, status, trace);
+}
 
 // One step of the backward substitution for row block bk (b0 = bk NB):
 // lv holds this thread's half column of L_{bk, c} (c = tid / 2 < b0, rows
@@ -1371,9 +1401,7 @@ __device__ __forceinline__ void backward_load(const double* lrow, int npad, int 
 // WIDE: n > 33 NB, some row blocks span more columns than one pass of the
 // work-group covers (the columns past the first pass are loaded in place).
 template <bool WIDE>
-__global__ void __launch_bounds__(NB * NB) k_chol_backward(const double* lrow, int n, double* y,
-                                                           const double* inv, const int* status,
-                                                           long long* trace) {
+__device__ __forceinline__ void k_chol_backward_body(const double* lrow, int n, double* y, const double* inv, const int* status, long long* trace) {
   if (status[0] != 0) return;
   const int tid = threadIdx.x;
   const int nbk = (n + NB - 1) / NB, npad = nbk * NB;
@@ -1415,6 +1443,10 @@ __global__ void __launch_bounds__(NB * NB) k_chol_backward(const double* lrow, i
   if (tr) trace[2] = wall_clock64();
   for (int i = tid; i < n; i += NB * NB) y[i] = ys[i];
 }
+template <bool WIDE>
+__global__ void __launch_bounds__(NB * NB) k_chol_backward(const double* lrow, int n, double* y, const double* inv, const int* status, long long* trace) {
+  k_chol_backward_body<WIDE>(lrow, n, y, inv, status, trace);
+}
 
 
 template <int W, bool LDS>
@@ -1447,6 +1479,106 @@ hipError_t dispatch_width(const DevNet& d, int col0, int ncols, int width, int m
 }
 
 inline int cdiv(long a, long b) { return int((a + b - 1) / b); }
+
+
+// ------------------------------------------------------------ batches
+// Batched launches: one launch serves every instance of a batch (instance =
+// blockIdx.z unless noted); each instance's work uses its own DevNet and the
+// same kernel bodies as the single-instance launches, so results are the
+// same bit for bit.
+
+__global__ void __launch_bounds__(kBlock) k_eval_lines_b(const DevNet* __restrict__ nets,
+                                                        const BatchArg* __restrict__ a) {
+  const int b = blockIdx.z;
+  k_eval_lines_body(nets[b], a[b].x, a[b].u, a[b].lam, a[b].y, 1);
+}
+__global__ void __launch_bounds__(kBlock) k_gather_b(const DevNet* __restrict__ nets) {
+  const DevNet& d = nets[blockIdx.z];
+  k_gather_body(d.d_total, d.eg_ptr, d.eg_idx, d.eg_coef, d.eg_cst, d.src, d.dst);
+}
+// per-instance vector copies kept by the handles (Sigma_s for the recovery,
+// the right-hand side for the Cholesky solve): dst[i] = src[i], i < n
+__global__ void __launch_bounds__(kBlock) k_copy_b(const BatchArg* __restrict__ a, int which) {
+  const BatchArg& q = a[blockIdx.z];
+  const double* src = which == 0 ? q.sig_s : q.rhs;
+  double* dst = which == 0 ? q.sig_s_keep : q.bwork;
+  const int n = which == 0 ? q.m : q.nu;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void __launch_bounds__(kBlock) k_assemble_k_b(const DevNet* __restrict__ nets,
+                                                        const BatchArg* __restrict__ a) {
+  const int b = blockIdx.z;
+  k_assemble_k_body(nets[b], a[b].sig_x, a[b].sig_u, a[b].sig_s);
+}
+__global__ void __launch_bounds__(kBlock) k_rtilde_b(const DevNet* __restrict__ nets,
+                                                    const BatchArg* __restrict__ a) {
+  const int b = blockIdx.z;
+  k_rtilde_body(nets[b], a[b].r, a[b].sig_s_keep);
+}
+// status[first .. first + count) = 0 for every instance
+__global__ void k_clear_status_b(const DevNet* __restrict__ nets, int first, int count) {
+  if ((int)threadIdx.x < count) nets[blockIdx.z].status[first + threadIdx.x] = 0;
+}
+__global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave_b(const DevNet* __restrict__ nets) {
+  const DevNet& d = nets[blockIdx.z];
+  if (d.rw_ok) k_refactor_wave_body(d);
+}
+__global__ void __launch_bounds__(kRefThreads) k_refactor_b(const DevNet* __restrict__ nets) {
+  const DevNet& d = nets[blockIdx.z];
+  if (!d.rw_ok) k_refactor_body(d);
+}
+__global__ void __launch_bounds__(kBlock) k_transcribe_b(const DevNet* __restrict__ nets) {
+  k_transcribe_body(nets[blockIdx.z]);
+}
+// work-group g takes tile tiles[g] = {instance, tile of W columns}
+template <int W, bool LDS>
+__global__ void __launch_bounds__(kCondThreads) k_condense_b(const DevNet* __restrict__ nets,
+                                                            const BatchArg* __restrict__ a,
+                                                            const int2* __restrict__ tiles) {
+  const int2 t = tiles[blockIdx.x];
+  const DevNet& d = nets[t.x];
+  const BatchArg& q = a[t.x];
+  k_condense_body<W, LDS, MODE_COLUMNS>(d, t.y, 0, d.nu + 1, q.r, nullptr, q.K, q.ldk, q.rhs,
+                                        nullptr);
+}
+__global__ void k_symmetrize_b(const BatchArg* __restrict__ a) {
+  const BatchArg& q = a[blockIdx.z];
+  k_symmetrize_body(q.K, q.ldk, q.nu);
+}
+__global__ void __launch_bounds__(256) k_chol_step_b(const BatchArg* __restrict__ a, int k) {
+  const BatchArg& q = a[blockIdx.z];
+  const int nbk = (q.nu + NB - 1) / NB;
+  if (k >= nbk) return;
+  const int T = nbk - 1 - k;
+  if ((int)blockIdx.x >= (nbk - k) + (k >= 1 ? T * (T + 1) / 2 : 0)) return;
+  k_chol_step_body(q.K, q.ldk, q.nu, k, q.delta, q.bwork, q.p, q.cinv,
+                   q.cinv + (size_t)nbk * NB * NB, q.lrow, q.status, nullptr);
+}
+template <bool WIDE>
+__global__ void __launch_bounds__(NB * NB) k_chol_backward_b(const BatchArg* __restrict__ a) {
+  const BatchArg& q = a[blockIdx.z];
+  k_chol_backward_body<WIDE>(q.lrow, q.nu, q.p, q.cinv, q.status, nullptr);
+}
+__global__ void __launch_bounds__(kBlock) k_recover_partial_b(const DevNet* __restrict__ nets,
+                                                             const BatchArg* __restrict__ a) {
+  const int b = blockIdx.z;
+  k_recover_partial_body(nets[b], a[b].p);
+}
+__global__ void __launch_bounds__(kBlock) k_recover_finish_b(const DevNet* __restrict__ nets,
+                                                            const BatchArg* __restrict__ a) {
+  const int b = blockIdx.z;
+  k_recover_finish_body(nets[b], a[b].p);
+}
+// out[5 b + i] = status[i] of instance b, i < 5
+__global__ void k_gather_status_b(const DevNet* __restrict__ nets, int* out) {
+  if (threadIdx.x < 5) out[5 * blockIdx.z + threadIdx.x] = nets[blockIdx.z].status[threadIdx.x];
+}
+__global__ void __launch_bounds__(kBlock) k_finish_step_b(const DevNet* __restrict__ nets,
+                                                         const BatchArg* __restrict__ a) {
+  const int b = blockIdx.z;
+  k_finish_step_body(nets[b], a[b].r, a[b].sig_s_keep, a[b].p);
+}
 
 }  // namespace
 
@@ -1483,6 +1615,25 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_condense<1, false, MODE_RECOVER>)};
   for (const void* f : fns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+  const void* bfns[] = {
+      reinterpret_cast<const void*>(&k_condense_b<1, true>),
+      reinterpret_cast<const void*>(&k_condense_b<2, true>),
+      reinterpret_cast<const void*>(&k_condense_b<3, true>),
+      reinterpret_cast<const void*>(&k_condense_b<4, true>),
+      reinterpret_cast<const void*>(&k_condense_b<8, true>),
+      reinterpret_cast<const void*>(&k_condense_b<1, false>),
+      reinterpret_cast<const void*>(&k_condense_b<2, false>),
+      reinterpret_cast<const void*>(&k_condense_b<3, false>),
+      reinterpret_cast<const void*>(&k_condense_b<4, false>),
+      reinterpret_cast<const void*>(&k_condense_b<8, false>),
+      reinterpret_cast<const void*>(&k_refactor_wave_b),
+      reinterpret_cast<const void*>(&k_refactor_b)};
+  for (const void* f : bfns)
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward_b<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward_b<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
   for (const void* f : gfns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   (void)hipGetLastError();
@@ -1588,6 +1739,86 @@ hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, doubl
     hipLaunchKernelGGL(k_chol_backward<true>, dim3(64), dim3(NB * NB),
                        (size_t)nbk * NB * sizeof(double), st, (const double*)lrow, n, y,
                        (const double*)dinv, (const int*)status, trace ? trace + 8 * nbk : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const int2* tiles,
+                                 const BatchShape& sh, hipStream_t st) {
+  const int B = sh.count;
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval_lines_b, dim3(cdiv(sh.max_lines, kBlock), 1, B), dim3(kBlock), 0, st,
+                     nets, args);
+  hipLaunchKernelGGL(k_gather_b, dim3(cdiv(sh.max_dst, kBlock), 1, B), dim3(kBlock), 0, st, nets);
+  hipLaunchKernelGGL(k_copy_b, dim3(cdiv(sh.max_m, kBlock), 1, B), dim3(kBlock), 0, st, args, 0);
+  hipLaunchKernelGGL(k_assemble_k_b, dim3(cdiv(sh.max_nnz_k, kBlock), 1, B), dim3(kBlock), 0, st,
+                     nets, args);
+  hipLaunchKernelGGL(k_rtilde_b, dim3(cdiv(sh.max_nw, kBlock), 1, B), dim3(kBlock), 0, st, nets,
+                     args);
+  hipLaunchKernelGGL(k_clear_status_b, dim3(1, 1, B), dim3(64), 0, st, nets, 2, 2);
+  if (sh.any_wave)
+    hipLaunchKernelGGL(k_refactor_wave_b, dim3(1, 1, B), dim3(kRwWaves * 64), sh.lds_wave, st,
+                       nets);
+  if (sh.any_staged)
+    hipLaunchKernelGGL(k_refactor_b, dim3(1, 1, B), dim3(kRefThreads), sh.lds_staged, st, nets);
+  hipLaunchKernelGGL(k_transcribe_b, dim3(64, 1, B), dim3(kBlock), 0, st, nets);
+  const int W = sh.width;
+#define RH_BATCH_COND(WW, LL)                                                                   \
+  hipLaunchKernelGGL((k_condense_b<WW, LL>), dim3(sh.ntiles), dim3(kCondThreads), sh.lds_condense, \
+                     st, nets, args, tiles)
+  if (sh.lds) {
+    if (W == 1) RH_BATCH_COND(1, true);
+    else if (W == 2) RH_BATCH_COND(2, true);
+    else if (W == 3) RH_BATCH_COND(3, true);
+    else if (W == 4) RH_BATCH_COND(4, true);
+    else RH_BATCH_COND(8, true);
+  } else {
+    if (W == 1) RH_BATCH_COND(1, false);
+    else if (W == 2) RH_BATCH_COND(2, false);
+    else if (W == 3) RH_BATCH_COND(3, false);
+    else if (W == 4) RH_BATCH_COND(4, false);
+    else RH_BATCH_COND(8, false);
+  }
+#undef RH_BATCH_COND
+  hipLaunchKernelGGL(k_symmetrize_b, dim3(cdiv(sh.max_nu, 16), cdiv(sh.max_nu, 16), B),
+                     dim3(16, 16), 0, st, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_solve(const DevNet* nets, const BatchArg* args, const BatchShape& sh,
+                              hipStream_t st) {
+  const int B = sh.count;
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_b, dim3(cdiv(sh.max_nu, kBlock), 1, B), dim3(kBlock), 0, st, args, 1);
+  hipLaunchKernelGGL(k_clear_status_b, dim3(1, 1, B), dim3(64), 0, st, nets, 0, 2);
+  int max_nbk = 0;
+  for (int v : sh.nbk) max_nbk = v > max_nbk ? v : max_nbk;
+  for (int k = 0; k < max_nbk; ++k) {
+    int grid = 0;
+    for (int nbk : sh.nbk)
+      if (k < nbk) {
+        const int T = nbk - 1 - k, g = (nbk - k) + (k >= 1 ? T * (T + 1) / 2 : 0);
+        grid = g > grid ? g : grid;
+      }
+    hipLaunchKernelGGL(k_chol_step_b, dim3(grid, 1, B), dim3(256), 0, st, args, k);
+  }
+  if (max_nbk <= 33)
+    hipLaunchKernelGGL(k_chol_backward_b<false>, dim3(1, 1, B), dim3(NB * NB),
+                       (size_t)max_nbk * NB * sizeof(double), st, args);
+  else
+    hipLaunchKernelGGL(k_chol_backward_b<true>, dim3(1, 1, B), dim3(NB * NB),
+                       (size_t)max_nbk * NB * sizeof(double), st, args);
+  hipLaunchKernelGGL(k_recover_partial_b, dim3(cdiv(sh.max_nx, kBlock), kRecChunks, B),
+                     dim3(kBlock), 0, st, nets, args);
+  hipLaunchKernelGGL(k_recover_finish_b,
+                     dim3(cdiv(sh.max_nx > sh.max_nu ? sh.max_nx : sh.max_nu, kBlock), 1, B),
+                     dim3(kBlock), 0, st, nets, args);
+  hipLaunchKernelGGL(k_finish_step_b, dim3(cdiv(sh.max_m, kBlock), 1, B), dim3(kBlock), 0, st,
+                     nets, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const DevNet* nets, int count, int* out, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_gather_status_b, dim3(1, 1, count), dim3(64), 0, st, nets, out);
   return hipGetLastError();
 }
 

@@ -122,6 +122,22 @@ rh_status alloc(rh_net* n, size_t count, T** out) {
     if ((expr) != hipSuccess) return RH_ERR_HIP;  \
   } while (0)
 
+}  // namespace
+
+struct rh_batch {
+  std::vector<rh_net*> nets;
+  hipStream_t stream = nullptr;
+  rh::BatchShape shape;
+  rh::DevNet* d_nets = nullptr;
+  rh::BatchArg* d_args = nullptr;
+  int2* d_tiles = nullptr;
+  int* d_status = nullptr;
+  std::vector<rh::DevNet> h_nets;
+  std::vector<rh::BatchArg> h_args;
+};
+
+namespace {
+
 rh_status upload_sweep(rh_net* n, const rh::Sweep& s, rh::DevSweep& d) {
   d.nlev = s.nlev;
   RH_TRY(upload(n, s.lev_ptr, &d.lev_ptr));
@@ -536,6 +552,162 @@ rh_status rh_set_loads(rh_net* n, const double* pd, const double* qd) {
   RH_HIP(hipMemcpyAsync(base + n->s.nb, qd, sizeof(double) * n->s.nb, hipMemcpyDeviceToDevice,
                         n->stream));
   return RH_OK;
+}
+
+rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
+                          rh_batch** out) {
+  if (!nets || count < 1 || !out) return RH_ERR_ARG;
+  *out = nullptr;
+  auto* b = new rh_batch();
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  rh::BatchShape& sh = b->shape;
+  sh.count = count;
+  std::vector<int2> tiles;
+  const size_t lds_max = size_t(rh::max_lds_bytes());
+  for (int i = 0; i < count; ++i) {
+    rh_net* n = nets[i];
+    if (!n) { delete b; return RH_ERR_ARG; }
+    if (i == 0) { sh.width = n->width; sh.lds = n->lds; }
+    if (n->width != sh.width || n->lds != sh.lds) { delete b; return RH_ERR_ARG; }
+    const rh::DevNet& d = n->d;
+    if (size_t((d.nu + 31) / 32) * 32 * sizeof(double) + 25 * 1024 > lds_max) {
+      delete b;
+      return RH_ERR_ARG;
+    }
+    b->nets.push_back(n);
+    sh.max_lines = std::max(sh.max_lines, std::max(d.nl, d.nu));
+    sh.max_dst = std::max(sh.max_dst, d.d_total);
+    sh.max_nnz_k = std::max(sh.max_nnz_k, d.nnz_k);
+    sh.max_nw = std::max(sh.max_nw, d.nw);
+    sh.max_nx = std::max(sh.max_nx, d.nx);
+    sh.max_nu = std::max(sh.max_nu, d.nu);
+    sh.max_m = std::max(sh.max_m, d.m);
+    if (d.rw_ok) {
+      sh.any_wave = true;
+      sh.lds_wave = std::max(sh.lds_wave, size_t(d.rw_nnz_u + 1 + d.nx) * sizeof(double) +
+                                              size_t(rh::kRwWaves) * d.rw_nlev * sizeof(int));
+    } else {
+      sh.any_staged = true;
+      sh.lds_staged = std::max(sh.lds_staged, size_t(d.rf_lds_doubles) * sizeof(double));
+    }
+    sh.lds_condense = std::max(sh.lds_condense, rh::condense_lds_bytes(d, sh.width, sh.lds));
+    sh.nbk.push_back((d.nu + 31) / 32);
+    const int ntile = (d.nu + 1 + sh.width - 1) / sh.width;
+    for (int t = 0; t < ntile; ++t) tiles.push_back(int2{i, t});
+  }
+  sh.ntiles = int(tiles.size());
+  if (sh.lds_wave > lds_max || sh.lds_staged > lds_max || sh.lds_condense > lds_max) {
+    delete b;
+    return RH_ERR_ARG;
+  }
+  b->h_nets.resize(count);
+  b->h_args.resize(count);
+  if (hipMalloc(&b->d_nets, sizeof(rh::DevNet) * count) != hipSuccess ||
+      hipMalloc(&b->d_args, sizeof(rh::BatchArg) * count) != hipSuccess ||
+      hipMalloc(&b->d_tiles, sizeof(int2) * tiles.size()) != hipSuccess ||
+      hipMalloc(&b->d_status, sizeof(int) * 5 * count) != hipSuccess) {
+    rh_batch_destroy(b);
+    return RH_ERR_OOM;
+  }
+  if (hipMemcpy(b->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    rh_batch_destroy(b);
+    return RH_ERR_HIP;
+  }
+  *out = b;
+  return RH_OK;
+}
+
+void rh_batch_destroy(rh_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  (void)hipFree(b->d_nets);
+  (void)hipFree(b->d_args);
+  (void)hipFree(b->d_tiles);
+  (void)hipFree(b->d_status);
+  delete b;
+}
+
+namespace {
+// the instances' current device descriptors (profiling or new loads change
+// them between calls) and the per-call arguments, to the device
+rh_status batch_upload(rh_batch* b) {
+  for (size_t i = 0; i < b->nets.size(); ++i) {
+    rh_net* n = b->nets[i];
+    b->h_nets[i] = n->d;
+    rh::BatchArg& a = b->h_args[i];
+    a.sig_s_keep = n->sig_s;
+    a.bwork = n->bwork;
+    a.cinv = n->cinv;
+    a.lrow = n->lrow;
+    a.status = n->status;
+    a.nu = n->d.nu;
+    a.m = n->d.m;
+  }
+  RH_HIP(hipMemcpyAsync(b->d_nets, b->h_nets.data(), sizeof(rh::DevNet) * b->nets.size(),
+                        hipMemcpyHostToDevice, b->stream));
+  RH_HIP(hipMemcpyAsync(b->d_args, b->h_args.data(), sizeof(rh::BatchArg) * b->nets.size(),
+                        hipMemcpyHostToDevice, b->stream));
+  return RH_OK;
+}
+}  // namespace
+
+rh_status rh_batch_condense(rh_batch* b, const rh_batch_condense_item* items) {
+  if (!b || !items) return RH_ERR_ARG;
+  for (size_t i = 0; i < b->nets.size(); ++i) {
+    const rh_batch_condense_item& it = items[i];
+    if (!it.x || !it.u || !it.lam || !it.y || !it.sig_x || !it.sig_u || !it.sig_s || !it.r ||
+        !it.K || !it.rhs || it.ldk < b->nets[i]->d.nu)
+      return RH_ERR_ARG;
+    rh::BatchArg& a = b->h_args[i];
+    a = rh::BatchArg{};
+    a.x = it.x; a.u = it.u; a.lam = it.lam; a.y = it.y;
+    a.sig_x = it.sig_x; a.sig_u = it.sig_u; a.sig_s = it.sig_s; a.r = it.r;
+    a.K = it.K; a.ldk = long(it.ldk); a.rhs = it.rhs;
+  }
+  // the instances' own streams may still run earlier work on them
+  for (rh_net* n : b->nets)
+    if (n->stream != b->stream) RH_HIP(hipStreamSynchronize(n->stream));
+  RH_TRY(batch_upload(b));
+  RH_HIP(rh::launch_batch_condense(b->d_nets, b->d_args, b->d_tiles, b->shape, b->stream));
+  for (rh_net* n : b->nets) {
+    n->condensed = true;
+    n->rhs_cols = true;
+  }
+  return RH_OK;
+}
+
+rh_status rh_batch_solve(rh_batch* b, const rh_batch_solve_item* items, int32_t* status) {
+  if (!b || !items) return RH_ERR_ARG;
+  for (size_t i = 0; i < b->nets.size(); ++i) {
+    const rh_batch_solve_item& it = items[i];
+    rh_net* n = b->nets[i];
+    if (!it.K || !it.rhs || !it.r || !it.p || it.ldk < n->d.nu || !(it.delta_w >= 0.0))
+      return RH_ERR_ARG;
+    if (!n->condensed || !n->rhs_cols) return RH_ERR_STATE;
+    rh::BatchArg& a = b->h_args[i];
+    a = rh::BatchArg{};
+    a.K = it.K; a.ldk = long(it.ldk); a.delta = it.delta_w; a.rhs = const_cast<double*>(it.rhs);
+    a.r = it.r; a.p = it.p;
+  }
+  RH_TRY(batch_upload(b));
+  RH_HIP(rh::launch_batch_solve(b->d_nets, b->d_args, b->shape, b->stream));
+  RH_HIP(rh::launch_batch_status(b->d_nets, int(b->nets.size()), b->d_status, b->stream));
+  std::vector<int> hs(5 * b->nets.size());
+  RH_HIP(hipMemcpyAsync(hs.data(), b->d_status, sizeof(int) * hs.size(), hipMemcpyDeviceToHost,
+                        b->stream));
+  RH_HIP(hipStreamSynchronize(b->stream));
+  rh_status worst = RH_OK;
+  for (size_t i = 0; i < b->nets.size(); ++i) {
+    rh_status si = RH_OK;
+    if (hs[5 * i + 4] != 0) si = RH_ERR_STATE;
+    else if (hs[5 * i] != 0) si = RH_NOT_POSDEF;
+    else if (hs[5 * i + 2] != 0) si = RH_SMALL_PIVOT;
+    if (status) status[i] = si;
+    if (si != RH_OK && worst == RH_OK) worst = si;
+  }
+  return worst;
 }
 
 rh_status rh_eval_residual(rh_net* n, const double* x, const double* u, double* g, double* h,

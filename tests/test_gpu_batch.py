@@ -1,0 +1,98 @@
+"""Batched condensation and solve (rh_batch_*): a heterogeneous batch (two
+load scenarios of the 1354-bus network, 118-, 300- and 9-bus networks) gives,
+instance by instance, bit for bit the K_cond, right-hand side and step of the
+single-instance calls (same kernel bodies, same summation order), and so the
+oracle's values within the parity tolerances."""
+import numpy as np
+import pytest
+
+import synthnet
+from oracle.model import Model
+from oracle import reduction as R
+from helpers import random_point, residual_vector
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _api():
+    from paper_2203_11875_amd import api
+    return api
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _batch_nets():
+    base = synthnet.case1354(0)
+    return [base, synthnet.scale_loads(base, 7), synthnet.case118(0), synthnet.case300(0),
+            synthnet.case9(0)]
+
+
+def test_batch_matches_single_instance_bitwise():
+    api = _api()
+    nets = _batch_nets()
+    Gs = [api.Net(n) for n in nets]
+    pts, rs = [], []
+    for i, n in enumerate(nets):
+        M = Model(n)
+        pts.append(random_point(M, 10 + i, sig_range=(10.0, 1e4)))
+        rs.append(residual_vector(M, 20 + i))
+    B = api.Batch(Gs)
+    Kb, rhsb = B.condense([p + (r,) for p, r in zip(pts, rs)])
+    pb, stb = B.solve([K.clone() for K in Kb], 0.0, rhsb, rs)
+    torch.cuda.synchronize()
+    assert stb[0] == 0 and stb[1] == 0      # the 1354-bus members are positive definite here
+    for i, (G, p, r) in enumerate(zip(Gs, pts, rs)):
+        K, rhs = G.condense_reduced_hessian(*p, r=r)
+        ps, code = G.solve_condensed_kkt(K.clone(), 0.0, rhs, r)
+        torch.cuda.synchronize()
+        assert code == stb[i], nets[i].name
+        assert np.array_equal(_np(K), _np(Kb[i])), nets[i].name
+        assert np.array_equal(_np(rhs), _np(rhsb[i])), nets[i].name
+        if code == 0:
+            assert np.array_equal(_np(ps), _np(pb[i])), nets[i].name
+    B.close()
+
+
+def test_batch_matches_oracle_small_instances():
+    """The 9- and 118-bus members against the oracle's explicit condensation."""
+    api = _api()
+    nets = [synthnet.case9(0), synthnet.case118(0), synthnet.small(5, 7, 2, seed=1)]
+    Gs = [api.Net(n) for n in nets]
+    Ms = [Model(n) for n in nets]
+    pts = [random_point(M, 3) for M in Ms]
+    rs = [residual_vector(M, 4) for M in Ms]
+    B = api.Batch(Gs)
+    Kb, rhsb = B.condense([p + (r,) for p, r in zip(pts, rs)])
+    torch.cuda.synchronize()
+    for M, p, r, K, rhs in zip(Ms, pts, rs, Kb, rhsb):
+        blocks = R.kkt_blocks(M, *p)
+        Kref = R.symmetrize(R.condensed_matrix(blocks))
+        Kg = _np(K).T
+        assert np.linalg.norm(Kg - Kref) <= 1e-8 * np.linalg.norm(Kref)
+    B.close()
+
+
+def test_batch_rejects_mixed_widths_and_solve_before_condense():
+    api = _api()
+    G1 = api.Net(synthnet.case9(0), panel_width=1)
+    G2 = api.Net(synthnet.case9(1), panel_width=2)
+    with pytest.raises(Exception):
+        api.Batch([G1, G2])
+    G3 = api.Net(synthnet.case9(2))
+    B = api.Batch([G3])
+    M = Model(synthnet.case9(2))
+    r = residual_vector(M, 1)
+    with pytest.raises(Exception):
+        B.solve([torch.zeros((M.nu, M.nu), dtype=torch.float64, device="cuda")], 0.0,
+                [np.zeros(M.nu)], [r])
+    B.close()
