@@ -887,7 +887,7 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
 void build_condense_records(const Symbolic& s, int W, CondenseRecords& R) {
   const long nw = s.nw, nu = s.nu;
   auto p_row = [&](long v) { return unsigned(v * W * 8); };                          // P row v
-  auto h_row = [&](long v) { return unsigned((nw + 1 + s.kst.pos[v]) * W * 8); };  // H row v
+  auto h_row = [&](long v) { return unsigned(s.kst.pos[v] * W * 8); };   // H row v (over P)
   const Sweep* sws[4] = {&s.sl, &s.su, &s.sut, &s.slt};
   size_t nsteps = 0;
   for (auto* sw : sws) nsteps += size_t(sw->ks_nstep) + 1;
@@ -1178,7 +1178,7 @@ rh_status host_check_condense(const Symbolic& s, int W, uint64_t seed, int ncols
     const int j = cols[ci];
     const bool rhs = j == nu;
     // ---- emulation of the condensation kernel for column 0 of a W-wide panel
-    std::vector<double> pan(size_t(2 * nw + 1) * W, 0.0);
+    std::vector<double> pan(size_t(nw + 1) * W, 0.0), scr(size_t(nw) * W, 0.0);
     auto at = [&](unsigned off) -> double& { return pan[off / 8]; };
     if (rhs) {
       pan[size_t(nw) * W] = 1.0;
@@ -1241,12 +1241,13 @@ rh_status host_check_condense(const Symbolic& s, int W, uint64_t seed, int ncols
             acc = std::fma(v, at(o), acc);
             while (b < int(ls.end.size()) && q + 1 == ls.end[b]) {
               const int p = b * kKRowBlock + t;
-              if (p < nw) pan[size_t(nw + 1 + p) * W] = acc;
+              if (p < nw) scr[size_t(p) * W] = acc;
               acc = 0.0;
               ++b;
             }
           }
         }
+        for (int p = 0; p < nw; ++p) pan[size_t(p) * W] = scr[size_t(p) * W];   // H over P
       }
     }
     std::vector<double> out(nu);

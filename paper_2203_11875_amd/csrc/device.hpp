@@ -57,6 +57,7 @@ struct DevNet {
   // batch; block ends per lane; destinations of the K entries, rt terms and
   // G_u entries); H position of each w row, control at each G position.
   double* lblk;
+  double* hscr;           // per column tile: nw x W doubles of H before it replaces P
   int tr_n, trd_n;
   const int *tr_dst, *tr_src, *trd_dst, *trd_src;
   double *kstr, *gstr;

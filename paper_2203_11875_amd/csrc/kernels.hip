@@ -836,10 +836,10 @@ __device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
 // Column nu (if requested) is the condensed right-hand side: V = 0, Z = -G_x^{-1} r4,
 // H += rt, and rhs = -out. In MODE_RECOVER (one column): V = p_u,
 // Z = -G_x^{-1}(r4 + G_u p_u) = p_x, H += rt, Psi = -p_lambda.
-// Panels (LDS or global, W doubles per row): P = [V; Z; indicator] (nw + 1
+// Panel (LDS or global, W doubles per row): P = [V; Z; indicator] (nw + 1
 // rows; the indicator row is 1 in the right-hand-side / recovery column and
-// multiplies each K row's rt term), then H (nw rows, in K-stream order:
-// w row v at hpos[v]).
+// multiplies each K row's rt term), then H over its first nw rows (in
+// K-stream order: w row v at hpos[v]).
 template <int W, bool LDS, int mode>
 __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int col0, int col_end,
                                                 const double* r, const double* vin, double* K,
@@ -850,12 +850,12 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
     return;
   }
   const int nw = d.nw, nu = d.nu, nx = d.nx;
-  double* P = LDS ? panel_lds : d.panel + (size_t)blk * (2 * nw + 1) * W;
-  double* H = P + (size_t)(nw + 1) * W;
+  double* P = LDS ? panel_lds : d.panel + (size_t)blk * (nw + 1) * W;
+  double* H = P;   // H replaces P after the Hessian product
   char* pb = reinterpret_cast<char*>(P);
   // step metadata of the four sweeps (with their idle steps) and the block
   // ends of the two record streams, staged in LDS
-  int4* m_sl = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(2 * nw + 1) * W : 0));
+  int4* m_sl = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(nw + 1) * W : 0));
   int4* m_su = m_sl + d.sl.nstep + 1;
   int4* m_sut = m_su + d.su.nstep + 1;
   int4* m_slt = m_sut + d.sut.nstep + 1;
@@ -923,14 +923,25 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
     }
   }
   // H = K [V ; Z] (+ rt through the indicator row), row block by row block,
-  // H rows in stream order
+  // H rows in stream order; P is read to the end of the product, so H goes to
+  // the tile's global scratch and then over P (its rows 0 .. nw - 1)
+  double* scr = d.hscr + (size_t)blk * nw * W;
   row_stream<W, LDS>(d.kstr, d.kst_nbat, kb_end, d.kb_n, pb,
                      [&](int b, const double(&acc)[W]) {
                        const int p = b * kKRowBlock + tid;
                        if (p < nw)
 #pragma unroll
-                         for (int c = 0; c < W; ++c) H[p * W + c] = acc[c];
+                         for (int c = 0; c < W; ++c) scr[p * W + c] = acc[c];
                      });
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");   // the scratch stores complete
+  for (int i0 = tid; i0 < nw * W; i0 += 8 * T) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = scr[min(i0 + k * T, nw * W - 1)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + k * T < nw * W) H[i0 + k * T] = v[k];
+  }
   panel_sync<LDS>();
   tick(d, 4);
   sweep<W, LDS>(d.sut, d.lblk, m_sut, pb);
@@ -950,24 +961,23 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
     indexed_loop(d.hpos + nu, nx, [&](int i, int hp) { plam[d.perm[i]] = -H[hp * W]; });
     return;
   }
-  // out = H_u - G_u^T Psi: the stream sums G_u^T Psi - H_u; written over the
-  // (no longer needed) V rows of P in stream order, then to K / rhs
+  // out = H_u - G_u^T Psi: the stream sums G_u^T Psi - H_u per control, written
+  // to the K_cond column (rhs = -out for the right-hand-side column)
   row_stream<W, LDS>(d.gstr, d.gst_nbat, gt_end, d.gt_nb, pb,
                      [&](int b, const double(&acc)[W]) {
                        const int p = b * kKRowBlock + tid;
-                       if (p < nu)
+                       if (p < nu) {
+                         const int q = d.grow[p];
 #pragma unroll
-                         for (int c = 0; c < W; ++c) P[p * W + c] = -acc[c];
+                         for (int c = 0; c < W; ++c) {
+                           const int j = jc0 + c;
+                           if (j < nu)
+                             K[(size_t)j * ldk + q] = -acc[c];
+                           else if (j < col_end)
+                             rhs[q] = acc[c];
+                         }
+                       }
                      });
-  panel_sync<LDS>();
-  for (int c = 0; c < W; ++c) {
-    const int j = jc0 + c;
-    if (j >= col_end) break;
-    if (j < nu)
-      indexed_loop(d.grow, nu, [&](int p, int q) { K[(size_t)j * ldk + q] = P[p * W + c]; });
-    else
-      indexed_loop(d.grow, nu, [&](int p, int q) { rhs[q] = -P[p * W + c]; });
-  }
   tick(d, 7);
 }
 template <int W, bool LDS, int mode>
@@ -1587,7 +1597,7 @@ size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels) {
   const size_t meta = sizeof(int) * (kSweepMeta * (size_t)(d.sl.nstep + d.su.nstep + d.sut.nstep +
                                                            d.slt.nstep + 4) +
                                      (size_t)d.kb_n + (size_t)d.gt_nb);
-  return (lds_panels ? (size_t)(2 * d.nw + 1) * width * sizeof(double) : 0) + meta;
+  return (lds_panels ? (size_t)(d.nw + 1) * width * sizeof(double) : 0) + meta;
 }
 
 void prepare_lds_kernels() {

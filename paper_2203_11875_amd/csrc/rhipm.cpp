@@ -408,11 +408,12 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   rh::prepare_lds_kernels();
   d.panel = nullptr;
   d.panel_doubles = 0;
+  const size_t ntile = (size_t(s.nu) + 1 + want - 1) / want;
   if (!lds) {
-    const size_t nblk = (size_t(s.nu) + 1 + want - 1) / want;
-    d.panel_doubles = nblk * 2 * size_t(s.nw) * want;
+    d.panel_doubles = ntile * (size_t(s.nw) + 1) * want;
     RH_TRY(alloc(n, d.panel_doubles, &d.panel));
   }
+  RH_TRY(alloc(n, ntile * size_t(s.nw) * want, &d.hscr));
   if (size_t(s.rf_lds_doubles) * sizeof(double) > lds_max) return RH_ERR_ARG;
   RH_HIP(hipDeviceSynchronize());
   return RH_OK;
