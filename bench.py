@@ -83,7 +83,9 @@ def batched_run(api, torch, steps, warmup):
     T = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=dev)
     Gs = [api.Net(n) for n in nets]
     pts = [tuple(map(T, iterate(G, n, seed=i))) for i, (G, n) in enumerate(zip(Gs, nets))]
-    B = api.Batch(Gs)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    B = api.Batch(Gs, stream=stream)
     delta = np.zeros(len(nets))
 
     def step():
@@ -91,25 +93,37 @@ def batched_run(api, torch, steps, warmup):
         _, st = B.solve(Ks, delta, rhss, [p[7] for p in pts])
         return st
 
-    for _ in range(max(1, warmup)):
-        st = step()
-        for _ in range(20):       # inertia correction per instance, as in an IPM iteration
-            bad = [i for i, c in enumerate(st) if c == 1]
-            if not bad:
-                break
-            for i in bad:
-                delta[i] = 1e-4 if delta[i] == 0.0 else delta[i] * 8.0
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, warmup)):
             st = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+            for _ in range(20):       # inertia correction per instance, as in an IPM iteration
+                bad = [i for i, c in enumerate(st) if c == 1]
+                if not bad:
+                    break
+                for i in bad:
+                    delta[i] = 1e-4 if delta[i] == 0.0 else delta[i] * 8.0
+                st = step()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        stream.synchronize()
+        el = time.perf_counter() - t0
+        # the same step captured in a HIP graph and replayed
+        B.capture(pts, delta)
+        B.replay()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.replay()
+        stream.synchronize()
+        el_graph = time.perf_counter() - t0
     B.close()
     n = len(nets)
     return {"instances": n, "condensations_per_s": n * steps / el,
-            "ms_per_batch_step": 1e3 * el / steps, "steps": steps,
+            "ms_per_batch_step": 1e3 * el / steps,
+            "graph_condensations_per_s": n * steps / el_graph,
+            "graph_ms_per_batch_step": 1e3 * el_graph / steps, "steps": steps,
             "composition": "64 x syn1354 load scenarios (nu 519), 32 x syn118 (nu 107), "
                            "16 x syn300 (nu 137)",
             "step": "batched eval + refactor + condense + symmetrize + Cholesky + solve + "
@@ -308,6 +322,11 @@ def main():
         line["ipm"] = ipm_run(api, net, torch, args.ipm_iters)
     if not args.no_batch:
         line["batched"] = batched_run(api, torch, args.batch_steps, 2)
+        best, times = api.autotune(net, (x, u, lam, y, sx, su, ss, r), widths=(1, 2, 4),
+                                   lds=(1, 0), reps=3)
+        line["autotune"] = {"best": {"panel_width": best[0], "lds_panel": best[1]},
+                            "condensation_us": {f"w{w}_lds{l}": round(v, 1)
+                                                for (w, l), v in times.items()}}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args_np, args.cpu_seconds)
     print(json.dumps(line), flush=True)

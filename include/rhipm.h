@@ -183,8 +183,8 @@ rh_status rh_set_loads(rh_net* net, const double* pd_dev, const double* qd_dev);
  * Batches (several networks or load scenarios condensed and solved together;
  * Sections 3.3-3.4 per instance). A batch refers to existing handles, which
  * must share the panel width and LDS placement (the defaults do) and must
- * not be used by other calls while a batch call runs; the handles outlive
- * the batch. Every batched kernel serves all instances in one launch, with
+ * not be used by other calls while a batch call runs (each batch call first
+ * waits for the instances' own streams); the handles outlive the batch. Every batched kernel serves all instances in one launch, with
  * the same kernel bodies as the single-instance calls, so each instance's
  * results equal, bit for bit, those of rh_condense_reduced_hessian (with r)
  * and rh_solve_condensed_kkt on the same inputs. hip_stream: the batch's
@@ -218,6 +218,19 @@ rh_status rh_batch_condense(rh_batch* batch, const rh_batch_condense_item* items
  * first non-OK code or RH_OK. Synchronises the batch stream. RH_ERR_STATE if
  * an instance was not condensed with a right-hand side before. */
 rh_status rh_batch_solve(rh_batch* batch, const rh_batch_solve_item* items, int32_t* status);
+/* One batched step (condensation of every instance, then its solve and
+ * recovery) captured once into a HIP graph on the batch stream (which must
+ * not be NULL) and replayed: the graph's kernels read the instances'
+ * descriptors and arguments from device arrays that rh_batch_replay
+ * refreshes before each launch, so new items (same shapes) need no new
+ * capture. solve items must use the condensation items' K, ldk, rhs and r.
+ * rh_batch_replay: items may both be NULL (reuse the captured ones); status
+ * as rh_batch_solve; RH_ERR_STATE without a capture. The graph holds kernel
+ * launches only. */
+rh_status rh_batch_capture(rh_batch* batch, const rh_batch_condense_item* citems,
+                           const rh_batch_solve_item* sitems);
+rh_status rh_batch_replay(rh_batch* batch, const rh_batch_condense_item* citems,
+                          const rh_batch_solve_item* sitems, int32_t* status);
 
 /* g (nx), h (m), f (1): device outputs at device inputs x (nx), u (nu)
  * (Section 2.1's functions of the state-control form). */

@@ -101,6 +101,10 @@ SIGNATURES = {
     "rh_batch_destroy": (None, [vp]),
     "rh_batch_condense": (C.c_int, [vp, C.POINTER(rh_batch_condense_item)]),
     "rh_batch_solve": (C.c_int, [vp, C.POINTER(rh_batch_solve_item), i32p]),
+    "rh_batch_capture": (C.c_int, [vp, C.POINTER(rh_batch_condense_item),
+                                   C.POINTER(rh_batch_solve_item)]),
+    "rh_batch_replay": (C.c_int, [vp, C.POINTER(rh_batch_condense_item),
+                                  C.POINTER(rh_batch_solve_item), i32p]),
 }
 
 PHASES = ["eval", "refactor", "condense", "symmetrize", "cholesky", "recover"]

@@ -8,6 +8,7 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
+from ._abi import RhError
 
 _LIB = None
 
@@ -243,6 +244,36 @@ class Net:
         return p, code
 
 
+def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), reps=3):
+    """Launch-shape autotuner: times the condensation (all columns with the
+    right-hand side) of `net` at `point` = (x, u, lam, y, sig_x, sig_u,
+    sig_s, r) for each panel width and panel placement, and returns
+    (best (width, lds), {(width, lds): microseconds}). Configurations the
+    device cannot hold are skipped."""
+    import time
+    import torch
+    times = {}
+    for w in widths:
+        for l in lds:
+            try:
+                G = Net(net, panel_width=w, lds_panel=l)
+            except RhError:
+                continue
+            if (int(G.info["panel_width"]), int(G.info["lds_panel"])) != (w, l):
+                G.close()
+                continue
+            G.condense_reduced_hessian(*point[:7], r=point[7])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                G.condense_reduced_hessian(*point[:7], r=point[7])
+            torch.cuda.synchronize()
+            times[(w, l)] = 1e6 * (time.perf_counter() - t0) / reps
+            G.close()
+    best = min(times, key=times.get)
+    return best, times
+
+
 class Batch:
     """Several device network handles condensed and solved together
     (rh_batch_*): one launch per kernel for all instances."""
@@ -305,6 +336,46 @@ class Batch:
             _check(code, "rh_batch_solve")
         self._keep = keep
         return ps, [int(v) for v in st]
+
+    def _items(self, points, delta_w):
+        t = self.torch
+        ci = (_abi.rh_batch_condense_item * len(self.nets))()
+        si = (_abi.rh_batch_solve_item * len(self.nets))()
+        keep, Ks, rhss, ps = [], [], [], []
+        for i, (G, pt) in enumerate(zip(self.nets, points)):
+            nx, nu, m = G.nx, G.nu, G.m
+            x, u, lam, y, sx, su, ss, r = pt
+            a = [G._t(x, nx), G._t(u, nu), G._t(lam, nx), G._t(y, m), G._t(sx, nx),
+                 G._t(su, nu), G._t(ss, m), G._t(r, nu + 2 * nx + 2 * m)]
+            K = t.empty((nu, nu), dtype=t.float64, device=G.device)
+            rhs = t.empty(nu, dtype=t.float64, device=G.device)
+            p = t.empty(nu + 2 * nx + 2 * m, dtype=t.float64, device=G.device)
+            for name, v in zip(("x", "u", "lam", "y", "sig_x", "sig_u", "sig_s", "r"), a):
+                setattr(ci[i], name, _ptr(v))
+            ci[i].K, ci[i].ldk, ci[i].rhs = _ptr(K), nu, _ptr(rhs)
+            si[i].K, si[i].ldk, si[i].rhs, si[i].r, si[i].p = _ptr(K), nu, _ptr(rhs), _ptr(a[7]), _ptr(p)
+            si[i].delta_w = float(delta_w[i] if hasattr(delta_w, "__len__") else delta_w)
+            keep.append(a)
+            Ks.append(K)
+            rhss.append(rhs)
+            ps.append(p)
+        return ci, si, keep, Ks, rhss, ps
+
+    def capture(self, points, delta_w=0.0):
+        """Capture one batched step (condensation + solve) into a HIP graph
+        (rh_batch_capture); replay() runs it again on the same buffers."""
+        ci, si, keep, Ks, rhss, ps = self._items(points, delta_w)
+        _check(lib().rh_batch_capture(self.h, ci, si), "rh_batch_capture")
+        self._graph = (ci, si, keep, Ks, rhss, ps)
+
+    def replay(self):
+        """Returns (Ks, rhss, ps, status codes) of the captured step's buffers."""
+        ci, si, keep, Ks, rhss, ps = self._graph
+        st = (C.c_int32 * len(self.nets))()
+        code = lib().rh_batch_replay(self.h, None, None, st)
+        if code < 0 and not any(int(v) for v in st):
+            _check(code, "rh_batch_replay")
+        return Ks, rhss, ps, [int(v) for v in st]
 
     def close(self):
         if getattr(self, "h", None) is not None and _LIB is not None:

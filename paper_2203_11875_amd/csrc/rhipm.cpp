@@ -127,6 +127,8 @@ rh_status alloc(rh_net* n, size_t count, T** out) {
 struct rh_batch {
   std::vector<rh_net*> nets;
   hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;          // captured condensation + solve (rh_batch_capture)
+  hipGraphExec_t graph_exec = nullptr;
   rh::BatchShape shape;
   rh::DevNet* d_nets = nullptr;
   rh::BatchArg* d_args = nullptr;
@@ -623,6 +625,8 @@ void rh_batch_destroy(rh_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   else (void)hipDeviceSynchronize();
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   (void)hipFree(b->d_nets);
   (void)hipFree(b->d_args);
   (void)hipFree(b->d_tiles);
@@ -631,6 +635,17 @@ void rh_batch_destroy(rh_batch* b) {
 }
 
 namespace {
+// the instances' own streams may still run earlier work on their buffers
+rh_status batch_wait_instances(rh_batch* b) {
+  std::vector<hipStream_t> seen;
+  for (rh_net* n : b->nets)
+    if (n->stream != b->stream && std::find(seen.begin(), seen.end(), n->stream) == seen.end()) {
+      seen.push_back(n->stream);
+      RH_HIP(hipStreamSynchronize(n->stream));
+    }
+  return RH_OK;
+}
+
 // the instances' current device descriptors (profiling or new loads change
 // them between calls) and the per-call arguments, to the device
 rh_status batch_upload(rh_batch* b) {
@@ -667,9 +682,7 @@ rh_status rh_batch_condense(rh_batch* b, const rh_batch_condense_item* items) {
     a.sig_x = it.sig_x; a.sig_u = it.sig_u; a.sig_s = it.sig_s; a.r = it.r;
     a.K = it.K; a.ldk = long(it.ldk); a.rhs = it.rhs;
   }
-  // the instances' own streams may still run earlier work on them
-  for (rh_net* n : b->nets)
-    if (n->stream != b->stream) RH_HIP(hipStreamSynchronize(n->stream));
+  RH_TRY(batch_wait_instances(b));
   RH_TRY(batch_upload(b));
   RH_HIP(rh::launch_batch_condense(b->d_nets, b->d_args, b->d_tiles, b->shape, b->stream));
   for (rh_net* n : b->nets) {
@@ -678,6 +691,10 @@ rh_status rh_batch_condense(rh_batch* b, const rh_batch_condense_item* items) {
   }
   return RH_OK;
 }
+
+namespace {
+rh_status batch_statuses(rh_batch* b, int32_t* status);
+}  // namespace
 
 rh_status rh_batch_solve(rh_batch* b, const rh_batch_solve_item* items, int32_t* status) {
   if (!b || !items) return RH_ERR_ARG;
@@ -692,8 +709,14 @@ rh_status rh_batch_solve(rh_batch* b, const rh_batch_solve_item* items, int32_t*
     a.K = it.K; a.ldk = long(it.ldk); a.delta = it.delta_w; a.rhs = const_cast<double*>(it.rhs);
     a.r = it.r; a.p = it.p;
   }
+  RH_TRY(batch_wait_instances(b));
   RH_TRY(batch_upload(b));
   RH_HIP(rh::launch_batch_solve(b->d_nets, b->d_args, b->shape, b->stream));
+  return batch_statuses(b, status);
+}
+
+namespace {
+rh_status batch_statuses(rh_batch* b, int32_t* status) {
   RH_HIP(rh::launch_batch_status(b->d_nets, int(b->nets.size()), b->d_status, b->stream));
   std::vector<int> hs(5 * b->nets.size());
   RH_HIP(hipMemcpyAsync(hs.data(), b->d_status, sizeof(int) * hs.size(), hipMemcpyDeviceToHost,
@@ -709,6 +732,71 @@ rh_status rh_batch_solve(rh_batch* b, const rh_batch_solve_item* items, int32_t*
     if (si != RH_OK && worst == RH_OK) worst = si;
   }
   return worst;
+}
+
+// condensation + solve arguments in one BatchArg per instance
+rh_status batch_fill_step(rh_batch* b, const rh_batch_condense_item* ci,
+                          const rh_batch_solve_item* si) {
+  for (size_t i = 0; i < b->nets.size(); ++i) {
+    const rh_batch_condense_item& c = ci[i];
+    const rh_batch_solve_item& q = si[i];
+    const int nu = b->nets[i]->d.nu;
+    if (!c.x || !c.u || !c.lam || !c.y || !c.sig_x || !c.sig_u || !c.sig_s || !c.r || !c.K ||
+        !c.rhs || c.ldk < nu || q.K != c.K || q.ldk != c.ldk || q.rhs != c.rhs || q.r != c.r ||
+        !q.p || !(q.delta_w >= 0.0))
+      return RH_ERR_ARG;
+    rh::BatchArg& a = b->h_args[i];
+    a = rh::BatchArg{};
+    a.x = c.x; a.u = c.u; a.lam = c.lam; a.y = c.y;
+    a.sig_x = c.sig_x; a.sig_u = c.sig_u; a.sig_s = c.sig_s; a.r = c.r;
+    a.K = c.K; a.ldk = long(c.ldk); a.rhs = c.rhs; a.p = q.p; a.delta = q.delta_w;
+  }
+  return RH_OK;
+}
+}  // namespace
+
+rh_status rh_batch_capture(rh_batch* b, const rh_batch_condense_item* citems,
+                           const rh_batch_solve_item* sitems) {
+  if (!b || !citems || !sitems || !b->stream) return RH_ERR_ARG;
+  RH_TRY(batch_fill_step(b, citems, sitems));
+  RH_TRY(batch_wait_instances(b));
+  RH_TRY(batch_upload(b));
+  RH_HIP(hipStreamSynchronize(b->stream));
+  if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  RH_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e1 = rh::launch_batch_condense(b->d_nets, b->d_args, b->d_tiles, b->shape, b->stream);
+  hipError_t e2 = rh::launch_batch_solve(b->d_nets, b->d_args, b->shape, b->stream);
+  hipGraph_t g = nullptr;
+  hipError_t e3 = hipStreamEndCapture(b->stream, &g);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return RH_ERR_HIP;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    b->graph_exec = nullptr;
+    return RH_ERR_HIP;
+  }
+  return RH_OK;
+}
+
+rh_status rh_batch_replay(rh_batch* b, const rh_batch_condense_item* citems,
+                          const rh_batch_solve_item* sitems, int32_t* status) {
+  if (!b || !b->graph_exec) return RH_ERR_STATE;
+  if (citems || sitems) {
+    if (!citems || !sitems) return RH_ERR_ARG;
+    RH_TRY(batch_fill_step(b, citems, sitems));
+  }
+  // refresh the device descriptors and arguments the graph's kernels read
+  RH_TRY(batch_wait_instances(b));
+  RH_TRY(batch_upload(b));
+  RH_HIP(hipGraphLaunch(b->graph_exec, b->stream));
+  for (rh_net* n : b->nets) {
+    n->condensed = true;
+    n->rhs_cols = true;
+  }
+  return batch_statuses(b, status);
 }
 
 rh_status rh_eval_residual(rh_net* n, const double* x, const double* u, double* g, double* h,

@@ -96,3 +96,48 @@ def test_batch_rejects_mixed_widths_and_solve_before_condense():
         B.solve([torch.zeros((M.nu, M.nu), dtype=torch.float64, device="cuda")], 0.0,
                 [np.zeros(M.nu)], [r])
     B.close()
+
+
+def test_batch_graph_replays_match_eager():
+    """The captured batched step (HIP graph, kernel launches only), replayed
+    several times with eager work of the same handles in between, gives the
+    eager batched results bit for bit on every replay."""
+    api = _api()
+    nets = [synthnet.case118(0), synthnet.case9(0), synthnet.case300(0)]
+    stream = torch.cuda.Stream()
+    Gs = [api.Net(n) for n in nets]
+    pts = []
+    for i, n in enumerate(nets):
+        M = Model(n)
+        p = random_point(M, 30 + i, sig_range=(10.0, 1e4))
+        pts.append(tuple(torch.as_tensor(np.asarray(v, np.float64), device="cuda")
+                         for v in p + (residual_vector(M, 40 + i),)))
+    with torch.cuda.stream(stream):
+        B = api.Batch(Gs, stream=stream)
+        Ke, rhse = B.condense(pts)
+        pe, ste = B.solve([K.clone() for K in Ke], 0.0, rhse, [p[7] for p in pts])
+        Ke = [_np(K) for K in Ke]
+        B.capture(pts, 0.0)
+        for rep in range(3):
+            Ks, rhss, ps, st = B.replay()
+            stream.synchronize()
+            assert st == ste
+            for i in range(len(nets)):
+                assert np.array_equal(_np(rhss[i]), _np(rhse[i])), (rep, i)
+                if st[i] == 0:
+                    assert np.array_equal(_np(ps[i]), _np(pe[i])), (rep, i)
+            # eager work on the same handles between replays (on their own stream)
+            Gs[0].condense_reduced_hessian(*pts[0][:7], r=pts[0][7])
+            torch.cuda.synchronize()
+        B.close()
+
+
+def test_autotuner_picks_a_measured_configuration():
+    api = _api()
+    net = synthnet.case118(0)
+    M = Model(net)
+    pt = random_point(M, 5) + (residual_vector(M, 6),)
+    pt = tuple(torch.as_tensor(np.asarray(v, np.float64), device="cuda") for v in pt)
+    best, times = api.autotune(net, pt, widths=(1, 2), lds=(1, 0), reps=2)
+    assert best in times and len(times) == 4
+    assert times[best] == min(times.values())
