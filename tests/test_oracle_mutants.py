@@ -121,3 +121,63 @@ def test_charging_not_halved_is_caught(monkeypatch):
         self.y_ff = 1.0 / z + 1.0j * np.asarray(net.b)   # full b at each end
     monkeypatch.setattr(om.Model, "__init__", init)
     assert _caught()
+
+
+# ---------------------------------------------------------------- sensitivity
+import oracle.sensitivity as osn
+import test_oracle_sensitivity as ts
+
+SENS_PINS = [
+    lambda: ts.test_load_jacobian_matches_residual_differences("syn5"),
+    lambda: ts.test_sensitivity_matches_differences_of_barrier_solution("syn5", 1e-3),
+    lambda: ts.test_objective_gradient_is_envelope("syn5"),
+]
+_ORIG_FP = osn.load_jacobian
+_ORIG_C = osn.output_jacobian
+
+
+def _fp_no_cost_term(ipm, w, s):
+    Fp = _ORIG_FP(ipm, w, s)
+    o = osn.offsets(ipm)
+    Fp[o[0]:o[2], ipm.M.ref] = 0.0
+    return Fp
+
+
+def _fp_qg_rows_negated(ipm, w, s):
+    Fp = _ORIG_FP(ipm, w, s)
+    o = osn.offsets(ipm)
+    Fp[o[4] + 1:o[4] + 1 + ipm.M.ng, :] *= -1.0
+    return Fp
+
+
+def _c_pg_ref_sign(ipm, w, s):
+    C = _ORIG_C(ipm, w, s)
+    o = osn.offsets(ipm)
+    C[:, o[2]] *= -1.0
+    return C
+
+
+SENS_MUTANTS = {
+    "cost_term_of_pd_ref_dropped": _fp_no_cost_term,
+    "qg_load_rows_negated": _fp_qg_rows_negated,
+    "pg_ref_output_sign": _c_pg_ref_sign,
+}
+
+
+@pytest.mark.parametrize("name", sorted(SENS_MUTANTS))
+def test_sensitivity_mutant_is_caught(name, monkeypatch):
+    attr = "load_jacobian" if name != "pg_ref_output_sign" else "output_jacobian"
+    monkeypatch.setattr(osn, attr, SENS_MUTANTS[name])
+    caught = False
+    for pin in SENS_PINS:
+        try:
+            pin()
+        except (AssertionError, np.linalg.LinAlgError):
+            caught = True
+            break
+    assert caught, f"mutant {name} survived every pin"
+
+
+def test_unmutated_sensitivity_passes_its_pins():
+    for pin in SENS_PINS:
+        pin()
