@@ -367,6 +367,39 @@ rh_status rh_ipm_solve(rh_ipm* ipm, rh_ipm_info* info);
 /* Device copies of the current point (any pointer may be NULL). */
 rh_status rh_ipm_get_state(const rh_ipm* ipm, double* x, double* u, double* s, double* lam,
                            double* y);
+/* ---------------------------------------------------------------------------
+ * Differentiation of the solution in the loads (implicit function theorem
+ * at the final barrier problem). With the bound multipliers eliminated, the
+ * barrier problem's first-order conditions F(w, s, lambda, y; Pd, Qd) = 0 have
+ * the augmented matrix K_aug of the KKT system (Section 2.2.1, eq.
+ * kktmatrix:normal) as Jacobian, so d(solution)/d(loads) = -K_aug^{-1} dF/dp.
+ * K_aug is symmetric: the gradient of a weighted sum of outputs needs one
+ * adjoint solve K_aug xi = c, done by the reduction and condensation of
+ * Theorems 1-2 (the condensed matrix at the final iterate, its Cholesky
+ * factor, two sparse triangular solves for the recovery), then the sparse
+ * product -xi^T dF/dp: the loads enter the P balance rows (non-reference
+ * buses), the Q balance rows (PQ buses), h_0 = Pg_ref (Pd at the reference
+ * bus), h_{1+g} = Qg (Qd at generator buses) and, through the cost of Pg_ref,
+ * the stationarity rows (2 c2_ref base^2 grad h_0 in Pd_ref).
+ * ------------------------------------------------------------------------- */
+/* Outputs at the current point, device arrays (any may be NULL): pg[ng] in
+ * generator order (the reference generator's Pg is -s_0, equal to
+ * P_ref + Pd_ref at a solution), vm[nb] in bus order, f[1] the objective with
+ * the network's own (unscaled) costs. Stream-ordered; RH_ERR_ARG, RH_ERR_HIP. */
+rh_status rh_ipm_outputs(const rh_ipm* ipm, double* pg, double* vm, double* f);
+/* Gradient of L = dpg . Pg + dvm . Vm + df * f (outputs as rh_ipm_outputs)
+ * with respect to the loads: gpd[nb], gqd[nb] (device, in the units of the
+ * descriptor's pd, qd). dpg[ng], dvm[nb], df[1] are device arrays; a NULL
+ * weight counts as zero. xi (device, nu + 2 nx + 2 m, optional) receives the
+ * adjoint solution packed as the step of rh_solve_condensed_kkt. Requires a
+ * converged solver (RH_ERR_STATE otherwise); the network must hold the loads
+ * it was solved with. Sigma is the final iterate's (bound multiplier / bound
+ * slack), with no inertia correction: RH_NOT_POSDEF if the condensed matrix
+ * is not positive definite there (then no gradient is written).
+ * RH_SMALL_PIVOT is not fatal. Overwrites the solver's step buffers (a later
+ * rh_ipm_step recomputes them). Synchronises the stream. */
+rh_status rh_ipm_backward(rh_ipm* ipm, const double* dpg, const double* dvm, const double* df,
+                          double* gpd, double* gqd, double* xi);
 /* Frees the solver and restores the network's objective scale to 1. */
 void rh_ipm_destroy(rh_ipm* ipm);
 

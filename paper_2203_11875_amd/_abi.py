@@ -97,6 +97,8 @@ SIGNATURES = {
     "rh_ipm_solve": (C.c_int, [vp, C.POINTER(rh_ipm_info)]),
     "rh_ipm_get_state": (C.c_int, [vp, vp, vp, vp, vp, vp]),
     "rh_ipm_destroy": (None, [vp]),
+    "rh_ipm_outputs": (C.c_int, [vp, vp, vp, vp]),
+    "rh_ipm_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "rh_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]),
     "rh_batch_destroy": (None, [vp]),
     "rh_batch_condense": (C.c_int, [vp, C.POINTER(rh_batch_condense_item)]),

@@ -449,3 +449,96 @@ class Ipm:
         out = [t.empty(k, dtype=t.float64, device=n.device) for k in (n.nx, n.nu, n.m, n.nx, n.m)]
         _check(lib().rh_ipm_get_state(self.h, *[_ptr(a) for a in out]), "rh_ipm_get_state")
         return dict(zip(("x", "u", "s", "lam", "y"), out))
+
+    def outputs(self):
+        """(Pg per generator, Vm per bus, f) at the current point
+        (rh_ipm_outputs)."""
+        t, n = self.net.torch, self.net
+        pg = t.empty(n.info["ng"], dtype=t.float64, device=n.device)
+        vm = t.empty(n.info["nb"], dtype=t.float64, device=n.device)
+        f = t.empty(1, dtype=t.float64, device=n.device)
+        _check(lib().rh_ipm_outputs(self.h, _ptr(pg), _ptr(vm), _ptr(f)), "rh_ipm_outputs")
+        return pg, vm, f[0]
+
+    def backward(self, dpg=None, dvm=None, df=None, want_xi=False):
+        """Gradient of dpg . Pg + dvm . Vm + df f in (Pd, Qd) (rh_ipm_backward);
+        returns (grad_pd, grad_qd[, xi])."""
+        t, n = self.net.torch, self.net
+        nb, ng = n.info["nb"], n.info["ng"]
+        a = n._t(dpg, ng) if dpg is not None else None
+        b = n._t(dvm, nb) if dvm is not None else None
+        c = n._t(t.as_tensor(df, dtype=t.float64).reshape(1), 1) if df is not None else None
+        gpd = t.empty(nb, dtype=t.float64, device=n.device)
+        gqd = t.empty(nb, dtype=t.float64, device=n.device)
+        xi = (t.empty(n.nu + 2 * n.nx + 2 * n.m, dtype=t.float64, device=n.device)
+              if want_xi else None)
+        code = lib().rh_ipm_backward(self.h, _ptr(a), _ptr(b), _ptr(c), _ptr(gpd), _ptr(gqd),
+                                     _ptr(xi))
+        if code not in (_abi.RH_OK, _abi.RH_SMALL_PIVOT):
+            _check(code, "rh_ipm_backward")
+        return (gpd, gqd, xi) if want_xi else (gpd, gqd)
+
+
+class OPFLayer:
+    """Differentiable AC optimal power flow: loads (Pd, Qd) -> (Pg, Vm, f).
+
+    The forward pass sets the loads on the layer's device network and runs
+    the interior-point method to tol; the backward pass differentiates the
+    solution by the implicit function theorem (rh_ipm_backward: one adjoint
+    solve with the condensed KKT system at the final iterate). Each forward
+    call keeps its solver for its backward pass; the loads are set again
+    before differentiating, so several forward calls may precede the
+    backward ones."""
+
+    def __init__(self, net, tol=1e-8, max_iter=200, **net_kw):
+        self.net = net if isinstance(net, Net) else Net(net, **net_kw)
+        self.tol, self.max_iter = float(tol), int(max_iter)
+
+    def __call__(self, pd, qd):
+        return _OPFFunction.apply(pd, qd, self)
+
+    def _solve(self, pd, qd):
+        n = self.net
+        n.set_loads(pd, qd)
+        ipm = Ipm(n, tol=self.tol, max_iter=self.max_iter)
+        n._ipm = None       # the solver belongs to the autograd graph
+        code, info = ipm.solve()
+        if code != _abi.RH_OK:
+            _check(code, "rh_ipm_solve")
+        return ipm, info
+
+
+def _make_opf_function():
+    import torch
+
+    class _OPF(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, pd, qd, layer):
+            n = layer.net
+            pdd, qdd = n._t(pd, n.info["nb"]), n._t(qd, n.info["nb"])
+            ipm, info = layer._solve(pdd, qdd)
+            pg, vm, f = ipm.outputs()
+            ctx.ipm, ctx.layer, ctx.loads, ctx.info = ipm, layer, (pdd, qdd), info
+            return pg, vm, f
+
+        @staticmethod
+        def backward(ctx, gpg, gvm, gf):
+            n = ctx.layer.net
+            n.set_loads(*ctx.loads)
+            gpd, gqd = ctx.ipm.backward(gpg, gvm, gf)
+            return gpd, gqd, None
+
+    return _OPF
+
+
+class _Lazy:
+    def __init__(self):
+        self.fn = None
+
+    def apply(self, *a):
+        if self.fn is None:
+            self.fn = _make_opf_function()
+        return self.fn.apply(*a)
+
+
+_OPFFunction = _Lazy()

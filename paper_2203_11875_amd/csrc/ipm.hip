@@ -286,6 +286,86 @@ __global__ void __launch_bounds__(kVec) k_ipm_init_s(DevNet d, IpmDev v, double 
   if (j < v.m) v.s[j] = push_inside(-d.dst[d.d_h + j], v.sl[j], v.su[j], push, frac);
 }
 
+// ---------------------------------------------------------------------------
+// Differentiation of the solution in the loads (implicit function theorem at
+// the final barrier problem; the adjoint system is K_aug, symmetric, solved
+// through the same condensation).
+
+// Outputs: Pg of every generator (the reference generator's is -s_0, which
+// equals h_0 at a solution), Vm of every bus, f with unscaled costs.
+__global__ void __launch_bounds__(kRed) k_opf_outputs(DevNet d, IpmDev v, double inv_sigma,
+                                                     double* pg, double* vm, double* f) {
+  if (vm)
+    for (int i = threadIdx.x; i < d.nb; i += kRed)
+      vm[i] = d.vmu[i] >= 0 ? v.w[d.vmu[i]] : v.w[v.nu + d.vmx_nat[i]];
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < d.ng; g += kRed) {
+    const double p = d.pg_u[g] >= 0 ? v.w[d.pg_u[g]] : -v.s[0];
+    if (pg) pg[g] = p;
+    const double bp = d.base * p;
+    acc += (d.c2[g] * bp * bp + d.c1[g] * bp + d.c0[g]) * inv_sigma;
+  }
+  __shared__ double res[1];
+  double val[1] = {acc};
+  const int kind[1] = {2};
+  block_reduce<1>(val, kind, res);
+  __syncthreads();
+  if (threadIdx.x == 0 && f) f[0] = res[0];
+}
+
+__global__ void __launch_bounds__(kVec) k_fill_zero(double* x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// r = -c with c = (d outputs / d(w, s))^T (dpg, dvm, df); zero elsewhere
+// (cleared before). The Vm and Pg entries of u and the Vm entries of x are
+// distinct, so every thread writes its own entry.
+__global__ void __launch_bounds__(kVec) k_adjoint_rhs(DevNet d, IpmDev v, double inv_sigma,
+                                                     const double* dpg, const double* dvm,
+                                                     const double* df, double* r) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < d.nb && dvm) r[d.vmu[t] >= 0 ? d.vmu[t] : v.nu + d.vmx_nat[t]] = -dvm[t];
+  if (t < d.ng) {
+    const int k = d.pg_u[t];
+    const double p = k >= 0 ? v.w[k] : -v.s[0];
+    const double dcost = d.base * (2.0 * d.c2[t] * d.base * p + d.c1[t]) * inv_sigma;
+    const double c = (dpg ? dpg[t] : 0.0) + (df ? df[0] * dcost : 0.0);
+    if (k >= 0) r[k] = -c;
+    else r[v.nu + v.nx] = c;            // Pg_ref = -s_0: c_s0 = -c
+  }
+}
+
+// grad_p = -xi^T dF/dp: the loads enter the P and Q balance rows (lambda),
+// h_0 = Pg_ref and h_{1+g} = Qg (y), and through the cost of Pg_ref the
+// stationarity rows, as 2 c2_ref base^2 (grad h_0) in Pd_ref.
+__global__ void __launch_bounds__(kRed) k_adjoint_grad(DevNet d, IpmDev v, const double* xi,
+                                                      double* gpd, double* gqd) {
+  const int nw = v.nu + v.nx;
+  const double* xl = xi + nw + v.m;
+  const double* xy = xl + v.nx;
+  const double* A = d.dst + d.d_a;
+  double acc = 0.0;
+  for (int e = d.a_ptr[0] + threadIdx.x; e < d.a_ptr[1]; e += kRed) {
+    const int c = d.a_col[e];
+    acc += A[e] * xi[c < v.nu ? c : v.nu + d.perm[c - v.nu]];
+  }
+  __shared__ double a0[1];
+  double val[1] = {acc};
+  const int kind[1] = {2};
+  block_reduce<1>(val, kind, a0);
+  __syncthreads();
+  const double cref = 2.0 * d.c2_ref * d.base * d.base * a0[0];
+  for (int i = threadIdx.x; i < d.nb; i += kRed) {
+    double gp = d.th_nat[i] >= 0 ? xl[d.th_nat[i]] : 0.0;
+    if (i == d.ref) gp += xy[0] + cref;
+    double gq = d.vmx_nat[i] >= 0 ? xl[d.vmx_nat[i]] : 0.0;
+    if (d.vmu[i] >= 0) gq += xy[1 + d.vmu[i]];
+    gpd[i] = -gp;
+    gqd[i] = -gq;
+  }
+}
+
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 inline int vec_grid(const IpmDev& v) {
   int n = v.nu + v.nx;
@@ -337,6 +417,29 @@ hipError_t launch_ipm_init_s(const DevNet& d, const IpmDev& v, double push, doub
                              hipStream_t st) {
   hipLaunchKernelGGL(k_ipm_init_s, dim3(cdiv(v.m > 0 ? v.m : 1, kVec)), dim3(kVec), 0, st, d, v,
                      push, frac);
+  return hipGetLastError();
+}
+
+hipError_t launch_opf_outputs(const DevNet& d, const IpmDev& v, double inv_sigma, double* pg,
+                              double* vm, double* f, hipStream_t st) {
+  hipLaunchKernelGGL(k_opf_outputs, dim3(1), dim3(kRed), 0, st, d, v, inv_sigma, pg, vm, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_rhs(const DevNet& d, const IpmDev& v, double inv_sigma,
+                              const double* dpg, const double* dvm, const double* df, double* r,
+                              hipStream_t st) {
+  const int np = v.nu + 2 * v.nx + 2 * v.m;
+  hipLaunchKernelGGL(k_fill_zero, dim3(cdiv(np, kVec)), dim3(kVec), 0, st, r, np);
+  const int n = d.nb > d.ng ? d.nb : d.ng;
+  hipLaunchKernelGGL(k_adjoint_rhs, dim3(cdiv(n, kVec)), dim3(kVec), 0, st, d, v, inv_sigma, dpg,
+                     dvm, df, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_grad(const DevNet& d, const IpmDev& v, const double* xi, double* gpd,
+                               double* gqd, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint_grad, dim3(1), dim3(kRed), 0, st, d, v, xi, gpd, gqd);
   return hipGetLastError();
 }
 

@@ -67,4 +67,17 @@ hipError_t launch_ipm_init_w(const IpmDev& v, double push, double frac, hipStrea
 hipError_t launch_ipm_init_s(const DevNet& d, const IpmDev& v, double push, double frac,
                              hipStream_t st);
 
+// Differentiation in the loads. Outputs: pg[ng] (reference generator: -s_0),
+// vm[nb], f[1] (unscaled costs); any may be null.
+hipError_t launch_opf_outputs(const DevNet& d, const IpmDev& v, double inv_sigma, double* pg,
+                              double* vm, double* f, hipStream_t st);
+// r (packed r1..r5) = -(d outputs / d(w, s))^T (dpg, dvm, df); null weights are 0.
+hipError_t launch_adjoint_rhs(const DevNet& d, const IpmDev& v, double inv_sigma,
+                              const double* dpg, const double* dvm, const double* df, double* r,
+                              hipStream_t st);
+// gpd, gqd (nb) = -xi^T dF/d(Pd, Qd) for the packed adjoint xi (A values of the
+// last evaluation in d.dst).
+hipError_t launch_adjoint_grad(const DevNet& d, const IpmDev& v, const double* xi, double* gpd,
+                               double* gqd, hipStream_t st);
+
 }  // namespace rh

@@ -1222,6 +1222,8 @@ void rh_ipm_destroy(rh_ipm* p) {
 rh_status rh_ipm_step(rh_ipm* p, rh_ipm_info* info) {
   if (!p) return RH_ERR_ARG;
   rh_net* n = p->net;
+  // another solver on the same network may have changed the objective scale
+  if (n->obj_scale != p->sigma_f) RH_TRY(rh_set_objective_scale(n, p->sigma_f));
   auto& v = p->v;
   const auto& d = n->d;
   hipStream_t st = n->stream;
@@ -1353,6 +1355,42 @@ rh_status rh_ipm_solve(rh_ipm* p, rh_ipm_info* info) {
   }
   if (info) *info = last;
   return RH_OK;
+}
+
+rh_status rh_ipm_outputs(const rh_ipm* p, double* pg, double* vm, double* f) {
+  if (!p) return RH_ERR_ARG;
+  rh_net* n = p->net;
+  RH_HIP(rh::launch_opf_outputs(n->d, p->v, 1.0 / p->sigma_f, pg, vm, f, n->stream));
+  return RH_OK;
+}
+
+rh_status rh_ipm_backward(rh_ipm* p, const double* dpg, const double* dvm, const double* df,
+                          double* gpd, double* gqd, double* xi) {
+  if (!p || !gpd || !gqd) return RH_ERR_ARG;
+  if (!p->converged) return RH_ERR_STATE;
+  rh_net* n = p->net;
+  auto& v = p->v;
+  const auto& d = n->d;
+  hipStream_t st = n->stream;
+  const int nu = v.nu;
+  if (n->obj_scale != p->sigma_f) RH_TRY(rh_set_objective_scale(n, p->sigma_f));
+  {
+    PhaseScope ps(n, RH_PHASE_EVAL);
+    RH_HIP(rh::launch_eval(d, v.w + nu, v.w, v.lam, v.y, true, st));
+  }
+  // Sigma of the final iterate (the residuals prep writes are replaced by the
+  // adjoint right-hand side)
+  RH_HIP(rh::launch_ipm_prep(d, v, p->mu, st));
+  RH_HIP(rh::launch_adjoint_rhs(d, v, 1.0 / p->sigma_f, dpg, dvm, df, v.r, st));
+  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
+  const rh_status code = rh_solve_condensed_kkt(n, p->K, nu, 0.0, p->rhs, v.r, v.p, nullptr);
+  if (code != RH_OK && code != RH_SMALL_PIVOT) return code;
+  RH_HIP(rh::launch_adjoint_grad(d, v, v.p, gpd, gqd, st));
+  if (xi) {
+    const size_t np = size_t(nu) + 2 * size_t(v.nx) + 2 * size_t(v.m);
+    RH_HIP(hipMemcpyAsync(xi, v.p, sizeof(double) * np, hipMemcpyDeviceToDevice, st));
+  }
+  return code;
 }
 
 rh_status rh_ipm_get_state(const rh_ipm* p, double* x, double* u, double* s, double* lam,

@@ -1,0 +1,165 @@
+"""Differentiation of the OPF solution in the loads on the GPU
+(rh_ipm_outputs, rh_ipm_backward, api.OPFLayer) against the oracle's implicit
+differentiation (oracle.sensitivity) at the oracle's own optimum, both solved
+from the same start by the same method to 1e-8. The two optima agree to the
+solver tolerance, so the gradients are compared at 1e-5 of their largest
+entry; at the 1354-bus size the objective gradient is checked against the
+envelope theorem (multipliers of the GPU's own solution)."""
+import numpy as np
+import pytest
+
+import synthnet
+from oracle.ipm import LinRedIPM, IPMOptions, flat_start
+from oracle import sensitivity as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _api():
+    from paper_2203_11875_amd import api
+    return api
+
+
+NETS = {
+    "syn9-0": lambda: synthnet.case9(0),
+    "syn5": lambda: synthnet.small(5, 7, 2, seed=1),
+    "syn118": lambda: synthnet.case118(0),
+}
+
+
+def _weights(net, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(net.ng), rng.standard_normal(net.nb), 1e-3
+
+
+def _oracle(net, dpg, dvm, df):
+    ipm = LinRedIPM(net, IPMOptions(tol=1e-8))
+    x0, u0 = flat_start(ipm.M)
+    st, _, ok = ipm.solve(x0, u0)
+    assert ok
+    sw, ss = S.primal_dual_sigmas(ipm, st)
+    gpd, gqd, xi = S.load_gradient(ipm, st.w, st.s, st.lam, st.y, sw, ss, dpg, dvm, df)
+    return S.outputs(ipm, st.w, st.s), (gpd, gqd), xi
+
+
+@pytest.mark.parametrize("name", list(NETS))
+def test_layer_gradient_matches_oracle(name):
+    net = NETS[name]()
+    print(f"opf layer vs oracle: {name}", flush=True)
+    dpg, dvm, df = _weights(net, 11)
+    (opg, ovm, of), (ogpd, ogqd), _ = _oracle(net, dpg, dvm, df)
+    api = _api()
+    layer = api.OPFLayer(net, tol=1e-8)
+    dev = layer.net.device
+    pd = torch.tensor(net.pd, dtype=torch.float64, device=dev, requires_grad=True)
+    qd = torch.tensor(net.qd, dtype=torch.float64, device=dev, requires_grad=True)
+    pg, vm, f = layer(pd, qd)
+    np.testing.assert_allclose(pg.detach().cpu().numpy(), opg, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(vm.detach().cpu().numpy(), ovm, rtol=0, atol=1e-6)
+    assert abs(f.item() - of) <= 1e-6 * abs(of)
+    L = (pg * torch.tensor(dpg, device=dev)).sum() + (vm * torch.tensor(dvm, device=dev)).sum() \
+        + df * f
+    L.backward()
+    gpd, gqd = pd.grad.cpu().numpy(), qd.grad.cpu().numpy()
+    scale = max(np.abs(ogpd).max(), np.abs(ogqd).max())
+    assert scale > 1.0
+    assert np.abs(gpd - ogpd).max() <= 1e-5 * scale, np.abs(gpd - ogpd).max() / scale
+    assert np.abs(gqd - ogqd).max() <= 1e-5 * scale, np.abs(gqd - ogqd).max() / scale
+
+
+def test_adjoint_vector_matches_oracle():
+    net = NETS["syn9-0"]()
+    dpg, dvm, df = _weights(net, 2)
+    _, _, oxi = _oracle(net, dpg, dvm, df)
+    api = _api()
+    G = api.Net(net)
+    ipm = api.Ipm(G, tol=1e-8)
+    code, _ = ipm.solve()
+    assert code == 0
+    gpd, gqd, xi = ipm.backward(dpg, dvm, df, want_xi=True)
+    xi = xi.cpu().numpy()
+    # xi is (u, x, s, lambda, y) in both; the multiplier blocks carry the
+    # objective scale, which both sides share
+    assert np.abs(xi - oxi).max() <= 1e-5 * np.abs(oxi).max()
+
+
+def test_backward_needs_a_converged_solver():
+    api = _api()
+    G = api.Net(synthnet.case9(0))
+    ipm = api.Ipm(G, tol=1e-8)
+    with pytest.raises(api.RhError) as e:
+        ipm.backward(None, None, 1.0)
+    assert "state" in str(e.value).lower() or e.value.code == -5
+
+
+def test_two_scenarios_forward_then_backward():
+    """Each forward call keeps its own solver; the backward passes in reverse
+    order reproduce single-scenario results bit for bit."""
+    net = synthnet.case9(0)
+    api = _api()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    scen = [(net.pd * s, net.qd * s) for s in (1.0, 0.9)]
+    dpg, dvm, df = _weights(net, 4)
+    w_pg, w_vm = torch.tensor(dpg, device=dev), torch.tensor(dvm, device=dev)
+
+    def run(layer, pd_np, qd_np):
+        pd = torch.tensor(pd_np, dtype=torch.float64, device=dev, requires_grad=True)
+        qd = torch.tensor(qd_np, dtype=torch.float64, device=dev, requires_grad=True)
+        pg, vm, f = layer(pd, qd)
+        return pd, qd, (pg * w_pg).sum() + (vm * w_vm).sum() + df * f
+
+    single = []
+    for pd_np, qd_np in scen:
+        layer = api.OPFLayer(net, tol=1e-8)
+        pd, qd, L = run(layer, pd_np, qd_np)
+        L.backward()
+        single.append((pd.grad.cpu().numpy(), qd.grad.cpu().numpy()))
+    layer = api.OPFLayer(net, tol=1e-8)
+    runs = [run(layer, *s) for s in scen]
+    for k in (1, 0):
+        pd, qd, L = runs[k]
+        L.backward()
+        np.testing.assert_array_equal(pd.grad.cpu().numpy(), single[k][0])
+        np.testing.assert_array_equal(qd.grad.cpu().numpy(), single[k][1])
+    assert np.abs(single[0][0] - single[1][0]).max() > 1e-6
+
+
+def test_objective_gradient_is_envelope_1354():
+    """df*/dPd_i, df*/dQd_i equal the balance multipliers of the solution
+    (plus the y terms of Pg_ref and Qg), divided by the objective scale."""
+    net = synthnet.case1354(0)
+    api = _api()
+    print("opf layer envelope: syn1354", flush=True)
+    G = api.Net(net)
+    ipm = api.Ipm(G, tol=1e-8)
+    code, info = ipm.solve()
+    assert code == 0
+    sig = info["obj_scale"]
+    gpd, gqd = ipm.backward(None, None, 1.0)
+    gpd, gqd = gpd.cpu().numpy(), gqd.cpu().numpy()
+    st = {k: v.cpu().numpy() for k, v in ipm.state().items()}
+    pg, _, _ = ipm.outputs()
+    pg = pg.cpu().numpy()
+    xk, xb, _, _ = G.index_maps()
+    epd, eqd = np.zeros(net.nb), np.zeros(net.nb)
+    for k in range(len(xk)):
+        (epd if xk[k] == 0 else eqd)[xb[k]] += st["lam"][k]
+    ref = int(np.flatnonzero(np.asarray(net.bus_type) == 3)[0])
+    rg = int(np.flatnonzero(np.asarray(net.gen_bus) == ref)[0])
+    B = net.base_mva
+    epd[ref] += st["y"][0] + sig * B * (2.0 * net.c2[rg] * B * pg[rg] + net.c1[rg])
+    for g in range(net.ng):
+        eqd[net.gen_bus[g]] += st["y"][1 + g]
+    epd /= sig
+    eqd /= sig
+    scale = np.abs(np.concatenate([epd, eqd])).max()
+    assert np.abs(gpd - epd).max() <= 1e-5 * scale, np.abs(gpd - epd).max() / scale
+    assert np.abs(gqd - eqd).max() <= 1e-5 * scale, np.abs(gqd - eqd).max() / scale
