@@ -131,6 +131,50 @@ def batched_run(api, torch, steps, warmup):
             "delta_w_nonzero": int((delta > 0).sum())}
 
 
+def differentiated_run(api, torch, count=16):
+    """Differentiated OPF (api.OPFLayer): load scenarios of the 1354-bus
+    network (every bus load scaled by U[0.8, 1.2], scenario seeds 1..count),
+    each solved to a scaled KKT error of 1e-8 (forward) and differentiated
+    (backward: gradient of Pg . w_pg + Vm . w_vm + f in (Pd, Qd), one adjoint
+    solve through the condensed KKT system)."""
+    import numpy as np
+    import synthnet
+    base = synthnet.case1354(0)
+    dev = torch.device("cuda", 0)
+    layer = api.OPFLayer(base, tol=1e-8)
+    rng = np.random.default_rng(0)
+    w_pg = torch.as_tensor(rng.standard_normal(base.ng), device=dev)
+    w_vm = torch.as_tensor(rng.standard_normal(base.nb), device=dev)
+    scen = [synthnet.scale_loads(base, s) for s in range(1, count + 1)]
+    loads = [(torch.as_tensor(n.pd, device=dev), torch.as_tensor(n.qd, device=dev)) for n in scen]
+    # one untimed scenario (first use of every kernel)
+    pd = loads[0][0].clone().requires_grad_(True)
+    pg, vm, f = layer(pd, loads[0][1])
+    ((pg * w_pg).sum() + (vm * w_vm).sum() + f).backward()
+    torch.cuda.synchronize()
+    t_fwd = t_bwd = 0.0
+    iters = 0
+    for pdv, qdv in loads:
+        pd = pdv.clone().requires_grad_(True)
+        qd = qdv.clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        pg, vm, f = layer(pd, qd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ((pg * w_pg).sum() + (vm * w_vm).sum() + f).backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_fwd += t1 - t0
+        t_bwd += t2 - t1
+        iters += int(layer.last_info["iter"])
+    return {"scenarios": count, "scenarios_per_s": count / (t_fwd + t_bwd),
+            "forward_ms": 1e3 * t_fwd / count, "backward_ms": 1e3 * t_bwd / count,
+            "ipm_iterations_mean": iters / count, "tol": 1e-8,
+            "step": "forward: IPM from the flat start to 1e-8; backward: evaluation, "
+                    "condensation with the adjoint right-hand side, Cholesky, recovery, "
+                    "load-gradient scatter"}
+
+
 def algorithmic_bytes(info, ncols):
     """Paper-dataflow bytes of one condensation launch: every stage reads its
     input panel and writes its output panel (8 (12 nx + 5 nu) bytes per
@@ -226,6 +270,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ipm", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--ipm-iters", type=int, default=150)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -327,6 +372,8 @@ def main():
         line["autotune"] = {"best": {"panel_width": best[0], "lds_panel": best[1]},
                             "condensation_us": {f"w{w}_lds{l}": round(v, 1)
                                                 for (w, l), v in times.items()}}
+    if not args.no_diff:
+        line["differentiated"] = differentiated_run(api, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args_np, args.cpu_seconds)
     print(json.dumps(line), flush=True)

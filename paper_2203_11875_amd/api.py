@@ -505,6 +505,7 @@ class OPFLayer:
         code, info = ipm.solve()
         if code != _abi.RH_OK:
             _check(code, "rh_ipm_solve")
+        self.last_info = info
         return ipm, info
 
 
