@@ -181,3 +181,45 @@ def test_sensitivity_mutant_is_caught(name, monkeypatch):
 def test_unmutated_sensitivity_passes_its_pins():
     for pin in SENS_PINS:
         pin()
+
+
+# --------------------------------------------------------------------- RedLin
+import oracle.redlin as orl
+import test_oracle_redlin as trl
+
+REDLIN_PINS = [
+    lambda: trl.test_reduced_derivatives_match_differences("syn5"),
+    lambda: trl.test_reduced_step_equals_condensed_forms("syn5"),
+    lambda: trl.test_redlin_reaches_linred_optimum("syn5"),
+]
+_ORIG_DERIV = orl.RedLinIPM.derivatives
+
+
+def _deriv_no_state_rows(self, u, x, y):
+    D = _ORIG_DERIV(self, u, x, y)
+    D["A_hat"] = D["A_hat"].copy()
+    D["A_hat"][self.m:] = 0.0
+    return D
+
+
+def _deriv_adjoint_yx_sign(self, u, x, y):
+    y2 = y.copy()
+    y2[self.m:] *= -1.0
+    D = _ORIG_DERIV(self, u, x, y2)
+    D2 = _ORIG_DERIV(self, u, x, y)
+    D2["lam"], D2["grad_lr"], D2["W_hat"] = D["lam"], D["grad_lr"], D["W_hat"]
+    return D2
+
+
+@pytest.mark.parametrize("name,fn", [("state_rows_dropped_from_A_hat", _deriv_no_state_rows),
+                                     ("adjoint_state_multiplier_sign", _deriv_adjoint_yx_sign)])
+def test_redlin_mutant_is_caught(name, fn, monkeypatch):
+    monkeypatch.setattr(orl.RedLinIPM, "derivatives", fn)
+    caught = False
+    for pin in REDLIN_PINS:
+        try:
+            pin()
+        except (AssertionError, RuntimeError, np.linalg.LinAlgError):
+            caught = True
+            break
+    assert caught, f"mutant {name} survived every pin"
