@@ -280,12 +280,14 @@ rh_status rh_solve_condensed_kkt(rh_net* net, double* K, int64_t ldk, double del
  * RH_PHASE_SYMMETRIZE  (K + K^T)/2
  * RH_PHASE_CHOLESKY    dense Cholesky with forward/backward substitution
  * RH_PHASE_RECOVER     p_x, p_lambda, p_s, p_y
+ * RH_PHASE_PROJECT     Newton-Raphson power flow (evaluations, refactorisations
+ *                      and solves of the projection; rh_power_flow, RedLin)
  * rh_profile_enable resets the totals; rh_profile_read waits for the
  * recorded events and returns milliseconds and call counts per phase (host
  * arrays of RH_NPHASES entries, either may be NULL).
  * ------------------------------------------------------------------------- */
 enum { RH_PHASE_EVAL = 0, RH_PHASE_REFACTOR, RH_PHASE_CONDENSE, RH_PHASE_SYMMETRIZE,
-       RH_PHASE_CHOLESKY, RH_PHASE_RECOVER, RH_NPHASES };
+       RH_PHASE_CHOLESKY, RH_PHASE_RECOVER, RH_PHASE_PROJECT, RH_NPHASES };
 rh_status rh_profile_enable(rh_net* net, int32_t on);
 rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
 /* In-kernel phase timestamps (device wall clock, 100 MHz) of the first
@@ -344,7 +346,7 @@ typedef struct {
   int64_t ls_trials;     /* line-search trial points evaluated                       */
   double obj_scale;      /* objective scale in use                                   */
   int32_t converged;     /* 1: E_0 <= tol at the start of this call (no step taken)   */
-  int32_t reserved;
+  int32_t pf_iters;      /* RedLin: Newton-Raphson steps of this call's projections  */
 } rh_ipm_info;
 
 /* Fills the defaults. */
@@ -402,6 +404,55 @@ rh_status rh_ipm_backward(rh_ipm* ipm, const double* dpg, const double* dvm, con
                           double* gpd, double* gqd, double* xi);
 /* Frees the solver and restores the network's objective scale to 1. */
 void rh_ipm_destroy(rh_ipm* ipm);
+
+/* ---------------------------------------------------------------------------
+ * Newton-Raphson power flow: the projection of Algorithm 2 (Section 2.3.1,
+ * implicit function theorem; the paper's tolerance 1e-10). x (device, nx,
+ * natural order) is the start and receives the solution of g(x, u) = 0 for
+ * the control u (device, nu). Every iteration evaluates g, reads max |g|,
+ * refactorises G_x with the static pivots of the analysis and solves
+ * G_x dx = g with the condensation's triangular sweeps (x -= dx). Stops when
+ * max |g| <= tol (RH_OK) or after max_iter steps or a non-finite residual
+ * (RH_NOT_CONVERGED; x holds the last iterate). iters, residual (host,
+ * optional): steps taken and the last max |g|. Synchronises the stream once
+ * per step. RH_ERR_ARG for tol <= 0, max_iter < 0 or null pointers.
+ * ------------------------------------------------------------------------- */
+rh_status rh_power_flow(rh_net* net, const double* u, double* x, double tol, int32_t max_iter,
+                        int32_t* iters, double* residual);
+
+/* ---------------------------------------------------------------------------
+ * Reduce-then-linearize interior-point method: Algorithm 2 ("RedLin",
+ * Section 2.3). The state is eliminated by the projection (rh_power_flow at
+ * tolerance 1e-10, at most 20 steps, warm-started from the linearised state
+ * step); the bounded states (Vm at PQ buses) move into
+ * h_r = [h; -x_b] with slacks s_r = [s_h; s_x] (m + nxb entries, s_x bounded
+ * by the state bounds); each iteration computes the adjoint
+ * lambda = -G_x^{-T}(grad_x f + A_x^T y_h - y_x), condenses the reduced KKT
+ * system (eq. reduced:kktsystem, +I reading of its (s, y) blocks) through
+ * the full-space condensation (with g = 0 it equals the reduced one with the
+ * state slacks' Sigma in place of Sigma_x and r4 = 0), factors it with
+ * inertia correction, and runs the filter line search of rh_ipm_step on
+ * (u, s_r, y_r), projecting every trial point (a trial whose projection fails
+ * is rejected). Barrier update, constants, initial point and objective
+ * scaling as rh_ipm_* (the scale is taken at the projected initial point;
+ * RH_NOT_CONVERGED from create if that projection fails). info->pf_iters:
+ * Newton steps of the call's projections. Handles, streams and errors as
+ * rh_ipm_*.
+ * ------------------------------------------------------------------------- */
+typedef struct rh_redlin rh_redlin;
+rh_status rh_redlin_create(rh_net* net, const rh_ipm_options* opts, const double* x0,
+                           const double* u0, rh_redlin** out);
+rh_status rh_redlin_step(rh_redlin* rl, rh_ipm_info* info);
+rh_status rh_redlin_solve(rh_redlin* rl, rh_ipm_info* info);
+/* Device copies of the current point (any pointer may be NULL): x[nx],
+ * u[nu], s[m + nxb] (s_h, then the bounded states' slacks), lam[nx] (the
+ * adjoint of the last iteration), y[m + nxb]. */
+rh_status rh_redlin_get_state(const rh_redlin* rl, double* x, double* u, double* s, double* lam,
+                              double* y);
+/* Sizes of the reduced slack vector: mr = m + nxb, nxb bounded states. */
+rh_status rh_redlin_dims(const rh_redlin* rl, int64_t* mr, int64_t* nxb);
+/* Frees the solver and restores the network's objective scale to 1. */
+void rh_redlin_destroy(rh_redlin* rl);
 
 #ifdef __cplusplus
 }

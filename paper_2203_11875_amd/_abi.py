@@ -50,7 +50,7 @@ class rh_ipm_info(C.Structure):
     _fields_ = [("iter", C.c_int64), ("obj", C.c_double), ("inf_pr", C.c_double),
                 ("err", C.c_double), ("mu", C.c_double), ("alpha_pr", C.c_double),
                 ("alpha_du", C.c_double), ("delta_w", C.c_double), ("ls_trials", C.c_int64),
-                ("obj_scale", C.c_double), ("converged", C.c_int32), ("reserved", C.c_int32)]
+                ("obj_scale", C.c_double), ("converged", C.c_int32), ("pf_iters", C.c_int32)]
 
 
 class rh_batch_condense_item(C.Structure):
@@ -99,6 +99,14 @@ SIGNATURES = {
     "rh_ipm_destroy": (None, [vp]),
     "rh_ipm_outputs": (C.c_int, [vp, vp, vp, vp]),
     "rh_ipm_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+    "rh_power_flow": (C.c_int, [vp, vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                                C.POINTER(C.c_double)]),
+    "rh_redlin_create": (C.c_int, [vp, C.POINTER(rh_ipm_options), vp, vp, C.POINTER(vp)]),
+    "rh_redlin_step": (C.c_int, [vp, C.POINTER(rh_ipm_info)]),
+    "rh_redlin_solve": (C.c_int, [vp, C.POINTER(rh_ipm_info)]),
+    "rh_redlin_get_state": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+    "rh_redlin_dims": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "rh_redlin_destroy": (None, [vp]),
     "rh_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]),
     "rh_batch_destroy": (None, [vp]),
     "rh_batch_condense": (C.c_int, [vp, C.POINTER(rh_batch_condense_item)]),
@@ -109,7 +117,7 @@ SIGNATURES = {
                                   C.POINTER(rh_batch_solve_item), i32p]),
 }
 
-PHASES = ["eval", "refactor", "condense", "symmetrize", "cholesky", "recover"]
+PHASES = ["eval", "refactor", "condense", "symmetrize", "cholesky", "recover", "project"]
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:

@@ -182,6 +182,18 @@ class Net:
         _check(lib().rh_set_loads(self.h, _ptr(pd), _ptr(qd)), "rh_set_loads")
         self._keep = (pd, qd)
 
+    def power_flow(self, u, x0, tol=1e-10, max_iter=20):
+        """Newton-Raphson power flow (rh_power_flow): returns (x, status,
+        iterations, max |g|); x starts at x0."""
+        u = self._t(u, self.nu)
+        x = self._t(x0, self.nx).clone()
+        it, res = C.c_int32(0), C.c_double(0.0)
+        code = lib().rh_power_flow(self.h, _ptr(u), _ptr(x), float(tol), int(max_iter),
+                                   C.byref(it), C.byref(res))
+        if code < 0:
+            _check(code, "rh_power_flow")
+        return x, code, it.value, res.value
+
     def eval_residual(self, x, u):
         t = self.torch
         x, u = self._t(x, self.nx), self._t(u, self.nu)
@@ -392,7 +404,7 @@ class Batch:
 def _info_ipm(info):
     return {name: (float(getattr(info, name)) if isinstance(getattr(info, name), float)
                    else int(getattr(info, name)))
-            for name, _ in _abi.rh_ipm_info._fields_ if name != "reserved"}
+            for name, _ in _abi.rh_ipm_info._fields_}
 
 
 class Ipm:
@@ -477,6 +489,62 @@ class Ipm:
         if code not in (_abi.RH_OK, _abi.RH_SMALL_PIVOT):
             _check(code, "rh_ipm_backward")
         return (gpd, gqd, xi) if want_xi else (gpd, gqd)
+
+
+class RedLin:
+    """Reduce-then-linearize solver (Algorithm 2) on a device network handle
+    (rh_redlin_*)."""
+
+    def __init__(self, net, x0=None, u0=None, tol=1e-6, max_iter=200, mu_init=0.1,
+                 obj_scale=0.0):
+        if not isinstance(net, Net):
+            raise TypeError("RedLin needs an api.Net")
+        self.net = net
+        o = _abi.rh_ipm_options()
+        _check(lib().rh_ipm_default_options(C.byref(o)), "rh_ipm_default_options")
+        o.tol, o.max_iter, o.mu_init, o.obj_scale = float(tol), int(max_iter), float(mu_init), \
+            float(obj_scale)
+        xs = net._t(x0, net.nx) if x0 is not None else None
+        us = net._t(u0, net.nu) if u0 is not None else None
+        h = C.c_void_p()
+        _check(lib().rh_redlin_create(net.h, C.byref(o), _ptr(xs), _ptr(us), C.byref(h)),
+               "rh_redlin_create")
+        self.h = h
+        mr, nxb = C.c_int64(0), C.c_int64(0)
+        _check(lib().rh_redlin_dims(self.h, C.byref(mr), C.byref(nxb)), "rh_redlin_dims")
+        self.mr, self.nxb = mr.value, nxb.value
+
+    def close(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.rh_redlin_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self):
+        info = _abi.rh_ipm_info()
+        code = lib().rh_redlin_step(self.h, C.byref(info))
+        if code < 0:
+            _check(code, "rh_redlin_step")
+        return code, _info_ipm(info)
+
+    def solve(self):
+        info = _abi.rh_ipm_info()
+        code = lib().rh_redlin_solve(self.h, C.byref(info))
+        if code < 0:
+            _check(code, "rh_redlin_solve")
+        return code, _info_ipm(info)
+
+    def state(self):
+        t, n = self.net.torch, self.net
+        out = [t.empty(k, dtype=t.float64, device=n.device)
+               for k in (n.nx, n.nu, self.mr, n.nx, self.mr)]
+        _check(lib().rh_redlin_get_state(self.h, *[_ptr(a) for a in out]), "rh_redlin_get_state")
+        return dict(zip(("x", "u", "s", "lam", "y"), out))
 
 
 class OPFLayer:

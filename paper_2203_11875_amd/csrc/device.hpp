@@ -134,9 +134,14 @@ hipError_t launch_rtilde(const DevNet& d, const double* r, const double* sig_s, 
 // mode 0: identity columns [col0, col0 + ncols) (col == nu: the right-hand-side column)
 hipError_t launch_condense(const DevNet& d, int col0, int ncols, int width, bool lds,
                            const double* r, double* K, long ldk, double* rhs, hipStream_t st);
-// recovery of p_x and p_lambda from p_u (one column)
-hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, double* p,
-                          hipStream_t st);
+// recovery of p_x and p_lambda from p_u (one column; the handle's panel
+// width and placement, whose records the sweeps read)
+hipError_t launch_recover(const DevNet& d, int width, bool lds, const double* pu,
+                          const double* r, double* p, hipStream_t st);
+// x = scale * G_x^{-1} b (or G_x^{-T} b) [+ x if accumulate] with the factors
+// of the last refactorisation (b, x natural order; one wave).
+hipError_t launch_gx_solve(const DevNet& d, int width, bool lds, bool transpose, const double* b,
+                           double* x, double scale, bool accumulate, hipStream_t st);
 // Recovery from the stored columns of the last condensation (which included
 // the right-hand-side column): p_x = Z p_u + d, p_lambda = -(Psi p_u + Psi_rhs).
 hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st);

@@ -988,6 +988,50 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, i
   k_condense_body<W, LDS, mode>(d, blockIdx.x, col0, col_end, r, vin, K, ldk, rhs, p_out);
 }
 
+// x = G_x^{-1} b (TRANS = 0: L then U sweep) or x = G_x^{-T} b (TRANS = 1:
+// U^T then L^T sweep) with the factors of the last refactorisation, in one
+// wave, on column 0 of a condensation panel (the records of the handle's
+// panel width W); b and x in natural order. x = scale * solution, plus the
+// old x if accumulate (a Newton step x -= G_x^{-1} g is scale -1).
+template <int W, bool LDS, int TRANS>
+__global__ void __launch_bounds__(kCondThreads) k_gx_solve(DevNet d, const double* b, double* x,
+                                                          double scale, int accumulate) {
+  extern __shared__ double panel_lds[];
+  if (LDS && (size_t)(lds_double*)panel_lds != 0) {   // the records assume LDS address 0
+    if (threadIdx.x == 0) d.status[4] = 1;
+    return;
+  }
+  const int nw = d.nw, nu = d.nu, nx = d.nx, tid = threadIdx.x, T = kCondThreads;
+  double* P = LDS ? panel_lds : d.panel;
+  char* pb = reinterpret_cast<char*>(P);
+  const DevSweep& s1 = TRANS ? d.sut : d.sl;
+  const DevSweep& s2 = TRANS ? d.slt : d.su;
+  int4* m1 = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(nw + 1) * W : 0));
+  int4* m2 = m1 + s1.nstep + 1;
+  stage_meta(s1, m1);
+  stage_meta(s2, m2);
+  for (int i = tid; i < (nw + 1) * W; i += T) P[i] = 0.0;
+  panel_sync<LDS>();
+  if (TRANS)
+    indexed_loop(d.hpos + nu, nx, [&](int i, int hp) { P[hp * W] = b[d.perm[i]]; });
+  else
+    for (int i = tid; i < nx; i += T) P[(nu + i) * W] = b[d.perm[i]];
+  panel_sync<LDS>();
+  sweep<W, LDS>(s1, d.lblk, m1, pb);
+  sweep<W, LDS>(s2, d.lblk, m2, pb);
+  panel_sync<LDS>();
+  if (TRANS)
+    indexed_loop(d.hpos + nu, nx, [&](int i, int hp) {
+      const int k = d.perm[i];
+      x[k] = (accumulate ? x[k] : 0.0) + scale * P[hp * W];
+    });
+  else
+    for (int i = tid; i < nx; i += T) {
+      const int k = d.perm[i];
+      x[k] = (accumulate ? x[k] : 0.0) + scale * P[(nu + i) * W];
+    }
+}
+
 // Recovery from the stored columns: thread i (internal x index) of chunk ch
 // sums the columns [ch * cw, (ch + 1) * cw) of Z and Psi against p_u; the
 // partial sums are combined in a fixed order by k_recover_finish, so the
@@ -1615,14 +1659,42 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_condense<3, true, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<4, true, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<8, true, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<1, true, MODE_RECOVER>)};
+      reinterpret_cast<const void*>(&k_condense<1, true, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<2, true, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<3, true, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<4, true, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<8, true, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, true, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, true, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, true, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, true, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, true, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, true, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, true, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, true, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, true, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, true, 1>)};
   const void* gfns[] = {
       reinterpret_cast<const void*>(&k_condense<1, false, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<2, false, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<3, false, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<4, false, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<8, false, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<1, false, MODE_RECOVER>)};
+      reinterpret_cast<const void*>(&k_condense<1, false, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<2, false, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<3, false, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<4, false, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<8, false, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, false, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, false, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, false, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, false, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, false, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, false, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, false, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, false, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, false, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, false, 1>)};
   for (const void* f : fns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   const void* bfns[] = {
@@ -1701,12 +1773,42 @@ hipError_t launch_condense(const DevNet& d, int col0, int ncols, int width, bool
                                nullptr, st);
 }
 
-hipError_t launch_recover(const DevNet& d, const double* pu, const double* r, double* p,
-                          hipStream_t st) {
-  const bool lds = condense_lds_bytes(d, 1, true) <= (size_t)max_lds_bytes();
+hipError_t launch_recover(const DevNet& d, int width, bool lds, const double* pu,
+                          const double* r, double* p, hipStream_t st) {
   if (lds)
-    return launch_condense_t<1, true>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
-  return launch_condense_t<1, false>(d, 0, 1, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
+    return dispatch_width<true>(d, 0, 1, width, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
+  return dispatch_width<false>(d, 0, 1, width, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
+}
+
+template <int W, bool LDS, int TRANS>
+hipError_t launch_gx_solve_t(const DevNet& d, const double* b, double* x, double scale,
+                             int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL((k_gx_solve<W, LDS, TRANS>), dim3(1), dim3(kCondThreads),
+                     condense_lds_bytes(d, W, LDS), st, d, b, x, scale, accumulate);
+  return hipGetLastError();
+}
+
+template <bool LDS, int TRANS>
+hipError_t gx_solve_width(const DevNet& d, int width, const double* b, double* x, double scale,
+                          int accumulate, hipStream_t st) {
+  switch (width) {
+    case 1: return launch_gx_solve_t<1, LDS, TRANS>(d, b, x, scale, accumulate, st);
+    case 2: return launch_gx_solve_t<2, LDS, TRANS>(d, b, x, scale, accumulate, st);
+    case 3: return launch_gx_solve_t<3, LDS, TRANS>(d, b, x, scale, accumulate, st);
+    case 4: return launch_gx_solve_t<4, LDS, TRANS>(d, b, x, scale, accumulate, st);
+    case 8: return launch_gx_solve_t<8, LDS, TRANS>(d, b, x, scale, accumulate, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gx_solve(const DevNet& d, int width, bool lds, bool transpose, const double* b,
+                           double* x, double scale, bool accumulate, hipStream_t st) {
+  const int acc = accumulate ? 1 : 0;
+  if (lds)
+    return transpose ? gx_solve_width<true, 1>(d, width, b, x, scale, acc, st)
+                     : gx_solve_width<true, 0>(d, width, b, x, scale, acc, st);
+  return transpose ? gx_solve_width<false, 1>(d, width, b, x, scale, acc, st)
+                   : gx_solve_width<false, 0>(d, width, b, x, scale, acc, st);
 }
 
 hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st) {

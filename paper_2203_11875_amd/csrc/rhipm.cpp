@@ -13,6 +13,7 @@
 #include "analysis.hpp"
 #include "device.hpp"
 #include "ipm.hpp"
+#include "redlin.hpp"
 
 struct rh_symbolic {
   rh::Symbolic s;
@@ -36,6 +37,7 @@ struct rh_net {
   std::vector<void*> allocs;
   int width = 2;
   bool lds = true;
+  double* pf_scal = nullptr;  // device scalar of the power-flow residual checks
   bool condensed = false;
   bool rhs_cols = false;     // the last condensation stored the right-hand-side column
   double* sig_s = nullptr;   // copy of Sigma_s from the last condensation
@@ -919,7 +921,7 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
       RH_HIP(rh::launch_recover_stored(d, p, st));
     } else {
       RH_HIP(rh::launch_rtilde(d, r, n->sig_s, st));
-      RH_HIP(rh::launch_recover(d, p, r, p, st));
+      RH_HIP(rh::launch_recover(d, n->width, n->lds, p, r, p, st));
     }
     RH_HIP(rh::launch_finish_step(d, r, n->sig_s, p, st));
   }
@@ -1003,8 +1005,8 @@ struct rh_ipm {
 
 namespace {
 
-template <typename T>
-rh_status ialloc(rh_ipm* p, size_t count, T** out) {
+template <typename H, typename T>
+rh_status ialloc(H* p, size_t count, T** out) {
   void* q = nullptr;
   if (hipMalloc(&q, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) return RH_ERR_OOM;
   p->allocs.push_back(q);
@@ -1012,8 +1014,8 @@ rh_status ialloc(rh_ipm* p, size_t count, T** out) {
   return RH_OK;
 }
 
-template <typename T>
-rh_status iupload(rh_ipm* p, const std::vector<T>& h, const T** out) {
+template <typename H, typename T>
+rh_status iupload(H* p, const std::vector<T>& h, const T** out) {
   T* q = nullptr;
   RH_TRY(ialloc(p, h.size(), &q));
   if (!h.empty() && hipMemcpy(q, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
@@ -1022,9 +1024,76 @@ rh_status iupload(rh_ipm* p, const std::vector<T>& h, const T** out) {
   return RH_OK;
 }
 
-void free_ipm(rh_ipm* p) {
+template <typename H>
+void free_ipm(H* p) {
   for (void* q : p->allocs) (void)hipFree(q);
   p->allocs.clear();
+}
+
+// Device vectors of an interior-point handle on network n (natural order,
+// w = [u; x]): bounds, the generator of each Pg control, G_x by internal
+// columns (for G^T lambda), iterate, multipliers, residual, step, trial point
+// and reduction slots. nfin: finite bounds of w and s.
+template <typename H>
+rh_status setup_ipm_dev(H* p, rh_net* n, rh::IpmDev& v, int* nfin) {
+  const rh::Symbolic& s = n->s;
+  v.nu = s.nu;
+  v.nx = s.nx;
+  v.m = s.m;
+  const int nw = s.nw, m = s.m, nx = s.nx, nu = s.nu;
+  *nfin = 0;
+  RH_TRY(iupload(p, n->wl, &v.wl));
+  RH_TRY(iupload(p, n->wu, &v.wu));
+  RH_TRY(iupload(p, n->sl, &v.sl));
+  RH_TRY(iupload(p, n->su, &v.su));
+  for (const auto* b : {&n->wl, &n->wu, &n->sl, &n->su})
+    for (double x : *b) *nfin += std::isfinite(x) ? 1 : 0;
+  {
+    std::vector<int> ug(nu, -1);
+    for (int k = 0; k < nu; ++k)
+      if (s.u_kind[k] == 2) ug[k] = s.u_ref[k];
+    RH_TRY(iupload(p, ug, &v.u_gen));
+    // G_x by internal columns (transposed products with lambda)
+    std::vector<std::vector<std::pair<int, int>>> cols(nx);
+    for (int r = 0; r < nx; ++r)
+      for (int e = s.gx_ptr[r]; e < s.gx_ptr[r + 1]; ++e)
+        cols[s.iperm[s.gx_col[e]]].push_back({s.iperm[r], s.gx_lu[e]});
+    std::vector<int> cptr(nx + 1, 0), crow, cpos;
+    for (int c = 0; c < nx; ++c) {
+      for (auto& q : cols[c]) {
+        crow.push_back(q.first);
+        cpos.push_back(q.second);
+      }
+      cptr[c + 1] = int(crow.size());
+    }
+    RH_TRY(iupload(p, cptr, &v.gx_cptr));
+    RH_TRY(iupload(p, crow, &v.gx_crow));
+    RH_TRY(iupload(p, cpos, &v.gx_cpos));
+  }
+  const size_t np = size_t(nw) + 2 * size_t(m) + nx;
+  RH_TRY(ialloc(p, nw, &v.w));
+  RH_TRY(ialloc(p, m, &v.s));
+  RH_TRY(ialloc(p, nx, &v.lam));
+  RH_TRY(ialloc(p, m, &v.y));
+  RH_TRY(ialloc(p, nw, &v.zl));
+  RH_TRY(ialloc(p, nw, &v.zu));
+  RH_TRY(ialloc(p, m, &v.zsl));
+  RH_TRY(ialloc(p, m, &v.zsu));
+  RH_TRY(ialloc(p, nw, &v.gf));
+  RH_TRY(ialloc(p, nw, &v.gl));
+  RH_TRY(ialloc(p, nw, &v.sig_w));
+  RH_TRY(ialloc(p, m, &v.sig_s));
+  RH_TRY(ialloc(p, np, &v.r));
+  RH_TRY(ialloc(p, np, &v.p));
+  RH_TRY(ialloc(p, nw, &v.pzl));
+  RH_TRY(ialloc(p, nw, &v.pzu));
+  RH_TRY(ialloc(p, m, &v.pzsl));
+  RH_TRY(ialloc(p, m, &v.pzsu));
+  RH_TRY(ialloc(p, nw, &v.wt));
+  RH_TRY(ialloc(p, m, &v.st));
+  RH_TRY(ialloc(p, rh::IR_NSLOT, &v.red));
+  RH_TRY(ialloc(p, 2, &v.f));
+  return RH_OK;
 }
 
 // Reads the reduction slots (and the two objective values) after the stream
@@ -1120,57 +1189,7 @@ rh_status rh_ipm_create(rh_net* n, const rh_ipm_options* opts, const double* x0,
     st_ = (expr);                  \
     if (st_ != RH_OK) return fail(st_); \
   } while (0)
-  IPM_TRY(iupload(p.get(), n->wl, &v.wl));
-  IPM_TRY(iupload(p.get(), n->wu, &v.wu));
-  IPM_TRY(iupload(p.get(), n->sl, &v.sl));
-  IPM_TRY(iupload(p.get(), n->su, &v.su));
-  for (const auto* b : {&n->wl, &n->wu, &n->sl, &n->su})
-    for (double x : *b) p->nfin += std::isfinite(x) ? 1 : 0;
-  {
-    std::vector<int> ug(nu, -1);
-    for (int k = 0; k < nu; ++k)
-      if (s.u_kind[k] == 2) ug[k] = s.u_ref[k];
-    IPM_TRY(iupload(p.get(), ug, &v.u_gen));
-    // G_x by internal columns (transposed products with lambda)
-    std::vector<std::vector<std::pair<int, int>>> cols(nx);
-    for (int r = 0; r < nx; ++r)
-      for (int e = s.gx_ptr[r]; e < s.gx_ptr[r + 1]; ++e)
-        cols[s.iperm[s.gx_col[e]]].push_back({s.iperm[r], s.gx_lu[e]});
-    std::vector<int> cptr(nx + 1, 0), crow, cpos;
-    for (int c = 0; c < nx; ++c) {
-      for (auto& q : cols[c]) {
-        crow.push_back(q.first);
-        cpos.push_back(q.second);
-      }
-      cptr[c + 1] = int(crow.size());
-    }
-    IPM_TRY(iupload(p.get(), cptr, &v.gx_cptr));
-    IPM_TRY(iupload(p.get(), crow, &v.gx_crow));
-    IPM_TRY(iupload(p.get(), cpos, &v.gx_cpos));
-  }
-  const size_t np = size_t(nw) + 2 * size_t(m) + nx;
-  IPM_TRY(ialloc(p.get(), nw, &v.w));
-  IPM_TRY(ialloc(p.get(), m, &v.s));
-  IPM_TRY(ialloc(p.get(), nx, &v.lam));
-  IPM_TRY(ialloc(p.get(), m, &v.y));
-  IPM_TRY(ialloc(p.get(), nw, &v.zl));
-  IPM_TRY(ialloc(p.get(), nw, &v.zu));
-  IPM_TRY(ialloc(p.get(), m, &v.zsl));
-  IPM_TRY(ialloc(p.get(), m, &v.zsu));
-  IPM_TRY(ialloc(p.get(), nw, &v.gf));
-  IPM_TRY(ialloc(p.get(), nw, &v.gl));
-  IPM_TRY(ialloc(p.get(), nw, &v.sig_w));
-  IPM_TRY(ialloc(p.get(), m, &v.sig_s));
-  IPM_TRY(ialloc(p.get(), np, &v.r));
-  IPM_TRY(ialloc(p.get(), np, &v.p));
-  IPM_TRY(ialloc(p.get(), nw, &v.pzl));
-  IPM_TRY(ialloc(p.get(), nw, &v.pzu));
-  IPM_TRY(ialloc(p.get(), m, &v.pzsl));
-  IPM_TRY(ialloc(p.get(), m, &v.pzsu));
-  IPM_TRY(ialloc(p.get(), nw, &v.wt));
-  IPM_TRY(ialloc(p.get(), m, &v.st));
-  IPM_TRY(ialloc(p.get(), rh::IR_NSLOT, &v.red));
-  IPM_TRY(ialloc(p.get(), 2, &v.f));
+  IPM_TRY(setup_ipm_dev(p.get(), n, v, &p->nfin));
   IPM_TRY(ialloc(p.get(), size_t(nu) * nu, &p->K));
   IPM_TRY(ialloc(p.get(), size_t(nu) * nu, &p->Kc));
   IPM_TRY(ialloc(p.get(), nu, &p->rhs));
@@ -1403,6 +1422,453 @@ rh_status rh_ipm_get_state(const rh_ipm* p, double* x, double* u, double* s, dou
   if (s) RH_HIP(hipMemcpyAsync(s, v.s, sizeof(double) * v.m, hipMemcpyDeviceToDevice, st));
   if (lam) RH_HIP(hipMemcpyAsync(lam, v.lam, sizeof(double) * v.nx, hipMemcpyDeviceToDevice, st));
   if (y) RH_HIP(hipMemcpyAsync(y, v.y, sizeof(double) * v.m, hipMemcpyDeviceToDevice, st));
+  return RH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Newton-Raphson power flow and the reduce-then-linearize driver (Algorithm 2)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr double kPfTol = 1e-10;   // projection tolerance (the paper's)
+constexpr int kPfMaxIter = 20;
+
+// Newton-Raphson on g(x, u) = 0 in place: every iteration evaluates g, reads
+// max |g| (one scalar), refactorises G_x and solves x -= G_x^{-1} g with the
+// condensation's sweeps. iters: Newton steps taken; res: the last max |g|.
+rh_status newton_pf(rh_net* n, const double* u, double* x, double tol, int max_iter, int* iters,
+                    double* res) {
+  const auto& d = n->d;
+  hipStream_t st = n->stream;
+  if (!n->pf_scal) RH_TRY(alloc(n, 4, &n->pf_scal));
+  for (int k = 0;; ++k) {
+    double gm = 0.0;
+    RH_HIP(rh::launch_eval(d, x, u, nullptr, nullptr, false, st));
+    RH_HIP(rh::launch_absmax(d.dst + d.d_g, d.nx, n->pf_scal, st));
+    RH_HIP(hipMemcpyAsync(&gm, n->pf_scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    RH_HIP(hipStreamSynchronize(st));
+    if (iters) *iters = k;
+    if (res) *res = gm;
+    if (gm <= tol) return RH_OK;
+    if (k >= max_iter || !std::isfinite(gm)) return RH_NOT_CONVERGED;
+    RH_HIP(rh::launch_refactor(d, st));
+    RH_HIP(rh::launch_gx_solve(d, n->width, n->lds, false, d.dst + d.d_g, x, -1.0, true, st));
+  }
+}
+
+}  // namespace
+
+struct rh_redlin {
+  rh_net* net = nullptr;
+  rh_ipm_options opt{};
+  rh::IpmDev v{};       // full space: w = [u; x], lambda (adjoint), s -> sr, y -> yr
+  rh::IpmDev rv{};      // reduced variables: w = u, s = s_r, y = y_r (nx = 0)
+  rh::RedLinDev R{};
+  std::vector<void*> allocs;
+  double *K = nullptr, *Kc = nullptr, *rhs = nullptr, *adj = nullptr, *scal = nullptr;
+  double mu = 0.1, delta_last = 0.0, theta0 = -1.0, sigma_f = 1.0;
+  std::vector<std::pair<double, double>> filt;
+  long iter = 0;
+  int nfin = 0;
+  bool converged = false;
+};
+
+namespace {
+
+double redlin_error(const rh_redlin* p, const double* red, double mu) {
+  const double sd = std::max(kSMax, (red[rh::IR_LYSUM] + red[rh::IR_ZSUM]) /
+                                        std::max(1, p->R.mr + p->nfin)) / kSMax;
+  const double sc = std::max(kSMax, red[rh::IR_ZSUM] / std::max(1, p->nfin)) / kSMax;
+  const double ed = std::max(red[rh::IR_DUAL_W], red[rh::IR_DUAL_S]) / sd;
+  const double ep = red[rh::IR_PRIM_H];
+  const double ec =
+      p->nfin ? std::max(red[rh::IR_DZ_MAX] - mu, mu - red[rh::IR_DZ_MIN]) / sc : 0.0;
+  return std::max(ed, std::max(ep, ec));
+}
+
+rh_status redlin_read(rh_redlin* p, double* red, double* f) {
+  RH_HIP(hipStreamSynchronize(p->net->stream));
+  RH_HIP(hipMemcpy(red, p->R.red, sizeof(double) * rh::IR_NSLOT, hipMemcpyDeviceToHost));
+  if (f) RH_HIP(hipMemcpy(f, p->v.f, sizeof(double) * 2, hipMemcpyDeviceToHost));
+  return RH_OK;
+}
+
+// Derivatives at the current (projected) point: adjoint lambda =
+// -G_x^{-T}(grad_x f + A_x^T y_h - y_x), then the Hessian of
+// f + lambda^T g + y_h^T h, grad L (whose u part is the reduced gradient),
+// the objective and the reductions.
+rh_status redlin_derivatives(rh_redlin* p, double* red, double* f) {
+  rh_net* n = p->net;
+  const auto& d = n->d;
+  auto& v = p->v;
+  hipStream_t st = n->stream;
+  const int nu = v.nu;
+  {
+    PhaseScope ps(n, RH_PHASE_EVAL);
+    RH_HIP(rh::launch_fill(v.lam, v.nx, 0.0, st));
+    RH_HIP(rh::launch_eval(d, v.w + nu, v.w, nullptr, nullptr, false, st));
+    RH_HIP(rh::launch_ipm_lag_grad(d, v, st));
+    RH_HIP(rh::launch_redlin_adj_rhs(v, p->R, p->adj, st));
+  }
+  {
+    PhaseScope ps(n, RH_PHASE_REFACTOR);
+    RH_HIP(rh::launch_refactor(d, st));
+    RH_HIP(rh::launch_gx_solve(d, n->width, n->lds, true, p->adj, v.lam, 1.0, false, st));
+  }
+  {
+    PhaseScope ps(n, RH_PHASE_EVAL);
+    RH_HIP(rh::launch_eval(d, v.w + nu, v.w, v.lam, v.y, true, st));
+    RH_HIP(rh::launch_ipm_lag_grad(d, v, st));
+    RH_HIP(rh::launch_eval_objective(d, v.w, v.f, st));
+    RH_HIP(rh::launch_redlin_stats(d, v, p->R, v.w, p->R.sr, 1, st));
+  }
+  return redlin_read(p, red, f);
+}
+
+void redlin_info(const rh_redlin* p, rh_ipm_info* info, double obj, double inf_pr, double err,
+                 double alpha, double alpha_z, double delta, long trials, long pf) {
+  if (!info) return;
+  std::memset(info, 0, sizeof(*info));
+  info->iter = p->iter;
+  info->obj = obj;
+  info->inf_pr = inf_pr;
+  info->err = err;
+  info->mu = p->mu;
+  info->alpha_pr = alpha;
+  info->alpha_du = alpha_z;
+  info->delta_w = delta;
+  info->ls_trials = trials;
+  info->obj_scale = p->sigma_f;
+  info->converged = p->converged ? 1 : 0;
+  info->pf_iters = int32_t(pf);
+}
+
+}  // namespace
+
+extern "C" {
+
+rh_status rh_power_flow(rh_net* n, const double* u, double* x, double tol, int32_t max_iter,
+                        int32_t* iters, double* residual) {
+  if (!n || !u || !x || !(tol > 0.0) || max_iter < 0) return RH_ERR_ARG;
+  int k = 0;
+  double res = 0.0;
+  rh_status c;
+  {
+    PhaseScope ps(n, RH_PHASE_PROJECT);
+    c = newton_pf(n, u, x, tol, max_iter, &k, &res);
+  }
+  if (iters) *iters = k;
+  if (residual) *residual = res;
+  return c;
+}
+
+rh_status rh_redlin_create(rh_net* n, const rh_ipm_options* opts, const double* x0,
+                           const double* u0, rh_redlin** out) {
+  if (!n || !out) return RH_ERR_ARG;
+  std::unique_ptr<rh_redlin> p(new (std::nothrow) rh_redlin());
+  if (!p) return RH_ERR_OOM;
+  p->net = n;
+  if (opts) p->opt = *opts; else rh_ipm_default_options(&p->opt);
+  if (!(p->opt.tol > 0.0) || p->opt.max_iter < 0 || !(p->opt.mu_init > 0.0) ||
+      !(p->opt.obj_scale >= 0.0))
+    return RH_ERR_ARG;
+  if ((x0 == nullptr) != (u0 == nullptr)) return RH_ERR_ARG;
+  rh_status st_ = RH_OK;
+  auto fail = [&](rh_status c) { free_ipm(p.get()); return c; };
+#define RL_TRY(expr)               \
+  do {                             \
+    st_ = (expr);                  \
+    if (st_ != RH_OK) return fail(st_); \
+  } while (0)
+  auto& v = p->v;
+  auto& R = p->R;
+  int nfin_full = 0;
+  RL_TRY(setup_ipm_dev(p.get(), n, v, &nfin_full));
+  const rh::Symbolic& s = n->s;
+  const int nu = s.nu, nx = s.nx, m = s.m;
+  // bounded states and the slack bounds of h_r = [h; -x_b]
+  std::vector<int> xb, xbi(nx, -1);
+  for (int k = 0; k < nx; ++k)
+    if (std::isfinite(n->wl[nu + k]) || std::isfinite(n->wu[nu + k])) {
+      xbi[k] = int(xb.size());
+      xb.push_back(k);
+    }
+  std::vector<double> rsl(n->sl), rsu(n->su);
+  for (int k : xb) {
+    rsl.push_back(n->wl[nu + k]);
+    rsu.push_back(n->wu[nu + k]);
+  }
+  R.m = m;
+  R.nxb = int(xb.size());
+  R.mr = m + R.nxb;
+  const int mr = R.mr;
+  RL_TRY(iupload(p.get(), xb, &R.xb));
+  RL_TRY(iupload(p.get(), xbi, &R.xbi));
+  RL_TRY(iupload(p.get(), rsl, &R.rsl));
+  RL_TRY(iupload(p.get(), rsu, &R.rsu));
+  RL_TRY(ialloc(p.get(), mr, &R.sr));
+  RL_TRY(ialloc(p.get(), mr, &R.yr));
+  RL_TRY(ialloc(p.get(), mr, &R.zsl));
+  RL_TRY(ialloc(p.get(), mr, &R.zsu));
+  RL_TRY(ialloc(p.get(), size_t(nu) + 2 * size_t(mr), &R.rp));
+  RL_TRY(ialloc(p.get(), mr, &R.pzsl));
+  RL_TRY(ialloc(p.get(), mr, &R.pzsu));
+  RL_TRY(ialloc(p.get(), mr, &R.st));
+  RL_TRY(ialloc(p.get(), nu, &R.zero));
+  RL_TRY(ialloc(p.get(), rh::IR_NSLOT, &R.red));
+  RL_TRY(ialloc(p.get(), size_t(nu) * nu, &p->K));
+  RL_TRY(ialloc(p.get(), size_t(nu) * nu, &p->Kc));
+  RL_TRY(ialloc(p.get(), nu, &p->rhs));
+  RL_TRY(ialloc(p.get(), nx, &p->adj));
+  RL_TRY(ialloc(p.get(), 4, &p->scal));
+  v.s = R.sr;            // the h rows' slacks and multipliers lead s_r, y_r
+  v.y = R.yr;
+  p->nfin = 0;
+  for (int k = 0; k < nu; ++k)
+    p->nfin += (std::isfinite(n->wl[k]) ? 1 : 0) + (std::isfinite(n->wu[k]) ? 1 : 0);
+  for (int j = 0; j < mr; ++j)
+    p->nfin += (std::isfinite(rsl[j]) ? 1 : 0) + (std::isfinite(rsu[j]) ? 1 : 0);
+  auto& rv = p->rv;
+  rv.nu = nu;
+  rv.nx = 0;
+  rv.m = mr;
+  rv.wl = v.wl;
+  rv.wu = v.wu;
+  rv.sl = R.rsl;
+  rv.su = R.rsu;
+  rv.w = v.w;
+  rv.s = R.sr;
+  rv.y = R.yr;
+  rv.zl = v.zl;
+  rv.zu = v.zu;
+  rv.zsl = R.zsl;
+  rv.zsu = R.zsu;
+  rv.gf = R.zero;
+  rv.p = R.rp;
+  rv.pzl = v.pzl;
+  rv.pzu = v.pzu;
+  rv.pzsl = R.pzsl;
+  rv.pzsu = R.pzsu;
+  rv.wt = v.wt;
+  rv.st = R.st;
+  rv.red = R.red;
+  rv.f = v.f;
+  hipStream_t st = n->stream;
+  if (rh::launch_fill(R.zero, nu, 0.0, st) != hipSuccess) return fail(RH_ERR_HIP);
+  // initial point: the caller's, or theta = 0, Vm = 1, Pg mid-range
+  if (x0) {
+    if (hipMemcpyAsync(v.w, u0, sizeof(double) * nu, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(v.w + nu, x0, sizeof(double) * nx, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return fail(RH_ERR_HIP);
+  } else {
+    std::vector<double> w(s.nw, 0.0);
+    for (int k = 0; k < nu; ++k)
+      w[k] = s.u_kind[k] == 1 ? 1.0 : 0.5 * (n->wl[k] + n->wu[k]);
+    for (int k = 0; k < nx; ++k) w[nu + k] = s.x_kind[k] == 1 ? 1.0 : 0.0;
+    if (hipMemcpy(v.w, w.data(), sizeof(double) * s.nw, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RH_ERR_HIP);
+  }
+  RL_TRY(rh_set_objective_scale(n, 1.0));
+  // controls pushed inside their bounds (multipliers 1, y_r = 0), then the
+  // state projected onto g = 0
+  if (rh::launch_ipm_init_w(rv, kBoundPush, kBoundFrac, st) != hipSuccess) return fail(RH_ERR_HIP);
+  int k = 0;
+  RL_TRY(newton_pf(n, v.w, v.w + nu, kPfTol, kPfMaxIter, &k, nullptr));
+  // objective scale at the projected point; slacks s_r = [-h; x_b] pushed inside
+  if (rh::launch_fill(v.lam, nx, 0.0, st) != hipSuccess ||
+      rh::launch_ipm_lag_grad(n->d, v, st) != hipSuccess ||
+      rh::launch_redlin_init_s(n->d, v, R, kBoundPush, kBoundFrac, st) != hipSuccess ||
+      rh::launch_redlin_stats(n->d, v, R, v.w, R.sr, 1, st) != hipSuccess)
+    return fail(RH_ERR_HIP);
+  double red[rh::IR_NSLOT];
+  RL_TRY(redlin_read(p.get(), red, nullptr));
+  p->sigma_f = p->opt.obj_scale > 0.0 ? p->opt.obj_scale
+                                      : std::min(1.0, 100.0 / std::max(red[rh::IR_GFMAX], 1e-300));
+  RL_TRY(rh_set_objective_scale(n, p->sigma_f));
+#undef RL_TRY
+  p->mu = p->opt.mu_init;
+  *out = p.release();
+  return RH_OK;
+}
+
+void rh_redlin_destroy(rh_redlin* p) {
+  if (!p) return;
+  if (p->net) {
+    (void)hipStreamSynchronize(p->net->stream);
+    (void)rh_set_objective_scale(p->net, 1.0);
+  }
+  free_ipm(p);
+  delete p;
+}
+
+rh_status rh_redlin_step(rh_redlin* p, rh_ipm_info* info) {
+  if (!p) return RH_ERR_ARG;
+  rh_net* n = p->net;
+  if (n->obj_scale != p->sigma_f) RH_TRY(rh_set_objective_scale(n, p->sigma_f));
+  auto& v = p->v;
+  auto& R = p->R;
+  const auto& d = n->d;
+  hipStream_t st = n->stream;
+  const int nu = v.nu, nx = v.nx;
+  double red[rh::IR_NSLOT], f2[2];
+  RH_TRY(redlin_derivatives(p, red, f2));
+  const double f0 = f2[0];
+  const double e0 = redlin_error(p, red, 0.0);
+  if (e0 <= p->opt.tol) {
+    p->converged = true;
+    redlin_info(p, info, f0 / p->sigma_f, red[rh::IR_PRIM_H], e0, 0.0, 0.0, 0.0, 0, 0);
+    return RH_OK;
+  }
+  if (p->iter >= p->opt.max_iter) {
+    redlin_info(p, info, f0 / p->sigma_f, red[rh::IR_PRIM_H], e0, 0.0, 0.0, 0.0, 0, 0);
+    return RH_NOT_CONVERGED;
+  }
+  for (int k = 0; k < 10; ++k) {
+    if (redlin_error(p, red, p->mu) > kKappaEps * p->mu) break;
+    const double nm = std::max(p->opt.tol / 10.0, std::min(kKappaMu * p->mu, std::pow(p->mu, kThetaMu)));
+    if (nm == p->mu) break;
+    p->mu = nm;
+    p->filt.clear();
+  }
+  const double mu = p->mu;
+  // the reduced KKT system through the full-space condensation
+  RH_HIP(rh::launch_redlin_prep(d, v, R, mu, st));
+  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
+  RH_HIP(hipMemcpyAsync(p->Kc, p->K, sizeof(double) * size_t(nu) * nu, hipMemcpyDeviceToDevice, st));
+  double delta = 0.0;
+  rh_status code = rh_solve_condensed_kkt(n, p->K, nu, 0.0, p->rhs, v.r, v.p, nullptr);
+  if (code == RH_NOT_POSDEF) {
+    delta = p->delta_last == 0.0 ? kDelta0 : std::max(kDeltaMin, kKwMinus * p->delta_last);
+    for (;;) {
+      RH_HIP(hipMemcpyAsync(p->K, p->Kc, sizeof(double) * size_t(nu) * nu,
+                            hipMemcpyDeviceToDevice, st));
+      code = rh_solve_condensed_kkt(n, p->K, nu, delta, p->rhs, v.r, v.p, nullptr);
+      if (code != RH_NOT_POSDEF) break;
+      delta *= p->delta_last == 0.0 ? kKwPlusBar : kKwPlus;
+      if (delta > kDeltaMax) {
+        redlin_info(p, info, f0 / p->sigma_f, red[rh::IR_PRIM_H], e0, 0.0, 0.0, delta, 0, 0);
+        return RH_NOT_CONVERGED;
+      }
+    }
+    p->delta_last = delta;
+  }
+  if (code < 0) return code;
+  // reduced step, bound-multiplier steps, largest steps to the boundary
+  const double tau = std::max(kTauMin, 1.0 - mu);
+  RH_HIP(rh::launch_redlin_pack(v, R, mu, p->scal, st));
+  RH_HIP(rh::launch_ipm_dir(p->rv, mu, tau, st));
+  double rd[rh::IR_NSLOT], dphi_f = 0.0;
+  RH_TRY(redlin_read(p, rd, nullptr));
+  RH_HIP(hipMemcpy(&dphi_f, p->scal, sizeof(double), hipMemcpyDeviceToHost));
+  const double a_pri = rd[rh::IR_APRI], a_dual = rd[rh::IR_ADUAL];
+  const double dphi = rd[rh::IR_DPHI] + dphi_f;
+  const double theta = red[rh::IR_THETA];
+  const double phi = f0 - mu * red[rh::IR_LOGSUM];
+  if (p->iter == 0 && p->theta0 < 0.0) p->theta0 = theta;
+  const double th0 = p->theta0 < 0.0 ? theta : p->theta0;
+  const double theta_max = 1e4 * std::max(1.0, th0), theta_min = 1e-4 * std::max(1.0, th0);
+  double a_min = kGammaTheta;
+  if (dphi < 0.0) {
+    a_min = std::min(a_min, kGammaPhi * theta / -dphi);
+    if (theta <= theta_min)
+      a_min = std::min(a_min, kDeltaSw * std::pow(theta, kSTheta) / std::pow(-dphi, kSPhi));
+  }
+  a_min *= kGammaAlpha;
+  double alpha = a_pri;
+  long trials = 0, pf = 0;
+  bool ftype = false;
+  double rt[rh::IR_NSLOT], ft[2];
+  for (;;) {
+    if (alpha < a_min) {
+      redlin_info(p, info, f0 / p->sigma_f, red[rh::IR_PRIM_H], e0, alpha, a_dual, delta, trials,
+                  pf);
+      return RH_NOT_CONVERGED;
+    }
+    // trial point: controls and slacks along the step, the state projected
+    // from its linearised step
+    RH_HIP(rh::launch_ipm_trial(p->rv, alpha, st));
+    RH_HIP(rh::launch_redlin_trial_x(v, alpha, st));
+    int k = 0;
+    rh_status pc;
+    {
+      PhaseScope ps(n, RH_PHASE_PROJECT);
+      pc = newton_pf(n, v.wt, v.wt + nu, kPfTol, kPfMaxIter, &k, nullptr);
+    }
+    if (pc < 0) return pc;
+    ++trials;
+    pf += k;
+    bool ok = pc == RH_OK;
+    ftype = false;
+    if (ok) {
+      RH_HIP(rh::launch_eval_objective(d, v.wt, v.f + 1, st));
+      RH_HIP(rh::launch_redlin_stats(d, v, R, v.wt, R.st, 0, st));
+      RH_TRY(redlin_read(p, rt, ft));
+      const double th_t = rt[rh::IR_THETA];
+      const double ph_t = ft[1] - mu * rt[rh::IR_LOGSUM];
+      ok = std::isfinite(ph_t) && th_t <= theta_max;
+      if (ok)
+        for (const auto& e : p->filt)
+          if (th_t >= e.first && ph_t >= e.second) {
+            ok = false;
+            break;
+          }
+      if (ok) {
+        const bool switching =
+            dphi < 0.0 && alpha * std::pow(-dphi, kSPhi) > kDeltaSw * std::pow(theta, kSTheta);
+        if (switching && theta <= theta_min) {
+          ok = ph_t <= phi + kEtaPhi * alpha * dphi;
+          ftype = true;
+        } else {
+          ok = th_t <= (1.0 - kGammaTheta) * theta || ph_t <= phi - kGammaPhi * theta;
+        }
+      }
+    }
+    if (ok) break;
+    alpha *= 0.5;
+  }
+  if (!ftype) p->filt.push_back({(1.0 - kGammaTheta) * theta, phi - kGammaPhi * theta});
+  RH_HIP(rh::launch_ipm_update(p->rv, alpha, a_dual, mu, kKappaSigma, st));
+  RH_HIP(hipMemcpyAsync(v.w + nu, v.wt + nu, sizeof(double) * nx, hipMemcpyDeviceToDevice, st));
+  p->iter += 1;
+  redlin_info(p, info, ft[1] / p->sigma_f, rt[rh::IR_PRIM_H], e0, alpha, a_dual, delta, trials, pf);
+  return RH_OK;
+}
+
+rh_status rh_redlin_solve(rh_redlin* p, rh_ipm_info* info) {
+  if (!p) return RH_ERR_ARG;
+  rh_ipm_info last{};
+  for (;;) {
+    rh_status c = rh_redlin_step(p, &last);
+    if (c != RH_OK) {
+      if (info) *info = last;
+      return c;
+    }
+    if (last.converged) break;
+  }
+  if (info) *info = last;
+  return RH_OK;
+}
+
+rh_status rh_redlin_get_state(const rh_redlin* p, double* x, double* u, double* s, double* lam,
+                              double* y) {
+  if (!p) return RH_ERR_ARG;
+  const auto& v = p->v;
+  hipStream_t st = p->net->stream;
+  const size_t mr = size_t(p->R.mr);
+  if (u) RH_HIP(hipMemcpyAsync(u, v.w, sizeof(double) * v.nu, hipMemcpyDeviceToDevice, st));
+  if (x) RH_HIP(hipMemcpyAsync(x, v.w + v.nu, sizeof(double) * v.nx, hipMemcpyDeviceToDevice, st));
+  if (s) RH_HIP(hipMemcpyAsync(s, p->R.sr, sizeof(double) * mr, hipMemcpyDeviceToDevice, st));
+  if (lam) RH_HIP(hipMemcpyAsync(lam, v.lam, sizeof(double) * v.nx, hipMemcpyDeviceToDevice, st));
+  if (y) RH_HIP(hipMemcpyAsync(y, p->R.yr, sizeof(double) * mr, hipMemcpyDeviceToDevice, st));
+  return RH_OK;
+}
+
+rh_status rh_redlin_dims(const rh_redlin* p, int64_t* mr, int64_t* nxb) {
+  if (!p) return RH_ERR_ARG;
+  if (mr) *mr = p->R.mr;
+  if (nxb) *nxb = p->R.nxb;
   return RH_OK;
 }
 

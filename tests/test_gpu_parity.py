@@ -163,13 +163,16 @@ def test_set_loads_changes_residual():
     assert _rel(_np(g), go) <= 1e-12 and _rel(_np(h), ho) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["syn9", "syn1354"])
-def test_solve_after_condensation_without_rhs(name):
+@pytest.mark.parametrize("name,width", [("syn9", 1), ("syn1354", 1), ("syn118", 2),
+                                        ("syn1354", 3)])
+def test_solve_after_condensation_without_rhs(name, width):
     """Recovery by the single-column pass (condensation called without r),
-    with the right-hand side condensed separately on the same factors."""
+    with the right-hand side condensed separately on the same factors; the
+    pass reads the sweep records of the handle's panel width."""
     net = NETS[name]()
     M = Model(net)
-    G = _net_api().Net(net)
+    G = _net_api().Net(net, panel_width=width)
+    assert G.info["panel_width"] == width
     x, u, lam, y, sx, su, ss = random_point(M, 3, lam_scale=1.0, sig_range=(10.0, 1e4))
     r = residual_vector(M, 4)
     args = list(map(_t, (x, u, lam, y, sx, su, ss)))
