@@ -225,6 +225,34 @@ def ipm_run(api, net, torch, max_iter):
             "tol": 1e-6, "start": "flat (theta 0, Vm 1, Pg mid-range)"}
 
 
+def redlin_run(api, net, torch, max_iter):
+    """RedLin (Algorithm 2, rh_redlin_step) from the flat start to a scaled
+    KKT error of 1e-6: iterations per second, with the projection's
+    Newton-Raphson steps and its share of the time."""
+    G = api.Net(net)
+    rl = api.RedLin(G, tol=1e-6, max_iter=max_iter)
+    G.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, code, info, pf = 0, 0, {}, 0
+    while iters <= max_iter:
+        code, info = rl.step()
+        if code != 0 or info["converged"]:
+            break
+        iters += 1
+        pf += info["pf_iters"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phases = G.profile_read()
+    rl.close()
+    G.close()
+    return {"iters_per_s": iters / el if iters else 0.0, "iterations": iters,
+            "ms_per_iter": 1e3 * el / max(1, iters), "converged": bool(info.get("converged")),
+            "status": int(code), "objective": info.get("obj"), "pf_newton_steps": pf,
+            "projection_ms_per_iter": phases["project"][0] / max(1, iters),
+            "tol": 1e-6, "start": "flat (theta 0, Vm 1, Pg mid-range), projected"}
+
+
 def cpu_baseline(net, args_np, seconds):
     """The oracle's full step (dense LU of G_x, explicit K_cond, RHS, Cholesky,
     recovery) on the host, repeated for a bounded time."""
@@ -372,6 +400,8 @@ def main():
         line["autotune"] = {"best": {"panel_width": best[0], "lds_panel": best[1]},
                             "condensation_us": {f"w{w}_lds{l}": round(v, 1)
                                                 for (w, l), v in times.items()}}
+    if not args.no_ipm:
+        line["redlin"] = redlin_run(api, net, torch, args.ipm_iters)
     if not args.no_diff:
         line["differentiated"] = differentiated_run(api, torch)
     if not args.no_cpu_baseline:
