@@ -366,6 +366,22 @@ rh_status rh_ipm_create(rh_net* net, const rh_ipm_options* opts, const double* x
 rh_status rh_ipm_step(rh_ipm* ipm, rh_ipm_info* info);
 /* Iterates until converged (RH_OK) or a step fails (its code). */
 rh_status rh_ipm_solve(rh_ipm* ipm, rh_ipm_info* info);
+/* One iteration of every solver of a batch in lockstep (Algorithm 1 for load
+ * scenarios or networks solved together). Solver i must drive the batch's
+ * network i (rh_batch_create over the same handles, in the same order). The
+ * evaluations, bound-multiplier steps, filter line searches (one trial per
+ * unfinished solver per round) and updates run per solver, on the solvers'
+ * streams, with their scalars read together; the condensation and the first
+ * solve (delta_w = 0) run as one batched launch each over all instances
+ * (rh_batch_condense / rh_batch_solve); inertia-correction retries run per
+ * solver. A solver whose point already satisfies the tolerance takes no step
+ * (info converged = 1, as rh_ipm_step). infos[count], codes[count] (host,
+ * optional): each solver's info and status as rh_ipm_step would return them;
+ * the iterates equal rh_ipm_step's on each solver bit for bit. Returns RH_OK,
+ * or a negative code on a hard error (RH_ERR_ARG for a solver not on the
+ * batch's network i). */
+rh_status rh_ipm_batch_step(rh_batch* batch, rh_ipm* const* ipms, rh_ipm_info* infos,
+                            int32_t* codes);
 /* Device copies of the current point (any pointer may be NULL). */
 rh_status rh_ipm_get_state(const rh_ipm* ipm, double* x, double* u, double* s, double* lam,
                            double* y);

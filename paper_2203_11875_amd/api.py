@@ -491,6 +491,28 @@ class Ipm:
         return (gpd, gqd, xi) if want_xi else (gpd, gqd)
 
 
+class IpmBatch:
+    """Solvers on the networks of a batch stepped in lockstep
+    (rh_ipm_batch_step): the condensation and the first solve of every
+    iteration are one batched launch each over all instances."""
+
+    def __init__(self, batch, ipms):
+        if len(ipms) != len(batch.nets):
+            raise ValueError("one solver per network of the batch")
+        self.batch, self.ipms = batch, list(ipms)
+        self._h = (C.c_void_p * len(ipms))(*[i.h.value for i in ipms])
+
+    def step(self):
+        """One lockstep iteration; returns [(status, info dict)] per solver."""
+        n = len(self.ipms)
+        infos = (_abi.rh_ipm_info * n)()
+        codes = (C.c_int32 * n)()
+        _check(lib().rh_ipm_batch_step(self.batch.h, C.cast(self._h, C.c_void_p),
+                                       C.cast(infos, C.c_void_p), C.cast(codes, C.c_void_p)),
+               "rh_ipm_batch_step")
+        return [(int(codes[i]), _info_ipm(infos[i])) for i in range(n)]
+
+
 class RedLin:
     """Reduce-then-linearize solver (Algorithm 2) on a device network handle
     (rh_redlin_*)."""

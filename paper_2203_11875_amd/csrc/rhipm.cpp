@@ -1118,23 +1118,6 @@ double opt_error(const rh_ipm* p, const double* red, double mu) {
   return std::max(ed, std::max(ep, ec));
 }
 
-// Evaluation at the current iterate: derivative values (with the Hessian),
-// gradient of the Lagrangian, reductions and the objective.
-rh_status eval_iterate(rh_ipm* p, double* red, double* f) {
-  rh_net* n = p->net;
-  const auto& d = n->d;
-  auto& v = p->v;
-  hipStream_t st = n->stream;
-  {
-    PhaseScope ps(n, RH_PHASE_EVAL);
-    RH_HIP(rh::launch_eval(d, v.w + v.nu, v.w, v.lam, v.y, true, st));
-    RH_HIP(rh::launch_eval_objective(d, v.w, v.f, st));
-    RH_HIP(rh::launch_ipm_lag_grad(d, v, st));
-    RH_HIP(rh::launch_ipm_stats(d, v, v.w, v.s, 1, st));
-  }
-  return read_red(p, red, f);
-}
-
 void fill_info(const rh_ipm* p, rh_ipm_info* info, double obj, double inf_pr, double err,
                double alpha, double alpha_z, double delta, long trials) {
   if (!info) return;
@@ -1150,6 +1133,207 @@ void fill_info(const rh_ipm* p, rh_ipm_info* info, double obj, double inf_pr, do
   info->ls_trials = trials;
   info->converged = p->converged ? 1 : 0;
   info->obj_scale = p->sigma_f;
+}
+
+// One iteration of Algorithm 1 in stages, so that a batch of solvers can run
+// them in lockstep (rh_ipm_batch_step) with the condensation and the solve
+// batched; rh_ipm_step runs the same stages for one solver.
+struct IpmStep {
+  double red[rh::IR_NSLOT] = {}, f2[2] = {}, f0 = 0.0, e0 = 0.0, mu = 0.0, delta = 0.0;
+  double a_pri = 1.0, a_dual = 1.0, dphi = 0.0, theta = 0.0, phi = 0.0;
+  double theta_max = 0.0, theta_min = 0.0, a_min = 0.0, alpha = 1.0;
+  double rt[rh::IR_NSLOT] = {}, ft[2] = {};
+  long trials = 0;
+  bool ftype = false;
+  bool done = false;      // the iteration ended (converged, failed or max_iter)
+  rh_status code = RH_OK;
+};
+
+// Evaluation at the current iterate (launches only).
+rh_status ipm_eval_launch(rh_ipm* p) {
+  rh_net* n = p->net;
+  // another solver on the same network may have changed the objective scale
+  if (n->obj_scale != p->sigma_f) RH_TRY(rh_set_objective_scale(n, p->sigma_f));
+  const auto& d = n->d;
+  auto& v = p->v;
+  hipStream_t st = n->stream;
+  PhaseScope ps(n, RH_PHASE_EVAL);
+  RH_HIP(rh::launch_eval(d, v.w + v.nu, v.w, v.lam, v.y, true, st));
+  RH_HIP(rh::launch_eval_objective(d, v.w, v.f, st));
+  RH_HIP(rh::launch_ipm_lag_grad(d, v, st));
+  RH_HIP(rh::launch_ipm_stats(d, v, v.w, v.s, 1, st));
+  return RH_OK;
+}
+
+// Convergence test, iteration limit, barrier update, residuals and Sigma.
+rh_status ipm_begin(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
+  RH_TRY(read_red(p, s.red, s.f2));
+  const double* red = s.red;
+  s.f0 = s.f2[0];
+  s.e0 = opt_error(p, red, 0.0);
+  const double inf_pr = std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]);
+  if (s.e0 <= p->opt.tol) {
+    p->converged = true;
+    fill_info(p, info, s.f0 / p->sigma_f, inf_pr, s.e0, 0.0, 0.0, 0.0, 0);
+    s.done = true;
+    s.code = RH_OK;
+    return RH_OK;
+  }
+  if (p->iter >= p->opt.max_iter) {
+    fill_info(p, info, s.f0 / p->sigma_f, inf_pr, s.e0, 0.0, 0.0, 0.0, 0);
+    s.done = true;
+    s.code = RH_NOT_CONVERGED;
+    return RH_OK;
+  }
+  // barrier update (monotone)
+  for (int k = 0; k < 10; ++k) {
+    if (opt_error(p, red, p->mu) > kKappaEps * p->mu) break;
+    const double nm = std::max(p->opt.tol / 10.0, std::min(kKappaMu * p->mu, std::pow(p->mu, kThetaMu)));
+    if (nm == p->mu) break;
+    p->mu = nm;
+    p->filt.clear();
+  }
+  s.mu = p->mu;
+  RH_HIP(rh::launch_ipm_prep(p->net->d, p->v, s.mu, p->net->stream));
+  return RH_OK;
+}
+
+rh_status ipm_condense_single(rh_ipm* p) {
+  rh_net* n = p->net;
+  auto& v = p->v;
+  const int nu = v.nu;
+  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
+  RH_HIP(hipMemcpyAsync(p->Kc, p->K, sizeof(double) * size_t(nu) * nu, hipMemcpyDeviceToDevice,
+                        n->stream));
+  return RH_OK;
+}
+
+rh_status ipm_first_solve(rh_ipm* p) {
+  return rh_solve_condensed_kkt(p->net, p->K, p->v.nu, 0.0, p->rhs, p->v.r, p->v.p, nullptr);
+}
+
+// Inertia correction after the first solve (delta_w = 0) returned `code`:
+// K_cond + delta_w I from the saved copy until the factorisation succeeds.
+rh_status ipm_factor(rh_ipm* p, IpmStep& s, rh_ipm_info* info, rh_status code) {
+  rh_net* n = p->net;
+  auto& v = p->v;
+  const int nu = v.nu;
+  s.delta = 0.0;
+  if (code == RH_NOT_POSDEF) {
+    double delta = p->delta_last == 0.0 ? kDelta0 : std::max(kDeltaMin, kKwMinus * p->delta_last);
+    for (;;) {
+      RH_HIP(hipMemcpyAsync(p->K, p->Kc, sizeof(double) * size_t(nu) * nu,
+                            hipMemcpyDeviceToDevice, n->stream));
+      code = rh_solve_condensed_kkt(n, p->K, nu, delta, p->rhs, v.r, v.p, nullptr);
+      if (code != RH_NOT_POSDEF) break;
+      delta *= p->delta_last == 0.0 ? kKwPlusBar : kKwPlus;
+      if (delta > kDeltaMax) {
+        fill_info(p, info, s.f0 / p->sigma_f,
+                  std::max(s.red[rh::IR_PRIM_G], s.red[rh::IR_PRIM_H]), s.e0, 0.0, 0.0, delta, 0);
+        s.done = true;
+        s.code = RH_NOT_CONVERGED;
+        return RH_OK;
+      }
+    }
+    p->delta_last = delta;
+    s.delta = delta;
+  }
+  if (code < 0) return code;
+  return RH_OK;
+}
+
+// bound-multiplier steps and the largest steps to the boundary
+rh_status ipm_dir_launch(rh_ipm* p, IpmStep& s) {
+  const double tau = std::max(kTauMin, 1.0 - s.mu);
+  RH_HIP(rh::launch_ipm_dir(p->v, s.mu, tau, p->net->stream));
+  return RH_OK;
+}
+
+// line-search constants of the filter method
+rh_status ipm_dir_read(rh_ipm* p, IpmStep& s) {
+  double rd[rh::IR_NSLOT];
+  RH_TRY(read_red(p, rd, nullptr));
+  s.a_pri = rd[rh::IR_APRI];
+  s.a_dual = rd[rh::IR_ADUAL];
+  s.dphi = rd[rh::IR_DPHI];
+  s.theta = s.red[rh::IR_THETA];
+  s.phi = s.f0 - s.mu * s.red[rh::IR_LOGSUM];
+  if (p->iter == 0 && p->theta0 < 0.0) p->theta0 = s.theta;
+  const double th0 = p->theta0 < 0.0 ? s.theta : p->theta0;
+  s.theta_max = 1e4 * std::max(1.0, th0);
+  s.theta_min = 1e-4 * std::max(1.0, th0);
+  double a_min = kGammaTheta;
+  if (s.dphi < 0.0) {
+    a_min = std::min(a_min, kGammaPhi * s.theta / -s.dphi);
+    if (s.theta <= s.theta_min)
+      a_min = std::min(a_min, kDeltaSw * std::pow(s.theta, kSTheta) / std::pow(-s.dphi, kSPhi));
+  }
+  s.a_min = a_min * kGammaAlpha;
+  s.alpha = s.a_pri;
+  s.trials = 0;
+  return RH_OK;
+}
+
+// false (and the iteration ends with RH_NOT_CONVERGED) once the step is too short
+bool ipm_trial_ok(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
+  if (s.alpha >= s.a_min) return true;
+  fill_info(p, info, s.f0 / p->sigma_f, std::max(s.red[rh::IR_PRIM_G], s.red[rh::IR_PRIM_H]),
+            s.e0, s.alpha, s.a_dual, s.delta, s.trials);
+  s.done = true;
+  s.code = RH_NOT_CONVERGED;
+  return false;
+}
+
+rh_status ipm_trial_launch(rh_ipm* p, IpmStep& s) {
+  rh_net* n = p->net;
+  const auto& d = n->d;
+  auto& v = p->v;
+  hipStream_t st = n->stream;
+  RH_HIP(rh::launch_ipm_trial(v, s.alpha, st));
+  RH_HIP(rh::launch_eval(d, v.wt + v.nu, v.wt, nullptr, nullptr, false, st));
+  RH_HIP(rh::launch_eval_objective(d, v.wt, v.f + 1, st));
+  RH_HIP(rh::launch_ipm_stats(d, v, v.wt, v.st, 0, st));
+  return RH_OK;
+}
+
+// filter acceptance of the trial point; halves alpha if rejected
+rh_status ipm_trial_judge(rh_ipm* p, IpmStep& s, bool* accepted) {
+  RH_TRY(read_red(p, s.rt, s.ft));
+  ++s.trials;
+  const double th_t = s.rt[rh::IR_THETA];
+  const double ph_t = s.ft[1] - s.mu * s.rt[rh::IR_LOGSUM];
+  bool ok = std::isfinite(ph_t) && th_t <= s.theta_max;
+  if (ok)
+    for (const auto& e : p->filt)
+      if (th_t >= e.first && ph_t >= e.second) {
+        ok = false;
+        break;
+      }
+  s.ftype = false;
+  if (ok) {
+    const bool switching = s.dphi < 0.0 &&
+                           s.alpha * std::pow(-s.dphi, kSPhi) > kDeltaSw * std::pow(s.theta, kSTheta);
+    if (switching && s.theta <= s.theta_min) {
+      ok = ph_t <= s.phi + kEtaPhi * s.alpha * s.dphi;
+      s.ftype = true;
+    } else {
+      ok = th_t <= (1.0 - kGammaTheta) * s.theta || ph_t <= s.phi - kGammaPhi * s.theta;
+    }
+  }
+  *accepted = ok;
+  if (!ok) s.alpha *= 0.5;
+  return RH_OK;
+}
+
+rh_status ipm_finish(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
+  if (!s.ftype) p->filt.push_back({(1.0 - kGammaTheta) * s.theta, s.phi - kGammaPhi * s.theta});
+  RH_HIP(rh::launch_ipm_update(p->v, s.alpha, s.a_dual, s.mu, kKappaSigma, p->net->stream));
+  p->iter += 1;
+  fill_info(p, info, s.ft[1] / p->sigma_f, std::max(s.rt[rh::IR_PRIM_G], s.rt[rh::IR_PRIM_H]), s.e0,
+            s.alpha, s.a_dual, s.delta, s.trials);
+  s.done = true;
+  s.code = RH_OK;
+  return RH_OK;
 }
 
 }  // namespace
@@ -1240,124 +1424,94 @@ void rh_ipm_destroy(rh_ipm* p) {
 
 rh_status rh_ipm_step(rh_ipm* p, rh_ipm_info* info) {
   if (!p) return RH_ERR_ARG;
-  rh_net* n = p->net;
-  // another solver on the same network may have changed the objective scale
-  if (n->obj_scale != p->sigma_f) RH_TRY(rh_set_objective_scale(n, p->sigma_f));
-  auto& v = p->v;
-  const auto& d = n->d;
-  hipStream_t st = n->stream;
-  const int nu = v.nu, nw = v.nu + v.nx;
-  double red[rh::IR_NSLOT], f2[2];
-  RH_TRY(eval_iterate(p, red, f2));
-  const double f0 = f2[0];
-  const double e0 = opt_error(p, red, 0.0);
-  if (e0 <= p->opt.tol) {
-    p->converged = true;
-    fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
-              0.0, 0.0, 0.0, 0);
-    return RH_OK;
-  }
-  if (p->iter >= p->opt.max_iter) {
-    fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
-              0.0, 0.0, 0.0, 0);
-    return RH_NOT_CONVERGED;
-  }
-  // barrier update (monotone)
-  for (int k = 0; k < 10; ++k) {
-    if (opt_error(p, red, p->mu) > kKappaEps * p->mu) break;
-    const double nm = std::max(p->opt.tol / 10.0, std::min(kKappaMu * p->mu, std::pow(p->mu, kThetaMu)));
-    if (nm == p->mu) break;
-    p->mu = nm;
-    p->filt.clear();
-  }
-  const double mu = p->mu;
-  // step: residuals and Sigma, condensation, Cholesky with inertia correction
-  RH_HIP(rh::launch_ipm_prep(d, v, mu, st));
-  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
-  RH_HIP(hipMemcpyAsync(p->Kc, p->K, sizeof(double) * size_t(nu) * nu, hipMemcpyDeviceToDevice, st));
-  double delta = 0.0;
-  rh_status code = rh_solve_condensed_kkt(n, p->K, nu, 0.0, p->rhs, v.r, v.p, nullptr);
-  if (code == RH_NOT_POSDEF) {
-    delta = p->delta_last == 0.0 ? kDelta0 : std::max(kDeltaMin, kKwMinus * p->delta_last);
-    for (;;) {
-      RH_HIP(hipMemcpyAsync(p->K, p->Kc, sizeof(double) * size_t(nu) * nu,
-                            hipMemcpyDeviceToDevice, st));
-      code = rh_solve_condensed_kkt(n, p->K, nu, delta, p->rhs, v.r, v.p, nullptr);
-      if (code != RH_NOT_POSDEF) break;
-      delta *= p->delta_last == 0.0 ? kKwPlusBar : kKwPlus;
-      if (delta > kDeltaMax) {
-        fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
-                  0.0, 0.0, delta, 0);
-        return RH_NOT_CONVERGED;
-      }
-    }
-    p->delta_last = delta;
-  }
-  if (code < 0) return code;
-  // bound-multiplier steps and the largest steps to the boundary
-  const double tau = std::max(kTauMin, 1.0 - mu);
-  RH_HIP(rh::launch_ipm_dir(v, mu, tau, st));
-  double rd[rh::IR_NSLOT];
-  RH_TRY(read_red(p, rd, nullptr));
-  const double a_pri = rd[rh::IR_APRI], a_dual = rd[rh::IR_ADUAL], dphi = rd[rh::IR_DPHI];
-  // filter line search on the barrier objective phi and the violation theta
-  const double theta = red[rh::IR_THETA];
-  const double phi = f0 - mu * red[rh::IR_LOGSUM];
-  if (p->iter == 0 && p->theta0 < 0.0) p->theta0 = theta;
-  const double th0 = p->theta0 < 0.0 ? theta : p->theta0;
-  const double theta_max = 1e4 * std::max(1.0, th0), theta_min = 1e-4 * std::max(1.0, th0);
-  double a_min = kGammaTheta;
-  if (dphi < 0.0) {
-    a_min = std::min(a_min, kGammaPhi * theta / -dphi);
-    if (theta <= theta_min)
-      a_min = std::min(a_min, kDeltaSw * std::pow(theta, kSTheta) / std::pow(-dphi, kSPhi));
-  }
-  a_min *= kGammaAlpha;
-  double alpha = a_pri;
-  long trials = 0;
-  bool ftype = false;
-  double rt[rh::IR_NSLOT], ft[2];
+  IpmStep s;
+  RH_TRY(ipm_eval_launch(p));
+  RH_TRY(ipm_begin(p, s, info));
+  if (s.done) return s.code;
+  RH_TRY(ipm_condense_single(p));
+  RH_TRY(ipm_factor(p, s, info, ipm_first_solve(p)));
+  if (s.done) return s.code;
+  RH_TRY(ipm_dir_launch(p, s));
+  RH_TRY(ipm_dir_read(p, s));
   for (;;) {
-    if (alpha < a_min) {
-      fill_info(p, info, f0 / p->sigma_f, std::max(red[rh::IR_PRIM_G], red[rh::IR_PRIM_H]), e0,
-                alpha, a_dual, delta, trials);
-      return RH_NOT_CONVERGED;
-    }
-    RH_HIP(rh::launch_ipm_trial(v, alpha, st));
-    RH_HIP(rh::launch_eval(d, v.wt + nu, v.wt, nullptr, nullptr, false, st));
-    RH_HIP(rh::launch_eval_objective(d, v.wt, v.f + 1, st));
-    RH_HIP(rh::launch_ipm_stats(d, v, v.wt, v.st, 0, st));
-    RH_TRY(read_red(p, rt, ft));
-    ++trials;
-    const double th_t = rt[rh::IR_THETA];
-    const double ph_t = ft[1] - mu * rt[rh::IR_LOGSUM];
-    bool ok = std::isfinite(ph_t) && th_t <= theta_max;
-    if (ok)
-      for (const auto& e : p->filt)
-        if (th_t >= e.first && ph_t >= e.second) {
-          ok = false;
-          break;
-        }
-    ftype = false;
-    if (ok) {
-      const bool switching =
-          dphi < 0.0 && alpha * std::pow(-dphi, kSPhi) > kDeltaSw * std::pow(theta, kSTheta);
-      if (switching && theta <= theta_min) {
-        ok = ph_t <= phi + kEtaPhi * alpha * dphi;
-        ftype = true;
-      } else {
-        ok = th_t <= (1.0 - kGammaTheta) * theta || ph_t <= phi - kGammaPhi * theta;
-      }
-    }
-    if (ok) break;
-    alpha *= 0.5;
+    if (!ipm_trial_ok(p, s, info)) return s.code;
+    RH_TRY(ipm_trial_launch(p, s));
+    bool accepted = false;
+    RH_TRY(ipm_trial_judge(p, s, &accepted));
+    if (accepted) break;
   }
-  if (!ftype) p->filt.push_back({(1.0 - kGammaTheta) * theta, phi - kGammaPhi * theta});
-  RH_HIP(rh::launch_ipm_update(v, alpha, a_dual, mu, kKappaSigma, st));
-  p->iter += 1;
-  fill_info(p, info, ft[1] / p->sigma_f, std::max(rt[rh::IR_PRIM_G], rt[rh::IR_PRIM_H]), e0, alpha,
-            a_dual, delta, trials);
-  (void)nw;
+  return ipm_finish(p, s, info);
+}
+
+rh_status rh_ipm_batch_step(rh_batch* b, rh_ipm* const* ipms, rh_ipm_info* infos,
+                            int32_t* codes) {
+  if (!b || !ipms) return RH_ERR_ARG;
+  const size_t cnt = b->nets.size();
+  for (size_t i = 0; i < cnt; ++i)
+    if (!ipms[i] || ipms[i]->net != b->nets[i]) return RH_ERR_ARG;
+  std::vector<IpmStep> S(cnt);
+  auto inf = [&](size_t i) { return infos ? &infos[i] : nullptr; };
+  for (size_t i = 0; i < cnt; ++i) RH_TRY(ipm_eval_launch(ipms[i]));
+  bool any = false;
+  for (size_t i = 0; i < cnt; ++i) {
+    RH_TRY(ipm_begin(ipms[i], S[i], inf(i)));
+    any = any || !S[i].done;
+  }
+  if (any) {
+    // one batched condensation and one batched solve (delta_w = 0) for every
+    // instance (finished ones too: their matrices are the solver's scratch)
+    std::vector<rh_batch_condense_item> ci(cnt);
+    std::vector<rh_batch_solve_item> si(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+      rh_ipm* p = ipms[i];
+      auto& v = p->v;
+      const int nu = v.nu;
+      ci[i] = rh_batch_condense_item{};
+      ci[i].x = v.w + nu; ci[i].u = v.w; ci[i].lam = v.lam; ci[i].y = v.y;
+      ci[i].sig_x = v.sig_w + nu; ci[i].sig_u = v.sig_w; ci[i].sig_s = v.sig_s;
+      ci[i].r = v.r; ci[i].K = p->K; ci[i].ldk = nu; ci[i].rhs = p->rhs;
+      si[i] = rh_batch_solve_item{};
+      si[i].K = p->K; si[i].ldk = nu; si[i].delta_w = 0.0; si[i].rhs = p->rhs;
+      si[i].r = v.r; si[i].p = v.p;
+    }
+    RH_TRY(rh_batch_condense(b, ci.data()));
+    for (size_t i = 0; i < cnt; ++i) {
+      const int nu = ipms[i]->v.nu;
+      RH_HIP(hipMemcpyAsync(ipms[i]->Kc, ipms[i]->K, sizeof(double) * size_t(nu) * nu,
+                            hipMemcpyDeviceToDevice, b->stream));
+    }
+    std::vector<int32_t> st(cnt, RH_OK);
+    const rh_status bs = rh_batch_solve(b, si.data(), st.data());
+    if (bs < 0 && bs != RH_ERR_STATE) return bs;
+    // inertia-correction retries per solver (the batch stream has drained)
+    for (size_t i = 0; i < cnt; ++i)
+      if (!S[i].done) RH_TRY(ipm_factor(ipms[i], S[i], inf(i), rh_status(st[i])));
+    for (size_t i = 0; i < cnt; ++i)
+      if (!S[i].done) RH_TRY(ipm_dir_launch(ipms[i], S[i]));
+    for (size_t i = 0; i < cnt; ++i)
+      if (!S[i].done) RH_TRY(ipm_dir_read(ipms[i], S[i]));
+    // filter line searches in lockstep: one trial per unfinished solver per round
+    std::vector<char> acc(cnt, 0);
+    for (;;) {
+      bool pending = false;
+      for (size_t i = 0; i < cnt; ++i)
+        if (!S[i].done && !acc[i] && ipm_trial_ok(ipms[i], S[i], inf(i))) {
+          RH_TRY(ipm_trial_launch(ipms[i], S[i]));
+          pending = true;
+        }
+      if (!pending) break;
+      for (size_t i = 0; i < cnt; ++i)
+        if (!S[i].done && !acc[i]) {
+          bool ok = false;
+          RH_TRY(ipm_trial_judge(ipms[i], S[i], &ok));
+          acc[i] = ok ? 1 : 0;
+        }
+    }
+    for (size_t i = 0; i < cnt; ++i)
+      if (!S[i].done && acc[i]) RH_TRY(ipm_finish(ipms[i], S[i], inf(i)));
+  }
+  if (codes)
+    for (size_t i = 0; i < cnt; ++i) codes[i] = S[i].code;
   return RH_OK;
 }
 
