@@ -229,6 +229,44 @@ def concurrent_scenarios(api, torch, count=16, workers=4):
                     "host threads with one handle and stream each"}
 
 
+def batched_scenarios(api, torch, count=16):
+    """The differentiated OPF scenarios of differentiated_run as one
+    api.OPFBatchLayer call: the forward solves all scenarios in lockstep with
+    one batched condensation and solve per round; the backward differentiates
+    each scenario."""
+    import numpy as np
+    import synthnet
+    base = synthnet.case1354(0)
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(0)
+    w_pg = torch.as_tensor(rng.standard_normal(base.ng), device=dev)
+    w_vm = torch.as_tensor(rng.standard_normal(base.nb), device=dev)
+    scen = [synthnet.scale_loads(base, s) for s in range(1, count + 1)]
+    layer = api.OPFBatchLayer(base, count, tol=1e-8)
+    pd0 = torch.as_tensor(np.stack([n.pd for n in scen]), device=dev)
+    qd0 = torch.as_tensor(np.stack([n.qd for n in scen]), device=dev)
+
+    def run():
+        pd = pd0.clone().requires_grad_(True)
+        qd = qd0.clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        pg, vm, f = layer(pd, qd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ((pg * w_pg).sum() + (vm * w_vm).sum() + f.sum()).backward()
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1
+
+    run()                               # untimed first use of every handle
+    tf, tb = run()
+    iters = sum(int(i["iter"]) for i in layer.last_infos)
+    return {"scenarios": count, "scenarios_per_s": count / (tf + tb),
+            "forward_ms": 1e3 * tf, "backward_ms": 1e3 * tb,
+            "ipm_iters_per_s_forward": iters / tf, "ipm_iterations_mean": iters / count,
+            "step": "forward: all scenarios in lockstep to 1e-8 (rh_ipm_batch_step); "
+                    "backward: one adjoint solve per scenario"}
+
+
 def algorithmic_bytes(info, ncols):
     """Paper-dataflow bytes of one condensation launch: every stage reads its
     input panel and writes its output panel (8 (12 nx + 5 nu) bytes per
@@ -502,6 +540,7 @@ def main():
         line["differentiated"] = differentiated_run(api, torch)
         line["differentiated"]["concurrent"] = concurrent_scenarios(api, torch, 16,
                                                                     args.workers)
+        line["differentiated"]["batched"] = batched_scenarios(api, torch, 16)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args_np, args.cpu_seconds)
     print(json.dumps(line), flush=True)

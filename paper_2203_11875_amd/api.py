@@ -599,6 +599,64 @@ class OPFLayer:
         return ipm, info
 
 
+class OPFBatchLayer:
+    """OPFLayer over a batch of load scenarios of one network: (Pd, Qd) of
+    shape (S, nb) -> (Pg (S, ng), Vm (S, nb), f (S)). The forward pass solves
+    all scenarios in lockstep (rh_ipm_batch_step: one batched condensation
+    and solve per round, each scenario on its own handle and stream); the
+    backward pass differentiates each scenario as OPFLayer does. Gradients
+    equal those of OPFLayer scenario by scenario, bit for bit."""
+
+    def __init__(self, net, count, tol=1e-8, max_iter=200, **net_kw):
+        import torch
+        self.torch = torch
+        self.count, self.tol, self.max_iter = int(count), float(tol), int(max_iter)
+        self.nets = [Net(net, stream=torch.cuda.Stream(), **net_kw) for _ in range(self.count)]
+        self.batch = Batch(self.nets, stream=torch.cuda.Stream())
+        self.nb, self.ng = self.nets[0].info["nb"], self.nets[0].info["ng"]
+
+    def __call__(self, pd, qd):
+        return _OPFBatchFunction.apply(pd, qd, self)
+
+    def _solve(self, pd, qd):
+        self._fork()
+        ipms = []
+        for i, G in enumerate(self.nets):
+            G.set_loads(pd[i], qd[i])
+            ipm = Ipm(G, tol=self.tol, max_iter=self.max_iter)
+            G._ipm = None        # the solvers belong to the autograd graph
+            ipms.append(ipm)
+        ib = IpmBatch(self.batch, ipms)
+        done = [False] * self.count
+        infos = [None] * self.count
+        for _ in range(self.max_iter + 2):
+            for i, (code, info) in enumerate(ib.step()):
+                if done[i]:
+                    continue
+                if code != _abi.RH_OK:
+                    _check(code, "rh_ipm_batch_step")
+                if info["converged"]:
+                    done[i], infos[i] = True, info
+            if all(done):
+                break
+        if not all(done):
+            _check(_abi.RH_NOT_CONVERGED, "rh_ipm_batch_step")
+        self.last_infos = infos
+        return ipms
+
+    def _fork(self):
+        """Every handle's stream waits for the caller's (inputs ready)."""
+        cur = self.torch.cuda.current_stream()
+        for G in self.nets:
+            G.stream.wait_stream(cur)
+
+    def _join(self):
+        """The caller's stream waits for every handle's (outputs ready)."""
+        cur = self.torch.cuda.current_stream()
+        for G in self.nets:
+            cur.wait_stream(G.stream)
+
+
 def _make_opf_function():
     import torch
 
@@ -619,17 +677,48 @@ def _make_opf_function():
             gpd, gqd = ctx.ipm.backward(gpg, gvm, gf)
             return gpd, gqd, None
 
-    return _OPF
+    class _OPFBatch(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, pd, qd, layer):
+            S, nb = layer.count, layer.nb
+            n0 = layer.nets[0]
+            pdd = n0._t(pd).reshape(S, nb).contiguous()
+            qdd = n0._t(qd).reshape(S, nb).contiguous()
+            ipms = layer._solve(pdd, qdd)
+            outs = [ipm.outputs() for ipm in ipms]
+            layer._join()
+            ctx.ipms, ctx.layer, ctx.loads = ipms, layer, (pdd, qdd)
+            return (torch.stack([o[0] for o in outs]), torch.stack([o[1] for o in outs]),
+                    torch.stack([o[2] for o in outs]))
+
+        @staticmethod
+        def backward(ctx, gpg, gvm, gf):
+            layer = ctx.layer
+            pdd, qdd = ctx.loads
+            layer._fork()
+            gp, gq = [], []
+            for i, (G, ipm) in enumerate(zip(layer.nets, ctx.ipms)):
+                G.set_loads(pdd[i], qdd[i])
+                a, b = ipm.backward(gpg[i] if gpg is not None else None,
+                                    gvm[i] if gvm is not None else None,
+                                    gf[i] if gf is not None else None)
+                gp.append(a)
+                gq.append(b)
+            layer._join()
+            return torch.stack(gp), torch.stack(gq), None
+
+    return _OPF, _OPFBatch
 
 
 class _Lazy:
-    def __init__(self):
-        self.fn = None
+    def __init__(self, which):
+        self.which, self.fn = which, None
 
     def apply(self, *a):
         if self.fn is None:
-            self.fn = _make_opf_function()
+            self.fn = _make_opf_function()[self.which]
         return self.fn.apply(*a)
 
 
-_OPFFunction = _Lazy()
+_OPFFunction = _Lazy(0)
+_OPFBatchFunction = _Lazy(1)

@@ -163,3 +163,30 @@ def test_objective_gradient_is_envelope_1354():
     scale = np.abs(np.concatenate([epd, eqd])).max()
     assert np.abs(gpd - epd).max() <= 1e-5 * scale, np.abs(gpd - epd).max() / scale
     assert np.abs(gqd - eqd).max() <= 1e-5 * scale, np.abs(gqd - eqd).max() / scale
+
+
+def test_batch_layer_equals_single_layer():
+    """OPFBatchLayer (lockstep forward over scenarios) gives, scenario by
+    scenario, the outputs and gradients of OPFLayer bit for bit."""
+    api = _api()
+    base = synthnet.case118(0)
+    scen = [synthnet.scale_loads(base, s) for s in (1, 2, 3)]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rng = np.random.default_rng(9)
+    w_pg = torch.tensor(rng.standard_normal((3, base.ng)), device=dev)
+    w_vm = torch.tensor(rng.standard_normal((3, base.nb)), device=dev)
+    w_f = torch.tensor(rng.standard_normal(3) * 1e-3, device=dev)
+    pd = torch.tensor(np.stack([n.pd for n in scen]), device=dev, requires_grad=True)
+    qd = torch.tensor(np.stack([n.qd for n in scen]), device=dev, requires_grad=True)
+    blayer = api.OPFBatchLayer(base, 3, tol=1e-8)
+    pg, vm, f = blayer(pd, qd)
+    ((pg * w_pg).sum() + (vm * w_vm).sum() + (f * w_f).sum()).backward()
+    for i in range(3):
+        layer = api.OPFLayer(base, tol=1e-8)
+        pdi = pd.detach()[i].clone().requires_grad_(True)
+        qdi = qd.detach()[i].clone().requires_grad_(True)
+        pgi, vmi, fi = layer(pdi, qdi)
+        ((pgi * w_pg[i]).sum() + (vmi * w_vm[i]).sum() + fi * w_f[i]).backward()
+        assert torch.equal(pgi, pg[i]) and torch.equal(vmi, vm[i]) and torch.equal(fi, f[i])
+        assert torch.equal(pdi.grad, pd.grad[i]) and torch.equal(qdi.grad, qd.grad[i])
+    assert not torch.equal(pd.grad[0], pd.grad[1])
