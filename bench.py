@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("reduced-Hessian condensations/s + IPM iters/s, 1354-bus FP64; "
           "plain vs batched/adjoint")
+FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 (MFMA)
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_condense_syn1354_pmc.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_11875_amd", "csrc", "kernels.hip")
@@ -265,6 +266,27 @@ def batched_scenarios(api, torch, count=16):
             "ipm_iters_per_s_forward": iters / tf, "ipm_iterations_mean": iters / count,
             "step": "forward: all scenarios in lockstep to 1e-8 (rh_ipm_batch_step); "
                     "backward: one adjoint solve per scenario"}
+
+
+def _progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def other_stages(info, phases, steps):
+    """The step's other large stages and what bounds them: the refactorisation
+    is one work-group walking the level sets of L (a dependency chain, not a
+    bandwidth or MFMA limit); the Cholesky of the nu x nu condensed matrix is
+    n^3 / 3 flops on FP64 MFMA in one launch per 32-column block."""
+    nu = info["nu"]
+    ref_us = 1e3 * phases["refactor"][0] / steps
+    chol_us = 1e3 * phases["cholesky"][0] / steps
+    flops = nu ** 3 / 3.0
+    tf = flops / (chol_us * 1e-6) / 1e12
+    return {"refactor": {"us": ref_us, "bound": "latency", "levels": info["levels_lower"],
+                         "us_per_level": ref_us / max(1, info["levels_lower"])},
+            "cholesky": {"us": chol_us, "bound": "mfma", "flops": flops, "achieved": tf,
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
+                         "launches": (nu + 31) // 32 + 1}}
 
 
 def algorithmic_bytes(info, ncols):
@@ -521,12 +543,16 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "bytes_per_column": per_col, "columns_per_launch": ncols},
         "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
+        "other_stages": other_stages(G.info, phases, args.steps),
         "paper_context": PAPER_CONTEXT,
     }
+    _progress("single-instance steps done")
     if not args.no_ipm:
         line["ipm"] = ipm_run(api, net, torch, args.ipm_iters)
+        _progress("ipm done")
     if not args.no_batch:
         line["batched"] = batched_run(api, torch, args.batch_steps, 2)
+        _progress("batched condensation done")
         best, times = api.autotune(net, (x, u, lam, y, sx, su, ss, r), widths=(1, 2, 4),
                                    lds=(1, 0), reps=3)
         line["autotune"] = {"best": {"panel_width": best[0], "lds_panel": best[1]},
@@ -534,13 +560,16 @@ def main():
                                                 for (w, l), v in times.items()}}
     if not args.no_ipm:
         line["redlin"] = redlin_run(api, net, torch, args.ipm_iters)
+        _progress("redlin done")
     if not args.no_ipm and not args.no_batch:
         line["ipm_batched"] = ipm_batched_run(api, torch, 16, args.ipm_iters)
+        _progress("lockstep ipm done")
     if not args.no_diff:
         line["differentiated"] = differentiated_run(api, torch)
         line["differentiated"]["concurrent"] = concurrent_scenarios(api, torch, 16,
                                                                     args.workers)
         line["differentiated"]["batched"] = batched_scenarios(api, torch, 16)
+        _progress("differentiated done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(net, args_np, args.cpu_seconds)
     print(json.dumps(line), flush=True)
