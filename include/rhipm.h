@@ -113,6 +113,8 @@ typedef struct {
   int64_t refactor_kernel;             /* 0 wave-resident, 1 level-staged          */
   int64_t steps_lower;                 /* work-group passes of the L sweep         */
   int64_t sweep_steps;                 /* passes of all four sweeps of one column  */
+  int64_t refactor_split;              /* leading levels factored one launch each,
+                                          a task per work-group (wave-resident path) */
 } rh_info;
 
 typedef struct rh_symbolic rh_symbolic;

@@ -37,7 +37,8 @@ class rh_info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "nx", "nu", "m", "nb", "nl", "ng", "nnz_gx", "nnz_lu", "nnz_gu", "nnz_a", "nnz_k",
         "levels_lower", "levels_upper", "refactor_ops", "max_lu_row", "panel_width",
-        "lds_panel", "max_row_ops", "refactor_kernel", "steps_lower", "sweep_steps")]
+        "lds_panel", "max_row_ops", "refactor_kernel", "steps_lower", "sweep_steps",
+        "refactor_split")]
 
 
 class rh_ipm_options(C.Structure):

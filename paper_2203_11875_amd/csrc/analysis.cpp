@@ -549,6 +549,9 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
     s.rw_levend.clear();
     s.rw_rec.clear();
     s.rw_lane.clear();
+    s.rw_lanelu.clear();
+    s.rw_split = 0;
+    s.rw_split_grid = 0;
     std::vector<int> ustart(nx + 1, 0);
     for (int i = 0; i < nx; ++i) ustart[i + 1] = ustart[i] + (s.lu_ptr[i + 1] - s.lu_diag[i] - 1);
     s.rw_nnz_u = ustart[nx];
@@ -609,7 +612,8 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
             const int off = int(s.rw_lane.size());
             const int npk = (t.nsteps + 1) / 2;
             std::vector<int> blk(size_t(npk) * 64, int(unsigned(zslot) | (unsigned(zslot) << 16)));
-            int rec[kRwRec] = {off, t.nsteps, t.wide, 0};
+            std::vector<int> lublk(size_t(t.nsteps) * 64, -1);
+            int rec[kRwRec] = {off, t.nsteps, t.wide, int(s.rw_lanelu.size())};
             for (size_t g = 0; g < t.rows.size(); ++g) {
               const int i = t.rows[g], rp0 = s.lu_ptr[i], len = s.lu_ptr[i + 1] - rp0;
               const int nl = s.lu_diag[i] - rp0;
@@ -629,16 +633,27 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
                   if (q & 1) wv = (wv & 0xffffu) | (unsigned(u) << 16);
                   else wv = (wv & 0xffff0000u) | unsigned(u);
                   w2 = int(wv);
+                  lublk[size_t(q) * 64 + lane0 + p] = s.rf_op_src[o];
                 }
               }
             }
             s.rw_lane.insert(s.rw_lane.end(), blk.begin(), blk.end());
+            s.rw_lanelu.insert(s.rw_lanelu.end(), lublk.begin(), lublk.end());
             s.rw_rec.insert(s.rw_rec.end(), rec, rec + kRwRec);
             ++cnt;
           }
           s.rw_levend[size_t(w) * nlev + l] = cnt;
         }
         s.rw_wbeg[w + 1] = s.rw_wbeg[w] + cnt;
+      }
+      // leading levels where some wave has many tasks go to the
+      // multi-work-group kernel
+      for (int l = 1; l < nlev; ++l) {
+        int mx = 0;
+        for (int w = 0; w < kRwWaves; ++w) mx = std::max(mx, int(wave_tasks[w][l].size()));
+        if (mx < kRwSplitMin) break;
+        s.rw_split = l;
+        s.rw_split_grid = std::max(s.rw_split_grid, mx);
       }
       // a dummy record (loaded, never run, by waves past their last task)
       // pointing at one block of 64 ints that also stands in for the packed

@@ -26,6 +26,9 @@ constexpr int kRefLdsBudget = 155 * 1024;   // bytes of LDS the refactorisation 
 constexpr int kRwWaves = 8;
 constexpr int kRwRec = 24;
 constexpr int kRwPacked = 32;
+// a level is factored by the multi-work-group kernel while some wave of the
+// single work-group would run at least this many tasks in it
+constexpr int kRwSplitMin = 3;
 // Condensation sweep steps: entries a lane holds in registers, most lanes
 // per row (one DPP row), threads of the work-group, ints of step metadata.
 constexpr int kSweepPF = 8;
@@ -178,6 +181,12 @@ struct Symbolic {
   std::vector<int> rw_rec;                 // kRwRec ints per task (wave-major order)
   std::vector<int> rw_lane;                // per-lane task data (see analysis.cpp)
   std::vector<int> rw_ustart;              // nx: first LDS slot of each row's U entries
+  // levels 1 .. rw_split run one task per work-group, one launch per level
+  // (levels with many tasks per wave); per step and lane of a task, the LU
+  // position of the U entry it subtracts (-1: none), at record field 3
+  int rw_split = 0;
+  int rw_split_grid = 0;                   // largest task count of one wave in those levels
+  std::vector<int> rw_lanelu;
   std::vector<double> k_cdiag;             // constant diagonal (2 c2 base^2 on Pg)
   std::vector<int> sig_map;                // w -> index into [Sigma_u ; Sigma_x(natural)]
   // evaluation gather: dst = [luval | gu | a | g(natural) | h]

@@ -66,6 +66,8 @@ struct DevNet {
   // wave-resident refactorisation (rw_ok): task records, per-lane data
   int rw_ok, rw_nnz_u, rw_nlev, rw_ntask, rw_lane_pad;
   const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane, *rw_ustart;
+  int rw_split, rw_split_grid;      // levels 1..rw_split: one launch per level, a task per WG
+  const int* rw_lanelu;             // per task step and lane: LU position of the U entry, or -1
   const int* rf_lmeta;    // 6 ints per refactorisation level
   int rf_lds_doubles;
   const double* k_cdiag;

@@ -465,10 +465,91 @@ __device__ __forceinline__ void rw_run(const DevNet& d, const RwSet& X, double* 
   }
 }
 
+// rw_run with U from the LU values in global memory (the rows of earlier
+// levels, finished by earlier launches) and the pivot reciprocals in
+// d.rinv: the same operations in the same order, so the results equal the
+// wave-resident kernel's bit for bit.
+__device__ __forceinline__ void rw_run_global(const DevNet& d, const RwSet& X, int lu0, int lane) {
+  const double* lu = d.dst + d.d_lu;
+  const int* pos = d.rw_lanelu + lu0 + lane;
+  const int nsteps = __builtin_amdgcn_readfirstlane(X.nsteps);
+  const int wide = __builtin_amdgcn_readfirstlane(X.wide);
+  double acc = X.init;
+  const double r = X.pos >= 0 ? d.rinv[X.rcol] : 0.0;
+  double amax = fabs(acc);
+  if (wide) {
+    for (int c = 0; c < nsteps; c += 8) {
+      double u[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int p = c + s < nsteps ? pos[(c + s) * 64] : -1;
+        u[s] = ld_or0(lu, p < 0 ? 0 : p, p >= 0);
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int q = c + s;
+        if (q >= nsteps) break;
+        const double l = readlane_d(acc * r, q);
+        if (X.pos == q) acc = l;
+        acc = fma(-l, u[s], acc);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  } else {
+    double u[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int p = s < nsteps ? pos[s * 64] : -1;
+      u[s] = ld_or0(lu, p < 0 ? 0 : p, p >= 0);
+    }
+    rw_steps16<0>(acc, r, X, nsteps, u);
+    for (int off = 8; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  }
+  if (X.ipos >= 0) d.dst[d.d_lu + X.ipos] = acc;
+  if (X.drow >= 0) {
+    d.rinv[X.drow] = 1.0 / acc;
+    if (!(fabs(acc) > 1e-14 * amax)) {
+      d.status[2] = 1;
+      d.status[3] = X.drow;
+    }
+  }
+}
+
+// Level lev (1 <= lev <= rw_split) of the refactorisation: one task per
+// single-wave work-group, task blockIdx.x of wave blockIdx.y's list. Launch
+// lev = 0 writes the pivot reciprocals of the rows of level 0 (no
+// elimination), which level 1 reads.
+__device__ __forceinline__ void k_refactor_level_body(const DevNet& d, int lev) {
+  const int lane = threadIdx.x;
+  if (lev == 0) {
+    const double* lu = d.dst + d.d_lu;
+    const int nb = gridDim.x * gridDim.y;
+    for (int q = (blockIdx.y * gridDim.x + blockIdx.x) * 64 + lane; q < d.rf_lev_ptr[1];
+         q += nb * 64) {
+      const int i = d.rf_rows[q];
+      d.rinv[i] = 1.0 / lu[d.lu_diag[i]];
+    }
+    return;
+  }
+  const int w = blockIdx.y;
+  const int* lend = d.rw_levend + (size_t)w * d.rw_nlev;
+  const int k = lend[lev - 1] + blockIdx.x;
+  if (k >= lend[lev]) return;
+  const int cnt = d.rw_wbeg[w + 1] - d.rw_wbeg[w];
+  RwRec R;
+  RwSet X;
+  rw_rec_load(d, w, k, cnt, R);
+  rw_set_load(d, R, X, lane);
+  rw_run_global(d, X, __builtin_amdgcn_readfirstlane(R.v[3]), lane);
+}
+__global__ void __launch_bounds__(64) k_refactor_level(DevNet d, int lev) {
+  k_refactor_level_body(d, lev);
+}
+
 // Work-group 0 factors. Work-groups 8 h (h >= 1), dispatched to the same XCD
 // as work-group 0, read the task tables and the values into that XCD's L2
 // ahead of it and exit; the others exit at once.
-__device__ __forceinline__ void k_refactor_wave_body(const DevNet& d) {
+__device__ __forceinline__ void k_refactor_wave_body(const DevNet& d, int split) {
   if (blockIdx.x != 0) {
     if (blockIdx.x % 8 != 0) return;
     const int h = blockIdx.x / 8 - 1, nh = gridDim.x / 8 - 1;
@@ -495,16 +576,21 @@ __device__ __forceinline__ void k_refactor_wave_body(const DevNet& d) {
   long long* tr = d.trace && threadIdx.x == 0 ? d.trace + 127 : nullptr;
   if (tr) tr[0] = wall_clock64();
   const int cnt = d.rw_wbeg[wave + 1] - d.rw_wbeg[wave];
+  // levels 1 .. split were factored by k_refactor_level (their rows are
+  // final in global memory and their reciprocals in d.rinv)
+  const int k0 = d.rw_levend[wave * d.rw_nlev + split];
   RwRec r0, r1;
   RwSet A, B;
-  rw_rec_load(d, wave, 0, cnt, r0);
-  rw_rec_load(d, wave, 1, cnt, r1);
+  rw_rec_load(d, wave, k0, cnt, r0);
+  rw_rec_load(d, wave, k0 + 1, cnt, r1);
   rw_set_load(d, r0, A, lane);
   if (threadIdx.x == 0) ulds[d.rw_nnz_u] = 0.0;
   for (int t = threadIdx.x; t < kRwWaves * d.rw_nlev; t += kRwWaves * 64) levend[t] = d.rw_levend[t];
-  // level 0: rows without lower entries keep their values
+  // level 0 (rows without lower entries keep their values) and the levels
+  // factored before: U rows and pivot reciprocals into LDS
   const double* lu = d.dst + d.d_lu;
-  for (int q = threadIdx.x; q < d.rf_lev_ptr[1]; q += kRwWaves * 64) {
+  const int nlev0 = d.rf_lev_ptr[1];
+  for (int q = threadIdx.x; q < d.rf_lev_ptr[split + 1]; q += kRwWaves * 64) {
     const int i = d.rf_rows[q], rp0 = d.lu_ptr[i], rd = d.lu_diag[i], r1e = d.lu_ptr[i + 1];
     const int u0 = d.rw_ustart[i];
     double amax = 0.0;
@@ -514,8 +600,8 @@ __device__ __forceinline__ void k_refactor_wave_body(const DevNet& d) {
       if (p > rd) ulds[u0 + (p - rd - 1)] = v;
     }
     const double piv = lu[rd];
-    rinv[i] = 1.0 / piv;
-    if (!(fabs(piv) > 1e-14 * amax)) {
+    rinv[i] = q < nlev0 ? 1.0 / piv : d.rinv[i];
+    if (q < nlev0 && !(fabs(piv) > 1e-14 * amax)) {
       d.status[2] = 1;
       d.status[3] = i;
     }
@@ -523,11 +609,11 @@ __device__ __forceinline__ void k_refactor_wave_body(const DevNet& d) {
   lds_barrier();
   const int* lend = levend + wave * d.rw_nlev;
   if (tr) tr[1] = wall_clock64();
-  int k = 0;
-  for (int lev = 1; lev < d.rw_nlev; ++lev) {
+  int k = k0;
+  for (int lev = split + 1; lev < d.rw_nlev; ++lev) {
     const int end = lend[lev];
     while (k < end) {
-      if ((k & 1) == 0) {
+      if (((k - k0) & 1) == 0) {
         rw_set_load(d, r1, B, lane);
         rw_rec_load(d, wave, k + 2, cnt, r0);
         rw_run(d, A, ulds, rinv, lane);
@@ -542,8 +628,8 @@ __device__ __forceinline__ void k_refactor_wave_body(const DevNet& d) {
     if (tr && lev < 128) tr[1 + lev] = wall_clock64();
   }
 }
-__global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d) {
-  k_refactor_wave_body(d);
+__global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d, int split) {
+  k_refactor_wave_body(d, split);
 }
 
 // The condensation runs one wave per work-group (one thread per lane of a
@@ -1576,7 +1662,7 @@ __global__ void k_clear_status_b(const DevNet* __restrict__ nets, int first, int
 }
 __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave_b(const DevNet* __restrict__ nets) {
   const DevNet& d = nets[blockIdx.z];
-  if (d.rw_ok) k_refactor_wave_body(d);
+  if (d.rw_ok) k_refactor_wave_body(d, 0);
 }
 __global__ void __launch_bounds__(kRefThreads) k_refactor_b(const DevNet* __restrict__ nets) {
   const DevNet& d = nets[blockIdx.z];
@@ -1748,10 +1834,14 @@ hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double*
 
 hipError_t launch_refactor(const DevNet& d, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, d.status + 2, 2, 0);
-  if (d.rw_ok)
+  if (d.rw_ok) {
+    for (int lev = d.rw_split > 0 ? 0 : 1; lev <= d.rw_split; ++lev)
+      hipLaunchKernelGGL(k_refactor_level, dim3(d.rw_split_grid, kRwWaves), dim3(64), 0, st, d,
+                         lev);
     hipLaunchKernelGGL(k_refactor_wave, dim3(32), dim3(kRwWaves * 64),
                        (size_t)(d.rw_nnz_u + 1 + d.nx) * sizeof(double) +
-                           (size_t)kRwWaves * d.rw_nlev * sizeof(int), st, d);
+                           (size_t)kRwWaves * d.rw_nlev * sizeof(int), st, d, d.rw_split);
+  }
   else
     hipLaunchKernelGGL(k_refactor, dim3(1), dim3(kRefThreads),
                        (size_t)d.rf_lds_doubles * sizeof(double), st, d);

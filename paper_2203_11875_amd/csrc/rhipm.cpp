@@ -201,6 +201,7 @@ void fill_info(const rh::Symbolic& s, rh_info* info) {
   info->max_lu_row = s.max_row;
   info->max_row_ops = s.max_row_ops;
   info->refactor_kernel = s.rw_ok ? 0 : 1;
+  info->refactor_split = s.rw_ok ? s.rw_split : 0;
 }
 
 void copy_maps(const rh::Symbolic& s, int32_t* x_kind, int32_t* x_bus, int32_t* u_kind,
@@ -335,9 +336,11 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   d.rw_ok = s.rw_ok ? 1 : 0;
   d.rw_nnz_u = s.rw_nnz_u;
   d.rw_nlev = s.sl.nlev;
-  d.rw_wbeg = d.rw_levend = d.rw_rec = d.rw_lane = d.rw_ustart = nullptr;
+  d.rw_wbeg = d.rw_levend = d.rw_rec = d.rw_lane = d.rw_ustart = d.rw_lanelu = nullptr;
   d.rw_ntask = 0;
   d.rw_lane_pad = 0;
+  d.rw_split = s.rw_ok ? s.rw_split : 0;
+  d.rw_split_grid = s.rw_split_grid;
   if (s.rw_ok) {
     d.rw_ntask = int(s.rw_rec.size()) / rh::kRwRec - 1;
     d.rw_lane_pad = int(s.rw_lane.size()) - 64;
@@ -346,6 +349,7 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
     RH_TRY(upload(n, s.rw_rec, &d.rw_rec));
     RH_TRY(upload(n, s.rw_lane, &d.rw_lane));
     RH_TRY(upload(n, s.rw_ustart, &d.rw_ustart));
+    RH_TRY(upload(n, s.rw_lanelu, &d.rw_lanelu));
   }
   RH_TRY(upload(n, s.rf_lmeta, &d.rf_lmeta));
   d.rf_lds_doubles = s.rf_lds_doubles;
