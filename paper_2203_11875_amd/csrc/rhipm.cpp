@@ -38,6 +38,10 @@ struct rh_net {
   int width = 2;
   bool lds = true;
   double* pf_scal = nullptr;  // device scalar of the power-flow residual checks
+  // second stream: K assembly and rt run beside the refactorisation (which
+  // occupies one work-group); events fork and join it
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool condensed = false;
   bool rhs_cols = false;     // the last condensation stored the right-hand-side column
   double* sig_s = nullptr;   // copy of Sigma_s from the last condensation
@@ -513,6 +517,11 @@ rh_status rh_init_network(const rh_network_desc* desc, const rh_options* opts, v
   n->stream = static_cast<hipStream_t>(hip_stream);
   rh_status st = rh::analyze(*desc, opts, n->s);
   if (st == RH_OK) st = build_device(n, *desc, opts);
+  if (st == RH_OK &&
+      (hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&n->ev_fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming) != hipSuccess))
+    st = RH_ERR_HIP;
   if (st != RH_OK) {
     rh_destroy_network(n);
     return st;
@@ -525,8 +534,12 @@ void rh_destroy_network(rh_net* n) {
   if (!n) return;
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   else (void)hipDeviceSynchronize();
+  if (n->side) (void)hipStreamSynchronize(n->side);
   for (auto& t : n->timers)
     for (auto& e : t.ev) (void)hipEventDestroy(e);
+  if (n->ev_fork) (void)hipEventDestroy(n->ev_fork);
+  if (n->ev_join) (void)hipEventDestroy(n->ev_join);
+  if (n->side) (void)hipStreamDestroy(n->side);
   for (void* p : n->allocs) (void)hipFree(p);
   delete n;
 }
@@ -834,15 +847,18 @@ rh_status condense_evaluated(rh_net* n, const double* sig_x, const double* sig_u
   hipStream_t st = n->stream;
   n->condensed = false;
   RH_HIP(hipMemcpyAsync(n->sig_s, sig_s, sizeof(double) * d.m, hipMemcpyDeviceToDevice, st));
-  {
-    PhaseScope ps(n, RH_PHASE_EVAL);
-    RH_HIP(rh::launch_assemble_k(d, sig_x, sig_u, sig_s, st));
-    RH_HIP(rh::launch_rtilde(d, r, sig_s, st));   // r == NULL: rt = 0
-  }
+  // K assembly and rt on the side stream, beside the refactorisation; the
+  // condensation waits for both
+  RH_HIP(hipEventRecord(n->ev_fork, st));
+  RH_HIP(hipStreamWaitEvent(n->side, n->ev_fork, 0));
+  RH_HIP(rh::launch_assemble_k(d, sig_x, sig_u, sig_s, n->side));
+  RH_HIP(rh::launch_rtilde(d, r, sig_s, n->side));   // r == NULL: rt = 0
+  RH_HIP(hipEventRecord(n->ev_join, n->side));
   {
     PhaseScope ps(n, RH_PHASE_REFACTOR);
     RH_HIP(rh::launch_refactor(d, st));
   }
+  RH_HIP(hipStreamWaitEvent(st, n->ev_join, 0));
   const int ncols = d.nu + (r ? 1 : 0);
   {
     PhaseScope ps(n, RH_PHASE_CONDENSE);
