@@ -511,6 +511,19 @@ def main():
     el = time.perf_counter() - t0
     phases = G.profile_read()
     G.profile_enable(False)
+    # per-step spread: the same step timed one at a time with events on the
+    # library's stream (outside the timed region above)
+    import numpy as np
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(G.stream)
+        step(delta)
+        b.record(G.stream)
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    spread = {"p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
+              "p90": float(np.percentile(per, 90))}
 
     ms_step = 1e3 * el / args.steps
     cond_ms, cond_calls = phases["condense"]
@@ -543,6 +556,7 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "bytes_per_column": per_col, "columns_per_launch": ncols},
         "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
+        "step_ms_spread": spread,
         "other_stages": other_stages(G.info, phases, args.steps),
         "paper_context": PAPER_CONTEXT,
     }
