@@ -1389,6 +1389,29 @@ rh_status check_levels(const Symbolic& s) {
       }
     }
   }
+  // wave-resident refactorisation: every task's global U positions (read by
+  // the per-level launches) name the same U entries as its packed LDS slots,
+  // and the split levels are a prefix of the L levels
+  if (s.rw_ok) {
+    if (s.rw_split < 0 || s.rw_split >= s.sl.nlev) return RH_ERR_STATE;
+    std::vector<int> slot_lu(size_t(s.rw_nnz_u) + 1, -1);
+    for (int i = 0; i < s.nx; ++i)
+      for (int p = s.lu_diag[i] + 1; p < s.lu_ptr[i + 1]; ++p)
+        slot_lu[size_t(s.rw_ustart[i]) + (p - s.lu_diag[i] - 1)] = p;
+    const int ntask = int(s.rw_rec.size()) / kRwRec - 1;
+    for (int k = 0; k < ntask; ++k) {
+      const int* rec = &s.rw_rec[size_t(k) * kRwRec];
+      const int off = rec[0], nsteps = rec[1], lu0 = rec[3];
+      if (lu0 < 0 || size_t(lu0) + size_t(nsteps) * 64 > s.rw_lanelu.size()) return RH_ERR_STATE;
+      for (int q = 0; q < nsteps; ++q)
+        for (int lane = 0; lane < 64; ++lane) {
+          const unsigned pk = unsigned(s.rw_lane[size_t(off) + size_t(q / 2) * 64 + lane]);
+          const int ui = int((pk >> (16 * (q & 1))) & 0xffffu);
+          const int want = ui >= s.rw_nnz_u ? -1 : slot_lu[ui];
+          if (s.rw_lanelu[size_t(lu0) + size_t(q) * 64 + lane] != want) return RH_ERR_STATE;
+        }
+    }
+  }
   return RH_OK;
 }
 

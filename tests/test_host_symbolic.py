@@ -52,6 +52,16 @@ def test_levels_valid(net):
     assert S.info["levels_lower"] >= 1 and S.info["nnz_lu"] >= S.info["nnz_gx"]
 
 
+def test_refactor_split_levels_1354():
+    """The leading levels with many rows of the 1354-bus factorisation run as
+    per-level launches; their tables (global U positions of every task step)
+    agree with the wave-resident ones (checked by check_levels)."""
+    S = _lib().Symbolic(synthnet.case1354(0))
+    assert S.info["refactor_kernel"] == 0
+    assert 1 <= S.info["refactor_split"] < S.info["levels_lower"]
+    assert S.check_levels() == 0
+
+
 @pytest.mark.parametrize("width", [1, 3])
 @pytest.mark.parametrize("net", NETS[:4], ids=lambda n: n.name)
 def test_condensation_records_emulated_match_dense(net, width):
