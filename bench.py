@@ -323,9 +323,10 @@ def ipm_run(api, net, torch, max_iter):
     ipm = api.Ipm(G, tol=1e-6, max_iter=max_iter)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, code, info = 0, 0, {}
+    iters, code, info, trace = 0, 0, {}, []
     while iters <= max_iter:
         code, info = ipm.step()
+        trace.append(float(f"{info['err']:.3g}"))
         if code != 0 or info["converged"]:
             break
         iters += 1
@@ -336,7 +337,8 @@ def ipm_run(api, net, torch, max_iter):
     return {"iters_per_s": iters / el if iters else 0.0, "iterations": iters,
             "ms_per_iter": 1e3 * el / max(1, iters), "converged": bool(info.get("converged")),
             "status": int(code), "objective": info.get("obj"), "kkt_error": info.get("err"),
-            "tol": 1e-6, "start": "flat (theta 0, Vm 1, Pg mid-range)"}
+            "tol": 1e-6, "start": "flat (theta 0, Vm 1, Pg mid-range)",
+            "kkt_error_per_iteration": trace}
 
 
 def ipm_batched_run(api, torch, count=16, max_iter=150):
@@ -387,9 +389,10 @@ def redlin_run(api, net, torch, max_iter):
     G.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, code, info, pf = 0, 0, {}, 0
+    iters, code, info, pf, trace = 0, 0, {}, 0, []
     while iters <= max_iter:
         code, info = rl.step()
+        trace.append(float(f"{info['err']:.3g}"))
         if code != 0 or info["converged"]:
             break
         iters += 1
@@ -403,7 +406,9 @@ def redlin_run(api, net, torch, max_iter):
             "ms_per_iter": 1e3 * el / max(1, iters), "converged": bool(info.get("converged")),
             "status": int(code), "objective": info.get("obj"), "pf_newton_steps": pf,
             "projection_ms_per_iter": phases["project"][0] / max(1, iters),
-            "tol": 1e-6, "start": "flat (theta 0, Vm 1, Pg mid-range), projected"}
+            "phases_ms_per_iter": {k: v[0] / max(1, iters) for k, v in phases.items()},
+            "tol": 1e-6, "start": "flat (theta 0, Vm 1, Pg mid-range), projected",
+            "kkt_error_per_iteration": trace}
 
 
 def cpu_baseline(net, args_np, seconds):
