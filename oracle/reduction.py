@@ -186,3 +186,20 @@ def condensed_columns_sparse(blocks, cols, splu=None):
         q = K @ np.concatenate([ej, sj])
         out[:, k] = q[:nu] - Gu.T @ splu.solve(q[nu:], trans="T")
     return out, splu
+
+
+def condensed_rhs_sparse(blocks, r, splu=None):
+    """condensed_rhs with a sparse LU of G_x (large networks): d = -G_x^{-1} r4
+    and [I; S]^T v = v_u - G_u^T G_x^{-T} v_x."""
+    import scipy.sparse.linalg as spla
+    nu, nx, m = blocks["nu"], blocks["nx"], blocks["m"]
+    G = blocks["G"].tocsc()
+    Gx, Gu = G[:, nu:].tocsc(), G[:, :nu].tocsc()
+    if splu is None:
+        splu = spla.splu(Gx, permc_spec="COLAMD", diag_pivot_thresh=1.0)
+    r1, r2, r3, r4, r5 = unpack(r, nu, nx, m)
+    A, K, sig_s = blocks["A"], blocks["K"], blocks["sig_s"]
+    rt = np.concatenate([r1, r2]) + A.T @ (sig_s * r5 - r3)
+    d = -splu.solve(r4)
+    v = rt + K @ np.concatenate([np.zeros(nu), d])
+    return -(v[:nu] - Gu.T @ splu.solve(v[nu:], trans="T")), splu

@@ -189,3 +189,29 @@ def test_solve_after_condensation_without_rhs(name, width):
     pu = np.linalg.solve(Kc + delta * np.eye(M.nu), b)
     want = np.concatenate(R.recover(B, r, pu, S, lu))
     assert np.abs(_np(p) - want).max() <= 1e-8 * np.abs(want).max()
+
+
+def test_condense_9241_sampled_columns():
+    """The 9241-bus condensation (nx 17036, nu 2889) in the launch shape the
+    library picks, against the oracle on sampled columns and the full
+    right-hand side (sparse LU of G_x on the host)."""
+    net = synthnet.case9241(0)
+    M = Model(net)
+    print("condense syn9241 (sampled columns)", flush=True)
+    G = _net_api().Net(net)
+    x, u, lam, y, sx, su, ss = random_point(M, 0)
+    r = residual_vector(M, 1)
+    K, rhs = G.condense_reduced_hessian(*map(_t, (x, u, lam, y, sx, su, ss)), r=_t(r))
+    torch.cuda.synchronize()
+    B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
+    cols = [0, 1, 700, 1444, 1445, 2000, M.nu - 1]
+    want, splu = R.condensed_columns_sparse(B, cols)
+    Kg = _np(K).T
+    for k, j in enumerate(cols):
+        # K is symmetrised: compare with the mean of column and row j
+        wj = want[:, k]
+        err = np.linalg.norm(0.5 * (Kg[:, j] + Kg[j, :]) - wj) / np.linalg.norm(wj)
+        assert err <= 1e-8, (j, err)
+        assert np.array_equal(Kg[:, j], Kg[j, :])
+    b, _ = R.condensed_rhs_sparse(B, r, splu)
+    assert _rel(_np(rhs), b) <= 1e-8

@@ -156,3 +156,20 @@ def test_sparse_columns_match_dense():
     cols = [0, 5, 53, 54, 106]
     Ks, _ = R.condensed_columns_sparse(B, cols)
     assert np.abs(Ks - Kc[:, cols]).max() <= 1e-9 * np.abs(Kc).max()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sparse_condensation_equals_dense(seed):
+    """The sparse-LU forms (used at 9241 buses) equal the dense definitions."""
+    net = synthnet.case118(0)
+    M = Model(net)
+    x, u, lam, y, sx, su, ss = random_point(M, seed)
+    B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
+    Kc = R.condensed_matrix(B)
+    cols = [0, 5, M.nu - 1]
+    got, splu = R.condensed_columns_sparse(B, cols)
+    np.testing.assert_allclose(got, Kc[:, cols], rtol=0, atol=1e-9 * np.abs(Kc).max())
+    r = residual_vector(M, seed)
+    b, _, _ = R.condensed_rhs(B, r)
+    bs, _ = R.condensed_rhs_sparse(B, r, splu)
+    np.testing.assert_allclose(bs, b, rtol=0, atol=1e-9 * np.abs(b).max())
