@@ -562,6 +562,9 @@ def main():
                      "bytes_per_column": per_col, "columns_per_launch": ncols},
         "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
         "step_ms_spread": spread,
+        "condensation_only_per_s": 1e3 / sum(phases[k][0] / args.steps
+                                              for k in ("eval", "refactor", "condense",
+                                                        "symmetrize")),
         "other_stages": other_stages(G.info, phases, args.steps),
         "paper_context": PAPER_CONTEXT,
     }

@@ -215,3 +215,31 @@ def test_condense_9241_sampled_columns():
         assert np.array_equal(Kg[:, j], Kg[j, :])
     b, _ = R.condensed_rhs_sparse(B, r, splu)
     assert _rel(_np(rhs), b) <= 1e-8
+
+
+def test_solve_9241_matches_oracle():
+    """The condensed solve at 9241 buses: blocked Cholesky of the 2889 x 2889
+    K_cond + delta I (the wide backward-substitution variant) and the
+    control step, against the oracle's K_cond from sparse-LU columns, factored
+    and solved densely on the host."""
+    net = synthnet.case9241(0)
+    M = Model(net)
+    print("solve syn9241", flush=True)
+    G = _net_api().Net(net)
+    x, u, lam, y, sx, su, ss = random_point(M, 3, lam_scale=1.0, sig_range=(1.0, 1e3))
+    r = residual_vector(M, 4)
+    K, rhs = G.condense_reduced_hessian(*map(_t, (x, u, lam, y, sx, su, ss)), r=_t(r))
+    B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
+    Kc, splu = R.condensed_columns_sparse(B, range(M.nu))
+    Kc = R.symmetrize(Kc)
+    delta = max(0.0, -np.linalg.eigvalsh(Kc).min()) * 1.5 + 1.0
+    Kd = Kc + delta * np.eye(M.nu)
+    b, _ = R.condensed_rhs_sparse(B, r, splu)
+    p, code = G.solve_condensed_kkt(K, delta, rhs, _t(r))
+    torch.cuda.synchronize()
+    assert code == 0
+    pu = np.linalg.solve(Kd, b)
+    got = _np(p)[:M.nu]
+    assert np.abs(got - pu).max() <= 1e-8 * np.abs(pu).max()
+    Lg = np.tril(_np(K).T)
+    assert _rel(Lg, np.linalg.cholesky(Kd)) <= 1e-8
