@@ -112,19 +112,34 @@ def batched_run(api, torch, steps, warmup):
         el = time.perf_counter() - t0
         # the same step captured in a HIP graph and replayed
         B.capture(pts, delta)
-        B.replay()
+        for _ in range(2):
+            B.replay()
         stream.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             B.replay()
         stream.synchronize()
         el_graph = time.perf_counter() - t0
+        # each replay on its own, timed with events on the batch stream
+        import numpy as np
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(max(steps, 10))]
+        for a, b in evs:
+            a.record(stream)
+            B.replay()
+            b.record(stream)
+            stream.synchronize()
+        per = np.array([a.elapsed_time(b) for a, b in evs])
     B.close()
     n = len(nets)
     return {"instances": n, "condensations_per_s": n * steps / el,
             "ms_per_batch_step": 1e3 * el / steps,
             "graph_condensations_per_s": n * steps / el_graph,
             "graph_ms_per_batch_step": 1e3 * el_graph / steps, "steps": steps,
+            "graph_replay_ms": {"p10": float(np.percentile(per, 10)),
+                                "p50": float(np.median(per)),
+                                "p90": float(np.percentile(per, 90))},
+            "graph_condensations_per_s_median": n / (float(np.median(per)) * 1e-3),
             "composition": "64 x syn1354 load scenarios (nu 519), 32 x syn118 (nu 107), "
                            "16 x syn300 (nu 137)",
             "step": "batched eval + refactor + condense + symmetrize + Cholesky + solve + "
@@ -458,7 +473,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--workers", type=int, default=8)
-    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--ipm-iters", type=int, default=150)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 512 MiB first (a plain copy kernel of known "
