@@ -948,6 +948,67 @@ void build_condense_records(const Symbolic& s, int W, CondenseRecords& R) {
       }
     }
   }
+  // Per column tile of the identity columns, the L-sweep steps that can
+  // change its panel. Column j starts nonzero only in the rows of G_u's
+  // column j, and a row turns nonzero only through a lower entry from a
+  // nonzero row (the reach of those rows in the graph of L). A step whose
+  // rows all lie outside the tile's reach subtracts zeros from zeros, so it
+  // is left out and the results stay the same bit for bit. The tile holding
+  // the right-hand-side column (a dense r4) keeps every step.
+  {
+    const int nx = s.nx;
+    std::vector<std::vector<int>> lchild(nx);
+    for (int i = 0; i < nx; ++i)
+      for (int p = s.lu_ptr[i]; p < s.lu_diag[i]; ++p) lchild[s.lu_col[p]].push_back(i);
+    const Sweep& sl = s.sl;
+    std::vector<std::vector<int>> step_rows(sl.ks_nstep);
+    for (int st = 0; st < sl.ks_nstep; ++st) {
+      const int* m = &sl.ks_meta[size_t(kSweepMeta) * st];
+      for (int t = 0; t < m[1]; ++t) step_rows[st].push_back(sl.lb_row[m[0] + t]);
+    }
+    const int ntile = int((nu + 1 + W - 1) / W);
+    R.lsk_ptr.assign(ntile + 1, 0);
+    R.lsk_meta.clear();
+    std::vector<char> in(nx);
+    std::vector<int> stack;
+    for (int tile = 0; tile < ntile; ++tile) {
+      const long j0 = long(tile) * W, j1 = std::min<long>(j0 + W, nu + 1);
+      const bool full = j1 > nu;
+      std::fill(in.begin(), in.end(), 0);
+      if (!full) {
+        for (long j = j0; j < j1; ++j)
+          for (int e = s.gucsc_ptr[j]; e < s.gucsc_ptr[j + 1]; ++e) {
+            const int r = s.gucsc_row[e];
+            if (!in[r]) {
+              in[r] = 1;
+              stack.push_back(r);
+            }
+          }
+        while (!stack.empty()) {
+          const int k = stack.back();
+          stack.pop_back();
+          for (int i : lchild[k])
+            if (!in[i]) {
+              in[i] = 1;
+              stack.push_back(i);
+            }
+        }
+      }
+      for (int st = 0; st < sl.ks_nstep; ++st) {
+        bool need = full;
+        for (int r : step_rows[st])
+          if (in[r]) {
+            need = true;
+            break;
+          }
+        if (need)
+          R.lsk_meta.insert(R.lsk_meta.end(), R.meta[0].begin() + 4 * size_t(st),
+                            R.meta[0].begin() + 4 * size_t(st) + 4);
+      }
+      R.lsk_meta.insert(R.lsk_meta.end(), R.meta[0].end() - 4, R.meta[0].end());   // idle step
+      R.lsk_ptr[tile + 1] = int(R.lsk_meta.size() / 4);
+    }
+  }
   // record streams
   auto stream = [&](const Symbolic::LaneStream& ls, bool gt, std::vector<double>& str,
                     std::vector<int>& dst, std::vector<int>* xdst) {

@@ -216,6 +216,10 @@ struct CondenseRecords {
   std::vector<int> gdst;             // nnz_gu: gstr index of each G_u entry (CSR)
   std::vector<int> hpos;             // nw: H position of w row v
   std::vector<int> grow;             // nu: control at G-stream position p
+  // per column tile (W identity columns, the last tile with the right-hand
+  // side): the L-sweep step entries (as meta[0]) that can change its panel,
+  // then the idle step; lsk_ptr in entries of 4 ints
+  std::vector<int> lsk_ptr, lsk_meta;
 };
 void build_condense_records(const Symbolic& sym, int W, CondenseRecords& out);
 

@@ -63,6 +63,9 @@ struct DevNet {
   double *kstr, *gstr;
   int kst_nbat, kb_n, gst_nbat, gt_nb;
   const int *kb_end, *gt_end, *kdst, *krt_dst, *gdst, *hpos, *grow;
+  // per column tile: the L-sweep steps that can change its panel (entries of
+  // 4 ints as DevSweep::meta, then the idle step); null = every step
+  const int *lsk_ptr, *lsk_meta;
   // wave-resident refactorisation (rw_ok): task records, per-lane data
   int rw_ok, rw_nnz_u, rw_nlev, rw_ntask, rw_lane_pad;
   const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane, *rw_ustart;

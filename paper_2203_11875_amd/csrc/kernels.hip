@@ -782,9 +782,7 @@ __device__ __forceinline__ void sweep_step(const StepFetch& f, char* pb) {
 constexpr int kDepth = 4;
 
 template <int W, bool LDS>
-__device__ __forceinline__ void sweep(const DevSweep& s, const double* lblk, const int4* meta,
-                                      char* pb) {
-  const int n = s.nstep;
+__device__ __forceinline__ void sweep(int n, const double* lblk, const int4* meta, char* pb) {
   if (n == 0) return;
   StepFetch f[kDepth];
   const int4 idle = meta[n];
@@ -947,7 +945,17 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   int4* m_slt = m_sut + d.sut.nstep + 1;
   int* kb_end = reinterpret_cast<int*>(m_slt + d.slt.nstep + 1);
   int* gt_end = kb_end + d.kb_n;
-  stage_meta(d.sl, m_sl);
+  // the L sweep of an identity-column tile runs only the steps that can
+  // change its panel (the reach of G_u's columns in L)
+  int nsl = d.sl.nstep;
+  if (mode == MODE_COLUMNS && d.lsk_ptr && col0 == 0) {
+    const int a = d.lsk_ptr[blk];
+    nsl = d.lsk_ptr[blk + 1] - a - 1;
+    const int4* src = reinterpret_cast<const int4*>(d.lsk_meta) + a;
+    for (int i = threadIdx.x; i <= nsl; i += kCondThreads) m_sl[i] = src[i];
+  } else {
+    stage_meta(d.sl, m_sl);
+  }
   stage_meta(d.su, m_su);
   stage_meta(d.sut, m_sut);
   stage_meta(d.slt, m_slt);
@@ -983,9 +991,9 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   }
   panel_sync<LDS>();
   tick(d, 1);
-  sweep<W, LDS>(d.sl, d.lblk, m_sl, pb);
+  sweep<W, LDS>(nsl, d.lblk, m_sl, pb);
   tick(d, 2);
-  sweep<W, LDS>(d.su, d.lblk, m_su, pb);
+  sweep<W, LDS>(d.su.nstep, d.lblk, m_su, pb);
   tick(d, 3);
   if (mode == MODE_COLUMNS) {
     // keep Z = S e_j (and d for the right-hand-side column) for the recovery
@@ -1030,9 +1038,9 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   }
   panel_sync<LDS>();
   tick(d, 4);
-  sweep<W, LDS>(d.sut, d.lblk, m_sut, pb);
+  sweep<W, LDS>(d.sut.nstep, d.lblk, m_sut, pb);
   tick(d, 5);
-  sweep<W, LDS>(d.slt, d.lblk, m_slt, pb);
+  sweep<W, LDS>(d.slt.nstep, d.lblk, m_slt, pb);
   tick(d, 6);
   if (mode == MODE_COLUMNS) {
     for (int c = 0; c < W; ++c) {
@@ -1103,8 +1111,8 @@ __global__ void __launch_bounds__(kCondThreads) k_gx_solve(DevNet d, const doubl
   else
     for (int i = tid; i < nx; i += T) P[(nu + i) * W] = b[d.perm[i]];
   panel_sync<LDS>();
-  sweep<W, LDS>(s1, d.lblk, m1, pb);
-  sweep<W, LDS>(s2, d.lblk, m2, pb);
+  sweep<W, LDS>(s1.nstep, d.lblk, m1, pb);
+  sweep<W, LDS>(s2.nstep, d.lblk, m2, pb);
   panel_sync<LDS>();
   if (TRANS)
     indexed_loop(d.hpos + nu, nx, [&](int i, int hp) {

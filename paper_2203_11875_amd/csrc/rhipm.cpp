@@ -181,6 +181,8 @@ rh_status upload_condense_records(rh_net* n, int W) {
   RH_TRY(upload(n, R.gdst, &d.gdst));
   RH_TRY(upload(n, R.hpos, &d.hpos));
   RH_TRY(upload(n, R.grow, &d.grow));
+  RH_TRY(upload(n, R.lsk_ptr, &d.lsk_ptr));
+  RH_TRY(upload(n, R.lsk_meta, &d.lsk_meta));
   return RH_OK;
 }
 
