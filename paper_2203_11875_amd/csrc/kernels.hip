@@ -469,13 +469,16 @@ __device__ __forceinline__ void rw_run(const DevNet& d, const RwSet& X, double* 
 // levels, finished by earlier launches) and the pivot reciprocals in
 // d.rinv: the same operations in the same order, so the results equal the
 // wave-resident kernel's bit for bit.
-__device__ __forceinline__ void rw_run_global(const DevNet& d, const RwSet& X, int lu0, int lane) {
+__device__ __forceinline__ void rw_run_global(const DevNet& d, const RwSet& X, int lu0, int lane,
+                                              bool first) {
   const double* lu = d.dst + d.d_lu;
   const int* pos = d.rw_lanelu + lu0 + lane;
   const int nsteps = __builtin_amdgcn_readfirstlane(X.nsteps);
   const int wide = __builtin_amdgcn_readfirstlane(X.wide);
   double acc = X.init;
-  const double r = X.pos >= 0 ? d.rinv[X.rcol] : 0.0;
+  // the lower entries of a level-1 row are rows of level 0, whose pivots are
+  // their values (the launch writes their reciprocals for later levels)
+  const double r = X.pos < 0 ? 0.0 : first ? 1.0 / lu[d.lu_diag[X.rcol]] : d.rinv[X.rcol];
   double amax = fabs(acc);
   if (wide) {
     for (int c = 0; c < nsteps; c += 8) {
@@ -516,12 +519,12 @@ __device__ __forceinline__ void rw_run_global(const DevNet& d, const RwSet& X, i
 }
 
 // Level lev (1 <= lev <= rw_split) of the refactorisation: one task per
-// single-wave work-group, task blockIdx.x of wave blockIdx.y's list. Launch
-// lev = 0 writes the pivot reciprocals of the rows of level 0 (no
-// elimination), which level 1 reads.
+// single-wave work-group, task blockIdx.x of wave blockIdx.y's list. The
+// launch of level 1 also writes the pivot reciprocals of the rows of level 0
+// (no elimination), which later levels read.
 __device__ __forceinline__ void k_refactor_level_body(const DevNet& d, int lev) {
   const int lane = threadIdx.x;
-  if (lev == 0) {
+  if (lev == 1) {
     const double* lu = d.dst + d.d_lu;
     const int nb = gridDim.x * gridDim.y;
     for (int q = (blockIdx.y * gridDim.x + blockIdx.x) * 64 + lane; q < d.rf_lev_ptr[1];
@@ -529,7 +532,6 @@ __device__ __forceinline__ void k_refactor_level_body(const DevNet& d, int lev) 
       const int i = d.rf_rows[q];
       d.rinv[i] = 1.0 / lu[d.lu_diag[i]];
     }
-    return;
   }
   const int w = blockIdx.y;
   const int* lend = d.rw_levend + (size_t)w * d.rw_nlev;
@@ -540,7 +542,7 @@ __device__ __forceinline__ void k_refactor_level_body(const DevNet& d, int lev) 
   RwSet X;
   rw_rec_load(d, w, k, cnt, R);
   rw_set_load(d, R, X, lane);
-  rw_run_global(d, X, __builtin_amdgcn_readfirstlane(R.v[3]), lane);
+  rw_run_global(d, X, __builtin_amdgcn_readfirstlane(R.v[3]), lane, lev == 1);
 }
 __global__ void __launch_bounds__(64) k_refactor_level(DevNet d, int lev) {
   k_refactor_level_body(d, lev);
@@ -1843,7 +1845,7 @@ hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double*
 hipError_t launch_refactor(const DevNet& d, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, d.status + 2, 2, 0);
   if (d.rw_ok) {
-    for (int lev = d.rw_split > 0 ? 0 : 1; lev <= d.rw_split; ++lev)
+    for (int lev = 1; lev <= d.rw_split; ++lev)
       hipLaunchKernelGGL(k_refactor_level, dim3(d.rw_split_grid, kRwWaves), dim3(64), 0, st, d,
                          lev);
     hipLaunchKernelGGL(k_refactor_wave, dim3(32), dim3(kRwWaves * 64),
