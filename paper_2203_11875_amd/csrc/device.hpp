@@ -127,6 +127,14 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
                                  const BatchShape& sh, hipStream_t st);
 hipError_t launch_batch_solve(const DevNet* nets, const BatchArg* args, const BatchShape& sh,
                               hipStream_t st);
+struct IpmDev;
+// Evaluation of a lockstep batch of interior-point solvers (rh_ipm_batch_step):
+// derivative values at args' (x, u, lam, y) with the Hessian (trial = 0) or
+// without it at the trial points (trial = 1, args hold wt), and the objective
+// of each active instance into its f[trial].
+hipError_t launch_batch_ipm_eval(const DevNet* nets, const BatchArg* args, const IpmDev* ipms,
+                                 const double* sc, const BatchShape& sh, int trial,
+                                 hipStream_t st);
 // out[5 b + i] = status word i of instance b (device array of 5 count ints)
 hipError_t launch_batch_status(const DevNet* nets, int count, int* out, hipStream_t st);
 

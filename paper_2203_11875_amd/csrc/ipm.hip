@@ -32,7 +32,7 @@ __device__ __forceinline__ double push_inside(double v, double lo, double hi, do
   return v;
 }
 
-__global__ void __launch_bounds__(kVec) k_ipm_lag_grad(DevNet d, IpmDev v) {
+__device__ __forceinline__ void ipm_lag_grad_body(const DevNet& d, const IpmDev& v) {
   const int nw = v.nu + v.nx;
   const int vi = blockIdx.x * blockDim.x + threadIdx.x;
   if (vi >= nw) return;
@@ -66,6 +66,9 @@ __global__ void __launch_bounds__(kVec) k_ipm_lag_grad(DevNet d, IpmDev v) {
   v.gf[out] = gfv;
   v.gl[out] = gfv + acc;
 }
+__global__ void __launch_bounds__(kVec) k_ipm_lag_grad(DevNet d, IpmDev v) {
+  ipm_lag_grad_body(d, v);
+}
 
 // Work-group reduction of kinds: 0 max, 1 min, 2 sum.
 template <int N>
@@ -91,8 +94,8 @@ __device__ void block_reduce(double (&val)[N], const int (&kind)[N], double* out
   }
 }
 
-__global__ void __launch_bounds__(kRed) k_ipm_stats(DevNet d, IpmDev v, const double* w,
-                                                    const double* s, int full) {
+__device__ __forceinline__ void ipm_stats_body(const DevNet& d, const IpmDev& v, const double* w,
+                                               const double* s, int full) {
   const int nw = v.nu + v.nx;
   const double* g = d.dst + d.d_g;
   const double* h = d.dst + d.d_h;
@@ -160,8 +163,11 @@ __global__ void __launch_bounds__(kRed) k_ipm_stats(DevNet d, IpmDev v, const do
   const int kind[11] = {0, 0, 0, 0, 0, 1, 2, 2, 2, 2, 0};
   block_reduce<11>(val, kind, v.red);
 }
+__global__ void __launch_bounds__(kRed) k_ipm_stats(DevNet d, IpmDev v, const double* w, const double* s, int full) {
+  ipm_stats_body(d, v, w, s, full);
+}
 
-__global__ void __launch_bounds__(kVec) k_ipm_prep(DevNet d, IpmDev v, double mu) {
+__device__ __forceinline__ void ipm_prep_body(const DevNet& d, const IpmDev& v, double mu) {
   const int nw = v.nu + v.nx;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nw) {
@@ -181,8 +187,11 @@ __global__ void __launch_bounds__(kVec) k_ipm_prep(DevNet d, IpmDev v, double mu
   }
   if (i < v.nx) v.r[nw + v.m + i] = d.dst[d.d_g + i];     // r4 = g
 }
+__global__ void __launch_bounds__(kVec) k_ipm_prep(DevNet d, IpmDev v, double mu) {
+  ipm_prep_body(d, v, mu);
+}
 
-__global__ void __launch_bounds__(kRed) k_ipm_dir(IpmDev v, double mu, double tau) {
+__device__ __forceinline__ void ipm_dir_body(const IpmDev& v, double mu, double tau) {
   const int nw = v.nu + v.nx;
   double apri = 1.0, adual = 1.0, dphi = 0.0;
   for (int i = threadIdx.x; i < nw; i += kRed) {
@@ -230,20 +239,26 @@ __global__ void __launch_bounds__(kRed) k_ipm_dir(IpmDev v, double mu, double ta
   const int kind[3] = {1, 1, 2};
   block_reduce<3>(val, kind, v.red + IR_APRI);
 }
+__global__ void __launch_bounds__(kRed) k_ipm_dir(IpmDev v, double mu, double tau) {
+  ipm_dir_body(v, mu, tau);
+}
 
-__global__ void __launch_bounds__(kVec) k_ipm_trial(IpmDev v, double alpha) {
+__device__ __forceinline__ void ipm_trial_body(const IpmDev& v, double alpha) {
   const int nw = v.nu + v.nx;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nw) v.wt[i] = v.w[i] + alpha * v.p[i];
   if (i < v.m) v.st[i] = v.s[i] + alpha * v.p[nw + i];
+}
+__global__ void __launch_bounds__(kVec) k_ipm_trial(IpmDev v, double alpha) {
+  ipm_trial_body(v, alpha);
 }
 
 __device__ __forceinline__ double clip_z(double z, double d, double mu, double k) {
   return fmin(fmax(z, mu / (k * d)), k * mu / d);
 }
 
-__global__ void __launch_bounds__(kVec) k_ipm_update(IpmDev v, double alpha, double alpha_z,
-                                                    double mu, double ks) {
+__device__ __forceinline__ void ipm_update_body(const IpmDev& v, double alpha, double alpha_z,
+                                                double mu, double ks) {
   const int nw = v.nu + v.nx;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nw) {
@@ -262,6 +277,9 @@ __global__ void __launch_bounds__(kVec) k_ipm_update(IpmDev v, double alpha, dou
     v.y[i] += alpha * v.p[nw + v.m + v.nx + i];
   }
   if (i < v.nx) v.lam[i] += alpha * v.p[nw + v.m + i];
+}
+__global__ void __launch_bounds__(kVec) k_ipm_update(IpmDev v, double alpha, double alpha_z, double mu, double ks) {
+  ipm_update_body(v, alpha, alpha_z, mu, ks);
 }
 
 __global__ void __launch_bounds__(kVec) k_ipm_init_w(IpmDev v, double push, double frac) {
@@ -366,6 +384,45 @@ __global__ void __launch_bounds__(kRed) k_adjoint_grad(DevNet d, IpmDev v, const
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched forms (instance = blockIdx.z) for solvers stepped in lockstep: the
+// same bodies, per-instance scalars in sc (IpmScalar slots), instances whose
+// active slot is 0 skip the launch.
+__device__ __forceinline__ bool ipm_active(const double* sc) {
+  return sc[kIpmSc * blockIdx.z + IS_ACTIVE] != 0.0;
+}
+__global__ void __launch_bounds__(kVec) k_ipm_lag_grad_b(const DevNet* nets, const IpmDev* ipms,
+                                                        const double* sc) {
+  if (!ipm_active(sc)) return;
+  ipm_lag_grad_body(nets[blockIdx.z], ipms[blockIdx.z]);
+}
+__global__ void __launch_bounds__(kRed) k_ipm_stats_b(const DevNet* nets, const IpmDev* ipms,
+                                                     const double* sc, int trial, int full) {
+  if (!ipm_active(sc)) return;
+  const IpmDev& v = ipms[blockIdx.z];
+  ipm_stats_body(nets[blockIdx.z], v, trial ? v.wt : v.w, trial ? v.st : v.s, full);
+}
+__global__ void __launch_bounds__(kVec) k_ipm_prep_b(const DevNet* nets, const IpmDev* ipms,
+                                                    const double* sc) {
+  if (!ipm_active(sc)) return;
+  ipm_prep_body(nets[blockIdx.z], ipms[blockIdx.z], sc[kIpmSc * blockIdx.z + IS_MU]);
+}
+__global__ void __launch_bounds__(kRed) k_ipm_dir_b(const IpmDev* ipms, const double* sc) {
+  if (!ipm_active(sc)) return;
+  const double* q = sc + kIpmSc * blockIdx.z;
+  ipm_dir_body(ipms[blockIdx.z], q[IS_MU], q[IS_TAU]);
+}
+__global__ void __launch_bounds__(kVec) k_ipm_trial_b(const IpmDev* ipms, const double* sc) {
+  if (!ipm_active(sc)) return;
+  ipm_trial_body(ipms[blockIdx.z], sc[kIpmSc * blockIdx.z + IS_ALPHA]);
+}
+__global__ void __launch_bounds__(kVec) k_ipm_update_b(const IpmDev* ipms, const double* sc,
+                                                      double ks) {
+  if (!ipm_active(sc)) return;
+  const double* q = sc + kIpmSc * blockIdx.z;
+  ipm_update_body(ipms[blockIdx.z], q[IS_ALPHA], q[IS_ALPHA_Z], q[IS_MU], ks);
+}
+
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 inline int vec_grid(const IpmDev& v) {
   int n = v.nu + v.nx;
@@ -440,6 +497,34 @@ hipError_t launch_adjoint_rhs(const DevNet& d, const IpmDev& v, double inv_sigma
 hipError_t launch_adjoint_grad(const DevNet& d, const IpmDev& v, const double* xi, double* gpd,
                                double* gqd, hipStream_t st) {
   hipLaunchKernelGGL(k_adjoint_grad, dim3(1), dim3(kRed), 0, st, d, v, xi, gpd, gqd);
+  return hipGetLastError();
+}
+
+hipError_t launch_ipm_batch(IpmBatchOp op, const DevNet* nets, const IpmDev* ipms,
+                            const double* sc, int count, int max_n, int trial, int full,
+                            double ks, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const dim3 vg(cdiv(max_n > 0 ? max_n : 1, kVec), 1, count), rg(1, 1, count);
+  switch (op) {
+    case IB_LAG_GRAD:
+      hipLaunchKernelGGL(k_ipm_lag_grad_b, vg, dim3(kVec), 0, st, nets, ipms, sc);
+      break;
+    case IB_STATS:
+      hipLaunchKernelGGL(k_ipm_stats_b, rg, dim3(kRed), 0, st, nets, ipms, sc, trial, full);
+      break;
+    case IB_PREP:
+      hipLaunchKernelGGL(k_ipm_prep_b, vg, dim3(kVec), 0, st, nets, ipms, sc);
+      break;
+    case IB_DIR:
+      hipLaunchKernelGGL(k_ipm_dir_b, rg, dim3(kRed), 0, st, ipms, sc);
+      break;
+    case IB_TRIAL:
+      hipLaunchKernelGGL(k_ipm_trial_b, vg, dim3(kVec), 0, st, ipms, sc);
+      break;
+    case IB_UPDATE:
+      hipLaunchKernelGGL(k_ipm_update_b, vg, dim3(kVec), 0, st, ipms, sc, ks);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -29,6 +29,11 @@ enum IpmRed : int {
   IR_NSLOT = 16
 };
 
+// Per-instance scalars of the batched launches (kIpmSc doubles each).
+enum IpmScalar : int { IS_MU = 0, IS_TAU = 1, IS_ALPHA = 2, IS_ALPHA_Z = 3, IS_ACTIVE = 4 };
+constexpr int kIpmSc = 8;
+enum IpmBatchOp : int { IB_LAG_GRAD, IB_STATS, IB_PREP, IB_DIR, IB_TRIAL, IB_UPDATE };
+
 // All pointers are device memory owned by the interior-point handle; vectors
 // in the library's natural order, w = [u; x].
 struct IpmDev {
@@ -66,6 +71,15 @@ hipError_t launch_ipm_update(const IpmDev& v, double alpha, double alpha_z, doub
 hipError_t launch_ipm_init_w(const IpmDev& v, double push, double frac, hipStream_t st);
 hipError_t launch_ipm_init_s(const DevNet& d, const IpmDev& v, double push, double frac,
                              hipStream_t st);
+
+// One batched launch of an iteration kernel over count instances (nets,
+// ipms, sc: device arrays; sc holds kIpmSc scalars per instance, instances
+// with IS_ACTIVE = 0 skip). max_n: largest element count (nu + nx or m) of an
+// instance for the element-wise kernels; trial / full as launch_ipm_stats
+// (trial: at the trial point wt, st); ks: kappa_sigma of the update.
+hipError_t launch_ipm_batch(IpmBatchOp op, const DevNet* nets, const IpmDev* ipms,
+                            const double* sc, int count, int max_n, int trial, int full,
+                            double ks, hipStream_t st);
 
 // Differentiation in the loads. Outputs: pg[ng] (reference generator: -s_0),
 // vm[nb], f[1] (unscaled costs); any may be null.

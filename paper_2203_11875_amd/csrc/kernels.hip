@@ -10,6 +10,7 @@
 
 #include "analysis.hpp"
 #include "device.hpp"
+#include "ipm.hpp"
 
 namespace rh {
 
@@ -1191,10 +1192,9 @@ __global__ void __launch_bounds__(kBlock) k_finish_step(DevNet d, const double* 
   k_finish_step_body(d, r, sig_s, p);
 }
 
-__global__ void __launch_bounds__(kBlock) k_objective(DevNet d, const double* u,
-                                                     const double* c2, const double* c1,
-                                                     const double* c0, const int* pg_u,
-                                                     double* f) {
+__device__ __forceinline__ void k_objective_body(const DevNet& d, const double* u,
+                                                 const double* c2, const double* c1,
+                                                 const double* c0, const int* pg_u, double* f) {
   __shared__ double part[kBlock];
   double acc = 0.0;
   for (int g = threadIdx.x; g < d.ng; g += blockDim.x) {
@@ -1209,6 +1209,22 @@ __global__ void __launch_bounds__(kBlock) k_objective(DevNet d, const double* u,
     __syncthreads();
   }
   if (threadIdx.x == 0) *f = part[0];
+}
+__global__ void __launch_bounds__(kBlock) k_objective(DevNet d, const double* u,
+                                                     const double* c2, const double* c1,
+                                                     const double* c0, const int* pg_u,
+                                                     double* f) {
+  k_objective_body(d, u, c2, c1, c0, pg_u, f);
+}
+// objective of each active instance of a lockstep batch at its iterate
+// (trial = 0: w into f[0]) or trial point (trial = 1: wt into f[1])
+__global__ void __launch_bounds__(kBlock) k_objective_b(const DevNet* __restrict__ nets,
+                                                       const IpmDev* __restrict__ ipms,
+                                                       const double* sc, int trial) {
+  if (sc[kIpmSc * blockIdx.z + IS_ACTIVE] == 0.0) return;
+  const DevNet& d = nets[blockIdx.z];
+  const IpmDev& v = ipms[blockIdx.z];
+  k_objective_body(d, trial ? v.wt : v.w, d.c2, d.c1, d.c0, d.pg_u, v.f + trial);
 }
 
 // --------------------------------------------------------- dense Cholesky
@@ -1638,9 +1654,10 @@ inline int cdiv(long a, long b) { return int((a + b - 1) / b); }
 // same bit for bit.
 
 __global__ void __launch_bounds__(kBlock) k_eval_lines_b(const DevNet* __restrict__ nets,
-                                                        const BatchArg* __restrict__ a) {
+                                                        const BatchArg* __restrict__ a,
+                                                        int hessian) {
   const int b = blockIdx.z;
-  k_eval_lines_body(nets[b], a[b].x, a[b].u, a[b].lam, a[b].y, 1);
+  k_eval_lines_body(nets[b], a[b].x, a[b].u, a[b].lam, a[b].y, hessian);
 }
 __global__ void __launch_bounds__(kBlock) k_gather_b(const DevNet* __restrict__ nets) {
   const DevNet& d = nets[blockIdx.z];
@@ -1959,7 +1976,7 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
   const int B = sh.count;
   if (B == 0) return hipSuccess;
   hipLaunchKernelGGL(k_eval_lines_b, dim3(cdiv(sh.max_lines, kBlock), 1, B), dim3(kBlock), 0, st,
-                     nets, args);
+                     nets, args, 1);
   hipLaunchKernelGGL(k_gather_b, dim3(cdiv(sh.max_dst, kBlock), 1, B), dim3(kBlock), 0, st, nets);
   hipLaunchKernelGGL(k_copy_b, dim3(cdiv(sh.max_m, kBlock), 1, B), dim3(kBlock), 0, st, args, 0);
   hipLaunchKernelGGL(k_assemble_k_b, dim3(cdiv(sh.max_nnz_k, kBlock), 1, B), dim3(kBlock), 0, st,
@@ -2031,6 +2048,18 @@ hipError_t launch_batch_solve(const DevNet* nets, const BatchArg* args, const Ba
 
 hipError_t launch_batch_status(const DevNet* nets, int count, int* out, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_gather_status_b, dim3(1, 1, count), dim3(64), 0, st, nets, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_ipm_eval(const DevNet* nets, const BatchArg* args, const IpmDev* ipms,
+                                 const double* sc, const BatchShape& sh, int trial,
+                                 hipStream_t st) {
+  const int B = sh.count;
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval_lines_b, dim3(cdiv(sh.max_lines, kBlock), 1, B), dim3(kBlock), 0, st,
+                     nets, args, trial ? 0 : 1);
+  hipLaunchKernelGGL(k_gather_b, dim3(cdiv(sh.max_dst, kBlock), 1, B), dim3(kBlock), 0, st, nets);
+  hipLaunchKernelGGL(k_objective_b, dim3(1, 1, B), dim3(kBlock), 0, st, nets, ipms, sc, trial);
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "analysis.hpp"
@@ -142,6 +143,16 @@ struct rh_batch {
   int* d_status = nullptr;
   std::vector<rh::DevNet> h_nets;
   std::vector<rh::BatchArg> h_args;
+  // lockstep interior-point solvers (rh_ipm_batch_step): their device
+  // descriptors with the reductions redirected to batch-wide arrays, the
+  // evaluation arguments at the iterates and at the trial points, and the
+  // per-instance scalars
+  std::vector<void*> ipm_solvers;
+  rh::IpmDev* d_ipm = nullptr;
+  rh::BatchArg *d_eargs = nullptr, *d_targs = nullptr;
+  double *d_sc = nullptr, *d_red = nullptr, *d_f = nullptr;
+  std::vector<double> h_sc, h_red, h_f;
+  int max_vec = 0;
 };
 
 namespace {
@@ -652,6 +663,9 @@ void rh_batch_destroy(rh_batch* b) {
   (void)hipFree(b->d_args);
   (void)hipFree(b->d_tiles);
   (void)hipFree(b->d_status);
+  for (void* q : {(void*)b->d_ipm, (void*)b->d_eargs, (void*)b->d_targs, (void*)b->d_sc,
+                  (void*)b->d_red, (void*)b->d_f})
+    if (q) (void)hipFree(q);
   delete b;
 }
 
@@ -1187,9 +1201,9 @@ rh_status ipm_eval_launch(rh_ipm* p) {
   return RH_OK;
 }
 
-// Convergence test, iteration limit, barrier update, residuals and Sigma.
-rh_status ipm_begin(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
-  RH_TRY(read_red(p, s.red, s.f2));
+// Convergence test, iteration limit and barrier update from the reductions
+// of the evaluation in s.red, s.f2.
+void ipm_begin_logic(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
   const double* red = s.red;
   s.f0 = s.f2[0];
   s.e0 = opt_error(p, red, 0.0);
@@ -1199,13 +1213,13 @@ rh_status ipm_begin(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
     fill_info(p, info, s.f0 / p->sigma_f, inf_pr, s.e0, 0.0, 0.0, 0.0, 0);
     s.done = true;
     s.code = RH_OK;
-    return RH_OK;
+    return;
   }
   if (p->iter >= p->opt.max_iter) {
     fill_info(p, info, s.f0 / p->sigma_f, inf_pr, s.e0, 0.0, 0.0, 0.0, 0);
     s.done = true;
     s.code = RH_NOT_CONVERGED;
-    return RH_OK;
+    return;
   }
   // barrier update (monotone)
   for (int k = 0; k < 10; ++k) {
@@ -1216,7 +1230,13 @@ rh_status ipm_begin(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
     p->filt.clear();
   }
   s.mu = p->mu;
-  RH_HIP(rh::launch_ipm_prep(p->net->d, p->v, s.mu, p->net->stream));
+}
+
+// Reads the evaluation's reductions, then the above, then residuals and Sigma.
+rh_status ipm_begin(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
+  RH_TRY(read_red(p, s.red, s.f2));
+  ipm_begin_logic(p, s, info);
+  if (!s.done) RH_HIP(rh::launch_ipm_prep(p->net->d, p->v, s.mu, p->net->stream));
   return RH_OK;
 }
 
@@ -1271,10 +1291,9 @@ rh_status ipm_dir_launch(rh_ipm* p, IpmStep& s) {
   return RH_OK;
 }
 
-// line-search constants of the filter method
-rh_status ipm_dir_read(rh_ipm* p, IpmStep& s) {
-  double rd[rh::IR_NSLOT];
-  RH_TRY(read_red(p, rd, nullptr));
+// line-search constants of the filter method from the reductions rd of
+// launch_ipm_dir
+void ipm_dir_logic(rh_ipm* p, IpmStep& s, const double* rd) {
   s.a_pri = rd[rh::IR_APRI];
   s.a_dual = rd[rh::IR_ADUAL];
   s.dphi = rd[rh::IR_DPHI];
@@ -1293,6 +1312,12 @@ rh_status ipm_dir_read(rh_ipm* p, IpmStep& s) {
   s.a_min = a_min * kGammaAlpha;
   s.alpha = s.a_pri;
   s.trials = 0;
+}
+
+rh_status ipm_dir_read(rh_ipm* p, IpmStep& s) {
+  double rd[rh::IR_NSLOT];
+  RH_TRY(read_red(p, rd, nullptr));
+  ipm_dir_logic(p, s, rd);
   return RH_OK;
 }
 
@@ -1318,9 +1343,9 @@ rh_status ipm_trial_launch(rh_ipm* p, IpmStep& s) {
   return RH_OK;
 }
 
-// filter acceptance of the trial point; halves alpha if rejected
-rh_status ipm_trial_judge(rh_ipm* p, IpmStep& s, bool* accepted) {
-  RH_TRY(read_red(p, s.rt, s.ft));
+// filter acceptance of the trial point from its reductions in s.rt, s.ft;
+// halves alpha if rejected
+void ipm_trial_logic(rh_ipm* p, IpmStep& s, bool* accepted) {
   ++s.trials;
   const double th_t = s.rt[rh::IR_THETA];
   const double ph_t = s.ft[1] - s.mu * s.rt[rh::IR_LOGSUM];
@@ -1344,17 +1369,118 @@ rh_status ipm_trial_judge(rh_ipm* p, IpmStep& s, bool* accepted) {
   }
   *accepted = ok;
   if (!ok) s.alpha *= 0.5;
+}
+
+rh_status ipm_trial_judge(rh_ipm* p, IpmStep& s, bool* accepted) {
+  RH_TRY(read_red(p, s.rt, s.ft));
+  ipm_trial_logic(p, s, accepted);
   return RH_OK;
 }
 
-rh_status ipm_finish(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
+// bookkeeping of an accepted step (the update itself is launched apart)
+void ipm_finish_logic(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
   if (!s.ftype) p->filt.push_back({(1.0 - kGammaTheta) * s.theta, s.phi - kGammaPhi * s.theta});
-  RH_HIP(rh::launch_ipm_update(p->v, s.alpha, s.a_dual, s.mu, kKappaSigma, p->net->stream));
   p->iter += 1;
   fill_info(p, info, s.ft[1] / p->sigma_f, std::max(s.rt[rh::IR_PRIM_G], s.rt[rh::IR_PRIM_H]), s.e0,
             s.alpha, s.a_dual, s.delta, s.trials);
   s.done = true;
   s.code = RH_OK;
+}
+
+rh_status ipm_finish(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
+  RH_HIP(rh::launch_ipm_update(p->v, s.alpha, s.a_dual, s.mu, kKappaSigma, p->net->stream));
+  ipm_finish_logic(p, s, info);
+  return RH_OK;
+}
+
+// Device descriptors of the batch's solvers (uploaded when the solvers
+// change): copies of their IpmDev with the reductions and objective values
+// redirected to batch-wide arrays, and the evaluation arguments.
+rh_status ipm_batch_bind(rh_batch* b, rh_ipm* const* ipms) {
+  const size_t cnt = b->nets.size();
+  bool same = b->ipm_solvers.size() == cnt && b->d_ipm;
+  for (size_t i = 0; same && i < cnt; ++i) same = b->ipm_solvers[i] == ipms[i];
+  if (same) return RH_OK;
+  auto grab = [](size_t bytes, auto** out) {
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) return RH_ERR_OOM;
+    *out = static_cast<std::remove_pointer_t<decltype(out)>>(q);
+    return RH_OK;
+  };
+  if (!b->d_ipm) {
+    RH_TRY(grab(sizeof(rh::IpmDev) * cnt, &b->d_ipm));
+    RH_TRY(grab(sizeof(rh::BatchArg) * cnt, &b->d_eargs));
+    RH_TRY(grab(sizeof(rh::BatchArg) * cnt, &b->d_targs));
+    RH_TRY(grab(sizeof(double) * rh::kIpmSc * cnt, &b->d_sc));
+    RH_TRY(grab(sizeof(double) * rh::IR_NSLOT * cnt, &b->d_red));
+    RH_TRY(grab(sizeof(double) * 2 * cnt, &b->d_f));
+  }
+  std::vector<rh::IpmDev> dv(cnt);
+  std::vector<rh::BatchArg> ea(cnt), ta(cnt);
+  b->max_vec = 0;
+  for (size_t i = 0; i < cnt; ++i) {
+    const rh::IpmDev& v = ipms[i]->v;
+    dv[i] = v;
+    dv[i].red = b->d_red + rh::IR_NSLOT * i;
+    dv[i].f = b->d_f + 2 * i;
+    ea[i] = rh::BatchArg{};
+    ea[i].x = v.w + v.nu; ea[i].u = v.w; ea[i].lam = v.lam; ea[i].y = v.y;
+    ta[i] = rh::BatchArg{};
+    ta[i].x = v.wt + v.nu; ta[i].u = v.wt;
+    b->max_vec = std::max(b->max_vec, std::max(v.nu + v.nx, v.m));
+  }
+  hipStream_t st = b->stream;
+  RH_HIP(hipMemcpyAsync(b->d_ipm, dv.data(), sizeof(rh::IpmDev) * cnt, hipMemcpyHostToDevice, st));
+  RH_HIP(hipMemcpyAsync(b->d_eargs, ea.data(), sizeof(rh::BatchArg) * cnt, hipMemcpyHostToDevice,
+                        st));
+  RH_HIP(hipMemcpyAsync(b->d_targs, ta.data(), sizeof(rh::BatchArg) * cnt, hipMemcpyHostToDevice,
+                        st));
+  RH_HIP(hipStreamSynchronize(st));
+  b->ipm_solvers.assign(ipms, ipms + cnt);
+  b->h_sc.assign(size_t(rh::kIpmSc) * cnt, 0.0);
+  b->h_red.assign(size_t(rh::IR_NSLOT) * cnt, 0.0);
+  b->h_f.assign(2 * cnt, 0.0);
+  return RH_OK;
+}
+
+void ipm_sc(rh_batch* b, size_t i, double mu, double tau, double alpha, double alpha_z,
+            bool active) {
+  double* q = &b->h_sc[size_t(rh::kIpmSc) * i];
+  q[rh::IS_MU] = mu;
+  q[rh::IS_TAU] = tau;
+  q[rh::IS_ALPHA] = alpha;
+  q[rh::IS_ALPHA_Z] = alpha_z;
+  q[rh::IS_ACTIVE] = active ? 1.0 : 0.0;
+}
+
+// Evaluation of the active solvers at their iterates (trial = 0: with the
+// Hessian, objective, grad L, full reductions) or trial points (trial = 1:
+// objective and the primal reductions); scalars uploaded first.
+rh_status ipm_batch_launch(rh_batch* b, int trial, bool upload_sc) {
+  hipStream_t st = b->stream;
+  const int cnt = int(b->nets.size());
+  if (upload_sc)
+    RH_HIP(hipMemcpyAsync(b->d_sc, b->h_sc.data(), sizeof(double) * b->h_sc.size(),
+                          hipMemcpyHostToDevice, st));
+  RH_HIP(rh::launch_batch_ipm_eval(b->d_nets, trial ? b->d_targs : b->d_eargs, b->d_ipm, b->d_sc,
+                                   b->shape, trial, st));
+  if (!trial)
+    RH_HIP(rh::launch_ipm_batch(rh::IB_LAG_GRAD, b->d_nets, b->d_ipm, b->d_sc, cnt, b->max_vec, 0,
+                                0, 0.0, st));
+  RH_HIP(rh::launch_ipm_batch(rh::IB_STATS, b->d_nets, b->d_ipm, b->d_sc, cnt, b->max_vec, trial,
+                              trial ? 0 : 1, 0.0, st));
+  return RH_OK;
+}
+
+// all reductions (and objective values) of the batch to the host
+rh_status ipm_batch_read(rh_batch* b, bool with_f) {
+  hipStream_t st = b->stream;
+  RH_HIP(hipMemcpyAsync(b->h_red.data(), b->d_red, sizeof(double) * b->h_red.size(),
+                        hipMemcpyDeviceToHost, st));
+  if (with_f)
+    RH_HIP(hipMemcpyAsync(b->h_f.data(), b->d_f, sizeof(double) * b->h_f.size(),
+                          hipMemcpyDeviceToHost, st));
+  RH_HIP(hipStreamSynchronize(st));
   return RH_OK;
 }
 
@@ -1471,17 +1597,36 @@ rh_status rh_ipm_batch_step(rh_batch* b, rh_ipm* const* ipms, rh_ipm_info* infos
   const size_t cnt = b->nets.size();
   for (size_t i = 0; i < cnt; ++i)
     if (!ipms[i] || ipms[i]->net != b->nets[i]) return RH_ERR_ARG;
+  RH_TRY(ipm_batch_bind(b, ipms));
+  hipStream_t st = b->stream;
   std::vector<IpmStep> S(cnt);
   auto inf = [&](size_t i) { return infos ? &infos[i] : nullptr; };
-  for (size_t i = 0; i < cnt; ++i) RH_TRY(ipm_eval_launch(ipms[i]));
+  for (size_t i = 0; i < cnt; ++i) {
+    rh_ipm* p = ipms[i];
+    if (p->net->obj_scale != p->sigma_f) RH_TRY(rh_set_objective_scale(p->net, p->sigma_f));
+  }
+  RH_TRY(batch_wait_instances(b));
+  RH_TRY(batch_upload(b));
+  // evaluation of every solver at its iterate (one launch per kernel)
+  for (size_t i = 0; i < cnt; ++i) ipm_sc(b, i, 0.0, 0.0, 0.0, 0.0, true);
+  RH_TRY(ipm_batch_launch(b, 0, true));
+  RH_TRY(ipm_batch_read(b, true));
   bool any = false;
   for (size_t i = 0; i < cnt; ++i) {
-    RH_TRY(ipm_begin(ipms[i], S[i], inf(i)));
+    std::copy_n(&b->h_red[i * rh::IR_NSLOT], rh::IR_NSLOT, S[i].red);
+    std::copy_n(&b->h_f[2 * i], 2, S[i].f2);
+    ipm_begin_logic(ipms[i], S[i], inf(i));
     any = any || !S[i].done;
   }
   if (any) {
-    // one batched condensation and one batched solve (delta_w = 0) for every
-    // instance (finished ones too: their matrices are the solver's scratch)
+    // residuals and Sigma, then one batched condensation and one batched
+    // solve (delta_w = 0) for every instance (finished ones too: their
+    // matrices are the solver's scratch)
+    for (size_t i = 0; i < cnt; ++i) ipm_sc(b, i, S[i].mu, 0.0, 0.0, 0.0, !S[i].done);
+    RH_HIP(hipMemcpyAsync(b->d_sc, b->h_sc.data(), sizeof(double) * b->h_sc.size(),
+                          hipMemcpyHostToDevice, st));
+    RH_HIP(rh::launch_ipm_batch(rh::IB_PREP, b->d_nets, b->d_ipm, b->d_sc, int(cnt), b->max_vec, 0,
+                                0, 0.0, st));
     std::vector<rh_batch_condense_item> ci(cnt);
     std::vector<rh_batch_solve_item> si(cnt);
     for (size_t i = 0; i < cnt; ++i) {
@@ -1500,37 +1645,60 @@ rh_status rh_ipm_batch_step(rh_batch* b, rh_ipm* const* ipms, rh_ipm_info* infos
     for (size_t i = 0; i < cnt; ++i) {
       const int nu = ipms[i]->v.nu;
       RH_HIP(hipMemcpyAsync(ipms[i]->Kc, ipms[i]->K, sizeof(double) * size_t(nu) * nu,
-                            hipMemcpyDeviceToDevice, b->stream));
+                            hipMemcpyDeviceToDevice, st));
     }
-    std::vector<int32_t> st(cnt, RH_OK);
-    const rh_status bs = rh_batch_solve(b, si.data(), st.data());
+    std::vector<int32_t> stt(cnt, RH_OK);
+    const rh_status bs = rh_batch_solve(b, si.data(), stt.data());
     if (bs < 0 && bs != RH_ERR_STATE) return bs;
     // inertia-correction retries per solver (the batch stream has drained)
     for (size_t i = 0; i < cnt; ++i)
-      if (!S[i].done) RH_TRY(ipm_factor(ipms[i], S[i], inf(i), rh_status(st[i])));
+      if (!S[i].done) RH_TRY(ipm_factor(ipms[i], S[i], inf(i), rh_status(stt[i])));
+    RH_TRY(batch_wait_instances(b));
+    // bound-multiplier steps and the largest steps to the boundary
     for (size_t i = 0; i < cnt; ++i)
-      if (!S[i].done) RH_TRY(ipm_dir_launch(ipms[i], S[i]));
+      ipm_sc(b, i, S[i].mu, std::max(kTauMin, 1.0 - S[i].mu), 0.0, 0.0, !S[i].done);
+    RH_HIP(hipMemcpyAsync(b->d_sc, b->h_sc.data(), sizeof(double) * b->h_sc.size(),
+                          hipMemcpyHostToDevice, st));
+    RH_HIP(rh::launch_ipm_batch(rh::IB_DIR, b->d_nets, b->d_ipm, b->d_sc, int(cnt), b->max_vec, 0,
+                                0, 0.0, st));
+    RH_TRY(ipm_batch_read(b, false));
     for (size_t i = 0; i < cnt; ++i)
-      if (!S[i].done) RH_TRY(ipm_dir_read(ipms[i], S[i]));
+      if (!S[i].done) ipm_dir_logic(ipms[i], S[i], &b->h_red[i * rh::IR_NSLOT]);
     // filter line searches in lockstep: one trial per unfinished solver per round
     std::vector<char> acc(cnt, 0);
     for (;;) {
       bool pending = false;
-      for (size_t i = 0; i < cnt; ++i)
-        if (!S[i].done && !acc[i] && ipm_trial_ok(ipms[i], S[i], inf(i))) {
-          RH_TRY(ipm_trial_launch(ipms[i], S[i]));
-          pending = true;
-        }
+      for (size_t i = 0; i < cnt; ++i) {
+        const bool go = !S[i].done && !acc[i] && ipm_trial_ok(ipms[i], S[i], inf(i));
+        ipm_sc(b, i, S[i].mu, 0.0, S[i].alpha, 0.0, go);
+        pending = pending || go;
+      }
       if (!pending) break;
+      RH_HIP(hipMemcpyAsync(b->d_sc, b->h_sc.data(), sizeof(double) * b->h_sc.size(),
+                            hipMemcpyHostToDevice, st));
+      RH_HIP(rh::launch_ipm_batch(rh::IB_TRIAL, b->d_nets, b->d_ipm, b->d_sc, int(cnt),
+                                  b->max_vec, 0, 0, 0.0, st));
+      RH_TRY(ipm_batch_launch(b, 1, false));
+      RH_TRY(ipm_batch_read(b, true));
       for (size_t i = 0; i < cnt; ++i)
-        if (!S[i].done && !acc[i]) {
+        if (b->h_sc[size_t(rh::kIpmSc) * i + rh::IS_ACTIVE] != 0.0) {
+          std::copy_n(&b->h_red[i * rh::IR_NSLOT], rh::IR_NSLOT, S[i].rt);
+          std::copy_n(&b->h_f[2 * i], 2, S[i].ft);
           bool ok = false;
-          RH_TRY(ipm_trial_judge(ipms[i], S[i], &ok));
+          ipm_trial_logic(ipms[i], S[i], &ok);
           acc[i] = ok ? 1 : 0;
         }
     }
+    // updates of the accepted steps
     for (size_t i = 0; i < cnt; ++i)
-      if (!S[i].done && acc[i]) RH_TRY(ipm_finish(ipms[i], S[i], inf(i)));
+      ipm_sc(b, i, S[i].mu, 0.0, S[i].alpha, S[i].a_dual, !S[i].done && acc[i]);
+    RH_HIP(hipMemcpyAsync(b->d_sc, b->h_sc.data(), sizeof(double) * b->h_sc.size(),
+                          hipMemcpyHostToDevice, st));
+    RH_HIP(rh::launch_ipm_batch(rh::IB_UPDATE, b->d_nets, b->d_ipm, b->d_sc, int(cnt), b->max_vec,
+                                0, 0, kKappaSigma, st));
+    for (size_t i = 0; i < cnt; ++i)
+      if (!S[i].done && acc[i]) ipm_finish_logic(ipms[i], S[i], inf(i));
+    RH_HIP(hipStreamSynchronize(st));
   }
   if (codes)
     for (size_t i = 0; i < cnt; ++i) codes[i] = S[i].code;
