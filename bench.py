@@ -248,8 +248,8 @@ def concurrent_scenarios(api, torch, count=16, workers=4):
 def batched_scenarios(api, torch, count=16):
     """The differentiated OPF scenarios of differentiated_run as one
     api.OPFBatchLayer call: the forward solves all scenarios in lockstep with
-    one batched condensation and solve per round; the backward differentiates
-    each scenario."""
+    one batched condensation and solve per round; the backward batches the
+    adjoint solves of all scenarios."""
     import numpy as np
     import synthnet
     base = synthnet.case1354(0)
@@ -280,7 +280,8 @@ def batched_scenarios(api, torch, count=16):
             "forward_ms": 1e3 * tf, "backward_ms": 1e3 * tb,
             "ipm_iters_per_s_forward": iters / tf, "ipm_iterations_mean": iters / count,
             "step": "forward: all scenarios in lockstep to 1e-8 (rh_ipm_batch_step); "
-                    "backward: one adjoint solve per scenario"}
+                    "backward: the adjoint solves of all scenarios in one batched "
+                    "condensation and solve (rh_ipm_batch_backward)"}
 
 
 def _progress(msg):

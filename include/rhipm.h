@@ -420,6 +420,19 @@ rh_status rh_ipm_outputs(const rh_ipm* ipm, double* pg, double* vm, double* f);
  * rh_ipm_step recomputes them). Synchronises the stream. */
 rh_status rh_ipm_backward(rh_ipm* ipm, const double* dpg, const double* dvm, const double* df,
                           double* gpd, double* gqd, double* xi);
+/* rh_ipm_backward for every solver of a batch at once (solver i on the
+ * batch's network i, all converged; the network i must hold the loads its
+ * solver was solved with): the condensation with the adjoint right-hand
+ * sides and the solve are one batched launch each. Host arrays of count
+ * device pointers: dpg, dvm, df (the arrays or their entries may be NULL:
+ * zero weights), gpd, gqd (outputs, nb entries each). codes[count] (host,
+ * optional): each solver's status as rh_ipm_backward's (RH_NOT_POSDEF: no
+ * gradient written for it). The gradients equal rh_ipm_backward's bit for
+ * bit. Returns RH_OK, RH_ERR_STATE if a solver has not converged, or another
+ * negative code on a hard error. Synchronises the batch's stream. */
+rh_status rh_ipm_batch_backward(rh_batch* batch, rh_ipm* const* ipms, const double* const* dpg,
+                                const double* const* dvm, const double* const* df,
+                                double* const* gpd, double* const* gqd, int32_t* codes);
 /* Frees the solver and restores the network's objective scale to 1. */
 void rh_ipm_destroy(rh_ipm* ipm);
 

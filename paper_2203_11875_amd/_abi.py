@@ -101,6 +101,7 @@ SIGNATURES = {
     "rh_ipm_outputs": (C.c_int, [vp, vp, vp, vp]),
     "rh_ipm_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "rh_ipm_batch_step": (C.c_int, [vp, vp, vp, vp]),
+    "rh_ipm_batch_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "rh_power_flow": (C.c_int, [vp, vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_double)]),
     "rh_redlin_create": (C.c_int, [vp, C.POINTER(rh_ipm_options), vp, vp, C.POINTER(vp)]),

@@ -512,6 +512,36 @@ class IpmBatch:
                "rh_ipm_batch_step")
         return [(int(codes[i]), _info_ipm(infos[i])) for i in range(n)]
 
+    def backward(self, dpg=None, dvm=None, df=None):
+        """Gradients in (Pd, Qd) of every converged solver at once
+        (rh_ipm_batch_backward); dpg (S, ng), dvm (S, nb), df (S) device
+        tensors or None. Returns (grad_pd (S, nb), grad_qd (S, nb), codes)."""
+        t = self.batch.torch
+        n0 = self.ipms[0].net
+        S, nb = len(self.ipms), n0.info["nb"]
+        dev = n0.device
+
+        def rows(a, width):
+            if a is None:
+                return None, None
+            a = a.to(device=dev, dtype=t.float64).reshape(S, width).contiguous()
+            arr = (C.c_void_p * S)(*[a[i].data_ptr() for i in range(S)])
+            return a, arr
+
+        keep = [rows(dpg, n0.info["ng"]), rows(dvm, nb), rows(df, 1)]
+        gpd = t.empty((S, nb), dtype=t.float64, device=dev)
+        gqd = t.empty((S, nb), dtype=t.float64, device=dev)
+        gp = (C.c_void_p * S)(*[gpd[i].data_ptr() for i in range(S)])
+        gq = (C.c_void_p * S)(*[gqd[i].data_ptr() for i in range(S)])
+        codes = (C.c_int32 * S)()
+        arg = lambda k: C.cast(k[1], C.c_void_p) if k[1] is not None else None
+        _check(lib().rh_ipm_batch_backward(self.batch.h, C.cast(self._h, C.c_void_p),
+                                           arg(keep[0]), arg(keep[1]), arg(keep[2]),
+                                           C.cast(gp, C.c_void_p), C.cast(gq, C.c_void_p),
+                                           C.cast(codes, C.c_void_p)),
+               "rh_ipm_batch_backward")
+        return gpd, gqd, [int(codes[i]) for i in range(S)]
+
 
 class RedLin:
     """Reduce-then-linearize solver (Algorithm 2) on a device network handle
@@ -627,6 +657,7 @@ class OPFBatchLayer:
             G._ipm = None        # the solvers belong to the autograd graph
             ipms.append(ipm)
         ib = IpmBatch(self.batch, ipms)
+        self._ib = ib
         done = [False] * self.count
         infos = [None] * self.count
         for _ in range(self.max_iter + 2):
@@ -642,7 +673,7 @@ class OPFBatchLayer:
         if not all(done):
             _check(_abi.RH_NOT_CONVERGED, "rh_ipm_batch_step")
         self.last_infos = infos
-        return ipms
+        return ipms, ib
 
     def _fork(self):
         """Every handle's stream waits for the caller's (inputs ready)."""
@@ -684,10 +715,10 @@ def _make_opf_function():
             n0 = layer.nets[0]
             pdd = n0._t(pd).reshape(S, nb).contiguous()
             qdd = n0._t(qd).reshape(S, nb).contiguous()
-            ipms = layer._solve(pdd, qdd)
+            ipms, ib = layer._solve(pdd, qdd)
             outs = [ipm.outputs() for ipm in ipms]
             layer._join()
-            ctx.ipms, ctx.layer, ctx.loads = ipms, layer, (pdd, qdd)
+            ctx.ipms, ctx.ib, ctx.layer, ctx.loads = ipms, ib, layer, (pdd, qdd)
             return (torch.stack([o[0] for o in outs]), torch.stack([o[1] for o in outs]),
                     torch.stack([o[2] for o in outs]))
 
@@ -696,16 +727,14 @@ def _make_opf_function():
             layer = ctx.layer
             pdd, qdd = ctx.loads
             layer._fork()
-            gp, gq = [], []
-            for i, (G, ipm) in enumerate(zip(layer.nets, ctx.ipms)):
+            for i, G in enumerate(layer.nets):
                 G.set_loads(pdd[i], qdd[i])
-                a, b = ipm.backward(gpg[i] if gpg is not None else None,
-                                    gvm[i] if gvm is not None else None,
-                                    gf[i] if gf is not None else None)
-                gp.append(a)
-                gq.append(b)
+            gp, gq, codes = ctx.ib.backward(gpg, gvm, gf)
+            for c in codes:
+                if c not in (_abi.RH_OK, _abi.RH_SMALL_PIVOT):
+                    _check(c, "rh_ipm_batch_backward")
             layer._join()
-            return torch.stack(gp), torch.stack(gq), None
+            return gp, gq, None
 
     return _OPF, _OPFBatch
 

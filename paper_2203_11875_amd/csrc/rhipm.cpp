@@ -1756,6 +1756,61 @@ rh_status rh_ipm_backward(rh_ipm* p, const double* dpg, const double* dvm, const
   return code;
 }
 
+rh_status rh_ipm_batch_backward(rh_batch* b, rh_ipm* const* ipms, const double* const* dpg,
+                                const double* const* dvm, const double* const* df,
+                                double* const* gpd, double* const* gqd, int32_t* codes) {
+  if (!b || !ipms || !gpd || !gqd) return RH_ERR_ARG;
+  const size_t cnt = b->nets.size();
+  for (size_t i = 0; i < cnt; ++i) {
+    if (!ipms[i] || ipms[i]->net != b->nets[i] || !gpd[i] || !gqd[i]) return RH_ERR_ARG;
+    if (!ipms[i]->converged) return RH_ERR_STATE;
+  }
+  RH_TRY(ipm_batch_bind(b, ipms));
+  hipStream_t st = b->stream;
+  for (size_t i = 0; i < cnt; ++i) {
+    rh_ipm* p = ipms[i];
+    if (p->net->obj_scale != p->sigma_f) RH_TRY(rh_set_objective_scale(p->net, p->sigma_f));
+  }
+  RH_TRY(batch_wait_instances(b));
+  RH_TRY(batch_upload(b));
+  // Sigma of each final iterate, the adjoint right-hand sides, then one
+  // batched condensation and solve
+  for (size_t i = 0; i < cnt; ++i) ipm_sc(b, i, ipms[i]->mu, 0.0, 0.0, 0.0, true);
+  RH_HIP(hipMemcpyAsync(b->d_sc, b->h_sc.data(), sizeof(double) * b->h_sc.size(),
+                        hipMemcpyHostToDevice, st));
+  RH_HIP(rh::launch_ipm_batch(rh::IB_PREP, b->d_nets, b->d_ipm, b->d_sc, int(cnt), b->max_vec, 0,
+                              0, 0.0, st));
+  std::vector<rh_batch_condense_item> ci(cnt);
+  std::vector<rh_batch_solve_item> si(cnt);
+  for (size_t i = 0; i < cnt; ++i) {
+    rh_ipm* p = ipms[i];
+    auto& v = p->v;
+    const int nu = v.nu;
+    RH_HIP(rh::launch_adjoint_rhs(p->net->d, v, 1.0 / p->sigma_f, dpg ? dpg[i] : nullptr,
+                                  dvm ? dvm[i] : nullptr, df ? df[i] : nullptr, v.r, st));
+    ci[i] = rh_batch_condense_item{};
+    ci[i].x = v.w + nu; ci[i].u = v.w; ci[i].lam = v.lam; ci[i].y = v.y;
+    ci[i].sig_x = v.sig_w + nu; ci[i].sig_u = v.sig_w; ci[i].sig_s = v.sig_s;
+    ci[i].r = v.r; ci[i].K = p->K; ci[i].ldk = nu; ci[i].rhs = p->rhs;
+    si[i] = rh_batch_solve_item{};
+    si[i].K = p->K; si[i].ldk = nu; si[i].delta_w = 0.0; si[i].rhs = p->rhs;
+    si[i].r = v.r; si[i].p = v.p;
+  }
+  RH_TRY(rh_batch_condense(b, ci.data()));
+  std::vector<int32_t> stt(cnt, RH_OK);
+  const rh_status bs = rh_batch_solve(b, si.data(), stt.data());
+  if (bs < 0 && bs != RH_ERR_STATE) return bs;
+  for (size_t i = 0; i < cnt; ++i) {
+    if (stt[i] != RH_OK && stt[i] != RH_SMALL_PIVOT) continue;
+    rh_ipm* p = ipms[i];
+    RH_HIP(rh::launch_adjoint_grad(p->net->d, p->v, p->v.p, gpd[i], gqd[i], st));
+  }
+  RH_HIP(hipStreamSynchronize(st));
+  if (codes)
+    for (size_t i = 0; i < cnt; ++i) codes[i] = stt[i];
+  return RH_OK;
+}
+
 rh_status rh_ipm_get_state(const rh_ipm* p, double* x, double* u, double* s, double* lam,
                            double* y) {
   if (!p) return RH_ERR_ARG;
