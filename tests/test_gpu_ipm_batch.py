@@ -87,3 +87,15 @@ def test_batch_step_rejects_mismatched_solver():
     B = api.Batch(Gs)
     with pytest.raises(api.RhError):
         api.IpmBatch(B, ipms).step()
+
+
+def test_batch_backward_needs_converged_solvers():
+    api = _api()
+    nets = _nets()[:2]
+    Gs = [api.Net(n) for n in nets]
+    ipms = [api.Ipm(G, tol=1e-8) for G in Gs]
+    B = api.Batch(Gs)
+    with pytest.raises(api.RhError) as e:
+        api.IpmBatch(B, ipms).backward(None, None, torch.ones(2, dtype=torch.float64,
+                                                              device="cuda"))
+    assert e.value.code == -5
