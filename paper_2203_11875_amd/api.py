@@ -699,6 +699,7 @@ def _make_opf_function():
             ipm, info = layer._solve(pdd, qdd)
             pg, vm, f = ipm.outputs()
             ctx.ipm, ctx.layer, ctx.loads, ctx.info = ipm, layer, (pdd, qdd), info
+            ctx.devices = (torch.as_tensor(pd).device, torch.as_tensor(qd).device)
             return pg, vm, f
 
         @staticmethod
@@ -706,7 +707,7 @@ def _make_opf_function():
             n = ctx.layer.net
             n.set_loads(*ctx.loads)
             gpd, gqd = ctx.ipm.backward(gpg, gvm, gf)
-            return gpd, gqd, None
+            return gpd.to(ctx.devices[0]), gqd.to(ctx.devices[1]), None
 
     class _OPFBatch(torch.autograd.Function):
         @staticmethod
@@ -719,6 +720,8 @@ def _make_opf_function():
             outs = [ipm.outputs() for ipm in ipms]
             layer._join()
             ctx.ipms, ctx.ib, ctx.layer, ctx.loads = ipms, ib, layer, (pdd, qdd)
+            ctx.devices = (torch.as_tensor(pd).device, torch.as_tensor(qd).device)
+            ctx.shapes = (torch.as_tensor(pd).shape, torch.as_tensor(qd).shape)
             return (torch.stack([o[0] for o in outs]), torch.stack([o[1] for o in outs]),
                     torch.stack([o[2] for o in outs]))
 
@@ -734,7 +737,8 @@ def _make_opf_function():
                 if c not in (_abi.RH_OK, _abi.RH_SMALL_PIVOT):
                     _check(c, "rh_ipm_batch_backward")
             layer._join()
-            return gp, gq, None
+            return (gp.reshape(ctx.shapes[0]).to(ctx.devices[0]),
+                    gq.reshape(ctx.shapes[1]).to(ctx.devices[1]), None)
 
     return _OPF, _OPFBatch
 

@@ -190,3 +190,21 @@ def test_batch_layer_equals_single_layer():
         assert torch.equal(pgi, pg[i]) and torch.equal(vmi, vm[i]) and torch.equal(fi, f[i])
         assert torch.equal(pdi.grad, pd.grad[i]) and torch.equal(qdi.grad, qd.grad[i])
     assert not torch.equal(pd.grad[0], pd.grad[1])
+
+
+def test_layer_accepts_host_loads():
+    """Loads given as CPU tensors get their gradients on the CPU."""
+    api = _api()
+    net = synthnet.case9(0)
+    layer = api.OPFLayer(net, tol=1e-8)
+    pd = torch.tensor(net.pd, dtype=torch.float64, requires_grad=True)
+    qd = torch.tensor(net.qd, dtype=torch.float64, requires_grad=True)
+    _, _, f = layer(pd, qd)
+    f.backward()
+    assert pd.grad.device.type == "cpu" and qd.grad.device.type == "cpu"
+    ref = api.OPFLayer(net, tol=1e-8)
+    pd2 = torch.tensor(net.pd, dtype=torch.float64, device="cuda", requires_grad=True)
+    qd2 = torch.tensor(net.qd, dtype=torch.float64, device="cuda", requires_grad=True)
+    _, _, f2 = ref(pd2, qd2)
+    f2.backward()
+    assert torch.equal(pd.grad, pd2.grad.cpu()) and torch.equal(qd.grad, qd2.grad.cpu())
