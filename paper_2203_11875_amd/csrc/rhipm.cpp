@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -147,7 +148,7 @@ struct rh_batch {
   // descriptors with the reductions redirected to batch-wide arrays, the
   // evaluation arguments at the iterates and at the trial points, and the
   // per-instance scalars
-  std::vector<void*> ipm_solvers;
+  std::vector<unsigned long long> ipm_solvers;   // ids of the bound solvers
   rh::IpmDev* d_ipm = nullptr;
   rh::BatchArg *d_eargs = nullptr, *d_targs = nullptr;
   double *d_sc = nullptr, *d_red = nullptr, *d_f = nullptr;
@@ -1026,6 +1027,7 @@ constexpr double kSPhi = 2.3, kEtaPhi = 1e-8, kGammaAlpha = 0.05;
 
 struct rh_ipm {
   rh_net* net = nullptr;
+  unsigned long long id = 0;   // unique per solver created in this process
   rh_ipm_options opt{};
   rh::IpmDev v{};
   std::vector<void*> allocs;
@@ -1398,8 +1400,10 @@ rh_status ipm_finish(rh_ipm* p, IpmStep& s, rh_ipm_info* info) {
 // redirected to batch-wide arrays, and the evaluation arguments.
 rh_status ipm_batch_bind(rh_batch* b, rh_ipm* const* ipms) {
   const size_t cnt = b->nets.size();
+  // solvers are told apart by their ids (a new solver may reuse the address
+  // of a destroyed one)
   bool same = b->ipm_solvers.size() == cnt && b->d_ipm;
-  for (size_t i = 0; same && i < cnt; ++i) same = b->ipm_solvers[i] == ipms[i];
+  for (size_t i = 0; same && i < cnt; ++i) same = b->ipm_solvers[i] == ipms[i]->id;
   if (same) return RH_OK;
   auto grab = [](size_t bytes, auto** out) {
     void* q = nullptr;
@@ -1436,7 +1440,8 @@ rh_status ipm_batch_bind(rh_batch* b, rh_ipm* const* ipms) {
   RH_HIP(hipMemcpyAsync(b->d_targs, ta.data(), sizeof(rh::BatchArg) * cnt, hipMemcpyHostToDevice,
                         st));
   RH_HIP(hipStreamSynchronize(st));
-  b->ipm_solvers.assign(ipms, ipms + cnt);
+  b->ipm_solvers.resize(cnt);
+  for (size_t i = 0; i < cnt; ++i) b->ipm_solvers[i] = ipms[i]->id;
   b->h_sc.assign(size_t(rh::kIpmSc) * cnt, 0.0);
   b->h_red.assign(size_t(rh::IR_NSLOT) * cnt, 0.0);
   b->h_f.assign(2 * cnt, 0.0);
@@ -1503,6 +1508,8 @@ rh_status rh_ipm_create(rh_net* n, const rh_ipm_options* opts, const double* x0,
   if (!n || !out) return RH_ERR_ARG;
   std::unique_ptr<rh_ipm> p(new (std::nothrow) rh_ipm());
   if (!p) return RH_ERR_OOM;
+  static std::atomic<unsigned long long> next_id{1};
+  p->id = next_id.fetch_add(1);
   p->net = n;
   if (opts) p->opt = *opts; else rh_ipm_default_options(&p->opt);
   if (!(p->opt.tol > 0.0) || p->opt.max_iter < 0 || !(p->opt.mu_init > 0.0) ||

@@ -99,3 +99,32 @@ def test_batch_backward_needs_converged_solvers():
         api.IpmBatch(B, ipms).backward(None, None, torch.ones(2, dtype=torch.float64,
                                                               device="cuda"))
     assert e.value.code == -5
+
+
+def test_batch_rebinds_new_solvers():
+    """A batch stepped with one set of solvers, then (after those are closed)
+    with new ones, steps the new ones from their own starting points: the
+    binding follows the solvers, not the addresses they happen to get."""
+    api = _api()
+    nets = _nets()[:2]
+    Gs = [api.Net(n) for n in nets]
+    B = api.Batch(Gs)
+    first = [api.Ipm(G, tol=1e-6) for G in Gs]
+    IB = api.IpmBatch(B, first)
+    for _ in range(3):
+        IB.step()
+    for p in first:
+        p.close()
+    second = [api.Ipm(G, tol=1e-6) for G in Gs]
+    got = api.IpmBatch(B, second).step()
+    for i, G in enumerate(Gs):
+        ref = api.Ipm(G, tol=1e-6)
+        code, info = ref.step()
+        assert got[i][0] == code == 0
+        for key in ("mu", "alpha_pr", "alpha_du", "obj", "err"):
+            assert got[i][1][key] == info[key], (i, key)
+        s1 = {k: v.cpu().numpy() for k, v in second[i].state().items()}
+        s2 = {k: v.cpu().numpy() for k, v in ref.state().items()}
+        for k in s1:
+            assert np.array_equal(s1[k], s2[k]), (i, k)
+        ref.close()
