@@ -1365,8 +1365,8 @@ __device__ __forceinline__ void store_quad_lower(double* A, long ld, int n, int 
 // inv (column-major) and y_k = L_kk^{-1} b_k. The remaining groups apply
 // panel k - 1 to the trailing tiles (i, j), k < j <= i. The diagonal tile
 // (k, k) of A is read by every panel group of the launch, so L_kk goes to A
-// one launch later. The off-diagonal tiles are also stored by rows in lrow
-// (row block i: NB rows of nbk NB entries) for the backward substitution.
+// one launch later. The off-diagonal tiles are also stored in the row-block
+// panels of lrow (column after column) for the backward substitution.
 // delta enters each diagonal tile on its first touch (k <= 1).
 __device__ __forceinline__ void k_chol_step_body(double* A, long ld, int n, int k, double delta, double* b, double* y, double* inv, double* dl, double* lrow, int* status, long long* trace) {
   if (status[0] != 0) return;
@@ -1473,9 +1473,8 @@ __device__ __forceinline__ void k_chol_step_body(double* A, long ld, int n, int 
     for (int idx = tid; idx < NB * NB; idx += 256) {
       const int r = idx % NB, c = idx / NB, row = bi * NB + r;
       if (row < n) A[(size_t)(k0 + c) * ld + row] = P[NB + r][c];
-      // the same tile by rows, for the backward substitution
-      const int rr = idx / NB, cc = idx % NB;
-      lrow[((size_t)bi * NB + rr) * npad + k0 + cc] = P[NB + rr][cc];
+      // the same tile in the row-block panel of the backward substitution
+      lrow[(size_t)bi * NB * npad + (size_t)(k0 + c) * NB + r] = P[NB + r][c];
     }
     if (tid < NB && bi * NB + tid < n) b[bi * NB + tid] = bks[tid];
     return;
@@ -1505,15 +1504,57 @@ __global__ void __launch_bounds__(256) k_chol_step(double* A, long ld, int n, in
   k_chol_step_body(A, ld, n, k, delta, b, y, inv, dl, lrow, status, trace);
 }
 
-// One step of the backward substitution for row block bk (b0 = bk NB):
-// lv holds this thread's half column of L_{bk, c} (c = tid / 2 < b0, rows
-// b0 + 16 (tid & 1) + q), loaded one step ahead; Ms[bk % 3] holds
-// L_bk,bk^{-T} (column-major), parked one step ahead from mpark.
+// Row-block panels of L for the backward substitution: row block i is the
+// NB x i NB slice L_{i, 0:i} stored column after column, NB rows contiguous
+// (entry (r, c) at lrow[i NB npad + c NB + r]). A wave reads the 32 columns
+// of its pass as one contiguous 8 KB run: in load j, lane l holds rows
+// 2 (l & 15), 2 (l & 15) + 1 of column 4 j + (l >> 4) of the run.
+struct Panel { double2 v[8]; };
+
+__device__ __forceinline__ void panel_load(const double* lrow, size_t off, Panel& pl, int lane) {
+  const double2* p = reinterpret_cast<const double2*>(lrow + off) + lane;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) pl.v[j] = p[64 * j];
+}
+
+// The 32 column sums sum_r L(r, c) x_r of a wave's run: the products of a
+// load are summed over its 16 lanes by recursive halving (each exchange
+// sends the half of the partial sums the partner keeps), so a lane ends with
+// one column: j = 4 (l & 1) + 2 ((l >> 1) & 1) + ((l >> 2) & 1).
+__device__ __forceinline__ double panel_dot(const Panel& pl, double x0, double x1, bool ok0,
+                                            bool ok1, int lane) {
+  double v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    v[j] = fma(ok0 ? pl.v[j].x : 0.0, x0, (ok1 ? pl.v[j].y : 0.0) * x1);
+#pragma unroll
+  for (int half = 4, m = 1; half >= 1; half >>= 1, m <<= 1) {
+    const bool hi = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double send = hi ? v[i] : v[half + i];
+      const double keep = hi ? v[half + i] : v[i];
+      v[i] = keep + __shfl_xor(send, m);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 8);
+}
+
+__device__ __forceinline__ int panel_col(int lane) {
+  return 4 * (4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1)) + (lane >> 4);
+}
+
+// One step of the backward substitution for row block bk (b0 = bk NB): pl
+// holds this wave's first run of panel bk (columns 32 wave .. + 31), loaded
+// one step ahead; rows past n are zeroed here, at the use, so the loads stay
+// in flight until then. Ms[bk % 3] holds L_bk,bk^{-T} (column-major), parked
+// by the previous step from mpark (the inverse of block bk - 1, loaded a
+// step before that).
 template <bool WIDE>
 __device__ __forceinline__ void backward_block(const double* lrow, int npad, int n, int bk,
                                                double* ys, double* xb, double (*Ms)[NB * NB],
-                                               const double (&lv)[16], double mpark, int tid) {
-  const int b0 = bk * NB, lane = tid & 63, wave = tid >> 6, hh = tid & 1;
+                                               const Panel& pl, double mpark, int tid) {
+  const int b0 = bk * NB, lane = tid & 63, wave = tid >> 6;
   if (wave == 0) {                              // x_b = L_bb^{-T} y_b
     const int t = lane & 31, hs = lane >> 5;
     const double* m = Ms[bk % 3];
@@ -1528,34 +1569,37 @@ __device__ __forceinline__ void backward_block(const double* lrow, int npad, int
   }
   if (bk > 0) Ms[(bk + 2) % 3][tid] = mpark;    // inverse of block bk - 1
   lds_barrier();
-  for (int base = 0; base < (WIDE ? 2 * b0 : 1); base += NB * NB) {
-    const int idx = base + tid, c = idx >> 1;
-    double v = 0.0;
-    if (base == 0) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) v = fma(lv[q], xb[16 * hh + q], v);
-    } else if (WIDE && idx < 2 * b0) {         // columns beyond the first 512
-      const double* rows = lrow + ((size_t)b0 + 16 * hh) * npad + c;
-#pragma nounroll
-      for (int q = 0; q < 16; ++q)
-        v = fma(ld_or0(rows, (size_t)q * npad, b0 + 16 * hh + q < n), xb[16 * hh + q], v);
+  const int r0 = 2 * (lane & 15);
+  const bool ok0 = b0 + r0 < n, ok1 = b0 + r0 + 1 < n;
+  const double x0 = xb[r0], x1 = xb[r0 + 1];
+  const int cl = panel_col(lane);
+  for (int c0 = 32 * wave; c0 < (WIDE ? b0 : 32 * wave + 1); c0 += NB * NB / 2) {
+    double s;
+    if (c0 == 32 * wave) {
+      s = panel_dot(pl, x0, x1, ok0, ok1, lane);
+    } else {                                   // columns past the first 512: in place
+      Panel q;
+      panel_load(lrow, (size_t)bk * NB * npad + (size_t)c0 * NB, q, lane);
+      s = panel_dot(q, x0, x1, ok0, ok1, lane);
     }
-    v += __shfl_xor(v, 1);
-    if (hh == 0 && idx < 2 * b0) ys[c] -= v;
+    if ((lane & 8) == 0 && c0 + cl < b0) ys[c0 + cl] -= s;
   }
   lds_barrier();
 }
 
-__device__ __forceinline__ void backward_load(const double* lrow, int npad, int n, int bk,
-                                              const double* inv, double (&lv)[16], double& mv,
-                                              int tid) {
-  if (bk < 0) return;
-  const int b0 = bk * NB, hh = tid & 1, c = tid >> 1;
-  const bool have = 2 * b0 > tid;
-  const double* rows = lrow + ((size_t)b0 + 16 * hh) * npad + c;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) lv[q] = ld_or0(rows, (size_t)q * npad, have && b0 + 16 * hh + q < n);
-  mv = inv[(size_t)bk * NB * NB + tid];
+// This wave's first run of panel bk for the step of block bk: waves past
+// the block's columns read the first run instead (unused). Issued
+// unconditionally (bk < 0 reads block 0, unused) so that the compiler
+// counts the loads in flight exactly and waits for each set only at its use.
+__device__ __forceinline__ void backward_load_l(const double* lrow, int npad, int bk, Panel& pl,
+                                                int tid) {
+  bk = max(bk, 0);
+  const int wave = tid >> 6, cw = 32 * wave < bk * NB ? 32 * wave : 0;
+  panel_load(lrow, (size_t)bk * NB * npad + (size_t)cw * NB, pl, tid & 63);
+}
+// this thread's entry of L_bk,bk^{-T}
+__device__ __forceinline__ void backward_load_m(const double* inv, int bk, double& mv, int tid) {
+  mv = inv[(size_t)max(bk, 0) * NB * NB + tid];
 }
 
 // Backward substitution L^T x = y (x over y) by work-group 0, by NB-row
@@ -1563,9 +1607,10 @@ __device__ __forceinline__ void backward_load(const double* lrow, int npad, int 
 // y_c -= L_bc^T x_b for every column c left of the block. The operands of
 // block b - 1 are loaded while block b is processed (two register sets).
 // Work-groups 8 h (h >= 1), dispatched to the same XCD as work-group 0, read
-// the rows of L ahead of it into that XCD's L2 and exit; the rest exit.
+// the panels ahead of it into that XCD's L2 and exit; the rest exit.
 // WIDE: n > 33 NB, some row blocks span more columns than one pass of the
-// work-group covers (the columns past the first pass are loaded in place).
+// work-group covers (16 waves x 32 columns; the runs past the first pass are
+// loaded in place).
 template <bool WIDE>
 __device__ __forceinline__ void k_chol_backward_body(const double* lrow, int n, double* y, const double* inv, const int* status, long long* trace) {
   if (status[0] != 0) return;
@@ -1577,11 +1622,9 @@ __device__ __forceinline__ void k_chol_backward_body(const double* lrow, int n, 
     // helper h touches row blocks nbk - 1 - h, nbk - 1 - h - nh, ...
     double acc = 0.0;
     for (int bk = nbk - 1 - h; bk >= 0; bk -= nh) {
-      const int b0 = bk * NB;
-      for (int idx = tid; idx < NB * b0 / 8; idx += NB * NB) {   // one 64-byte piece each
-        const int r = idx / (b0 / 8), c8 = idx % (b0 / 8);
-        acc += lrow[((size_t)b0 + r) * npad + 8 * c8];
-      }
+      const double* panel = lrow + (size_t)bk * NB * npad;        // NB * bk NB contiguous
+      for (int idx = tid; idx < NB * bk * NB / 8; idx += NB * NB)  // one 64-byte piece each
+        acc += panel[8 * (size_t)idx];
     }
     asm volatile("" :: "v"(acc));             // keeps the loads
     return;
@@ -1591,19 +1634,29 @@ __device__ __forceinline__ void k_chol_backward_body(const double* lrow, int n, 
   __shared__ double Ms[3][NB * NB];
   const bool tr = trace != nullptr && tid == 0;
   if (tr) trace[0] = wall_clock64();
-  double l0[16], l1[16], m0 = 0.0, m1 = 0.0;
-  backward_load(lrow, npad, n, nbk - 1, inv, l0, m0, tid);
-  backward_load(lrow, npad, n, nbk - 2, inv, l1, m1, tid);
+  // step bk parks the inverse of block bk - 1 (ma or mb), loaded one step
+  // before; after a step the registers it used take the loads two steps ahead
+  // (issued after y and in this order: the loop's first steps then wait for
+  // no load issued after the one they use)
+  Panel l0, l1;
+  double m = 0.0, ma = 0.0, mb = 0.0;
   for (int i = tid; i < nbk * NB; i += NB * NB) ys[i] = i < n ? y[i] : 0.0;
-  Ms[(nbk - 1) % 3][tid] = m0;
+  backward_load_m(inv, nbk - 1, m, tid);
+  backward_load_m(inv, nbk - 2, ma, tid);
+  backward_load_m(inv, nbk - 3, mb, tid);
+  backward_load_l(lrow, npad, nbk - 1, l0, tid);
+  backward_load_l(lrow, npad, nbk - 2, l1, tid);
+  Ms[(nbk - 1) % 3][tid] = m;
   __syncthreads();
   if (tr) trace[1] = wall_clock64();
   int bk = nbk - 1;
   for (; bk >= 1; bk -= 2) {
-    backward_block<WIDE>(lrow, npad, n, bk, ys, xb, Ms, l0, m1, tid);
-    backward_load(lrow, npad, n, bk - 2, inv, l0, m0, tid);
-    backward_block<WIDE>(lrow, npad, n, bk - 1, ys, xb, Ms, l1, m0, tid);
-    backward_load(lrow, npad, n, bk - 3, inv, l1, m1, tid);
+    backward_block<WIDE>(lrow, npad, n, bk, ys, xb, Ms, l0, ma, tid);
+    backward_load_l(lrow, npad, bk - 2, l0, tid);
+    backward_load_m(inv, bk - 3, ma, tid);
+    backward_block<WIDE>(lrow, npad, n, bk - 1, ys, xb, Ms, l1, mb, tid);
+    backward_load_l(lrow, npad, bk - 3, l1, tid);
+    backward_load_m(inv, bk - 4, mb, tid);
   }
   if (bk == 0) backward_block<WIDE>(lrow, npad, n, 0, ys, xb, Ms, l0, 0.0, tid);
   if (tr) trace[2] = wall_clock64();
