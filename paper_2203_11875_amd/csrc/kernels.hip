@@ -1511,6 +1511,11 @@ __global__ void __launch_bounds__(256) k_chol_step(double* A, long ld, int n, in
 // 2 (l & 15), 2 (l & 15) + 1 of column 4 j + (l >> 4) of the run.
 struct Panel { double2 v[8]; };
 
+// the most row blocks one pass of the backward work-group serves: the last
+// block's panel then has (kBackNarrowBlocks - 1) NB = NB * NB / 2 columns,
+// one run of 32 per wave
+constexpr int kBackNarrowBlocks = NB * NB / 2 / NB + 1;
+
 __device__ __forceinline__ void panel_load(const double* lrow, size_t off, Panel& pl, int lane) {
   const double2* p = reinterpret_cast<const double2*>(lrow + off) + lane;
 #pragma unroll
@@ -1608,9 +1613,9 @@ __device__ __forceinline__ void backward_load_m(const double* inv, int bk, doubl
 // block b - 1 are loaded while block b is processed (two register sets).
 // Work-groups 8 h (h >= 1), dispatched to the same XCD as work-group 0, read
 // the panels ahead of it into that XCD's L2 and exit; the rest exit.
-// WIDE: n > 33 NB, some row blocks span more columns than one pass of the
-// work-group covers (16 waves x 32 columns; the runs past the first pass are
-// loaded in place).
+// WIDE: more than kBackNarrowBlocks row blocks, so some row blocks span more
+// columns than one pass of the work-group covers (16 waves x 32 columns; the
+// runs past the first pass are loaded in place).
 template <bool WIDE>
 __device__ __forceinline__ void k_chol_backward_body(const double* lrow, int n, double* y, const double* inv, const int* status, long long* trace) {
   if (status[0] != 0) return;
@@ -2013,7 +2018,7 @@ hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, doubl
     hipLaunchKernelGGL(k_chol_step, dim3(grid), dim3(256), 0, st, K, ldk, n, k, delta, b, y, dinv,
                        dl, lrow, status, trace);
   }
-  if (nbk <= 33)
+  if (nbk <= kBackNarrowBlocks)
     hipLaunchKernelGGL(k_chol_backward<false>, dim3(64), dim3(NB * NB),
                        (size_t)nbk * NB * sizeof(double), st, (const double*)lrow, n, y,
                        (const double*)dinv, (const int*)status, trace ? trace + 8 * nbk : nullptr);
@@ -2083,7 +2088,7 @@ hipError_t launch_batch_solve(const DevNet* nets, const BatchArg* args, const Ba
       }
     hipLaunchKernelGGL(k_chol_step_b, dim3(grid, 1, B), dim3(256), 0, st, args, k);
   }
-  if (max_nbk <= 33)
+  if (max_nbk <= kBackNarrowBlocks)
     hipLaunchKernelGGL(k_chol_backward_b<false>, dim3(1, 1, B), dim3(NB * NB),
                        (size_t)max_nbk * NB * sizeof(double), st, args);
   else

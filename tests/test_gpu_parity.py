@@ -35,6 +35,10 @@ NETS = {
     "syn118": lambda: synthnet.case118(0),
     "syn300": lambda: synthnet.case300(0),
     "syn1354": lambda: synthnet.case1354(0),
+    # 400 generators: nu = 799, 25 blocks of 32, between the one-pass (<= 544)
+    # and the 9241-bus sizes of the backward substitution
+    "syn1354g400": lambda: synthnet.make_network(1354, 1991, 400, seed=0, load_frac=0.6,
+                                                 name="syn1354g400"),
 }
 
 
@@ -86,7 +90,7 @@ def test_condense_matches_oracle(name, seed, refactor):
     assert _rel(_np(rhs), b) <= 1e-8
 
 
-@pytest.mark.parametrize("name", ["syn9", "syn118", "syn1354"])
+@pytest.mark.parametrize("name", ["syn9", "syn118", "syn1354", "syn1354g400"])
 @pytest.mark.parametrize("delta", [0.0, 10.0])
 def test_solve_matches_oracle(name, delta):
     net = NETS[name]()
