@@ -1373,7 +1373,7 @@ void ipm_trial_logic(rh_ipm* p, IpmStep& s, bool* accepted) {
   if (!ok) s.alpha *= 0.5;
 }
 
-rh_status ipm_trial_judge(rh_ipm* p, IpmStep& s, bool* accepted) {
+rh_status ipm_trial_accept(rh_ipm* p, IpmStep& s, bool* accepted) {
   RH_TRY(read_red(p, s.rt, s.ft));
   ipm_trial_logic(p, s, accepted);
   return RH_OK;
@@ -1592,7 +1592,7 @@ rh_status rh_ipm_step(rh_ipm* p, rh_ipm_info* info) {
     if (!ipm_trial_ok(p, s, info)) return s.code;
     RH_TRY(ipm_trial_launch(p, s));
     bool accepted = false;
-    RH_TRY(ipm_trial_judge(p, s, &accepted));
+    RH_TRY(ipm_trial_accept(p, s, &accepted));
     if (accepted) break;
   }
   return ipm_finish(p, s, info);
