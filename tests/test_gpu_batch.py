@@ -63,6 +63,36 @@ def test_batch_matches_single_instance_bitwise():
     B.close()
 
 
+def test_batch_multipass_backward_matches_single_instance():
+    """A batch whose largest member has 25 row blocks (nu = 799) runs the
+    multi-pass backward substitution for every member; each member's step
+    equals its single-instance solve bit for bit (delta_w large enough that
+    every factorisation succeeds)."""
+    api = _api()
+    nets = [synthnet.make_network(1354, 1991, 400, seed=0, load_frac=0.6, name="syn1354g400"),
+            synthnet.case118(0), synthnet.case9(0)]
+    print("batch multi-pass backward: syn1354g400 + syn118 + syn9", flush=True)
+    Gs = [api.Net(n) for n in nets]
+    pts, rs = [], []
+    for i, n in enumerate(nets):
+        M = Model(n)
+        pts.append(random_point(M, 30 + i, sig_range=(10.0, 1e4)))
+        rs.append(residual_vector(M, 40 + i))
+    B = api.Batch(Gs)
+    Kb, rhsb = B.condense([p + (r,) for p, r in zip(pts, rs)])
+    delta = 1e6
+    pb, stb = B.solve([K.clone() for K in Kb], delta, rhsb, rs)
+    torch.cuda.synchronize()
+    assert list(stb) == [0, 0, 0]
+    for i, (G, p, r) in enumerate(zip(Gs, pts, rs)):
+        K, rhs = G.condense_reduced_hessian(*p, r=r)
+        ps, code = G.solve_condensed_kkt(K.clone(), delta, rhs, r)
+        torch.cuda.synchronize()
+        assert code == 0, nets[i].name
+        assert np.array_equal(_np(ps), _np(pb[i])), nets[i].name
+    B.close()
+
+
 def test_batch_matches_oracle_small_instances():
     """The 9- and 118-bus members against the oracle's explicit condensation."""
     api = _api()
