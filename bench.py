@@ -46,7 +46,7 @@ def workload(name):
     if name == "syn118":
         return synthnet.case118(0)
     if name == "syn9":
-        return synthnet.case9(0)
+        return synthnet.case9(1)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -460,6 +460,116 @@ def cpu_baseline(net, args_np, seconds):
                       f"{el:.1f} s)"}
 
 
+def workload_name(net, key):
+    if key == "syn1354":
+        return (f"{net.name}: seeded synthetic 1354-bus stand-in for 1354pegase (nb {net.nb}, "
+                f"nl {net.nl}, ng {net.ng}; transmission-like line data x ~ U[0.005, 0.05], "
+                f"r = x U[0.1, 0.3], b ~ U[0, 0.1], rate ~ U[2, 8], loads Pd ~ U[0.05, 0.5] "
+                f"on 60% of buses)")
+    if key == "syn9241":
+        return (f"{net.name}: seeded synthetic 9241-bus stand-in for 9241pegase (nb {net.nb}, "
+                f"nl {net.nl}, ng {net.ng}; line data as syn1354, loads on 70% of buses)")
+    return net.name
+
+
+def single_instance(api, torch, net, steps, warmup, width=0, lds=1, key="syn1354"):
+    """One instance, one step = eval + refactor + condense (nu + 1 columns) +
+    symmetrize + Cholesky + solve + recovery on a seeded iterate; timed over
+    `steps` steps after `warmup`, with per-phase HIP events on the library's
+    stream and a per-step spread; the condensation kernel's roofline."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    G = api.Net(net, panel_width=width, lds_panel=lds)
+    args_np = iterate(G, net)
+    T = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=dev)
+    x, u, lam, y, sx, su, ss, r = map(T, args_np)
+    nu = G.nu
+    K = torch.empty((nu, nu), dtype=torch.float64, device=dev)
+    rhs = torch.empty(nu, dtype=torch.float64, device=dev)
+
+    def step(delta):
+        G.condense_reduced_hessian(x, u, lam, y, sx, su, ss, r=r, K=K, rhs=rhs)
+        p, code = G.solve_condensed_kkt(K, delta, rhs, r)
+        return code
+
+    delta = 0.0
+    for _ in range(max(1, warmup)):
+        code = step(delta)
+        while code == 1:        # inertia correction as in an IPM iteration
+            delta = 1e-4 if delta == 0.0 else delta * 8.0
+            code = step(delta)
+        if code != 0:
+            raise SystemExit(f"solve failed with status {code}")
+    torch.cuda.synchronize()
+    G.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(delta)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phases = G.profile_read()
+    G.profile_enable(False)
+    # per-step spread: the same step timed one at a time with events on the
+    # library's stream (outside the timed region above)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(max(steps, 10))]
+    for a, b in evs:
+        a.record(G.stream)
+        step(delta)
+        b.record(G.stream)
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    spread = {"p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
+              "p90": float(np.percentile(per, 90))}
+    cond_ms, cond_calls = phases["condense"]
+    kern_s = cond_ms / 1e3 / max(1, cond_calls)
+    ncols = nu + 1
+    alg_bytes, per_col = algorithmic_bytes(G.info, ncols)
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = measured_traffic() if key == "syn1354" else None
+    return {
+        "_net": G, "_args": args_np,
+        "value": steps / el,
+        "ms_per_step": 1e3 * el / steps,
+        "config": {"workload": workload_name(net, key),
+                   "nx": G.nx, "nu": nu, "m": G.m,
+                   "step": "eval + refactor + condense (nu+1 columns) + symmetrize + "
+                           "Cholesky + solve + recovery",
+                   "panel_width": G.info["panel_width"], "lds_panel": G.info["lds_panel"],
+                   "levels": G.info["levels_lower"], "nnz_lu": G.info["nnz_lu"],
+                   "delta_w": delta},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_condense", "kernel_avg_us": kern_s * 1e6,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "bytes_per_column": per_col, "columns_per_launch": ncols},
+        "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
+        "step_ms_spread": spread,
+        "condensation_only_per_s": 1e3 / sum(phases[k][0] / steps
+                                              for k in ("eval", "refactor", "condense",
+                                                        "symmetrize")),
+        "other_stages": other_stages(G.info, phases, steps),
+    }
+
+
+def large_block(api, torch, steps, warmup):
+    """The 9241-bus stand-in (nx 17036, nu 2889): one instance, the same step;
+    condensations per second, the condensation kernel's HBM roofline and the
+    dense Cholesky's FP64-MFMA roofline at n = 2889."""
+    import synthnet
+    net = synthnet.case9241(0)
+    one = single_instance(api, torch, net, steps, warmup, key="syn9241")
+    G = one.pop("_net")
+    one.pop("_args")
+    G.close()
+    out = {"value": one["value"], "unit": "condensations/s",
+           "ms_per_step": one["ms_per_step"], "steps": steps, "warmup": warmup}
+    out.update({k: v for k, v in one.items() if k not in ("value", "ms_per_step")})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,6 +583,9 @@ def main():
     ap.add_argument("--no-ipm", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 9241-bus block")
+    ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--ipm-iters", type=int, default=150)
@@ -501,90 +614,28 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    G = api.Net(net, panel_width=args.width, lds_panel=args.lds)
-    args_np = iterate(G, net)
-    T = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=dev)
-    x, u, lam, y, sx, su, ss, r = map(T, args_np)
-    nu = G.nu
-    K = torch.empty((nu, nu), dtype=torch.float64, device=dev)
-    rhs = torch.empty(nu, dtype=torch.float64, device=dev)
-
-    def step(delta):
-        G.condense_reduced_hessian(x, u, lam, y, sx, su, ss, r=r, K=K, rhs=rhs)
-        p, code = G.solve_condensed_kkt(K, delta, rhs, r)
-        return code
-
-    delta = 0.0
-    for _ in range(max(1, args.warmup)):
-        code = step(delta)
-        while code == 1:        # inertia correction as in an IPM iteration
-            delta = 1e-4 if delta == 0.0 else delta * 8.0
-            code = step(delta)
-        if code != 0:
-            raise SystemExit(f"solve failed with status {code}")
-    torch.cuda.synchronize()
-    G.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(delta)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    phases = G.profile_read()
-    G.profile_enable(False)
-    # per-step spread: the same step timed one at a time with events on the
-    # library's stream (outside the timed region above)
-    import numpy as np
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(G.stream)
-        step(delta)
-        b.record(G.stream)
-    torch.cuda.synchronize()
-    per = np.array([a.elapsed_time(b) for a, b in evs])
-    spread = {"p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
-              "p90": float(np.percentile(per, 90))}
-
-    ms_step = 1e3 * el / args.steps
-    cond_ms, cond_calls = phases["condense"]
-    kern_s = cond_ms / 1e3 / max(1, cond_calls)
-    ncols = nu + 1
-    alg_bytes, per_col = algorithmic_bytes(G.info, ncols)
-    achieved = alg_bytes / kern_s / 1e9
-    traffic = measured_traffic()
+    one = single_instance(api, torch, net, args.steps, args.warmup, args.width, args.lds,
+                          key=args.workload)
+    G, args_np = one.pop("_net"), one.pop("_args")
     line = {
         "metric": METRIC,
-        "value": args.steps / el,
+        "value": one["value"],
         "unit": "condensations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": one["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{net.name}: seeded synthetic 1354-bus stand-in for "
-                               f"1354pegase (nb {net.nb}, nl {net.nl}, ng {net.ng})"
-                               if args.workload == "syn1354" else net.name,
-                   "nx": G.nx, "nu": nu, "m": G.m,
-                   "step": "eval + refactor + condense (nu+1 columns) + symmetrize + "
-                           "Cholesky + solve + recovery",
-                   "panel_width": G.info["panel_width"], "lds_panel": G.info["lds_panel"],
-                   "levels": G.info["levels_lower"], "nnz_lu": G.info["nnz_lu"],
-                   "delta_w": delta},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": "k_condense", "kernel_avg_us": kern_s * 1e6,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "bytes_per_column": per_col, "columns_per_launch": ncols},
-        "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
-        "step_ms_spread": spread,
-        "condensation_only_per_s": 1e3 / sum(phases[k][0] / args.steps
-                                              for k in ("eval", "refactor", "condense",
-                                                        "symmetrize")),
-        "other_stages": other_stages(G.info, phases, args.steps),
-        "paper_context": PAPER_CONTEXT,
+        "config": one["config"],
+        "roofline": one["roofline"],
     }
+    line.update({k: v for k, v in one.items() if k not in line and k != "value"})
+    line["paper_context"] = PAPER_CONTEXT
+    x, u, lam, y, sx, su, ss, r = (torch.as_tensor(np.asarray(a, np.float64), device=dev)
+                                   for a in args_np)
     _progress("single-instance steps done")
+    if not args.no_large:
+        line["syn9241"] = large_block(api, torch, args.large_steps, 2)
+        _progress("syn9241 done")
     if not args.no_ipm:
         line["ipm"] = ipm_run(api, net, torch, args.ipm_iters)
         _progress("ipm done")

@@ -25,9 +25,10 @@ The barrier terms of eq. kktmatrix:normal generalise to two-sided bounds:
 Sigma = zl / (w - wl) + zu / (wu - w) and the residuals carry
 -mu / (w - wl) + mu / (wu - w).
 
-The step is computed here by a dense solve of the augmented system (the
-oracle does not condense); the library computes the same step through the
-condensed matrix.
+The step is computed here by a direct solve of the augmented system (the
+oracle does not condense): a dense LU, or for large networks a sparse LU with
+partial pivoting of the same matrix; the library computes the same step
+through the condensed matrix.
 """
 from __future__ import annotations
 
@@ -67,6 +68,9 @@ class IPMOptions:
     eta_phi: float = 1e-8
     gamma_alpha: float = 0.05
     obj_scale: float = 0.0     # 0: automatic (see above)
+    # "dense": K_aug factored densely; "sparse": the same system by a sparse
+    # LU with partial pivoting (networks whose dense K_aug is too large)
+    linear_solver: str = "dense"
 
 
 @dataclass
@@ -205,7 +209,8 @@ class LinRedIPM:
         g, h, _ = self.evaluate(w, s)
         r = np.concatenate([r_w, r3, g, h + s])          # r1, r2 (= r_w), r3, r4, r5
         B = R.kkt_blocks(self.M, x, u, st.lam, st.y, sig_w[self.nu:], sig_w[:self.nu], sig_s)
-        p = R.solve_augmented(B, r, delta_w=delta)      # [p_u, p_x, p_s, p_lambda, p_y]
+        solve = R.solve_augmented_sparse if self.opt.linear_solver == "sparse" else R.solve_augmented
+        p = solve(B, r, delta_w=delta)                  # [p_u, p_x, p_s, p_lambda, p_y]
         return B, r, p, sig_w, sig_s
 
     def inertia_ok(self, st, sig_w, sig_s, delta):

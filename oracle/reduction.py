@@ -159,6 +159,32 @@ def solve_augmented(blocks, r, delta_w=0.0):
     return [p[o[i]:o[i + 1]] for i in range(5)]
 
 
+def augmented_matrix_sparse(blocks, delta_w=0.0):
+    """K_aug of augmented_matrix as a sparse matrix (same blocks, same order)."""
+    nu, nx, m = blocks["nu"], blocks["nx"], blocks["m"]
+    sig = np.concatenate([blocks["sig_u"] + delta_w, blocks["sig_x"]])
+    W = blocks["W"] + sp.diags(sig)
+    G, A = blocks["G"], blocks["A"]
+    I = sp.identity(m, format="csr")
+    return sp.bmat([[W, None, G.T, A.T],
+                    [None, sp.diags(blocks["sig_s"]), None, I],
+                    [G, None, None, None],
+                    [A, I, None, None]], format="csc")
+
+
+def solve_augmented_sparse(blocks, r, delta_w=0.0):
+    """The step of solve_augmented (K_aug p = -r) by a sparse LU with partial
+    pivoting (SuperLU) instead of a dense one: for networks whose dense K_aug
+    is too large to factor at every iteration."""
+    import scipy.sparse.linalg as spla
+    nu, nx, m = blocks["nu"], blocks["nx"], blocks["m"]
+    lu = spla.splu(augmented_matrix_sparse(blocks, delta_w), permc_spec="COLAMD",
+                   diag_pivot_thresh=1.0)
+    p = lu.solve(-np.asarray(r, float))
+    o = np.cumsum([0, nu, nx, m, nx, m])
+    return [p[o[i]:o[i + 1]] for i in range(5)]
+
+
 def inertia(M, tol=None):
     """(n+, n-, n0) of a symmetric matrix by its eigenvalues."""
     ev = np.linalg.eigvalsh(0.5 * (M + M.T))
@@ -203,3 +229,26 @@ def condensed_rhs_sparse(blocks, r, splu=None):
     d = -splu.solve(r4)
     v = rt + K @ np.concatenate([np.zeros(nu), d])
     return -(v[:nu] - Gu.T @ splu.solve(v[nu:], trans="T")), splu
+
+
+def recover_sparse(blocks, r, pu, splu=None):
+    """recover() with a sparse LU of G_x: p_x = -G_x^{-1}(G_u p_u + r4),
+    p_lambda = -G_x^{-T}(rt_x + (K p)_x), p_s = -r5 - A p,
+    p_y = -r3 - Sigma_s p_s."""
+    import scipy.sparse.linalg as spla
+    nu, nx, m = blocks["nu"], blocks["nx"], blocks["m"]
+    G = blocks["G"].tocsc()
+    Gx, Gu = G[:, nu:].tocsc(), G[:, :nu].tocsc()
+    if splu is None:
+        splu = spla.splu(Gx, permc_spec="COLAMD", diag_pivot_thresh=1.0)
+    r1, r2, r3, r4, r5 = unpack(r, nu, nx, m)
+    A, K, sig_s = blocks["A"], blocks["K"], blocks["sig_s"]
+    pu = np.asarray(pu, float)
+    rt = np.concatenate([r1, r2]) + A.T @ (sig_s * r5 - r3)
+    px = -splu.solve(Gu @ pu + r4)
+    p = np.concatenate([pu, px])
+    Kp = K @ p
+    plam = -splu.solve(rt[nu:] + Kp[nu:], trans="T")
+    ps = -r5 - A @ p
+    py = -r3 - sig_s * ps
+    return pu, px, ps, plam, py

@@ -177,13 +177,23 @@ def output_sensitivity(ipm, w, s, lam, y, sig_w, sig_s):
     return -output_jacobian(ipm, w, s) @ np.linalg.solve(K, load_jacobian(ipm, w, s))
 
 
-def load_gradient(ipm, w, s, lam, y, sig_w, sig_s, dpg, dvm, df):
+def load_gradient(ipm, w, s, lam, y, sig_w, sig_s, dpg, dvm, df, sparse=False):
     """Gradient of L = dpg . Pg + dvm . Vm + df f with respect to (Pd, Qd):
     the adjoint xi = K_aug^{-1} C^T [dpg; dvm; df], then -dF/dp^T xi.
-    Returns (grad_Pd, grad_Qd, xi) with xi in (u, x, s, lambda, y) order."""
-    K = kkt_matrix(ipm, w, s, lam, y, sig_w, sig_s)
+    Returns (grad_Pd, grad_Qd, xi) with xi in (u, x, s, lambda, y) order.
+    sparse: solve with K_aug by a sparse LU (large networks) instead of a
+    dense one."""
     c = output_jacobian(ipm, w, s).T @ np.concatenate([dpg, dvm, [df]])
-    xi = np.linalg.solve(K, c)
+    if sparse:
+        import scipy.sparse.linalg as spla
+        x, u = ipm.split(w)
+        nu = ipm.nu
+        B = R.kkt_blocks(ipm.M, x, u, lam, y, sig_w[nu:], sig_w[:nu], sig_s)
+        lu = spla.splu(R.augmented_matrix_sparse(B), permc_spec="COLAMD",
+                       diag_pivot_thresh=1.0)
+        xi = lu.solve(c)
+    else:
+        xi = np.linalg.solve(kkt_matrix(ipm, w, s, lam, y, sig_w, sig_s), c)
     gp = -load_jacobian(ipm, w, s).T @ xi
     nb = ipm.M.nb
     return gp[:nb], gp[nb:], xi

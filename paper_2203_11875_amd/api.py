@@ -729,6 +729,15 @@ def _make_opf_function():
         def backward(ctx, gpg, gvm, gf):
             layer = ctx.layer
             pdd, qdd = ctx.loads
+            S, dev = layer.count, layer.nets[0].device
+
+            def dense(a, width):
+                # on the caller's stream, before the handles' streams wait for it
+                if a is None:
+                    return None
+                return a.to(device=dev, dtype=torch.float64).reshape(S, width).contiguous()
+
+            gpg, gvm, gf = dense(gpg, layer.ng), dense(gvm, layer.nb), dense(gf, 1)
             layer._fork()
             for i, G in enumerate(layer.nets):
                 G.set_loads(pdd[i], qdd[i])

@@ -38,3 +38,31 @@ def balanced_control(M, vg=1.02):
 
 def residual_vector(M, seed, scale=1.0):
     return synthnet.random_vector(M.nu + 2 * M.nx + 2 * M.m, seed, scale)
+
+
+def kcond_entry_error(Kg, Kc):
+    """Largest entrywise error of K_cond, each entry (i, j) measured against
+    sqrt(|K_ii K_jj|) of the reference (the scale a symmetric matrix's
+    entries are bounded by when it is definite)."""
+    d = np.sqrt(np.abs(np.diag(Kc)))
+    scale = np.outer(d, d)
+    scale = np.where(scale > 0, scale, np.abs(Kc).max())
+    return float((np.abs(np.asarray(Kg) - Kc) / scale).max())
+
+
+STEP_BLOCKS = ("p_u", "p_x", "p_s", "p_lambda", "p_y")
+
+
+def step_block_errors(got, want, nu, nx, m):
+    """Error of each block of a packed step (p_u, p_x, p_s, p_lambda, p_y)
+    relative to that block's own largest entry."""
+    o = np.cumsum([0, nu, nx, m, nx, m])
+    got, want = np.asarray(got), np.asarray(want)
+    out = {}
+    for k, name in enumerate(STEP_BLOCKS):
+        g, w = got[o[k]:o[k + 1]], want[o[k]:o[k + 1]]
+        if w.size == 0:
+            continue
+        ref = np.abs(w).max()
+        out[name] = float(np.abs(g - w).max() / ref) if ref > 0 else float(np.abs(g).max())
+    return out

@@ -9,7 +9,7 @@ import pytest
 import synthnet
 from oracle.model import Model
 from oracle import reduction as R
-from helpers import random_point, residual_vector
+from helpers import random_point, residual_vector, kcond_entry_error
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def _np(t):
 def _batch_nets():
     base = synthnet.case1354(0)
     return [base, synthnet.scale_loads(base, 7), synthnet.case118(0), synthnet.case300(0),
-            synthnet.case9(0)]
+            synthnet.case9(1)]
 
 
 def test_batch_matches_single_instance_bitwise():
@@ -70,7 +70,7 @@ def test_batch_multipass_backward_matches_single_instance():
     every factorisation succeeds)."""
     api = _api()
     nets = [synthnet.make_network(1354, 1991, 400, seed=0, load_frac=0.6, name="syn1354g400"),
-            synthnet.case118(0), synthnet.case9(0)]
+            synthnet.case118(0), synthnet.case9(1)]
     print("batch multi-pass backward: syn1354g400 + syn118 + syn9", flush=True)
     Gs = [api.Net(n) for n in nets]
     pts, rs = [], []
@@ -96,7 +96,7 @@ def test_batch_multipass_backward_matches_single_instance():
 def test_batch_matches_oracle_small_instances():
     """The 9- and 118-bus members against the oracle's explicit condensation."""
     api = _api()
-    nets = [synthnet.case9(0), synthnet.case118(0), synthnet.small(5, 7, 2, seed=1)]
+    nets = [synthnet.case9(1), synthnet.case118(0), synthnet.small(5, 7, 2, seed=1)]
     Gs = [api.Net(n) for n in nets]
     Ms = [Model(n) for n in nets]
     pts = [random_point(M, 3) for M in Ms]
@@ -109,18 +109,21 @@ def test_batch_matches_oracle_small_instances():
         Kref = R.symmetrize(R.condensed_matrix(blocks))
         Kg = _np(K).T
         assert np.linalg.norm(Kg - Kref) <= 1e-8 * np.linalg.norm(Kref)
+        assert kcond_entry_error(Kg, Kref) <= 1e-8
+        b, _, _ = R.condensed_rhs(blocks, r)
+        assert np.abs(_np(rhs) - b).max() <= 1e-8 * np.abs(b).max()
     B.close()
 
 
 def test_batch_rejects_mixed_widths_and_solve_before_condense():
     api = _api()
-    G1 = api.Net(synthnet.case9(0), panel_width=1)
-    G2 = api.Net(synthnet.case9(1), panel_width=2)
+    G1 = api.Net(synthnet.case9(1), panel_width=1)
+    G2 = api.Net(synthnet.case9(3), panel_width=2)
     with pytest.raises(Exception):
         api.Batch([G1, G2])
-    G3 = api.Net(synthnet.case9(2))
+    G3 = api.Net(synthnet.case9(5))
     B = api.Batch([G3])
-    M = Model(synthnet.case9(2))
+    M = Model(synthnet.case9(5))
     r = residual_vector(M, 1)
     with pytest.raises(Exception):
         B.solve([torch.zeros((M.nu, M.nu), dtype=torch.float64, device="cuda")], 0.0,
@@ -133,7 +136,7 @@ def test_batch_graph_replays_match_eager():
     several times with eager work of the same handles in between, gives the
     eager batched results bit for bit on every replay."""
     api = _api()
-    nets = [synthnet.case118(0), synthnet.case9(0), synthnet.case300(0)]
+    nets = [synthnet.case118(0), synthnet.case9(1), synthnet.case300(0)]
     stream = torch.cuda.Stream()
     Gs = [api.Net(n) for n in nets]
     pts = []

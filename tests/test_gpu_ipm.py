@@ -4,6 +4,9 @@ shifts, objective) and the same final point. The oracle solves the augmented
 KKT system densely, the library through the condensed matrix, so the steps
 agree to rounding; the tolerances below (1e-6 relative on iterates, exact on
 the discrete decisions) leave room for that."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -28,8 +31,8 @@ def _api():
 
 
 NETS = {
-    "syn9-0": lambda: synthnet.case9(0),
     "syn9-1": lambda: synthnet.case9(1),
+    "syn9-3": lambda: synthnet.case9(3),
     "syn5": lambda: synthnet.small(5, 7, 2, seed=1),
     "syn118": lambda: synthnet.case118(0),
 }
@@ -87,17 +90,28 @@ def test_objective_scale_scales_f():
     G.close()
 
 
-def test_ipm_1354_reaches_a_kkt_point():
-    """The 1354-bus stand-in solved to 1e-6 on the GPU; the final point is
+def test_ipm_1354_matches_oracle():
+    """The 1354-bus stand-in solved to 1e-6 on the GPU against the oracle's
+    run of the same method from the same start (tests/golden/ipm_syn1354.json,
+    written by the oracle alone): same iteration count, optimal objective
+    within 1e-6 relative, optimal control within 1e-6; the final point is also
     checked with the oracle's model (feasibility and bounds)."""
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                       "golden", "ipm_syn1354.json")))["tol_1e-6"]
     net = synthnet.case1354(0)
     api = _api()
     G = api.Net(net)
+    print("ipm syn1354 to 1e-6", flush=True)
     ipm = api.Ipm(G, tol=1e-6, max_iter=150)
     code, info = ipm.solve()
     assert code == 0 and info["converged"] == 1, info
+    assert info["iter"] == gold["iterations"], (info["iter"], gold["iterations"])
+    assert abs(info["obj"] - gold["objective"]) <= 1e-6 * abs(gold["objective"])
+    assert abs(info["obj_scale"] - gold["obj_scale"]) <= 1e-12 * gold["obj_scale"]
     s = ipm.state()
     x, u = s["x"].cpu().numpy(), s["u"].cpu().numpy()
+    uo = np.asarray(gold["u"])
+    assert np.abs(u - uo).max() <= 1e-6 * max(1.0, np.abs(uo).max())
     M = Model(net)
     g, h, f = M.functions(x, u)
     hl, hu = M.h_bounds()

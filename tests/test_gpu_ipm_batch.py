@@ -23,7 +23,7 @@ def _api():
 
 
 def _nets():
-    base = synthnet.case9(0)
+    base = synthnet.case9(1)
     return [base, synthnet.scale_loads(base, 1), synthnet.case118(0),
             synthnet.scale_loads(synthnet.case118(0), 2)]
 

@@ -3,8 +3,12 @@
 differentiation (oracle.sensitivity) at the oracle's own optimum, both solved
 from the same start by the same method to 1e-8. The two optima agree to the
 solver tolerance, so the gradients are compared at 1e-5 of their largest
-entry; at the 1354-bus size the objective gradient is checked against the
-envelope theorem (multipliers of the GPU's own solution)."""
+entry; at the 1354-bus size the oracle's results come from a golden file that
+the oracle alone writes, and the objective gradient is also checked against
+the envelope theorem (multipliers of the GPU's own solution)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -29,7 +33,7 @@ def _api():
 
 
 NETS = {
-    "syn9-0": lambda: synthnet.case9(0),
+    "syn9-1": lambda: synthnet.case9(1),
     "syn5": lambda: synthnet.small(5, 7, 2, seed=1),
     "syn118": lambda: synthnet.case118(0),
 }
@@ -76,7 +80,7 @@ def test_layer_gradient_matches_oracle(name):
 
 
 def test_adjoint_vector_matches_oracle():
-    net = NETS["syn9-0"]()
+    net = NETS["syn9-1"]()
     dpg, dvm, df = _weights(net, 2)
     _, _, oxi = _oracle(net, dpg, dvm, df)
     api = _api()
@@ -93,7 +97,7 @@ def test_adjoint_vector_matches_oracle():
 
 def test_backward_needs_a_converged_solver():
     api = _api()
-    G = api.Net(synthnet.case9(0))
+    G = api.Net(synthnet.case9(1))
     ipm = api.Ipm(G, tol=1e-8)
     with pytest.raises(api.RhError) as e:
         ipm.backward(None, None, 1.0)
@@ -103,7 +107,7 @@ def test_backward_needs_a_converged_solver():
 def test_two_scenarios_forward_then_backward():
     """Each forward call keeps its own solver; the backward passes in reverse
     order reproduce single-scenario results bit for bit."""
-    net = synthnet.case9(0)
+    net = synthnet.case9(1)
     api = _api()
     dev = torch.device("cuda", torch.cuda.current_device())
     scen = [(net.pd * s, net.qd * s) for s in (1.0, 0.9)]
@@ -130,6 +134,38 @@ def test_two_scenarios_forward_then_backward():
         np.testing.assert_array_equal(pd.grad.cpu().numpy(), single[k][0])
         np.testing.assert_array_equal(qd.grad.cpu().numpy(), single[k][1])
     assert np.abs(single[0][0] - single[1][0]).max() > 1e-6
+
+
+def test_layer_gradient_1354_matches_oracle():
+    """The 1354-bus stand-in (the differentiated-OPF workload): outputs and the
+    load gradient of a random weighting of (Pg, Vm, f) against the oracle's
+    implicit differentiation at its own optimum (both solved from the flat
+    start to 1e-8 by the same method; tests/golden/ipm_syn1354.json, written
+    by the oracle alone), at 1e-5 of the gradient's largest entry."""
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                       "golden", "ipm_syn1354.json")))["tol_1e-8"]
+    net = synthnet.case1354(0)
+    rng = np.random.default_rng(11)
+    dpg, dvm, df = rng.standard_normal(net.ng), rng.standard_normal(net.nb), 1e-3
+    api = _api()
+    print("opf layer vs oracle: syn1354", flush=True)
+    layer = api.OPFLayer(net, tol=1e-8)
+    dev = layer.net.device
+    pd = torch.tensor(net.pd, dtype=torch.float64, device=dev, requires_grad=True)
+    qd = torch.tensor(net.qd, dtype=torch.float64, device=dev, requires_grad=True)
+    pg, vm, f = layer(pd, qd)
+    np.testing.assert_allclose(pg.detach().cpu().numpy(), gold["pg"], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(vm.detach().cpu().numpy(), gold["vm"], rtol=0, atol=1e-6)
+    assert abs(f.item() - gold["f"]) <= 1e-6 * abs(gold["f"])
+    L = (pg * torch.tensor(dpg, device=dev)).sum() + (vm * torch.tensor(dvm, device=dev)).sum() \
+        + df * f
+    L.backward()
+    gpd, gqd = pd.grad.cpu().numpy(), qd.grad.cpu().numpy()
+    ogpd, ogqd = np.asarray(gold["grad_pd"]), np.asarray(gold["grad_qd"])
+    scale = max(np.abs(ogpd).max(), np.abs(ogqd).max())
+    assert scale > 1.0
+    assert np.abs(gpd - ogpd).max() <= 1e-5 * scale, np.abs(gpd - ogpd).max() / scale
+    assert np.abs(gqd - ogqd).max() <= 1e-5 * scale, np.abs(gqd - ogqd).max() / scale
 
 
 def test_objective_gradient_is_envelope_1354():
@@ -192,10 +228,33 @@ def test_batch_layer_equals_single_layer():
     assert not torch.equal(pd.grad[0], pd.grad[1])
 
 
+def test_batch_layer_with_broadcast_gradients():
+    """A loss whose output gradients are expanded (stride-0) tensors,
+    pg.sum() + f.sum(): the batched backward converts them on the caller's
+    stream before the solvers' streams start, and gives the single-scenario
+    gradients bit for bit."""
+    api = _api()
+    base = synthnet.case118(0)
+    scen = [synthnet.scale_loads(base, s) for s in (4, 5)]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    pd = torch.tensor(np.stack([n.pd for n in scen]), device=dev, requires_grad=True)
+    qd = torch.tensor(np.stack([n.qd for n in scen]), device=dev, requires_grad=True)
+    blayer = api.OPFBatchLayer(base, 2, tol=1e-8)
+    pg, vm, f = blayer(pd, qd)
+    (pg.sum() + f.sum()).backward()
+    for i in range(2):
+        layer = api.OPFLayer(base, tol=1e-8)
+        pdi = pd.detach()[i].clone().requires_grad_(True)
+        qdi = qd.detach()[i].clone().requires_grad_(True)
+        pgi, _, fi = layer(pdi, qdi)
+        (pgi.sum() + fi).backward()
+        assert torch.equal(pdi.grad, pd.grad[i]) and torch.equal(qdi.grad, qd.grad[i])
+
+
 def test_layer_accepts_host_loads():
     """Loads given as CPU tensors get their gradients on the CPU."""
     api = _api()
-    net = synthnet.case9(0)
+    net = synthnet.case9(1)
     layer = api.OPFLayer(net, tol=1e-8)
     pd = torch.tensor(net.pd, dtype=torch.float64, requires_grad=True)
     qd = torch.tensor(net.qd, dtype=torch.float64, requires_grad=True)

@@ -1,17 +1,27 @@
 """Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
 
-Tolerances: g, h, f 1e-12 relative; K_cond and the condensed right-hand side
-1e-8 relative in the Frobenius / max norm (the accuracy target of the method's
-FP64 condensation); the step 1e-8 relative to its largest entry. The GPU path
-sums in a fixed order, so repeated calls and different panel widths must agree
-bitwise."""
+Tolerances: g, h, f 1e-12 relative; K_cond entry by entry, each entry (i, j)
+within 1e-8 of sqrt(|K_ii K_jj|) (the accuracy target of the method's FP64
+condensation, applied to every entry, so a wrong weak row or column fails),
+and in the Frobenius norm; the condensed right-hand side 1e-8 of its largest
+entry; every block of the step (p_u, p_x, p_s, p_lambda, p_y) within 1e-8 of
+that block's own largest entry; the Cholesky factor row by row, each entry of
+row i within 1e-8 of sqrt(K_ii) (which bounds every entry of that row of L).
+At the interior-point method's own iterates, where K_cond is ill-conditioned,
+the step is checked by its backward error in the oracle's augmented system.
+The GPU path sums in a fixed order, so repeated calls and different panel
+widths must agree bitwise."""
+import os
+
 import numpy as np
 import pytest
 
 import synthnet
 from oracle.model import Model
 from oracle import reduction as R, cholesky as OC
-from helpers import random_point, residual_vector
+from helpers import (random_point, residual_vector, kcond_entry_error, step_block_errors)
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +40,7 @@ def _net_api():
 
 
 NETS = {
-    "syn9": lambda: synthnet.case9(0),
+    "syn9": lambda: synthnet.case9(1),
     "syn5": lambda: synthnet.small(5, 7, 2, seed=1),
     "syn118": lambda: synthnet.case118(0),
     "syn300": lambda: synthnet.case300(0),
@@ -52,6 +62,25 @@ def _np(t):
 
 def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _linf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _factor_row_error(Lg, Kd):
+    """Entries of row i of the Cholesky factor against sqrt(K_ii): the row's
+    squares sum to K_ii, so that bounds every entry of the row."""
+    Lo = np.linalg.cholesky(Kd)
+    d = np.sqrt(np.abs(np.diag(Kd)))
+    return float((np.abs(Lg - Lo) / d[:, None]).max())
+
+
+def _check_step(got, want, nu, nx, m, tol=1e-8):
+    errs = step_block_errors(got, want, nu, nx, m)
+    for name, e in errs.items():
+        assert e <= tol, (name, errs)
+    return errs
 
 
 @pytest.mark.parametrize("name", list(NETS))
@@ -85,9 +114,10 @@ def test_condense_matches_oracle(name, seed, refactor):
     Kc = R.symmetrize(R.condensed_matrix(B, S))
     b, _, _ = R.condensed_rhs(B, r, S, lu)
     Kg = _np(K).T          # column-major nu x nu
+    assert kcond_entry_error(Kg, Kc) <= 1e-8, kcond_entry_error(Kg, Kc)
     assert _rel(Kg, Kc) <= 1e-8, _rel(Kg, Kc)
     assert np.array_equal(Kg, Kg.T)
-    assert _rel(_np(rhs), b) <= 1e-8
+    assert _linf(_np(rhs), b) <= 1e-8
 
 
 @pytest.mark.parametrize("name", ["syn9", "syn118", "syn1354", "syn1354g400"])
@@ -112,12 +142,11 @@ def test_solve_matches_oracle(name, delta):
     assert code == 0
     pu = np.linalg.solve(Kc, b)
     want = np.concatenate(R.recover(B, r, pu, S, lu))
-    got = _np(p)
-    assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+    _check_step(_np(p), want, M.nu, M.nx, M.m)
     # the lower triangle of K now holds the Cholesky factor of K_cond + delta I
     Lg = np.tril(_np(K).T)
-    Lo = np.linalg.cholesky(Kc)
-    assert _rel(Lg, Lo) <= 1e-8
+    assert _factor_row_error(Lg, Kc) <= 1e-8
+    assert _rel(Lg, np.linalg.cholesky(Kc)) <= 1e-8
 
 
 def test_cholesky_reports_indefinite():
@@ -192,40 +221,16 @@ def test_solve_after_condensation_without_rhs(name, width):
     b, _, _ = R.condensed_rhs(B, r, S, lu)
     pu = np.linalg.solve(Kc + delta * np.eye(M.nu), b)
     want = np.concatenate(R.recover(B, r, pu, S, lu))
-    assert np.abs(_np(p) - want).max() <= 1e-8 * np.abs(want).max()
-
-
-def test_condense_9241_sampled_columns():
-    """The 9241-bus condensation (nx 17036, nu 2889) in the launch shape the
-    library picks, against the oracle on sampled columns and the full
-    right-hand side (sparse LU of G_x on the host)."""
-    net = synthnet.case9241(0)
-    M = Model(net)
-    print("condense syn9241 (sampled columns)", flush=True)
-    G = _net_api().Net(net)
-    x, u, lam, y, sx, su, ss = random_point(M, 0)
-    r = residual_vector(M, 1)
-    K, rhs = G.condense_reduced_hessian(*map(_t, (x, u, lam, y, sx, su, ss)), r=_t(r))
-    torch.cuda.synchronize()
-    B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
-    cols = [0, 1, 700, 1444, 1445, 2000, M.nu - 1]
-    want, splu = R.condensed_columns_sparse(B, cols)
-    Kg = _np(K).T
-    for k, j in enumerate(cols):
-        # K is symmetrised: compare with the mean of column and row j
-        wj = want[:, k]
-        err = np.linalg.norm(0.5 * (Kg[:, j] + Kg[j, :]) - wj) / np.linalg.norm(wj)
-        assert err <= 1e-8, (j, err)
-        assert np.array_equal(Kg[:, j], Kg[j, :])
-    b, _ = R.condensed_rhs_sparse(B, r, splu)
-    assert _rel(_np(rhs), b) <= 1e-8
+    _check_step(_np(p), want, M.nu, M.nx, M.m)
 
 
 def test_solve_9241_matches_oracle():
-    """The condensed solve at 9241 buses: blocked Cholesky of the 2889 x 2889
-    K_cond + delta I (the wide backward-substitution variant) and the
-    control step, against the oracle's K_cond from sparse-LU columns, factored
-    and solved densely on the host."""
+    """The 9241-bus network (nx 17036, nu 2889) in the launch shape the
+    library picks: every entry of K_cond and the right-hand side against the
+    oracle's sparse-LU columns, then the blocked Cholesky of the
+    2889 x 2889 K_cond + delta I (the wide backward-substitution variant) and
+    every block of the recovered step against the oracle's dense solve of
+    its K_cond and its sparse-LU recovery."""
     net = synthnet.case9241(0)
     M = Model(net)
     print("solve syn9241", flush=True)
@@ -233,17 +238,75 @@ def test_solve_9241_matches_oracle():
     x, u, lam, y, sx, su, ss = random_point(M, 3, lam_scale=1.0, sig_range=(1.0, 1e3))
     r = residual_vector(M, 4)
     K, rhs = G.condense_reduced_hessian(*map(_t, (x, u, lam, y, sx, su, ss)), r=_t(r))
+    Kg = _np(K).T.copy()
     B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
     Kc, splu = R.condensed_columns_sparse(B, range(M.nu))
     Kc = R.symmetrize(Kc)
-    delta = max(0.0, -np.linalg.eigvalsh(Kc).min()) * 1.5 + 1.0
-    Kd = Kc + delta * np.eye(M.nu)
+    print(f"syn9241 K_cond entry error {kcond_entry_error(Kg, Kc):.2e}", flush=True)
+    assert kcond_entry_error(Kg, Kc) <= 1e-8
+    assert np.array_equal(Kg, Kg.T)
     b, _ = R.condensed_rhs_sparse(B, r, splu)
+    assert _linf(_np(rhs), b) <= 1e-8
+    delta = 1.0           # then x10 until K_cond + delta I has a Cholesky factor
+    while OC.try_cholesky(Kc + delta * np.eye(M.nu)) is None:
+        delta *= 10.0
+    Kd = Kc + delta * np.eye(M.nu)
     p, code = G.solve_condensed_kkt(K, delta, rhs, _t(r))
     torch.cuda.synchronize()
     assert code == 0
     pu = np.linalg.solve(Kd, b)
-    got = _np(p)[:M.nu]
-    assert np.abs(got - pu).max() <= 1e-8 * np.abs(pu).max()
+    want = np.concatenate(R.recover_sparse(B, r, pu, splu))
+    errs = _check_step(_np(p), want, M.nu, M.nx, M.m)
+    print(f"syn9241 step block errors {errs}", flush=True)
     Lg = np.tril(_np(K).T)
-    assert _rel(Lg, np.linalg.cholesky(Kd)) <= 1e-8
+    assert _factor_row_error(Lg, Kd) <= 1e-8
+
+
+@pytest.mark.parametrize("tag", ["it0", "it10", "last"])
+def test_condense_and_solve_at_ipm_iterates_1354(tag):
+    """K_cond, the right-hand side and the step at the oracle interior-point
+    method's own iterates on the 1354-bus network (iterations 0, 10 and the
+    last one of a run to 1e-6, where Sigma spans many decades and K_cond is
+    ill-conditioned), with the objective scale and the inertia shift the
+    method used there. K_cond and the right-hand side entry by entry; the
+    step by its backward error in the oracle's augmented system (a stable
+    solve of an ill-conditioned system is only accurate in that sense), and
+    by its forward error relative to the condition number."""
+    z = np.load(os.path.join(GOLD, "iterates_syn1354.npz"))
+    net = synthnet.case1354(0)
+    sig = float(z[f"{tag}_obj_scale"])
+    Ms = Model(net.copy(c2=net.c2 * sig, c1=net.c1 * sig, c0=net.c0 * sig))
+    api = _net_api()
+    G = api.Net(net)
+    assert api.lib().rh_set_objective_scale(G.h, sig) == 0
+    args = [z[f"{tag}_{k}"] for k in ("x", "u", "lam", "y", "sig_x", "sig_u", "sig_s")]
+    r = z[f"{tag}_r"]
+    delta = float(z[f"{tag}_delta_w"])
+    print(f"syn1354 iterate {tag}: delta_w {delta:g}", flush=True)
+    K, rhs = G.condense_reduced_hessian(*map(_t, args), r=_t(r))
+    Kg = _np(K).T.copy()
+    B = R.kkt_blocks(Ms, *args)
+    S, lu = R.sensitivity(B)
+    Kc = R.symmetrize(R.condensed_matrix(B, S))
+    err = kcond_entry_error(Kg, Kc)
+    print(f"  K_cond entry error {err:.2e}, cond {np.linalg.cond(Kc + delta * np.eye(Ms.nu)):.2e}",
+          flush=True)
+    assert err <= 1e-8
+    b, _, _ = R.condensed_rhs(B, r, S, lu)
+    assert _linf(_np(rhs), b) <= 1e-8
+    p, code = G.solve_condensed_kkt(K, delta, rhs, _t(r))
+    torch.cuda.synchronize()
+    assert code == 0
+    got = _np(p)
+    Kaug = R.augmented_matrix_sparse(B, delta)
+    res = np.abs(Kaug @ got + r).max()
+    scale = np.abs(Kaug).max() * np.abs(got).max() + np.abs(r).max()
+    print(f"  step backward error {res / scale:.2e}", flush=True)
+    assert res <= 1e-12 * scale
+    Kd = Kc + delta * np.eye(Ms.nu)
+    want = np.concatenate(R.recover(B, r, np.linalg.solve(Kd, b), S, lu))
+    errs = step_block_errors(got, want, Ms.nu, Ms.nx, Ms.m)
+    print(f"  step block errors {errs}", flush=True)
+    kappa = np.linalg.cond(Kd)
+    for name, e in errs.items():
+        assert e <= max(1e-8, 1e-14 * kappa), (name, e, kappa)

@@ -29,14 +29,14 @@ def _api():
 
 
 NETS = {
-    "syn9-0": lambda: synthnet.case9(0),
     "syn9-1": lambda: synthnet.case9(1),
+    "syn9-3": lambda: synthnet.case9(3),
     "syn5": lambda: synthnet.small(5, 7, 2, seed=1),
     "syn118": lambda: synthnet.case118(0),
 }
 
 
-@pytest.mark.parametrize("name", ["syn9-0", "syn118", "syn1354"])
+@pytest.mark.parametrize("name", ["syn9-1", "syn118", "syn1354"])
 def test_power_flow_matches_oracle(name):
     net = synthnet.case1354(0) if name == "syn1354" else NETS[name]()
     print(f"power flow: {name}", flush=True)
@@ -53,7 +53,7 @@ def test_power_flow_matches_oracle(name):
 
 
 def test_power_flow_reports_failure():
-    net = synthnet.case9(0)
+    net = synthnet.case9(1)
     rl = RedLinIPM(net, IPMOptions())
     x0, u0 = flat_start(rl.M)
     u = u0.copy()

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     assert names == set(_abi.SIGNATURES), "binding and header disagree"
 
 
-NETS = [synthnet.case9(0), synthnet.small(5, 7, 2, seed=1), synthnet.case118(0),
+NETS = [synthnet.case9(1), synthnet.small(5, 7, 2, seed=1), synthnet.case118(0),
         synthnet.case300(0), synthnet.case1354(0)]
 
 
@@ -108,7 +108,7 @@ def test_patterns_cover_oracle_and_host_refactorisation_solves(net, refactor):
 
 def test_rejects_bad_networks():
     api = _lib()
-    net = synthnet.case9(0)
+    net = synthnet.case9(1)
     bad = net.copy(bus_type=np.full(net.nb, 1, np.int32))          # no reference bus
     with pytest.raises(RuntimeError, match="invalid argument"):
         api.Symbolic(bad)

@@ -42,6 +42,31 @@ def test_lossless_line_closed_form():
             assert abs(got - want) < 1e-10
 
 
+def test_generator_cost_closed_form():
+    """The objective f of a 2-bus network with generators at both buses
+    against the cost closed form evaluated by hand (tests/golden/cost_2bus.json):
+    pins the MW cost convention, c0, and the reference generator's output
+    taken from the power balance."""
+    gold = json.load(open(os.path.join(GOLD, "cost_2bus.json")))
+    c = gold["network"]
+    net = synthnet.Network(
+        nb=2, base_mva=100.0, bus_type=np.array([BUS_REF, BUS_PV], np.int32),
+        pd=np.array(c["pd"]), qd=np.array([0.0, 0.1]),
+        vmin=np.full(2, 0.9), vmax=np.full(2, 1.1),
+        f=np.array([0], np.int32), t=np.array([1], np.int32),
+        r=np.array([0.0]), x=np.array([c["X"]]), b=np.array([0.0]), rate=np.array([0.0]),
+        gen_bus=np.array([0, 1], np.int32), c2=np.array(c["c2"]), c1=np.array(c["c1"]),
+        c0=np.array(c["c0"]), pmin=np.zeros(2), pmax=np.full(2, 3.0),
+        qmin=np.full(2, -3.0), qmax=np.full(2, 3.0))
+    M = Model(net)
+    assert M.nx == 1 and M.nu == 3          # theta_1; Vm_0, Vm_1, Pg_1
+    x, u = M.join(np.array([c["theta0"], c["theta1"]]), np.array([c["V0"], c["V1"]]),
+                  np.array([0.0, c["pg1"]]))
+    _, h, f = M.functions(x, u)
+    assert abs(h[0] - gold["pg_ref"]) <= 1e-10           # h_0 = Pg_ref
+    assert abs(float(np.real(f)) - gold["f"]) <= 1e-8 * gold["f"]
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_injections_match_complex_phasors(seed):
     """S_i = V_i conj(sum_k Y_ik V_k) with Y assembled here from r, x, b."""
@@ -110,7 +135,7 @@ def _complex_step_jac(M, x, u, which, lam=None, y=None):
     return np.array(cols).T
 
 
-@pytest.mark.parametrize("name,net", [("syn9", synthnet.case9(0)),
+@pytest.mark.parametrize("name,net", [("syn9", synthnet.case9(1)),
                                       ("syn12", synthnet.small(12, 18, 4, seed=3))])
 def test_first_derivatives_complex_step(name, net):
     M = Model(net)
@@ -124,7 +149,7 @@ def test_first_derivatives_complex_step(name, net):
         assert np.abs(cs - ana).max() <= 1e-12 * scale, which
 
 
-@pytest.mark.parametrize("name,net", [("syn9", synthnet.case9(1)),
+@pytest.mark.parametrize("name,net", [("syn9", synthnet.case9(3)),
                                       ("syn12", synthnet.small(12, 18, 4, seed=4))])
 def test_hessian_complex_step_of_gradient(name, net):
     M = Model(net)
@@ -149,7 +174,7 @@ def test_state_control_dimensions_match_table1():
 
 
 def test_nine_bus_dimensions():
-    M = Model(synthnet.case9(0))
+    M = Model(synthnet.case9(1))
     assert (M.nx, M.nu, M.m) == (14, 5, 4)
 
 

@@ -16,7 +16,7 @@ import test_oracle_reduction as tr
 PINS = [
     lambda: tm.test_lossless_line_closed_form(),
     lambda: tm.test_injections_match_complex_phasors(0),
-    lambda: tm.test_first_derivatives_complex_step("syn9", synthnet.case9(0)),
+    lambda: tm.test_first_derivatives_complex_step("syn9", synthnet.case9(1)),
     lambda: tm.test_hessian_complex_step_of_gradient("syn12", synthnet.small(12, 18, 4, seed=4)),
     lambda: tr.test_kcond_is_inverse_of_kaug_inverse_uu_block("syn12", tr.NETS[2][1], 0),
     lambda: tr.test_condensed_solve_equals_augmented_solve("syn12", tr.NETS[2][1], 0.0),

@@ -22,8 +22,8 @@ from oracle.redlin import RedLinIPM
 from oracle import reduction as R
 
 NETS = {
-    "syn9-0": lambda: synthnet.case9(0),
     "syn9-1": lambda: synthnet.case9(1),
+    "syn9-3": lambda: synthnet.case9(3),
     "syn5": lambda: synthnet.small(5, 7, 2, seed=1),
 }
 
@@ -137,7 +137,7 @@ def test_redlin_answer_is_full_space_kkt_point(name):
 
 
 def test_projection_fails_cleanly():
-    rl = RedLinIPM(synthnet.case9(0), IPMOptions())
+    rl = RedLinIPM(synthnet.case9(1), IPMOptions())
     x0, u0 = flat_start(rl.M)
     u = u0.copy()
     u[rl.M.ng:] *= 60.0          # far more generation than any flow can carry
