@@ -454,10 +454,48 @@ def cpu_baseline(net, args_np, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or done >= 200:
             break
+    # one iteration of the oracle's Algorithm 1 (sparse LU of K_aug) from the
+    # flat start, a few times
+    from oracle.ipm import LinRedIPM, IPMOptions, flat_start
+    o = LinRedIPM(net, IPMOptions(tol=1e-6, linear_solver="sparse"))
+    st = o.initial_state(*flat_start(o.M))
+    t1 = time.perf_counter()
+    its = 0
+    while its < 3 and time.perf_counter() - t1 < seconds:
+        o.iterate(st)
+        its += 1
+    ipm_s = (time.perf_counter() - t1) / its
     return {"value": done / el, "unit": "condensations/s", "cores": int(cores),
             "kind": "oracle",
             "sample": f"{done} full steps of the oracle on {net.name} (numpy/scipy FP64, "
-                      f"{el:.1f} s)"}
+                      f"{el:.1f} s); then {its} iterations of its Algorithm 1",
+            "cpu_model": _cpu_model(), "blas": _blas_info(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "ipm_iters_per_s": 1.0 / ipm_s,
+            "ipm_iteration": "oracle Algorithm 1 from the flat start: model derivatives, "
+                             "inertia test on the dense K_cond, sparse LU solve of K_aug, "
+                             "filter line search"}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _blas_info():
+    try:
+        from threadpoolctl import threadpool_info
+        return [{k: t.get(k) for k in ("internal_api", "version", "threading_layer",
+                                       "num_threads", "architecture")}
+                for t in threadpool_info() if t.get("user_api") == "blas"]
+    except Exception as e:       # threadpoolctl missing or failing: say so
+        return f"unavailable ({type(e).__name__})"
 
 
 def workload_name(net, key):
@@ -522,6 +560,8 @@ def single_instance(api, torch, net, steps, warmup, width=0, lds=1, key="syn1354
     per = np.array([a.elapsed_time(b) for a, b in evs])
     spread = {"p10": float(np.percentile(per, 10)), "p50": float(np.median(per)),
               "p90": float(np.percentile(per, 90))}
+    graph = graph_replay(api, torch, G, (x, u, lam, y, sx, su, ss, r), delta,
+                         reps=max(50, steps))
     cond_ms, cond_calls = phases["condense"]
     kern_s = cond_ms / 1e3 / max(1, cond_calls)
     ncols = nu + 1
@@ -547,11 +587,44 @@ def single_instance(api, torch, net, steps, warmup, width=0, lds=1, key="syn1354
                      "bytes_per_column": per_col, "columns_per_launch": ncols},
         "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
         "step_ms_spread": spread,
+        "graph_replay": graph,
         "condensation_only_per_s": 1e3 / sum(phases[k][0] / steps
                                               for k in ("eval", "refactor", "condense",
                                                         "symmetrize")),
         "other_stages": other_stages(G.info, phases, steps),
     }
+
+
+def graph_replay(api, torch, G, point, delta, reps=50, warmup=5):
+    """The same step (condensation with the right-hand side, Cholesky, solve,
+    recovery) captured once in a HIP graph, as a one-member batch (the
+    batched kernels run the single-instance bodies: same results bit for
+    bit), and replayed: `warmup` replays, then `reps` replays each timed with
+    HIP events on the batch's stream. Milliseconds p10 / p50 / p90 and the
+    rate at the median."""
+    import numpy as np
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    B = api.Batch([G], stream=stream)
+    with torch.cuda.stream(stream):
+        B.capture([point], np.array([delta]))
+        for _ in range(warmup):
+            B.replay()
+        stream.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            B.replay()
+            b.record(stream)
+        stream.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    B.close()
+    p50 = float(np.median(per))
+    return {"replays": reps, "ms_p10": float(np.percentile(per, 10)), "ms_p50": p50,
+            "ms_p90": float(np.percentile(per, 90)), "condensations_per_s_p50": 1e3 / p50,
+            "step": "condensation (nu+1 columns) + symmetrize + Cholesky + solve + recovery "
+                    "as one captured graph (a one-member batch)"}
 
 
 def large_block(api, torch, steps, warmup):

@@ -59,7 +59,8 @@ typedef enum {
   RH_NOT_POSDEF = 1,      /* Cholesky met a non-positive pivot: K_cond + delta_w I
                              is not positive definite (wrong inertia of K_aug)   */
   RH_SMALL_PIVOT = 2,     /* static-pivot refactorisation of G_x met |u_kk| below
-                             1e-14 * max|G_x|                                      */
+                             1e-14 * max|row|: its factors (and K_cond) are not
+                             used                                                */
   RH_NOT_CONVERGED = 3,
   RH_ERR_ARG = -1,        /* invalid argument (null pointer, bad size, bad data)  */
   RH_ERR_HIP = -2,        /* a HIP runtime call failed                            */
@@ -266,9 +267,9 @@ rh_status rh_condense_reduced_hessian(rh_net* net, const double* x, const double
  * those of its right-hand-side column): r must then be the same residual. Device arrays: K (in: K_cond, out: Cholesky
  * factor in the lower triangle), rhs (nu), r (packed), p (packed step, output).
  * dev_status (device int32[2], may be NULL): [status, index of failing pivot].
- * The call synchronises the stream once and returns RH_NOT_POSDEF when the
- * factorisation fails (p is then undefined) or RH_SMALL_PIVOT if the last
- * refactorisation of G_x met a tiny pivot. */
+ * The call synchronises the stream once and returns RH_SMALL_PIVOT if the last
+ * refactorisation of G_x met a tiny pivot (checked first: K_cond and p are then
+ * unusable), else RH_NOT_POSDEF when the Cholesky fails (p is then undefined). */
 rh_status rh_solve_condensed_kkt(rh_net* net, double* K, int64_t ldk, double delta_w,
                                  const double* rhs, const double* r, double* p,
                                  int32_t* dev_status);
@@ -363,7 +364,9 @@ rh_status rh_ipm_create(rh_net* net, const rh_ipm_options* opts, const double* x
 /* One iteration. If the point already satisfies E_0 <= tol, takes no step and
  * sets info->converged. Returns RH_NOT_CONVERGED when the line search fails,
  * the inertia correction exceeds 1e40 or max_iter iterations were taken;
- * RH_SMALL_PIVOT is not fatal (the step is taken). info (host) may be NULL.
+ * RH_SMALL_PIVOT when the refactorisation of G_x at this iterate met a tiny
+ * static pivot: no step is taken and the iterate is unchanged. info (host)
+ * may be NULL.
  * Synchronises the stream a few times per iteration. */
 rh_status rh_ipm_step(rh_ipm* ipm, rh_ipm_info* info);
 /* Iterates until converged (RH_OK) or a step fails (its code). */
@@ -415,8 +418,8 @@ rh_status rh_ipm_outputs(const rh_ipm* ipm, double* pg, double* vm, double* f);
  * converged solver (RH_ERR_STATE otherwise); the network must hold the loads
  * it was solved with. Sigma is the final iterate's (bound multiplier / bound
  * slack), with no inertia correction: RH_NOT_POSDEF if the condensed matrix
- * is not positive definite there (then no gradient is written).
- * RH_SMALL_PIVOT is not fatal. Overwrites the solver's step buffers (a later
+ * is not positive definite there, RH_SMALL_PIVOT if the refactorisation of
+ * G_x met a tiny static pivot (in both cases no gradient is written). Overwrites the solver's step buffers (a later
  * rh_ipm_step recomputes them). Synchronises the stream. */
 rh_status rh_ipm_backward(rh_ipm* ipm, const double* dpg, const double* dvm, const double* df,
                           double* gpd, double* gqd, double* xi);
@@ -426,8 +429,8 @@ rh_status rh_ipm_backward(rh_ipm* ipm, const double* dpg, const double* dvm, con
  * sides and the solve are one batched launch each. Host arrays of count
  * device pointers: dpg, dvm, df (the arrays or their entries may be NULL:
  * zero weights), gpd, gqd (outputs, nb entries each). codes[count] (host,
- * optional): each solver's status as rh_ipm_backward's (RH_NOT_POSDEF: no
- * gradient written for it). The gradients equal rh_ipm_backward's bit for
+ * optional): each solver's status as rh_ipm_backward's (RH_NOT_POSDEF or
+ * RH_SMALL_PIVOT: no gradient written for it). The gradients equal rh_ipm_backward's bit for
  * bit. Returns RH_OK, RH_ERR_STATE if a solver has not converged, or another
  * negative code on a hard error. Synchronises the batch's stream. */
 rh_status rh_ipm_batch_backward(rh_batch* batch, rh_ipm* const* ipms, const double* const* dpg,

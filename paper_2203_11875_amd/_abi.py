@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librhipm.so")
+# RHIPM_LIB selects another build of the library (the host-sanitised one)
+LIB_PATH = os.environ.get("RHIPM_LIB") or os.path.join(HERE, "librhipm.so")
 
 RH_OK, RH_NOT_POSDEF, RH_SMALL_PIVOT, RH_NOT_CONVERGED = 0, 1, 2, 3
 RH_ERR_ARG, RH_ERR_HIP, RH_ERR_OOM, RH_ERR_SINGULAR, RH_ERR_STATE = -1, -2, -3, -4, -5

@@ -486,8 +486,7 @@ class Ipm:
               if want_xi else None)
         code = lib().rh_ipm_backward(self.h, _ptr(a), _ptr(b), _ptr(c), _ptr(gpd), _ptr(gqd),
                                      _ptr(xi))
-        if code not in (_abi.RH_OK, _abi.RH_SMALL_PIVOT):
-            _check(code, "rh_ipm_backward")
+        _check(code, "rh_ipm_backward")
         return (gpd, gqd, xi) if want_xi else (gpd, gqd)
 
 
@@ -743,8 +742,7 @@ def _make_opf_function():
                 G.set_loads(pdd[i], qdd[i])
             gp, gq, codes = ctx.ib.backward(gpg, gvm, gf)
             for c in codes:
-                if c not in (_abi.RH_OK, _abi.RH_SMALL_PIVOT):
-                    _check(c, "rh_ipm_batch_backward")
+                _check(c, "rh_ipm_batch_backward")
             layer._join()
             return (gp.reshape(ctx.shapes[0]).to(ctx.devices[0]),
                     gq.reshape(ctx.shapes[1]).to(ctx.devices[1]), None)

@@ -1050,6 +1050,13 @@ rh_status host_refactor(const Symbolic& s, const double* gxv, std::vector<double
   std::vector<double>& lu = lu_out;
   lu.assign(s.lu_col.size(), 0.0);
   for (size_t p = 0; p < s.gx_col.size(); ++p) lu[s.gx_lu[p]] = gxv[p];
+  // the device's static-pivot test: a pivot is too small when it is not
+  // above 1e-14 times the largest entry of its row of G_x
+  std::vector<double> rowmax(nx, 0.0);
+  for (int i = 0; i < nx; ++i)
+    for (int p = s.lu_ptr[i]; p < s.lu_ptr[i + 1]; ++p)
+      rowmax[i] = std::max(rowmax[i], std::fabs(lu[p]));
+  auto tiny = [&](int i, double piv) { return !(std::fabs(piv) > 1e-14 * rowmax[i]); };
   if (s.rw_ok) {
     // the wave-resident schedule, lane by lane as the device runs it
     std::vector<double> ulds(size_t(s.rw_nnz_u) + 1, 0.0), rinv(nx, 0.0);
@@ -1058,7 +1065,7 @@ rh_status host_refactor(const Symbolic& s, const double* gxv, std::vector<double
       const int i = s.sl.rows[q];
       for (int p = s.lu_diag[i] + 1; p < s.lu_ptr[i + 1]; ++p)
         ulds[s.rw_ustart[i] + (p - s.lu_diag[i] - 1)] = lu[p];
-      if (lu[s.lu_diag[i]] == 0.0) return RH_SMALL_PIVOT;
+      if (tiny(i, lu[s.lu_diag[i]])) return RH_SMALL_PIVOT;
       rinv[i] = 1.0 / lu[s.lu_diag[i]];
     }
     for (int lv = 0; lv < nlev; ++lv)
@@ -1068,7 +1075,7 @@ rh_status host_refactor(const Symbolic& s, const double* gxv, std::vector<double
         for (int k = k0; k < k1; ++k) {
           const int* R = &s.rw_rec[size_t(s.rw_wbeg[w] + k) * kRwRec];
           const int nsteps = R[1], wide = R[2];
-          double acc[64], r[64], amax[64];
+          double acc[64], r[64];
           int ipos[64], pos[64], udst[64], drow[64];
           for (int ln = 0; ln < 64; ++ln) {
             const int seg = wide ? 0 : ln >> 4, p = wide ? ln : ln & 15;
@@ -1079,7 +1086,6 @@ rh_status host_refactor(const Symbolic& s, const double* gxv, std::vector<double
             udst[ln] = p > nl && p < len ? R[16 + seg] + (p - nl - 1) : -1;
             drow[ln] = p == nl && p < len ? R[20 + seg] : -1;
             pos[ln] = p < nl ? p : -1;
-            amax[ln] = std::fabs(acc[ln]);
           }
           for (int q = 0; q < nsteps; ++q) {
             double t[64];
@@ -1096,11 +1102,10 @@ rh_status host_refactor(const Symbolic& s, const double* gxv, std::vector<double
             if (ipos[ln] >= 0) lu[ipos[ln]] = acc[ln];
             if (udst[ln] >= 0) ulds[udst[ln]] = acc[ln];
             if (drow[ln] >= 0) {
-              if (acc[ln] == 0.0) return RH_SMALL_PIVOT;
+              if (tiny(drow[ln], acc[ln])) return RH_SMALL_PIVOT;
               rinv[drow[ln]] = 1.0 / acc[ln];
             }
           }
-          (void)amax;
         }
       }
   } else
@@ -1117,7 +1122,7 @@ rh_status host_refactor(const Symbolic& s, const double* gxv, std::vector<double
       }
     }
   for (int i = 0; i < nx; ++i)
-    if (lu[s.lu_diag[i]] == 0.0) return RH_SMALL_PIVOT;
+    if (tiny(i, lu[s.lu_diag[i]])) return RH_SMALL_PIVOT;
   return RH_OK;
 }
 

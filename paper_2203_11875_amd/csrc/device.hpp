@@ -170,6 +170,11 @@ hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
 hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
                                  double* y, double* dinv, double* lrow, int* status,
                                  hipStream_t st, long long* trace = nullptr);
+// Doubles of the Cholesky workspaces of order n (dinv and lrow above).
+constexpr size_t chol_inv_doubles(int n) { return 2 * size_t((n + 31) / 32) * 32 * 32; }
+constexpr size_t chol_lrow_doubles(int n) {
+  return size_t((n + 31) / 32) * 32 * size_t((n + 31) / 32) * 32;
+}
 hipError_t launch_eval_objective(const DevNet& d, const double* u, double* f, hipStream_t st);
 int max_lds_bytes();
 // LDS one row of the refactorisation stages (row, U sources, pivots, schedule).

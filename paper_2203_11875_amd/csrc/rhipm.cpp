@@ -409,8 +409,8 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   }
   RH_TRY(alloc(n, s.m, &n->sig_s));
   RH_TRY(alloc(n, s.nu, &n->bwork));
-  RH_TRY(alloc(n, 2 * size_t((s.nu + 31) / 32) * 32 * 32, &n->cinv));
-  RH_TRY(alloc(n, size_t((s.nu + 31) / 32 * 32) * size_t((s.nu + 31) / 32 * 32), &n->lrow));
+  RH_TRY(alloc(n, rh::chol_inv_doubles(s.nu), &n->cinv));
+  RH_TRY(alloc(n, rh::chol_lrow_doubles(s.nu), &n->lrow));
   RH_TRY(alloc(n, 8, &n->status));
   RH_TRY(alloc(n, 256, &n->trace));
   RH_HIP(hipMemset(n->trace, 0, 256 * sizeof(long long)));
@@ -762,8 +762,8 @@ rh_status batch_statuses(rh_batch* b, int32_t* status) {
   for (size_t i = 0; i < b->nets.size(); ++i) {
     rh_status si = RH_OK;
     if (hs[5 * i + 4] != 0) si = RH_ERR_STATE;
-    else if (hs[5 * i] != 0) si = RH_NOT_POSDEF;
     else if (hs[5 * i + 2] != 0) si = RH_SMALL_PIVOT;
+    else if (hs[5 * i] != 0) si = RH_NOT_POSDEF;
     if (status) status[i] = si;
     if (si != RH_OK && worst == RH_OK) worst = si;
   }
@@ -968,8 +968,10 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   RH_HIP(hipMemcpyAsync(hs, n->status, sizeof(hs), hipMemcpyDeviceToHost, st));
   RH_HIP(hipStreamSynchronize(st));
   if (hs[4] != 0) return RH_ERR_STATE;   // condensation panels not at LDS address 0
-  if (hs[0] != 0) return RH_NOT_POSDEF;
+  // a tiny static pivot makes G_x's factors, hence K_cond, unusable: it is
+  // reported before the Cholesky's outcome
   if (hs[2] != 0) return RH_SMALL_PIVOT;
+  if (hs[0] != 0) return RH_NOT_POSDEF;
   return RH_OK;
 }
 
@@ -1263,6 +1265,15 @@ rh_status ipm_factor(rh_ipm* p, IpmStep& s, rh_ipm_info* info, rh_status code) {
   auto& v = p->v;
   const int nu = v.nu;
   s.delta = 0.0;
+  if (code == RH_SMALL_PIVOT) {
+    // the static pivots of G_x no longer hold at this iterate: no step is
+    // taken from these factors (the iterate is left unchanged)
+    fill_info(p, info, s.f0 / p->sigma_f, std::max(s.red[rh::IR_PRIM_G], s.red[rh::IR_PRIM_H]),
+              s.e0, 0.0, 0.0, 0.0, 0);
+    s.done = true;
+    s.code = RH_SMALL_PIVOT;
+    return RH_OK;
+  }
   if (code == RH_NOT_POSDEF) {
     double delta = p->delta_last == 0.0 ? kDelta0 : std::max(kDeltaMin, kKwMinus * p->delta_last);
     for (;;) {
@@ -1754,7 +1765,7 @@ rh_status rh_ipm_backward(rh_ipm* p, const double* dpg, const double* dvm, const
   RH_HIP(rh::launch_adjoint_rhs(d, v, 1.0 / p->sigma_f, dpg, dvm, df, v.r, st));
   RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
   const rh_status code = rh_solve_condensed_kkt(n, p->K, nu, 0.0, p->rhs, v.r, v.p, nullptr);
-  if (code != RH_OK && code != RH_SMALL_PIVOT) return code;
+  if (code != RH_OK) return code;     // no gradient from unusable factors
   RH_HIP(rh::launch_adjoint_grad(d, v, v.p, gpd, gqd, st));
   if (xi) {
     const size_t np = size_t(nu) + 2 * size_t(v.nx) + 2 * size_t(v.m);
@@ -1808,7 +1819,7 @@ rh_status rh_ipm_batch_backward(rh_batch* b, rh_ipm* const* ipms, const double* 
   const rh_status bs = rh_batch_solve(b, si.data(), stt.data());
   if (bs < 0 && bs != RH_ERR_STATE) return bs;
   for (size_t i = 0; i < cnt; ++i) {
-    if (stt[i] != RH_OK && stt[i] != RH_SMALL_PIVOT) continue;
+    if (stt[i] != RH_OK) continue;     // no gradient from unusable factors
     rh_ipm* p = ipms[i];
     RH_HIP(rh::launch_adjoint_grad(p->net->d, p->v, p->v.p, gpd[i], gqd[i], st));
   }

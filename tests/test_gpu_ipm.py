@@ -120,3 +120,42 @@ def test_ipm_1354_matches_oracle():
     assert float(f) == pytest.approx(info["obj"], rel=1e-9)
     ipm.close()
     G.close()
+
+
+def test_tiny_static_pivot_stops_the_step():
+    """At a point where the static pivots of G_x fail (a lossless line
+    carrying a 90-degree angle difference; the matrix itself is nonsingular,
+    see test_host_symbolic.py), the solve reports RH_SMALL_PIVOT ahead of the
+    Cholesky's outcome, and rh_ipm_step returns RH_SMALL_PIVOT without moving
+    the iterate."""
+    from oracle.model import BUS_PQ, BUS_REF
+    net = synthnet.Network(
+        nb=3, base_mva=100.0, bus_type=np.array([BUS_REF, BUS_PQ, BUS_PQ], np.int32),
+        pd=np.array([0.0, 0.3, 0.2]), qd=np.array([0.0, 0.1, 0.05]),
+        vmin=np.full(3, 0.9), vmax=np.full(3, 1.1),
+        f=np.array([0, 1], np.int32), t=np.array([1, 2], np.int32),
+        r=np.zeros(2), x=np.array([0.1, 0.1]), b=np.zeros(2), rate=np.zeros(2),
+        gen_bus=np.array([0], np.int32), c2=np.array([0.02]), c1=np.array([20.0]),
+        c0=np.array([0.0]), pmin=np.array([0.0]), pmax=np.array([2.0]),
+        qmin=np.array([-2.0]), qmax=np.array([2.0]))
+    api = _api()
+    M = Model(net)
+    x0, u0 = M.join(np.array([0.0, -np.pi / 2, -np.pi / 2]), np.ones(3), np.zeros(1))
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=dev)
+    G = api.Net(net)
+    ones = lambda n: T(np.ones(n))
+    r = T(np.ones(M.nu + 2 * M.nx + 2 * M.m))
+    K, rhs = G.condense_reduced_hessian(T(x0), T(u0), T(np.zeros(M.nx)), T(np.zeros(M.m)),
+                                        ones(M.nx), ones(M.nu), ones(M.m), r=r)
+    _, code = G.solve_condensed_kkt(K, 0.0, rhs, r)
+    assert code == 2                       # RH_SMALL_PIVOT
+    ipm = api.Ipm(G, x0=T(x0), u0=T(u0), tol=1e-6)
+    before = {k: v.clone() for k, v in ipm.state().items()}
+    code, info = ipm.step()
+    assert code == 2, (code, info)
+    after = ipm.state()
+    for k in before:
+        assert torch.equal(before[k], after[k]), k
+    ipm.close()
+    G.close()

@@ -130,3 +130,58 @@ def test_nine_bus_sizes_and_9241_analysis():
     S = _lib().Symbolic(synthnet.case9241(0))
     assert (S.info["nx"], S.info["nu"]) == (17036, 2889)
     assert S.check_levels() == 0
+
+
+def _line_pair(x01, x12):
+    """Reference bus 0 (generator), PQ buses 1 and 2, lossless lines 0-1 and
+    1-2 with reactances x01, x12."""
+    from oracle.model import BUS_PQ, BUS_REF
+    return synthnet.Network(
+        nb=3, base_mva=100.0, bus_type=np.array([BUS_REF, BUS_PQ, BUS_PQ], np.int32),
+        pd=np.array([0.0, 0.3, 0.2]), qd=np.array([0.0, 0.1, 0.05]),
+        vmin=np.full(3, 0.9), vmax=np.full(3, 1.1),
+        f=np.array([0, 1], np.int32), t=np.array([1, 2], np.int32),
+        r=np.zeros(2), x=np.array([x01, x12]), b=np.zeros(2), rate=np.zeros(2),
+        gen_bus=np.array([0], np.int32), c2=np.array([0.02]), c1=np.array([20.0]),
+        c0=np.array([0.0]), pmin=np.array([0.0]), pmax=np.array([2.0]),
+        qmin=np.array([-2.0]), qmax=np.array([2.0]))
+
+
+def _gx_values(S, M, theta, vm):
+    x, u = M.join(theta, vm, np.zeros(M.ng))
+    G, _, _ = M.jacobians(x, u)
+    Gx = G.tocsr()[:, M.nu:]
+    ptr, col, _ = S.gx_pattern()
+    return np.asarray(Gx[np.repeat(np.arange(M.nx), np.diff(ptr)), col]).ravel(), \
+        Gx.toarray()
+
+
+@pytest.mark.parametrize("case", ["quarter_turn", "near_zero_reactance"])
+def test_static_pivot_flags_tiny_pivots(case):
+    """The static-pivot refactorisation (host emulation of the device
+    schedule) reports RH_SMALL_PIVOT when a pivot is not above 1e-14 of its
+    row's largest entry, on two crafted G_x: (a) a lossless line carrying a
+    90-degree angle difference, where dP/dtheta at its PQ end vanishes
+    (cos(pi/2) = 0) while the matrix stays nonsingular; (b) a line of
+    reactance 1e-16 p.u. between two PQ buses, whose eliminated pivot is the
+    difference of two admittances of 1e16. The same networks at ordinary
+    points solve to rounding."""
+    S_cls = _lib().Symbolic
+    if case == "quarter_turn":
+        net = _line_pair(0.1, 0.1)
+        bad = (np.array([0.0, -np.pi / 2, -np.pi / 2]), np.ones(3))
+    else:
+        net = _line_pair(0.1, 1e-16)
+        bad = (np.array([0.0, -0.05, -0.05]), np.ones(3))
+    good = (np.array([0.0, -0.05, -0.08]), np.array([1.0, 0.98, 0.97]))
+    S = S_cls(net)
+    M = Model(net)
+    vals, Gd = _gx_values(S, M, *good)
+    if case == "quarter_turn":
+        b = np.arange(1.0, M.nx + 1)
+        z = S.host_solve(vals, b)
+        assert np.abs(Gd @ z - b).max() <= 1e-10 * np.abs(Gd).max() * np.abs(z).max()
+    vals, Gd = _gx_values(S, M, *bad)
+    assert np.linalg.matrix_rank(Gd) == M.nx or case != "quarter_turn"
+    with pytest.raises(RuntimeError, match="small pivot"):
+        S.host_solve(vals, np.ones(M.nx))
