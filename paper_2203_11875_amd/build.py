@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librhipm.so")
-SOURCES = ["analysis.cpp", "kernels.hip", "ipm.hip", "redlin.hip", "rhipm.cpp"]
+SOURCES = ["analysis.cpp", "kernels.hip", "chol.hip", "ipm.hip", "redlin.hip", "rhipm.cpp"]
 
 
 def hipcc() -> str:

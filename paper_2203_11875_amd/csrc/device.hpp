@@ -117,7 +117,7 @@ struct BatchShape {
   bool lds = true, any_wave = false, any_staged = false;
   int max_lines = 0, max_dst = 0, max_nnz_k = 0, max_nw = 0, max_nx = 0, max_nu = 0, max_m = 0;
   size_t lds_wave = 0, lds_staged = 0, lds_condense = 0;
-  std::vector<int> nbk;   // Cholesky blocks of each instance
+  std::vector<int> orders;   // order (nu) of each instance's condensed matrix
 };
 // Condensation of every instance (eval, K assembly, rt, refactorisation,
 // columns with the right-hand side, symmetrisation) and the solve with
@@ -161,16 +161,27 @@ hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st);
 hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,
                               hipStream_t st);
 hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
-// Cholesky of the lower triangle of K + delta I in place, L y = b (b is
-// destroyed), then L^T x = y with x written over y. status[0..1] device.
-// dinv: workspace of ceil(n / 32) * 32 * 32 doubles (inverted diagonal blocks).
-// Workspaces: dinv (2 * 1024 * ceil(n / 32) doubles), lrow ((32 ceil(n / 32))^2
-// doubles). trace (optional, device int64[8 * (ceil(n / 32) + 1)]): wall-clock
-// stamps of the first work-group of every launch, for profiling.
-hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
-                                 double* y, double* dinv, double* lrow, int* status,
-                                 hipStream_t st, long long* trace = nullptr);
-// Doubles of the Cholesky workspaces of order n (dinv and lrow above).
+// Cholesky of the lower triangle of K + delta I in place (K holds L on
+// return), the forward substitution L y = b folded into the factorisation
+// (y over b: b is destroyed) and the backward substitution L^T x = y into x.
+// status[0..1] (device): 0, or 1 and the first column whose pivot is not
+// positive. Workspaces: dl (chol_inv_doubles(n)), X (chol_lrow_doubles(n):
+// the inverses of the diagonal super-blocks of L^T). trace (optional,
+// device int64[8 ceil(n / 32)]): wall-clock stamps of the diagonal
+// work-group of every factorisation launch.
+hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b, double* x,
+                                 double* dl, double* X, int* status, hipStream_t st,
+                                 long long* trace = nullptr);
+// The same for every instance of a batch (orders[i] = order of instance i;
+// args[i]: K, ldk, delta, bwork (b), p (x), cinv (dl), lrow (X), status).
+hipError_t launch_batch_cholesky(const BatchArg* args, const std::vector<int>& orders,
+                                 hipStream_t st);
+// Panel columns per super-block of an order with nbk 32-column panels: one
+// super-block up to 24 panels (order 768), 16 panels (512 columns) above.
+__host__ __device__ constexpr int chol_superblock(int nbk) { return nbk <= 24 ? nbk : 16; }
+// Kernel launches of one launch_cholesky_solve (status clear excluded).
+int chol_launches(int n);
+// Doubles of the Cholesky workspaces of order n (dl and X above).
 constexpr size_t chol_inv_doubles(int n) { return 2 * size_t((n + 31) / 32) * 32 * 32; }
 constexpr size_t chol_lrow_doubles(int n) {
   return size_t((n + 31) / 32) * 32 * size_t((n + 31) / 32) * 32;

@@ -1,9 +1,8 @@
 // HIP kernels (gfx950) of the condensation hot path:
 //   derivative values on fixed patterns, static-pivot refactorisation of G_x,
 //   the fused tangent-solve / Hessian-product / adjoint-solve pipeline that
-//   builds K_cond column blocks, symmetrisation, blocked Cholesky with the
-//   forward substitution folded into the panel step, backward substitution,
-//   and the step recovery.
+//   builds K_cond column blocks, symmetrisation and the step recovery (the
+//   dense Cholesky and its solves are in chol.hip).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1240,439 +1239,6 @@ __global__ void k_symmetrize(double* K, long ld, int n) {
   k_symmetrize_body(K, ld, n);
 }
 
-constexpr int NB = 32;   // panel width of the blocked Cholesky
-
-
-typedef double d4_t __attribute__((ext_vector_type(4)));
-
-// Position of row r of a published panel column in LDS: the diagonal-tile
-// rows in the order (r % 4) * 8 + r / 4, so that the 8 rows a wave needs as
-// column indices (w + 4 t, t < 8) are contiguous; rows >= NB follow as is.
-__device__ __forceinline__ int cpos(int r) { return r < NB ? (r & 3) * 8 + (r >> 2) : r; }
-
-// In-place factorisation of a 64 x NB panel slice P in LDS by the four waves
-// of a work-group: rows 0..NB-1 hold the symmetric diagonal tile D (lower
-// part used), rows NB..2NB-1 a tile B below it. On return rows 0..NB-1 hold
-// L = chol(D) (zero above the diagonal) and rows NB..2NB-1 hold B L^{-T}.
-// Wave w owns columns w + 4 t (t < 8) with lane = row, 8 registers per lane.
-//
-// The elimination is scaled so that no square root or division sits on the
-// pivot-to-pivot chain: with d_j the current pivot and d_j = alpha_j 2^e_j
-// (alpha_j in [1/2, 1), exact), the trailing entries become
-//   T_ic <- alpha_j T_ic - 2^-e_j T_ij T_cj,
-// which is 2^-e_j d_j times the usual Schur update, so the working matrix at
-// step j is sigma_j times the true Schur complement with
-// sigma_{j+1} = sigma_j alpha_j (a power-of-two-free product, bounded in
-// [2^-NB, 1]). Column c of L is then T_.c / sqrt(sigma_c d_c), applied to all
-// columns at the end. Pivot j costs one barrier: the owner of column j + 1
-// applies step j to that column first and publishes it. Returns the first
-// non-positive pivot among this wave's columns, or -1.
-__device__ __forceinline__ int chol_panel64(double (*P)[NB + 1], double (*cb)[2 * NB], int wave,
-                                            int lane) {   // cb: [4][2 NB], two published + two dummy
-  double a[8], sg[8], dg[8];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    a[t] = P[lane][wave + 4 * t];
-    sg[t] = 1.0;
-    dg[t] = 1.0;
-  }
-  if (wave == 0) cb[0][cpos(lane)] = a[0];
-  lds_barrier();
-  double sigma = 1.0;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int ow = j & 3, tj = j >> 2;
-    const double* cbj = cb[j & 1];
-    const double d = cbj[cpos(j)];
-    const double tij = cbj[cpos(lane)];
-    // register tn holds column j + 1 in its owner wave; in every wave the
-    // columns w + 4 t right of j are t > tn, and t = tn when w > j - 4 tn
-    const int tn = (j + 1) >> 2, on = (j + 1) & 3;
-    double xn = j + 1 < NB ? cbj[wave * 8 + (tn & 7)] : 0.0;
-    asm volatile("" : "+v"(xn));             // load it with d and t_ij
-    int e;
-    const double alpha = frexp(d, &e);
-    const double bij = ldexp(-tij, -e);        // -2^-e_j T_ij
-    sg[tj] = wave == ow ? sigma : sg[tj];
-    dg[tj] = wave == ow ? d : dg[tj];
-    sigma *= alpha;
-    if (j + 1 < NB) {
-      const bool cn = wave > j - 4 * tn;
-      a[tn] = fma(cn ? bij : 0.0, xn, (cn ? alpha : 1.0) * a[tn]);
-      // the owner publishes column j + 1; the other waves write a dummy row
-      double* dst = wave == on ? &cb[(j + 1) & 1][cpos(lane)] : &cb[2 + ((j + 1) & 1)][lane];
-      *dst = a[tn];
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = tn + 1; t < 8; ++t) a[t] = fma(bij, cbj[wave * 8 + t], alpha * a[t]);
-      // keep this step's updates ahead of the barrier (not sunk into the next
-      // pivot's critical path)
-#pragma unroll
-      for (int t = tn; t < 8; ++t) asm volatile("" : "+v"(a[t]));
-      __builtin_amdgcn_sched_barrier(0);
-      lds_barrier();
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  int fl = -1;
-#pragma unroll
-  for (int t = 7; t >= 0; --t) {
-    const int c = wave + 4 * t;
-    if (!(dg[t] > 0.0)) fl = c;
-    const double v = a[t] * rsqrt(sg[t] * dg[t]);
-    a[t] = (lane < NB && lane < c) ? 0.0 : v;
-  }
-#pragma unroll
-  for (int t = 0; t < 8; ++t) P[lane][wave + 4 * t] = a[t];
-  return fl;
-}
-
-// 16 x 16 quadrant of a 32 x 32 tile in the accumulator layout of
-// v_mfma_f64_16x16x4f64 computing the transposed product: lane li + 16 kk,
-// register e holds element (row ri + li, column cj + 4 e + kk), so each
-// register is four coalesced 128-byte row runs.
-__device__ __forceinline__ d4_t load_quad(const double* A, long ld, int n, int ri, int cj, int li,
-                                          int kk, double diag_add) {
-  d4_t v;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int r = ri + li, c = cj + 4 * e + kk;
-    double x = ld_or0(A, (size_t)c * ld + r, r < n && c < n);
-    if (r == c) x += diag_add;
-    v[e] = x;
-  }
-  return v;
-}
-
-__device__ __forceinline__ void store_quad_lower(double* A, long ld, int n, int ri, int cj, int li,
-                                                 int kk, d4_t v) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int r = ri + li, c = cj + 4 * e + kk;
-    if (r < n && c <= r) A[(size_t)c * ld + r] = v[e];
-  }
-}
-
-// Blocked right-looking Cholesky of A + delta I (lower triangle) with the
-// forward substitution L y = b folded in; one launch per column block k.
-// Work-groups [0, nbk - k) are the panel of column block k: group g owns row
-// block i = k + g. It applies the rank-NB update of panel k - 1 to the
-// diagonal tile (k, k) and to its own tile (i, k) on MFMA, and
-// b_i -= L_{i,k-1} y_{k-1}; the four waves then factor the 64 x NB slice
-// [A_kk; A_ik] (chol_panel64), which yields L_kk redundantly in every group
-// and L_ik = A_ik L_kk^{-T}. Group 0 carries the identity below the diagonal
-// tile instead, which yields L_kk^{-T}: it stores L_kk in dl, L_kk^{-T} in
-// inv (column-major) and y_k = L_kk^{-1} b_k. The remaining groups apply
-// panel k - 1 to the trailing tiles (i, j), k < j <= i. The diagonal tile
-// (k, k) of A is read by every panel group of the launch, so L_kk goes to A
-// one launch later. The off-diagonal tiles are also stored in the row-block
-// panels of lrow (column after column) for the backward substitution.
-// delta enters each diagonal tile on its first touch (k <= 1).
-__device__ __forceinline__ void k_chol_step_body(double* A, long ld, int n, int k, double delta, double* b, double* y, double* inv, double* dl, double* lrow, int* status, long long* trace) {
-  if (status[0] != 0) return;
-  const bool tr = trace != nullptr && blockIdx.x == 0 && threadIdx.x == 0;
-  if (tr) trace[8 * k] = wall_clock64();
-  const int nbk = (n + NB - 1) / NB;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, kk = lane >> 4;
-  const int qi = wave >> 1, qj = wave & 1;
-  const int k0 = k * NB, pc0 = k0 - NB;
-  const double dfirst = k <= 1 ? delta : 0.0;
-  const int npanel = nbk - k;
-  if ((int)blockIdx.x >= npanel) {            // trailing tile, update from panel k - 1
-    int t = blockIdx.x - npanel, ti = 0;
-    while (t > ti) {
-      t -= ti + 1;
-      ++ti;
-    }
-    const int bi = k + 1 + ti, bj = k + 1 + t;
-    if (bi == bj && qi < qj) return;           // strictly upper quadrant of a diagonal tile
-    const int ri = bi * NB + qi * 16, cj = bj * NB + qj * 16;
-    d4_t acc = load_quad(A, ld, n, ri, cj, li, kk, bi == bj ? dfirst : 0.0);
-#pragma unroll
-    for (int s = 0; s < NB; s += 4) {
-      const size_t col = (size_t)(pc0 + s + kk) * ld;
-      const double av = -ld_or0(A, col + cj + li, cj + li < n);
-      const double bv = ld_or0(A, col + ri + li, ri + li < n);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    store_quad_lower(A, ld, n, ri, cj, li, kk, acc);
-    return;
-  }
-
-  __shared__ double P[2 * NB][NB + 1];
-  __shared__ double cb[4][2 * NB];
-  __shared__ double red[NB], bks[NB];
-  __shared__ int fails[4];
-  const bool own = blockIdx.x > 0;
-  const int bi = k + blockIdx.x;
-  const int bsz = min(NB, n - k0);
-  double bval = 0.0;
-  if (tid < NB && bi * NB + tid < n) bval = b[bi * NB + tid];
-  const bool dq = !(qi == 0 && qj == 1);
-  const int cj = k0 + qj * 16, rd = k0 + qi * 16, ro = bi * NB + qi * 16;
-  // every operand load of this work-group is issued before the first MFMA
-  // (no branch between them, so they are all in flight together)
-  d4_t dacc = load_quad(A, ld, dq ? n : 0, rd, cj, li, kk, dfirst);
-  d4_t oacc = load_quad(A, ld, own ? n : 0, ro, cj, li, kk, 0.0);
-  double bpart = 0.0;
-  if (k > 0) {
-    double av[NB / 4], bd[NB / 4], bo[NB / 4], yv[NB / 4];
-#pragma unroll
-    for (int s4 = 0; s4 < NB / 4; ++s4) {
-      const size_t col = (size_t)(pc0 + 4 * s4 + kk) * ld;
-      av[s4] = -ld_or0(A, col + cj + li, cj + li < n);
-      bd[s4] = ld_or0(A, col + rd + li, dq && rd + li < n);
-      bo[s4] = ld_or0(A, col + ro + li, own && ro + li < n);
-      yv[s4] = y[pc0 + 4 * s4 + kk];
-    }
-#pragma unroll
-    for (int s4 = 0; s4 < NB / 4; ++s4) {
-      dacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bd[s4], dacc, 0, 0, 0);
-      oacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bo[s4], oacc, 0, 0, 0);
-      bpart = fma(own ? bo[s4] : bd[s4], yv[s4], bpart);   // L_{rb,k-1} y_{k-1}
-    }
-    bpart += __shfl_xor(bpart, 16);
-    bpart += __shfl_xor(bpart, 32);
-  }
-  if (tr) {
-    asm volatile("" :: "v"(dacc[0]));
-    trace[8 * k + 1] = wall_clock64();
-  }
-  if (qj == 0 && kk == 0) red[qi * 16 + li] = bpart;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int rl = qi * 16 + li, cl = qj * 16 + 4 * e + kk;
-    if (dq) P[rl][cl] = (rl >= bsz || cl >= bsz) ? (rl == cl ? 1.0 : 0.0) : dacc[e];
-    P[NB + rl][cl] = own ? oacc[e] : (rl == cl ? 1.0 : 0.0);
-  }
-  if (dq && qi == 1 && qj == 0) {              // the strictly upper quadrant is not
-#pragma unroll                                 // computed: mirror it (symmetric tile)
-    for (int e = 0; e < 4; ++e) P[4 * e + kk][16 + li] = P[16 + li][4 * e + kk];
-  }
-  lds_barrier();
-  if (tr) trace[8 * k + 2] = wall_clock64();
-  if (tid < NB) bks[tid] = bval - red[tid];     // b_i after panel k - 1
-  const int fl = chol_panel64(P, cb, wave, lane);
-  if (lane == 0) fails[wave] = fl;
-  __syncthreads();
-  if (tr) trace[8 * k + 3] = wall_clock64();
-  int first = -1;
-#pragma unroll
-  for (int w = 0; w < 4; ++w)
-    if (fails[w] >= 0 && (first < 0 || fails[w] < first)) first = fails[w];
-  if (first >= 0 && first < bsz) {
-    if (blockIdx.x == 0 && tid == 0) {
-      status[1] = k0 + first;
-      status[0] = 1;
-    }
-    return;
-  }
-  if (own) {
-    const int npad = nbk * NB;
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-      const int r = idx % NB, c = idx / NB, row = bi * NB + r;
-      if (row < n) A[(size_t)(k0 + c) * ld + row] = P[NB + r][c];
-      // the same tile in the row-block panel of the backward substitution
-      lrow[(size_t)bi * NB * npad + (size_t)(k0 + c) * NB + r] = P[NB + r][c];
-    }
-    if (tid < NB && bi * NB + tid < n) b[bi * NB + tid] = bks[tid];
-    return;
-  }
-  const bool last = k + 1 == nbk;               // the only work-group of its launch
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx % NB, c = idx / NB;
-    inv[(size_t)k * NB * NB + idx] = P[NB + r][c];       // L_kk^{-T}, column-major
-    if (last) {
-      if (c <= r && k0 + r < n) A[(size_t)(k0 + c) * ld + k0 + r] = P[r][c];
-    } else {
-      dl[(size_t)k * NB * NB + idx] = P[r][c];           // L_kk, column-major
-    }
-    // tile (k - 1, k - 1) is read by no work-group of this launch: store
-    // the factor left there by the previous launch
-    if (k > 0 && c <= r) A[(size_t)(k0 - NB + c) * ld + k0 - NB + r] = dl[(size_t)(k - 1) * NB * NB + idx];
-  }
-  if (tid < bsz) {                             // y_k = L_kk^{-1} b_k
-    double v = 0.0;
-#pragma unroll 8
-    for (int s = 0; s < NB; ++s) v = fma(P[NB + s][tid], bks[s], v);
-    y[k0 + tid] = v;
-  }
-  if (tr) trace[8 * k + 4] = wall_clock64();
-}
-__global__ void __launch_bounds__(256) k_chol_step(double* A, long ld, int n, int k, double delta, double* b, double* y, double* inv, double* dl, double* lrow, int* status, long long* trace) {
-  k_chol_step_body(A, ld, n, k, delta, b, y, inv, dl, lrow, status, trace);
-}
-
-// Row-block panels of L for the backward substitution: row block i is the
-// NB x i NB slice L_{i, 0:i} stored column after column, NB rows contiguous
-// (entry (r, c) at lrow[i NB npad + c NB + r]). A wave reads the 32 columns
-// of its pass as one contiguous 8 KB run: in load j, lane l holds rows
-// 2 (l & 15), 2 (l & 15) + 1 of column 4 j + (l >> 4) of the run.
-struct Panel { double2 v[8]; };
-
-// the most row blocks one pass of the backward work-group serves: the last
-// block's panel then has (kBackNarrowBlocks - 1) NB = NB * NB / 2 columns,
-// one run of 32 per wave
-constexpr int kBackNarrowBlocks = NB * NB / 2 / NB + 1;
-
-__device__ __forceinline__ void panel_load(const double* lrow, size_t off, Panel& pl, int lane) {
-  const double2* p = reinterpret_cast<const double2*>(lrow + off) + lane;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) pl.v[j] = p[64 * j];
-}
-
-// The 32 column sums sum_r L(r, c) x_r of a wave's run: the products of a
-// load are summed over its 16 lanes by recursive halving (each exchange
-// sends the half of the partial sums the partner keeps), so a lane ends with
-// one column: j = 4 (l & 1) + 2 ((l >> 1) & 1) + ((l >> 2) & 1).
-__device__ __forceinline__ double panel_dot(const Panel& pl, double x0, double x1, bool ok0,
-                                            bool ok1, int lane) {
-  double v[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j)
-    v[j] = fma(ok0 ? pl.v[j].x : 0.0, x0, (ok1 ? pl.v[j].y : 0.0) * x1);
-#pragma unroll
-  for (int half = 4, m = 1; half >= 1; half >>= 1, m <<= 1) {
-    const bool hi = (lane & m) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const double send = hi ? v[i] : v[half + i];
-      const double keep = hi ? v[half + i] : v[i];
-      v[i] = keep + __shfl_xor(send, m);
-    }
-  }
-  return v[0] + __shfl_xor(v[0], 8);
-}
-
-__device__ __forceinline__ int panel_col(int lane) {
-  return 4 * (4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1)) + (lane >> 4);
-}
-
-// One step of the backward substitution for row block bk (b0 = bk NB): pl
-// holds this wave's first run of panel bk (columns 32 wave .. + 31), loaded
-// one step ahead; rows past n are zeroed here, at the use, so the loads stay
-// in flight until then. Ms[bk % 3] holds L_bk,bk^{-T} (column-major), parked
-// by the previous step from mpark (the inverse of block bk - 1, loaded a
-// step before that).
-template <bool WIDE>
-__device__ __forceinline__ void backward_block(const double* lrow, int npad, int n, int bk,
-                                               double* ys, double* xb, double (*Ms)[NB * NB],
-                                               const Panel& pl, double mpark, int tid) {
-  const int b0 = bk * NB, lane = tid & 63, wave = tid >> 6;
-  if (wave == 0) {                              // x_b = L_bb^{-T} y_b
-    const int t = lane & 31, hs = lane >> 5;
-    const double* m = Ms[bk % 3];
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v = fma(m[(16 * hs + q) * NB + t], ys[b0 + 16 * hs + q], v);
-    v += __shfl_xor(v, 32);
-    if (hs == 0) {
-      xb[t] = v;
-      ys[b0 + t] = v;
-    }
-  }
-  if (bk > 0) Ms[(bk + 2) % 3][tid] = mpark;    // inverse of block bk - 1
-  lds_barrier();
-  const int r0 = 2 * (lane & 15);
-  const bool ok0 = b0 + r0 < n, ok1 = b0 + r0 + 1 < n;
-  const double x0 = xb[r0], x1 = xb[r0 + 1];
-  const int cl = panel_col(lane);
-  for (int c0 = 32 * wave; c0 < (WIDE ? b0 : 32 * wave + 1); c0 += NB * NB / 2) {
-    double s;
-    if (c0 == 32 * wave) {
-      s = panel_dot(pl, x0, x1, ok0, ok1, lane);
-    } else {                                   // columns past the first 512: in place
-      Panel q;
-      panel_load(lrow, (size_t)bk * NB * npad + (size_t)c0 * NB, q, lane);
-      s = panel_dot(q, x0, x1, ok0, ok1, lane);
-    }
-    if ((lane & 8) == 0 && c0 + cl < b0) ys[c0 + cl] -= s;
-  }
-  lds_barrier();
-}
-
-// This wave's first run of panel bk for the step of block bk: waves past
-// the block's columns read the first run instead (unused). Issued
-// unconditionally (bk < 0 reads block 0, unused) so that the compiler
-// counts the loads in flight exactly and waits for each set only at its use.
-__device__ __forceinline__ void backward_load_l(const double* lrow, int npad, int bk, Panel& pl,
-                                                int tid) {
-  bk = max(bk, 0);
-  const int wave = tid >> 6, cw = 32 * wave < bk * NB ? 32 * wave : 0;
-  panel_load(lrow, (size_t)bk * NB * npad + (size_t)cw * NB, pl, tid & 63);
-}
-// this thread's entry of L_bk,bk^{-T}
-__device__ __forceinline__ void backward_load_m(const double* inv, int bk, double& mv, int tid) {
-  mv = inv[(size_t)max(bk, 0) * NB * NB + tid];
-}
-
-// Backward substitution L^T x = y (x over y) by work-group 0, by NB-row
-// blocks from the bottom (right-looking): x_b = L_bb^{-T} y_b, then
-// y_c -= L_bc^T x_b for every column c left of the block. The operands of
-// block b - 1 are loaded while block b is processed (two register sets).
-// Work-groups 8 h (h >= 1), dispatched to the same XCD as work-group 0, read
-// the panels ahead of it into that XCD's L2 and exit; the rest exit.
-// WIDE: more than kBackNarrowBlocks row blocks, so some row blocks span more
-// columns than one pass of the work-group covers (16 waves x 32 columns; the
-// runs past the first pass are loaded in place).
-template <bool WIDE>
-__device__ __forceinline__ void k_chol_backward_body(const double* lrow, int n, double* y, const double* inv, const int* status, long long* trace) {
-  if (status[0] != 0) return;
-  const int tid = threadIdx.x;
-  const int nbk = (n + NB - 1) / NB, npad = nbk * NB;
-  if (blockIdx.x != 0) {
-    if (blockIdx.x % 8 != 0) return;
-    const int h = blockIdx.x / 8, nh = (gridDim.x - 1) / 8;
-    // helper h touches row blocks nbk - 1 - h, nbk - 1 - h - nh, ...
-    double acc = 0.0;
-    for (int bk = nbk - 1 - h; bk >= 0; bk -= nh) {
-      const double* panel = lrow + (size_t)bk * NB * npad;        // NB * bk NB contiguous
-      for (int idx = tid; idx < NB * bk * NB / 8; idx += NB * NB)  // one 64-byte piece each
-        acc += panel[8 * (size_t)idx];
-    }
-    asm volatile("" :: "v"(acc));             // keeps the loads
-    return;
-  }
-  extern __shared__ double ys[];               // nbk * NB
-  __shared__ double xb[NB];
-  __shared__ double Ms[3][NB * NB];
-  const bool tr = trace != nullptr && tid == 0;
-  if (tr) trace[0] = wall_clock64();
-  // step bk parks the inverse of block bk - 1 (ma or mb), loaded one step
-  // before; after a step the registers it used take the loads two steps ahead
-  // (issued after y and in this order: the loop's first steps then wait for
-  // no load issued after the one they use)
-  Panel l0, l1;
-  double m = 0.0, ma = 0.0, mb = 0.0;
-  for (int i = tid; i < nbk * NB; i += NB * NB) ys[i] = i < n ? y[i] : 0.0;
-  backward_load_m(inv, nbk - 1, m, tid);
-  backward_load_m(inv, nbk - 2, ma, tid);
-  backward_load_m(inv, nbk - 3, mb, tid);
-  backward_load_l(lrow, npad, nbk - 1, l0, tid);
-  backward_load_l(lrow, npad, nbk - 2, l1, tid);
-  Ms[(nbk - 1) % 3][tid] = m;
-  __syncthreads();
-  if (tr) trace[1] = wall_clock64();
-  int bk = nbk - 1;
-  for (; bk >= 1; bk -= 2) {
-    backward_block<WIDE>(lrow, npad, n, bk, ys, xb, Ms, l0, ma, tid);
-    backward_load_l(lrow, npad, bk - 2, l0, tid);
-    backward_load_m(inv, bk - 3, ma, tid);
-    backward_block<WIDE>(lrow, npad, n, bk - 1, ys, xb, Ms, l1, mb, tid);
-    backward_load_l(lrow, npad, bk - 3, l1, tid);
-    backward_load_m(inv, bk - 4, mb, tid);
-  }
-  if (bk == 0) backward_block<WIDE>(lrow, npad, n, 0, ys, xb, Ms, l0, 0.0, tid);
-  if (tr) trace[2] = wall_clock64();
-  for (int i = tid; i < n; i += NB * NB) y[i] = ys[i];
-}
-template <bool WIDE>
-__global__ void __launch_bounds__(NB * NB) k_chol_backward(const double* lrow, int n, double* y, const double* inv, const int* status, long long* trace) {
-  k_chol_backward_body<WIDE>(lrow, n, y, inv, status, trace);
-}
-
-
 template <int W, bool LDS>
 hipError_t launch_condense_t(const DevNet& d, int col0, int ncols, int mode, const double* r,
                              const double* vin, double* K, long ldk, double* rhs, double* p,
@@ -1771,20 +1337,6 @@ __global__ void k_symmetrize_b(const BatchArg* __restrict__ a) {
   const BatchArg& q = a[blockIdx.z];
   k_symmetrize_body(q.K, q.ldk, q.nu);
 }
-__global__ void __launch_bounds__(256) k_chol_step_b(const BatchArg* __restrict__ a, int k) {
-  const BatchArg& q = a[blockIdx.z];
-  const int nbk = (q.nu + NB - 1) / NB;
-  if (k >= nbk) return;
-  const int T = nbk - 1 - k;
-  if ((int)blockIdx.x >= (nbk - k) + (k >= 1 ? T * (T + 1) / 2 : 0)) return;
-  k_chol_step_body(q.K, q.ldk, q.nu, k, q.delta, q.bwork, q.p, q.cinv,
-                   q.cinv + (size_t)nbk * NB * NB, q.lrow, q.status, nullptr);
-}
-template <bool WIDE>
-__global__ void __launch_bounds__(NB * NB) k_chol_backward_b(const BatchArg* __restrict__ a) {
-  const BatchArg& q = a[blockIdx.z];
-  k_chol_backward_body<WIDE>(q.lrow, q.nu, q.p, q.cinv, q.status, nullptr);
-}
 __global__ void __launch_bounds__(kBlock) k_recover_partial_b(const DevNet* __restrict__ nets,
                                                              const BatchArg* __restrict__ a) {
   const int b = blockIdx.z;
@@ -1820,10 +1372,6 @@ void prepare_lds_kernels() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor_wave),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
   const void* fns[] = {
       reinterpret_cast<const void*>(&k_condense<1, true, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<2, true, MODE_COLUMNS>),
@@ -1883,10 +1431,6 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_refactor_b)};
   for (const void* f : bfns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward_b<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backward_b<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 25 * 1024);
   for (const void* f : gfns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   (void)hipGetLastError();
@@ -2005,30 +1549,6 @@ hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b,
-                                 double* y, double* dinv, double* lrow, int* status,
-                                 hipStream_t st, long long* trace) {
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, status, 2, 0);
-  if (n <= 0) return hipGetLastError();
-  const int nbk = cdiv(n, NB);
-  double* dl = dinv + (size_t)nbk * NB * NB;
-  for (int k = 0; k < nbk; ++k) {
-    const int T = nbk - 1 - k;
-    const int grid = (nbk - k) + (k >= 1 ? T * (T + 1) / 2 : 0);
-    hipLaunchKernelGGL(k_chol_step, dim3(grid), dim3(256), 0, st, K, ldk, n, k, delta, b, y, dinv,
-                       dl, lrow, status, trace);
-  }
-  if (nbk <= kBackNarrowBlocks)
-    hipLaunchKernelGGL(k_chol_backward<false>, dim3(64), dim3(NB * NB),
-                       (size_t)nbk * NB * sizeof(double), st, (const double*)lrow, n, y,
-                       (const double*)dinv, (const int*)status, trace ? trace + 8 * nbk : nullptr);
-  else
-    hipLaunchKernelGGL(k_chol_backward<true>, dim3(64), dim3(NB * NB),
-                       (size_t)nbk * NB * sizeof(double), st, (const double*)lrow, n, y,
-                       (const double*)dinv, (const int*)status, trace ? trace + 8 * nbk : nullptr);
-  return hipGetLastError();
-}
-
 hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const int2* tiles,
                                  const BatchShape& sh, hipStream_t st) {
   const int B = sh.count;
@@ -2077,23 +1597,10 @@ hipError_t launch_batch_solve(const DevNet* nets, const BatchArg* args, const Ba
   if (B == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_b, dim3(cdiv(sh.max_nu, kBlock), 1, B), dim3(kBlock), 0, st, args, 1);
   hipLaunchKernelGGL(k_clear_status_b, dim3(1, 1, B), dim3(64), 0, st, nets, 0, 2);
-  int max_nbk = 0;
-  for (int v : sh.nbk) max_nbk = v > max_nbk ? v : max_nbk;
-  for (int k = 0; k < max_nbk; ++k) {
-    int grid = 0;
-    for (int nbk : sh.nbk)
-      if (k < nbk) {
-        const int T = nbk - 1 - k, g = (nbk - k) + (k >= 1 ? T * (T + 1) / 2 : 0);
-        grid = g > grid ? g : grid;
-      }
-    hipLaunchKernelGGL(k_chol_step_b, dim3(grid, 1, B), dim3(256), 0, st, args, k);
+  {
+    const hipError_t e = launch_batch_cholesky(args, sh.orders, st);
+    if (e != hipSuccess) return e;
   }
-  if (max_nbk <= kBackNarrowBlocks)
-    hipLaunchKernelGGL(k_chol_backward_b<false>, dim3(1, 1, B), dim3(NB * NB),
-                       (size_t)max_nbk * NB * sizeof(double), st, args);
-  else
-    hipLaunchKernelGGL(k_chol_backward_b<true>, dim3(1, 1, B), dim3(NB * NB),
-                       (size_t)max_nbk * NB * sizeof(double), st, args);
   hipLaunchKernelGGL(k_recover_partial_b, dim3(cdiv(sh.max_nx, kBlock), kRecChunks, B),
                      dim3(kBlock), 0, st, nets, args);
   hipLaunchKernelGGL(k_recover_finish_b,

@@ -606,10 +606,6 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
     if (i == 0) { sh.width = n->width; sh.lds = n->lds; }
     if (n->width != sh.width || n->lds != sh.lds) { delete b; return RH_ERR_ARG; }
     const rh::DevNet& d = n->d;
-    if (size_t((d.nu + 31) / 32) * 32 * sizeof(double) + 25 * 1024 > lds_max) {
-      delete b;
-      return RH_ERR_ARG;
-    }
     b->nets.push_back(n);
     sh.max_lines = std::max(sh.max_lines, std::max(d.nl, d.nu));
     sh.max_dst = std::max(sh.max_dst, d.d_total);
@@ -627,7 +623,7 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
       sh.lds_staged = std::max(sh.lds_staged, size_t(d.rf_lds_doubles) * sizeof(double));
     }
     sh.lds_condense = std::max(sh.lds_condense, rh::condense_lds_bytes(d, sh.width, sh.lds));
-    sh.nbk.push_back((d.nu + 31) / 32);
+    sh.orders.push_back(d.nu);
     const int ntile = (d.nu + 1 + sh.width - 1) / sh.width;
     for (int t = 0; t < ntile; ++t) tiles.push_back(int2{i, t});
   }
@@ -939,9 +935,6 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   if (ldk < n->s.nu || !(delta_w >= 0.0)) return RH_ERR_ARG;
   if (!n->condensed) return RH_ERR_STATE;
   const auto& d = n->d;
-  // the backward substitution keeps the right-hand side in LDS
-  if (size_t((d.nu + 31) / 32) * 32 * sizeof(double) + 25 * 1024 > size_t(rh::max_lds_bytes()))
-    return RH_ERR_ARG;
   hipStream_t st = n->stream;
   RH_HIP(hipMemcpyAsync(n->bwork, rhs, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, st));
   {
