@@ -274,6 +274,26 @@ rh_status rh_solve_condensed_kkt(rh_net* net, double* K, int64_t ldk, double del
                                  const double* rhs, const double* r, double* p,
                                  int32_t* dev_status);
 
+/* Allocation-free dense solve, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). It is the Cholesky and solve stage of
+ * rh_solve_condensed_kkt, with the same kernels and the same results bit for
+ * bit, on a caller's matrix and with no network handle: K (device,
+ * column-major, n x n, leading dimension ldk >= n; the lower triangle is read)
+ * is factored in place (K + delta_w I = L L^T, L in the lower triangle) and
+ * x (device, n) receives (K + delta_w I)^{-1} b; b (device, n) is not
+ * modified. dev_status (device int32[2]): [0, or 1 when a pivot is not
+ * positive; index of the first such pivot]. The workspaces (5.3 MB) live in
+ * one static device array per device, which the library keeps until the
+ * process ends: every call on a device shares it, so calls that overlap on
+ * one device (other streams, other threads) race. 0 <= n <= 1024, else
+ * RH_ERR_ARG. Enqueued on hip_stream (NULL: the null stream); the call does
+ * not synchronise and returns RH_OK once the work is enqueued: the numerical
+ * outcome is in dev_status. */
+rh_status rh_cholesky_solve_noalloc(double* K, int64_t ldk, int32_t n, double delta_w,
+                                    const double* b, double* x, int32_t* dev_status,
+                                    void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Per-phase device timers (hipEvent pairs on the handle's stream), reported
  * like the paper's per-phase totals (Table 3: Chol., Reduction). Phases:

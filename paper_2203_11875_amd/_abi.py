@@ -89,6 +89,8 @@ SIGNATURES = {
     "rh_condense_reduced_hessian": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                               C.c_int64, vp]),
     "rh_solve_condensed_kkt": (C.c_int, [vp, vp, C.c_int64, C.c_double, vp, vp, vp, vp]),
+    "rh_cholesky_solve_noalloc": (C.c_int, [vp, C.c_int64, C.c_int32, C.c_double, vp, vp, vp,
+                                            vp]),
     "rh_profile_enable": (C.c_int, [vp, C.c_int32]),
     "rh_profile_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "rh_profile_kernel_trace": (C.c_int, [vp, C.POINTER(C.c_int64)]),

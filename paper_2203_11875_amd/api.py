@@ -256,6 +256,26 @@ class Net:
         return p, code
 
 
+def cholesky_solve_noalloc(K, delta_w, b, x, status, stream=None):
+    """rh_cholesky_solve_noalloc: K (n x n float64 CUDA tensor, read as
+    column-major with leading dimension n: a row-major symmetric K is the same
+    matrix) factored in place, x = (K + delta_w I)^{-1} b, status (int32[2]
+    on the device) as in the header. Enqueued on `stream` (a torch stream,
+    default: the current one); the call allocates nothing and does not
+    synchronise."""
+    import torch
+    n = int(b.shape[0])
+    for t_, shape, dt in ((K, (n, n), torch.float64), (b, (n,), torch.float64),
+                          (x, (n,), torch.float64), (status, (2,), torch.int32)):
+        if tuple(t_.shape) != shape or t_.dtype != dt or not t_.is_cuda or not t_.is_contiguous():
+            raise ValueError("cholesky_solve_noalloc: K (n, n), b, x (n,) float64 and status (2,) "
+                             "int32, contiguous device tensors")
+    s = stream if stream is not None else torch.cuda.current_stream(K.device)
+    _check(lib().rh_cholesky_solve_noalloc(_ptr(K), n, n, float(delta_w), _ptr(b), _ptr(x),
+                                           _ptr(status), C.c_void_p(s.cuda_stream)),
+           "rh_cholesky_solve_noalloc")
+
+
 def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), reps=3):
     """Launch-shape autotuner: times the condensation (all columns with the
     right-hand side) of `net` at `point` = (x, u, lam, y, sig_x, sig_u,

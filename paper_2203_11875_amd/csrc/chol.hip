@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "device.hpp"
@@ -543,6 +544,10 @@ __global__ void __launch_bounds__(kThreads) k_chol_back(Inst c, int t) {
 __global__ void k_chol_clear(int* status) {
   if (threadIdx.x < 2) status[threadIdx.x] = 0;
 }
+__global__ void k_chol_copy(double* dst, const double* src, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
 
 __device__ __forceinline__ Inst batch_inst(const BatchArg& q) {
   return Inst{q.K, q.ldk, q.nu, q.delta, q.bwork, q.p, q.cinv, q.lrow, q.status};
@@ -601,6 +606,57 @@ hipError_t launch_batch_cholesky(const BatchArg* args, const std::vector<int>& o
     if (grid > 0) hipLaunchKernelGGL(k_chol_back_b, dim3(grid, 1, B), dim3(kThreads), 0, st, args, t);
   }
   return hipGetLastError();
+}
+
+// ------------------------------------------------ allocation-free solve
+// Workspace of launch_cholesky_solve_noalloc: every device the library runs
+// on holds one copy until the process ends. Layout (doubles): the
+// right-hand-side work vector (kNoallocMaxOrder), the diagonal factor tiles
+// (chol_inv_doubles), then the inverse super-blocks (the largest over
+// orders <= kNoallocMaxOrder: 768^2 at a single 24-panel super-block).
+namespace {
+constexpr size_t kNoallocX = 768 * 768;
+constexpr size_t kNoallocDoubles =
+    size_t(kNoallocMaxOrder) + chol_inv_doubles(kNoallocMaxOrder) + kNoallocX;
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};   // device address of `scratch` per device ordinal
+
+size_t x_doubles(int n) {
+  const int nbk = (n + CB - 1) / CB, sb = chol_superblock(nbk);
+  return size_t((nbk + sb - 1) / sb) * size_t(sb * CB) * size_t(sb * CB);
+}
+}  // namespace
+
+hipError_t noalloc_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_cholesky_solve_noalloc(double* K, long ldk, int n, double delta, const double* b,
+                                         double* x, int* status, hipStream_t st) {
+  if (n < 0 || n > kNoallocMaxOrder || x_doubles(n) > kNoallocX) return hipErrorInvalidValue;
+  double* base = nullptr;
+  const hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return e;
+  double* bw = base;
+  double* dl = bw + kNoallocMaxOrder;
+  double* X = dl + chol_inv_doubles(kNoallocMaxOrder);
+  if (n > 0) hipLaunchKernelGGL(k_chol_copy, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                                st, bw, b, n);
+  return launch_cholesky_solve(K, ldk, n, delta, bw, x, dl, X, status, st, nullptr);
 }
 
 }  // namespace rh

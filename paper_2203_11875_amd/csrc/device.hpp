@@ -179,6 +179,13 @@ hipError_t launch_batch_cholesky(const BatchArg* args, const std::vector<int>& o
 // Panel columns per super-block of an order with nbk 32-column panels: one
 // super-block up to 24 panels (order 768), 16 panels (512 columns) above.
 __host__ __device__ constexpr int chol_superblock(int nbk) { return nbk <= 24 ? nbk : 16; }
+// The same with no workspace argument: the workspaces live in a static device
+// array of the library (one per device, shared by every call on it), for
+// orders up to kNoallocMaxOrder; b is copied there first and left unchanged.
+// hipErrorInvalidValue past the maximum order.
+constexpr int kNoallocMaxOrder = 1024;
+hipError_t launch_cholesky_solve_noalloc(double* K, long ldk, int n, double delta, const double* b,
+                                         double* x, int* status, hipStream_t st);
 // Kernel launches of one launch_cholesky_solve (status clear excluded).
 int chol_launches(int n);
 // Doubles of the Cholesky workspaces of order n (dl and X above).

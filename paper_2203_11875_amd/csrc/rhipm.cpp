@@ -968,6 +968,16 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   return RH_OK;
 }
 
+rh_status rh_cholesky_solve_noalloc(double* K, int64_t ldk, int32_t n, double delta_w,
+                                    const double* b, double* x, int32_t* dev_status,
+                                    void* hip_stream) {
+  if (n < 0 || n > rh::kNoallocMaxOrder || !(delta_w >= 0.0) || !dev_status) return RH_ERR_ARG;
+  if (n > 0 && (!K || !b || !x || ldk < n)) return RH_ERR_ARG;
+  RH_HIP(rh::launch_cholesky_solve_noalloc(K, long(ldk), n, delta_w, b, x, dev_status,
+                                           static_cast<hipStream_t>(hip_stream)));
+  return RH_OK;
+}
+
 rh_status rh_profile_enable(rh_net* n, int32_t on) {
   if (!n) return RH_ERR_ARG;
   for (auto& t : n->timers) {

@@ -31,3 +31,19 @@ def test_every_bound_signature_is_exported():
     assert len(_abi.SIGNATURES) > 40
     for name in _abi.SIGNATURES:
         assert hasattr(lib, name), name
+
+
+def test_noalloc_solve_rejects_bad_arguments_before_any_device_work():
+    """rh_cholesky_solve_noalloc checks its arguments on the host: orders past
+    its static workspace (1024), a negative shift or a missing status word
+    return RH_ERR_ARG without touching the device (the pointers are never
+    dereferenced)."""
+    import ctypes as C
+    from paper_2203_11875_amd import _abi
+    lib = _abi.load()
+    f = lib.rh_cholesky_solve_noalloc
+    dummy = C.c_void_p(0x1000)
+    assert f(dummy, 1025, 1025, 0.0, dummy, dummy, dummy, None) == _abi.RH_ERR_ARG
+    assert f(dummy, 8, 8, -1.0, dummy, dummy, dummy, None) == _abi.RH_ERR_ARG
+    assert f(dummy, 8, 8, 0.0, dummy, dummy, None, None) == _abi.RH_ERR_ARG
+    assert f(dummy, 4, 8, 0.0, dummy, dummy, dummy, None) == _abi.RH_ERR_ARG   # ldk < n
