@@ -109,7 +109,11 @@ typedef struct {
   int64_t levels_lower, levels_upper;  /* level sets of the L / U sweeps         */
   int64_t refactor_ops;                /* multiply-adds of one refactorisation   */
   int64_t max_lu_row;
-  int64_t panel_width, lds_panel;      /* chosen launch shape of the condensation */
+  int64_t panel_width, lds_panel;      /* chosen launch shape of the condensation:
+                                          lds_panel 0 panels in global memory, 1 in
+                                          LDS, 2 in LDS with the sweep metadata read
+                                          from global memory (a panel that fills the
+                                          LDS; one column per work-group) */
   int64_t max_row_ops;                 /* refactorisation multiply-adds of one row */
   int64_t refactor_kernel;             /* 0 wave-resident, 1 level-staged          */
   int64_t steps_lower;                 /* work-group passes of the L sweep         */
@@ -317,8 +321,11 @@ rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
  * work-group of the last condensation launched while profiling was on:
  * [0] start, [1] panel filled, [2] after L, [3] after U (Z), [4] after the
  * Hessian product, [5] after U^T, [6] after L^T (Psi), [7] columns written.
- * [16 + l] end of level l of the L sweep. Host array of 256 entries;
- * synchronises the stream. */
+ * [16 + l] end of level l of the L sweep; [128 + l] end of level l of the
+ * wave-resident refactorisation; [256 + 8 k + j] the Cholesky's diagonal
+ * work-group in factorisation launch k < 24 of the last solve (j = 0 start,
+ * 1 previous panel applied, 2 slice factored, 3 stores issued). Host array
+ * of 512 entries; synchronises the stream. */
 rh_status rh_profile_kernel_trace(rh_net* net, int64_t* ticks);
 
 /* Multiplies the objective (every generator cost coefficient) by scale > 0

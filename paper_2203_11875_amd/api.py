@@ -234,10 +234,19 @@ class Net:
         return {name: (float(ms[k]), int(calls[k])) for k, name in enumerate(_abi.PHASES)}
 
     def profile_kernel_trace(self):
-        t = (C.c_int64 * 256)()
+        t = (C.c_int64 * 512)()
         _check(lib().rh_profile_kernel_trace(self.h, t), "rh_profile_kernel_trace")
         names = ["start", "filled", "L", "U", "hvp", "UT", "LT", "written"]
         out = {names[k]: (t[k] - t[0]) / 100.0 for k in range(8)}   # microseconds
+        # Cholesky factorisation launches: [start, panel k-1 applied, factored,
+        # stores issued] of the diagonal work-group, microseconds from launch 0
+        chol = []
+        for k in range(24):
+            v = [t[256 + 8 * k + j] for j in range(4)]
+            if v[0] == 0:
+                break
+            chol.append([(x - t[256]) / 100.0 for x in v])
+        out["cholesky"] = chol
         return out
 
     def solve_condensed_kkt(self, K, delta_w, rhs, r):

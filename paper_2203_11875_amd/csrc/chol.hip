@@ -8,7 +8,9 @@
 //    of panel k - 1 to the diagonal tile (k, k) and to their own tile on
 //    MFMA, then factor the 64 x 32 slice [A_kk; A_ik] in LDS: every one of
 //    them yields L_kk (redundantly) and its own L_ik = A_ik L_kk^{-T};
-//  * trailing work-groups apply panel k - 1 to the tiles right of column k;
+//  * trailing work-groups apply the panels before k to the tiles right of
+//    column k: to the next column every launch, to the others four panels at
+//    a time (a rank-128 update every fourth launch);
 //  * the forward substitution L y = b rides along (b_i -= L_{i,k-1} y_{k-1}
 //    in the panel work-groups, y_k = L_kk^{-1} b_k), y written over b;
 //  * identity rows: the columns are grouped in super-blocks of S = 32 SB
@@ -34,6 +36,7 @@ namespace rh {
 namespace {
 
 constexpr int CB = 32;          // panel width
+constexpr int kTraceLaunches = 24;   // launches stamped when a trace buffer is given
 constexpr int kThreads = 256;   // four waves per work-group
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -133,6 +136,15 @@ __device__ __forceinline__ d4_t quad_update(d4_t acc, const double* lr, long ldr
 }
 
 // ---------------------------------------------------------------- panel
+// 1 / x to the last bit or so: the hardware reciprocal refined by two Newton
+// steps (x a positive normal number here; other values are flagged by the
+// caller as non-positive pivots).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // In-place factorisation of the 64 x 32 slice P (LDS): rows 0..31 hold the
 // symmetric diagonal tile D (both triangles), rows 32..63 a tile B. On
 // return rows 0..31 hold L = chol(D) (zero above the diagonal) and rows
@@ -143,22 +155,25 @@ __device__ __forceinline__ d4_t quad_update(d4_t acc, const double* lr, long ldr
 // are column j's entries below it) and updates every row's later columns,
 //   T_ic <- alpha_j T_ic - 2^-e_j T_ij T_jc   (d_j = T_jj = alpha_j 2^e_j),
 // which is 2^-e_j d_j times the usual Schur update: no division or square
-// root sits on the pivot-to-pivot chain, and the block's columns are scaled
-// to L = T / sqrt(sigma_j d_j) once at the end (sigma_j: the product of the
-// alphas before pivot j). The block's L columns then go through LDS to the
-// waves to its right, which apply the rank-8 update to their own columns.
+// root sits on the pivot-to-pivot chain. Column j of L is T_.j / sqrt(sigma_j
+// d_j) (sigma_j: the product of the alphas before pivot j). The block's
+// columns go through LDS as they are, T (zero above the diagonal), with the
+// weights 1 / (sigma_j d_j): the waves to its right apply the rank-8 update
+// sum_j T_ij T_cj / (sigma_j d_j) = sum_j L_ij L_cj to their own columns,
+// while the eliminating wave scales its columns to L off that chain.
 // Returns the first column whose pivot is not positive, or -1.
 constexpr int PS = CB + 1;   // LDS row stride of the slice
-__device__ __forceinline__ int panel_factor(double (*P)[PS], double (*Lx)[8][64], int wave,
-                                            int lane) {
+__device__ __forceinline__ int panel_factor(double (*P)[PS], double (*Lx)[8][64],
+                                            double (*Lw)[8], int wave, int lane) {
   double a[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) a[t] = P[lane][8 * wave + t];
   int fl = -1;
+  double sd[8];   // sigma_j d_j of the wave's own pivots
   for (int s = 0; s < 4; ++s) {
     double (*lb)[64] = Lx[s & 1];
+    double* lw = Lw[s & 1];
     if (wave == s) {
-      double sg[8], dg[8];
       double sigma = 1.0;
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
@@ -166,28 +181,38 @@ __device__ __forceinline__ int panel_factor(double (*P)[PS], double (*Lx)[8][64]
         const double d = lane_read(a[jj], j);
         int e;
         const double alpha = frexp(d, &e);
-        sg[jj] = sigma;
-        dg[jj] = d;
+        sd[jj] = sigma * d;
         sigma *= alpha;
         const double bi = ldexp(-a[jj], -e);
 #pragma unroll
         for (int cc = jj + 1; cc < 8; ++cc) a[cc] = fma(bi, lane_read(a[cc], j), alpha * a[cc]);
       }
+      // publish T (zero above the diagonal) and the weights
 #pragma unroll
-      for (int jj = 7; jj >= 0; --jj) {
+      for (int jj = 0; jj < 8; ++jj) {
         const int j = 8 * s + jj;
-        if (!(dg[jj] > 0.0)) fl = j;
-        const double v = a[jj] * rsqrt(sg[jj] * dg[jj]);
-        a[jj] = lane < j ? 0.0 : v;      // above the diagonal of D (and the pivot rows' upper part)
+        a[jj] = lane < j ? 0.0 : a[jj];
         lb[jj][lane] = a[jj];
       }
+      if (lane < 8) {
+        double v = sd[0];
+#pragma unroll
+        for (int jj = 1; jj < 8; ++jj) v = lane == jj ? sd[jj] : v;
+        lw[lane] = rcp_nr(v);
+      }
     }
-    if (s == 3) break;
-    lds_sync();
-    if (wave > s) {
+    if (s < 3) lds_sync();
+    if (wave == s) {
+      // scale the own columns to L while the next wave updates its columns
+#pragma unroll
+      for (int jj = 7; jj >= 0; --jj) {
+        if (!(sd[jj] > 0.0)) fl = 8 * s + jj;
+        a[jj] *= rsqrt(sd[jj]);
+      }
+    } else if (wave > s) {
       double lr[8];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) lr[m] = lb[m][lane];
+      for (int m = 0; m < 8; ++m) lr[m] = lb[m][lane] * lw[m];
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int c = 8 * wave + t;
@@ -213,6 +238,7 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
                                            long long* trace) {
   __shared__ double P[2 * CB][PS];
   __shared__ double Lx[2][8][64];
+  __shared__ double Lw[2][8];
   __shared__ double red[CB], bks[CB];
   __shared__ int fails[4];
   const int n = c.n;
@@ -222,7 +248,7 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
   const int k0 = k * CB, pc0 = k0 - CB;
   const int sg = k / G.sb, kap = k - sg * G.sb, s0 = sg * G.sb;
   double* Xs = c.X + (size_t)sg * G.S * G.S;
-  const bool tr = trace != nullptr && role == ROLE_DIAG && tid == 0;
+  const bool tr = trace != nullptr && role == ROLE_DIAG && tid == 0 && k < kTraceLaunches;
   if (tr) trace[8 * k] = wall_clock64();
   const int bsz = min(CB, n - k0);
   const int bi = k + idx;   // ROLE_ROWS
@@ -251,6 +277,12 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
     const int row = (role == ROLE_DIAG ? k0 : bi * CB) + tid;
     if (row < n) bval = c.b[row];
   }
+  // the factor tile of launch k - 1 (stored to A by this launch's diagonal
+  // group), requested now so that its latency is not at the tail
+  double dlv[CB * CB / kThreads];
+#pragma unroll
+  for (int j = 0; j < CB * CB / kThreads; ++j)
+    dlv[j] = (role == ROLE_DIAG && k > 0) ? c.dl[(size_t)(k - 1) * CB * CB + tid + j * kThreads] : 0.0;
   const double* dbase = c.A + (size_t)(k0 + qj * 16) * ld + k0 + qi * 16;
   const double* safe = c.A;
   d4_t dacc = quad_load(dbase, ld, dq ? n - k0 - qi * 16 : 0, n - k0 - qj * 16, li, kk, safe);
@@ -305,7 +337,7 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
   }
   lds_sync();
   if (tid < CB) bks[tid] = bval - red[tid];
-  const int fl = panel_factor(P, Lx, wave, lane);
+  const int fl = panel_factor(P, Lx, Lw, wave, lane);
   if (lane == 0) fails[wave] = fl;
   __syncthreads();
   if (tr) trace[8 * k + 2] = wall_clock64();
@@ -337,7 +369,9 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
   }
   // ROLE_DIAG
   const bool last = k + 1 == G.nbk;
-  for (int e = tid; e < CB * CB; e += kThreads) {
+#pragma unroll
+  for (int j = 0; j < CB * CB / kThreads; ++j) {
+    const int e = tid + j * kThreads;
     const int r = e % CB, col = e / CB;
     Xs[(size_t)(kap * CB + col) * G.S + kap * CB + r] = P[CB + r][col];   // L_kk^{-T}
     if (last) {
@@ -346,8 +380,7 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
       c.dl[(size_t)k * CB * CB + e] = P[r][col];
     }
     // tile (k - 1, k - 1) is read by no work-group of this launch
-    if (k > 0 && col <= r)
-      c.A[(size_t)(pc0 + col) * ld + pc0 + r] = c.dl[(size_t)(k - 1) * CB * CB + e];
+    if (k > 0 && col <= r) c.A[(size_t)(pc0 + col) * ld + pc0 + r] = dlv[j];
   }
   if (tid < bsz) {   // y_k = L_kk^{-1} b_k, over b_k
     double v = 0.0;
@@ -358,25 +391,89 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
   if (tr) trace[8 * k + 3] = wall_clock64();
 }
 
-// Trailing tile (bi, bj), k < bj <= bi: A_ij -= L(bi, k-1) L(bj, k-1)^T.
+// Trailing update of launch k >= 1 with the panels pf .. k - 1 not yet
+// applied, pf = G floor((k - 1) / G) (G = kGroup): when k is a multiple of G,
+// every tile right of column k (rank 32 G: work-group t covers the 2 x 2
+// tiles bi = k + 1 + 2 RI + (w >> 1), bj = k + 1 + 2 RJ + (w & 1), RJ <= RI,
+// regions enumerated row by row); otherwise only column k + 1, the next
+// panel's (work-group t covers bi = k + 1 + 4 t + w). A tile then has every
+// panel before its own column's but the last applied when its column comes
+// up, and is read and written once per G launches instead of every launch.
+// One 32 x 32 tile per wave, A_ij -= sum_p L(bi, p) L(bj, p)^T on MFMA.
+constexpr int kGroup = 4;
 __device__ __forceinline__ void chol_trailing(const Inst& c, int k, int t) {
-  int ti = 0;
-  while (t > ti) {
-    t -= ti + 1;
-    ++ti;
-  }
-  const int bi = k + 1 + ti, bj = k + 1 + t;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, kk = lane >> 4, qi = wave >> 1, qj = wave & 1;
-  if (bi == bj && qi < qj) return;
+  const int li = lane & 15, kk = lane >> 4;
+  const int nbk = (c.n + CB - 1) / CB;
+  int bi, bj;
+  if (k % kGroup == 0) {
+    int ri = 0;
+    while (t > ri) {
+      t -= ri + 1;
+      ++ri;
+    }
+    bi = k + 1 + 2 * ri + (wave >> 1);
+    bj = k + 1 + 2 * t + (wave & 1);
+  } else {
+    bi = k + 1 + 4 * t + wave;
+    bj = k + 1;
+  }
+  if (bi >= nbk || bj > bi) return;
   const int n = c.n;
   const long ld = c.ld;
-  const int ri = bi * CB + qi * 16, cj = bj * CB + qj * 16, pc0 = (k - 1) * CB;
-  double* base = c.A + (size_t)cj * ld + ri;
-  d4_t acc = quad_load(base, ld, n - ri, n - cj, li, kk, c.A);
-  acc = quad_update(acc, c.A + (size_t)pc0 * ld + ri, ld, n - ri, c.A + (size_t)pc0 * ld + cj, ld,
-                    n - cj, li, kk, c.A);
-  quad_store(base, ld, n - ri, n - cj, li, kk, acc, bi == bj, qi * 16, qj * 16);
+  const int r0 = bi * CB, c0 = bj * CB;
+  const bool diag = bi == bj;
+  d4_t acc[2][2];
+#pragma unroll
+  for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+    for (int qj = 0; qj < 2; ++qj) {
+      double* base = c.A + (size_t)(c0 + qj * 16) * ld + r0 + qi * 16;
+      acc[qi][qj] = (diag && qi < qj) ? d4_t{0.0, 0.0, 0.0, 0.0}
+                                      : quad_load(base, ld, n - r0 - qi * 16, n - c0 - qj * 16,
+                                                  li, kk, c.A);
+    }
+  for (int p = kGroup * ((k - 1) / kGroup); p < k; ++p) {
+    const double* lr = c.A + (size_t)p * CB * ld + r0;
+    const double* lc = c.A + (size_t)p * CB * ld + c0;
+    double bv[2][CB / 4], av[2][CB / 4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+      for (int s = 0; s < CB / 4; ++s) {
+        const int col = 4 * s + kk;
+        bv[q][s] = ld0(lr, (size_t)col * ld + q * 16 + li, r0 + q * 16 + li < n, c.A);
+        av[q][s] = -ld0(lc, (size_t)col * ld + q * 16 + li, c0 + q * 16 + li < n, c.A);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < CB / 4; ++s)
+#pragma unroll
+      for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+        for (int qj = 0; qj < 2; ++qj)
+          if (!(diag && qi < qj))
+            acc[qi][qj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qj][s], bv[qi][s],
+                                                               acc[qi][qj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+    for (int qj = 0; qj < 2; ++qj)
+      if (!(diag && qi < qj))
+        quad_store(c.A + (size_t)(c0 + qj * 16) * ld + r0 + qi * 16, ld, n - r0 - qi * 16,
+                   n - c0 - qj * 16, li, kk, acc[qi][qj], diag, qi * 16, qj * 16);
+}
+
+// Work-groups of the trailing update of launch k (see chol_trailing).
+__host__ __device__ __forceinline__ int chol_trailing_groups(int nbk, int k) {
+  const int T = nbk - 1 - k;
+  if (k < 1 || T < 1) return 0;
+  if (k % kGroup == 0) {
+    const int R = (T + 1) / 2;
+    return R * (R + 1) / 2;
+  }
+  return (T + 3) / 4;
 }
 
 // Identity tile (r, cc) of the super-block, r < kap < cc:
@@ -399,7 +496,7 @@ __device__ __forceinline__ void chol_ident_trailing(const Inst& c, const Geo& G,
 }
 
 // Work-group bid of launch k: [diag | rows | identity panels | identity
-// trailing | trailing | delta].
+// trailing | trailing regions | delta].
 __device__ __forceinline__ void chol_step(const Inst& c, int k, int bid, long long* trace) {
   if (c.status[0] != 0) return;
   const Geo G = geo(c.n);
@@ -407,8 +504,7 @@ __device__ __forceinline__ void chol_step(const Inst& c, int k, int bid, long lo
   const int sg = k / G.sb, kap = k - sg * G.sb, sbn = min(G.sb, G.nbk - sg * G.sb);
   const int nA = G.nbk - k, nB = kap, nDc = sbn - 1 - kap;
   const int nD = kap >= 1 ? kap * nDc : 0;
-  const int T = G.nbk - 1 - k;
-  const int nC = k >= 1 ? T * (T + 1) / 2 : 0;
+  const int nC = chol_trailing_groups(G.nbk, k);
   int t = bid;
   if (t < nA) {
     chol_panel(c, G, k, t == 0 ? ROLE_DIAG : ROLE_ROWS, t, trace);
@@ -442,8 +538,7 @@ __host__ __device__ __forceinline__ int chol_step_groups(int n, int k) {
   const int sb = chol_superblock(nbk);
   const int sg = k / sb, kap = k - sg * sb;
   const int sbn = sb < nbk - sg * sb ? sb : nbk - sg * sb;
-  const int T = nbk - 1 - k;
-  return (nbk - k) + kap + (kap >= 1 ? kap * (sbn - 1 - kap) : 0) + (k >= 1 ? T * (T + 1) / 2 : 0) +
+  return (nbk - k) + kap + (kap >= 1 ? kap * (sbn - 1 - kap) : 0) + chol_trailing_groups(nbk, k) +
          (k == 0 ? 1 : 0);
 }
 

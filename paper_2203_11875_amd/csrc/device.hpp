@@ -22,6 +22,10 @@ struct DevSweep {
 
 struct DevNet {
   int nb, nl, ng, nx, nu, m, nw, nlim, ref, ref_gen;
+  // 1: the condensation's panel fills the LDS, so the kernels read the sweep
+  // metadata from global memory instead of staging it (one column per
+  // work-group)
+  int meta_global;
   double base, c2_ref, c1_ref, cost_rank1;
   const double *c2, *c1, *c0;
   const int* pg_u;
@@ -114,7 +118,7 @@ struct BatchArg {
 // dynamic LDS of the batched launches.
 struct BatchShape {
   int count = 0, width = 1, ntiles = 0;
-  bool lds = true, any_wave = false, any_staged = false;
+  bool lds = true, meta_global = false, any_wave = false, any_staged = false;
   int max_lines = 0, max_dst = 0, max_nnz_k = 0, max_nw = 0, max_nx = 0, max_nu = 0, max_m = 0;
   size_t lds_wave = 0, lds_staged = 0, lds_condense = 0;
   std::vector<int> orders;   // order (nu) of each instance's condensed matrix
@@ -167,8 +171,9 @@ hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
 // status[0..1] (device): 0, or 1 and the first column whose pivot is not
 // positive. Workspaces: dl (chol_inv_doubles(n)), X (chol_lrow_doubles(n):
 // the inverses of the diagonal super-blocks of L^T). trace (optional,
-// device int64[8 ceil(n / 32)]): wall-clock stamps of the diagonal
-// work-group of every factorisation launch.
+// device int64[192]): wall-clock stamps of the diagonal work-group of the
+// first 24 factorisation launches (8 k + 0: start, + 1: panel k - 1 applied,
+// + 2: slice factored, + 3: stores issued).
 hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b, double* x,
                                  double* dl, double* X, int* status, hipStream_t st,
                                  long long* trace = nullptr);

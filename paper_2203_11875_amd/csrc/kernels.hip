@@ -926,10 +926,15 @@ __device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
 // rows; the indicator row is 1 in the right-hand-side / recovery column and
 // multiplies each K row's rt term), then H over its first nw rows (in
 // K-stream order: w row v at hpos[v]).
-template <int W, bool LDS, int mode>
+// PM (panel mode): 0 panels in global memory, 1 panels and sweep metadata in
+// LDS, 2 panels in LDS with the sweep metadata read where it is (global
+// memory, the same for every work-group), for networks whose panel alone
+// fills the LDS.
+template <int W, int PM, int mode>
 __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int col0, int col_end,
                                                 const double* r, const double* vin, double* K,
                                                 long ldk, double* rhs, double* p_out) {
+  constexpr bool LDS = PM != 0;
   extern __shared__ double panel_lds[];
   if (LDS && (size_t)(lds_double*)panel_lds != 0) {   // the records assume LDS address 0
     if (blk == 0 && threadIdx.x == 0) d.status[4] = 1;
@@ -939,28 +944,44 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   double* P = LDS ? panel_lds : d.panel + (size_t)blk * (nw + 1) * W;
   double* H = P;   // H replaces P after the Hessian product
   char* pb = reinterpret_cast<char*>(P);
-  // step metadata of the four sweeps (with their idle steps) and the block
-  // ends of the two record streams, staged in LDS
-  int4* m_sl = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(nw + 1) * W : 0));
-  int4* m_su = m_sl + d.sl.nstep + 1;
-  int4* m_sut = m_su + d.su.nstep + 1;
-  int4* m_slt = m_sut + d.sut.nstep + 1;
-  int* kb_end = reinterpret_cast<int*>(m_slt + d.slt.nstep + 1);
-  int* gt_end = kb_end + d.kb_n;
+  // step metadata of the four sweeps (with their idle steps), staged in LDS
+  // unless PM == 2, then the block ends of the two record streams in LDS
+  int4* mlds = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(nw + 1) * W : 0));
+  const int4 *m_sl, *m_su, *m_sut, *m_slt;
+  int* kb_end;
   // the L sweep of an identity-column tile runs only the steps that can
   // change its panel (the reach of G_u's columns in L)
-  int nsl = d.sl.nstep;
-  if (mode == MODE_COLUMNS && d.lsk_ptr && col0 == 0) {
-    const int a = d.lsk_ptr[blk];
-    nsl = d.lsk_ptr[blk + 1] - a - 1;
-    const int4* src = reinterpret_cast<const int4*>(d.lsk_meta) + a;
-    for (int i = threadIdx.x; i <= nsl; i += kCondThreads) m_sl[i] = src[i];
+  const bool reach = mode == MODE_COLUMNS && d.lsk_ptr && col0 == 0;
+  const int lsk_a = reach ? d.lsk_ptr[blk] : 0;
+  const int nsl = reach ? d.lsk_ptr[blk + 1] - lsk_a - 1 : d.sl.nstep;
+  if constexpr (PM == 2) {
+    m_sl = reach ? reinterpret_cast<const int4*>(d.lsk_meta) + lsk_a
+                 : reinterpret_cast<const int4*>(d.sl.meta);
+    m_su = reinterpret_cast<const int4*>(d.su.meta);
+    m_sut = reinterpret_cast<const int4*>(d.sut.meta);
+    m_slt = reinterpret_cast<const int4*>(d.slt.meta);
+    kb_end = reinterpret_cast<int*>(mlds);
   } else {
-    stage_meta(d.sl, m_sl);
+    int4* s_sl = mlds;
+    int4* s_su = s_sl + d.sl.nstep + 1;
+    int4* s_sut = s_su + d.su.nstep + 1;
+    int4* s_slt = s_sut + d.sut.nstep + 1;
+    if (reach) {
+      const int4* src = reinterpret_cast<const int4*>(d.lsk_meta) + lsk_a;
+      for (int i = threadIdx.x; i <= nsl; i += kCondThreads) s_sl[i] = src[i];
+    } else {
+      stage_meta(d.sl, s_sl);
+    }
+    stage_meta(d.su, s_su);
+    stage_meta(d.sut, s_sut);
+    stage_meta(d.slt, s_slt);
+    m_sl = s_sl;
+    m_su = s_su;
+    m_sut = s_sut;
+    m_slt = s_slt;
+    kb_end = reinterpret_cast<int*>(s_slt + d.slt.nstep + 1);
   }
-  stage_meta(d.su, m_su);
-  stage_meta(d.sut, m_sut);
-  stage_meta(d.slt, m_slt);
+  int* gt_end = kb_end + d.kb_n;
   for (int i = threadIdx.x; i < d.kb_n; i += kCondThreads) kb_end[i] = d.kb_end[i];
   for (int i = threadIdx.x; i < d.gt_nb; i += kCondThreads) gt_end[i] = d.gt_end[i];
   panel_sync<LDS>();
@@ -1076,12 +1097,12 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
                      });
   tick(d, 7);
 }
-template <int W, bool LDS, int mode>
+template <int W, int PM, int mode>
 __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, int col_end,
                                                           const double* r, const double* vin,
                                                           double* K, long ldk, double* rhs,
                                                           double* p_out) {
-  k_condense_body<W, LDS, mode>(d, blockIdx.x, col0, col_end, r, vin, K, ldk, rhs, p_out);
+  k_condense_body<W, PM, mode>(d, blockIdx.x, col0, col_end, r, vin, K, ldk, rhs, p_out);
 }
 
 // x = G_x^{-1} b (TRANS = 0: L then U sweep) or x = G_x^{-T} b (TRANS = 1:
@@ -1089,9 +1110,10 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, i
 // wave, on column 0 of a condensation panel (the records of the handle's
 // panel width W); b and x in natural order. x = scale * solution, plus the
 // old x if accumulate (a Newton step x -= G_x^{-1} g is scale -1).
-template <int W, bool LDS, int TRANS>
+template <int W, int PM, int TRANS>
 __global__ void __launch_bounds__(kCondThreads) k_gx_solve(DevNet d, const double* b, double* x,
                                                           double scale, int accumulate) {
+  constexpr bool LDS = PM != 0;
   extern __shared__ double panel_lds[];
   if (LDS && (size_t)(lds_double*)panel_lds != 0) {   // the records assume LDS address 0
     if (threadIdx.x == 0) d.status[4] = 1;
@@ -1102,10 +1124,18 @@ __global__ void __launch_bounds__(kCondThreads) k_gx_solve(DevNet d, const doubl
   char* pb = reinterpret_cast<char*>(P);
   const DevSweep& s1 = TRANS ? d.sut : d.sl;
   const DevSweep& s2 = TRANS ? d.slt : d.su;
-  int4* m1 = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(nw + 1) * W : 0));
-  int4* m2 = m1 + s1.nstep + 1;
-  stage_meta(s1, m1);
-  stage_meta(s2, m2);
+  const int4 *m1, *m2;
+  if constexpr (PM == 2) {
+    m1 = reinterpret_cast<const int4*>(s1.meta);
+    m2 = reinterpret_cast<const int4*>(s2.meta);
+  } else {
+    int4* l1 = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(nw + 1) * W : 0));
+    int4* l2 = l1 + s1.nstep + 1;
+    stage_meta(s1, l1);
+    stage_meta(s2, l2);
+    m1 = l1;
+    m2 = l2;
+  }
   for (int i = tid; i < (nw + 1) * W; i += T) P[i] = 0.0;
   panel_sync<LDS>();
   if (TRANS)
@@ -1239,17 +1269,17 @@ __global__ void k_symmetrize(double* K, long ld, int n) {
   k_symmetrize_body(K, ld, n);
 }
 
-template <int W, bool LDS>
+template <int W, int PM>
 hipError_t launch_condense_t(const DevNet& d, int col0, int ncols, int mode, const double* r,
                              const double* vin, double* K, long ldk, double* rhs, double* p,
                              hipStream_t st) {
   const int nblk = (ncols + W - 1) / W;
-  const size_t lds = condense_lds_bytes(d, W, LDS);
+  const size_t lds = condense_lds_bytes(d, W, PM != 0);
   if (mode == MODE_RECOVER)
-    hipLaunchKernelGGL((k_condense<W, LDS, MODE_RECOVER>), dim3(nblk), dim3(kCondThreads), lds,
+    hipLaunchKernelGGL((k_condense<W, PM, MODE_RECOVER>), dim3(nblk), dim3(kCondThreads), lds,
                        st, d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
   else
-    hipLaunchKernelGGL((k_condense<W, LDS, MODE_COLUMNS>), dim3(nblk), dim3(kCondThreads), lds,
+    hipLaunchKernelGGL((k_condense<W, PM, MODE_COLUMNS>), dim3(nblk), dim3(kCondThreads), lds,
                        st, d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
   return hipGetLastError();
 }
@@ -1258,6 +1288,10 @@ template <bool LDS>
 hipError_t dispatch_width(const DevNet& d, int col0, int ncols, int width, int mode,
                           const double* r, const double* vin, double* K, long ldk, double* rhs,
                           double* p, hipStream_t st) {
+  if (LDS && d.meta_global) {   // panel mode 2: one column per work-group only
+    if (width != 1) return hipErrorInvalidValue;
+    return launch_condense_t<1, 2>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+  }
   switch (width) {
     case 1: return launch_condense_t<1, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     case 2: return launch_condense_t<2, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
@@ -1323,15 +1357,15 @@ __global__ void __launch_bounds__(kBlock) k_transcribe_b(const DevNet* __restric
   k_transcribe_body(nets[blockIdx.z]);
 }
 // work-group g takes tile tiles[g] = {instance, tile of W columns}
-template <int W, bool LDS>
+template <int W, int PM>
 __global__ void __launch_bounds__(kCondThreads) k_condense_b(const DevNet* __restrict__ nets,
                                                             const BatchArg* __restrict__ a,
                                                             const int2* __restrict__ tiles) {
   const int2 t = tiles[blockIdx.x];
   const DevNet& d = nets[t.x];
   const BatchArg& q = a[t.x];
-  k_condense_body<W, LDS, MODE_COLUMNS>(d, t.y, 0, d.nu + 1, q.r, nullptr, q.K, q.ldk, q.rhs,
-                                        nullptr);
+  k_condense_body<W, PM, MODE_COLUMNS>(d, t.y, 0, d.nu + 1, q.r, nullptr, q.K, q.ldk, q.rhs,
+                                       nullptr);
 }
 __global__ void k_symmetrize_b(const BatchArg* __restrict__ a) {
   const BatchArg& q = a[blockIdx.z];
@@ -1361,9 +1395,11 @@ __global__ void __launch_bounds__(kBlock) k_finish_step_b(const DevNet* __restri
 
 size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels) {
   static_assert(kSweepMeta == 4, "one int4 of metadata per step");
-  const size_t meta = sizeof(int) * (kSweepMeta * (size_t)(d.sl.nstep + d.su.nstep + d.sut.nstep +
-                                                           d.slt.nstep + 4) +
-                                     (size_t)d.kb_n + (size_t)d.gt_nb);
+  const size_t sweeps = (lds_panels && d.meta_global)
+                            ? 0
+                            : kSweepMeta * (size_t)(d.sl.nstep + d.su.nstep + d.sut.nstep +
+                                                    d.slt.nstep + 4);
+  const size_t meta = sizeof(int) * (sweeps + (size_t)d.kb_n + (size_t)d.gt_nb);
   return (lds_panels ? (size_t)(d.nw + 1) * width * sizeof(double) : 0) + meta;
 }
 
@@ -1373,60 +1409,65 @@ void prepare_lds_kernels() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor_wave),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   const void* fns[] = {
-      reinterpret_cast<const void*>(&k_condense<1, true, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<2, true, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<3, true, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<4, true, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<8, true, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<1, true, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<2, true, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<3, true, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<4, true, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<8, true, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_gx_solve<1, true, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<2, true, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<3, true, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<4, true, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<8, true, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<1, true, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<2, true, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<3, true, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<4, true, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<8, true, 1>)};
+      reinterpret_cast<const void*>(&k_condense<1, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<2, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<3, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<4, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<8, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<2, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<3, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<4, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<8, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, 1, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, 1, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, 1, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, 1, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, 1, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, 1, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, 1, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, 1, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, 1, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, 1, 1>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, 2, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, 2, 1>)};
   const void* gfns[] = {
-      reinterpret_cast<const void*>(&k_condense<1, false, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<2, false, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<3, false, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<4, false, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<8, false, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<1, false, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<2, false, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<3, false, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<4, false, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<8, false, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_gx_solve<1, false, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<2, false, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<3, false, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<4, false, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<8, false, 0>),
-      reinterpret_cast<const void*>(&k_gx_solve<1, false, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<2, false, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<3, false, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<4, false, 1>),
-      reinterpret_cast<const void*>(&k_gx_solve<8, false, 1>)};
+      reinterpret_cast<const void*>(&k_condense<1, 0, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<2, 0, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<3, 0, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<4, 0, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<8, 0, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 0, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<2, 0, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<3, 0, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<4, 0, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<8, 0, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, 0, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, 0, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, 0, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, 0, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, 0, 0>),
+      reinterpret_cast<const void*>(&k_gx_solve<1, 0, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<2, 0, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<3, 0, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<4, 0, 1>),
+      reinterpret_cast<const void*>(&k_gx_solve<8, 0, 1>)};
   for (const void* f : fns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   const void* bfns[] = {
-      reinterpret_cast<const void*>(&k_condense_b<1, true>),
-      reinterpret_cast<const void*>(&k_condense_b<2, true>),
-      reinterpret_cast<const void*>(&k_condense_b<3, true>),
-      reinterpret_cast<const void*>(&k_condense_b<4, true>),
-      reinterpret_cast<const void*>(&k_condense_b<8, true>),
-      reinterpret_cast<const void*>(&k_condense_b<1, false>),
-      reinterpret_cast<const void*>(&k_condense_b<2, false>),
-      reinterpret_cast<const void*>(&k_condense_b<3, false>),
-      reinterpret_cast<const void*>(&k_condense_b<4, false>),
-      reinterpret_cast<const void*>(&k_condense_b<8, false>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 2>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 1>),
+      reinterpret_cast<const void*>(&k_condense_b<2, 1>),
+      reinterpret_cast<const void*>(&k_condense_b<3, 1>),
+      reinterpret_cast<const void*>(&k_condense_b<4, 1>),
+      reinterpret_cast<const void*>(&k_condense_b<8, 1>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 0>),
+      reinterpret_cast<const void*>(&k_condense_b<2, 0>),
+      reinterpret_cast<const void*>(&k_condense_b<3, 0>),
+      reinterpret_cast<const void*>(&k_condense_b<4, 0>),
+      reinterpret_cast<const void*>(&k_condense_b<8, 0>),
       reinterpret_cast<const void*>(&k_refactor_wave_b),
       reinterpret_cast<const void*>(&k_refactor_b)};
   for (const void* f : bfns)
@@ -1499,17 +1540,21 @@ hipError_t launch_recover(const DevNet& d, int width, bool lds, const double* pu
   return dispatch_width<false>(d, 0, 1, width, MODE_RECOVER, r, pu, nullptr, 0, nullptr, p, st);
 }
 
-template <int W, bool LDS, int TRANS>
+template <int W, int PM, int TRANS>
 hipError_t launch_gx_solve_t(const DevNet& d, const double* b, double* x, double scale,
                              int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL((k_gx_solve<W, LDS, TRANS>), dim3(1), dim3(kCondThreads),
-                     condense_lds_bytes(d, W, LDS), st, d, b, x, scale, accumulate);
+  hipLaunchKernelGGL((k_gx_solve<W, PM, TRANS>), dim3(1), dim3(kCondThreads),
+                     condense_lds_bytes(d, W, PM != 0), st, d, b, x, scale, accumulate);
   return hipGetLastError();
 }
 
 template <bool LDS, int TRANS>
 hipError_t gx_solve_width(const DevNet& d, int width, const double* b, double* x, double scale,
                           int accumulate, hipStream_t st) {
+  if (LDS && d.meta_global) {
+    if (width != 1) return hipErrorInvalidValue;
+    return launch_gx_solve_t<1, 2, TRANS>(d, b, x, scale, accumulate, st);
+  }
   switch (width) {
     case 1: return launch_gx_solve_t<1, LDS, TRANS>(d, b, x, scale, accumulate, st);
     case 2: return launch_gx_solve_t<2, LDS, TRANS>(d, b, x, scale, accumulate, st);
@@ -1572,18 +1617,21 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
 #define RH_BATCH_COND(WW, LL)                                                                   \
   hipLaunchKernelGGL((k_condense_b<WW, LL>), dim3(sh.ntiles), dim3(kCondThreads), sh.lds_condense, \
                      st, nets, args, tiles)
-  if (sh.lds) {
-    if (W == 1) RH_BATCH_COND(1, true);
-    else if (W == 2) RH_BATCH_COND(2, true);
-    else if (W == 3) RH_BATCH_COND(3, true);
-    else if (W == 4) RH_BATCH_COND(4, true);
-    else RH_BATCH_COND(8, true);
+  if (sh.lds && sh.meta_global) {
+    if (W != 1) return hipErrorInvalidValue;
+    RH_BATCH_COND(1, 2);
+  } else if (sh.lds) {
+    if (W == 1) RH_BATCH_COND(1, 1);
+    else if (W == 2) RH_BATCH_COND(2, 1);
+    else if (W == 3) RH_BATCH_COND(3, 1);
+    else if (W == 4) RH_BATCH_COND(4, 1);
+    else RH_BATCH_COND(8, 1);
   } else {
-    if (W == 1) RH_BATCH_COND(1, false);
-    else if (W == 2) RH_BATCH_COND(2, false);
-    else if (W == 3) RH_BATCH_COND(3, false);
-    else if (W == 4) RH_BATCH_COND(4, false);
-    else RH_BATCH_COND(8, false);
+    if (W == 1) RH_BATCH_COND(1, 0);
+    else if (W == 2) RH_BATCH_COND(2, 0);
+    else if (W == 3) RH_BATCH_COND(3, 0);
+    else if (W == 4) RH_BATCH_COND(4, 0);
+    else RH_BATCH_COND(8, 0);
   }
 #undef RH_BATCH_COND
   hipLaunchKernelGGL(k_symmetrize_b, dim3(cdiv(sh.max_nu, 16), cdiv(sh.max_nu, 16), B),

@@ -412,8 +412,8 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(alloc(n, rh::chol_inv_doubles(s.nu), &n->cinv));
   RH_TRY(alloc(n, rh::chol_lrow_doubles(s.nu), &n->lrow));
   RH_TRY(alloc(n, 8, &n->status));
-  RH_TRY(alloc(n, 256, &n->trace));
-  RH_HIP(hipMemset(n->trace, 0, 256 * sizeof(long long)));
+  RH_TRY(alloc(n, 512, &n->trace));
+  RH_HIP(hipMemset(n->trace, 0, 512 * sizeof(long long)));
   d.trace = nullptr;
   d.status = n->status;
   RH_HIP(hipMemset(n->status, 0, 8 * sizeof(int)));
@@ -423,10 +423,21 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   if (want != 1 && want != 2 && want != 3 && want != 4 && want != 8) return RH_ERR_ARG;
   bool lds = !opts || opts->lds_panel != 0;
   if (lds && rh::condense_lds_bytes(d, want, true) > lds_max) {
-    // keep the panels in LDS with a narrower tile if possible
+    // keep the panels in LDS with a narrower tile if possible, then with the
+    // sweep metadata left in global memory (one column per work-group)
     int w = want;
     while (w > 1 && rh::condense_lds_bytes(d, w, true) > lds_max) w = (w == 8 ? 4 : w - 1);
-    if (rh::condense_lds_bytes(d, w, true) <= lds_max) want = w; else lds = false;
+    if (rh::condense_lds_bytes(d, w, true) <= lds_max) {
+      want = w;
+    } else {
+      d.meta_global = 1;
+      if (rh::condense_lds_bytes(d, 1, true) <= lds_max) {
+        want = 1;
+      } else {
+        d.meta_global = 0;
+        lds = false;
+      }
+    }
   }
   n->width = want;
   n->lds = lds;
@@ -562,7 +573,7 @@ rh_status rh_get_info(const rh_net* n, rh_info* info) {
   if (!n || !info) return RH_ERR_ARG;
   fill_info(n->s, info);
   info->panel_width = n->width;
-  info->lds_panel = n->lds ? 1 : 0;
+  info->lds_panel = n->lds ? (n->d.meta_global ? 2 : 1) : 0;
   return RH_OK;
 }
 
@@ -622,12 +633,19 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
       sh.any_staged = true;
       sh.lds_staged = std::max(sh.lds_staged, size_t(d.rf_lds_doubles) * sizeof(double));
     }
-    sh.lds_condense = std::max(sh.lds_condense, rh::condense_lds_bytes(d, sh.width, sh.lds));
+    sh.meta_global = sh.meta_global || d.meta_global != 0;
     sh.orders.push_back(d.nu);
     const int ntile = (d.nu + 1 + sh.width - 1) / sh.width;
     for (int t = 0; t < ntile; ++t) tiles.push_back(int2{i, t});
   }
   sh.ntiles = int(tiles.size());
+  // one panel mode for the whole launch: the sweep metadata of every member
+  // is read from global memory when one member's panel fills the LDS
+  for (int i = 0; i < count; ++i) {
+    rh::DevNet dd = nets[i]->d;
+    dd.meta_global = sh.meta_global ? 1 : 0;
+    sh.lds_condense = std::max(sh.lds_condense, rh::condense_lds_bytes(dd, sh.width, sh.lds));
+  }
   if (sh.lds_wave > lds_max || sh.lds_staged > lds_max || sh.lds_condense > lds_max) {
     delete b;
     return RH_ERR_ARG;
@@ -941,7 +959,7 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
     // L y = b is solved into p[0:nu], then L^T p_u = y in place
     PhaseScope ps(n, RH_PHASE_CHOLESKY);
     RH_HIP(rh::launch_cholesky_solve(K, long(ldk), d.nu, delta_w, n->bwork, p, n->cinv, n->lrow,
-                                     n->status, st));
+                                     n->status, st, n->profiling ? n->trace + 256 : nullptr));
   }
   {
     PhaseScope ps(n, RH_PHASE_RECOVER);
@@ -993,9 +1011,9 @@ rh_status rh_profile_enable(rh_net* n, int32_t on) {
 rh_status rh_profile_kernel_trace(rh_net* n, int64_t* ticks) {
   if (!n || !ticks) return RH_ERR_ARG;
   RH_HIP(hipStreamSynchronize(n->stream));
-  long long h[256];
+  long long h[512];
   RH_HIP(hipMemcpy(h, n->trace, sizeof(h), hipMemcpyDeviceToHost));
-  for (int k = 0; k < 256; ++k) ticks[k] = h[k];
+  for (int k = 0; k < 512; ++k) ticks[k] = h[k];
   return RH_OK;
 }
 
