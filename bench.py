@@ -292,7 +292,9 @@ def other_stages(info, phases, steps):
     """The step's other large stages and what bounds them: the refactorisation
     is one work-group walking the level sets of L (a dependency chain, not a
     bandwidth or MFMA limit); the Cholesky of the nu x nu condensed matrix is
-    n^3 / 3 flops on FP64 MFMA in one launch per 32-column block."""
+    n^3 / 3 flops on FP64 MFMA in one launch per 32-column panel, then one
+    matrix-vector product per inverse super-block (and one between two of
+    them) for the backward substitution."""
     nu = info["nu"]
     ref_us = 1e3 * phases["refactor"][0] / steps
     chol_us = 1e3 * phases["cholesky"][0] / steps
@@ -302,7 +304,17 @@ def other_stages(info, phases, steps):
                          "us_per_level": ref_us / max(1, info["levels_lower"])},
             "cholesky": {"us": chol_us, "bound": "mfma", "flops": flops, "achieved": tf,
                          "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
-                         "launches": (nu + 31) // 32 + 1}}
+                         "launches": chol_launches(nu)}}
+
+
+def chol_launches(n):
+    """Kernel launches of one Cholesky + solve of order n: one per 32-column
+    panel, 2 s - 1 for the backward substitution over s super-blocks (one
+    super-block up to 24 panels, 16-panel super-blocks above), and the
+    status clear."""
+    nbk = (n + 31) // 32
+    sb = nbk if nbk <= 24 else 16
+    return nbk + 2 * ((nbk + sb - 1) // sb) - 1 + 1
 
 
 def algorithmic_bytes(info, ncols):

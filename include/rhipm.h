@@ -188,7 +188,7 @@ rh_status rh_set_loads(rh_net* net, const double* pd_dev, const double* qd_dev);
 
 /* ---------------------------------------------------------------------------
  * Batches (several networks or load scenarios condensed and solved together;
- * Sections 3.3-3.4 per instance). A batch refers to existing handles, which
+ * Section 3.3 per instance). A batch refers to existing handles, which
  * must share the panel width and LDS placement (the defaults do) and must
  * not be used by other calls while a batch call runs (each batch call first
  * waits for the instances' own streams); the handles outlive the batch. Every batched kernel serves all instances in one launch, with

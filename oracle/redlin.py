@@ -8,7 +8,7 @@ the reduced problem
     min f_r(u)  s.t.  h_r(u) + s = 0,  ul <= u <= uu,  sl <= s <= su,
     f_r(u) = f(x(u), u),  h_r(u) = [h(x(u), u); -x_b(u)]
 is solved by an interior-point method. x_b are the states with bounds (Vm at
-PQ buses; angles are free), whose bounds move into h_r (Section 2.3.2,
+PQ buses; angles are free), whose bounds move into h_r (Section 2.3.1,
 difference (ii)); their slacks are s_x = x_b with bounds [xl, xu].
 
 Every iteration:

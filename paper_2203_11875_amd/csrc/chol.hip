@@ -648,12 +648,12 @@ __device__ __forceinline__ Inst batch_inst(const BatchArg& q) {
   return Inst{q.K, q.ldk, q.nu, q.delta, q.bwork, q.p, q.cinv, q.lrow, q.status};
 }
 __global__ void __launch_bounds__(kThreads) k_chol_b(const BatchArg* __restrict__ a, int k) {
-  const Inst c = batch_inst(a[blockIdx.z]);
+  const Inst c = batch_inst(cst(a, blockIdx.z));
   if ((int)blockIdx.x >= chol_step_groups(c.n, k)) return;
   chol_step(c, k, blockIdx.x, nullptr);
 }
 __global__ void __launch_bounds__(kThreads) k_chol_back_b(const BatchArg* __restrict__ a, int t) {
-  const Inst c = batch_inst(a[blockIdx.z]);
+  const Inst c = batch_inst(cst(a, blockIdx.z));
   if ((int)blockIdx.x >= chol_back_groups(c.n, t)) return;
   chol_back(c, t, blockIdx.x);
 }

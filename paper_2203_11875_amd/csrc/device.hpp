@@ -9,6 +9,16 @@
 
 namespace rh {
 
+// Read-only descriptor arrays of the batched launches (written by the host
+// before the launch, never by a kernel) are read through the constant
+// address space: pointers loaded from constant memory are known to address
+// global memory, so the kernels use global rather than flat loads and
+// stores through them (a flat load also holds up every wait for LDS).
+template <class T>
+__device__ __forceinline__ const T& cst(const T* p, int i) {
+  return *(const T*)((const __attribute__((address_space(4))) T*)p + i);
+}
+
 struct DevSweep {
   int nlev = 0;
   const int* lev_ptr = nullptr;   // nlev + 1: level sets (refactorisation schedule)
@@ -119,6 +129,7 @@ struct BatchArg {
 struct BatchShape {
   int count = 0, width = 1, ntiles = 0;
   bool lds = true, meta_global = false, any_wave = false, any_staged = false;
+  int max_split = 0, max_split_grid = 0;   // refactorisation levels run one launch each
   int max_lines = 0, max_dst = 0, max_nnz_k = 0, max_nw = 0, max_nx = 0, max_nu = 0, max_m = 0;
   size_t lds_wave = 0, lds_staged = 0, lds_condense = 0;
   std::vector<int> orders;   // order (nu) of each instance's condensed matrix

@@ -394,33 +394,33 @@ __device__ __forceinline__ bool ipm_active(const double* sc) {
 __global__ void __launch_bounds__(kVec) k_ipm_lag_grad_b(const DevNet* nets, const IpmDev* ipms,
                                                         const double* sc) {
   if (!ipm_active(sc)) return;
-  ipm_lag_grad_body(nets[blockIdx.z], ipms[blockIdx.z]);
+  ipm_lag_grad_body(cst(nets, blockIdx.z), cst(ipms, blockIdx.z));
 }
 __global__ void __launch_bounds__(kRed) k_ipm_stats_b(const DevNet* nets, const IpmDev* ipms,
                                                      const double* sc, int trial, int full) {
   if (!ipm_active(sc)) return;
-  const IpmDev& v = ipms[blockIdx.z];
-  ipm_stats_body(nets[blockIdx.z], v, trial ? v.wt : v.w, trial ? v.st : v.s, full);
+  const IpmDev& v = cst(ipms, blockIdx.z);
+  ipm_stats_body(cst(nets, blockIdx.z), v, trial ? v.wt : v.w, trial ? v.st : v.s, full);
 }
 __global__ void __launch_bounds__(kVec) k_ipm_prep_b(const DevNet* nets, const IpmDev* ipms,
                                                     const double* sc) {
   if (!ipm_active(sc)) return;
-  ipm_prep_body(nets[blockIdx.z], ipms[blockIdx.z], sc[kIpmSc * blockIdx.z + IS_MU]);
+  ipm_prep_body(cst(nets, blockIdx.z), cst(ipms, blockIdx.z), sc[kIpmSc * blockIdx.z + IS_MU]);
 }
 __global__ void __launch_bounds__(kRed) k_ipm_dir_b(const IpmDev* ipms, const double* sc) {
   if (!ipm_active(sc)) return;
   const double* q = sc + kIpmSc * blockIdx.z;
-  ipm_dir_body(ipms[blockIdx.z], q[IS_MU], q[IS_TAU]);
+  ipm_dir_body(cst(ipms, blockIdx.z), q[IS_MU], q[IS_TAU]);
 }
 __global__ void __launch_bounds__(kVec) k_ipm_trial_b(const IpmDev* ipms, const double* sc) {
   if (!ipm_active(sc)) return;
-  ipm_trial_body(ipms[blockIdx.z], sc[kIpmSc * blockIdx.z + IS_ALPHA]);
+  ipm_trial_body(cst(ipms, blockIdx.z), sc[kIpmSc * blockIdx.z + IS_ALPHA]);
 }
 __global__ void __launch_bounds__(kVec) k_ipm_update_b(const IpmDev* ipms, const double* sc,
                                                       double ks) {
   if (!ipm_active(sc)) return;
   const double* q = sc + kIpmSc * blockIdx.z;
-  ipm_update_body(ipms[blockIdx.z], q[IS_ALPHA], q[IS_ALPHA_Z], q[IS_MU], ks);
+  ipm_update_body(cst(ipms, blockIdx.z), q[IS_ALPHA], q[IS_ALPHA_Z], q[IS_MU], ks);
 }
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }

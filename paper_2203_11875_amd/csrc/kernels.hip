@@ -1251,8 +1251,8 @@ __global__ void __launch_bounds__(kBlock) k_objective_b(const DevNet* __restrict
                                                        const IpmDev* __restrict__ ipms,
                                                        const double* sc, int trial) {
   if (sc[kIpmSc * blockIdx.z + IS_ACTIVE] == 0.0) return;
-  const DevNet& d = nets[blockIdx.z];
-  const IpmDev& v = ipms[blockIdx.z];
+  const DevNet& d = cst(nets, blockIdx.z);
+  const IpmDev& v = cst(ipms, blockIdx.z);
   k_objective_body(d, trial ? v.wt : v.w, d.c2, d.c1, d.c0, d.pg_u, v.f + trial);
 }
 
@@ -1315,16 +1315,16 @@ __global__ void __launch_bounds__(kBlock) k_eval_lines_b(const DevNet* __restric
                                                         const BatchArg* __restrict__ a,
                                                         int hessian) {
   const int b = blockIdx.z;
-  k_eval_lines_body(nets[b], a[b].x, a[b].u, a[b].lam, a[b].y, hessian);
+  k_eval_lines_body(cst(nets, b), cst(a, b).x, cst(a, b).u, cst(a, b).lam, cst(a, b).y, hessian);
 }
 __global__ void __launch_bounds__(kBlock) k_gather_b(const DevNet* __restrict__ nets) {
-  const DevNet& d = nets[blockIdx.z];
+  const DevNet& d = cst(nets, blockIdx.z);
   k_gather_body(d.d_total, d.eg_ptr, d.eg_idx, d.eg_coef, d.eg_cst, d.src, d.dst);
 }
 // per-instance vector copies kept by the handles (Sigma_s for the recovery,
 // the right-hand side for the Cholesky solve): dst[i] = src[i], i < n
 __global__ void __launch_bounds__(kBlock) k_copy_b(const BatchArg* __restrict__ a, int which) {
-  const BatchArg& q = a[blockIdx.z];
+  const BatchArg& q = cst(a, blockIdx.z);
   const double* src = which == 0 ? q.sig_s : q.rhs;
   double* dst = which == 0 ? q.sig_s_keep : q.bwork;
   const int n = which == 0 ? q.m : q.nu;
@@ -1334,27 +1334,35 @@ __global__ void __launch_bounds__(kBlock) k_copy_b(const BatchArg* __restrict__ 
 __global__ void __launch_bounds__(kBlock) k_assemble_k_b(const DevNet* __restrict__ nets,
                                                         const BatchArg* __restrict__ a) {
   const int b = blockIdx.z;
-  k_assemble_k_body(nets[b], a[b].sig_x, a[b].sig_u, a[b].sig_s);
+  k_assemble_k_body(cst(nets, b), cst(a, b).sig_x, cst(a, b).sig_u, cst(a, b).sig_s);
 }
 __global__ void __launch_bounds__(kBlock) k_rtilde_b(const DevNet* __restrict__ nets,
                                                     const BatchArg* __restrict__ a) {
   const int b = blockIdx.z;
-  k_rtilde_body(nets[b], a[b].r, a[b].sig_s_keep);
+  k_rtilde_body(cst(nets, b), cst(a, b).r, cst(a, b).sig_s_keep);
 }
 // status[first .. first + count) = 0 for every instance
 __global__ void k_clear_status_b(const DevNet* __restrict__ nets, int first, int count) {
-  if ((int)threadIdx.x < count) nets[blockIdx.z].status[first + threadIdx.x] = 0;
+  if ((int)threadIdx.x < count) cst(nets, blockIdx.z).status[first + threadIdx.x] = 0;
+}
+// Levels 1 .. rw_split of every instance with the wave-resident
+// refactorisation, one launch per level for the batch (instances with fewer
+// split levels skip), then the wave-resident kernel from each instance's split.
+__global__ void __launch_bounds__(64) k_refactor_level_b(const DevNet* __restrict__ nets, int lev) {
+  const DevNet& d = cst(nets, blockIdx.z);
+  if (!d.rw_ok || lev > d.rw_split) return;
+  k_refactor_level_body(d, lev);
 }
 __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave_b(const DevNet* __restrict__ nets) {
-  const DevNet& d = nets[blockIdx.z];
-  if (d.rw_ok) k_refactor_wave_body(d, 0);
+  const DevNet& d = cst(nets, blockIdx.z);
+  if (d.rw_ok) k_refactor_wave_body(d, d.rw_split);
 }
 __global__ void __launch_bounds__(kRefThreads) k_refactor_b(const DevNet* __restrict__ nets) {
-  const DevNet& d = nets[blockIdx.z];
+  const DevNet& d = cst(nets, blockIdx.z);
   if (!d.rw_ok) k_refactor_body(d);
 }
 __global__ void __launch_bounds__(kBlock) k_transcribe_b(const DevNet* __restrict__ nets) {
-  k_transcribe_body(nets[blockIdx.z]);
+  k_transcribe_body(cst(nets, blockIdx.z));
 }
 // work-group g takes tile tiles[g] = {instance, tile of W columns}
 template <int W, int PM>
@@ -1362,33 +1370,33 @@ __global__ void __launch_bounds__(kCondThreads) k_condense_b(const DevNet* __res
                                                             const BatchArg* __restrict__ a,
                                                             const int2* __restrict__ tiles) {
   const int2 t = tiles[blockIdx.x];
-  const DevNet& d = nets[t.x];
-  const BatchArg& q = a[t.x];
+  const DevNet& d = cst(nets, t.x);
+  const BatchArg& q = cst(a, t.x);
   k_condense_body<W, PM, MODE_COLUMNS>(d, t.y, 0, d.nu + 1, q.r, nullptr, q.K, q.ldk, q.rhs,
                                        nullptr);
 }
 __global__ void k_symmetrize_b(const BatchArg* __restrict__ a) {
-  const BatchArg& q = a[blockIdx.z];
+  const BatchArg& q = cst(a, blockIdx.z);
   k_symmetrize_body(q.K, q.ldk, q.nu);
 }
 __global__ void __launch_bounds__(kBlock) k_recover_partial_b(const DevNet* __restrict__ nets,
                                                              const BatchArg* __restrict__ a) {
   const int b = blockIdx.z;
-  k_recover_partial_body(nets[b], a[b].p);
+  k_recover_partial_body(cst(nets, b), cst(a, b).p);
 }
 __global__ void __launch_bounds__(kBlock) k_recover_finish_b(const DevNet* __restrict__ nets,
                                                             const BatchArg* __restrict__ a) {
   const int b = blockIdx.z;
-  k_recover_finish_body(nets[b], a[b].p);
+  k_recover_finish_body(cst(nets, b), cst(a, b).p);
 }
 // out[5 b + i] = status[i] of instance b, i < 5
 __global__ void k_gather_status_b(const DevNet* __restrict__ nets, int* out) {
-  if (threadIdx.x < 5) out[5 * blockIdx.z + threadIdx.x] = nets[blockIdx.z].status[threadIdx.x];
+  if (threadIdx.x < 5) out[5 * blockIdx.z + threadIdx.x] = cst(nets, blockIdx.z).status[threadIdx.x];
 }
 __global__ void __launch_bounds__(kBlock) k_finish_step_b(const DevNet* __restrict__ nets,
                                                          const BatchArg* __restrict__ a) {
   const int b = blockIdx.z;
-  k_finish_step_body(nets[b], a[b].r, a[b].sig_s_keep, a[b].p);
+  k_finish_step_body(cst(nets, b), cst(a, b).r, cst(a, b).sig_s_keep, cst(a, b).p);
 }
 
 }  // namespace
@@ -1607,9 +1615,13 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
   hipLaunchKernelGGL(k_rtilde_b, dim3(cdiv(sh.max_nw, kBlock), 1, B), dim3(kBlock), 0, st, nets,
                      args);
   hipLaunchKernelGGL(k_clear_status_b, dim3(1, 1, B), dim3(64), 0, st, nets, 2, 2);
-  if (sh.any_wave)
+  if (sh.any_wave) {
+    for (int lev = 1; lev <= sh.max_split; ++lev)
+      hipLaunchKernelGGL(k_refactor_level_b, dim3(sh.max_split_grid, kRwWaves, B), dim3(64), 0, st,
+                         nets, lev);
     hipLaunchKernelGGL(k_refactor_wave_b, dim3(1, 1, B), dim3(kRwWaves * 64), sh.lds_wave, st,
                        nets);
+  }
   if (sh.any_staged)
     hipLaunchKernelGGL(k_refactor_b, dim3(1, 1, B), dim3(kRefThreads), sh.lds_staged, st, nets);
   hipLaunchKernelGGL(k_transcribe_b, dim3(64, 1, B), dim3(kBlock), 0, st, nets);

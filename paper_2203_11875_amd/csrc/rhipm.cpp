@@ -627,6 +627,8 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
     sh.max_m = std::max(sh.max_m, d.m);
     if (d.rw_ok) {
       sh.any_wave = true;
+      sh.max_split = std::max(sh.max_split, d.rw_split);
+      sh.max_split_grid = std::max(sh.max_split_grid, d.rw_split_grid);
       sh.lds_wave = std::max(sh.lds_wave, size_t(d.rw_nnz_u + 1 + d.nx) * sizeof(double) +
                                               size_t(rh::kRwWaves) * d.rw_nlev * sizeof(int));
     } else {
