@@ -83,7 +83,11 @@ struct DevNet {
   // wave-resident refactorisation (rw_ok): task records, per-lane data
   int rw_ok, rw_nnz_u, rw_nlev, rw_ntask, rw_lane_pad;
   const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane, *rw_ustart;
-  int rw_split, rw_split_grid;      // levels 1..rw_split: one launch per level, a task per WG
+  int rw_split, rw_split_grid;
+  // staged refactorisation of a large network: one launch per level over
+  // rf_level_grid work-groups (the most any level needs) instead of one
+  // work-group walking every level
+  int rf_per_level, rf_level_grid;      // levels 1..rw_split: one launch per level, a task per WG
   const int* rw_lanelu;             // per task step and lane: LU position of the U entry, or -1
   const int* rf_lmeta;    // 6 ints per refactorisation level
   int rf_lds_doubles;
@@ -130,6 +134,7 @@ struct BatchShape {
   int count = 0, width = 1, ntiles = 0;
   bool lds = true, meta_global = false, any_wave = false, any_staged = false;
   int max_split = 0, max_split_grid = 0;   // refactorisation levels run one launch each
+  int max_staged_levels = 0, max_staged_grid = 0;
   int max_lines = 0, max_dst = 0, max_nnz_k = 0, max_nw = 0, max_nx = 0, max_nu = 0, max_m = 0;
   size_t lds_wave = 0, lds_staged = 0, lds_condense = 0;
   std::vector<int> orders;   // order (nu) of each instance's condensed matrix

@@ -199,59 +199,77 @@ __global__ void k_fill_int(int* p, int n, int v) {
 // pivot is kept for the rows that follow.
 constexpr int kRefThreads = 1024;
 
-__device__ __forceinline__ void k_refactor_body(const DevNet& d) {
+// Level lev of the staged refactorisation: the work-group's row groups take
+// the level's rows first_group + g, first_group + g + group_stride, ...
+__device__ __forceinline__ void refactor_staged_level(const DevNet& d, int lev, int first_group,
+                                                      int group_stride) {
   extern __shared__ double ref_lds[];
   double* lu = d.dst + d.d_lu;
-  for (int lev = 0; lev < d.rf_nlev; ++lev) {
-    const int s0 = d.rf_lev_ptr[lev], s1 = d.rf_lev_ptr[lev + 1];
-    const int* mt = d.rf_lmeta + 6 * lev;
-    const int lanes = mt[0], stride = mt[1];
-    const int groups = kRefThreads / lanes;
-    const int g = threadIdx.x / lanes, lane = threadIdx.x & (lanes - 1);
-    double* rowbuf = ref_lds + (size_t)g * stride;
-    double* srcbuf = rowbuf + mt[2];
-    double* pivbuf = rowbuf + mt[3];
-    int* dstbuf = reinterpret_cast<int*>(rowbuf + mt[4]);
-    int* kbuf = dstbuf + mt[5];
-    for (int slot = s0 + g; slot < s1; slot += groups) {
-      const int4 i0 = *reinterpret_cast<const int4*>(d.rf_info + 8 * slot);
-      const int2 i1 = *reinterpret_cast<const int2*>(d.rf_info + 8 * slot + 4);
-      const int i = i0.x, rp0 = i0.y, rp1 = i0.z, rd = i0.w, o0 = i1.x, nops = i1.y;
-      const int nlow = rd - rp0;
-      double amax = 0.0;
-      for (int t = lane; t < rp1 - rp0; t += lanes) {
-        const double v = lu[rp0 + t];
-        rowbuf[t] = v;
-        amax = fmax(amax, fabs(v));
-      }
-      for (int t = lane; t < nops; t += lanes) {
-        srcbuf[t] = lu[d.rf_src[o0 + t]];
-        dstbuf[t] = d.rf_dst_local[o0 + t];
-      }
-      for (int t = lane; t < nlow; t += lanes) pivbuf[t] = d.rinv[d.lu_col[rp0 + t]];
-      for (int t = lane; t <= nlow; t += lanes) kbuf[t] = d.rf_kptr[rp0 + t] - o0;
-      for (int off = lanes / 2; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  const int s0 = d.rf_lev_ptr[lev], s1 = d.rf_lev_ptr[lev + 1];
+  const int* mt = d.rf_lmeta + 6 * lev;
+  const int lanes = mt[0], stride = mt[1];
+  const int g = threadIdx.x / lanes, lane = threadIdx.x & (lanes - 1);
+  double* rowbuf = ref_lds + (size_t)g * stride;
+  double* srcbuf = rowbuf + mt[2];
+  double* pivbuf = rowbuf + mt[3];
+  int* dstbuf = reinterpret_cast<int*>(rowbuf + mt[4]);
+  int* kbuf = dstbuf + mt[5];
+  for (int slot = s0 + first_group + g; slot < s1; slot += group_stride) {
+    const int4 i0 = *reinterpret_cast<const int4*>(d.rf_info + 8 * slot);
+    const int2 i1 = *reinterpret_cast<const int2*>(d.rf_info + 8 * slot + 4);
+    const int i = i0.x, rp0 = i0.y, rp1 = i0.z, rd = i0.w, o0 = i1.x, nops = i1.y;
+    const int nlow = rd - rp0;
+    double amax = 0.0;
+    for (int t = lane; t < rp1 - rp0; t += lanes) {
+      const double v = lu[rp0 + t];
+      rowbuf[t] = v;
+      amax = fmax(amax, fabs(v));
+    }
+    for (int t = lane; t < nops; t += lanes) {
+      srcbuf[t] = lu[d.rf_src[o0 + t]];
+      dstbuf[t] = d.rf_dst_local[o0 + t];
+    }
+    for (int t = lane; t < nlow; t += lanes) pivbuf[t] = d.rinv[d.lu_col[rp0 + t]];
+    for (int t = lane; t <= nlow; t += lanes) kbuf[t] = d.rf_kptr[rp0 + t] - o0;
+    for (int off = lanes / 2; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+    __builtin_amdgcn_wave_barrier();
+    for (int q = 0; q < nlow; ++q) {
+      const double l = rowbuf[q] * pivbuf[q];
       __builtin_amdgcn_wave_barrier();
-      for (int q = 0; q < nlow; ++q) {
-        const double l = rowbuf[q] * pivbuf[q];
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) rowbuf[q] = l;
-        for (int t = kbuf[q] + lane; t < kbuf[q + 1]; t += lanes)
-          rowbuf[dstbuf[t]] = fma(-l, srcbuf[t], rowbuf[dstbuf[t]]);
-        __builtin_amdgcn_wave_barrier();
-      }
-      for (int t = lane; t < rp1 - rp0; t += lanes) lu[rp0 + t] = rowbuf[t];
-      if (lane == 0) {
-        const double piv = rowbuf[rd - rp0];
-        d.rinv[i] = 1.0 / piv;
-        if (!(fabs(piv) > 1e-14 * amax)) {
-          d.status[2] = 1;
-          d.status[3] = i;
-        }
+      if (lane == 0) rowbuf[q] = l;
+      for (int t = kbuf[q] + lane; t < kbuf[q + 1]; t += lanes)
+        rowbuf[dstbuf[t]] = fma(-l, srcbuf[t], rowbuf[dstbuf[t]]);
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int t = lane; t < rp1 - rp0; t += lanes) lu[rp0 + t] = rowbuf[t];
+    if (lane == 0) {
+      const double piv = rowbuf[rd - rp0];
+      d.rinv[i] = 1.0 / piv;
+      if (!(fabs(piv) > 1e-14 * amax)) {
+        d.status[2] = 1;
+        d.status[3] = i;
       }
     }
+  }
+}
+
+__device__ __forceinline__ void k_refactor_body(const DevNet& d) {
+  for (int lev = 0; lev < d.rf_nlev; ++lev) {
+    const int groups = kRefThreads / d.rf_lmeta[6 * lev];
+    refactor_staged_level(d, lev, 0, groups);
     __syncthreads();
   }
+}
+// One level of the staged refactorisation over ceil(rows / groups)
+// work-groups (large networks: a level's rows need more row groups than one
+// work-group's LDS holds); the level's rows only read rows of earlier
+// levels, written by earlier launches.
+__device__ __forceinline__ void k_refactor_level_staged_body(const DevNet& d, int lev) {
+  const int groups = kRefThreads / d.rf_lmeta[6 * lev];
+  refactor_staged_level(d, lev, blockIdx.x * groups, groups * gridDim.x);
+}
+__global__ void __launch_bounds__(kRefThreads) k_refactor_level_staged(DevNet d, int lev) {
+  k_refactor_level_staged_body(d, lev);
 }
 __global__ void __launch_bounds__(kRefThreads) k_refactor(DevNet d) {
   k_refactor_body(d);
@@ -1359,7 +1377,13 @@ __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave_b(const DevNet*
 }
 __global__ void __launch_bounds__(kRefThreads) k_refactor_b(const DevNet* __restrict__ nets) {
   const DevNet& d = cst(nets, blockIdx.z);
-  if (!d.rw_ok) k_refactor_body(d);
+  if (!d.rw_ok && !d.rf_per_level) k_refactor_body(d);
+}
+__global__ void __launch_bounds__(kRefThreads) k_refactor_level_staged_b(const DevNet* __restrict__ nets,
+                                                                       int lev) {
+  const DevNet& d = cst(nets, blockIdx.z);
+  if (d.rw_ok || !d.rf_per_level || lev >= d.rf_nlev) return;
+  k_refactor_level_staged_body(d, lev);
 }
 __global__ void __launch_bounds__(kBlock) k_transcribe_b(const DevNet* __restrict__ nets) {
   k_transcribe_body(cst(nets, blockIdx.z));
@@ -1477,6 +1501,8 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_condense_b<4, 0>),
       reinterpret_cast<const void*>(&k_condense_b<8, 0>),
       reinterpret_cast<const void*>(&k_refactor_wave_b),
+      reinterpret_cast<const void*>(&k_refactor_level_staged),
+      reinterpret_cast<const void*>(&k_refactor_level_staged_b),
       reinterpret_cast<const void*>(&k_refactor_b)};
   for (const void* f : bfns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
@@ -1520,6 +1546,10 @@ hipError_t launch_refactor(const DevNet& d, hipStream_t st) {
                        (size_t)(d.rw_nnz_u + 1 + d.nx) * sizeof(double) +
                            (size_t)kRwWaves * d.rw_nlev * sizeof(int), st, d, d.rw_split);
   }
+  else if (d.rf_per_level)
+    for (int lev = 0; lev < d.rf_nlev; ++lev)
+      hipLaunchKernelGGL(k_refactor_level_staged, dim3(d.rf_level_grid), dim3(kRefThreads),
+                         (size_t)d.rf_lds_doubles * sizeof(double), st, d, lev);
   else
     hipLaunchKernelGGL(k_refactor, dim3(1), dim3(kRefThreads),
                        (size_t)d.rf_lds_doubles * sizeof(double), st, d);
@@ -1624,6 +1654,9 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
   }
   if (sh.any_staged)
     hipLaunchKernelGGL(k_refactor_b, dim3(1, 1, B), dim3(kRefThreads), sh.lds_staged, st, nets);
+  for (int lev = 0; lev < sh.max_staged_levels; ++lev)
+    hipLaunchKernelGGL(k_refactor_level_staged_b, dim3(sh.max_staged_grid, 1, B), dim3(kRefThreads),
+                       sh.lds_staged, st, nets, lev);
   hipLaunchKernelGGL(k_transcribe_b, dim3(64, 1, B), dim3(kBlock), 0, st, nets);
   const int W = sh.width;
 #define RH_BATCH_COND(WW, LL)                                                                   \

@@ -125,6 +125,10 @@ rh_status alloc(rh_net* n, size_t count, T** out) {
     rh_status _st = (expr);        \
     if (_st != RH_OK) return _st;  \
   } while (0)
+// Networks with at least this many states refactorise level by level over
+// many work-groups when they take the staged refactorisation.
+constexpr int kStagedPerLevelStates = 4096;
+
 #define RH_HIP(expr)                              \
   do {                                            \
     if ((expr) != hipSuccess) return RH_ERR_HIP;  \
@@ -359,6 +363,15 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   d.rw_lane_pad = 0;
   d.rw_split = s.rw_ok ? s.rw_split : 0;
   d.rw_split_grid = s.rw_split_grid;
+  // the staged refactorisation of a large network runs one launch per level,
+  // each level's rows spread over as many work-groups as its row groups need
+  d.rf_per_level = (!s.rw_ok && s.nx >= kStagedPerLevelStates) ? 1 : 0;
+  d.rf_level_grid = 1;
+  for (int l = 0; l < s.sl.nlev; ++l) {
+    const int rows = s.sl.lev_ptr[l + 1] - s.sl.lev_ptr[l];
+    const int groups = 1024 / s.rf_lmeta[6 * l];
+    d.rf_level_grid = std::max(d.rf_level_grid, (rows + groups - 1) / groups);
+  }
   if (s.rw_ok) {
     d.rw_ntask = int(s.rw_rec.size()) / rh::kRwRec - 1;
     d.rw_lane_pad = int(s.rw_lane.size()) - 64;
@@ -632,7 +645,12 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
       sh.lds_wave = std::max(sh.lds_wave, size_t(d.rw_nnz_u + 1 + d.nx) * sizeof(double) +
                                               size_t(rh::kRwWaves) * d.rw_nlev * sizeof(int));
     } else {
-      sh.any_staged = true;
+      if (d.rf_per_level) {
+        sh.max_staged_levels = std::max(sh.max_staged_levels, d.rf_nlev);
+        sh.max_staged_grid = std::max(sh.max_staged_grid, d.rf_level_grid);
+      } else {
+        sh.any_staged = true;
+      }
       sh.lds_staged = std::max(sh.lds_staged, size_t(d.rf_lds_doubles) * sizeof(double));
     }
     sh.meta_global = sh.meta_global || d.meta_global != 0;
