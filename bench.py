@@ -729,9 +729,10 @@ def main():
         _progress("batched condensation done")
         best, times = api.autotune(net, (x, u, lam, y, sx, su, ss, r), widths=(1, 2, 4),
                                    lds=(1, 0), reps=3)
-        line["autotune"] = {"best": {"panel_width": best[0], "lds_panel": best[1]},
-                            "condensation_us": {f"w{w}_lds{l}": round(v, 1)
-                                                for (w, l), v in times.items()}}
+        line["autotune"] = {"best": {"panel_width": best[0], "lds_panel": best[1],
+                                     "cond_waves": best[2]},
+                            "condensation_us": {f"w{w}_lds{l}_nw{nw}": round(v, 1)
+                                                for (w, l, nw), v in times.items()}}
     if not args.no_ipm:
         line["redlin"] = redlin_run(api, net, torch, args.ipm_iters)
         _progress("redlin done")

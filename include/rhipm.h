@@ -101,6 +101,14 @@ typedef struct {
   int32_t refactor;          /* 0 = wave-resident refactorisation when every LU
                                 row has at most 64 entries and U fits in LDS,
                                 1 = always the level-staged kernel              */
+  int32_t cond_waves;        /* waves per condensation work-group when it takes
+                                one column with its panel in LDS: 1 or 4 (the
+                                waves split each sweep's same-level steps and the
+                                record streams); 0 = auto (4 when the panel fills
+                                the LDS, else 1); other shapes always run 1     */
+  int32_t sweep_grouping;    /* with 4 waves: 0 = auto (by the sweeps' step and
+                                group counts), else 1 + a mask whose bit k puts
+                                sweep k (L, U, U^T, L^T) on all 4 waves        */
 } rh_options;
 
 typedef struct {
@@ -120,6 +128,14 @@ typedef struct {
   int64_t sweep_steps;                 /* passes of all four sweeps of one column  */
   int64_t refactor_split;              /* leading levels factored one launch each,
                                           a task per work-group (wave-resident path) */
+  int64_t cond_waves;                  /* waves per condensation work-group        */
+  int64_t steps_l, steps_u, steps_ut, steps_lt;     /* passes of each sweep (L, U,
+                                                       U^T, L^T) with one wave  */
+  int64_t groups_l, groups_u, groups_ut, groups_lt; /* the same with the steps of a
+                                                       level spread over 4 waves */
+  int64_t sweep_grouped;               /* bit k set: sweep k (L, U, U^T, L^T) runs
+                                          on all waves of a work-group, else on
+                                          one (with 4 waves per work-group)     */
 } rh_info;
 
 typedef struct rh_symbolic rh_symbolic;

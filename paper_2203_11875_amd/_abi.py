@@ -31,7 +31,8 @@ class rh_network_desc(C.Structure):
 
 class rh_options(C.Structure):
     _fields_ = [("panel_width", C.c_int32), ("ordering", C.c_int32),
-                ("lds_panel", C.c_int32), ("refactor", C.c_int32)]
+                ("lds_panel", C.c_int32), ("refactor", C.c_int32), ("cond_waves", C.c_int32),
+                ("sweep_grouping", C.c_int32)]
 
 
 class rh_info(C.Structure):
@@ -39,7 +40,8 @@ class rh_info(C.Structure):
         "nx", "nu", "m", "nb", "nl", "ng", "nnz_gx", "nnz_lu", "nnz_gu", "nnz_a", "nnz_k",
         "levels_lower", "levels_upper", "refactor_ops", "max_lu_row", "panel_width",
         "lds_panel", "max_row_ops", "refactor_kernel", "steps_lower", "sweep_steps",
-        "refactor_split")]
+        "refactor_split", "cond_waves", "steps_l", "steps_u", "steps_ut", "steps_lt",
+        "groups_l", "groups_u", "groups_ut", "groups_lt", "sweep_grouped")]
 
 
 class rh_ipm_options(C.Structure):

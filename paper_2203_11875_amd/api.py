@@ -49,12 +49,14 @@ class _Desc:
         self.desc = d
 
 
-def _opts(panel_width=0, lds_panel=1, refactor=0):
+def _opts(panel_width=0, lds_panel=1, refactor=0, cond_waves=0, sweep_grouping=0):
     o = _abi.rh_options()
     o.panel_width = int(panel_width)
     o.ordering = 0
     o.lds_panel = int(lds_panel)
     o.refactor = int(refactor)
+    o.cond_waves = int(cond_waves)
+    o.sweep_grouping = int(sweep_grouping)
     return o
 
 
@@ -65,10 +67,10 @@ def _info_dict(info):
 class Symbolic:
     """Host-only symbolic analysis (rh_analyze_network); needs no GPU."""
 
-    def __init__(self, net, panel_width=0, lds_panel=1, refactor=0):
+    def __init__(self, net, panel_width=0, lds_panel=1, refactor=0, cond_waves=0):
         self._desc = _Desc(net)
         h = C.c_void_p()
-        o = _opts(panel_width, lds_panel, refactor)
+        o = _opts(panel_width, lds_panel, refactor, cond_waves)
         _check(lib().rh_analyze_network(C.byref(self._desc.desc), C.byref(o), C.byref(h)),
                "rh_analyze_network")
         self.h = h
@@ -127,7 +129,8 @@ def _ptr(t):
 class Net:
     """Device handle (rh_init_network). Inputs are float64 CUDA tensors."""
 
-    def __init__(self, net, panel_width=0, lds_panel=1, stream=None, refactor=0):
+    def __init__(self, net, panel_width=0, lds_panel=1, stream=None, refactor=0, cond_waves=0,
+                 sweep_grouping=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("rhipm.Net needs a HIP device")
@@ -136,7 +139,7 @@ class Net:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._desc = _Desc(net)
         h = C.c_void_p()
-        o = _opts(panel_width, lds_panel, refactor)
+        o = _opts(panel_width, lds_panel, refactor, cond_waves, sweep_grouping)
         _check(lib().rh_init_network(C.byref(self._desc.desc), C.byref(o),
                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)),
                "rh_init_network")
@@ -285,32 +288,39 @@ def cholesky_solve_noalloc(K, delta_w, b, x, status, stream=None):
            "rh_cholesky_solve_noalloc")
 
 
-def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), reps=3):
+def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 4), reps=3):
     """Launch-shape autotuner: times the condensation (all columns with the
     right-hand side) of `net` at `point` = (x, u, lam, y, sig_x, sig_u,
-    sig_s, r) for each panel width and panel placement, and returns
-    (best (width, lds), {(width, lds): microseconds}). Configurations the
-    device cannot hold are skipped."""
+    sig_s, r) for each panel width, panel placement (lds 1: in LDS, with the
+    sweep metadata in global memory where the panel fills the LDS) and waves
+    per work-group (several only for one column in LDS), and returns
+    (best (width, lds, waves), {(width, lds, waves): microseconds}).
+    Configurations the device cannot hold are skipped."""
     import time
     import torch
     times = {}
     for w in widths:
         for l in lds:
-            try:
-                G = Net(net, panel_width=w, lds_panel=l)
-            except RhError:
-                continue
-            if (int(G.info["panel_width"]), int(G.info["lds_panel"])) != (w, l):
-                G.close()
-                continue
-            G.condense_reduced_hessian(*point[:7], r=point[7])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
+            for nw in waves:
+                if nw != 1 and (w != 1 or not l):
+                    continue
+                try:
+                    G = Net(net, panel_width=w, lds_panel=l, cond_waves=nw)
+                except RhError:
+                    continue
+                got = (int(G.info["panel_width"]), int(G.info["lds_panel"]) != 0,
+                       int(G.info["cond_waves"]))
+                if got != (w, bool(l), nw):
+                    G.close()
+                    continue
                 G.condense_reduced_hessian(*point[:7], r=point[7])
-            torch.cuda.synchronize()
-            times[(w, l)] = 1e6 * (time.perf_counter() - t0) / reps
-            G.close()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    G.condense_reduced_hessian(*point[:7], r=point[7])
+                torch.cuda.synchronize()
+                times[(w, l, nw)] = 1e6 * (time.perf_counter() - t0) / reps
+                G.close()
     best = min(times, key=times.get)
     return best, times
 

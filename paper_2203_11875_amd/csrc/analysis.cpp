@@ -157,7 +157,7 @@ bool build_sweep(Sweep& sw, int n, const std::vector<int>& level, int nlev,
       const int S = 1 << ls;
       if ((maxlen + S - 1) / S > kSweepPF) return false;
       const int R = int(std::min<size_t>(qs.size() - i, size_t(kSweepThreads / S)));
-      sw.ks_meta.insert(sw.ks_meta.end(), {sw.lb_n, R * S, ls, 0});
+      sw.ks_meta.insert(sw.ks_meta.end(), {sw.lb_n, R * S, ls, l});
       for (int t = 0; t < R * S; ++t) {
         const int q = qs[i + t / S], k = t % S;
         for (int j = 0; j < kSweepPF; ++j) {
@@ -899,6 +899,45 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
 }
 
 // ------------------------------------------------------------------ checks
+// A step list (4 ints per entry, the level third, the idle step last) as
+// kCondWaves lists of one length, wave after wave: consecutive steps of one
+// level go to the waves in turn, kCondWaves at a time (they touch distinct
+// rows and read only rows of earlier levels), a wave with no step in a group
+// takes the idle step, and every list ends with the idle step. Returns the
+// number of groups.
+int wave_groups(const Sweep& sw) {
+  int groups = 0;
+  for (int i = 0; i < sw.ks_nstep; ++groups) {
+    int j = i;
+    while (j < sw.ks_nstep && sw.ks_meta[size_t(kSweepMeta) * j + 3] == sw.ks_meta[size_t(kSweepMeta) * i + 3] &&
+           j - i < kCondWaves)
+      ++j;
+    i = j;
+  }
+  return groups;
+}
+
+int group_for_waves(const int* e, size_t n_with_idle, std::vector<int>& out) {
+  const size_t n = n_with_idle - 1;
+  const int* idle = e + 4 * n;
+  std::vector<std::vector<int>> lists(kCondWaves);
+  int groups = 0;
+  for (size_t i = 0; i < n; ++groups) {
+    size_t j = i;
+    while (j < n && e[4 * j + 2] == e[4 * i + 2] && j - i < size_t(kCondWaves)) ++j;
+    for (int w = 0; w < kCondWaves; ++w) {
+      const int* src = i + w < j ? e + 4 * (i + w) : idle;
+      lists[w].insert(lists[w].end(), src, src + 4);
+    }
+    i = j;
+  }
+  for (auto& l : lists) {
+    l.insert(l.end(), idle, idle + 4);
+    out.insert(out.end(), l.begin(), l.end());
+  }
+  return groups;
+}
+
 void build_condense_records(const Symbolic& s, int W, CondenseRecords& R) {
   const long nw = s.nw, nu = s.nu;
   auto p_row = [&](long v) { return unsigned(v * W * 8); };                          // P row v
@@ -919,7 +958,7 @@ void build_condense_records(const Symbolic& s, int W, CondenseRecords& R) {
     for (int st = 0; st <= sw.ks_nstep; ++st, ++g) {
       const bool idle_step = st == sw.ks_nstep;
       const int* m = idle_step ? nullptr : &sw.ks_meta[size_t(kSweepMeta) * st];
-      R.meta[k].insert(R.meta[k].end(), {int(g), idle_step ? 0 : m[2], 0, 0});
+      R.meta[k].insert(R.meta[k].end(), {int(g), idle_step ? 0 : m[2], idle_step ? -1 : m[3], 0});
       double* S = &R.steps[g * kStepDoubles];
       for (int t = 0; t < kSweepThreads; ++t) {
         // lanes past the step's rows take its padding block
@@ -1008,6 +1047,18 @@ void build_condense_records(const Symbolic& s, int W, CondenseRecords& R) {
       R.lsk_meta.insert(R.lsk_meta.end(), R.meta[0].end() - 4, R.meta[0].end());   // idle step
       R.lsk_ptr[tile + 1] = int(R.lsk_meta.size() / 4);
     }
+    // the same lists for work-groups of kCondWaves waves
+    R.lsk_gptr.assign(ntile + 1, 0);
+    R.lsk_gmeta.clear();
+    for (int tile = 0; tile < ntile; ++tile) {
+      group_for_waves(&R.lsk_meta[4 * size_t(R.lsk_ptr[tile])],
+                      size_t(R.lsk_ptr[tile + 1] - R.lsk_ptr[tile]), R.lsk_gmeta);
+      R.lsk_gptr[tile + 1] = int(R.lsk_gmeta.size() / 4);
+    }
+  }
+  for (int k = 0; k < 4; ++k) {
+    R.gmeta[k].clear();
+    R.ngrp[k] = group_for_waves(R.meta[k].data(), R.meta[k].size() / 4, R.gmeta[k]);
   }
   // record streams
   auto stream = [&](const Symbolic::LaneStream& ls, bool gt, std::vector<double>& str,

@@ -27,6 +27,10 @@ struct DevSweep {
   // DevNet::lblk, log2 lanes per row, 0, 0}, then the idle step
   int nstep = 0;
   const int* meta = nullptr;
+  // the same steps as kCondWaves lists of ngrp + 1 entries (wave after
+  // wave), for work-groups of kCondWaves waves
+  int ngrp = 0;
+  const int* gmeta = nullptr;
   int unit = 0;                   // 1: unit diagonal (L and L^T sweeps)
 };
 
@@ -36,6 +40,10 @@ struct DevNet {
   // metadata from global memory instead of staging it (one column per
   // work-group)
   int meta_global;
+  int cond_nw;   // waves per condensation work-group (1 or kCondWaves)
+  // with kCondWaves waves: bit k set = sweep k (L, U, U^T, L^T) runs on all
+  // of them (same-level steps spread over the waves), else on wave 0
+  int sweep_grouped;
   double base, c2_ref, c1_ref, cost_rank1;
   const double *c2, *c1, *c0;
   const int* pg_u;
@@ -80,6 +88,7 @@ struct DevNet {
   // per column tile: the L-sweep steps that can change its panel (entries of
   // 4 ints as DevSweep::meta, then the idle step); null = every step
   const int *lsk_ptr, *lsk_meta;
+  const int *lsk_gptr, *lsk_gmeta;   // the same, grouped for kCondWaves waves
   // wave-resident refactorisation (rw_ok): task records, per-lane data
   int rw_ok, rw_nnz_u, rw_nlev, rw_ntask, rw_lane_pad;
   const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane, *rw_ustart;
@@ -133,6 +142,7 @@ struct BatchArg {
 struct BatchShape {
   int count = 0, width = 1, ntiles = 0;
   bool lds = true, meta_global = false, any_wave = false, any_staged = false;
+  int cond_nw = 1;   // waves per condensation work-group
   int max_split = 0, max_split_grid = 0;   // refactorisation levels run one launch each
   int max_staged_levels = 0, max_staged_grid = 0;
   int max_lines = 0, max_dst = 0, max_nnz_k = 0, max_nw = 0, max_nx = 0, max_nu = 0, max_m = 0;
@@ -216,12 +226,15 @@ constexpr size_t chol_lrow_doubles(int n) {
 }
 hipError_t launch_eval_objective(const DevNet& d, const double* u, double* f, hipStream_t st);
 int max_lds_bytes();
+int device_cus();   // compute units of the current device
 // LDS one row of the refactorisation stages (row, U sources, pivots, schedule).
 size_t refactor_lds_per_row(const DevNet& d);
 // Dynamic LDS of one condensation work-group: the staged step metadata and
 // stream block ends, after the panels P and H (2 nw + 1 rows of `width`
 // doubles) when those live in LDS.
-size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels);
+// Dynamic LDS of a condensation work-group of `waves` waves (1 or
+// kCondWaves; several only for one column with the panel in LDS).
+size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels, int waves);
 // Allow the LDS-staged kernels dynamic LDS up to the device's maximum.
 void prepare_lds_kernels();
 

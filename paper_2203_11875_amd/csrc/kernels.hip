@@ -652,10 +652,18 @@ __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d, int s
   k_refactor_wave_body(d, split);
 }
 
-// The condensation runs one wave per work-group (one thread per lane of a
-// sweep step or of a row block).
+// A wave takes one sweep step or one row block at a time (one thread per
+// lane). The single-wave kernels (the G_x solves, condensation with more than
+// one column per work-group or with panels in global memory) run kCondThreads.
 constexpr int kCondThreads = kSweepThreads;
-static_assert(kCondThreads == 64 && kKRowBlock == kCondThreads, "one wave per work-group");
+static_assert(kCondThreads == 64 && kKRowBlock == kCondThreads, "one lane per row of a block");
+// Waves per condensation work-group (NW): one column with its panel in LDS
+// may take kCondWaves waves that share the panel (a sweep's same-level steps
+// are spread over them, the record streams split into ranges of row blocks);
+// every other shape runs one wave.
+__host__ __device__ constexpr bool cond_waves_ok(int W, int PM, int NW) {
+  return NW == 1 || (NW == kCondWaves && W == 1 && PM != 0);
+}
 
 // Ordering of panel accesses between the steps of one wave. A wave's LDS
 // operations complete in issue order, so for LDS panels a wavefront-scope
@@ -698,7 +706,7 @@ struct StepFetch {
 // Seven 16-byte loads, each contiguous over the wave (chunk k of the step at
 // k * kChunk doubles, lane t at 2 t).
 __device__ __forceinline__ void fetch_step(const double* lblk, const int4 m, StepFetch& f) {
-  const f64x2* b = reinterpret_cast<const f64x2*>(lblk + (size_t)m.x * kStepDoubles) + threadIdx.x;
+  const f64x2* b = reinterpret_cast<const f64x2*>(lblk + (size_t)m.x * kStepDoubles) + (threadIdx.x & 63);
 #pragma unroll
   for (int k = 0; k < PF / 2; ++k) f.v[k] = b[k * (kChunk / 2)];
 #pragma unroll
@@ -752,7 +760,7 @@ __device__ __forceinline__ void panel_st(char* pb, unsigned off, double v) {
 // leaves the row total in the group's last lane, the one that writes. The
 // summation order depends only on the schedule, so results repeat bitwise and
 // do not depend on W.
-template <int W, bool LDS>
+template <int W, bool LDS, int NW>
 __device__ __forceinline__ void sweep_step(const StepFetch& f, char* pb) {
   double acc[W];
 #pragma unroll
@@ -786,7 +794,12 @@ __device__ __forceinline__ void sweep_step(const StepFetch& f, char* pb) {
     for (int c = 0; c < W; ++c)
       panel_st<LDS>(pb, row + 8 * c, (xr[c] - acc[c]) * f.piv.x);
   }
-  panel_sync<LDS>();
+  // several waves: the steps of a group are done before the next group's
+  // reads (global loads of later steps stay in flight)
+  if constexpr (NW > 1)
+    lds_barrier();
+  else
+    panel_sync<LDS>();
 }
 
 // A whole sweep, step by step. A step's lane block needs only the step's
@@ -801,7 +814,7 @@ __device__ __forceinline__ void sweep_step(const StepFetch& f, char* pb) {
 // own block, never for the later steps').
 constexpr int kDepth = 4;
 
-template <int W, bool LDS>
+template <int W, bool LDS, int NW = 1>
 __device__ __forceinline__ void sweep(int n, const double* lblk, const int4* meta, char* pb) {
   if (n == 0) return;
   StepFetch f[kDepth];
@@ -812,7 +825,7 @@ __device__ __forceinline__ void sweep(int n, const double* lblk, const int4* met
   // past the end), a step's entry is read into scalar registers with lane
   // reads, so no memory latency falls inside the step loop
   for (int c = 0; c < n + kDepth - 1; c += 64) {
-    const int4 mv = meta[min(c + (int)threadIdx.x, n)];
+    const int4 mv = meta[min(c + (int)(threadIdx.x & 63), n)];
     // wait for it here (lgkmcnt(0)), once per chunk, so that no wait for it is
     // left at the head of the step loop
     __builtin_amdgcn_s_waitcnt(0xC07F);
@@ -823,7 +836,7 @@ __device__ __forceinline__ void sweep(int n, const double* lblk, const int4* met
         const int l = max(min(k0 + j, n) - c, 0);
         const int4 m{__builtin_amdgcn_readlane(mv.x, l), __builtin_amdgcn_readlane(mv.y, l), 0, 0};
         fetch_step(lblk, m, f[j]);
-        sweep_step<W, LDS>(f[(j + 1) % kDepth], pb);
+        sweep_step<W, LDS, NW>(f[(j + 1) % kDepth], pb);
       }
     }
   }
@@ -847,27 +860,38 @@ __device__ __forceinline__ void tick(const DevNet& d, int k) {
 constexpr int kStreamDepth = 4;
 static_assert(kStreamBatch == 8 && kBatchDoubles == 6 * 128, "batch = 4 + 2 chunks of 64 x 16 bytes");
 template <int W, bool LDS, class Flush>
-__device__ __forceinline__ void row_stream(const double* str, int nbat, const int* end_lds, int nblk,
-                                           const char* pb, Flush&& flush) {
+__device__ __forceinline__ void row_stream(const double* str, const int* end_lds, int b_lo,
+                                           int b_hi, const char* pb, Flush&& flush) {
+  if (b_lo >= b_hi) return;
+  const int ln = threadIdx.x & 63;
   // block ends through lane registers (refilled every 64 blocks)
   int ev = 0, ebase = -64;
   auto end = [&](int b) {
     if (b - ebase >= 64) {
       ebase = b;
-      ev = end_lds[min(b + (int)threadIdx.x, nblk - 1)];
+      ev = end_lds[min(b + ln, b_hi - 1)];
     }
     return __builtin_amdgcn_readlane(ev, b - ebase);
   };
-  const f64x2* lane = reinterpret_cast<const f64x2*>(str) + threadIdx.x;
+  // records [rec_start, rec_end) of blocks [b_lo, b_hi); the batch holding
+  // rec_start may begin with records of the block before b_lo (a range of
+  // another wave), which are left out
+  // (read directly: the cached end() serves non-decreasing blocks only)
+  const int rec_start = b_lo > 0 ? end_lds[b_lo - 1] : 0;
+  const int rec_end = end_lds[b_hi - 1];
+  const int first = rec_start / kStreamBatch;
+  const int nbat = (rec_end + kStreamBatch - 1) / kStreamBatch - first;
+  const f64x2* lane = reinterpret_cast<const f64x2*>(str) + ln + (size_t)first * (kBatchDoubles / 2);
   double acc[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) acc[c] = 0.0;
-  int b = 0, e = nblk > 0 ? end(0) : 0;
-  while (b < nblk && e == 0) {   // blocks without records
+  int b = b_lo, e = end(b_lo);
+  while (b < b_hi && e == rec_start) {   // blocks without records
     flush(b, acc);
     ++b;
-    e = b < nblk ? end(b) : 0x7fffffff;
+    e = b < b_hi ? end(b) : 0x7fffffff;
   }
+  if (nbat <= 0) return;
   f64x2 bv[kStreamDepth][kStreamBatch / 2];
   u32x4 bo[kStreamDepth][2];
 #pragma unroll
@@ -900,8 +924,8 @@ __device__ __forceinline__ void row_stream(const double* str, int nbat, const in
         for (int c = 0; c < W; ++c) x[r][c] = panel_ld<LDS>(pb, bo[jj][r / 4][r % 4] + 8 * c);
 #pragma unroll
       for (int r = 0; r < kStreamBatch; ++r) {
-        const int p = cb * kStreamBatch + r;
-        const double v = bv[jj][r / 2][r % 2];
+        const int p = (first + cb) * kStreamBatch + r;
+        const double v = p >= rec_start ? bv[jj][r / 2][r % 2] : 0.0;
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[c] = fma(v, x[r][c], acc[c]);
         while (p + 1 == e) {
@@ -909,11 +933,33 @@ __device__ __forceinline__ void row_stream(const double* str, int nbat, const in
 #pragma unroll
           for (int c = 0; c < W; ++c) acc[c] = 0.0;
           ++b;
-          e = b < nblk ? end(b) : 0x7fffffff;
+          e = b < b_hi ? end(b) : 0x7fffffff;
         }
       }
     }
   }
+}
+
+// The row blocks [first, last) of a record stream that wave `wave` of NW
+// takes: contiguous ranges holding about equal numbers of records (end_lds:
+// the blocks' record ends, in LDS).
+template <int NW>
+__device__ __forceinline__ int2 stream_range(const int* end_lds, int nblk) {
+  if (NW == 1 || nblk <= 0) return int2{0, nblk};
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const long total = end_lds[nblk - 1];
+  auto first_block = [&](int w) {
+    if (w == 0) return 0;
+    if (w >= NW) return nblk;
+    const long target = total * w / NW;
+    int cnt = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 64) {
+      const int bb = b0 + ln;
+      cnt += __popcll(__ballot(bb < nblk && end_lds[bb] <= target));
+    }
+    return cnt;
+  };
+  return int2{first_block(wave), first_block(wave + 1)};
 }
 
 // body(i, idx[i]) for i < n over the wave's lanes, the index loads of eight
@@ -921,13 +967,14 @@ __device__ __forceinline__ void row_stream(const double* str, int nbat, const in
 // their bodies, whose stores could otherwise hold back the next loads.
 template <class F>
 __device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
-  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kCondThreads) {
+  const int T = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * T) {
     int ix[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) ix[u] = idx[min(i0 + u * kCondThreads, n - 1)];
+    for (int u = 0; u < 8; ++u) ix[u] = idx[min(i0 + u * T, n - 1)];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (i0 + u * kCondThreads < n) body(i0 + u * kCondThreads, ix[u]);
+      if (i0 + u * T < n) body(i0 + u * T, ix[u]);
   }
 }
 
@@ -948,7 +995,7 @@ __device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
 // LDS, 2 panels in LDS with the sweep metadata read where it is (global
 // memory, the same for every work-group), for networks whose panel alone
 // fills the LDS.
-template <int W, int PM, int mode>
+template <int W, int PM, int NW, int mode>
 __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int col0, int col_end,
                                                 const double* r, const double* vin, double* K,
                                                 long ldk, double* rhs, double* p_out) {
@@ -963,53 +1010,77 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   double* H = P;   // H replaces P after the Hessian product
   char* pb = reinterpret_cast<char*>(P);
   // step metadata of the four sweeps (with their idle steps), staged in LDS
-  // unless PM == 2, then the block ends of the two record streams in LDS
+  // unless PM == 2, then the block ends of the two record streams in LDS.
+  // With NW waves a sweep whose bit is set in d.sweep_grouped runs on all of
+  // them, as NW lists of groups (wave w taking list w); the other sweeps run
+  // on one wave from the plain list while the other waves wait.
+  static_assert(cond_waves_ok(W, PM, NW), "several waves: one column, panel in LDS");
+  const int tid = threadIdx.x, T = 64 * NW, ln = tid & 63, wave = tid >> 6;
+  auto csync = [&]() {
+    if constexpr (NW > 1)
+      __syncthreads();
+    else
+      panel_sync<LDS>();
+  };
   int4* mlds = reinterpret_cast<int4*>(panel_lds + (LDS ? (size_t)(nw + 1) * W : 0));
-  const int4 *m_sl, *m_su, *m_sut, *m_slt;
-  int* kb_end;
   // the L sweep of an identity-column tile runs only the steps that can
   // change its panel (the reach of G_u's columns in L)
   const bool reach = mode == MODE_COLUMNS && d.lsk_ptr && col0 == 0;
-  const int lsk_a = reach ? d.lsk_ptr[blk] : 0;
-  const int nsl = reach ? d.lsk_ptr[blk + 1] - lsk_a - 1 : d.sl.nstep;
-  if constexpr (PM == 2) {
-    m_sl = reach ? reinterpret_cast<const int4*>(d.lsk_meta) + lsk_a
-                 : reinterpret_cast<const int4*>(d.sl.meta);
-    m_su = reinterpret_cast<const int4*>(d.su.meta);
-    m_sut = reinterpret_cast<const int4*>(d.sut.meta);
-    m_slt = reinterpret_cast<const int4*>(d.slt.meta);
-    kb_end = reinterpret_cast<int*>(mlds);
-  } else {
-    int4* s_sl = mlds;
-    int4* s_su = s_sl + d.sl.nstep + 1;
-    int4* s_sut = s_su + d.su.nstep + 1;
-    int4* s_slt = s_sut + d.sut.nstep + 1;
-    if (reach) {
-      const int4* src = reinterpret_cast<const int4*>(d.lsk_meta) + lsk_a;
-      for (int i = threadIdx.x; i <= nsl; i += kCondThreads) s_sl[i] = src[i];
-    } else {
-      stage_meta(d.sl, s_sl);
+  const int4* m_sw[4];
+  int n_sw[4];
+  bool grp[4];
+  int* kb_end;
+  {
+    const DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
+    int4* slot = mlds;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const DevSweep& sw = *sws[k];
+      grp[k] = NW > 1 && ((d.sweep_grouped >> k) & 1);
+      const int4* src;
+      int n;
+      if (k == 0 && reach) {
+        const int* ptr = grp[k] ? d.lsk_gptr : d.lsk_ptr;
+        const int a = ptr[blk], e = ptr[blk + 1];
+        src = reinterpret_cast<const int4*>(grp[k] ? d.lsk_gmeta : d.lsk_meta) + a;
+        n = grp[k] ? (e - a) / NW - 1 : e - a - 1;
+      } else {
+        src = reinterpret_cast<const int4*>(grp[k] ? sw.gmeta : sw.meta);
+        n = grp[k] ? sw.ngrp : sw.nstep;
+      }
+      const int lists = grp[k] ? NW : 1, mine = grp[k] ? wave * (n + 1) : 0;
+      n_sw[k] = n;
+      if constexpr (PM == 2) {
+        m_sw[k] = src + mine;
+      } else {
+        // the slot holds the sweep's whole list (a tile's reach list is no longer)
+        for (int i = tid; i < lists * (n + 1); i += T) slot[i] = src[i];
+        m_sw[k] = slot + mine;
+        slot += grp[k] ? NW * (sw.ngrp + 1) : sw.nstep + 1;
+      }
     }
-    stage_meta(d.su, s_su);
-    stage_meta(d.sut, s_sut);
-    stage_meta(d.slt, s_slt);
-    m_sl = s_sl;
-    m_su = s_su;
-    m_sut = s_sut;
-    m_slt = s_slt;
-    kb_end = reinterpret_cast<int*>(s_slt + d.slt.nstep + 1);
+    kb_end = reinterpret_cast<int*>(PM == 2 ? mlds : slot);
   }
+  // sweep k, then every wave waits for it; a sweep on one wave runs on wave
+  // blk mod NW, so that the sweeping waves of the work-groups that share a CU
+  // are spread over its SIMDs
+  auto run_sweep = [&](int k) {
+    if (grp[k])
+      sweep<W, LDS, NW>(n_sw[k], d.lblk, m_sw[k], pb);
+    else if (NW == 1 || wave == blk % NW)
+      sweep<W, LDS, 1>(n_sw[k], d.lblk, m_sw[k], pb);
+    csync();
+  };
   int* gt_end = kb_end + d.kb_n;
-  for (int i = threadIdx.x; i < d.kb_n; i += kCondThreads) kb_end[i] = d.kb_end[i];
-  for (int i = threadIdx.x; i < d.gt_nb; i += kCondThreads) gt_end[i] = d.gt_end[i];
-  panel_sync<LDS>();
+  for (int i = tid; i < d.kb_n; i += T) kb_end[i] = d.kb_end[i];
+  for (int i = tid; i < d.gt_nb; i += T) gt_end[i] = d.gt_end[i];
+  csync();
   tick(d, 0);
   const int jc0 = col0 + blk * W;
-  const int tid = threadIdx.x, T = kCondThreads;
   const double* gu = d.dst + d.d_gu;
   const double* r4 = r ? r + d.nu + d.nx + d.m : nullptr;
   for (int i = tid; i < (nw + 1) * W; i += T) P[i] = 0.0;
-  panel_sync<LDS>();
+  csync();
   for (int c = 0; c < W; ++c) {
     const int j = jc0 + c;
     if (j >= col_end) break;
@@ -1030,11 +1101,11 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
       for (int i = tid; i < nx; i += T) P[(nu + i) * W + c] = -r4[d.perm[i]];
     }
   }
-  panel_sync<LDS>();
+  csync();
   tick(d, 1);
-  sweep<W, LDS>(nsl, d.lblk, m_sl, pb);
+  run_sweep(0);
   tick(d, 2);
-  sweep<W, LDS>(d.su.nstep, d.lblk, m_su, pb);
+  run_sweep(1);
   tick(d, 3);
   if (mode == MODE_COLUMNS) {
     // keep Z = S e_j (and d for the right-hand-side column) for the recovery
@@ -1061,14 +1132,19 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   // H rows in stream order; P is read to the end of the product, so H goes to
   // the tile's global scratch and then over P (its rows 0 .. nw - 1)
   double* scr = d.hscr + (size_t)blk * nw * W;
-  row_stream<W, LDS>(d.kstr, d.kst_nbat, kb_end, d.kb_n, pb,
+  const int2 kr = stream_range<NW>(kb_end, d.kb_n);
+  row_stream<W, LDS>(d.kstr, kb_end, kr.x, kr.y, pb,
                      [&](int b, const double(&acc)[W]) {
-                       const int p = b * kKRowBlock + tid;
+                       const int p = b * kKRowBlock + ln;
                        if (p < nw)
 #pragma unroll
                          for (int c = 0; c < W; ++c) scr[p * W + c] = acc[c];
                      });
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");   // the scratch stores complete
+  // the scratch stores complete (every wave's) before any wave reads them
+  if constexpr (NW > 1)
+    __syncthreads();
+  else
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
   for (int i0 = tid; i0 < nw * W; i0 += 8 * T) {
     double v[8];
 #pragma unroll
@@ -1077,11 +1153,11 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
     for (int k = 0; k < 8; ++k)
       if (i0 + k * T < nw * W) H[i0 + k * T] = v[k];
   }
-  panel_sync<LDS>();
+  csync();
   tick(d, 4);
-  sweep<W, LDS>(d.sut.nstep, d.lblk, m_sut, pb);
+  run_sweep(2);
   tick(d, 5);
-  sweep<W, LDS>(d.slt.nstep, d.lblk, m_slt, pb);
+  run_sweep(3);
   tick(d, 6);
   if (mode == MODE_COLUMNS) {
     for (int c = 0; c < W; ++c) {
@@ -1098,9 +1174,10 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   }
   // out = H_u - G_u^T Psi: the stream sums G_u^T Psi - H_u per control, written
   // to the K_cond column (rhs = -out for the right-hand-side column)
-  row_stream<W, LDS>(d.gstr, d.gst_nbat, gt_end, d.gt_nb, pb,
+  const int2 gr = stream_range<NW>(gt_end, d.gt_nb);
+  row_stream<W, LDS>(d.gstr, gt_end, gr.x, gr.y, pb,
                      [&](int b, const double(&acc)[W]) {
-                       const int p = b * kKRowBlock + tid;
+                       const int p = b * kKRowBlock + ln;
                        if (p < nu) {
                          const int q = d.grow[p];
 #pragma unroll
@@ -1115,12 +1192,12 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
                      });
   tick(d, 7);
 }
-template <int W, int PM, int mode>
-__global__ void __launch_bounds__(kCondThreads) k_condense(DevNet d, int col0, int col_end,
+template <int W, int PM, int NW, int mode>
+__global__ void __launch_bounds__(64 * NW) k_condense(DevNet d, int col0, int col_end,
                                                           const double* r, const double* vin,
                                                           double* K, long ldk, double* rhs,
                                                           double* p_out) {
-  k_condense_body<W, PM, mode>(d, blockIdx.x, col0, col_end, r, vin, K, ldk, rhs, p_out);
+  k_condense_body<W, PM, NW, mode>(d, blockIdx.x, col0, col_end, r, vin, K, ldk, rhs, p_out);
 }
 
 // x = G_x^{-1} b (TRANS = 0: L then U sweep) or x = G_x^{-T} b (TRANS = 1:
@@ -1287,18 +1364,18 @@ __global__ void k_symmetrize(double* K, long ld, int n) {
   k_symmetrize_body(K, ld, n);
 }
 
-template <int W, int PM>
+template <int W, int PM, int NW = 1>
 hipError_t launch_condense_t(const DevNet& d, int col0, int ncols, int mode, const double* r,
                              const double* vin, double* K, long ldk, double* rhs, double* p,
                              hipStream_t st) {
   const int nblk = (ncols + W - 1) / W;
-  const size_t lds = condense_lds_bytes(d, W, PM != 0);
+  const size_t lds = condense_lds_bytes(d, W, PM != 0, NW);
   if (mode == MODE_RECOVER)
-    hipLaunchKernelGGL((k_condense<W, PM, MODE_RECOVER>), dim3(nblk), dim3(kCondThreads), lds,
-                       st, d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
+    hipLaunchKernelGGL((k_condense<W, PM, NW, MODE_RECOVER>), dim3(nblk), dim3(64 * NW), lds, st,
+                       d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
   else
-    hipLaunchKernelGGL((k_condense<W, PM, MODE_COLUMNS>), dim3(nblk), dim3(kCondThreads), lds,
-                       st, d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
+    hipLaunchKernelGGL((k_condense<W, PM, NW, MODE_COLUMNS>), dim3(nblk), dim3(64 * NW), lds, st,
+                       d, col0, col0 + ncols, r, vin, K, ldk, rhs, p);
   return hipGetLastError();
 }
 
@@ -1306,12 +1383,19 @@ template <bool LDS>
 hipError_t dispatch_width(const DevNet& d, int col0, int ncols, int width, int mode,
                           const double* r, const double* vin, double* K, long ldk, double* rhs,
                           double* p, hipStream_t st) {
+  const bool waves = LDS && d.cond_nw == kCondWaves;
   if (LDS && d.meta_global) {   // panel mode 2: one column per work-group only
     if (width != 1) return hipErrorInvalidValue;
-    return launch_condense_t<1, 2>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+    return waves ? launch_condense_t<1, 2, kCondWaves>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st)
+                 : launch_condense_t<1, 2>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
   }
+  if (waves && width != 1) return hipErrorInvalidValue;
   switch (width) {
-    case 1: return launch_condense_t<1, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+    case 1:
+      if constexpr (LDS)
+        if (waves)
+          return launch_condense_t<1, 1, kCondWaves>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+      return launch_condense_t<1, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     case 2: return launch_condense_t<2, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     case 3: return launch_condense_t<3, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     case 4: return launch_condense_t<4, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
@@ -1389,14 +1473,14 @@ __global__ void __launch_bounds__(kBlock) k_transcribe_b(const DevNet* __restric
   k_transcribe_body(cst(nets, blockIdx.z));
 }
 // work-group g takes tile tiles[g] = {instance, tile of W columns}
-template <int W, int PM>
-__global__ void __launch_bounds__(kCondThreads) k_condense_b(const DevNet* __restrict__ nets,
+template <int W, int PM, int NW = 1>
+__global__ void __launch_bounds__(64 * NW) k_condense_b(const DevNet* __restrict__ nets,
                                                             const BatchArg* __restrict__ a,
                                                             const int2* __restrict__ tiles) {
   const int2 t = tiles[blockIdx.x];
   const DevNet& d = cst(nets, t.x);
   const BatchArg& q = cst(a, t.x);
-  k_condense_body<W, PM, MODE_COLUMNS>(d, t.y, 0, d.nu + 1, q.r, nullptr, q.K, q.ldk, q.rhs,
+  k_condense_body<W, PM, NW, MODE_COLUMNS>(d, t.y, 0, d.nu + 1, q.r, nullptr, q.K, q.ldk, q.rhs,
                                        nullptr);
 }
 __global__ void k_symmetrize_b(const BatchArg* __restrict__ a) {
@@ -1425,12 +1509,19 @@ __global__ void __launch_bounds__(kBlock) k_finish_step_b(const DevNet* __restri
 
 }  // namespace
 
-size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels) {
+size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels, int nwv) {
   static_assert(kSweepMeta == 4, "one int4 of metadata per step");
-  const size_t sweeps = (lds_panels && d.meta_global)
-                            ? 0
-                            : kSweepMeta * (size_t)(d.sl.nstep + d.su.nstep + d.sut.nstep +
-                                                    d.slt.nstep + 4);
+  // step lists: per sweep nstep + 1 entries, or nwv lists of ngrp + 1 for a
+  // sweep that runs on all nwv waves (none when they are read from global
+  // memory)
+  size_t sweeps = 0;
+  if (!(lds_panels && d.meta_global)) {
+    const DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
+    for (int k = 0; k < 4; ++k)
+      sweeps += kSweepMeta * (nwv > 1 && ((d.sweep_grouped >> k) & 1)
+                                  ? (size_t)nwv * (sws[k]->ngrp + 1)
+                                  : (size_t)sws[k]->nstep + 1);
+  }
   const size_t meta = sizeof(int) * (sweeps + (size_t)d.kb_n + (size_t)d.gt_nb);
   return (lds_panels ? (size_t)(d.nw + 1) * width * sizeof(double) : 0) + meta;
 }
@@ -1441,16 +1532,16 @@ void prepare_lds_kernels() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refactor_wave),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   const void* fns[] = {
-      reinterpret_cast<const void*>(&k_condense<1, 1, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<2, 1, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<3, 1, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<4, 1, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<8, 1, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<1, 1, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<2, 1, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<3, 1, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<4, 1, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<8, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<2, 1, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<3, 1, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<4, 1, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<8, 1, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<2, 1, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<3, 1, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<4, 1, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<8, 1, 1, MODE_RECOVER>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 1, 0>),
       reinterpret_cast<const void*>(&k_gx_solve<2, 1, 0>),
       reinterpret_cast<const void*>(&k_gx_solve<3, 1, 0>),
@@ -1461,21 +1552,25 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_gx_solve<3, 1, 1>),
       reinterpret_cast<const void*>(&k_gx_solve<4, 1, 1>),
       reinterpret_cast<const void*>(&k_gx_solve<8, 1, 1>),
-      reinterpret_cast<const void*>(&k_condense<1, 2, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<1, 2, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, kCondWaves, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, kCondWaves, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, kCondWaves, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, kCondWaves, MODE_RECOVER>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 2, 0>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 2, 1>)};
   const void* gfns[] = {
-      reinterpret_cast<const void*>(&k_condense<1, 0, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<2, 0, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<3, 0, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<4, 0, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<8, 0, MODE_COLUMNS>),
-      reinterpret_cast<const void*>(&k_condense<1, 0, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<2, 0, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<3, 0, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<4, 0, MODE_RECOVER>),
-      reinterpret_cast<const void*>(&k_condense<8, 0, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 0, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<2, 0, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<3, 0, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<4, 0, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<8, 0, 1, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 0, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<2, 0, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<3, 0, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<4, 0, 1, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<8, 0, 1, MODE_RECOVER>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 0, 0>),
       reinterpret_cast<const void*>(&k_gx_solve<2, 0, 0>),
       reinterpret_cast<const void*>(&k_gx_solve<3, 0, 0>),
@@ -1490,6 +1585,8 @@ void prepare_lds_kernels() {
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   const void* bfns[] = {
       reinterpret_cast<const void*>(&k_condense_b<1, 2>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 2, kCondWaves>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 1, kCondWaves>),
       reinterpret_cast<const void*>(&k_condense_b<1, 1>),
       reinterpret_cast<const void*>(&k_condense_b<2, 1>),
       reinterpret_cast<const void*>(&k_condense_b<3, 1>),
@@ -1509,6 +1606,14 @@ void prepare_lds_kernels() {
   for (const void* f : gfns)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   (void)hipGetLastError();
+}
+
+int device_cus() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+    return 256;
+  return v;
 }
 
 int max_lds_bytes() {
@@ -1582,7 +1687,7 @@ template <int W, int PM, int TRANS>
 hipError_t launch_gx_solve_t(const DevNet& d, const double* b, double* x, double scale,
                              int accumulate, hipStream_t st) {
   hipLaunchKernelGGL((k_gx_solve<W, PM, TRANS>), dim3(1), dim3(kCondThreads),
-                     condense_lds_bytes(d, W, PM != 0), st, d, b, x, scale, accumulate);
+                     condense_lds_bytes(d, W, PM != 0, 1), st, d, b, x, scale, accumulate);
   return hipGetLastError();
 }
 
@@ -1660,13 +1765,20 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
   hipLaunchKernelGGL(k_transcribe_b, dim3(64, 1, B), dim3(kBlock), 0, st, nets);
   const int W = sh.width;
 #define RH_BATCH_COND(WW, LL)                                                                   \
-  hipLaunchKernelGGL((k_condense_b<WW, LL>), dim3(sh.ntiles), dim3(kCondThreads), sh.lds_condense, \
-                     st, nets, args, tiles)
+  hipLaunchKernelGGL((k_condense_b<WW, LL>), dim3(sh.ntiles), dim3(64), sh.lds_condense, st, nets, \
+                     args, tiles)
+#define RH_BATCH_COND_WAVES(LL)                                                                 \
+  hipLaunchKernelGGL((k_condense_b<1, LL, kCondWaves>), dim3(sh.ntiles), dim3(64 * kCondWaves),    \
+                     sh.lds_condense, st, nets, args, tiles)
+  const bool waves = sh.lds && sh.cond_nw == kCondWaves;
+  if (waves && W != 1) return hipErrorInvalidValue;
   if (sh.lds && sh.meta_global) {
     if (W != 1) return hipErrorInvalidValue;
-    RH_BATCH_COND(1, 2);
+    if (waves) RH_BATCH_COND_WAVES(2);
+    else RH_BATCH_COND(1, 2);
   } else if (sh.lds) {
-    if (W == 1) RH_BATCH_COND(1, 1);
+    if (waves) RH_BATCH_COND_WAVES(1);
+    else if (W == 1) RH_BATCH_COND(1, 1);
     else if (W == 2) RH_BATCH_COND(2, 1);
     else if (W == 3) RH_BATCH_COND(3, 1);
     else if (W == 4) RH_BATCH_COND(4, 1);
@@ -1679,6 +1791,7 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
     else RH_BATCH_COND(8, 0);
   }
 #undef RH_BATCH_COND
+#undef RH_BATCH_COND_WAVES
   hipLaunchKernelGGL(k_symmetrize_b, dim3(cdiv(sh.max_nu, 16), cdiv(sh.max_nu, 16), B),
                      dim3(16, 16), 0, st, args);
   return hipGetLastError();

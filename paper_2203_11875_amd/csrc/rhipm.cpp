@@ -167,8 +167,29 @@ rh_status upload_sweep(rh_net* n, const rh::Sweep& s, rh::DevSweep& d) {
   RH_TRY(upload(n, s.lev_ptr, &d.lev_ptr));
   RH_TRY(upload(n, s.rows, &d.rows));
   d.nstep = s.ks_nstep;
+  d.ngrp = rh::wave_groups(s);
   d.unit = s.has_diag ? 0 : 1;
   return RH_OK;
+}
+
+// Which sweeps run on all waves of a condensation work-group of kCondWaves
+// waves (bit k: L, U, U^T, L^T). A group of same-level steps, one per wave
+// and then a barrier, took about 1.6 times a single-wave step with one
+// work-group per CU and about 2.3 times with several (the waves of two
+// work-groups then share SIMDs), measured on the 9241- and 1354-bus networks;
+// a sweep is spread over the waves where its groups, weighted so, are fewer
+// than its steps.
+int sweep_grouping(const rh::DevNet& d, int ntile, size_t lds_max) {
+  const size_t per_wg = rh::condense_lds_bytes(d, 1, true, rh::kCondWaves);
+  const long by_lds = per_wg ? long(lds_max / per_wg) : 1;
+  const long cus = rh::device_cus();
+  const long per_cu = std::min(by_lds, (ntile + cus - 1) / cus);
+  const double f = per_cu <= 1 ? 1.6 : 2.3;
+  const rh::DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
+  int mask = 0;
+  for (int k = 0; k < 4; ++k)
+    if (f * sws[k]->ngrp < double(sws[k]->nstep)) mask |= 1 << k;
+  return mask;
 }
 
 // Condensation records for launch width W (see rh::CondenseRecords).
@@ -181,7 +202,11 @@ rh_status upload_condense_records(rh_net* n, int W) {
   RH_TRY(upload(n, R.steps, &pd));
   d.lblk = const_cast<double*>(pd);
   rh::DevSweep* dsw[4] = {&d.sl, &d.su, &d.sut, &d.slt};
-  for (int k = 0; k < 4; ++k) RH_TRY(upload(n, R.meta[k], &dsw[k]->meta));
+  for (int k = 0; k < 4; ++k) {
+    RH_TRY(upload(n, R.meta[k], &dsw[k]->meta));
+    RH_TRY(upload(n, R.gmeta[k], &dsw[k]->gmeta));
+    if (dsw[k]->ngrp != R.ngrp[k]) return RH_ERR_ARG;
+  }
   d.tr_n = int(R.tr_dst.size());
   d.trd_n = int(R.trd_dst.size());
   RH_TRY(upload(n, R.tr_dst, &d.tr_dst));
@@ -199,6 +224,8 @@ rh_status upload_condense_records(rh_net* n, int W) {
   RH_TRY(upload(n, R.grow, &d.grow));
   RH_TRY(upload(n, R.lsk_ptr, &d.lsk_ptr));
   RH_TRY(upload(n, R.lsk_meta, &d.lsk_meta));
+  RH_TRY(upload(n, R.lsk_gptr, &d.lsk_gptr));
+  RH_TRY(upload(n, R.lsk_gmeta, &d.lsk_gmeta));
   return RH_OK;
 }
 
@@ -224,6 +251,14 @@ void fill_info(const rh::Symbolic& s, rh_info* info) {
   info->max_row_ops = s.max_row_ops;
   info->refactor_kernel = s.rw_ok ? 0 : 1;
   info->refactor_split = s.rw_ok ? s.rw_split : 0;
+  info->steps_l = s.sl.ks_nstep;
+  info->steps_u = s.su.ks_nstep;
+  info->steps_ut = s.sut.ks_nstep;
+  info->steps_lt = s.slt.ks_nstep;
+  info->groups_l = rh::wave_groups(s.sl);
+  info->groups_u = rh::wave_groups(s.su);
+  info->groups_ut = rh::wave_groups(s.sut);
+  info->groups_lt = rh::wave_groups(s.slt);
 }
 
 void copy_maps(const rh::Symbolic& s, int32_t* x_kind, int32_t* x_bus, int32_t* u_kind,
@@ -435,21 +470,41 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   int want = opts && opts->panel_width > 0 ? opts->panel_width : 1;
   if (want != 1 && want != 2 && want != 3 && want != 4 && want != 8) return RH_ERR_ARG;
   bool lds = !opts || opts->lds_panel != 0;
-  if (lds && rh::condense_lds_bytes(d, want, true) > lds_max) {
+  const int want_nw = opts ? opts->cond_waves : 0;
+  if (want_nw != 0 && want_nw != 1 && want_nw != rh::kCondWaves) return RH_ERR_ARG;
+  const int want_grp = opts ? opts->sweep_grouping : 0;
+  if (want_grp < 0 || want_grp > 16) return RH_ERR_ARG;
+  if (lds && rh::condense_lds_bytes(d, want, true, 1) > lds_max) {
     // keep the panels in LDS with a narrower tile if possible, then with the
     // sweep metadata left in global memory (one column per work-group)
     int w = want;
-    while (w > 1 && rh::condense_lds_bytes(d, w, true) > lds_max) w = (w == 8 ? 4 : w - 1);
-    if (rh::condense_lds_bytes(d, w, true) <= lds_max) {
+    while (w > 1 && rh::condense_lds_bytes(d, w, true, 1) > lds_max) w = (w == 8 ? 4 : w - 1);
+    if (rh::condense_lds_bytes(d, w, true, 1) <= lds_max) {
       want = w;
     } else {
       d.meta_global = 1;
-      if (rh::condense_lds_bytes(d, 1, true) <= lds_max) {
+      if (rh::condense_lds_bytes(d, 1, true, 1) <= lds_max) {
         want = 1;
       } else {
         d.meta_global = 0;
         lds = false;
       }
+    }
+  }
+  // waves per work-group: several only for one column with its panel in LDS;
+  // the record streams split over the waves, each sweep runs on all of them
+  // or on one (sweep_grouping). By default several where the panel fills the
+  // LDS (one work-group per CU: 3.6 ms instead of 6.1 ms for the 9241-bus
+  // condensation), else one (with two or three work-groups per CU the
+  // single-wave kernel was faster: 123 us instead of 139 us at 1354 buses)
+  d.cond_nw = 1;
+  d.sweep_grouped = 0;
+  if (lds && want == 1) {
+    const int pick = want_nw != 0 ? want_nw : (d.meta_global ? rh::kCondWaves : 1);
+    if (pick == rh::kCondWaves && rh::condense_lds_bytes(d, 1, true, pick) <= lds_max) {
+      d.cond_nw = pick;
+      d.sweep_grouped = want_grp ? want_grp - 1 : sweep_grouping(d, s.nu + 1, lds_max);
+      if (rh::condense_lds_bytes(d, 1, true, pick) > lds_max) d.sweep_grouped = 0;
     }
   }
   n->width = want;
@@ -587,6 +642,8 @@ rh_status rh_get_info(const rh_net* n, rh_info* info) {
   fill_info(n->s, info);
   info->panel_width = n->width;
   info->lds_panel = n->lds ? (n->d.meta_global ? 2 : 1) : 0;
+  info->cond_waves = n->d.cond_nw;
+  info->sweep_grouped = n->d.sweep_grouped;
   return RH_OK;
 }
 
@@ -660,12 +717,23 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
   }
   sh.ntiles = int(tiles.size());
   // one panel mode for the whole launch: the sweep metadata of every member
-  // is read from global memory when one member's panel fills the LDS
-  for (int i = 0; i < count; ++i) {
-    rh::DevNet dd = nets[i]->d;
-    dd.meta_global = sh.meta_global ? 1 : 0;
-    sh.lds_condense = std::max(sh.lds_condense, rh::condense_lds_bytes(dd, sh.width, sh.lds));
-  }
+  // is read from global memory when one member's panel fills the LDS; several
+  // waves per work-group then, or when every member runs several
+  bool all_nw = sh.lds && sh.width == 1;
+  for (int i = 0; i < count; ++i) all_nw = all_nw && nets[i]->d.cond_nw == rh::kCondWaves;
+  auto lds_for = [&](int nw) {
+    size_t m = 0;
+    for (int i = 0; i < count; ++i) {
+      rh::DevNet dd = nets[i]->d;
+      dd.meta_global = sh.meta_global ? 1 : 0;
+      m = std::max(m, rh::condense_lds_bytes(dd, sh.width, sh.lds, nw));
+    }
+    return m;
+  };
+  sh.cond_nw = 1;
+  if (sh.lds && sh.width == 1 && (sh.meta_global || all_nw) && lds_for(rh::kCondWaves) <= lds_max)
+    sh.cond_nw = rh::kCondWaves;
+  sh.lds_condense = lds_for(sh.cond_nw);
   if (sh.lds_wave > lds_max || sh.lds_staged > lds_max || sh.lds_condense > lds_max) {
     delete b;
     return RH_ERR_ARG;

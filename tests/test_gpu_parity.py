@@ -173,14 +173,22 @@ def test_bitwise_repeatable_and_width_independent(name):
     x, u, lam, y, sx, su, ss = random_point(M, 5)
     args = list(map(_t, (x, u, lam, y, sx, su, ss)))
     outs = []
-    for width, lds in ((1, 1), (2, 1), (2, 1), (3, 1), (2, 0), (4, 0)):
-        G = _net_api().Net(net, panel_width=width, lds_panel=lds)
+    # (panel width, panels in LDS, waves per work-group, sweeps on all waves:
+    # 0 the library's choice, else 1 + a mask over L, U, U^T, L^T)
+    for width, lds, nw, grp in ((1, 1, 1, 0), (1, 1, 4, 1), (1, 1, 4, 16), (1, 1, 4, 1 + 5),
+                                (2, 1, 1, 0), (2, 1, 1, 0), (3, 1, 1, 0), (2, 0, 1, 0),
+                                (4, 0, 1, 0)):
+        G = _net_api().Net(net, panel_width=width, lds_panel=lds, cond_waves=nw,
+                           sweep_grouping=grp)
+        assert G.info["cond_waves"] == nw
+        if nw > 1:
+            assert G.info["sweep_grouped"] == grp - 1
         K, _ = G.condense_reduced_hessian(*args)
         torch.cuda.synchronize()
-        outs.append((width, lds, G.info["lds_panel"], _np(K).copy()))
+        outs.append((width, lds, nw, grp, G.info["lds_panel"], _np(K).copy()))
         G.close()
-    for w, l, used, K in outs[1:]:
-        assert np.array_equal(K, outs[0][3]), (w, l, used)
+    for w, l, nw, grp, used, K in outs[1:]:
+        assert np.array_equal(K, outs[0][5]), (w, l, nw, grp, used)
 
 
 def test_set_loads_changes_residual():
@@ -196,16 +204,20 @@ def test_set_loads_changes_residual():
     assert _rel(_np(g), go) <= 1e-12 and _rel(_np(h), ho) <= 1e-12
 
 
-@pytest.mark.parametrize("name,width", [("syn9", 1), ("syn1354", 1), ("syn118", 2),
-                                        ("syn1354", 3)])
-def test_solve_after_condensation_without_rhs(name, width):
+@pytest.mark.parametrize("name,width,nw", [("syn9", 1, 1), ("syn1354", 1, 1), ("syn1354", 1, 4),
+                                           ("syn118", 2, 1), ("syn1354", 3, 1)])
+@pytest.mark.parametrize("grp", [0, 16])
+def test_solve_after_condensation_without_rhs(name, width, nw, grp):
     """Recovery by the single-column pass (condensation called without r),
     with the right-hand side condensed separately on the same factors; the
-    pass reads the sweep records of the handle's panel width."""
+    pass reads the sweep records of the handle's panel width and runs the
+    handle's waves per work-group."""
     net = NETS[name]()
     M = Model(net)
-    G = _net_api().Net(net, panel_width=width)
-    assert G.info["panel_width"] == width
+    if grp and nw == 1:
+        pytest.skip("sweeps on several waves need several waves")
+    G = _net_api().Net(net, panel_width=width, cond_waves=nw, sweep_grouping=grp)
+    assert G.info["panel_width"] == width and G.info["cond_waves"] == nw
     x, u, lam, y, sx, su, ss = random_point(M, 3, lam_scale=1.0, sig_range=(10.0, 1e4))
     r = residual_vector(M, 4)
     args = list(map(_t, (x, u, lam, y, sx, su, ss)))
