@@ -96,7 +96,12 @@ typedef struct {
 
 typedef struct {
   int32_t panel_width;       /* columns per condensation work-group; 0 = auto    */
-  int32_t ordering;          /* 0 = minimum degree on the pattern of G_x          */
+  int32_t ordering;          /* symmetric ordering of G_x: 0 = minimum degree with
+                                a level term (fewest sweep and refactorisation
+                                levels; the default), 1 = plain minimum degree,
+                                2 = nested dissection (more levels and fill on
+                                power networks; a network whose LU rows then
+                                exceed a sweep step is rejected)                */
   int32_t lds_panel;         /* 1 = keep panels in LDS when they fit, 0 = global  */
   int32_t refactor;          /* 0 = wave-resident refactorisation when every LU
                                 row has at most 64 entries and U fits in LDS,

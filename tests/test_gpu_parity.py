@@ -120,6 +120,26 @@ def test_condense_matches_oracle(name, seed, refactor):
     assert _linf(_np(rhs), b) <= 1e-8
 
 
+@pytest.mark.parametrize("name,ordering", [("syn118", 1), ("syn118", 2), ("syn1354", 1)])
+def test_condense_matches_oracle_under_other_orderings(name, ordering):
+    """K_cond and the right-hand side entry by entry with G_x ordered by plain
+    minimum degree or nested dissection instead of the default."""
+    net = NETS[name]()
+    M = Model(net)
+    G = _net_api().Net(net, ordering=ordering)
+    x, u, lam, y, sx, su, ss = random_point(M, 2)
+    r = residual_vector(M, 2)
+    K, rhs = G.condense_reduced_hessian(*map(_t, (x, u, lam, y, sx, su, ss)), r=_t(r))
+    torch.cuda.synchronize()
+    B = R.kkt_blocks(M, x, u, lam, y, sx, su, ss)
+    S, lu = R.sensitivity(B)
+    Kc = R.symmetrize(R.condensed_matrix(B, S))
+    b, _, _ = R.condensed_rhs(B, r, S, lu)
+    Kg = _np(K).T
+    assert kcond_entry_error(Kg, Kc) <= 1e-8, kcond_entry_error(Kg, Kc)
+    assert _linf(_np(rhs), b) <= 1e-8
+
+
 @pytest.mark.parametrize("name", ["syn9", "syn118", "syn1354", "syn1354g400"])
 @pytest.mark.parametrize("delta", [0.0, 10.0])
 def test_solve_matches_oracle(name, delta):

@@ -106,6 +106,47 @@ def test_patterns_cover_oracle_and_host_refactorisation_solves(net, refactor):
         assert np.abs(A @ z - b).max() <= 1e-10 * max(1.0, np.abs(b).max()) * np.abs(Gd).max()
 
 
+@pytest.mark.parametrize("ordering", [0, 1, 2], ids=["md_level", "md", "nd"])
+@pytest.mark.parametrize("net", NETS, ids=lambda n: n.name)
+def test_each_ordering_gives_a_valid_factorisation(net, ordering):
+    """Every ordering of G_x (minimum degree with a level term, plain minimum
+    degree, nested dissection) gives a permutation whose level tables check
+    and whose host refactorisation solves G_x z = b. Nested dissection puts
+    its separators last, whose dense rows exceed a sweep step on the larger
+    networks: those are rejected with an argument error, not mis-solved."""
+    api = _lib()
+    if ordering == 2 and net.nb > 200:
+        with pytest.raises(api.RhError):
+            api.Symbolic(net, ordering=ordering)
+        return
+    S = api.Symbolic(net, ordering=ordering)
+    assert S.check_levels() == 0
+    M = Model(net)
+    rng = np.random.default_rng(3)
+    x, u = M.join(rng.normal(0, .1, net.nb), rng.uniform(.95, 1.05, net.nb),
+                  rng.uniform(0, 1, net.ng))
+    G, _, _ = M.jacobians(x, u)
+    Gx = G[:, M.nu:].tocsr()
+    ptr, col, perm = S.gx_pattern()
+    assert np.array_equal(np.sort(perm), np.arange(M.nx))
+    vals = np.asarray(Gx[np.repeat(np.arange(M.nx), np.diff(ptr)), col]).ravel()
+    b = rng.normal(size=M.nx)
+    z = S.host_solve(vals, b)
+    assert np.abs(Gx @ z - b).max() <= 1e-10 * max(1.0, np.abs(b).max()) * np.abs(Gx).max()
+
+
+def test_level_term_shortens_the_dependency_chain():
+    """The level term of the default ordering: on the 1354-bus network it
+    factors in about half the levels of plain minimum degree (22 against
+    43) with at most 2% more LU entries."""
+    api = _lib()
+    net = synthnet.case1354(0)
+    a, b = api.Symbolic(net, ordering=0).info, api.Symbolic(net, ordering=1).info
+    assert a["levels_lower"] <= 0.6 * b["levels_lower"], (a["levels_lower"], b["levels_lower"])
+    assert a["nnz_lu"] <= 1.02 * b["nnz_lu"]
+    assert a["sweep_steps"] < b["sweep_steps"]
+
+
 def test_rejects_bad_networks():
     api = _lib()
     net = synthnet.case9(1)
