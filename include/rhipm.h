@@ -107,13 +107,13 @@ typedef struct {
                                 row has at most 64 entries and U fits in LDS,
                                 1 = always the level-staged kernel              */
   int32_t cond_waves;        /* waves per condensation work-group when it takes
-                                one column with its panel in LDS: 1 or 4 (the
+                                one column with its panel in LDS: 1, 4 or 8 (the
                                 waves split each sweep's same-level steps and the
-                                record streams); 0 = auto (4 when the panel fills
+                                record streams); 0 = auto (8 when the panel fills
                                 the LDS, else 1); other shapes always run 1     */
-  int32_t sweep_grouping;    /* with 4 waves: 0 = auto (by the sweeps' step and
-                                group counts), else 1 + a mask whose bit k puts
-                                sweep k (L, U, U^T, L^T) on all 4 waves        */
+  int32_t sweep_grouping;    /* with several waves: 0 = auto (by the sweeps' step
+                                and group counts), else 1 + a mask whose bit k
+                                puts sweep k (L, U, U^T, L^T) on all the waves  */
 } rh_options;
 
 typedef struct {

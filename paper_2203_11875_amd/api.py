@@ -288,7 +288,7 @@ def cholesky_solve_noalloc(K, delta_w, b, x, status, stream=None):
            "rh_cholesky_solve_noalloc")
 
 
-def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 4), reps=3):
+def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 4, 8), reps=3):
     """Launch-shape autotuner: times the condensation (all columns with the
     right-hand side) of `net` at `point` = (x, u, lam, y, sig_x, sig_u,
     sig_s, r) for each panel width, panel placement (lds 1: in LDS, with the

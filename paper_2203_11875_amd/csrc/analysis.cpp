@@ -1086,27 +1086,27 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
 // rows and read only rows of earlier levels), a wave with no step in a group
 // takes the idle step, and every list ends with the idle step. Returns the
 // number of groups.
-int wave_groups(const Sweep& sw) {
+int wave_groups(const Sweep& sw, int nwaves) {
   int groups = 0;
   for (int i = 0; i < sw.ks_nstep; ++groups) {
     int j = i;
     while (j < sw.ks_nstep && sw.ks_meta[size_t(kSweepMeta) * j + 3] == sw.ks_meta[size_t(kSweepMeta) * i + 3] &&
-           j - i < kCondWaves)
+           j - i < nwaves)
       ++j;
     i = j;
   }
   return groups;
 }
 
-int group_for_waves(const int* e, size_t n_with_idle, std::vector<int>& out) {
+int group_for_waves(const int* e, size_t n_with_idle, int nwaves, std::vector<int>& out) {
   const size_t n = n_with_idle - 1;
   const int* idle = e + 4 * n;
-  std::vector<std::vector<int>> lists(kCondWaves);
+  std::vector<std::vector<int>> lists(nwaves);
   int groups = 0;
   for (size_t i = 0; i < n; ++groups) {
     size_t j = i;
-    while (j < n && e[4 * j + 2] == e[4 * i + 2] && j - i < size_t(kCondWaves)) ++j;
-    for (int w = 0; w < kCondWaves; ++w) {
+    while (j < n && e[4 * j + 2] == e[4 * i + 2] && j - i < size_t(nwaves)) ++j;
+    for (int w = 0; w < nwaves; ++w) {
       const int* src = i + w < j ? e + 4 * (i + w) : idle;
       lists[w].insert(lists[w].end(), src, src + 4);
     }
@@ -1228,19 +1228,24 @@ void build_condense_records(const Symbolic& s, int W, CondenseRecords& R) {
       R.lsk_meta.insert(R.lsk_meta.end(), R.meta[0].end() - 4, R.meta[0].end());   // idle step
       R.lsk_ptr[tile + 1] = int(R.lsk_meta.size() / 4);
     }
-    // the same lists for work-groups of kCondWaves waves
-    R.lsk_gptr.assign(ntile + 1, 0);
-    R.lsk_gmeta.clear();
-    for (int tile = 0; tile < ntile; ++tile) {
-      group_for_waves(&R.lsk_meta[4 * size_t(R.lsk_ptr[tile])],
-                      size_t(R.lsk_ptr[tile + 1] - R.lsk_ptr[tile]), R.lsk_gmeta);
-      R.lsk_gptr[tile + 1] = int(R.lsk_gmeta.size() / 4);
+    // the same lists for work-groups of several waves
+    for (int c = 0; c < 2; ++c) {
+      const int nwv = c ? kCondWavesWide : kCondWaves;
+      R.lsk_gptr[c].assign(ntile + 1, 0);
+      R.lsk_gmeta[c].clear();
+      for (int tile = 0; tile < ntile; ++tile) {
+        group_for_waves(&R.lsk_meta[4 * size_t(R.lsk_ptr[tile])],
+                        size_t(R.lsk_ptr[tile + 1] - R.lsk_ptr[tile]), nwv, R.lsk_gmeta[c]);
+        R.lsk_gptr[c][tile + 1] = int(R.lsk_gmeta[c].size() / 4);
+      }
     }
   }
-  for (int k = 0; k < 4; ++k) {
-    R.gmeta[k].clear();
-    R.ngrp[k] = group_for_waves(R.meta[k].data(), R.meta[k].size() / 4, R.gmeta[k]);
-  }
+  for (int c = 0; c < 2; ++c)
+    for (int k = 0; k < 4; ++k) {
+      R.gmeta[c][k].clear();
+      R.ngrp[c][k] = group_for_waves(R.meta[k].data(), R.meta[k].size() / 4,
+                                     c ? kCondWavesWide : kCondWaves, R.gmeta[c][k]);
+    }
   // record streams
   auto stream = [&](const Symbolic::LaneStream& ls, bool gt, std::vector<double>& str,
                     std::vector<int>& dst, std::vector<int>* xdst) {

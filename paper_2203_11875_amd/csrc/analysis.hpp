@@ -37,7 +37,11 @@ constexpr int kSweepThreads = 64;
 constexpr int kSweepMeta = 4;
 // Waves of a condensation work-group with one column and LDS panels: the
 // steps of one level are spread over them, and the record streams split.
+// Two counts: kCondWaves and kCondWavesWide (grouped lists for each are
+// built; index 0 and 1 of the per-count arrays).
 constexpr int kCondWaves = 4;
+constexpr int kCondWavesWide = 8;
+inline int wave_index(int nw) { return nw == kCondWavesWide ? 1 : 0; }
 // Row-blocked record streams of the condensation (K, G_u^T): batches of
 // kStreamBatch records per lane.
 constexpr int kStreamBatch = 8;
@@ -223,17 +227,18 @@ struct CondenseRecords {
   // side): the L-sweep step entries (as meta[0]) that can change its panel,
   // then the idle step; lsk_ptr in entries of 4 ints
   std::vector<int> lsk_ptr, lsk_meta;
-  // the step lists for work-groups of kCondWaves waves (group_for_waves):
-  // per sweep kCondWaves lists of ngrp + 1 entries, wave after wave; per
-  // column tile the same for its L-sweep steps (lsk_gptr in entries)
-  std::vector<int> gmeta[4];
-  int ngrp[4] = {0, 0, 0, 0};
-  std::vector<int> lsk_gptr, lsk_gmeta;
+  // the step lists for work-groups of NW waves (group_for_waves), [c] for
+  // NW = kCondWaves (c = 0) and kCondWavesWide (c = 1): per sweep NW lists
+  // of ngrp + 1 entries, wave after wave; per column tile the same for its
+  // L-sweep steps (lsk_gptr in entries)
+  std::vector<int> gmeta[2][4];
+  int ngrp[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  std::vector<int> lsk_gptr[2], lsk_gmeta[2];
 };
 void build_condense_records(const Symbolic& sym, int W, CondenseRecords& out);
-int group_for_waves(const int* entries, size_t n_with_idle, std::vector<int>& out);
+int group_for_waves(const int* entries, size_t n_with_idle, int nwaves, std::vector<int>& out);
 // The number of groups group_for_waves makes of a sweep's steps.
-int wave_groups(const Sweep& sw);
+int wave_groups(const Sweep& sw, int nwaves);
 
 // Host refactorisation + sweeps (for CPU tests of the schedule).
 rh_status host_solve(const Symbolic& sym, const double* gx_values_natural_csr,

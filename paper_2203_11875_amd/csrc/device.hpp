@@ -27,10 +27,10 @@ struct DevSweep {
   // DevNet::lblk, log2 lanes per row, 0, 0}, then the idle step
   int nstep = 0;
   const int* meta = nullptr;
-  // the same steps as kCondWaves lists of ngrp + 1 entries (wave after
-  // wave), for work-groups of kCondWaves waves
-  int ngrp = 0;
-  const int* gmeta = nullptr;
+  // the same steps as NW lists of ngrp + 1 entries (wave after wave), for
+  // work-groups of NW waves: [0] NW = kCondWaves, [1] NW = kCondWavesWide
+  int ngrp[2] = {0, 0};
+  const int* gmeta[2] = {nullptr, nullptr};
   int unit = 0;                   // 1: unit diagonal (L and L^T sweeps)
 };
 
@@ -40,9 +40,9 @@ struct DevNet {
   // metadata from global memory instead of staging it (one column per
   // work-group)
   int meta_global;
-  int cond_nw;   // waves per condensation work-group (1 or kCondWaves)
-  // with kCondWaves waves: bit k set = sweep k (L, U, U^T, L^T) runs on all
-  // of them (same-level steps spread over the waves), else on wave 0
+  int cond_nw;   // waves per condensation work-group (1, kCondWaves, kCondWavesWide)
+  // with several waves: bit k set = sweep k (L, U, U^T, L^T) runs on all of
+  // them (same-level steps spread over the waves), else on one
   int sweep_grouped;
   double base, c2_ref, c1_ref, cost_rank1;
   const double *c2, *c1, *c0;
@@ -88,7 +88,7 @@ struct DevNet {
   // per column tile: the L-sweep steps that can change its panel (entries of
   // 4 ints as DevSweep::meta, then the idle step); null = every step
   const int *lsk_ptr, *lsk_meta;
-  const int *lsk_gptr, *lsk_gmeta;   // the same, grouped for kCondWaves waves
+  const int *lsk_gptr[2], *lsk_gmeta[2];   // the same, grouped as DevSweep::gmeta
   // wave-resident refactorisation (rw_ok): task records, per-lane data
   int rw_ok, rw_nnz_u, rw_nlev, rw_ntask, rw_lane_pad;
   const int *rw_wbeg, *rw_levend, *rw_rec, *rw_lane, *rw_ustart;

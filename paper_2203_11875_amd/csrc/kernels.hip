@@ -658,11 +658,11 @@ __global__ void __launch_bounds__(kRwWaves * 64) k_refactor_wave(DevNet d, int s
 constexpr int kCondThreads = kSweepThreads;
 static_assert(kCondThreads == 64 && kKRowBlock == kCondThreads, "one lane per row of a block");
 // Waves per condensation work-group (NW): one column with its panel in LDS
-// may take kCondWaves waves that share the panel (a sweep's same-level steps
-// are spread over them, the record streams split into ranges of row blocks);
-// every other shape runs one wave.
+// may take kCondWaves or kCondWavesWide waves that share the panel (a
+// sweep's same-level steps are spread over them, the record streams split
+// into ranges of row blocks); every other shape runs one wave.
 __host__ __device__ constexpr bool cond_waves_ok(int W, int PM, int NW) {
-  return NW == 1 || (NW == kCondWaves && W == 1 && PM != 0);
+  return NW == 1 || ((NW == kCondWaves || NW == kCondWavesWide) && W == 1 && PM != 0);
 }
 
 // Ordering of panel accesses between the steps of one wave. A wave's LDS
@@ -1030,6 +1030,7 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   int n_sw[4];
   bool grp[4];
   int* kb_end;
+  constexpr int gi = NW == kCondWavesWide ? 1 : 0;   // which grouped lists
   {
     const DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
     int4* slot = mlds;
@@ -1040,13 +1041,13 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
       const int4* src;
       int n;
       if (k == 0 && reach) {
-        const int* ptr = grp[k] ? d.lsk_gptr : d.lsk_ptr;
+        const int* ptr = grp[k] ? d.lsk_gptr[gi] : d.lsk_ptr;
         const int a = ptr[blk], e = ptr[blk + 1];
-        src = reinterpret_cast<const int4*>(grp[k] ? d.lsk_gmeta : d.lsk_meta) + a;
+        src = reinterpret_cast<const int4*>(grp[k] ? d.lsk_gmeta[gi] : d.lsk_meta) + a;
         n = grp[k] ? (e - a) / NW - 1 : e - a - 1;
       } else {
-        src = reinterpret_cast<const int4*>(grp[k] ? sw.gmeta : sw.meta);
-        n = grp[k] ? sw.ngrp : sw.nstep;
+        src = reinterpret_cast<const int4*>(grp[k] ? sw.gmeta[gi] : sw.meta);
+        n = grp[k] ? sw.ngrp[gi] : sw.nstep;
       }
       const int lists = grp[k] ? NW : 1, mine = grp[k] ? wave * (n + 1) : 0;
       n_sw[k] = n;
@@ -1056,7 +1057,7 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
         // the slot holds the sweep's whole list (a tile's reach list is no longer)
         for (int i = tid; i < lists * (n + 1); i += T) slot[i] = src[i];
         m_sw[k] = slot + mine;
-        slot += grp[k] ? NW * (sw.ngrp + 1) : sw.nstep + 1;
+        slot += grp[k] ? NW * (sw.ngrp[gi] + 1) : sw.nstep + 1;
       }
     }
     kb_end = reinterpret_cast<int*>(PM == 2 ? mlds : slot);
@@ -1383,18 +1384,25 @@ template <bool LDS>
 hipError_t dispatch_width(const DevNet& d, int col0, int ncols, int width, int mode,
                           const double* r, const double* vin, double* K, long ldk, double* rhs,
                           double* p, hipStream_t st) {
-  const bool waves = LDS && d.cond_nw == kCondWaves;
+  const int nwv = LDS ? d.cond_nw : 1;
+  if (nwv != 1 && nwv != kCondWaves && nwv != kCondWavesWide) return hipErrorInvalidValue;
   if (LDS && d.meta_global) {   // panel mode 2: one column per work-group only
     if (width != 1) return hipErrorInvalidValue;
-    return waves ? launch_condense_t<1, 2, kCondWaves>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st)
-                 : launch_condense_t<1, 2>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+    if (nwv == kCondWavesWide)
+      return launch_condense_t<1, 2, kCondWavesWide>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+    if (nwv == kCondWaves)
+      return launch_condense_t<1, 2, kCondWaves>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+    return launch_condense_t<1, 2>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
   }
-  if (waves && width != 1) return hipErrorInvalidValue;
+  if (nwv > 1 && width != 1) return hipErrorInvalidValue;
   switch (width) {
     case 1:
-      if constexpr (LDS)
-        if (waves)
+      if constexpr (LDS) {
+        if (nwv == kCondWavesWide)
+          return launch_condense_t<1, 1, kCondWavesWide>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+        if (nwv == kCondWaves)
           return launch_condense_t<1, 1, kCondWaves>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
+      }
       return launch_condense_t<1, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     case 2: return launch_condense_t<2, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     case 3: return launch_condense_t<3, LDS>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
@@ -1519,7 +1527,7 @@ size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels, int nwv) 
     const DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
     for (int k = 0; k < 4; ++k)
       sweeps += kSweepMeta * (nwv > 1 && ((d.sweep_grouped >> k) & 1)
-                                  ? (size_t)nwv * (sws[k]->ngrp + 1)
+                                  ? (size_t)nwv * (sws[k]->ngrp[wave_index(nwv)] + 1)
                                   : (size_t)sws[k]->nstep + 1);
   }
   const size_t meta = sizeof(int) * (sweeps + (size_t)d.kb_n + (size_t)d.gt_nb);
@@ -1558,6 +1566,10 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_condense<1, 1, kCondWaves, MODE_RECOVER>),
       reinterpret_cast<const void*>(&k_condense<1, 2, kCondWaves, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<1, 2, kCondWaves, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, kCondWavesWide, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, kCondWavesWide, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, kCondWavesWide, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, kCondWavesWide, MODE_RECOVER>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 2, 0>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 2, 1>)};
   const void* gfns[] = {
@@ -1587,6 +1599,8 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_condense_b<1, 2>),
       reinterpret_cast<const void*>(&k_condense_b<1, 2, kCondWaves>),
       reinterpret_cast<const void*>(&k_condense_b<1, 1, kCondWaves>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 2, kCondWavesWide>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 1, kCondWavesWide>),
       reinterpret_cast<const void*>(&k_condense_b<1, 1>),
       reinterpret_cast<const void*>(&k_condense_b<2, 1>),
       reinterpret_cast<const void*>(&k_condense_b<3, 1>),
@@ -1767,17 +1781,20 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
 #define RH_BATCH_COND(WW, LL)                                                                   \
   hipLaunchKernelGGL((k_condense_b<WW, LL>), dim3(sh.ntiles), dim3(64), sh.lds_condense, st, nets, \
                      args, tiles)
-#define RH_BATCH_COND_WAVES(LL)                                                                 \
-  hipLaunchKernelGGL((k_condense_b<1, LL, kCondWaves>), dim3(sh.ntiles), dim3(64 * kCondWaves),    \
-                     sh.lds_condense, st, nets, args, tiles)
-  const bool waves = sh.lds && sh.cond_nw == kCondWaves;
-  if (waves && W != 1) return hipErrorInvalidValue;
+#define RH_BATCH_COND_WAVES(LL, NWV)                                                            \
+  hipLaunchKernelGGL((k_condense_b<1, LL, NWV>), dim3(sh.ntiles), dim3(64 * NWV), sh.lds_condense, \
+                     st, nets, args, tiles)
+  const int nwv = sh.lds ? sh.cond_nw : 1;
+  if (nwv != 1 && nwv != kCondWaves && nwv != kCondWavesWide) return hipErrorInvalidValue;
+  if (nwv > 1 && W != 1) return hipErrorInvalidValue;
   if (sh.lds && sh.meta_global) {
     if (W != 1) return hipErrorInvalidValue;
-    if (waves) RH_BATCH_COND_WAVES(2);
+    if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(2, kCondWavesWide);
+    else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(2, kCondWaves);
     else RH_BATCH_COND(1, 2);
   } else if (sh.lds) {
-    if (waves) RH_BATCH_COND_WAVES(1);
+    if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(1, kCondWavesWide);
+    else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(1, kCondWaves);
     else if (W == 1) RH_BATCH_COND(1, 1);
     else if (W == 2) RH_BATCH_COND(2, 1);
     else if (W == 3) RH_BATCH_COND(3, 1);

@@ -167,7 +167,8 @@ rh_status upload_sweep(rh_net* n, const rh::Sweep& s, rh::DevSweep& d) {
   RH_TRY(upload(n, s.lev_ptr, &d.lev_ptr));
   RH_TRY(upload(n, s.rows, &d.rows));
   d.nstep = s.ks_nstep;
-  d.ngrp = rh::wave_groups(s);
+  d.ngrp[0] = rh::wave_groups(s, rh::kCondWaves);
+  d.ngrp[1] = rh::wave_groups(s, rh::kCondWavesWide);
   d.unit = s.has_diag ? 0 : 1;
   return RH_OK;
 }
@@ -179,8 +180,8 @@ rh_status upload_sweep(rh_net* n, const rh::Sweep& s, rh::DevSweep& d) {
 // work-groups then share SIMDs), measured on the 9241- and 1354-bus networks;
 // a sweep is spread over the waves where its groups, weighted so, are fewer
 // than its steps.
-int sweep_grouping(const rh::DevNet& d, int ntile, size_t lds_max) {
-  const size_t per_wg = rh::condense_lds_bytes(d, 1, true, rh::kCondWaves);
+int sweep_grouping(const rh::DevNet& d, int nwv, int ntile, size_t lds_max) {
+  const size_t per_wg = rh::condense_lds_bytes(d, 1, true, nwv);
   const long by_lds = per_wg ? long(lds_max / per_wg) : 1;
   const long cus = rh::device_cus();
   const long per_cu = std::min(by_lds, (ntile + cus - 1) / cus);
@@ -188,7 +189,7 @@ int sweep_grouping(const rh::DevNet& d, int ntile, size_t lds_max) {
   const rh::DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
   int mask = 0;
   for (int k = 0; k < 4; ++k)
-    if (f * sws[k]->ngrp < double(sws[k]->nstep)) mask |= 1 << k;
+    if (f * sws[k]->ngrp[rh::wave_index(nwv)] < double(sws[k]->nstep)) mask |= 1 << k;
   return mask;
 }
 
@@ -204,8 +205,10 @@ rh_status upload_condense_records(rh_net* n, int W) {
   rh::DevSweep* dsw[4] = {&d.sl, &d.su, &d.sut, &d.slt};
   for (int k = 0; k < 4; ++k) {
     RH_TRY(upload(n, R.meta[k], &dsw[k]->meta));
-    RH_TRY(upload(n, R.gmeta[k], &dsw[k]->gmeta));
-    if (dsw[k]->ngrp != R.ngrp[k]) return RH_ERR_ARG;
+    for (int c = 0; c < 2; ++c) {
+      RH_TRY(upload(n, R.gmeta[c][k], &dsw[k]->gmeta[c]));
+      if (dsw[k]->ngrp[c] != R.ngrp[c][k]) return RH_ERR_ARG;
+    }
   }
   d.tr_n = int(R.tr_dst.size());
   d.trd_n = int(R.trd_dst.size());
@@ -224,8 +227,10 @@ rh_status upload_condense_records(rh_net* n, int W) {
   RH_TRY(upload(n, R.grow, &d.grow));
   RH_TRY(upload(n, R.lsk_ptr, &d.lsk_ptr));
   RH_TRY(upload(n, R.lsk_meta, &d.lsk_meta));
-  RH_TRY(upload(n, R.lsk_gptr, &d.lsk_gptr));
-  RH_TRY(upload(n, R.lsk_gmeta, &d.lsk_gmeta));
+  for (int c = 0; c < 2; ++c) {
+    RH_TRY(upload(n, R.lsk_gptr[c], &d.lsk_gptr[c]));
+    RH_TRY(upload(n, R.lsk_gmeta[c], &d.lsk_gmeta[c]));
+  }
   return RH_OK;
 }
 
@@ -255,10 +260,10 @@ void fill_info(const rh::Symbolic& s, rh_info* info) {
   info->steps_u = s.su.ks_nstep;
   info->steps_ut = s.sut.ks_nstep;
   info->steps_lt = s.slt.ks_nstep;
-  info->groups_l = rh::wave_groups(s.sl);
-  info->groups_u = rh::wave_groups(s.su);
-  info->groups_ut = rh::wave_groups(s.sut);
-  info->groups_lt = rh::wave_groups(s.slt);
+  info->groups_l = rh::wave_groups(s.sl, rh::kCondWaves);
+  info->groups_u = rh::wave_groups(s.su, rh::kCondWaves);
+  info->groups_ut = rh::wave_groups(s.sut, rh::kCondWaves);
+  info->groups_lt = rh::wave_groups(s.slt, rh::kCondWaves);
 }
 
 void copy_maps(const rh::Symbolic& s, int32_t* x_kind, int32_t* x_bus, int32_t* u_kind,
@@ -471,7 +476,8 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   if (want != 1 && want != 2 && want != 3 && want != 4 && want != 8) return RH_ERR_ARG;
   bool lds = !opts || opts->lds_panel != 0;
   const int want_nw = opts ? opts->cond_waves : 0;
-  if (want_nw != 0 && want_nw != 1 && want_nw != rh::kCondWaves) return RH_ERR_ARG;
+  if (want_nw != 0 && want_nw != 1 && want_nw != rh::kCondWaves && want_nw != rh::kCondWavesWide)
+    return RH_ERR_ARG;
   const int want_grp = opts ? opts->sweep_grouping : 0;
   if (want_grp < 0 || want_grp > 16) return RH_ERR_ARG;
   if (lds && rh::condense_lds_bytes(d, want, true, 1) > lds_max) {
@@ -493,17 +499,18 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   }
   // waves per work-group: several only for one column with its panel in LDS;
   // the record streams split over the waves, each sweep runs on all of them
-  // or on one (sweep_grouping). By default several where the panel fills the
-  // LDS (one work-group per CU: 3.6 ms instead of 6.1 ms for the 9241-bus
-  // condensation), else one (with two or three work-groups per CU the
-  // single-wave kernel was faster: 123 us instead of 139 us at 1354 buses)
+  // or on one (sweep_grouping). By default eight where the panel fills the
+  // LDS (one work-group per CU; the 9241-bus condensation call took 6.1 ms
+  // with one wave, 3.8 ms with four, 3.3 ms with eight), else one (with two
+  // or three work-groups per CU the single-wave kernel was faster: 123 us
+  // instead of 139 us with four waves at 1354 buses)
   d.cond_nw = 1;
   d.sweep_grouped = 0;
   if (lds && want == 1) {
-    const int pick = want_nw != 0 ? want_nw : (d.meta_global ? rh::kCondWaves : 1);
-    if (pick == rh::kCondWaves && rh::condense_lds_bytes(d, 1, true, pick) <= lds_max) {
+    const int pick = want_nw != 0 ? want_nw : (d.meta_global ? rh::kCondWavesWide : 1);
+    if (pick > 1 && rh::condense_lds_bytes(d, 1, true, pick) <= lds_max) {
       d.cond_nw = pick;
-      d.sweep_grouped = want_grp ? want_grp - 1 : sweep_grouping(d, s.nu + 1, lds_max);
+      d.sweep_grouped = want_grp ? want_grp - 1 : sweep_grouping(d, pick, s.nu + 1, lds_max);
       if (rh::condense_lds_bytes(d, 1, true, pick) > lds_max) d.sweep_grouped = 0;
     }
   }
@@ -719,8 +726,11 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
   // one panel mode for the whole launch: the sweep metadata of every member
   // is read from global memory when one member's panel fills the LDS; several
   // waves per work-group then, or when every member runs several
-  bool all_nw = sh.lds && sh.width == 1;
-  for (int i = 0; i < count; ++i) all_nw = all_nw && nets[i]->d.cond_nw == rh::kCondWaves;
+  // the members' wave count when they all agree on one above 1
+  int common_nw = nets[0]->d.cond_nw;
+  for (int i = 1; i < count; ++i)
+    if (nets[i]->d.cond_nw != common_nw) common_nw = 0;
+  const bool all_nw = sh.lds && sh.width == 1 && common_nw > 1;
   auto lds_for = [&](int nw) {
     size_t m = 0;
     for (int i = 0; i < count; ++i) {
@@ -731,8 +741,9 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
     return m;
   };
   sh.cond_nw = 1;
-  if (sh.lds && sh.width == 1 && (sh.meta_global || all_nw) && lds_for(rh::kCondWaves) <= lds_max)
-    sh.cond_nw = rh::kCondWaves;
+  const int want_b = all_nw ? common_nw : rh::kCondWavesWide;
+  if (sh.lds && sh.width == 1 && (sh.meta_global || all_nw) && lds_for(want_b) <= lds_max)
+    sh.cond_nw = want_b;
   sh.lds_condense = lds_for(sh.cond_nw);
   if (sh.lds_wave > lds_max || sh.lds_staged > lds_max || sh.lds_condense > lds_max) {
     delete b;
