@@ -522,14 +522,14 @@ def workload_name(net, key):
     return net.name
 
 
-def single_instance(api, torch, net, steps, warmup, width=0, lds=1, key="syn1354"):
+def single_instance(api, torch, net, steps, warmup, width=0, lds=1, key="syn1354", waves=0):
     """One instance, one step = eval + refactor + condense (nu + 1 columns) +
     symmetrize + Cholesky + solve + recovery on a seeded iterate; timed over
     `steps` steps after `warmup`, with per-phase HIP events on the library's
     stream and a per-step spread; the condensation kernel's roofline."""
     import numpy as np
     dev = torch.device("cuda", 0)
-    G = api.Net(net, panel_width=width, lds_panel=lds)
+    G = api.Net(net, panel_width=width, lds_panel=lds, cond_waves=waves)
     args_np = iterate(G, net)
     T = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=dev)
     x, u, lam, y, sx, su, ss, r = map(T, args_np)
@@ -663,6 +663,8 @@ def main():
     ap.add_argument("--workload", default="syn1354")
     ap.add_argument("--width", type=int, default=0)
     ap.add_argument("--lds", type=int, default=1)
+    ap.add_argument("--waves", type=int, default=0,
+                    help="waves per condensation work-group (0: the library's choice)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ipm", action="store_true")
@@ -700,7 +702,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     one = single_instance(api, torch, net, args.steps, args.warmup, args.width, args.lds,
-                          key=args.workload)
+                          key=args.workload, waves=args.waves)
     G, args_np = one.pop("_net"), one.pop("_args")
     line = {
         "metric": METRIC,

@@ -107,10 +107,11 @@ typedef struct {
                                 row has at most 64 entries and U fits in LDS,
                                 1 = always the level-staged kernel              */
   int32_t cond_waves;        /* waves per condensation work-group when it takes
-                                one column with its panel in LDS: 1, 4 or 8 (the
-                                waves split each sweep's same-level steps and the
-                                record streams); 0 = auto (8 when the panel fills
-                                the LDS, else 1); other shapes always run 1     */
+                                one column with its panel in LDS: 1, 2, 4 or 8
+                                (the waves split the record streams and, with 4
+                                or 8, each sweep's same-level steps); 0 = auto (8
+                                when the panel fills the LDS, else 2); other
+                                shapes always run 1                             */
   int32_t sweep_grouping;    /* with several waves: 0 = auto (by the sweeps' step
                                 and group counts), else 1 + a mask whose bit k
                                 puts sweep k (L, U, U^T, L^T) on all the waves  */
@@ -341,8 +342,9 @@ rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
 /* In-kernel phase timestamps (device wall clock, 100 MHz) of the first
  * work-group of the last condensation launched while profiling was on:
  * [0] start, [1] panel filled, [2] after L, [3] after U (Z), [4] after the
- * Hessian product, [5] after U^T, [6] after L^T (Psi), [7] columns written.
- * [16 + l] end of level l of the L sweep; [128 + l] end of level l of the
+ * Hessian product, [5] after U^T, [6] after L^T (Psi), [7] columns written,
+ * [8] Z column stored (start of the product), [9] K record stream done
+ * (before H is moved over the panel); [16 + l] end of level l of the L sweep; [128 + l] end of level l of the
  * wave-resident refactorisation; [256 + 8 k + j] the Cholesky's diagonal
  * work-group in factorisation launch k < 24 of the last solve (j = 0 start,
  * 1 previous panel applied, 2 slice factored, 3 stores issued). Host array

@@ -239,8 +239,8 @@ class Net:
     def profile_kernel_trace(self):
         t = (C.c_int64 * 512)()
         _check(lib().rh_profile_kernel_trace(self.h, t), "rh_profile_kernel_trace")
-        names = ["start", "filled", "L", "U", "hvp", "UT", "LT", "written"]
-        out = {names[k]: (t[k] - t[0]) / 100.0 for k in range(8)}   # microseconds
+        names = ["start", "filled", "L", "U", "hvp", "UT", "LT", "written", "zstored", "kstream"]
+        out = {names[k]: (t[k] - t[0]) / 100.0 for k in range(10)}   # microseconds
         # Cholesky factorisation launches: [start, panel k-1 applied, factored,
         # stores issued] of the diagonal work-group, microseconds from launch 0
         chol = []
@@ -288,7 +288,7 @@ def cholesky_solve_noalloc(K, delta_w, b, x, status, stream=None):
            "rh_cholesky_solve_noalloc")
 
 
-def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 4, 8), reps=3):
+def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 2, 4, 8), reps=3):
     """Launch-shape autotuner: times the condensation (all columns with the
     right-hand side) of `net` at `point` = (x, u, lam, y, sig_x, sig_u,
     sig_s, r) for each panel width, panel placement (lds 1: in LDS, with the

@@ -41,6 +41,8 @@ constexpr int kSweepMeta = 4;
 // built; index 0 and 1 of the per-count arrays).
 constexpr int kCondWaves = 4;
 constexpr int kCondWavesWide = 8;
+// two waves: the record streams split, every sweep on one wave
+constexpr int kCondWavesPair = 2;
 inline int wave_index(int nw) { return nw == kCondWavesWide ? 1 : 0; }
 // Row-blocked record streams of the condensation (K, G_u^T): batches of
 // kStreamBatch records per lane.

@@ -662,7 +662,12 @@ static_assert(kCondThreads == 64 && kKRowBlock == kCondThreads, "one lane per ro
 // sweep's same-level steps are spread over them, the record streams split
 // into ranges of row blocks); every other shape runs one wave.
 __host__ __device__ constexpr bool cond_waves_ok(int W, int PM, int NW) {
-  return NW == 1 || ((NW == kCondWaves || NW == kCondWavesWide) && W == 1 && PM != 0);
+  return NW == 1 ||
+         ((NW == kCondWavesPair || NW == kCondWaves || NW == kCondWavesWide) && W == 1 && PM != 0);
+}
+// step lists grouped for NW waves exist for these counts
+__host__ __device__ constexpr bool cond_waves_grouped(int NW) {
+  return NW == kCondWaves || NW == kCondWavesWide;
 }
 
 // Ordering of panel accesses between the steps of one wave. A wave's LDS
@@ -1037,7 +1042,7 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const DevSweep& sw = *sws[k];
-      grp[k] = NW > 1 && ((d.sweep_grouped >> k) & 1);
+      grp[k] = cond_waves_grouped(NW) && ((d.sweep_grouped >> k) & 1);
       const int4* src;
       int n;
       if (k == 0 && reach) {
@@ -1129,6 +1134,7 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
       p_out[v] = vin[v];
     }
   }
+  tick(d, 8);
   // H = K [V ; Z] (+ rt through the indicator row), row block by row block,
   // H rows in stream order; P is read to the end of the product, so H goes to
   // the tile's global scratch and then over P (its rows 0 .. nw - 1)
@@ -1141,6 +1147,7 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
 #pragma unroll
                          for (int c = 0; c < W; ++c) scr[p * W + c] = acc[c];
                      });
+  tick(d, 9);
   // the scratch stores complete (every wave's) before any wave reads them
   if constexpr (NW > 1)
     __syncthreads();
@@ -1385,9 +1392,12 @@ hipError_t dispatch_width(const DevNet& d, int col0, int ncols, int width, int m
                           const double* r, const double* vin, double* K, long ldk, double* rhs,
                           double* p, hipStream_t st) {
   const int nwv = LDS ? d.cond_nw : 1;
-  if (nwv != 1 && nwv != kCondWaves && nwv != kCondWavesWide) return hipErrorInvalidValue;
+  if (nwv != 1 && nwv != kCondWavesPair && nwv != kCondWaves && nwv != kCondWavesWide)
+    return hipErrorInvalidValue;
   if (LDS && d.meta_global) {   // panel mode 2: one column per work-group only
     if (width != 1) return hipErrorInvalidValue;
+    if (nwv == kCondWavesPair)
+      return launch_condense_t<1, 2, kCondWavesPair>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     if (nwv == kCondWavesWide)
       return launch_condense_t<1, 2, kCondWavesWide>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
     if (nwv == kCondWaves)
@@ -1398,6 +1408,8 @@ hipError_t dispatch_width(const DevNet& d, int col0, int ncols, int width, int m
   switch (width) {
     case 1:
       if constexpr (LDS) {
+        if (nwv == kCondWavesPair)
+          return launch_condense_t<1, 1, kCondWavesPair>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
         if (nwv == kCondWavesWide)
           return launch_condense_t<1, 1, kCondWavesWide>(d, col0, ncols, mode, r, vin, K, ldk, rhs, p, st);
         if (nwv == kCondWaves)
@@ -1526,7 +1538,7 @@ size_t condense_lds_bytes(const DevNet& d, int width, bool lds_panels, int nwv) 
   if (!(lds_panels && d.meta_global)) {
     const DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
     for (int k = 0; k < 4; ++k)
-      sweeps += kSweepMeta * (nwv > 1 && ((d.sweep_grouped >> k) & 1)
+      sweeps += kSweepMeta * (cond_waves_grouped(nwv) && ((d.sweep_grouped >> k) & 1)
                                   ? (size_t)nwv * (sws[k]->ngrp[wave_index(nwv)] + 1)
                                   : (size_t)sws[k]->nstep + 1);
   }
@@ -1570,6 +1582,10 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_condense<1, 1, kCondWavesWide, MODE_RECOVER>),
       reinterpret_cast<const void*>(&k_condense<1, 2, kCondWavesWide, MODE_COLUMNS>),
       reinterpret_cast<const void*>(&k_condense<1, 2, kCondWavesWide, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, kCondWavesPair, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 1, kCondWavesPair, MODE_RECOVER>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, kCondWavesPair, MODE_COLUMNS>),
+      reinterpret_cast<const void*>(&k_condense<1, 2, kCondWavesPair, MODE_RECOVER>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 2, 0>),
       reinterpret_cast<const void*>(&k_gx_solve<1, 2, 1>)};
   const void* gfns[] = {
@@ -1601,6 +1617,8 @@ void prepare_lds_kernels() {
       reinterpret_cast<const void*>(&k_condense_b<1, 1, kCondWaves>),
       reinterpret_cast<const void*>(&k_condense_b<1, 2, kCondWavesWide>),
       reinterpret_cast<const void*>(&k_condense_b<1, 1, kCondWavesWide>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 1, kCondWavesPair>),
+      reinterpret_cast<const void*>(&k_condense_b<1, 2, kCondWavesPair>),
       reinterpret_cast<const void*>(&k_condense_b<1, 1>),
       reinterpret_cast<const void*>(&k_condense_b<2, 1>),
       reinterpret_cast<const void*>(&k_condense_b<3, 1>),
@@ -1785,15 +1803,18 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
   hipLaunchKernelGGL((k_condense_b<1, LL, NWV>), dim3(sh.ntiles), dim3(64 * NWV), sh.lds_condense, \
                      st, nets, args, tiles)
   const int nwv = sh.lds ? sh.cond_nw : 1;
-  if (nwv != 1 && nwv != kCondWaves && nwv != kCondWavesWide) return hipErrorInvalidValue;
+  if (nwv != 1 && nwv != kCondWavesPair && nwv != kCondWaves && nwv != kCondWavesWide)
+    return hipErrorInvalidValue;
   if (nwv > 1 && W != 1) return hipErrorInvalidValue;
   if (sh.lds && sh.meta_global) {
     if (W != 1) return hipErrorInvalidValue;
-    if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(2, kCondWavesWide);
+    if (nwv == kCondWavesPair) RH_BATCH_COND_WAVES(2, kCondWavesPair);
+    else if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(2, kCondWavesWide);
     else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(2, kCondWaves);
     else RH_BATCH_COND(1, 2);
   } else if (sh.lds) {
-    if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(1, kCondWavesWide);
+    if (nwv == kCondWavesPair) RH_BATCH_COND_WAVES(1, kCondWavesPair);
+    else if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(1, kCondWavesWide);
     else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(1, kCondWaves);
     else if (W == 1) RH_BATCH_COND(1, 1);
     else if (W == 2) RH_BATCH_COND(2, 1);

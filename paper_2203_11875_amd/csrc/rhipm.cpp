@@ -476,7 +476,8 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   if (want != 1 && want != 2 && want != 3 && want != 4 && want != 8) return RH_ERR_ARG;
   bool lds = !opts || opts->lds_panel != 0;
   const int want_nw = opts ? opts->cond_waves : 0;
-  if (want_nw != 0 && want_nw != 1 && want_nw != rh::kCondWaves && want_nw != rh::kCondWavesWide)
+  if (want_nw != 0 && want_nw != 1 && want_nw != rh::kCondWavesPair && want_nw != rh::kCondWaves &&
+      want_nw != rh::kCondWavesWide)
     return RH_ERR_ARG;
   const int want_grp = opts ? opts->sweep_grouping : 0;
   if (want_grp < 0 || want_grp > 16) return RH_ERR_ARG;
@@ -499,18 +500,22 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   }
   // waves per work-group: several only for one column with its panel in LDS;
   // the record streams split over the waves, each sweep runs on all of them
-  // or on one (sweep_grouping). By default eight where the panel fills the
-  // LDS (one work-group per CU; the 9241-bus condensation call took 6.1 ms
-  // with one wave, 3.8 ms with four, 3.3 ms with eight), else one (with two
-  // or three work-groups per CU the single-wave kernel was faster: 123 us
-  // instead of 139 us with four waves at 1354 buses)
+  // or on one (sweep_grouping; always one with two waves). By default eight
+  // where the panel fills the LDS (one work-group per CU; the 9241-bus
+  // condensation call took 6.1 ms with one wave, 3.8 ms with four, 3.3 ms
+  // with eight), else two (two or three work-groups per CU: the kernel took
+  // 111 us with one wave, 104 us with two and 139 us with four at 1354
+  // buses, where the sweeps on one wave of a four-wave work-group ran
+  // slower than alone)
   d.cond_nw = 1;
   d.sweep_grouped = 0;
   if (lds && want == 1) {
-    const int pick = want_nw != 0 ? want_nw : (d.meta_global ? rh::kCondWavesWide : 1);
+    const int pick = want_nw != 0 ? want_nw : (d.meta_global ? rh::kCondWavesWide : rh::kCondWavesPair);
     if (pick > 1 && rh::condense_lds_bytes(d, 1, true, pick) <= lds_max) {
       d.cond_nw = pick;
-      d.sweep_grouped = want_grp ? want_grp - 1 : sweep_grouping(d, pick, s.nu + 1, lds_max);
+      d.sweep_grouped = pick == rh::kCondWavesPair ? 0
+                        : want_grp                 ? want_grp - 1
+                                                   : sweep_grouping(d, pick, s.nu + 1, lds_max);
       if (rh::condense_lds_bytes(d, 1, true, pick) > lds_max) d.sweep_grouped = 0;
     }
   }

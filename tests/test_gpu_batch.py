@@ -37,7 +37,7 @@ def _batch_nets():
             synthnet.case9(1)]
 
 
-@pytest.mark.parametrize("nw,grp", [(0, 0), (1, 0), (4, 16), (8, 16)])
+@pytest.mark.parametrize("nw,grp", [(0, 0), (1, 0), (2, 0), (4, 16), (8, 16)])
 def test_batch_matches_single_instance_bitwise(nw, grp):
     """nw: waves per condensation work-group of every member (0 = the
     library's choice; with 4 for all members the batch runs 4 as well), grp:
@@ -175,8 +175,8 @@ def test_autotuner_picks_a_measured_configuration():
     M = Model(net)
     pt = random_point(M, 5) + (residual_vector(M, 6),)
     pt = tuple(torch.as_tensor(np.asarray(v, np.float64), device="cuda") for v in pt)
-    best, times = api.autotune(net, pt, widths=(1, 2), lds=(1, 0), waves=(1, 4, 8), reps=2)
+    best, times = api.autotune(net, pt, widths=(1, 2), lds=(1, 0), waves=(1, 2, 4, 8), reps=2)
     # several waves only for one column with its panel in LDS
-    assert set(times) == {(1, 1, 1), (1, 1, 4), (1, 1, 8), (1, 0, 1), (2, 1, 1), (2, 0, 1)}
+    assert set(times) == {(1, 1, 1), (1, 1, 2), (1, 1, 4), (1, 1, 8), (1, 0, 1), (2, 1, 1), (2, 0, 1)}
     assert best in times
     assert times[best] == min(times.values())

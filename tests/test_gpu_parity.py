@@ -196,7 +196,7 @@ def test_bitwise_repeatable_and_width_independent(name):
     # (panel width, panels in LDS, waves per work-group, sweeps on all waves:
     # 0 the library's choice, else 1 + a mask over L, U, U^T, L^T)
     for width, lds, nw, grp in ((1, 1, 1, 0), (1, 1, 4, 1), (1, 1, 4, 16), (1, 1, 4, 1 + 5),
-                                (1, 1, 8, 1), (1, 1, 8, 16), (2, 1, 1, 0), (2, 1, 1, 0),
+                                (1, 1, 8, 1), (1, 1, 8, 16), (1, 1, 2, 1), (2, 1, 1, 0), (2, 1, 1, 0),
                                 (3, 1, 1, 0), (2, 0, 1, 0), (4, 0, 1, 0)):
         G = _net_api().Net(net, panel_width=width, lds_panel=lds, cond_waves=nw,
                            sweep_grouping=grp)
@@ -225,7 +225,8 @@ def test_set_loads_changes_residual():
 
 
 @pytest.mark.parametrize("name,width,nw", [("syn9", 1, 1), ("syn1354", 1, 1), ("syn1354", 1, 4),
-                                           ("syn1354", 1, 8), ("syn118", 2, 1), ("syn1354", 3, 1)])
+                                           ("syn1354", 1, 8), ("syn1354", 1, 2), ("syn118", 2, 1),
+                                           ("syn1354", 3, 1)])
 @pytest.mark.parametrize("grp", [0, 16])
 def test_solve_after_condensation_without_rhs(name, width, nw, grp):
     """Recovery by the single-column pass (condensation called without r),
