@@ -730,7 +730,7 @@ def main():
         line["batched"] = batched_run(api, torch, args.batch_steps, 2)
         _progress("batched condensation done")
         best, times = api.autotune(net, (x, u, lam, y, sx, su, ss, r), widths=(1, 2, 4),
-                                   lds=(1, 0), reps=3)
+                                   lds=(1, 0), reps=3, record=False)
         line["autotune"] = {"best": {"panel_width": best[0], "lds_panel": best[1],
                                      "cond_waves": best[2]},
                             "condensation_us": {f"w{w}_lds{l}_nw{nw}": round(v, 1)

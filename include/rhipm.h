@@ -210,15 +210,17 @@ rh_status rh_set_loads(rh_net* net, const double* pd_dev, const double* qd_dev);
 
 /* ---------------------------------------------------------------------------
  * Batches (several networks or load scenarios condensed and solved together;
- * Section 3.3 per instance). A batch refers to existing handles, which
- * must share the panel width and LDS placement (the defaults do) and must
+ * Section 3.3 per instance). A batch refers to existing handles, which must
  * not be used by other calls while a batch call runs (each batch call first
- * waits for the instances' own streams); the handles outlive the batch. Every batched kernel serves all instances in one launch, with
- * the same kernel bodies as the single-instance calls, so each instance's
- * results equal, bit for bit, those of rh_condense_reduced_hessian (with r)
- * and rh_solve_condensed_kkt on the same inputs. hip_stream: the batch's
- * stream (NULL = default). Errors: RH_ERR_ARG (mixed widths / placements,
- * an instance too large for LDS staging), RH_ERR_OOM, RH_ERR_HIP.
+ * waits for the instances' own streams); the handles outlive the batch. Every
+ * batched kernel serves all instances in one launch, except the condensation,
+ * which takes one launch per class of instances of one panel width and
+ * placement (each instance keeps its own launch shape); the kernel bodies are
+ * those of the single-instance calls, so each instance's results equal, bit
+ * for bit, those of rh_condense_reduced_hessian (with r) and
+ * rh_solve_condensed_kkt on the same inputs. hip_stream: the batch's stream
+ * (NULL = default). Errors: RH_ERR_ARG (an instance too large for LDS
+ * staging), RH_ERR_OOM, RH_ERR_HIP.
  * ------------------------------------------------------------------------- */
 typedef struct rh_batch rh_batch;
 typedef struct {

@@ -49,6 +49,38 @@ class _Desc:
         self.desc = d
 
 
+# Launch shapes chosen by autotune(), by network structure (launch_key): Net
+# takes them when its caller leaves the shape options unset.
+TUNING = {}
+
+
+def launch_key(net):
+    """Structure of a network that its launch shape depends on (the sizes and
+    the bus, branch and generator incidence; not the loads or line values),
+    as a hex digest: load scenarios of one network share a key."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.asarray([int(net.nb), int(net.nl), int(net.ng)], np.int64).tobytes())
+    for name in ("bus_type", "f", "t", "gen_bus"):
+        h.update(np.ascontiguousarray(getattr(net, name), dtype=np.int32).tobytes())
+    return h.hexdigest()
+
+
+def save_tuning(path):
+    """Writes TUNING as JSON ({key: [panel_width, lds_panel, cond_waves]})."""
+    import json
+    with open(path, "w") as f:
+        json.dump({k: list(v) for k, v in TUNING.items()}, f, indent=1, sort_keys=True)
+
+
+def load_tuning(path):
+    """Adds the entries of a file written by save_tuning to TUNING."""
+    import json
+    with open(path) as f:
+        for k, v in json.load(f).items():
+            TUNING[str(k)] = tuple(int(x) for x in v)
+
+
 def _opts(panel_width=0, lds_panel=1, refactor=0, cond_waves=0, sweep_grouping=0, ordering=0):
     o = _abi.rh_options()
     o.panel_width = int(panel_width)
@@ -127,13 +159,23 @@ def _ptr(t):
 
 
 class Net:
-    """Device handle (rh_init_network). Inputs are float64 CUDA tensors."""
+    """Device handle (rh_init_network). Inputs are float64 CUDA tensors.
 
-    def __init__(self, net, panel_width=0, lds_panel=1, stream=None, refactor=0, cond_waves=0,
-                 sweep_grouping=0, ordering=0):
+    panel_width, lds_panel and cond_waves left as None take the shape that
+    autotune() recorded for this network's structure (TUNING), else the
+    library's choice (0, 1, 0)."""
+
+    def __init__(self, net, panel_width=None, lds_panel=None, stream=None, refactor=0,
+                 cond_waves=None, sweep_grouping=0, ordering=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("rhipm.Net needs a HIP device")
+        if panel_width is None and lds_panel is None and cond_waves is None:
+            panel_width, lds_panel, cond_waves = TUNING.get(launch_key(net), (0, 1, 0))
+        panel_width = 0 if panel_width is None else panel_width
+        lds_panel = 1 if lds_panel is None else lds_panel
+        cond_waves = 0 if cond_waves is None else cond_waves
+        self.tuned = (panel_width, lds_panel, cond_waves)
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -288,14 +330,17 @@ def cholesky_solve_noalloc(K, delta_w, b, x, status, stream=None):
            "rh_cholesky_solve_noalloc")
 
 
-def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 2, 4, 8), reps=3):
+def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 2, 4, 8), reps=3, record=True):
     """Launch-shape autotuner: times the condensation (all columns with the
     right-hand side) of `net` at `point` = (x, u, lam, y, sig_x, sig_u,
     sig_s, r) for each panel width, panel placement (lds 1: in LDS, with the
     sweep metadata in global memory where the panel fills the LDS) and waves
     per work-group (several only for one column in LDS), and returns
     (best (width, lds, waves), {(width, lds, waves): microseconds}).
-    Configurations the device cannot hold are skipped."""
+    Configurations the device cannot hold are skipped. With record, the
+    best shape goes into TUNING under the network's launch_key, so that Net
+    handles of this network (any loads) created without shape options use
+    it; save_tuning / load_tuning keep it across processes."""
     import time
     import torch
     times = {}
@@ -322,6 +367,8 @@ def autotune(net, point, widths=(1, 2, 4), lds=(1, 0), waves=(1, 2, 4, 8), reps=
                 times[(w, l, nw)] = 1e6 * (time.perf_counter() - t0) / reps
                 G.close()
     best = min(times, key=times.get)
+    if record:
+        TUNING[launch_key(net)] = tuple(int(v) for v in best)
     return best, times
 
 

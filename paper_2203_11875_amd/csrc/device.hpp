@@ -137,16 +137,23 @@ struct BatchArg {
   int* status;
   int nu, m;
 };
+// One condensation launch of a batch: the members of one panel width and
+// placement, their column tiles contiguous in the tile table from tile0.
+struct CondClass {
+  int width = 1, nw = 1, tile0 = 0, ntiles = 0;
+  bool lds = true, meta_global = false;
+  size_t lds_bytes = 0;
+};
 // Host-side shape of a batch: maxima over the instances for the grids and
 // dynamic LDS of the batched launches.
 struct BatchShape {
-  int count = 0, width = 1, ntiles = 0;
-  bool lds = true, meta_global = false, any_wave = false, any_staged = false;
-  int cond_nw = 1;   // waves per condensation work-group
+  int count = 0;
+  bool any_wave = false, any_staged = false;
+  std::vector<CondClass> cls;   // condensation launches
   int max_split = 0, max_split_grid = 0;   // refactorisation levels run one launch each
   int max_staged_levels = 0, max_staged_grid = 0;
   int max_lines = 0, max_dst = 0, max_nnz_k = 0, max_nw = 0, max_nx = 0, max_nu = 0, max_m = 0;
-  size_t lds_wave = 0, lds_staged = 0, lds_condense = 0;
+  size_t lds_wave = 0, lds_staged = 0;
   std::vector<int> orders;   // order (nu) of each instance's condensed matrix
 };
 // Condensation of every instance (eval, K assembly, rt, refactorisation,

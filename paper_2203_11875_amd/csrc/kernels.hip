@@ -1795,41 +1795,47 @@ hipError_t launch_batch_condense(const DevNet* nets, const BatchArg* args, const
     hipLaunchKernelGGL(k_refactor_level_staged_b, dim3(sh.max_staged_grid, 1, B), dim3(kRefThreads),
                        sh.lds_staged, st, nets, lev);
   hipLaunchKernelGGL(k_transcribe_b, dim3(64, 1, B), dim3(kBlock), 0, st, nets);
-  const int W = sh.width;
+  // one condensation launch per class of members (panel width and placement)
+  for (const CondClass& c : sh.cls) {
+    if (c.ntiles == 0) continue;
+    const int2* ct = tiles + c.tile0;
+    const int W = c.width;
 #define RH_BATCH_COND(WW, LL)                                                                   \
-  hipLaunchKernelGGL((k_condense_b<WW, LL>), dim3(sh.ntiles), dim3(64), sh.lds_condense, st, nets, \
-                     args, tiles)
+  hipLaunchKernelGGL((k_condense_b<WW, LL>), dim3(c.ntiles), dim3(64), c.lds_bytes, st, nets, args, \
+                     ct)
 #define RH_BATCH_COND_WAVES(LL, NWV)                                                            \
-  hipLaunchKernelGGL((k_condense_b<1, LL, NWV>), dim3(sh.ntiles), dim3(64 * NWV), sh.lds_condense, \
-                     st, nets, args, tiles)
-  const int nwv = sh.lds ? sh.cond_nw : 1;
-  if (nwv != 1 && nwv != kCondWavesPair && nwv != kCondWaves && nwv != kCondWavesWide)
-    return hipErrorInvalidValue;
-  if (nwv > 1 && W != 1) return hipErrorInvalidValue;
-  if (sh.lds && sh.meta_global) {
-    if (W != 1) return hipErrorInvalidValue;
-    if (nwv == kCondWavesPair) RH_BATCH_COND_WAVES(2, kCondWavesPair);
-    else if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(2, kCondWavesWide);
-    else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(2, kCondWaves);
-    else RH_BATCH_COND(1, 2);
-  } else if (sh.lds) {
-    if (nwv == kCondWavesPair) RH_BATCH_COND_WAVES(1, kCondWavesPair);
-    else if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(1, kCondWavesWide);
-    else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(1, kCondWaves);
-    else if (W == 1) RH_BATCH_COND(1, 1);
-    else if (W == 2) RH_BATCH_COND(2, 1);
-    else if (W == 3) RH_BATCH_COND(3, 1);
-    else if (W == 4) RH_BATCH_COND(4, 1);
-    else RH_BATCH_COND(8, 1);
-  } else {
-    if (W == 1) RH_BATCH_COND(1, 0);
-    else if (W == 2) RH_BATCH_COND(2, 0);
-    else if (W == 3) RH_BATCH_COND(3, 0);
-    else if (W == 4) RH_BATCH_COND(4, 0);
-    else RH_BATCH_COND(8, 0);
-  }
+  hipLaunchKernelGGL((k_condense_b<1, LL, NWV>), dim3(c.ntiles), dim3(64 * NWV), c.lds_bytes, st, \
+                     nets, args, ct)
+    const int nwv = c.lds ? c.nw : 1;
+    if (nwv != 1 && nwv != kCondWavesPair && nwv != kCondWaves && nwv != kCondWavesWide)
+      return hipErrorInvalidValue;
+    if (nwv > 1 && W != 1) return hipErrorInvalidValue;
+    if (W != 1 && W != 2 && W != 3 && W != 4 && W != 8) return hipErrorInvalidValue;
+    if (c.lds && c.meta_global) {
+      if (W != 1) return hipErrorInvalidValue;
+      if (nwv == kCondWavesPair) RH_BATCH_COND_WAVES(2, kCondWavesPair);
+      else if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(2, kCondWavesWide);
+      else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(2, kCondWaves);
+      else RH_BATCH_COND(1, 2);
+    } else if (c.lds) {
+      if (nwv == kCondWavesPair) RH_BATCH_COND_WAVES(1, kCondWavesPair);
+      else if (nwv == kCondWavesWide) RH_BATCH_COND_WAVES(1, kCondWavesWide);
+      else if (nwv == kCondWaves) RH_BATCH_COND_WAVES(1, kCondWaves);
+      else if (W == 1) RH_BATCH_COND(1, 1);
+      else if (W == 2) RH_BATCH_COND(2, 1);
+      else if (W == 3) RH_BATCH_COND(3, 1);
+      else if (W == 4) RH_BATCH_COND(4, 1);
+      else RH_BATCH_COND(8, 1);
+    } else {
+      if (W == 1) RH_BATCH_COND(1, 0);
+      else if (W == 2) RH_BATCH_COND(2, 0);
+      else if (W == 3) RH_BATCH_COND(3, 0);
+      else if (W == 4) RH_BATCH_COND(4, 0);
+      else RH_BATCH_COND(8, 0);
+    }
 #undef RH_BATCH_COND
 #undef RH_BATCH_COND_WAVES
+  }
   hipLaunchKernelGGL(k_symmetrize_b, dim3(cdiv(sh.max_nu, 16), cdiv(sh.max_nu, 16), B),
                      dim3(16, 16), 0, st, args);
   return hipGetLastError();

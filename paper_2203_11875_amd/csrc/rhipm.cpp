@@ -693,11 +693,19 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
   sh.count = count;
   std::vector<int2> tiles;
   const size_t lds_max = size_t(rh::max_lds_bytes());
+  std::vector<int> cls_of(count, -1);   // condensation class of each member
   for (int i = 0; i < count; ++i) {
     rh_net* n = nets[i];
     if (!n) { delete b; return RH_ERR_ARG; }
-    if (i == 0) { sh.width = n->width; sh.lds = n->lds; }
-    if (n->width != sh.width || n->lds != sh.lds) { delete b; return RH_ERR_ARG; }
+    for (size_t c = 0; c < sh.cls.size(); ++c)
+      if (sh.cls[c].width == n->width && sh.cls[c].lds == n->lds) cls_of[i] = int(c);
+    if (cls_of[i] < 0) {
+      rh::CondClass c;
+      c.width = n->width;
+      c.lds = n->lds;
+      sh.cls.push_back(c);
+      cls_of[i] = int(sh.cls.size()) - 1;
+    }
     const rh::DevNet& d = n->d;
     b->nets.push_back(n);
     sh.max_lines = std::max(sh.max_lines, std::max(d.nl, d.nu));
@@ -722,35 +730,46 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
       }
       sh.lds_staged = std::max(sh.lds_staged, size_t(d.rf_lds_doubles) * sizeof(double));
     }
-    sh.meta_global = sh.meta_global || d.meta_global != 0;
     sh.orders.push_back(d.nu);
-    const int ntile = (d.nu + 1 + sh.width - 1) / sh.width;
-    for (int t = 0; t < ntile; ++t) tiles.push_back(int2{i, t});
   }
-  sh.ntiles = int(tiles.size());
-  // one panel mode for the whole launch: the sweep metadata of every member
-  // is read from global memory when one member's panel fills the LDS; several
-  // waves per work-group then, or when every member runs several
-  // the members' wave count when they all agree on one above 1
-  int common_nw = nets[0]->d.cond_nw;
-  for (int i = 1; i < count; ++i)
-    if (nets[i]->d.cond_nw != common_nw) common_nw = 0;
-  const bool all_nw = sh.lds && sh.width == 1 && common_nw > 1;
-  auto lds_for = [&](int nw) {
-    size_t m = 0;
+  // one condensation launch per class, its members' tiles contiguous. Within
+  // a class one panel mode: the sweep metadata of every member is read from
+  // global memory when one member's panel fills the LDS; several waves per
+  // work-group then, or when every member of the class runs several (their
+  // common count)
+  bool lds_ok = sh.lds_wave <= lds_max && sh.lds_staged <= lds_max;
+  for (size_t ci = 0; ci < sh.cls.size(); ++ci) {
+    rh::CondClass& c = sh.cls[ci];
+    c.tile0 = int(tiles.size());
+    int common_nw = -1;
     for (int i = 0; i < count; ++i) {
-      rh::DevNet dd = nets[i]->d;
-      dd.meta_global = sh.meta_global ? 1 : 0;
-      m = std::max(m, rh::condense_lds_bytes(dd, sh.width, sh.lds, nw));
+      if (cls_of[i] != int(ci)) continue;
+      const rh::DevNet& d = nets[i]->d;
+      c.meta_global = c.meta_global || (c.lds && d.meta_global != 0);
+      common_nw = common_nw < 0 || common_nw == d.cond_nw ? d.cond_nw : 0;
+      const int ntile = (d.nu + 1 + c.width - 1) / c.width;
+      for (int t = 0; t < ntile; ++t) tiles.push_back(int2{i, t});
     }
-    return m;
-  };
-  sh.cond_nw = 1;
-  const int want_b = all_nw ? common_nw : rh::kCondWavesWide;
-  if (sh.lds && sh.width == 1 && (sh.meta_global || all_nw) && lds_for(want_b) <= lds_max)
-    sh.cond_nw = want_b;
-  sh.lds_condense = lds_for(sh.cond_nw);
-  if (sh.lds_wave > lds_max || sh.lds_staged > lds_max || sh.lds_condense > lds_max) {
+    c.ntiles = int(tiles.size()) - c.tile0;
+    const bool all_nw = c.lds && c.width == 1 && common_nw > 1;
+    auto lds_for = [&](int nw) {
+      size_t m = 0;
+      for (int i = 0; i < count; ++i) {
+        if (cls_of[i] != int(ci)) continue;
+        rh::DevNet dd = nets[i]->d;
+        dd.meta_global = c.meta_global ? 1 : 0;
+        m = std::max(m, rh::condense_lds_bytes(dd, c.width, c.lds, nw));
+      }
+      return m;
+    };
+    c.nw = 1;
+    const int want_b = all_nw ? common_nw : rh::kCondWavesWide;
+    if (c.lds && c.width == 1 && (c.meta_global || all_nw) && lds_for(want_b) <= lds_max)
+      c.nw = want_b;
+    c.lds_bytes = lds_for(c.nw);
+    lds_ok = lds_ok && c.lds_bytes <= lds_max;
+  }
+  if (!lds_ok) {
     delete b;
     return RH_ERR_ARG;
   }

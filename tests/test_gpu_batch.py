@@ -119,12 +119,44 @@ def test_batch_matches_oracle_small_instances():
     B.close()
 
 
-def test_batch_rejects_mixed_widths_and_solve_before_condense():
+def test_batch_of_mixed_launch_shapes_matches_single_instances_bitwise():
+    """Members with their own panel width, placement and waves (one
+    condensation launch per width and placement) give, member by member, the
+    single-instance K_cond, right-hand side and step bit for bit."""
     api = _api()
-    G1 = api.Net(synthnet.case9(1), panel_width=1)
-    G2 = api.Net(synthnet.case9(3), panel_width=2)
-    with pytest.raises(Exception):
-        api.Batch([G1, G2])
+    nets = _batch_nets()
+    shapes = [dict(panel_width=1, lds_panel=1, cond_waves=2),
+              dict(panel_width=2, lds_panel=1),
+              dict(panel_width=1, lds_panel=0),
+              dict(panel_width=4, lds_panel=1),
+              dict(panel_width=1, lds_panel=1, cond_waves=4, sweep_grouping=16)]
+    Gs = [api.Net(n, **sh) for n, sh in zip(nets, shapes)]
+    assert len({(G.info["panel_width"], G.info["lds_panel"]) for G in Gs}) == 4
+    pts, rs = [], []
+    for i, n in enumerate(nets):
+        M = Model(n)
+        pts.append(random_point(M, 30 + i, sig_range=(10.0, 1e4)))
+        rs.append(residual_vector(M, 40 + i))
+    B = api.Batch(Gs)
+    Kb, rhsb = B.condense([p + (r,) for p, r in zip(pts, rs)])
+    pb, stb = B.solve([K.clone() for K in Kb], 0.0, rhsb, rs)
+    torch.cuda.synchronize()
+    for i, (G, p, r) in enumerate(zip(Gs, pts, rs)):
+        K, rhs = G.condense_reduced_hessian(*p, r=r)
+        ps, code = G.solve_condensed_kkt(K.clone(), 0.0, rhs, r)
+        torch.cuda.synchronize()
+        assert code == stb[i], nets[i].name
+        assert np.array_equal(_np(K), _np(Kb[i])), nets[i].name
+        assert np.array_equal(_np(rhs), _np(rhsb[i])), nets[i].name
+        if code == 0:
+            assert np.array_equal(_np(ps), _np(pb[i])), nets[i].name
+    B.close()
+    for G in Gs:
+        G.close()
+
+
+def test_batch_rejects_solve_before_condense():
+    api = _api()
     G3 = api.Net(synthnet.case9(5))
     B = api.Batch([G3])
     M = Model(synthnet.case9(5))
@@ -175,8 +207,23 @@ def test_autotuner_picks_a_measured_configuration():
     M = Model(net)
     pt = random_point(M, 5) + (residual_vector(M, 6),)
     pt = tuple(torch.as_tensor(np.asarray(v, np.float64), device="cuda") for v in pt)
-    best, times = api.autotune(net, pt, widths=(1, 2), lds=(1, 0), waves=(1, 2, 4, 8), reps=2)
-    # several waves only for one column with its panel in LDS
-    assert set(times) == {(1, 1, 1), (1, 1, 2), (1, 1, 4), (1, 1, 8), (1, 0, 1), (2, 1, 1), (2, 0, 1)}
-    assert best in times
-    assert times[best] == min(times.values())
+    key = api.launch_key(net)
+    try:
+        best, times = api.autotune(net, pt, widths=(1, 2), lds=(1, 0), waves=(1, 2, 4, 8), reps=2)
+        # several waves only for one column with its panel in LDS
+        assert set(times) == {(1, 1, 1), (1, 1, 2), (1, 1, 4), (1, 1, 8), (1, 0, 1), (2, 1, 1),
+                              (2, 0, 1)}
+        assert best in times
+        assert times[best] == min(times.values())
+        # the recorded shape is what a handle of the same network (other loads)
+        # created without shape options runs; explicit options still win
+        assert api.TUNING[key] == best
+        G = api.Net(synthnet.scale_loads(net, 3))
+        got = (G.info["panel_width"], int(G.info["lds_panel"] != 0), G.info["cond_waves"])
+        assert got == best, (got, best)
+        G.close()
+        G = api.Net(net, panel_width=2, lds_panel=0)
+        assert (G.info["panel_width"], G.info["lds_panel"], G.info["cond_waves"]) == (2, 0, 1)
+        G.close()
+    finally:
+        api.TUNING.pop(key, None)

@@ -147,6 +147,27 @@ def test_level_term_shortens_the_dependency_chain():
     assert a["sweep_steps"] < b["sweep_steps"]
 
 
+def test_launch_key_and_tuning_file(tmp_path):
+    """The tuning cache's key follows the network structure only: load
+    scenarios share it, another network does not; a saved table loads back."""
+    api = _lib()
+    a = synthnet.case118(0)
+    assert api.launch_key(a) == api.launch_key(synthnet.scale_loads(a, 5))
+    assert api.launch_key(a) != api.launch_key(synthnet.case300(0))
+    saved = dict(api.TUNING)
+    try:
+        api.TUNING.clear()
+        api.TUNING[api.launch_key(a)] = (2, 1, 1)
+        path = tmp_path / "tuning.json"
+        api.save_tuning(path)
+        api.TUNING.clear()
+        api.load_tuning(path)
+        assert api.TUNING == {api.launch_key(a): (2, 1, 1)}
+    finally:
+        api.TUNING.clear()
+        api.TUNING.update(saved)
+
+
 def test_rejects_bad_networks():
     api = _lib()
     net = synthnet.case9(1)
