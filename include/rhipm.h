@@ -102,7 +102,10 @@ typedef struct {
                                 2 = nested dissection (more levels and fill on
                                 power networks; a network whose LU rows then
                                 exceed a sweep step is rejected)                */
-  int32_t lds_panel;         /* 1 = keep panels in LDS when they fit, 0 = global  */
+  int32_t lds_panel;         /* 1 = keep panels in LDS when they fit, 0 = global,
+                                2 = in LDS with the sweep metadata read from
+                                global memory (width 1; chosen by 1 as well where
+                                the panel alone fills the LDS)                  */
   int32_t refactor;          /* 0 = wave-resident refactorisation when every LU
                                 row has at most 64 entries and U fits in LDS,
                                 1 = always the level-staged kernel              */

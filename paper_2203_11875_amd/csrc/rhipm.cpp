@@ -475,6 +475,17 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   int want = opts && opts->panel_width > 0 ? opts->panel_width : 1;
   if (want != 1 && want != 2 && want != 3 && want != 4 && want != 8) return RH_ERR_ARG;
   bool lds = !opts || opts->lds_panel != 0;
+  if (opts && (opts->lds_panel < 0 || opts->lds_panel > 2)) return RH_ERR_ARG;
+  // lds_panel 2: the sweep metadata read from global memory (one column per
+  // work-group) even where it would fit beside the panel
+  if (opts && opts->lds_panel == 2) {
+    if (want != 1) return RH_ERR_ARG;
+    d.meta_global = 1;
+    if (rh::condense_lds_bytes(d, 1, true, 1) > lds_max) {
+      d.meta_global = 0;
+      lds = false;
+    }
+  }
   const int want_nw = opts ? opts->cond_waves : 0;
   if (want_nw != 0 && want_nw != 1 && want_nw != rh::kCondWavesPair && want_nw != rh::kCondWaves &&
       want_nw != rh::kCondWavesWide)

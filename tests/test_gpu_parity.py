@@ -195,12 +195,16 @@ def test_bitwise_repeatable_and_width_independent(name):
     outs = []
     # (panel width, panels in LDS, waves per work-group, sweeps on all waves:
     # 0 the library's choice, else 1 + a mask over L, U, U^T, L^T)
+    # (lds 2: the step metadata read from global memory, as for a panel that
+    # fills the LDS)
     for width, lds, nw, grp in ((1, 1, 1, 0), (1, 1, 4, 1), (1, 1, 4, 16), (1, 1, 4, 1 + 5),
-                                (1, 1, 8, 1), (1, 1, 8, 16), (1, 1, 2, 1), (2, 1, 1, 0), (2, 1, 1, 0),
+                                (1, 1, 8, 1), (1, 1, 8, 16), (1, 1, 2, 1), (1, 2, 2, 1),
+                                (1, 2, 8, 16), (1, 2, 1, 0), (2, 1, 1, 0), (2, 1, 1, 0),
                                 (3, 1, 1, 0), (2, 0, 1, 0), (4, 0, 1, 0)):
         G = _net_api().Net(net, panel_width=width, lds_panel=lds, cond_waves=nw,
                            sweep_grouping=grp)
         assert G.info["cond_waves"] == nw
+        assert G.info["lds_panel"] == lds
         if nw > 1:
             assert G.info["sweep_grouped"] == grp - 1
         K, _ = G.condense_reduced_hessian(*args)
