@@ -671,14 +671,15 @@ __host__ __device__ constexpr bool cond_waves_grouped(int NW) {
 }
 
 // Ordering of panel accesses between the steps of one wave. A wave's LDS
-// operations complete in issue order, so for LDS panels a wavefront-scope
-// fence (no instruction; it keeps the compiler from moving accesses across)
-// is enough; panels in global memory take a workgroup-scope fence, which
-// waits for the stores.
+// operations complete in issue order, so for LDS panels a compiler-only
+// fence is enough: it keeps the compiler from moving accesses across and
+// emits no instruction (a wavefront-scope fence waits for the wave's LDS
+// operations, lgkmcnt(0), once per sweep step); panels in global memory take
+// a workgroup-scope fence, which waits for the stores.
 template <bool LDS>
 __device__ __forceinline__ void panel_sync() {
   if (LDS)
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   else
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 }
@@ -794,6 +795,11 @@ __device__ __forceinline__ void sweep_step(const StepFetch& f, char* pb) {
     if (f.ls >= 5) acc[c] = add_bcast<0x142, 0xA>(acc[c]);
     if (f.ls >= 6) acc[c] = add_bcast<0x143, 0xC>(acc[c]);
   }
+  // the row's old value read (lgkmcnt(0)) before the writer branch, on every
+  // path: otherwise the compiler keeps that read pending on the path that
+  // skips the branch, and the next step's record loads, which reuse its
+  // registers, wait for every LDS operation, the store just issued included
+  if (LDS) __builtin_amdgcn_s_waitcnt(0xC07F);
   if (rw >> 32) {
 #pragma unroll
     for (int c = 0; c < W; ++c)
