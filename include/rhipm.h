@@ -349,7 +349,8 @@ rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
  * [0] start, [1] panel filled, [2] after L, [3] after U (Z), [4] after the
  * Hessian product, [5] after U^T, [6] after L^T (Psi), [7] columns written,
  * [8] Z column stored (start of the product), [9] K record stream done
- * (before H is moved over the panel); [16 + l] end of level l of the L sweep; [128 + l] end of level l of the
+ * (before H is moved over the panel), [10] kernel entry (before the step
+ * metadata is staged); [16 + l] end of level l of the L sweep; [128 + l] end of level l of the
  * wave-resident refactorisation; [256 + 8 k + j] the Cholesky's diagonal
  * work-group in factorisation launch k < 24 of the last solve (j = 0 start,
  * 1 previous panel applied, 2 slice factored, 3 stores issued). Host array

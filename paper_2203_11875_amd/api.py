@@ -281,8 +281,9 @@ class Net:
     def profile_kernel_trace(self):
         t = (C.c_int64 * 512)()
         _check(lib().rh_profile_kernel_trace(self.h, t), "rh_profile_kernel_trace")
-        names = ["start", "filled", "L", "U", "hvp", "UT", "LT", "written", "zstored", "kstream"]
-        out = {names[k]: (t[k] - t[0]) / 100.0 for k in range(10)}   # microseconds
+        names = ["start", "filled", "L", "U", "hvp", "UT", "LT", "written", "zstored", "kstream",
+                 "entry"]
+        out = {names[k]: (t[k] - t[0]) / 100.0 for k in range(11)}   # microseconds
         # Cholesky factorisation launches: [start, panel k-1 applied, factored,
         # stores issued] of the diagonal work-group, microseconds from launch 0
         chol = []

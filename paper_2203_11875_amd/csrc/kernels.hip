@@ -989,6 +989,26 @@ __device__ __forceinline__ void indexed_loop(const int* idx, int n, F&& body) {
   }
 }
 
+// store(i, idx[i], load(i, idx[i])) for i < n over the work-group's threads: the
+// index loads and then the value loads of eight rounds issued together
+// (both clamped to row n - 1, whose index is valid, so that no load sits in
+// a branch) before the stores.
+template <class L, class S>
+__device__ __forceinline__ void gather_loop(const int* idx, int n, L&& load, S&& store) {
+  const int T = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * T) {
+    int ix[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ix[u] = idx[min(i0 + u * T, n - 1)];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = load(min(i0 + u * T, n - 1), ix[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * T < n) store(i0 + u * T, ix[u], v[u]);
+  }
+}
+
 // Columns [col0 + blk * W, ...) of the condensed matrix (Section 3.3), one
 // wave per work-group (blk = the work-group's tile):
 //   Z   = -G_x^{-1} G_u V          (L then U sweep; V = identity columns)
@@ -1016,6 +1036,7 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
     if (blk == 0 && threadIdx.x == 0) d.status[4] = 1;
     return;
   }
+  tick(d, 10);
   const int nw = d.nw, nu = d.nu, nx = d.nx;
   double* P = LDS ? panel_lds : d.panel + (size_t)blk * (nw + 1) * W;
   double* H = P;   // H replaces P after the Hessian product
@@ -1042,9 +1063,25 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
   bool grp[4];
   int* kb_end;
   constexpr int gi = NW == kCondWavesWide ? 1 : 0;   // which grouped lists
+  const int jc0 = col0 + blk * W;
+  const double* gu = d.dst + d.d_gu;
+  const double* r4 = r ? r + d.nu + d.nx + d.m : nullptr;
+  // The prologue's global reads go out in rounds that overlap: the first
+  // G_u entries of the identity columns (three dependent reads: column
+  // pointers, rows and sources, values) beside the staging of the step lists
+  // and stream block ends (one read each, all requested before any store).
+  int ge0[W], ge1[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int j = jc0 + c;
+    const bool idc = mode == MODE_COLUMNS && j < nu && j < col_end;
+    ge0[c] = idc ? d.gucsc_ptr[j] : 0;
+    ge1[c] = idc ? d.gucsc_ptr[j + 1] : 0;
+  }
+  const int4* lsrc[4];
+  int lcnt[4];
   {
     const DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
-    int4* slot = mlds;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const DevSweep& sw = *sws[k];
@@ -1060,19 +1097,47 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
         src = reinterpret_cast<const int4*>(grp[k] ? sw.gmeta[gi] : sw.meta);
         n = grp[k] ? sw.ngrp[gi] : sw.nstep;
       }
-      const int lists = grp[k] ? NW : 1, mine = grp[k] ? wave * (n + 1) : 0;
       n_sw[k] = n;
+      lsrc[k] = src;
+      lcnt[k] = (grp[k] ? NW : 1) * (n + 1);
+    }
+  }
+  // first round of the staging: every list's element tid
+  int4 v4[4];
+  if constexpr (PM != 2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v4[k] = tid < lcnt[k] ? lsrc[k][tid] : int4{0, 0, 0, 0};
+  }
+  const int vk = tid < d.kb_n ? d.kb_end[tid] : 0;
+  const int vg = tid < d.gt_nb ? d.gt_end[tid] : 0;
+  int grw[W], gfr[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int e = ge0[c] + tid;
+    grw[c] = e < ge1[c] ? d.gucsc_row[e] : 0;
+    gfr[c] = e < ge1[c] ? d.gucsc_from[e] : 0;
+  }
+  {
+    const DevSweep* sws[4] = {&d.sl, &d.su, &d.sut, &d.slt};
+    int4* slot = mlds;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int mine = grp[k] ? wave * (n_sw[k] + 1) : 0;
       if constexpr (PM == 2) {
-        m_sw[k] = src + mine;
+        m_sw[k] = lsrc[k] + mine;
       } else {
         // the slot holds the sweep's whole list (a tile's reach list is no longer)
-        for (int i = tid; i < lists * (n + 1); i += T) slot[i] = src[i];
+        if (tid < lcnt[k]) slot[tid] = v4[k];
+        for (int i = tid + T; i < lcnt[k]; i += T) slot[i] = lsrc[k][i];
         m_sw[k] = slot + mine;
-        slot += grp[k] ? NW * (sw.ngrp[gi] + 1) : sw.nstep + 1;
+        slot += grp[k] ? NW * (sws[k]->ngrp[gi] + 1) : sws[k]->nstep + 1;
       }
     }
     kb_end = reinterpret_cast<int*>(PM == 2 ? mlds : slot);
   }
+  double gvl[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) gvl[c] = ge0[c] + tid < ge1[c] ? gu[gfr[c]] : 0.0;
   // sweep k, then every wave waits for it; a sweep on one wave runs on wave
   // blk mod NW, so that the sweeping waves of the work-groups that share a CU
   // are spread over its SIMDs
@@ -1084,13 +1149,12 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
     csync();
   };
   int* gt_end = kb_end + d.kb_n;
-  for (int i = tid; i < d.kb_n; i += T) kb_end[i] = d.kb_end[i];
-  for (int i = tid; i < d.gt_nb; i += T) gt_end[i] = d.gt_end[i];
+  if (tid < d.kb_n) kb_end[tid] = vk;
+  if (tid < d.gt_nb) gt_end[tid] = vg;
+  for (int i = tid + T; i < d.kb_n; i += T) kb_end[i] = d.kb_end[i];
+  for (int i = tid + T; i < d.gt_nb; i += T) gt_end[i] = d.gt_end[i];
   csync();
   tick(d, 0);
-  const int jc0 = col0 + blk * W;
-  const double* gu = d.dst + d.d_gu;
-  const double* r4 = r ? r + d.nu + d.nx + d.m : nullptr;
   for (int i = tid; i < (nw + 1) * W; i += T) P[i] = 0.0;
   csync();
   for (int c = 0; c < W; ++c) {
@@ -1100,17 +1164,23 @@ __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int co
       if (tid == 0) P[nw * W + c] = 1.0;
     if (mode == MODE_RECOVER) {
       for (int v = tid; v < nu; v += T) P[v * W + c] = vin[v];
-      for (int i = tid; i < nx; i += T) {
-        double acc = r4[d.perm[i]];
+      // eight rows' dependent reads in flight at a time
+      indexed_loop(d.perm, nx, [&](int i, int pi) {
+        double acc = r4[pi];
         for (int e = d.gu_ptr[i]; e < d.gu_ptr[i + 1]; ++e) acc += gu[e] * vin[d.gu_col[e]];
         P[(nu + i) * W + c] = -acc;
-      }
+      });
     } else if (j < nu) {
       if (tid == 0) P[j * W + c] = 1.0;
-      for (int e = d.gucsc_ptr[j] + tid; e < d.gucsc_ptr[j + 1]; e += T)
+      if (ge0[c] + tid < ge1[c]) P[(nu + grw[c]) * W + c] = -gvl[c];
+      for (int e = ge0[c] + tid + T; e < ge1[c]; e += T)
         P[(nu + d.gucsc_row[e]) * W + c] = -gu[d.gucsc_from[e]];
     } else {
-      for (int i = tid; i < nx; i += T) P[(nu + i) * W + c] = -r4[d.perm[i]];
+      // the right-hand-side column, -r4 in the internal order (this tile's
+      // fill is on the launch's critical path: eight rows' reads in flight)
+      gather_loop(
+          d.perm, nx, [&](int, int pi) { return r4[pi]; },
+          [&](int i, int, double v) { P[(nu + i) * W + c] = -v; });
     }
   }
   csync();
@@ -1250,7 +1320,9 @@ __global__ void __launch_bounds__(kCondThreads) k_gx_solve(DevNet d, const doubl
   if (TRANS)
     indexed_loop(d.hpos + nu, nx, [&](int i, int hp) { P[hp * W] = b[d.perm[i]]; });
   else
-    for (int i = tid; i < nx; i += T) P[(nu + i) * W] = b[d.perm[i]];
+    gather_loop(
+        d.perm, nx, [&](int, int pi) { return b[pi]; },
+        [&](int i, int, double v) { P[(nu + i) * W] = v; });
   panel_sync<LDS>();
   sweep<W, LDS>(s1.nstep, d.lblk, m1, pb);
   sweep<W, LDS>(s2.nstep, d.lblk, m2, pb);
@@ -1261,10 +1333,10 @@ __global__ void __launch_bounds__(kCondThreads) k_gx_solve(DevNet d, const doubl
       x[k] = (accumulate ? x[k] : 0.0) + scale * P[hp * W];
     });
   else
-    for (int i = tid; i < nx; i += T) {
-      const int k = d.perm[i];
-      x[k] = (accumulate ? x[k] : 0.0) + scale * P[(nu + i) * W];
-    }
+    gather_loop(
+        d.perm, nx,
+        [&](int i, int k) { return (accumulate ? x[k] : 0.0) + scale * P[(nu + i) * W]; },
+        [&](int, int k, double v) { x[k] = v; });
 }
 
 // Recovery from the stored columns: thread i (internal x index) of chunk ch
