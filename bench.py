@@ -589,6 +589,8 @@ def single_instance(api, torch, net, steps, warmup, width=0, lds=1, key="syn1354
                    "step": "eval + refactor + condense (nu+1 columns) + symmetrize + "
                            "Cholesky + solve + recovery",
                    "panel_width": G.info["panel_width"], "lds_panel": G.info["lds_panel"],
+                   "cond_waves": G.info["cond_waves"],
+                   "ordering": "minimum degree with a level term (2 degree + level)",
                    "levels": G.info["levels_lower"], "nnz_lu": G.info["nnz_lu"],
                    "delta_w": delta},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
