@@ -860,8 +860,8 @@ __device__ __forceinline__ void tick(const DevNet& d, int k) {
   if (d.trace && blockIdx.x == 0 && threadIdx.x == 0) d.trace[k] = wall_clock64();
 }
 
-// Row-blocked record stream (one wave): lane t owns stream position
-// kKRowBlock * b + t of every block b; its records, kStreamBatch per batch
+// Row-blocked record stream, blocks [b_lo, b_hi) on one wave: lane t owns
+// stream position kKRowBlock * b + t of every block b; its records, kStreamBatch per batch
 // (values, then panel byte offsets from pb; each 16-byte chunk contiguous
 // over the wave), follow one another, block b covering records
 // [end[b-1], end[b]). Per record acc += value * panel[offset]; at the end of
@@ -1010,7 +1010,7 @@ __device__ __forceinline__ void gather_loop(const int* idx, int n, L&& load, S&&
 }
 
 // Columns [col0 + blk * W, ...) of the condensed matrix (Section 3.3), one
-// wave per work-group (blk = the work-group's tile):
+// work-group of NW waves per tile (blk = the work-group's tile):
 //   Z   = -G_x^{-1} G_u V          (L then U sweep; V = identity columns)
 //   H   =  K [V ; Z]               (one sparse product over all nu + nx rows)
 //   Psi =  G_x^{-T} H_x            (U^T then L^T sweep)
@@ -1025,7 +1025,8 @@ __device__ __forceinline__ void gather_loop(const int* idx, int n, L&& load, S&&
 // PM (panel mode): 0 panels in global memory, 1 panels and sweep metadata in
 // LDS, 2 panels in LDS with the sweep metadata read where it is (global
 // memory, the same for every work-group), for networks whose panel alone
-// fills the LDS.
+// fills the LDS. NW waves (several only for W = 1 with LDS panels) split the
+// record streams and, per sweep, run it together or leave it to one wave.
 template <int W, int PM, int NW, int mode>
 __device__ __forceinline__ void k_condense_body(const DevNet& d, int blk, int col0, int col_end,
                                                 const double* r, const double* vin, double* K,
