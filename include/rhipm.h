@@ -345,7 +345,9 @@ enum { RH_PHASE_EVAL = 0, RH_PHASE_REFACTOR, RH_PHASE_CONDENSE, RH_PHASE_SYMMETR
 rh_status rh_profile_enable(rh_net* net, int32_t on);
 rh_status rh_profile_read(rh_net* net, double* ms, int64_t* calls);
 /* In-kernel phase timestamps (device wall clock, 100 MHz) of the first
- * work-group of the last condensation launched while profiling was on:
+ * work-group of the last condensation launched while profiling was on (for
+ * rh_condense_reduced_hessian, the right-hand-side column's tile, which runs
+ * first):
  * [0] start, [1] panel filled, [2] after L, [3] after U (Z), [4] after the
  * Hessian product, [5] after U^T, [6] after L^T (Psi), [7] columns written,
  * [8] Z column stored (start of the product), [9] K record stream done

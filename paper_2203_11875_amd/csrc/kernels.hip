@@ -1282,7 +1282,11 @@ __global__ void __launch_bounds__(64 * NW) k_condense(DevNet d, int col0, int co
                                                           const double* r, const double* vin,
                                                           double* K, long ldk, double* rhs,
                                                           double* p_out) {
-  k_condense_body<W, PM, NW, mode>(d, blockIdx.x, col0, col_end, r, vin, K, ldk, rhs, p_out);
+  // the last tile (the right-hand-side column's, whose full L sweep and dense
+  // fill make it the longest) goes to the first work-group dispatched, on a
+  // CU that no third work-group shares
+  const int blk = blockIdx.x == 0 ? gridDim.x - 1 : blockIdx.x - 1;
+  k_condense_body<W, PM, NW, mode>(d, blk, col0, col_end, r, vin, K, ldk, rhs, p_out);
 }
 
 // x = G_x^{-1} b (TRANS = 0: L then U sweep) or x = G_x^{-T} b (TRANS = 1:
