@@ -753,13 +753,18 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
     rh::CondClass& c = sh.cls[ci];
     c.tile0 = int(tiles.size());
     int common_nw = -1;
+    // every member's last tile (the right-hand-side column's, the longest:
+    // full L sweep, dense fill) first, then the others
+    for (int i = 0; i < count; ++i)
+      if (cls_of[i] == int(ci))
+        tiles.push_back(int2{i, (nets[i]->d.nu + 1 + c.width - 1) / c.width - 1});
     for (int i = 0; i < count; ++i) {
       if (cls_of[i] != int(ci)) continue;
       const rh::DevNet& d = nets[i]->d;
       c.meta_global = c.meta_global || (c.lds && d.meta_global != 0);
       common_nw = common_nw < 0 || common_nw == d.cond_nw ? d.cond_nw : 0;
       const int ntile = (d.nu + 1 + c.width - 1) / c.width;
-      for (int t = 0; t < ntile; ++t) tiles.push_back(int2{i, t});
+      for (int t = 0; t + 1 < ntile; ++t) tiles.push_back(int2{i, t});
     }
     c.ntiles = int(tiles.size()) - c.tile0;
     const bool all_nw = c.lds && c.width == 1 && common_nw > 1;
