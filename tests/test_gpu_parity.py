@@ -228,10 +228,10 @@ def test_set_loads_changes_residual():
     assert _rel(_np(g), go) <= 1e-12 and _rel(_np(h), ho) <= 1e-12
 
 
-@pytest.mark.parametrize("name,width,nw", [("syn9", 1, 1), ("syn1354", 1, 1), ("syn1354", 1, 4),
-                                           ("syn1354", 1, 8), ("syn1354", 1, 2), ("syn118", 2, 1),
-                                           ("syn1354", 3, 1)])
-@pytest.mark.parametrize("grp", [0, 16])
+@pytest.mark.parametrize("name,width,nw,grp", [
+    ("syn9", 1, 1, 0), ("syn1354", 1, 1, 0), ("syn1354", 1, 2, 0), ("syn1354", 1, 4, 0),
+    ("syn1354", 1, 4, 16), ("syn1354", 1, 8, 0), ("syn1354", 1, 8, 16), ("syn118", 2, 1, 0),
+    ("syn1354", 3, 1, 0)])
 def test_solve_after_condensation_without_rhs(name, width, nw, grp):
     """Recovery by the single-column pass (condensation called without r),
     with the right-hand side condensed separately on the same factors; the
@@ -239,8 +239,6 @@ def test_solve_after_condensation_without_rhs(name, width, nw, grp):
     handle's waves per work-group."""
     net = NETS[name]()
     M = Model(net)
-    if grp and nw == 1:
-        pytest.skip("sweeps on several waves need several waves")
     G = _net_api().Net(net, panel_width=width, cond_waves=nw, sweep_grouping=grp)
     assert G.info["panel_width"] == width and G.info["cond_waves"] == nw
     x, u, lam, y, sx, su, ss = random_point(M, 3, lam_scale=1.0, sig_range=(10.0, 1e4))
