@@ -180,10 +180,11 @@ rh_status rh_symbolic_gx_pattern(const rh_symbolic* sym, int32_t* rowptr, int32_
  * G_x^T z = b (transpose = 1) with the level-ordered sweeps. Host arrays. */
 rh_status rh_symbolic_host_solve(const rh_symbolic* sym, const double* gx_values,
                                  const double* b, double* z, int32_t transpose);
-/* 0 if every dependency of every sweep lies in an earlier level set and the
+/* 0 if every dependency of every sweep lies in an earlier level set, the
  * condensation's step schedule is consistent (each row written once, by
  * the last lane of its group, with exactly its entries, after the rows it
- * reads). */
+ * reads) and its step lists for work-groups of 4 and 8 waves hold every
+ * step once, in schedule order, each group's steps of one level. */
 rh_status rh_symbolic_check_levels(const rh_symbolic* sym);
 /* Host check of the condensation's device records for panel width `width`
  * (1, 2, 3, 4, 8): emulates the condensation kernel lane by lane on random

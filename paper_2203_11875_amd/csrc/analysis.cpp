@@ -1672,6 +1672,41 @@ rh_status check_levels(const Symbolic& s) {
       const bool work = sw->has_diag || sw->ptr[q + 1] > sw->ptr[q];
       if ((step_of[i] >= 0) != work) return RH_ERR_STATE;
     }
+    // the step lists of work-groups of several waves: NW lists of ngrp + 1
+    // entries each ending with the idle step; group g holds, wave by wave,
+    // the next steps of the schedule, all of one level (so none reads a row
+    // another writes), idle steps after them; every step exactly once
+    for (const int nwv : {kCondWaves, kCondWavesWide}) {
+      std::vector<int> e;
+      for (int st = 0; st < sw->ks_nstep; ++st)
+        e.insert(e.end(), {st, sw->ks_meta[size_t(kSweepMeta) * st + 2],
+                           sw->ks_meta[size_t(kSweepMeta) * st + 3], 0});
+      e.insert(e.end(), {sw->ks_nstep, 0, -1, 0});
+      std::vector<int> out;
+      const int G = group_for_waves(e.data(), e.size() / 4, nwv, out);
+      if (G != wave_groups(*sw, nwv) || out.size() != size_t(4) * nwv * (G + 1))
+        return RH_ERR_STATE;
+      auto at = [&](int w, int g) { return &out[4 * (size_t(w) * (G + 1) + g)]; };
+      int next = 0;
+      for (int g = 0; g <= G; ++g) {
+        int lev = -2;
+        bool idle_seen = false;
+        for (int w = 0; w < nwv; ++w) {
+          const int* m = at(w, g);
+          if (m[0] == sw->ks_nstep) {   // idle
+            if (m[2] != -1) return RH_ERR_STATE;
+            idle_seen = true;
+            continue;
+          }
+          if (g == G || idle_seen || m[0] != next) return RH_ERR_STATE;
+          if (lev != -2 && m[2] != lev) return RH_ERR_STATE;
+          lev = m[2];
+          ++next;
+        }
+        if (g < G && lev == -2) return RH_ERR_STATE;   // an empty group
+      }
+      if (next != sw->ks_nstep) return RH_ERR_STATE;
+    }
     for (int st = 0; st < sw->ks_nstep; ++st) {
       const int* m = &sw->ks_meta[size_t(kSweepMeta) * st];
       const int b0 = m[0], TL = m[1], S = 1 << m[2];

@@ -47,6 +47,9 @@ def test_dimensions_and_index_maps_match_oracle(net):
 
 @pytest.mark.parametrize("net", NETS, ids=lambda n: n.name)
 def test_levels_valid(net):
+    """Level sets, the sweep step schedule and the step lists of work-groups
+    of 4 and 8 waves (every step once, a group's steps of one level, in
+    schedule order) pass the host check (rh_symbolic_check_levels)."""
     S = _lib().Symbolic(net)
     assert S.check_levels() == 0
     assert S.info["levels_lower"] >= 1 and S.info["nnz_lu"] >= S.info["nnz_gx"]
