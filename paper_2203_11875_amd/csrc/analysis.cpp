@@ -952,7 +952,7 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
           int wa = s.line_w[4 * l + a], wb = s.line_w[4 * l + b];
           if (wa < 0 || wb < 0) continue;
           int e = find_pos(s.k_ptr, s.k_col, wa, wb);
-          hl[e].push_back(HL_STRIDE * l + hl_index(std::min(a, b), std::max(a, b)));
+          hl[e].push_back(hl_index(std::min(a, b), std::max(a, b)) * nl + l);
         }
     for (int j = 0; j < s.m; ++j)
       for (int p = s.a_ptr[j]; p < s.a_ptr[j + 1]; ++p)
@@ -1005,7 +1005,7 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
       for (int kk = 0; kk < 4; ++kk) {
         int w = s.line_w[4 * l + kk];
         if (w < 0) continue;
-        terms[dst_of_w(w)].push_back({LF_STRIDE * l + base + kk, 1.0});
+        terms[dst_of_w(w)].push_back({(base + kk) * nl + l, 1.0});
       }
     }
   };
@@ -1013,7 +1013,7 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
     for (auto& le : ends[bus]) {
       int l = le.first, e = le.second;
       int slot = isP ? (e == 0 ? LF_PF : LF_PT) : (e == 0 ? LF_QF : LF_QT);
-      terms[dst].push_back({LF_STRIDE * l + slot, 1.0});
+      terms[dst].push_back({slot * nl + l, 1.0});
     }
   };
   for (int i = 0; i < nb; ++i) {
@@ -1060,9 +1060,9 @@ rh_status analyze(const rh_network_desc& d, const rh_options* opts, Symbolic& s)
         int w = s.line_w[4 * l + kk];
         if (w < 0) continue;
         terms[s.d_a + find_pos(s.a_ptr, s.a_col, row, w)].push_back(
-            {LF_STRIDE * l + (e == 0 ? LF_DSF2 : LF_DST2) + kk, 1.0});
+            {((e == 0 ? LF_DSF2 : LF_DST2) + kk) * nl + l, 1.0});
       }
-      terms[s.d_h + row].push_back({LF_STRIDE * l + (e == 0 ? LF_SF2 : LF_ST2), 1.0});
+      terms[s.d_h + row].push_back({(e == 0 ? LF_SF2 : LF_ST2) * nl + l, 1.0});
     }
   }
   s.eg.ptr.assign(s.d_total + 1, 0);

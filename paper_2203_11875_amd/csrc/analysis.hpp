@@ -57,7 +57,9 @@ constexpr int kChunk = 2 * kSweepThreads;           // doubles per chunk
 constexpr int kStepDoubles = 7 * kChunk;
 constexpr int kBatchDoubles = 6 * kChunk;
 
-// Per-line record written by the line-evaluation kernel (doubles).
+// Per-line record written by the line-evaluation kernel: LF_STRIDE slots of
+// nl doubles each, slot k of line l at k nl + l (consecutive lines, i.e.
+// consecutive threads, write consecutive doubles).
 enum LineSlot : int {
   LF_PF = 0, LF_QF = 1, LF_PT = 2, LF_QT = 3,
   LF_DPF = 4, LF_DQF = 8, LF_DPT = 12, LF_DQT = 16,   // 4 partials each
@@ -65,7 +67,8 @@ enum LineSlot : int {
   LF_STRIDE = 32
 };
 // Local variable order of a line: theta_from, theta_to, Vm_from, Vm_to.
-// Symmetric 4x4 blocks are stored as 10 entries (upper triangle, row major).
+// Symmetric 4x4 blocks are stored as 10 entries (upper triangle, row major),
+// entry k of line l at k nl + l.
 constexpr int HL_STRIDE = 10;
 inline int hl_index(int a, int b) {   // a <= b
   static const int base[4] = {0, 4, 7, 9};

@@ -94,22 +94,24 @@ __device__ __forceinline__ void k_eval_lines_body(const DevNet& d, const double*
   line_fun(-bff, tr.b, tr.a, tr.vf, tr.vt, true, &Qf, gQf, HQf);
   line_fun(gff, tr.e, tr.q, tr.vf, tr.vt, false, &Pt, gPt, HPt);
   line_fun(-bff, tr.q, -tr.e, tr.vf, tr.vt, false, &Qt, gQt, HQt);
-  double* o = d.src + (size_t)LF_STRIDE * l;
-  o[LF_PF] = Pf;
-  o[LF_QF] = Qf;
-  o[LF_PT] = Pt;
-  o[LF_QT] = Qt;
+  // slot k of line l at k nl + l: the lanes' stores are contiguous
+  const size_t nl = d.nl;
+  double* o = d.src + l;
+  o[LF_PF * nl] = Pf;
+  o[LF_QF * nl] = Qf;
+  o[LF_PT * nl] = Pt;
+  o[LF_QT * nl] = Qt;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    o[LF_DPF + k] = gPf[k];
-    o[LF_DQF + k] = gQf[k];
-    o[LF_DPT + k] = gPt[k];
-    o[LF_DQT + k] = gQt[k];
-    o[LF_DSF2 + k] = 2.0 * (Pf * gPf[k] + Qf * gQf[k]);
-    o[LF_DST2 + k] = 2.0 * (Pt * gPt[k] + Qt * gQt[k]);
+    o[(LF_DPF + k) * nl] = gPf[k];
+    o[(LF_DQF + k) * nl] = gQf[k];
+    o[(LF_DPT + k) * nl] = gPt[k];
+    o[(LF_DQT + k) * nl] = gQt[k];
+    o[(LF_DSF2 + k) * nl] = 2.0 * (Pf * gPf[k] + Qf * gQf[k]);
+    o[(LF_DST2 + k) * nl] = 2.0 * (Pt * gPt[k] + Qt * gQt[k]);
   }
-  o[LF_SF2] = Pf * Pf + Qf * Qf;
-  o[LF_ST2] = Pt * Pt + Qt * Qt;
+  o[LF_SF2 * nl] = Pf * Pf + Qf * Qf;
+  o[LF_ST2 * nl] = Pt * Pt + Qt * Qt;
   if (!hessian) return;
   const int* ws = d.line_wsrc + 8 * l;
   double wPf = ws[0] >= 0 ? lam[ws[0]] : 0.0;
@@ -130,7 +132,7 @@ __device__ __forceinline__ void k_eval_lines_body(const DevNet& d, const double*
   const double yst = ws[7] >= 0 ? y[ws[7]] : 0.0;
   const double cPf = wPf + 2.0 * ysf * Pf, cQf = wQf + 2.0 * ysf * Qf;
   const double cPt = wPt + 2.0 * yst * Pt, cQt = wQt + 2.0 * yst * Qt;
-  double* h = d.hl + (size_t)HL_STRIDE * l;
+  double* h = d.hl + l;   // entry idx at idx nl + l
   int idx = 0;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -139,7 +141,7 @@ __device__ __forceinline__ void k_eval_lines_body(const DevNet& d, const double*
       double v = cPf * HPf[idx] + cQf * HQf[idx] + cPt * HPt[idx] + cQt * HQt[idx];
       v += 2.0 * ysf * (gPf[a] * gPf[b] + gQf[a] * gQf[b]);
       v += 2.0 * yst * (gPt[a] * gPt[b] + gQt[a] * gQt[b]);
-      h[idx] = v;
+      h[idx * nl] = v;
     }
 }
 __global__ void __launch_bounds__(kBlock) k_eval_lines(DevNet d, const double* x, const double* u, const double* lam, const double* y, int hessian) {
