@@ -788,15 +788,30 @@ __device__ __forceinline__ void sweep_step(const StepFetch& f, char* pb) {
   double xr[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) xr[c] = panel_ld<LDS>(pb, row + 8 * c);
-  if (f.ls > 0) {   // one branch for the steps of one lane per row
+  // stages nested: a step leaves the tree with one branch after its last
+  // stage (each column's sums in the same order as stage by stage)
+  if (f.ls > 0) {
 #pragma unroll
-    for (int c = 0; c < W; ++c) {
-      acc[c] = add_shr<1>(acc[c]);
-      if (f.ls >= 2) acc[c] = add_shr<2>(acc[c]);
-      if (f.ls >= 3) acc[c] = add_shr<4>(acc[c]);
-      if (f.ls >= 4) acc[c] = add_shr<8>(acc[c]);
-      if (f.ls >= 5) acc[c] = add_bcast<0x142, 0xA>(acc[c]);
-      if (f.ls >= 6) acc[c] = add_bcast<0x143, 0xC>(acc[c]);
+    for (int c = 0; c < W; ++c) acc[c] = add_shr<1>(acc[c]);
+    if (f.ls > 1) {
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] = add_shr<2>(acc[c]);
+      if (f.ls > 2) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[c] = add_shr<4>(acc[c]);
+        if (f.ls > 3) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) acc[c] = add_shr<8>(acc[c]);
+          if (f.ls > 4) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) acc[c] = add_bcast<0x142, 0xA>(acc[c]);
+            if (f.ls > 5) {
+#pragma unroll
+              for (int c = 0; c < W; ++c) acc[c] = add_bcast<0x143, 0xC>(acc[c]);
+            }
+          }
+        }
+      }
     }
   }
   // the row's old value read (lgkmcnt(0)) before the writer branch, on every
