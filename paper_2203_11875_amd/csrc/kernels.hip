@@ -952,9 +952,19 @@ __device__ __forceinline__ void row_stream(const double* str, const int* end_lds
       for (int r = 0; r < kStreamBatch; ++r)
 #pragma unroll
         for (int c = 0; c < W; ++c) x[r][c] = panel_ld<LDS>(pb, bo[jj][r / 4][r % 4] + 8 * c);
+      const int p0 = (first + cb) * kStreamBatch;
+      if (p0 >= rec_start && p0 + kStreamBatch < e) {
+        // no block ends inside the batch and all its records are this
+        // range's: the same sums without a test per record
+#pragma unroll
+        for (int r = 0; r < kStreamBatch; ++r)
+#pragma unroll
+          for (int c = 0; c < W; ++c) acc[c] = fma(bv[jj][r / 2][r % 2], x[r][c], acc[c]);
+        continue;
+      }
 #pragma unroll
       for (int r = 0; r < kStreamBatch; ++r) {
-        const int p = (first + cb) * kStreamBatch + r;
+        const int p = p0 + r;
         const double v = p >= rec_start ? bv[jj][r / 2][r % 2] : 0.0;
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[c] = fma(v, x[r][c], acc[c]);
