@@ -610,8 +610,9 @@ def single_instance(api, torch, net, steps, warmup, width=0, lds=1, key="syn1354
 
 
 def graph_replay(api, torch, G, point, delta, reps=50, warmup=5):
-    """The same step (condensation with the right-hand side, Cholesky, solve,
-    recovery) captured once in a HIP graph, as a one-member batch (the
+    """The same step (evaluation, refactorisation, condensation with the
+    right-hand side, Cholesky, solve, recovery) captured once in a HIP graph,
+    as a one-member batch (the
     batched kernels run the single-instance bodies: same results bit for
     bit), and replayed: `warmup` replays, then `reps` replays each timed with
     HIP events on the batch's stream. Milliseconds p10 / p50 / p90 and the
@@ -637,8 +638,8 @@ def graph_replay(api, torch, G, point, delta, reps=50, warmup=5):
     p50 = float(np.median(per))
     return {"replays": reps, "ms_p10": float(np.percentile(per, 10)), "ms_p50": p50,
             "ms_p90": float(np.percentile(per, 90)), "condensations_per_s_p50": 1e3 / p50,
-            "step": "condensation (nu+1 columns) + symmetrize + Cholesky + solve + recovery "
-                    "as one captured graph (a one-member batch)"}
+            "step": "eval + refactor + condense (nu+1 columns) + symmetrize + Cholesky + solve "
+                    "+ recovery as one captured graph (a one-member batch)"}
 
 
 def large_block(api, torch, steps, warmup):
