@@ -303,9 +303,9 @@ class Net:
         rr = self._t(r, nu + 2 * nx + 2 * m)
         rhs = self._t(rhs, nu)
         p = t.empty(nu + 2 * nx + 2 * m, dtype=t.float64, device=self.device)
-        st = t.zeros(2, dtype=t.int32, device=self.device)
+        # the status comes back as the return code (no device copy wanted)
         code = lib().rh_solve_condensed_kkt(self.h, _ptr(K), nu, float(delta_w), _ptr(rhs),
-                                            _ptr(rr), _ptr(p), _ptr(st))
+                                            _ptr(rr), _ptr(p), None)
         if code < 0:
             _check(code, "rh_solve_condensed_kkt")
         return p, code
