@@ -65,7 +65,8 @@ __device__ __forceinline__ double ld0(const double* p, size_t i, bool ok, const 
 }
 
 // One instance: A (lower triangle, column-major, leading dimension ld) is
-// factored in place; b holds the right-hand side and receives y = L^{-1} b
+// factored in place; b_in holds the right-hand side (read by launch 0 only,
+// which writes every row of it, updated, to b); b receives y = L^{-1} b_in
 // and then the backward substitution's partial sums; x receives the
 // solution. dl: nbk 32 x 32 tiles; X: the inverse super-blocks.
 struct Inst {
@@ -73,6 +74,7 @@ struct Inst {
   long ld;
   int n;
   double delta;
+  const double* b_in;
   double* b;
   double* x;
   double* dl;
@@ -250,6 +252,12 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
   double* Xs = c.X + (size_t)sg * G.S * G.S;
   const bool tr = trace != nullptr && role == ROLE_DIAG && tid == 0 && k < kTraceLaunches;
   if (tr) trace[8 * k] = wall_clock64();
+  // launch 0 skips the status test and its diagonal group, the only writer
+  // of the status in a launch, clears it first
+  if (k == 0 && role == ROLE_DIAG && tid == 0) {
+    c.status[0] = 0;
+    c.status[1] = 0;
+  }
   const int bsz = min(CB, n - k0);
   const int bi = k + idx;   // ROLE_ROWS
   // own tile: (0, 0) element, leading dimension, valid rows; and its rows of
@@ -275,7 +283,7 @@ __device__ __forceinline__ void chol_panel(const Inst& c, const Geo& G, int k, i
   double bval = 0.0;
   if (role != ROLE_IDENT && tid < CB) {
     const int row = (role == ROLE_DIAG ? k0 : bi * CB) + tid;
-    if (row < n) bval = c.b[row];
+    if (row < n) bval = (k == 0 ? c.b_in : c.b)[row];
   }
   // the factor tile of launch k - 1 (stored to A by this launch's diagonal
   // group), requested now so that its latency is not at the tail
@@ -498,7 +506,7 @@ __device__ __forceinline__ void chol_ident_trailing(const Inst& c, const Geo& G,
 // Work-group bid of launch k: [diag | rows | identity panels | identity
 // trailing | trailing regions | delta].
 __device__ __forceinline__ void chol_step(const Inst& c, int k, int bid, long long* trace) {
-  if (c.status[0] != 0) return;
+  if (k > 0 && c.status[0] != 0) return;
   const Geo G = geo(c.n);
   if (k >= G.nbk) return;
   const int sg = k / G.sb, kap = k - sg * G.sb, sbn = min(G.sb, G.nbk - sg * G.sb);
@@ -639,13 +647,9 @@ __global__ void __launch_bounds__(kThreads) k_chol_back(Inst c, int t) {
 __global__ void k_chol_clear(int* status) {
   if (threadIdx.x < 2) status[threadIdx.x] = 0;
 }
-__global__ void k_chol_copy(double* dst, const double* src, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
 
 __device__ __forceinline__ Inst batch_inst(const BatchArg& q) {
-  return Inst{q.K, q.ldk, q.nu, q.delta, q.bwork, q.p, q.cinv, q.lrow, q.status};
+  return Inst{q.K, q.ldk, q.nu, q.delta, q.bwork, q.bwork, q.p, q.cinv, q.lrow, q.status};
 }
 __global__ void __launch_bounds__(kThreads) k_chol_b(const BatchArg* __restrict__ a, int k) {
   const Inst c = batch_inst(cst(a, blockIdx.z));
@@ -665,12 +669,14 @@ int chol_launches(int n) {
   return (n + CB - 1) / CB + chol_back_steps(n);
 }
 
-hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b, double* x,
-                                 double* dl, double* X, int* status, hipStream_t st,
-                                 long long* trace) {
-  hipLaunchKernelGGL(k_chol_clear, dim3(1), dim3(64), 0, st, status);
-  if (n <= 0) return hipGetLastError();
-  const Inst c{K, ldk, n, delta, b, x, dl, X, status};
+hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, const double* b_in,
+                                 double* b, double* x, double* dl, double* X, int* status,
+                                 hipStream_t st, long long* trace) {
+  if (n <= 0) {
+    hipLaunchKernelGGL(k_chol_clear, dim3(1), dim3(64), 0, st, status);
+    return hipGetLastError();
+  }
+  const Inst c{K, ldk, n, delta, b_in, b, x, dl, X, status};
   const int nbk = (n + CB - 1) / CB;
   for (int k = 0; k < nbk; ++k)
     hipLaunchKernelGGL(k_chol, dim3(chol_step_groups(n, k)), dim3(kThreads), 0, st, c, k, trace);
@@ -749,9 +755,7 @@ hipError_t launch_cholesky_solve_noalloc(double* K, long ldk, int n, double delt
   double* bw = base;
   double* dl = bw + kNoallocMaxOrder;
   double* X = dl + chol_inv_doubles(kNoallocMaxOrder);
-  if (n > 0) hipLaunchKernelGGL(k_chol_copy, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                                st, bw, b, n);
-  return launch_cholesky_solve(K, ldk, n, delta, bw, x, dl, X, status, st, nullptr);
+  return launch_cholesky_solve(K, ldk, n, delta, b, bw, x, dl, X, status, st, nullptr);
 }
 
 }  // namespace rh

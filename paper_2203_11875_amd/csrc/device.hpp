@@ -177,8 +177,9 @@ hipError_t launch_batch_status(const DevNet* nets, int count, int* out, hipStrea
 
 hipError_t launch_eval(const DevNet& d, const double* x, const double* u, const double* lam,
                        const double* y, bool hessian, hipStream_t st);
+// sig_s_keep (optional): receives a copy of sig_s.
 hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double* sig_u,
-                             const double* sig_s, hipStream_t st);
+                             const double* sig_s, double* sig_s_keep, hipStream_t st);
 hipError_t launch_refactor(const DevNet& d, hipStream_t st);
 hipError_t launch_rtilde(const DevNet& d, const double* r, const double* sig_s, hipStream_t st);
 // mode 0: identity columns [col0, col0 + ncols) (col == nu: the right-hand-side column)
@@ -199,17 +200,18 @@ hipError_t launch_finish_step(const DevNet& d, const double* r, const double* si
                               hipStream_t st);
 hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
 // Cholesky of the lower triangle of K + delta I in place (K holds L on
-// return), the forward substitution L y = b folded into the factorisation
-// (y over b: b is destroyed) and the backward substitution L^T x = y into x.
-// status[0..1] (device): 0, or 1 and the first column whose pivot is not
-// positive. Workspaces: dl (chol_inv_doubles(n)), X (chol_lrow_doubles(n):
+// return), the forward substitution L y = b_in folded into the factorisation
+// (b_in is read by the first launch only and may be b; y is written to b,
+// which then also holds partial sums) and the backward substitution
+// L^T x = y into x. status[0..1] (device, set by the first launch): 0, or 1
+// and the first column whose pivot is not positive. Workspaces: dl (chol_inv_doubles(n)), X (chol_lrow_doubles(n):
 // the inverses of the diagonal super-blocks of L^T). trace (optional,
 // device int64[192]): wall-clock stamps of the diagonal work-group of the
 // first 24 factorisation launches (8 k + 0: start, + 1: panel k - 1 applied,
 // + 2: slice factored, + 3: stores issued).
-hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, double* b, double* x,
-                                 double* dl, double* X, int* status, hipStream_t st,
-                                 long long* trace = nullptr);
+hipError_t launch_cholesky_solve(double* K, long ldk, int n, double delta, const double* b_in,
+                                 double* b, double* x, double* dl, double* X, int* status,
+                                 hipStream_t st, long long* trace = nullptr);
 // The same for every instance of a batch (orders[i] = order of instance i;
 // args[i]: K, ldk, delta, bwork (b), p (x), cinv (dl), lrow (X), status).
 hipError_t launch_batch_cholesky(const BatchArg* args, const std::vector<int>& orders,

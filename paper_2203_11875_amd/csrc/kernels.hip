@@ -180,7 +180,13 @@ __device__ __forceinline__ void k_assemble_k_body(const DevNet& d, const double*
   }
   d.kstr[d.kdst[e]] = acc;
 }
-__global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* sig_x, const double* sig_u, const double* sig_s) {
+// sig_s_keep (optional): receives a copy of sig_s (m entries) for the
+// recovery after the solve.
+__global__ void __launch_bounds__(kBlock) k_assemble_k(DevNet d, const double* sig_x, const double* sig_u, const double* sig_s,
+                                                       double* sig_s_keep) {
+  if (sig_s_keep)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += gridDim.x * blockDim.x)
+      sig_s_keep[i] = sig_s[i];
   k_assemble_k_body(d, sig_x, sig_u, sig_s);
 }
 
@@ -1779,9 +1785,10 @@ hipError_t launch_eval(const DevNet& d, const double* x, const double* u, const 
 }
 
 hipError_t launch_assemble_k(const DevNet& d, const double* sig_x, const double* sig_u,
-                             const double* sig_s, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble_k, dim3(cdiv(d.nnz_k, kBlock)), dim3(kBlock), 0, st, d, sig_x,
-                     sig_u, sig_s);
+                             const double* sig_s, double* sig_s_keep, hipStream_t st) {
+  const int grid = cdiv(d.nnz_k, kBlock);
+  hipLaunchKernelGGL(k_assemble_k, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, st, d, sig_x,
+                     sig_u, sig_s, sig_s_keep);
   return hipGetLastError();
 }
 

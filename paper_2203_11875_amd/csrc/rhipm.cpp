@@ -1016,12 +1016,12 @@ rh_status condense_evaluated(rh_net* n, const double* sig_x, const double* sig_u
   const auto& d = n->d;
   hipStream_t st = n->stream;
   n->condensed = false;
-  RH_HIP(hipMemcpyAsync(n->sig_s, sig_s, sizeof(double) * d.m, hipMemcpyDeviceToDevice, st));
-  // K assembly and rt on the side stream, beside the refactorisation; the
-  // condensation waits for both
+  // K assembly (which also keeps a copy of Sigma_s for the recovery) and rt
+  // on the side stream, beside the refactorisation; the condensation and
+  // everything after it wait for both
   RH_HIP(hipEventRecord(n->ev_fork, st));
   RH_HIP(hipStreamWaitEvent(n->side, n->ev_fork, 0));
-  RH_HIP(rh::launch_assemble_k(d, sig_x, sig_u, sig_s, n->side));
+  RH_HIP(rh::launch_assemble_k(d, sig_x, sig_u, sig_s, n->sig_s, n->side));
   RH_HIP(rh::launch_rtilde(d, r, sig_s, n->side));   // r == NULL: rt = 0
   RH_HIP(hipEventRecord(n->ev_join, n->side));
   {
@@ -1093,11 +1093,11 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
   if (!n->condensed) return RH_ERR_STATE;
   const auto& d = n->d;
   hipStream_t st = n->stream;
-  RH_HIP(hipMemcpyAsync(n->bwork, rhs, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, st));
   {
-    // L y = b is solved into p[0:nu], then L^T p_u = y in place
+    // L y = rhs into the work copy (rhs itself is left as it is), then
+    // L^T p_u = y into p[0:nu]
     PhaseScope ps(n, RH_PHASE_CHOLESKY);
-    RH_HIP(rh::launch_cholesky_solve(K, long(ldk), d.nu, delta_w, n->bwork, p, n->cinv, n->lrow,
+    RH_HIP(rh::launch_cholesky_solve(K, long(ldk), d.nu, delta_w, rhs, n->bwork, p, n->cinv, n->lrow,
                                      n->status, st, n->profiling ? n->trace + 256 : nullptr));
   }
   {
