@@ -186,6 +186,41 @@ def test_cholesky_reports_indefinite():
     assert code == 1   # RH_NOT_POSDEF
 
 
+def test_failed_solve_leaves_no_trace():
+    """The factorisation's first launch clears the status word and reads the
+    right-hand side: after a solve that meets a non-positive pivot, a solve
+    with an inertia shift on the same handle succeeds, leaves the right-hand
+    side as it was and equals the same solve on a fresh handle bit for bit."""
+    net = synthnet.case118(0)
+    M = Model(net)
+    api = _net_api()
+    for seed in range(6):
+        x, u, lam, y, sx, su, ss = random_point(M, seed, lam_scale=400.0)
+        Kc = R.symmetrize(R.condensed_matrix(R.kkt_blocks(M, x, u, lam, y, sx, su, ss)))
+        if OC.try_cholesky(Kc) is None:
+            break
+    else:
+        pytest.skip("no indefinite draw")
+    delta = 1.5 * max(0.0, -np.linalg.eigvalsh(Kc).min()) + 1e-3
+    r = residual_vector(M, 0)
+    args = list(map(_t, (x, u, lam, y, sx, su, ss)))
+    G = api.Net(net)
+    K, rhs = G.condense_reduced_hessian(*args, r=_t(r))
+    K0, rhs0 = K.clone(), rhs.clone()
+    _, code = G.solve_condensed_kkt(K, 0.0, rhs, _t(r))
+    assert code == 1   # RH_NOT_POSDEF
+    K.copy_(K0)
+    p, code = G.solve_condensed_kkt(K, delta, rhs, _t(r))
+    assert code == 0
+    assert torch.equal(rhs, rhs0)
+    H = api.Net(net)
+    K2, rhs2 = H.condense_reduced_hessian(*args, r=_t(r))
+    p2, code2 = H.solve_condensed_kkt(K2, delta, rhs2, _t(r))
+    torch.cuda.synchronize()
+    assert code2 == 0
+    assert torch.equal(p, p2)
+
+
 @pytest.mark.parametrize("name", ["syn118", "syn1354"])
 def test_bitwise_repeatable_and_width_independent(name):
     net = NETS[name]()
