@@ -196,8 +196,9 @@ hipError_t launch_gx_solve(const DevNet& d, int width, bool lds, bool transpose,
 // Recovery from the stored columns of the last condensation (which included
 // the right-hand-side column): p_x = Z p_u + d, p_lambda = -(Psi p_u + Psi_rhs).
 hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st);
+// hstat (optional, pinned host int[5]): receives the status words.
 hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,
-                              hipStream_t st);
+                              int* hstat, hipStream_t st);
 hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
 // Cholesky of the lower triangle of K + delta I in place (K holds L on
 // return), the forward substitution L y = b_in folded into the factorisation

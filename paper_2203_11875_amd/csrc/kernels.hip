@@ -1438,7 +1438,11 @@ __device__ __forceinline__ void k_finish_step_body(const DevNet& d, const double
   p[d.nu + d.nx + j] = ps;
   p[d.nu + 2 * d.nx + d.m + j] = -r3[j] - sig_s[j] * ps;
 }
-__global__ void __launch_bounds__(kBlock) k_finish_step(DevNet d, const double* r, const double* sig_s, double* p) {
+// hstat (optional, pinned host memory): receives the five status words,
+// final once the solve's earlier kernels have run (this is its last).
+__global__ void __launch_bounds__(kBlock) k_finish_step(DevNet d, const double* r, const double* sig_s, double* p,
+                                                        int* hstat) {
+  if (hstat && blockIdx.x == 0 && threadIdx.x < 5) hstat[threadIdx.x] = d.status[threadIdx.x];
   k_finish_step_body(d, r, sig_s, p);
 }
 
@@ -1878,8 +1882,10 @@ hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st) {
 }
 
 hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_finish_step, dim3(cdiv(d.m, kBlock)), dim3(kBlock), 0, st, d, r, sig_s, p);
+                              int* hstat, hipStream_t st) {
+  const int grid = cdiv(d.m, kBlock);
+  hipLaunchKernelGGL(k_finish_step, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, st, d, r, sig_s, p,
+                     hstat);
   return hipGetLastError();
 }
 

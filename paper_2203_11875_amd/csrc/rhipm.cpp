@@ -51,6 +51,7 @@ struct rh_net {
   double* cinv = nullptr;    // 32 x 32 diagonal blocks of the Cholesky factor: inverses, then factors
   double* lrow = nullptr;    // the Cholesky factor by row blocks (backward substitution)
   int* status = nullptr;
+  int* hstatus = nullptr;    // pinned host copy of the status words (the solve's last kernel writes it)
   long long* trace = nullptr;
   size_t panel_cap = 0;
   // objective scale (rh_set_objective_scale): unscaled cost data
@@ -465,6 +466,7 @@ rh_status build_device(rh_net* n, const rh_network_desc& desc, const rh_options*
   RH_TRY(alloc(n, rh::chol_inv_doubles(s.nu), &n->cinv));
   RH_TRY(alloc(n, rh::chol_lrow_doubles(s.nu), &n->lrow));
   RH_TRY(alloc(n, 8, &n->status));
+  RH_HIP(hipHostMalloc(reinterpret_cast<void**>(&n->hstatus), 8 * sizeof(int), hipHostMallocCoherent));
   RH_TRY(alloc(n, 512, &n->trace));
   RH_HIP(hipMemset(n->trace, 0, 512 * sizeof(long long)));
   d.trace = nullptr;
@@ -657,6 +659,7 @@ void rh_destroy_network(rh_net* n) {
   if (n->ev_join) (void)hipEventDestroy(n->ev_join);
   if (n->side) (void)hipStreamDestroy(n->side);
   for (void* p : n->allocs) (void)hipFree(p);
+  if (n->hstatus) (void)hipHostFree(n->hstatus);
   delete n;
 }
 
@@ -1110,13 +1113,12 @@ rh_status rh_solve_condensed_kkt(rh_net* n, double* K, int64_t ldk, double delta
       RH_HIP(rh::launch_rtilde(d, r, n->sig_s, st));
       RH_HIP(rh::launch_recover(d, n->width, n->lds, p, r, p, st));
     }
-    RH_HIP(rh::launch_finish_step(d, r, n->sig_s, p, st));
+    RH_HIP(rh::launch_finish_step(d, r, n->sig_s, p, n->hstatus, st));
   }
   if (dev_status)
     RH_HIP(hipMemcpyAsync(dev_status, n->status, 2 * sizeof(int), hipMemcpyDeviceToDevice, st));
-  int hs[5];
-  RH_HIP(hipMemcpyAsync(hs, n->status, sizeof(hs), hipMemcpyDeviceToHost, st));
   RH_HIP(hipStreamSynchronize(st));
+  const int* hs = n->hstatus;   // written by the step's last kernel
   if (hs[4] != 0) return RH_ERR_STATE;   // condensation panels not at LDS address 0
   // a tiny static pivot makes G_x's factors, hence K_cond, unusable: it is
   // reported before the Cholesky's outcome
