@@ -156,7 +156,8 @@ struct rh_batch {
   std::vector<unsigned long long> ipm_solvers;   // ids of the bound solvers
   rh::IpmDev* d_ipm = nullptr;
   rh::BatchArg *d_eargs = nullptr, *d_targs = nullptr;
-  double *d_sc = nullptr, *d_red = nullptr, *d_f = nullptr;
+  double* d_sc = nullptr;
+  double *d_red = nullptr, *d_f = nullptr;   // pinned host memory, written by the kernels
   std::vector<double> h_sc, h_red, h_f;
   int max_vec = 0;
 };
@@ -820,9 +821,10 @@ void rh_batch_destroy(rh_batch* b) {
   (void)hipFree(b->d_args);
   (void)hipFree(b->d_tiles);
   (void)hipFree(b->d_status);
-  for (void* q : {(void*)b->d_ipm, (void*)b->d_eargs, (void*)b->d_targs, (void*)b->d_sc,
-                  (void*)b->d_red, (void*)b->d_f})
+  for (void* q : {(void*)b->d_ipm, (void*)b->d_eargs, (void*)b->d_targs, (void*)b->d_sc})
     if (q) (void)hipFree(q);
+  for (void* q : {(void*)b->d_red, (void*)b->d_f})   // pinned host memory
+    if (q) (void)hipHostFree(q);
   delete b;
 }
 
@@ -1195,6 +1197,7 @@ struct rh_ipm {
   rh_ipm_options opt{};
   rh::IpmDev v{};
   std::vector<void*> allocs;
+  std::vector<void*> hallocs;   // pinned host memory (the reduction slots, objective values)
   double* K = nullptr;      // nu x nu condensed matrix (factored in place)
   double* Kc = nullptr;     // its copy for inertia-correction retries
   double* rhs = nullptr;
@@ -1216,6 +1219,19 @@ rh_status ialloc(H* p, size_t count, T** out) {
   return RH_OK;
 }
 
+// Pinned, coherent host memory for values that kernels write with plain
+// stores and the host reads once the stream has drained (reduction slots,
+// objective values): no copy back, no device-to-host transfer.
+template <typename H, typename T>
+rh_status halloc(H* p, size_t count, T** out) {
+  void* q = nullptr;
+  if (hipHostMalloc(&q, std::max<size_t>(1, count) * sizeof(T), hipHostMallocCoherent) != hipSuccess)
+    return RH_ERR_OOM;
+  p->hallocs.push_back(q);
+  *out = static_cast<T*>(q);
+  return RH_OK;
+}
+
 template <typename H, typename T>
 rh_status iupload(H* p, const std::vector<T>& h, const T** out) {
   T* q = nullptr;
@@ -1230,6 +1246,8 @@ template <typename H>
 void free_ipm(H* p) {
   for (void* q : p->allocs) (void)hipFree(q);
   p->allocs.clear();
+  for (void* q : p->hallocs) (void)hipHostFree(q);
+  p->hallocs.clear();
 }
 
 // Device vectors of an interior-point handle on network n (natural order,
@@ -1293,17 +1311,17 @@ rh_status setup_ipm_dev(H* p, rh_net* n, rh::IpmDev& v, int* nfin) {
   RH_TRY(ialloc(p, m, &v.pzsu));
   RH_TRY(ialloc(p, nw, &v.wt));
   RH_TRY(ialloc(p, m, &v.st));
-  RH_TRY(ialloc(p, rh::IR_NSLOT, &v.red));
-  RH_TRY(ialloc(p, 2, &v.f));
+  RH_TRY(halloc(p, rh::IR_NSLOT, &v.red));
+  RH_TRY(halloc(p, 2, &v.f));
   return RH_OK;
 }
 
-// Reads the reduction slots (and the two objective values) after the stream
-// has drained.
+// Reads the reduction slots (and the two objective values; both in pinned
+// host memory) after the stream has drained.
 rh_status read_red(rh_ipm* p, double* red, double* f) {
   RH_HIP(hipStreamSynchronize(p->net->stream));
-  RH_HIP(hipMemcpy(red, p->v.red, sizeof(double) * rh::IR_NSLOT, hipMemcpyDeviceToHost));
-  if (f) RH_HIP(hipMemcpy(f, p->v.f, sizeof(double) * 2, hipMemcpyDeviceToHost));
+  std::memcpy(red, p->v.red, sizeof(double) * rh::IR_NSLOT);
+  if (f) std::memcpy(f, p->v.f, sizeof(double) * 2);
   return RH_OK;
 }
 
@@ -1589,8 +1607,16 @@ rh_status ipm_batch_bind(rh_batch* b, rh_ipm* const* ipms) {
     RH_TRY(grab(sizeof(rh::BatchArg) * cnt, &b->d_eargs));
     RH_TRY(grab(sizeof(rh::BatchArg) * cnt, &b->d_targs));
     RH_TRY(grab(sizeof(double) * rh::kIpmSc * cnt, &b->d_sc));
-    RH_TRY(grab(sizeof(double) * rh::IR_NSLOT * cnt, &b->d_red));
-    RH_TRY(grab(sizeof(double) * 2 * cnt, &b->d_f));
+    // reductions and objective values: pinned host memory that the kernels
+    // write with plain stores and the host reads after a synchronise
+    auto hgrab = [](size_t bytes, double** out) {
+      void* q = nullptr;
+      if (hipHostMalloc(&q, bytes, hipHostMallocCoherent) != hipSuccess) return RH_ERR_OOM;
+      *out = static_cast<double*>(q);
+      return RH_OK;
+    };
+    RH_TRY(hgrab(sizeof(double) * rh::IR_NSLOT * cnt, &b->d_red));
+    RH_TRY(hgrab(sizeof(double) * 2 * cnt, &b->d_f));
   }
   std::vector<rh::IpmDev> dv(cnt);
   std::vector<rh::BatchArg> ea(cnt), ta(cnt);
@@ -1652,13 +1678,9 @@ rh_status ipm_batch_launch(rh_batch* b, int trial, bool upload_sc) {
 
 // all reductions (and objective values) of the batch to the host
 rh_status ipm_batch_read(rh_batch* b, bool with_f) {
-  hipStream_t st = b->stream;
-  RH_HIP(hipMemcpyAsync(b->h_red.data(), b->d_red, sizeof(double) * b->h_red.size(),
-                        hipMemcpyDeviceToHost, st));
-  if (with_f)
-    RH_HIP(hipMemcpyAsync(b->h_f.data(), b->d_f, sizeof(double) * b->h_f.size(),
-                          hipMemcpyDeviceToHost, st));
-  RH_HIP(hipStreamSynchronize(st));
+  RH_HIP(hipStreamSynchronize(b->stream));
+  std::memcpy(b->h_red.data(), b->d_red, sizeof(double) * b->h_red.size());   // pinned host memory
+  if (with_f) std::memcpy(b->h_f.data(), b->d_f, sizeof(double) * b->h_f.size());
   return RH_OK;
 }
 
@@ -2046,6 +2068,7 @@ struct rh_redlin {
   rh::IpmDev rv{};      // reduced variables: w = u, s = s_r, y = y_r (nx = 0)
   rh::RedLinDev R{};
   std::vector<void*> allocs;
+  std::vector<void*> hallocs;   // pinned host memory (the reduction slots, objective values)
   double *K = nullptr, *Kc = nullptr, *rhs = nullptr, *adj = nullptr, *scal = nullptr;
   double mu = 0.1, delta_last = 0.0, theta0 = -1.0, sigma_f = 1.0;
   std::vector<std::pair<double, double>> filt;
@@ -2069,8 +2092,8 @@ double redlin_error(const rh_redlin* p, const double* red, double mu) {
 
 rh_status redlin_read(rh_redlin* p, double* red, double* f) {
   RH_HIP(hipStreamSynchronize(p->net->stream));
-  RH_HIP(hipMemcpy(red, p->R.red, sizeof(double) * rh::IR_NSLOT, hipMemcpyDeviceToHost));
-  if (f) RH_HIP(hipMemcpy(f, p->v.f, sizeof(double) * 2, hipMemcpyDeviceToHost));
+  std::memcpy(red, p->R.red, sizeof(double) * rh::IR_NSLOT);   // pinned host memory
+  if (f) std::memcpy(f, p->v.f, sizeof(double) * 2);
   return RH_OK;
 }
 
@@ -2196,7 +2219,7 @@ rh_status rh_redlin_create(rh_net* n, const rh_ipm_options* opts, const double* 
   RL_TRY(ialloc(p.get(), mr, &R.pzsu));
   RL_TRY(ialloc(p.get(), mr, &R.st));
   RL_TRY(ialloc(p.get(), nu, &R.zero));
-  RL_TRY(ialloc(p.get(), rh::IR_NSLOT, &R.red));
+  RL_TRY(halloc(p.get(), rh::IR_NSLOT, &R.red));
   RL_TRY(ialloc(p.get(), size_t(nu) * nu, &p->K));
   RL_TRY(ialloc(p.get(), size_t(nu) * nu, &p->Kc));
   RL_TRY(ialloc(p.get(), nu, &p->rhs));
