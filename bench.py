@@ -112,9 +112,9 @@ def batched_run(api, torch, steps, warmup):
         el = time.perf_counter() - t0
         # the same step captured in a HIP graph and replayed
         B.capture(pts, delta)
-        for _ in range(2):
+        for _ in range(5):
             B.replay()
-        stream.synchronize()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             B.replay()

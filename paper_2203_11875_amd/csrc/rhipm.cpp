@@ -39,7 +39,7 @@ struct rh_net {
   std::vector<void*> allocs;
   int width = 2;
   bool lds = true;
-  double* pf_scal = nullptr;  // device scalar of the power-flow residual checks
+  double* pf_scal = nullptr;  // power-flow residual of the last check (pinned host memory)
   // second stream: K assembly and rt run beside the refactorisation (which
   // occupies one work-group); events fork and join it
   hipStream_t side = nullptr;
@@ -146,7 +146,7 @@ struct rh_batch {
   rh::DevNet* d_nets = nullptr;
   rh::BatchArg* d_args = nullptr;
   int2* d_tiles = nullptr;
-  int* d_status = nullptr;
+  int* d_status = nullptr;   // 5 status words per instance (pinned host memory)
   std::vector<rh::DevNet> h_nets;
   std::vector<rh::BatchArg> h_args;
   // lockstep interior-point solvers (rh_ipm_batch_step): their device
@@ -661,6 +661,7 @@ void rh_destroy_network(rh_net* n) {
   if (n->side) (void)hipStreamDestroy(n->side);
   for (void* p : n->allocs) (void)hipFree(p);
   if (n->hstatus) (void)hipHostFree(n->hstatus);
+  if (n->pf_scal) (void)hipHostFree(n->pf_scal);
   delete n;
 }
 
@@ -798,7 +799,8 @@ rh_status rh_batch_create(rh_net* const* nets, int32_t count, void* hip_stream,
   if (hipMalloc(&b->d_nets, sizeof(rh::DevNet) * count) != hipSuccess ||
       hipMalloc(&b->d_args, sizeof(rh::BatchArg) * count) != hipSuccess ||
       hipMalloc(&b->d_tiles, sizeof(int2) * tiles.size()) != hipSuccess ||
-      hipMalloc(&b->d_status, sizeof(int) * 5 * count) != hipSuccess) {
+      hipHostMalloc(reinterpret_cast<void**>(&b->d_status), sizeof(int) * 5 * count,
+                    hipHostMallocCoherent) != hipSuccess) {
     rh_batch_destroy(b);
     return RH_ERR_OOM;
   }
@@ -820,7 +822,7 @@ void rh_batch_destroy(rh_batch* b) {
   (void)hipFree(b->d_nets);
   (void)hipFree(b->d_args);
   (void)hipFree(b->d_tiles);
-  (void)hipFree(b->d_status);
+  if (b->d_status) (void)hipHostFree(b->d_status);
   for (void* q : {(void*)b->d_ipm, (void*)b->d_eargs, (void*)b->d_targs, (void*)b->d_sc})
     if (q) (void)hipFree(q);
   for (void* q : {(void*)b->d_red, (void*)b->d_f})   // pinned host memory
@@ -912,10 +914,8 @@ rh_status rh_batch_solve(rh_batch* b, const rh_batch_solve_item* items, int32_t*
 namespace {
 rh_status batch_statuses(rh_batch* b, int32_t* status) {
   RH_HIP(rh::launch_batch_status(b->d_nets, int(b->nets.size()), b->d_status, b->stream));
-  std::vector<int> hs(5 * b->nets.size());
-  RH_HIP(hipMemcpyAsync(hs.data(), b->d_status, sizeof(int) * hs.size(), hipMemcpyDeviceToHost,
-                        b->stream));
   RH_HIP(hipStreamSynchronize(b->stream));
+  const int* hs = b->d_status;   // pinned host memory, written by the status kernel
   rh_status worst = RH_OK;
   for (size_t i = 0; i < b->nets.size(); ++i) {
     rh_status si = RH_OK;
@@ -2043,13 +2043,14 @@ rh_status newton_pf(rh_net* n, const double* u, double* x, double tol, int max_i
                     double* res) {
   const auto& d = n->d;
   hipStream_t st = n->stream;
-  if (!n->pf_scal) RH_TRY(alloc(n, 4, &n->pf_scal));
+  if (!n->pf_scal)
+    RH_HIP(hipHostMalloc(reinterpret_cast<void**>(&n->pf_scal), 4 * sizeof(double),
+                         hipHostMallocCoherent));
   for (int k = 0;; ++k) {
-    double gm = 0.0;
     RH_HIP(rh::launch_eval(d, x, u, nullptr, nullptr, false, st));
     RH_HIP(rh::launch_absmax(d.dst + d.d_g, d.nx, n->pf_scal, st));
-    RH_HIP(hipMemcpyAsync(&gm, n->pf_scal, sizeof(double), hipMemcpyDeviceToHost, st));
     RH_HIP(hipStreamSynchronize(st));
+    const double gm = n->pf_scal[0];   // written by the reduction kernel
     if (iters) *iters = k;
     if (res) *res = gm;
     if (gm <= tol) return RH_OK;
