@@ -2225,7 +2225,7 @@ rh_status rh_redlin_create(rh_net* n, const rh_ipm_options* opts, const double* 
   RL_TRY(ialloc(p.get(), size_t(nu) * nu, &p->Kc));
   RL_TRY(ialloc(p.get(), nu, &p->rhs));
   RL_TRY(ialloc(p.get(), nx, &p->adj));
-  RL_TRY(ialloc(p.get(), 4, &p->scal));
+  RL_TRY(halloc(p.get(), 4, &p->scal));   // read by the host after each direction
   v.s = R.sr;            // the h rows' slacks and multipliers lead s_r, y_r
   v.y = R.yr;
   p->nfin = 0;
@@ -2363,8 +2363,8 @@ rh_status rh_redlin_step(rh_redlin* p, rh_ipm_info* info) {
   RH_HIP(rh::launch_redlin_pack(v, R, mu, p->scal, st));
   RH_HIP(rh::launch_ipm_dir(p->rv, mu, tau, st));
   double rd[rh::IR_NSLOT], dphi_f = 0.0;
-  RH_TRY(redlin_read(p, rd, nullptr));
-  RH_HIP(hipMemcpy(&dphi_f, p->scal, sizeof(double), hipMemcpyDeviceToHost));
+  RH_TRY(redlin_read(p, rd, nullptr));   // also drains the stream for p->scal (pinned)
+  dphi_f = p->scal[0];
   const double a_pri = rd[rh::IR_APRI], a_dual = rd[rh::IR_ADUAL];
   const double dphi = rd[rh::IR_DPHI] + dphi_f;
   const double theta = red[rh::IR_THETA];
