@@ -149,6 +149,7 @@ struct rh_batch {
   int* d_status = nullptr;   // 5 status words per instance (pinned host memory)
   std::vector<rh::DevNet> h_nets;
   std::vector<rh::BatchArg> h_args;
+  std::vector<char> up_nets, up_args;   // bytes of the last upload of h_nets, h_args
   // lockstep interior-point solvers (rh_ipm_batch_step): their device
   // descriptors with the reductions redirected to batch-wide arrays, the
   // evaluation arguments at the iterates and at the trial points, and the
@@ -857,10 +858,19 @@ rh_status batch_upload(rh_batch* b) {
     a.nu = n->d.nu;
     a.m = n->d.m;
   }
-  RH_HIP(hipMemcpyAsync(b->d_nets, b->h_nets.data(), sizeof(rh::DevNet) * b->nets.size(),
-                        hipMemcpyHostToDevice, b->stream));
-  RH_HIP(hipMemcpyAsync(b->d_args, b->h_args.data(), sizeof(rh::BatchArg) * b->nets.size(),
-                        hipMemcpyHostToDevice, b->stream));
+  // the kernels only read these arrays: bytes equal to the last upload are
+  // already on the device (a replay with the same arguments copies nothing)
+  const size_t nb = sizeof(rh::DevNet) * b->nets.size(), ab = sizeof(rh::BatchArg) * b->nets.size();
+  if (b->up_nets.size() != nb || std::memcmp(b->up_nets.data(), b->h_nets.data(), nb) != 0) {
+    RH_HIP(hipMemcpyAsync(b->d_nets, b->h_nets.data(), nb, hipMemcpyHostToDevice, b->stream));
+    b->up_nets.assign(reinterpret_cast<const char*>(b->h_nets.data()),
+                      reinterpret_cast<const char*>(b->h_nets.data()) + nb);
+  }
+  if (b->up_args.size() != ab || std::memcmp(b->up_args.data(), b->h_args.data(), ab) != 0) {
+    RH_HIP(hipMemcpyAsync(b->d_args, b->h_args.data(), ab, hipMemcpyHostToDevice, b->stream));
+    b->up_args.assign(reinterpret_cast<const char*>(b->h_args.data()),
+                      reinterpret_cast<const char*>(b->h_args.data()) + ab);
+  }
   return RH_OK;
 }
 }  // namespace
