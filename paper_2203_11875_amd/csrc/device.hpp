@@ -199,7 +199,8 @@ hipError_t launch_recover_stored(const DevNet& d, double* p, hipStream_t st);
 // hstat (optional, pinned host int[5]): receives the status words.
 hipError_t launch_finish_step(const DevNet& d, const double* r, const double* sig_s, double* p,
                               int* hstat, hipStream_t st);
-hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st);
+// K = (K + K^T) / 2 in place; copy (optional, same leading dimension): the result again.
+hipError_t launch_symmetrize(double* K, long ldk, int n, double* copy, hipStream_t st);
 // Cholesky of the lower triangle of K + delta I in place (K holds L on
 // return), the forward substitution L y = b_in folded into the factorisation
 // (b_in is read by the first launch only and may be b; y is written to b,

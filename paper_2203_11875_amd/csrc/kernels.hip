@@ -1482,16 +1482,26 @@ __global__ void __launch_bounds__(kBlock) k_objective_b(const DevNet* __restrict
 }
 
 // --------------------------------------------------------- dense Cholesky
-__device__ __forceinline__ void k_symmetrize_body(double* K, long ld, int n) {
+// copy (optional, same layout): receives the symmetrised matrix, diagonal
+// included (the saved copy for inertia-correction retries).
+__device__ __forceinline__ void k_symmetrize_body(double* K, long ld, int n, double* copy = nullptr) {
   const int i = blockIdx.x * 16 + threadIdx.x;
   const int j = blockIdx.y * 16 + threadIdx.y;
-  if (i >= n || j >= i) return;
+  if (i >= n || j > i) return;
+  if (j == i) {
+    if (copy) copy[(size_t)i * ld + i] = K[(size_t)i * ld + i];
+    return;
+  }
   const double v = 0.5 * (K[(size_t)j * ld + i] + K[(size_t)i * ld + j]);
   K[(size_t)j * ld + i] = v;
   K[(size_t)i * ld + j] = v;
+  if (copy) {
+    copy[(size_t)j * ld + i] = v;
+    copy[(size_t)i * ld + j] = v;
+  }
 }
-__global__ void k_symmetrize(double* K, long ld, int n) {
-  k_symmetrize_body(K, ld, n);
+__global__ void k_symmetrize(double* K, long ld, int n, double* copy) {
+  k_symmetrize_body(K, ld, n, copy);
 }
 
 template <int W, int PM, int NW = 1>
@@ -1889,8 +1899,9 @@ hipError_t launch_finish_step(const DevNet& d, const double* r, const double* si
   return hipGetLastError();
 }
 
-hipError_t launch_symmetrize(double* K, long ldk, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_symmetrize, dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, st, K, ldk, n);
+hipError_t launch_symmetrize(double* K, long ldk, int n, double* copy, hipStream_t st) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, st, K, ldk, n,
+                     copy);
   return hipGetLastError();
 }
 

@@ -1025,9 +1025,11 @@ namespace {
 // Condensation once the derivative values at (x, u, lambda, y) are in place
 // (rh_condense_reduced_hessian after its evaluation; the interior-point
 // driver after its own).
+// Kcopy (optional, leading dimension ldk): receives the symmetrised K_cond
+// as well (an interior-point solver's copy for inertia-correction retries).
 rh_status condense_evaluated(rh_net* n, const double* sig_x, const double* sig_u,
                              const double* sig_s, const double* r, double* K, int64_t ldk,
-                             double* rhs) {
+                             double* rhs, double* Kcopy = nullptr) {
   const auto& d = n->d;
   hipStream_t st = n->stream;
   n->condensed = false;
@@ -1051,7 +1053,7 @@ rh_status condense_evaluated(rh_net* n, const double* sig_x, const double* sig_u
   }
   {
     PhaseScope ps(n, RH_PHASE_SYMMETRIZE);
-    RH_HIP(rh::launch_symmetrize(K, long(ldk), d.nu, st));
+    RH_HIP(rh::launch_symmetrize(K, long(ldk), d.nu, Kcopy, st));
   }
   n->condensed = true;
   n->rhs_cols = r != nullptr;
@@ -1438,10 +1440,7 @@ rh_status ipm_condense_single(rh_ipm* p) {
   rh_net* n = p->net;
   auto& v = p->v;
   const int nu = v.nu;
-  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
-  RH_HIP(hipMemcpyAsync(p->Kc, p->K, sizeof(double) * size_t(nu) * nu, hipMemcpyDeviceToDevice,
-                        n->stream));
-  return RH_OK;
+  return condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs, p->Kc);
 }
 
 rh_status ipm_first_solve(rh_ipm* p) {
@@ -2348,8 +2347,7 @@ rh_status rh_redlin_step(rh_redlin* p, rh_ipm_info* info) {
   const double mu = p->mu;
   // the reduced KKT system through the full-space condensation
   RH_HIP(rh::launch_redlin_prep(d, v, R, mu, st));
-  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs));
-  RH_HIP(hipMemcpyAsync(p->Kc, p->K, sizeof(double) * size_t(nu) * nu, hipMemcpyDeviceToDevice, st));
+  RH_TRY(condense_evaluated(n, v.sig_w + nu, v.sig_w, v.sig_s, v.r, p->K, nu, p->rhs, p->Kc));
   double delta = 0.0;
   rh_status code = rh_solve_condensed_kkt(n, p->K, nu, 0.0, p->rhs, v.r, v.p, nullptr);
   if (code == RH_NOT_POSDEF) {
